@@ -1,0 +1,250 @@
+"""FP64 CPU oracle for the stochastic heat / Dean-Kawasaki finite-volume schemes.
+
+TEST INFRASTRUCTURE ONLY.  Only the test-suite, ``__graft_entry__.smoke()`` and
+the ``cpu_baseline`` leg of ``bench.py`` may import this package.  It shares no
+code with the HIP library in ``paper_2406_12157_amd`` and never imports it.
+
+The arithmetic lives in ``she_oracle.c`` (plain C, IEEE double,
+``-ffp-contract=off``); this module only compiles it with gcc and marshals
+arguments through ctypes.  What each C function computes, and which passage of
+the paper it follows, is documented in the C file.
+
+Parity status (what pins each part, see the tests under ``tests/``):
+  * Philox4x32-10        -- bit-exact against rocRAND's independent engine.
+  * Box-Muller normals   -- Kolmogorov-Smirnov and moment tests vs N(0,1).
+  * deterministic step   -- Fourier-mode decay by the closed-form amplification
+                            factor (FE: 1 - 4 r sum sin^2, PC: (1+g^2)/2).
+  * stochastic step      -- conservation to round-off (periodic); exact linear
+                            steady profile (Dirichlet); stationary covariance
+                            vs discrete Lyapunov solutions and closed forms.
+  * statistics           -- estimators checked on hand-made trajectories.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+from dataclasses import dataclass, field
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "she_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+
+def build(force: bool = False) -> str:
+    """Compile she_oracle.c into liboracle.so (gcc, -O2 -ffp-contract=off)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        subprocess.check_call(
+            ["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math",
+             "-fPIC", "-shared", "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+class _Desc(C.Structure):
+    _fields_ = [("dim", C.c_int32), ("n", C.c_int32 * 3), ("eq", C.c_int32),
+                ("bc", C.c_int32), ("scheme", C.c_int32), ("noise", C.c_int32),
+                ("r", C.c_double), ("sigma", C.c_double), ("u0", C.c_double),
+                ("u_left", C.c_double), ("u_right", C.c_double),
+                ("init_sd", C.c_double), ("seed", C.c_uint64),
+                ("realisation", C.c_uint32), ("pad_", C.c_uint32)]
+
+
+class _Stats(C.Structure):
+    _fields_ = [("burn_in", C.c_int64), ("every", C.c_int64), ("n_samples", C.c_int64),
+                ("s1", C.POINTER(C.c_double)), ("s2", C.POINTER(C.c_double)),
+                ("m2", C.POINTER(C.c_double)), ("sk", C.POINTER(C.c_double)),
+                ("n_bins", C.c_int32), ("pad_", C.c_int32),
+                ("sp_mean", C.c_double), ("sp_sq", C.c_double), ("sp_var", C.c_double),
+                ("clamp_count", C.c_int64), ("nonfinite", C.c_int32), ("pad2_", C.c_int32),
+                ("nonfinite_step", C.c_int64)]
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        build()
+        lib = C.CDLL(_LIB)
+        lib.or_philox4x32_10.argtypes = [C.POINTER(C.c_uint32)] * 3
+        lib.or_normal.restype = C.c_double
+        lib.or_normal.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint64, C.c_uint64]
+        lib.or_normals.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint64,
+                                   C.c_uint64, C.c_int64, C.POINTER(C.c_double)]
+        lib.or_ncells.restype = C.c_int64
+        lib.or_ncells.argtypes = [C.POINTER(_Desc)]
+        lib.or_nfaces.restype = C.c_int64
+        lib.or_nfaces.argtypes = [C.POINTER(_Desc)]
+        lib.or_n_bins.restype = C.c_int32
+        lib.or_n_bins.argtypes = [C.POINTER(_Desc)]
+        lib.or_bin_modes.argtypes = [C.POINTER(_Desc), C.POINTER(C.c_double)]
+        lib.or_reference.argtypes = [C.POINTER(_Desc), C.POINTER(C.c_double)]
+        lib.or_init.restype = C.c_int
+        lib.or_init.argtypes = [C.POINTER(_Desc), C.POINTER(C.c_double)]
+        lib.or_advance.restype = C.c_int
+        lib.or_advance.argtypes = [C.POINTER(_Desc), C.POINTER(C.c_double), C.c_int64,
+                                   C.c_int64, C.POINTER(_Stats)]
+        _lib = lib
+    return _lib
+
+
+def _dptr(a: np.ndarray):
+    assert a.dtype == np.float64 and a.flags.c_contiguous
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+@dataclass
+class Desc:
+    """One instance of the scheme (field meanings as in ``she_oracle.c``)."""
+    dim: int = 1
+    n: tuple = (64, 1, 1)
+    eq: int = 0            # 0 heat, 1 Dean-Kawasaki
+    bc: int = 0            # 0 periodic, 1 Dirichlet (1D)
+    scheme: int = 0        # 0 FE, 1 PC
+    noise: int = 0         # 0 instantaneous, 1 deterministic face value, 2 off
+    r: float = 0.2
+    sigma: float = 0.0
+    u0: float = 1.0
+    u_left: float = 1.0
+    u_right: float = 1.0
+    init_sd: float = 0.0
+    seed: int = 0
+    realisation: int = 0
+
+    def c(self) -> _Desc:
+        n = tuple(self.n) + (1,) * (3 - len(self.n))
+        return _Desc(self.dim, (C.c_int32 * 3)(*n), self.eq, self.bc, self.scheme,
+                     self.noise, self.r, self.sigma, self.u0, self.u_left, self.u_right,
+                     self.init_sd, self.seed, self.realisation, 0)
+
+    @property
+    def ncells(self) -> int:
+        return int(np.prod(self.n))
+
+
+def philox(ctr, key) -> np.ndarray:
+    """Raw Philox4x32-10 block for a 4-word counter and 2-word key."""
+    lib = _load()
+    c = (C.c_uint32 * 4)(*[int(v) & 0xFFFFFFFF for v in ctr])
+    k = (C.c_uint32 * 2)(*[int(v) & 0xFFFFFFFF for v in key])
+    o = (C.c_uint32 * 4)()
+    lib.or_philox4x32_10(c, k, o)
+    return np.array(list(o), dtype=np.uint32)
+
+
+def normals(seed: int, realisation: int, tag: int, step: int, face0: int, count: int) -> np.ndarray:
+    lib = _load()
+    out = np.zeros(count, dtype=np.float64)
+    lib.or_normals(seed, realisation, tag, step, face0, count, _dptr(out))
+    return out
+
+
+def nfaces(d: Desc) -> int:
+    return int(_load().or_nfaces(C.byref(d.c())))
+
+
+def n_bins(d: Desc) -> int:
+    return int(_load().or_n_bins(C.byref(d.c())))
+
+
+def bin_modes(d: Desc) -> np.ndarray:
+    out = np.zeros(n_bins(d), dtype=np.float64)
+    _load().or_bin_modes(C.byref(d.c()), _dptr(out))
+    return out
+
+
+def reference(d: Desc) -> np.ndarray:
+    out = np.zeros(d.ncells, dtype=np.float64)
+    _load().or_reference(C.byref(d.c()), _dptr(out))
+    return out
+
+
+def init(d: Desc) -> np.ndarray:
+    out = np.zeros(d.ncells, dtype=np.float64)
+    rc = _load().or_init(C.byref(d.c()), _dptr(out))
+    if rc != 0:
+        raise ValueError("oracle: invalid description (rc=%d)" % rc)
+    return out
+
+
+@dataclass
+class Stats:
+    """Sample accumulators (FP64) and their finalisation (population moments)."""
+    d: Desc
+    burn_in: int = 0
+    every: int = 1
+    per_cell: bool = True
+    corr: bool = False
+    sk: bool = False
+    _c: _Stats = field(default=None, repr=False)
+
+    def __post_init__(self):
+        nc = self.d.ncells
+        self.s1 = np.zeros(nc)
+        self.s2 = np.zeros(nc)
+        self.m2 = np.zeros((nc, nc)) if self.corr else None
+        if self.sk:
+            self.nb = nc if self.d.dim == 1 else n_bins(self.d)
+            self.sk_sum = np.zeros(self.nb)
+        else:
+            self.nb, self.sk_sum = 0, None
+        null = C.POINTER(C.c_double)()
+        self._c = _Stats(self.burn_in, self.every, 0,
+                         _dptr(self.s1) if self.per_cell else null,
+                         _dptr(self.s2) if self.per_cell else null,
+                         _dptr(self.m2) if self.corr else null,
+                         _dptr(self.sk_sum) if self.sk else null,
+                         self.nb, 0, 0.0, 0.0, 0.0, 0, 0, 0, 0)
+
+    @property
+    def n_samples(self) -> int:
+        return int(self._c.n_samples)
+
+    @property
+    def nonfinite(self) -> bool:
+        return bool(self._c.nonfinite)
+
+    @property
+    def clamp_count(self) -> int:
+        return int(self._c.clamp_count)
+
+    def mean(self) -> np.ndarray:
+        return reference(self.d) + self.s1 / self.n_samples
+
+    def var(self) -> np.ndarray:
+        m = self.s1 / self.n_samples
+        return self.s2 / self.n_samples - m * m
+
+    def cov(self) -> np.ndarray:
+        m = self.s1 / self.n_samples
+        return self.m2 / self.n_samples - np.outer(m, m)
+
+    def structure_factor(self) -> np.ndarray:
+        """1D: <|T_k|^2> per k.  nD: per radial shell, averaged over its modes."""
+        if self.d.dim == 1:
+            return self.sk_sum / self.n_samples
+        modes = bin_modes(self.d)
+        with np.errstate(invalid="ignore", divide="ignore"):
+            return self.sk_sum / (self.n_samples * modes)
+
+    def spatial(self):
+        """(mean of spatial-mean delta, mean of spatial-mean delta^2, mean spatial variance)."""
+        n = self.n_samples
+        return self._c.sp_mean / n, self._c.sp_sq / n, self._c.sp_var / n
+
+
+def advance(d: Desc, u: np.ndarray, step0: int, nsteps: int, stats: Stats | None = None) -> int:
+    """Advance ``u`` in place; returns 0, or 1 if a sample met a non-finite value."""
+    rc = _load().or_advance(C.byref(d.c()), _dptr(u), step0, nsteps,
+                            C.byref(stats._c) if stats is not None else None)
+    if rc < 0:
+        raise ValueError("oracle: invalid description (rc=%d)" % rc)
+    return rc
+
+
+def sigma_of(r: float, eps: float) -> float:
+    """Noise factor sqrt(2 r eps) (Sec. 3 discrete noise; Sec. 4 eq. DK with eps = 1/dV)."""
+    return float(np.sqrt(2.0 * r * eps))
