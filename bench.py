@@ -1,0 +1,205 @@
+"""Benchmark: cell-updates/s of the batched FP32 step on one MI355X.
+
+Workload (the batched FP32 configuration the metric is quoted on): 2D
+periodic stochastic heat equation, 512 x 512 cells x 256 independent
+realisations, forward Euler, r = 0.1, eps = 1e-2, T0 = 1 plus an equilibrium
+perturbation; the equal-time spatial statistics are sampled every 10 steps.
+A "step" is one time step of all 256 realisations (Philox + Box-Muller face
+noise, face fluxes, divergence update, and the sampling on sample steps).
+Inputs are resident in HBM when the timed region starts.
+
+Printed: one JSON line with the throughput, the roofline of the step kernel
+(HIP-event timing of the kernel on its stream, algorithmic bytes 8 B per
+FP32 cell-update), the plain single-realisation rate (one launch per step),
+the state error against the FP64 oracle on a sampled realisation, and the
+oracle's own rate on the host CPU.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "cell-updates/s (incl. RNG) + % HBM roofline, batched FP32 vs plain, at stated error"
+HBM_PEAK_GBS = 8000.0
+KERNEL_SRC = os.path.join(ROOT, "paper_2406_12157_amd", "csrc", "she_knd.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_step2d_c3.json")
+
+
+def kernel_hash() -> str:
+    h = hashlib.sha256()
+    for name in ("she_knd.hip", "she_rng.hpp", "she_internal.hpp"):
+        with open(os.path.join(ROOT, "paper_2406_12157_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def make_handle(she, cfg, stats):
+    from paper_2406_12157_amd import workloads as W  # noqa: F401
+    insts = [she.Instance(n=i["n"], eq=i["eq"], bc=i["bc"], scheme=i["scheme"], noise=i["noise"], r=i["r"],
+                          eps=i["eps"], u0=i["u0"], u_left=i["u_left"], u_right=i["u_right"],
+                          init_sd=i["init_sd"], seed=i["seed"], realisation=i["realisation"])
+             for i in cfg["instances"]]
+    return she.Handle(insts, precision=cfg["precision"], burn_in=0, sample_every=cfg["sample_every"],
+                      stats=stats), insts
+
+
+def timed_run(torch, h, steps, every):
+    """Wall time of `steps` sampled steps, plus HIP-event time of the step
+    kernel alone (events around each non-sample step on the library's stream)."""
+    ev = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(steps):
+        t = h.steps + 1
+        if t % every != 0 and len(ev) < 4096:
+            a = torch.cuda.Event(enable_timing=True)
+            b = torch.cuda.Event(enable_timing=True)
+            a.record()
+            h.run(1)
+            b.record()
+            ev.append((a, b))
+        else:
+            h.run(1)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kms = sum(a.elapsed_time(b) for a, b in ev) / max(1, len(ev))
+    return wall, kms, len(ev)
+
+
+def state_error(she, torch, cfg, realisation, steps):
+    """Max relative state error of one realisation after `steps` steps vs the
+    FP64 oracle started from the same field (bounded: one realisation)."""
+    import numpy as np
+    import oracle
+    c1 = dict(cfg)
+    c1["instances"] = [cfg["instances"][realisation]]
+    h, insts = make_handle(she, c1, 0)
+    u = h.read_field(0)
+    h.step(steps)
+    got = h.read_field(0)
+    h.close()
+    i = c1["instances"][0]
+    d = oracle.Desc(dim=2, n=tuple(i["n"]) + (1,), eq=i["eq"], scheme=i["scheme"], noise=i["noise"],
+                    r=float(np.float32(i["r"])), sigma=float(np.float32(np.sqrt(2 * i["r"] * i["eps"]))),
+                    u0=i["u0"], u_left=i["u_left"], u_right=i["u_right"], seed=i["seed"],
+                    realisation=i["realisation"])
+    oracle.advance(d, u, 0, steps)
+    return float(np.max(np.abs(got - u) / np.abs(u)))
+
+
+def cpu_baseline(cfg, seconds: float):
+    """The oracle (single thread, FP64) on one realisation of the workload for
+    about `seconds` of CPU time; rate in cell-updates/s."""
+    import oracle
+    import numpy as np
+    i = cfg["instances"][0]
+    d = oracle.Desc(dim=2, n=tuple(i["n"]) + (1,), eq=i["eq"], scheme=i["scheme"], noise=i["noise"], r=i["r"],
+                    sigma=float(np.sqrt(2 * i["r"] * i["eps"])), u0=i["u0"], u_left=i["u_left"],
+                    u_right=i["u_right"], init_sd=i["init_sd"], seed=i["seed"], realisation=i["realisation"])
+    u = oracle.init(d)
+    st = oracle.Stats(d, burn_in=0, every=cfg["sample_every"], per_cell=False)
+    cells = d.ncells
+    steps, t_used = 0, 0.0
+    t0 = time.perf_counter()
+    while t_used < seconds:
+        oracle.advance(d, u, steps, 5, st)
+        steps += 5
+        t_used = time.perf_counter() - t0
+    return dict(value=cells * steps / t_used, unit="cell-updates/s", cores=1, kind="oracle",
+                sample="1 of 256 realisations, 512x512, %d steps (FE, sampling every %d), %.1f s"
+                       % (steps, cfg["sample_every"], t_used))
+
+
+def read_traffic(cells_per_launch):
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except Exception:
+        return None
+    if t.get("kernel_hash") != kernel_hash():
+        return None
+    return t.get("hbm_bytes_per_launch")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--realisations", type=int, default=256)
+    ap.add_argument("--scheme", choices=["fe", "pc"], default="fe")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-error", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py: this build runs on one GPU only (--gpus 1); the path would shard by realisation "
+              "with no per-step communication, but no multi-GPU run is provided.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2406_12157_amd import she, workloads as W
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    she.load()
+    scheme = W.EM if args.scheme == "fe" else W.HEUN
+    cfg = W.c3(realisations=args.realisations, scheme=scheme)
+    every = cfg["sample_every"]
+
+    h, insts = make_handle(she, cfg, she.STAT_SPATIAL)
+    cells = sum(i.ncells for i in insts)
+    h.run(args.warmup)
+    torch.cuda.synchronize()
+    wall, kms, nev = timed_run(torch, h, args.steps, every)
+    st0 = h.stats(0)
+    h.close()
+    value = cells * args.steps / wall
+    ms_per_step = wall / args.steps * 1e3
+
+    bytes_per_launch = 8.0 * cells
+    achieved = bytes_per_launch / (kms * 1e-3) / 1e9
+    traffic = read_traffic(cells)
+    roofline = dict(bound="hbm", achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s", frac=achieved / HBM_PEAK_GBS,
+                    traffic=traffic, kernel="k_step2d<float,8,heat,%s>" % args.scheme,
+                    kernel_ms=kms, kernel_launches_timed=nev, algorithmic_bytes_per_launch=bytes_per_launch)
+
+    out = {"metric": METRIC, "value": value, "unit": "cell-updates/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": cfg["name"], "grid": [512, 512], "realisations": args.realisations,
+                      "scheme": args.scheme, "r": 0.1, "eps": 1e-2, "sample_every": every,
+                      "stats": "spatial mean/variance per sample (FP64)", "parallelism": "single GPU"},
+           "roofline": roofline}
+
+    if not args.no_plain:
+        pcfg = W.c3(realisations=1, scheme=scheme)
+        ph, pinsts = make_handle(she, pcfg, she.STAT_SPATIAL)
+        ph.run(args.warmup)
+        psteps = max(200, args.steps // 2)
+        pwall, pkms, _ = timed_run(torch, ph, psteps, every)
+        ph.close()
+        out["plain"] = {"value": pinsts[0].ncells * psteps / pwall, "ms_per_step": pwall / psteps * 1e3,
+                        "kernel_ms": pkms, "form": "1 realisation, one kernel launch per step, no graph"}
+        out["batched_over_plain"] = value / out["plain"]["value"]
+    if not args.no_error:
+        err_steps = 20
+        out["error"] = {"state_max_rel_vs_fp64_oracle": state_error(she, torch, cfg, args.realisations - 1,
+                                                                     err_steps),
+                        "steps": err_steps, "realisation": args.realisations - 1,
+                        "stats_samples": st0["n_samples"]}
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(cfg, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

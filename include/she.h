@@ -1,0 +1,206 @@
+/*
+ * she.h -- C ABI of the MI355X (gfx950) library for the finite-volume
+ * stochastic heat equation (SHE) and its Dean-Kawasaki (DK) species analogue.
+ *
+ * Method (Garcia, Bell, Nonaka, Srivastava, Ladiges, Kim, "An Introduction to
+ * Computational Fluctuating Hydrodynamics"):
+ *   - Sec. 3, FE scheme:  U_i += r (U_{i+1} - 2U_i + U_{i-1})
+ *                              + sigma (A_{i+1/2} N_{i+1/2} - A_{i-1/2} N_{i-1/2})
+ *     with sigma = sqrt(2 r eps), r = kappa dt/dx^2, eps = k_B/(rho c_V dV),
+ *     face amplitude A = T_face = (T_i + T_{i+1})/2 (SHE, Sec. 3) or
+ *     A = sqrt(max(n_face, 0)) with eps = 1/dV (DK, Sec. 4 eq. DK), and one
+ *     standard normal N per face per step (Sec. 3 discrete noise);
+ *   - Sec. 3, PC scheme: FE predictor U*, then
+ *     U^{n+1} = (U^n + U* + Delta(U*; same N)) / 2;
+ *   - Sec. 3, Dirichlet walls: ghost stencil (U_1 - 3U_0 + 2U_L) and wall-face
+ *     noise sqrt(2) A(U_L) N (1D only; 2D/3D grids are periodic);
+ *   - Sec. 3, statistics: time averages after a relaxation period, variance,
+ *     two-point correlation <dU_i dU_j>, structure factor <|U_k|^2>.
+ *   In 2D/3D every direction has its own independent face numbers (white noise
+ *   with independent Cartesian components, Sec. 2 eq. GWN) and the cells are
+ *   cubes of volume dV.
+ *
+ * Noise: Philox4x32-10 (Salmon et al., SC'11) + Box-Muller.  Counter of the
+ * block holding face f at step n with stream tag g and realisation q:
+ *     (f >> 2, n mod 2^32, ((n >> 32) & 0xFFFF) | g << 16, q),
+ * key (seed mod 2^32, seed div 2^32); lane f & 3; lanes (0,1) and (2,3) are
+ * Box-Muller pairs with u = ((word >> 9) + 1/2) 2^-23, even lane
+ * sqrt(-2 ln u_a) cos(2 pi u_b), odd lane ... sin(2 pi u_b).  Tag 0 = step
+ * noise, tag 1 = initial perturbation (face number = cell number).
+ * Face numbers: 1D f = low (left) face of cell f, f = 0..N-1 periodic,
+ * 0..N Dirichlet (f = N is the right wall); 2D/3D the low face of cell
+ * (x,y,z) in direction e is ((z*Ny + y)*dim + e)*Nx + x.
+ *
+ * Conventions for every call:
+ *   - every function returns she_status (0 = SHE_OK, < 0 = error);
+ *     she_last_error() gives a message; no exception crosses the ABI;
+ *   - all GPU work is enqueued on the stream given in she_config (NULL = the
+ *     null stream); she_step / she_run return without waiting; she_stats,
+ *     she_read_field, she_get_state synchronise that stream;
+ *   - host pointers are caller-owned and only read/written during the call;
+ *   - one handle must not be used from two host threads at once;
+ *   - device memory is allocated at she_create and freed at she_destroy,
+ *     or carved from a caller-owned device arena (she_config.arena), which the
+ *     caller keeps alive until she_destroy.
+ */
+#ifndef SHE_H
+#define SHE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct she_handle she_handle;
+
+typedef enum {
+    SHE_OK = 0,
+    SHE_EINVAL = -1,       /* invalid argument or configuration               */
+    SHE_EUNSTABLE = -2,    /* r above the explicit stability limit 1/(2 dim)  */
+    SHE_ENOMEM = -3,       /* device allocation failed / arena too small      */
+    SHE_EDEVICE = -4,      /* HIP runtime error                               */
+    SHE_ENONFINITE = -5,   /* a sample met a non-finite value; state frozen   */
+    SHE_ESTATE = -6,       /* checkpoint blob does not match this handle      */
+    SHE_EUNSUPPORTED = -7  /* valid in the method, not provided by a kernel   */
+} she_status;
+
+enum { SHE_HEAT = 0, SHE_SPECIES = 1 };                       /* equation      */
+enum { SHE_PERIODIC = 0, SHE_DIRICHLET = 1 };                 /* x boundary    */
+enum { SHE_EM = 0, SHE_HEUN = 1 };                            /* FE / PC       */
+enum { SHE_NOISE_INSTANT = 0, SHE_NOISE_FROZEN = 1, SHE_NOISE_OFF = 2 };
+enum { SHE_F32 = 0, SHE_F64 = 1 };                            /* state type    */
+
+/* statistics selected in she_config.stats_mask */
+enum {
+    SHE_STAT_MOMENTS = 1,  /* 1D: per-cell FP64 sums of dU and dU^2           */
+    SHE_STAT_CORR = 2,     /* 1D: full N x N covariance (MFMA X^T X blocks)   */
+    SHE_STAT_SK = 4,       /* nD: radially binned S(k) (FFT per sample);
+                              1D: S_k comes from the covariance (needs CORR)  */
+    SHE_STAT_SPATIAL = 8   /* per-instance spatial mean / variance per sample */
+};
+
+/* One instance (realisation) of the scheme.  Dirichlet walls only in 1D. */
+typedef struct {
+    int32_t dim;          /* 1, 2, 3                                          */
+    int32_t n[3];         /* cells per axis, unused axes = 1.  2D/3D: n[0] a
+                             power of two in [8, 1024]                         */
+    int32_t eq;           /* SHE_HEAT or SHE_SPECIES                          */
+    int32_t bc;           /* SHE_PERIODIC or SHE_DIRICHLET (dim == 1)         */
+    int32_t scheme;       /* SHE_EM or SHE_HEUN                               */
+    int32_t noise;        /* SHE_NOISE_*: face amplitude from the current
+                             state (paper's practice), from the deterministic
+                             profile (footnote of Sec. 2), or no noise        */
+    double r;             /* kappa dt/dx^2 (SHE) or D dt/dx^2 (DK)            */
+    double eps;           /* k_B/(rho c_V dV) (SHE) or 1/dV (DK)               */
+    double u0;            /* periodic: initial and reference value             */
+    double u_left;        /* Dirichlet wall values (x = 0 and x = L)           */
+    double u_right;
+    double init_sd;       /* std. dev. of the initial perturbation (tag 1)     */
+    uint64_t seed;        /* Philox key                                        */
+    uint32_t realisation; /* Philox counter word 3                             */
+    uint32_t reserved;    /* must be 0                                         */
+} she_instance_desc;
+
+typedef struct {
+    int32_t n_instances;
+    int32_t precision;            /* SHE_F32 or SHE_F64 for the state         */
+    const she_instance_desc *inst;/* n_instances entries, copied at create.
+                                     1D instances may differ in every field;
+                                     2D/3D instances must share all fields
+                                     except seed and realisation              */
+    int64_t burn_in;              /* sample after completed step t when
+                                     t > burn_in and t % sample_every == 0    */
+    int32_t sample_every;         /* >= 1                                      */
+    uint32_t stats_mask;          /* SHE_STAT_* bits                           */
+    int32_t block_threads;        /* tuning: 1D threads per instance (0 auto) */
+    int32_t rows_per_block;       /* tuning: 2D/3D march length (0 auto)      */
+    int32_t rows_per_group;       /* tuning: 3D rows per workgroup (0 auto)   */
+    int32_t reserved;             /* must be 0                                 */
+    void *stream;                 /* hipStream_t (e.g. torch's current stream)*/
+    void *arena;                  /* optional device memory for all buffers   */
+    size_t arena_bytes;
+} she_config;
+
+/* Results of one instance; caller-owned arrays with their capacities (in
+ * elements).  A NULL array is skipped; a too small capacity is SHE_EINVAL. */
+typedef struct {
+    int64_t n_samples;            /* samples taken since create / reset       */
+    int64_t steps;                /* completed steps                           */
+    double *mean;   int64_t mean_cap;  /* 1D: N time-averaged U_i;
+                                          nD: 1, time-averaged spatial mean   */
+    double *var;    int64_t var_cap;   /* 1D: N population variances;
+                                          nD: 1, time-averaged spatial var.   */
+    double *corr;   int64_t corr_cap;  /* 1D + CORR: N*N covariance, row-major */
+    double *sk;     int64_t sk_cap;    /* 1D + CORR: N values <|U_k|^2>;
+                                          nD + SK: shell averages, shell
+                                          round(|k|), signed k in [-N/2,N/2)  */
+    double *sk_modes; int64_t sk_modes_cap; /* nD: modes per shell            */
+    double sum_u;                 /* current sum of U over the cells (FP64)   */
+    int32_t nonfinite;            /* 1 if a sample met a non-finite value      */
+    int32_t reserved;
+    int64_t clamp_count;          /* DK: face evaluations with negative mean  */
+} she_stats_out;
+
+/* Validate cfg, allocate device buffers, write the initial state (steady
+ * profile + init_sd * N(tag 1)).  r > 1/(2 dim) is SHE_EUNSTABLE; periodic
+ * with u_left != u_right or Dirichlet in 2D/3D is SHE_EINVAL (the paper's
+ * program refuses a gradient with periodic walls). */
+she_status she_create(const she_config *cfg, she_handle **out);
+
+/* Bytes of device memory she_create needs for cfg (for a caller arena). */
+she_status she_arena_bytes(const she_config *cfg, size_t *bytes);
+
+/* Advance every instance by nsteps steps without sampling.  Async. */
+she_status she_step(she_handle *h, int64_t nsteps);
+
+/* Advance by nsteps steps, sampling by the burn-in / sample_every rule.  Async. */
+she_status she_run(she_handle *h, int64_t nsteps);
+
+/* Finalised statistics of one instance in FP64 (mean = ref + S1/M,
+ * var = S2/M - (S1/M)^2 with the population normalisation of the paper's
+ * program, cov = M2/M - m m^T, S_k).  Synchronises the stream.  Returns
+ * SHE_ENONFINITE (after filling out) if a sample met a non-finite value. */
+she_status she_stats(she_handle *h, int32_t instance, she_stats_out *out);
+
+/* Zero every statistics accumulator (the step count is kept). */
+she_status she_reset_stats(she_handle *h);
+
+/* Copy the current field of one instance to / from host FP64 (n = cells,
+ * x fastest).  read synchronises the stream; write is ordered on it. */
+she_status she_read_field(she_handle *h, int32_t instance, double *host, int64_t n);
+she_status she_write_field(she_handle *h, int32_t instance, const double *host, int64_t n);
+
+/* Completed step count of the handle. */
+she_status she_get_step(const she_handle *h, int64_t *steps);
+
+/* Checkpoint: state + step count + every statistics accumulator, as one
+ * host blob.  Resuming from it reproduces the uninterrupted run bit for bit
+ * (the noise is a function of the step count, not of a generator state). */
+she_status she_state_bytes(const she_handle *h, size_t *bytes);
+she_status she_get_state(she_handle *h, void *host, size_t bytes);
+she_status she_set_state(she_handle *h, const void *host, size_t bytes);
+
+/* Message of the last failed call on h (h == NULL: last she_create failure
+ * of this thread).  Valid until the next call on h. */
+const char *she_last_error(const she_handle *h);
+
+void she_destroy(she_handle *h);
+
+/* Verification entry points (same kernels' device functions):
+ * raw Philox4x32-10 words for count counters (host array 4*count, word 0
+ * first) under key (seed lo, seed hi) -> host out[4*count]; and count
+ * consecutive face normals in FP32 (precision SHE_F32) or FP64, as the step
+ * kernels draw them.  Both run on `stream` and synchronise it. */
+she_status she_debug_philox(uint64_t seed, const uint32_t *ctr, int64_t count,
+                            uint32_t *out, void *stream);
+she_status she_debug_normals(uint64_t seed, uint32_t realisation, uint32_t tag,
+                             uint64_t step, uint64_t face0, int64_t count,
+                             int32_t precision, double *out, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SHE_H */

@@ -1,0 +1,793 @@
+// Host runtime behind include/she.h: validation, device memory plan, launch
+// schedule, finalisation and checkpoints.  No arithmetic of the method lives
+// here beyond the FP64 coefficient sigma = sqrt(2 r eps) (Sec. 3: the face
+// noise alpha dt/dx * N/sqrt(dV dt) of the SHE; Sec. 4 eq. DK with eps = 1/dV).
+#include "she.h"
+#include "she_internal.hpp"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <numeric>
+#include <string>
+#include <vector>
+
+using namespace she;
+
+struct she_handle {
+    std::string err;
+    int dim = 1, prec = 0;
+    size_t esz = 4;
+    int n_inst = 0;
+    std::vector<she_instance_desc> inst;
+    int64_t burn_in = 0;
+    int32_t every = 1;
+    uint32_t mask = 0;
+    hipStream_t stream = nullptr;
+    int64_t steps = 0;
+    int device = 0;
+
+    // device memory
+    bool own = false;
+    char *base = nullptr;
+    size_t bytes = 0;
+
+    InstAcc *d_acc = nullptr;
+    double *d_fin = nullptr;      // finalisation scratch
+    size_t fin_len = 0;
+    double *d_init_sd = nullptr;
+
+    // 1D
+    Inst1D *d_tab = nullptr;
+    int32_t *d_order = nullptr;
+    void *d_pool = nullptr;
+    std::vector<Inst1D> tab;
+    int64_t total_cells = 0;
+    double *d_s1 = nullptr, *d_s2 = nullptr;
+    void *d_x = nullptr;
+    double *d_c = nullptr;
+    int64_t x_elems = 0, c_elems = 0;
+    int block1d = 64, maxg = 1, nmax = 0;
+    size_t smem1d = 0;
+
+    // 2D / 3D
+    ParamsND pnd{};
+    int64_t cells = 0;            // per instance
+    void *d_a = nullptr, *d_b = nullptr;
+    int cur = 0;                  // 0: state in d_a
+    uint32_t *d_real = nullptr;
+    double *d_part = nullptr;
+    int nparts = 0, cx = 4, ty = 1, nd_blocks = 0;
+    size_t smem3d = 0;
+    // 2D structure factor
+    int nbins = 0, sk_groups = 0;
+    void *d_half = nullptr;
+    double *d_skpart = nullptr, *d_sksum = nullptr, *d_skmodes = nullptr;
+    std::vector<double> skmodes;
+
+    void *field() const { return dim == 1 ? d_pool : (cur == 0 ? d_a : d_b); }
+};
+
+static thread_local std::string g_create_err;
+
+namespace {
+
+she_status fail(she_handle *h, she_status st, const std::string &msg)
+{
+    if (h)
+        h->err = msg;
+    else
+        g_create_err = msg;
+    return st;
+}
+
+she_status hipfail(she_handle *h, hipError_t e, const char *what)
+{
+    return fail(h, SHE_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define SHE_HIP(h, call)                                   \
+    do {                                                   \
+        hipError_t e_ = (call);                            \
+        if (e_ != hipSuccess) return hipfail((h), e_, #call); \
+    } while (0)
+
+bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
+
+size_t align256(size_t v) { return (v + 255) & ~static_cast<size_t>(255); }
+
+// Memory plan: a list of (pointer slot, bytes); carved in order from one block.
+struct Plan {
+    std::vector<std::pair<void **, size_t>> items;
+    size_t total = 0;
+    void add(void **slot, size_t bytes)
+    {
+        items.emplace_back(slot, bytes);
+        total += align256(bytes);
+    }
+    void carve(char *base)
+    {
+        size_t off = 0;
+        for (auto &it : items) {
+            *it.first = it.second ? base + off : nullptr;
+            off += align256(it.second);
+        }
+    }
+};
+
+she_status validate(const she_config *cfg, she_handle *h)
+{
+    if (!cfg) return fail(nullptr, SHE_EINVAL, "config is NULL");
+    if (cfg->n_instances < 1 || !cfg->inst) return fail(nullptr, SHE_EINVAL, "need at least one instance");
+    if (cfg->precision != SHE_F32 && cfg->precision != SHE_F64)
+        return fail(nullptr, SHE_EINVAL, "precision must be SHE_F32 or SHE_F64");
+    if (cfg->sample_every < 1) return fail(nullptr, SHE_EINVAL, "sample_every must be >= 1");
+    if (cfg->burn_in < 0) return fail(nullptr, SHE_EINVAL, "burn_in must be >= 0");
+    if (cfg->reserved != 0) return fail(nullptr, SHE_EINVAL, "reserved field must be 0");
+    if (cfg->stats_mask & ~0xFu) return fail(nullptr, SHE_EINVAL, "unknown stats_mask bits");
+    const int dim = cfg->inst[0].dim;
+    for (int i = 0; i < cfg->n_instances; ++i) {
+        const she_instance_desc &d = cfg->inst[i];
+        char buf[160];
+        std::snprintf(buf, sizeof buf, "instance %d: ", i);
+        const std::string pre(buf);
+        if (d.dim != dim) return fail(nullptr, SHE_EINVAL, pre + "all instances must have the same dim");
+        if (d.dim < 1 || d.dim > 3) return fail(nullptr, SHE_EINVAL, pre + "dim must be 1, 2 or 3");
+        for (int a = 0; a < 3; ++a) {
+            if (a < d.dim && d.n[a] < 1) return fail(nullptr, SHE_EINVAL, pre + "cell counts must be >= 1");
+            if (a >= d.dim && d.n[a] != 1) return fail(nullptr, SHE_EINVAL, pre + "unused axes must have n = 1");
+        }
+        if (d.eq != SHE_HEAT && d.eq != SHE_SPECIES) return fail(nullptr, SHE_EINVAL, pre + "bad equation");
+        if (d.bc != SHE_PERIODIC && d.bc != SHE_DIRICHLET) return fail(nullptr, SHE_EINVAL, pre + "bad boundary");
+        if (d.scheme != SHE_EM && d.scheme != SHE_HEUN) return fail(nullptr, SHE_EINVAL, pre + "bad scheme");
+        if (d.noise < 0 || d.noise > 2) return fail(nullptr, SHE_EINVAL, pre + "bad noise mode");
+        if (d.reserved != 0) return fail(nullptr, SHE_EINVAL, pre + "reserved field must be 0");
+        if (!(d.r >= 0.0) || !(d.eps >= 0.0) || !(d.init_sd >= 0.0) || !std::isfinite(d.u0) ||
+            !std::isfinite(d.u_left) || !std::isfinite(d.u_right))
+            return fail(nullptr, SHE_EINVAL, pre + "r, eps, init_sd must be >= 0 and values finite");
+        if (d.r > 0.5 / d.dim)
+            return fail(nullptr, SHE_EUNSTABLE, pre + "r above the explicit stability limit 1/(2 dim)");
+        if (d.bc == SHE_DIRICHLET && d.dim != 1)
+            return fail(nullptr, SHE_EINVAL, pre + "Dirichlet walls are provided in 1D only");
+        if (d.bc == SHE_PERIODIC && d.u_left != d.u_right)
+            return fail(nullptr, SHE_EINVAL, pre + "a wall gradient needs Dirichlet walls, not periodic");
+        if (d.dim == 1 && d.bc == SHE_PERIODIC && d.n[0] < 2)
+            return fail(nullptr, SHE_EINVAL, pre + "periodic 1D needs N >= 2");
+    }
+    (void)h;
+    return SHE_OK;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ create
+
+static she_status plan_1d(she_handle *h, const she_config *cfg, Plan &plan)
+{
+    const size_t es = h->esz;
+    h->tab.resize(h->n_inst);
+    int64_t off = 0, xo = 0, co = 0;
+    int nfg_max = 0;
+    const bool corr = (h->mask & SHE_STAT_CORR) != 0;
+    for (int i = 0; i < h->n_inst; ++i) {
+        const she_instance_desc &d = h->inst[i];
+        Inst1D &t = h->tab[i];
+        t.off = off;
+        t.n = d.n[0];
+        t.bc = d.bc;
+        t.scheme = d.scheme;
+        t.noise = d.noise;
+        t.eq = d.eq;
+        t.realisation = d.realisation;
+        t.seed = d.seed;
+        t.r = d.r;
+        t.sigma = std::sqrt(2.0 * d.r * d.eps);
+        t.u0 = d.u0;
+        t.uL = d.bc == SHE_DIRICHLET ? d.u_left : d.u0;
+        t.uR = d.bc == SHE_DIRICHLET ? d.u_right : d.u0;
+        if (corr) {
+            if (d.n[0] > 1024) return fail(nullptr, SHE_EUNSUPPORTED, "SHE_STAT_CORR needs N <= 1024");
+            t.x_off = xo;
+            t.c_off = co;
+            xo += static_cast<int64_t>(kCorrBlock) * d.n[0];
+            co += static_cast<int64_t>(d.n[0]) * d.n[0];
+        } else {
+            t.x_off = -1;
+            t.c_off = -1;
+        }
+        off += d.n[0];
+        h->nmax = std::max(h->nmax, d.n[0]);
+        const int nf = d.bc == SHE_DIRICHLET ? d.n[0] + 1 : d.n[0];
+        nfg_max = std::max(nfg_max, (nf + 3) / 4);
+    }
+    h->total_cells = off;
+    h->x_elems = xo;
+    h->c_elems = co;
+    // launch shape: threads per instance and Philox blocks per thread
+    int block = cfg->block_threads;
+    if (block == 0) block = nfg_max <= 128 ? 64 : 256;
+    if (block != 64 && block != 256) return fail(nullptr, SHE_EINVAL, "block_threads must be 0, 64 or 256");
+    int g = (nfg_max + block - 1) / block;
+    int maxg = 1;
+    while (maxg < g) maxg *= 2;
+    if (maxg > 8) return fail(nullptr, SHE_EUNSUPPORTED, "1D instance too large for the resident kernel");
+    h->block1d = block;
+    h->maxg = maxg;
+    const size_t nmax_pad = (h->nmax + 4) & ~3;
+    h->smem1d = (3 * nmax_pad + 8) * es;
+    if (h->smem1d > 64 * 1024)
+        return fail(nullptr, SHE_EUNSUPPORTED, "1D instance too large for LDS (64 KB per workgroup)");
+
+    plan.add(reinterpret_cast<void **>(&h->d_tab), sizeof(Inst1D) * h->n_inst);
+    plan.add(reinterpret_cast<void **>(&h->d_order), sizeof(int32_t) * h->n_inst);
+    plan.add(&h->d_pool, es * off);
+    if (h->mask & (SHE_STAT_MOMENTS | SHE_STAT_CORR)) {
+        plan.add(reinterpret_cast<void **>(&h->d_s1), sizeof(double) * off);
+        plan.add(reinterpret_cast<void **>(&h->d_s2), sizeof(double) * off);
+    }
+    if (corr) {
+        plan.add(&h->d_x, es * xo);
+        plan.add(reinterpret_cast<void **>(&h->d_c), sizeof(double) * co);
+    }
+    h->fin_len = 4 * static_cast<size_t>(h->nmax) + 2 * static_cast<size_t>(h->nmax) * h->nmax + 8;
+    return SHE_OK;
+}
+
+static she_status plan_nd(she_handle *h, const she_config *cfg, Plan &plan)
+{
+    const she_instance_desc &d0 = h->inst[0];
+    for (int i = 1; i < h->n_inst; ++i) {
+        const she_instance_desc &d = h->inst[i];
+        if (d.n[0] != d0.n[0] || d.n[1] != d0.n[1] || d.n[2] != d0.n[2] || d.eq != d0.eq || d.scheme != d0.scheme ||
+            d.noise != d0.noise || d.r != d0.r || d.eps != d0.eps || d.u0 != d0.u0 || d.init_sd != d0.init_sd ||
+            d.seed != d0.seed)
+            return fail(nullptr, SHE_EUNSUPPORTED,
+                        "2D/3D batches must share every field except the realisation number");
+    }
+    const int nx = d0.n[0];
+    if (!is_pow2(nx) || nx < 8 || nx > 1024)
+        return fail(nullptr, SHE_EUNSUPPORTED, "2D/3D kernels need n[0] a power of two in [8, 1024]");
+    if (h->mask & (SHE_STAT_CORR | SHE_STAT_MOMENTS))
+        return fail(nullptr, SHE_EUNSUPPORTED, "2D/3D statistics are SHE_STAT_SPATIAL (and SHE_STAT_SK)");
+    if (h->mask & SHE_STAT_SK) {
+        if (d0.dim != 2 || !is_pow2(d0.n[1]) || d0.n[1] < 2)
+            return fail(nullptr, SHE_EUNSUPPORTED, "SHE_STAT_SK is provided for 2D grids with n[1] a power of two");
+        h->mask |= SHE_STAT_SPATIAL;
+    }
+    int cx = 4;
+    while (nx / cx > 64) cx *= 2;
+    h->cx = cx;
+    const int LX = nx / cx;
+    ParamsND &p = h->pnd;
+    p.nx = nx;
+    p.ny = d0.n[1];
+    p.nz = d0.n[2];
+    p.dim = d0.dim;
+    p.eq = d0.eq;
+    p.scheme = d0.scheme;
+    p.noise = d0.noise;
+    p.n_inst = h->n_inst;
+    p.r = d0.r;
+    p.sigma = std::sqrt(2.0 * d0.r * d0.eps);
+    p.u0 = d0.u0;
+    p.seed = d0.seed;
+    h->cells = static_cast<int64_t>(p.nx) * p.ny * p.nz;
+    if (d0.dim == 2) {
+        // default march length: about 4096 row groups in flight, 1..32 rows each
+        int chunk = cfg->rows_per_block;
+        if (chunk <= 0) chunk = std::max(1, std::min(32, static_cast<int>(static_cast<int64_t>(h->n_inst) * p.ny / 4096)));
+        chunk = std::min(chunk, p.ny);
+        p.chunk = chunk;
+        const int nchunks = (p.ny + chunk - 1) / chunk;
+        h->nparts = nchunks;
+        const int gpb = 256 / LX;
+        h->nd_blocks = (h->n_inst * nchunks + gpb - 1) / gpb;
+    } else {
+        if (d0.scheme != SHE_EM) return fail(nullptr, SHE_EUNSUPPORTED, "3D kernel provides the FE scheme only");
+        int ty = cfg->rows_per_group;
+        if (ty == 0) {
+            ty = 1;
+            for (int c = 1; c <= p.ny; ++c)
+                if (p.ny % c == 0 && LX * c <= 256) ty = c;
+        }
+        if (ty < 1 || p.ny % ty != 0 || LX * ty > 256)
+            return fail(nullptr, SHE_EINVAL, "rows_per_group must divide n[1] with (n[0]/cx)*rows <= 256");
+        h->ty = ty;
+        int chunk = cfg->rows_per_block > 0 ? cfg->rows_per_block : 8;
+        chunk = std::min(chunk, p.nz);
+        p.chunk = chunk;
+        const int nzc = (p.nz + chunk - 1) / chunk;
+        h->nparts = (p.ny / ty) * nzc;
+        h->nd_blocks = h->n_inst * h->nparts;
+        h->smem3d = std::max(4 * static_cast<size_t>(ty) * nx * h->esz, 2 * sizeof(double) * ty);
+        if (h->smem3d > 64 * 1024) return fail(nullptr, SHE_EUNSUPPORTED, "3D tile exceeds 64 KB of LDS");
+    }
+    const size_t es = h->esz;
+    const size_t fbytes = es * static_cast<size_t>(h->cells) * h->n_inst;
+    plan.add(&h->d_a, fbytes);
+    plan.add(&h->d_b, fbytes);
+    plan.add(reinterpret_cast<void **>(&h->d_real), sizeof(uint32_t) * h->n_inst);
+    plan.add(reinterpret_cast<void **>(&h->d_part), 2 * sizeof(double) * h->nparts * h->n_inst);
+    h->fin_len = 8;
+    if (h->mask & SHE_STAT_SK) {
+        // shells round(|k|), signed k in [-N/2, N/2); mode counts per shell
+        const double kmax = std::sqrt(0.25 * nx * nx + 0.25 * p.ny * p.ny);
+        h->nbins = static_cast<int>(std::floor(kmax + 0.5)) + 1;
+        h->skmodes.assign(h->nbins, 0.0);
+        for (int ky = 0; ky < p.ny; ++ky)
+            for (int kx = 0; kx < nx; ++kx) {
+                const double sx = 2 * kx < nx ? kx : kx - nx, sy = 2 * ky < p.ny ? ky : ky - p.ny;
+                const int b = static_cast<int>(std::floor(std::sqrt(sx * sx + sy * sy) + 0.5));
+                if (b < h->nbins) h->skmodes[b] += 1.0;
+            }
+        h->sk_groups = sk2d_groups(h->prec, nx, p.ny);
+        const size_t nh = static_cast<size_t>(nx / 2 + 1);
+        plan.add(&h->d_half, 2 * es * nh * p.ny * h->n_inst);
+        plan.add(reinterpret_cast<void **>(&h->d_skpart), sizeof(double) * h->n_inst * h->sk_groups * h->nbins);
+        plan.add(reinterpret_cast<void **>(&h->d_sksum), sizeof(double) * h->n_inst * h->nbins);
+        plan.add(reinterpret_cast<void **>(&h->d_skmodes), sizeof(double) * h->nbins);
+        h->fin_len = 3 + h->nbins;
+    }
+    return SHE_OK;
+}
+
+static she_status build_plan(she_handle *h, const she_config *cfg, Plan &plan)
+{
+    h->dim = cfg->inst[0].dim;
+    h->prec = cfg->precision;
+    h->esz = cfg->precision == SHE_F32 ? 4 : 8;
+    h->n_inst = cfg->n_instances;
+    h->inst.assign(cfg->inst, cfg->inst + cfg->n_instances);
+    h->burn_in = cfg->burn_in;
+    h->every = cfg->sample_every;
+    h->mask = cfg->stats_mask;
+    if (h->mask & SHE_STAT_CORR) h->mask |= SHE_STAT_MOMENTS;
+    h->stream = static_cast<hipStream_t>(cfg->stream);
+    she_status st = h->dim == 1 ? plan_1d(h, cfg, plan) : plan_nd(h, cfg, plan);
+    if (st != SHE_OK) return st;
+    plan.add(reinterpret_cast<void **>(&h->d_acc), sizeof(InstAcc) * h->n_inst);
+    plan.add(reinterpret_cast<void **>(&h->d_init_sd), sizeof(double) * h->n_inst);
+    plan.add(reinterpret_cast<void **>(&h->d_fin), sizeof(double) * h->fin_len);
+    return SHE_OK;
+}
+
+extern "C" she_status she_arena_bytes(const she_config *cfg, size_t *bytes)
+{
+    if (!bytes) return fail(nullptr, SHE_EINVAL, "bytes is NULL");
+    she_status st = validate(cfg, nullptr);
+    if (st != SHE_OK) return st;
+    she_handle tmp;
+    Plan plan;
+    st = build_plan(&tmp, cfg, plan);
+    if (st != SHE_OK) return st;
+    *bytes = plan.total;
+    return SHE_OK;
+}
+
+static she_status zero_stats(she_handle *h)
+{
+    hipStream_t s = h->stream;
+    SHE_HIP(h, hipMemsetAsync(h->d_acc, 0, sizeof(InstAcc) * h->n_inst, s));
+    if (h->d_s1) SHE_HIP(h, hipMemsetAsync(h->d_s1, 0, sizeof(double) * h->total_cells, s));
+    if (h->d_s2) SHE_HIP(h, hipMemsetAsync(h->d_s2, 0, sizeof(double) * h->total_cells, s));
+    if (h->d_x) SHE_HIP(h, hipMemsetAsync(h->d_x, 0, h->esz * h->x_elems, s));
+    if (h->d_c) SHE_HIP(h, hipMemsetAsync(h->d_c, 0, sizeof(double) * h->c_elems, s));
+    if (h->d_sksum) SHE_HIP(h, hipMemsetAsync(h->d_sksum, 0, sizeof(double) * h->n_inst * h->nbins, s));
+    return SHE_OK;
+}
+
+extern "C" she_status she_create(const she_config *cfg, she_handle **out)
+{
+    if (!out) return fail(nullptr, SHE_EINVAL, "out is NULL");
+    *out = nullptr;
+    she_status st = validate(cfg, nullptr);
+    if (st != SHE_OK) return st;
+    she_handle *h = new she_handle();
+    Plan plan;
+    st = build_plan(h, cfg, plan);
+    if (st != SHE_OK) {
+        delete h;
+        return st;
+    }
+    hipError_t e = hipGetDevice(&h->device);
+    if (e != hipSuccess) {
+        delete h;
+        return fail(nullptr, SHE_EDEVICE, std::string("hipGetDevice: ") + hipGetErrorString(e));
+    }
+    if (cfg->arena) {
+        if (cfg->arena_bytes < plan.total) {
+            char buf[128];
+            std::snprintf(buf, sizeof buf, "arena too small: %zu bytes needed", plan.total);
+            delete h;
+            return fail(nullptr, SHE_ENOMEM, buf);
+        }
+        if (reinterpret_cast<uintptr_t>(cfg->arena) % 256 != 0) {
+            delete h;
+            return fail(nullptr, SHE_EINVAL, "arena must be 256-byte aligned");
+        }
+        h->base = static_cast<char *>(cfg->arena);
+        h->own = false;
+    } else {
+        e = hipMalloc(reinterpret_cast<void **>(&h->base), plan.total);
+        if (e != hipSuccess) {
+            delete h;
+            return fail(nullptr, SHE_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+        }
+        h->own = true;
+    }
+    h->bytes = plan.total;
+    plan.carve(h->base);
+
+    hipStream_t s = h->stream;
+    std::vector<double> sd(h->n_inst);
+    for (int i = 0; i < h->n_inst; ++i) sd[i] = h->inst[i].init_sd;
+#define CREATE_HIP(call)                                          \
+    do {                                                          \
+        hipError_t e_ = (call);                                   \
+        if (e_ != hipSuccess) {                                   \
+            std::string m_ = std::string(#call) + ": " + hipGetErrorString(e_); \
+            she_destroy(h);                                       \
+            return fail(nullptr, SHE_EDEVICE, m_);                \
+        }                                                         \
+    } while (0)
+    CREATE_HIP(hipMemcpyAsync(h->d_init_sd, sd.data(), sizeof(double) * h->n_inst, hipMemcpyHostToDevice, s));
+    if (h->dim == 1) {
+        // largest instances first (longest-processing-time order of the workgroups)
+        std::vector<int32_t> order(h->n_inst);
+        std::iota(order.begin(), order.end(), 0);
+        std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+            const int64_t wa = static_cast<int64_t>(h->tab[a].n) * (1 + h->tab[a].scheme);
+            const int64_t wb = static_cast<int64_t>(h->tab[b].n) * (1 + h->tab[b].scheme);
+            return wa > wb;
+        });
+        CREATE_HIP(hipMemcpyAsync(h->d_tab, h->tab.data(), sizeof(Inst1D) * h->n_inst, hipMemcpyHostToDevice, s));
+        CREATE_HIP(hipMemcpyAsync(h->d_order, order.data(), sizeof(int32_t) * h->n_inst, hipMemcpyHostToDevice, s));
+        CREATE_HIP(launch_init1d(h->prec, h->n_inst, h->nmax, s, h->d_tab, h->d_init_sd, h->d_pool));
+    } else {
+        std::vector<uint32_t> real(h->n_inst);
+        for (int i = 0; i < h->n_inst; ++i) real[i] = h->inst[i].realisation;
+        CREATE_HIP(hipMemcpyAsync(h->d_real, real.data(), sizeof(uint32_t) * h->n_inst, hipMemcpyHostToDevice, s));
+        h->pnd.realisation = h->d_real;
+        if (h->d_skmodes)
+            CREATE_HIP(hipMemcpyAsync(h->d_skmodes, h->skmodes.data(), sizeof(double) * h->nbins,
+                                      hipMemcpyHostToDevice, s));
+        CREATE_HIP(launch_initnd(h->prec, s, h->pnd, h->cells, h->inst[0].init_sd, h->d_a));
+        h->cur = 0;
+    }
+    // staged host copies must stay valid until the stream has consumed them
+    CREATE_HIP(hipStreamSynchronize(s));
+#undef CREATE_HIP
+    if (zero_stats(h) != SHE_OK) {
+        std::string m = h->err;
+        she_destroy(h);
+        return fail(nullptr, SHE_EDEVICE, m);
+    }
+    *out = h;
+    return SHE_OK;
+}
+
+extern "C" void she_destroy(she_handle *h)
+{
+    if (!h) return;
+    if (h->own && h->base) {
+        (void)hipStreamSynchronize(h->stream);
+        (void)hipFree(h->base);
+    }
+    delete h;
+}
+
+extern "C" const char *she_last_error(const she_handle *h)
+{
+    return h ? h->err.c_str() : g_create_err.c_str();
+}
+
+// ------------------------------------------------------------------ stepping
+
+static she_status advance(she_handle *h, int64_t nsteps, bool sampling)
+{
+    if (!h) return fail(nullptr, SHE_EINVAL, "handle is NULL");
+    if (nsteps < 0) return fail(h, SHE_EINVAL, "nsteps must be >= 0");
+    if (nsteps == 0) return SHE_OK;
+    hipStream_t s = h->stream;
+    if (h->dim == 1) {
+        Stats1D st{h->d_s1, h->d_s2, h->d_x, h->d_c, h->d_acc};
+        const bool stats = sampling && h->mask != 0;
+        const int64_t chunk = 1 << 16;
+        for (int64_t done = 0; done < nsteps;) {
+            const int32_t k = static_cast<int32_t>(std::min<int64_t>(chunk, nsteps - done));
+            SHE_HIP(h, launch_step1d(h->prec, h->block1d, h->maxg, stats, h->n_inst, h->smem1d, s, h->d_tab,
+                                     h->d_order, h->d_pool, h->steps, k, h->burn_in, h->every, h->mask, st));
+            h->steps += k;
+            done += k;
+        }
+        return SHE_OK;
+    }
+    const double inv_cells = 1.0 / static_cast<double>(h->cells);
+    for (int64_t k = 0; k < nsteps; ++k) {
+        const int64_t t = h->steps + 1;
+        const int sample = sampling && (h->mask & SHE_STAT_SPATIAL) && t > h->burn_in && t % h->every == 0;
+        const void *src = h->cur == 0 ? h->d_a : h->d_b;
+        void *dst = h->cur == 0 ? h->d_b : h->d_a;
+        if (h->dim == 2)
+            SHE_HIP(h, launch_step2d(h->prec, h->cx, h->pnd.eq, h->pnd.scheme, h->nd_blocks, s, h->pnd, src, dst,
+                                     h->steps, sample, h->d_part, h->d_acc));
+        else
+            SHE_HIP(h, launch_step3d(h->prec, h->cx, h->pnd.eq, h->ty, h->nd_blocks, h->smem3d, s, h->pnd, src, dst,
+                                     h->steps, sample, h->d_part, h->d_acc));
+        if (sample) {
+            SHE_HIP(h, launch_reduce_parts(h->n_inst, s, h->d_part, h->nparts, inv_cells, h->d_acc));
+            if (h->mask & SHE_STAT_SK)
+                SHE_HIP(h, launch_sk2d(h->prec, s, h->n_inst, h->pnd.nx, h->pnd.ny, h->pnd.u0, dst, h->d_half,
+                                       h->d_skpart, h->nbins, h->d_sksum, h->d_acc));
+        }
+        h->cur ^= 1;
+        h->steps += 1;
+    }
+    return SHE_OK;
+}
+
+extern "C" she_status she_step(she_handle *h, int64_t nsteps) { return advance(h, nsteps, false); }
+
+extern "C" she_status she_run(she_handle *h, int64_t nsteps) { return advance(h, nsteps, true); }
+
+extern "C" she_status she_get_step(const she_handle *h, int64_t *steps)
+{
+    if (!h || !steps) return SHE_EINVAL;
+    *steps = h->steps;
+    return SHE_OK;
+}
+
+extern "C" she_status she_reset_stats(she_handle *h)
+{
+    if (!h) return fail(nullptr, SHE_EINVAL, "handle is NULL");
+    return zero_stats(h);
+}
+
+// ------------------------------------------------------------------ results
+
+static she_status copy_out(she_handle *h, double *dst, int64_t cap, const double *src, int64_t n, const char *what)
+{
+    if (!dst) return SHE_OK;
+    if (cap < n) return fail(h, SHE_EINVAL, std::string("capacity too small for ") + what);
+    std::memcpy(dst, src, sizeof(double) * n);
+    return SHE_OK;
+}
+
+extern "C" she_status she_stats(she_handle *h, int32_t instance, she_stats_out *out)
+{
+    if (!h || !out) return fail(h, SHE_EINVAL, "NULL argument");
+    if (instance < 0 || instance >= h->n_inst) return fail(h, SHE_EINVAL, "instance out of range");
+    hipStream_t s = h->stream;
+    InstAcc acc;
+    SHE_HIP(h, hipMemcpyAsync(&acc, h->d_acc + instance, sizeof(InstAcc), hipMemcpyDeviceToHost, s));
+    SHE_HIP(h, hipStreamSynchronize(s));
+    out->n_samples = acc.n_samples;
+    out->steps = h->steps;
+    out->nonfinite = acc.nonfinite;
+    out->clamp_count = acc.clamp_count;
+    if (h->dim == 1) {
+        const int N = h->tab[instance].n;
+        const bool corr = h->tab[instance].x_off >= 0;
+        const int rows = static_cast<int>(acc.n_samples % kCorrBlock);
+        SHE_HIP(h, launch_fin1d(h->prec, s, h->d_tab, instance, N, h->d_pool, h->d_s1, h->d_s2,
+                                corr ? static_cast<char *>(h->d_x) + h->esz * h->tab[instance].x_off : nullptr,
+                                corr ? h->d_c + h->tab[instance].c_off : nullptr, acc.n_samples, rows, corr,
+                                h->d_fin));
+        const size_t len = 4 * static_cast<size_t>(N) + 2 * static_cast<size_t>(N) * N + 1;
+        std::vector<double> host(len);
+        SHE_HIP(h, hipMemcpyAsync(host.data(), h->d_fin, sizeof(double) * len, hipMemcpyDeviceToHost, s));
+        SHE_HIP(h, hipStreamSynchronize(s));
+        const int64_t nn = static_cast<int64_t>(N) * N;
+        she_status st;
+        if (h->d_s1 == nullptr && (out->mean || out->var))
+            return fail(h, SHE_EINVAL, "per-cell mean/var need SHE_STAT_MOMENTS");
+        if ((st = copy_out(h, out->mean, out->mean_cap, host.data(), N, "mean")) != SHE_OK) return st;
+        if ((st = copy_out(h, out->var, out->var_cap, host.data() + N, N, "var")) != SHE_OK) return st;
+        if ((out->corr || out->sk) && !corr) return fail(h, SHE_EINVAL, "corr / sk need SHE_STAT_CORR");
+        if ((st = copy_out(h, out->corr, out->corr_cap, host.data() + 2 * N, nn, "corr")) != SHE_OK) return st;
+        if ((st = copy_out(h, out->sk, out->sk_cap, host.data() + 2 * N + nn, N, "sk")) != SHE_OK) return st;
+        out->sum_u = host[3 * N + 2 * nn];
+    } else {
+        SHE_HIP(h, launch_finnd(h->prec, s, h->pnd, instance, h->cells, h->field(), h->d_acc, h->d_sksum,
+                                h->d_skmodes, h->nbins, h->d_fin));
+        std::vector<double> host(3 + h->nbins);
+        SHE_HIP(h, hipMemcpyAsync(host.data(), h->d_fin, sizeof(double) * host.size(), hipMemcpyDeviceToHost, s));
+        SHE_HIP(h, hipStreamSynchronize(s));
+        she_status st;
+        if ((st = copy_out(h, out->mean, out->mean_cap, host.data(), 1, "mean")) != SHE_OK) return st;
+        if ((st = copy_out(h, out->var, out->var_cap, host.data() + 1, 1, "var")) != SHE_OK) return st;
+        if (out->corr) return fail(h, SHE_EINVAL, "corr is 1D only");
+        if ((out->sk || out->sk_modes) && h->nbins == 0) return fail(h, SHE_EINVAL, "sk needs SHE_STAT_SK (2D)");
+        if ((st = copy_out(h, out->sk, out->sk_cap, host.data() + 3, h->nbins, "sk")) != SHE_OK) return st;
+        if ((st = copy_out(h, out->sk_modes, out->sk_modes_cap, h->skmodes.data(), h->nbins, "sk_modes")) != SHE_OK)
+            return st;
+        out->sum_u = host[2];
+    }
+    if (acc.nonfinite) return fail(h, SHE_ENONFINITE, "a sample met a non-finite value; state frozen");
+    return SHE_OK;
+}
+
+static int64_t inst_cells(const she_handle *h, int i)
+{
+    return h->dim == 1 ? h->tab[i].n : h->cells;
+}
+
+static char *inst_field(const she_handle *h, int i)
+{
+    const int64_t off = h->dim == 1 ? h->tab[i].off : static_cast<int64_t>(i) * h->cells;
+    return static_cast<char *>(h->field()) + h->esz * off;
+}
+
+extern "C" she_status she_read_field(she_handle *h, int32_t instance, double *host, int64_t n)
+{
+    if (!h || !host) return fail(h, SHE_EINVAL, "NULL argument");
+    if (instance < 0 || instance >= h->n_inst) return fail(h, SHE_EINVAL, "instance out of range");
+    const int64_t nc = inst_cells(h, instance);
+    if (n != nc) return fail(h, SHE_EINVAL, "n must equal the instance's cell count");
+    std::vector<char> buf(h->esz * nc);
+    SHE_HIP(h, hipMemcpyAsync(buf.data(), inst_field(h, instance), buf.size(), hipMemcpyDeviceToHost, h->stream));
+    SHE_HIP(h, hipStreamSynchronize(h->stream));
+    for (int64_t i = 0; i < nc; ++i)
+        host[i] = h->prec == SHE_F32 ? static_cast<double>(reinterpret_cast<float *>(buf.data())[i])
+                                     : reinterpret_cast<double *>(buf.data())[i];
+    return SHE_OK;
+}
+
+extern "C" she_status she_write_field(she_handle *h, int32_t instance, const double *host, int64_t n)
+{
+    if (!h || !host) return fail(h, SHE_EINVAL, "NULL argument");
+    if (instance < 0 || instance >= h->n_inst) return fail(h, SHE_EINVAL, "instance out of range");
+    const int64_t nc = inst_cells(h, instance);
+    if (n != nc) return fail(h, SHE_EINVAL, "n must equal the instance's cell count");
+    std::vector<char> buf(h->esz * nc);
+    for (int64_t i = 0; i < nc; ++i) {
+        if (h->prec == SHE_F32)
+            reinterpret_cast<float *>(buf.data())[i] = static_cast<float>(host[i]);
+        else
+            reinterpret_cast<double *>(buf.data())[i] = host[i];
+    }
+    SHE_HIP(h, hipMemcpyAsync(inst_field(h, instance), buf.data(), buf.size(), hipMemcpyHostToDevice, h->stream));
+    SHE_HIP(h, hipStreamSynchronize(h->stream));
+    return SHE_OK;
+}
+
+// ------------------------------------------------------------------ checkpoints
+
+namespace {
+struct Blob {
+    uint64_t magic;
+    uint64_t version;
+    int64_t steps;
+    int64_t dim, prec, n_inst, cells, x_elems, c_elems, stat_cells;
+    int64_t cur;
+};
+constexpr uint64_t kMagic = 0x3153544b50454853ull;  // "SHEPKTS1"
+
+struct Section {
+    void *dev;
+    size_t bytes;
+};
+
+std::vector<Section> sections(const she_handle *h)
+{
+    std::vector<Section> v;
+    if (h->dim == 1) {
+        v.push_back({h->d_pool, h->esz * h->total_cells});
+        if (h->d_s1) v.push_back({h->d_s1, sizeof(double) * h->total_cells});
+        if (h->d_s2) v.push_back({h->d_s2, sizeof(double) * h->total_cells});
+        if (h->d_x) v.push_back({h->d_x, h->esz * h->x_elems});
+        if (h->d_c) v.push_back({h->d_c, sizeof(double) * h->c_elems});
+    } else {
+        v.push_back({h->field(), h->esz * h->cells * h->n_inst});
+        if (h->d_sksum) v.push_back({h->d_sksum, sizeof(double) * h->n_inst * h->nbins});
+    }
+    v.push_back({h->d_acc, sizeof(InstAcc) * h->n_inst});
+    return v;
+}
+
+Blob header(const she_handle *h)
+{
+    Blob b{};
+    b.magic = kMagic;
+    b.version = 1;
+    b.steps = h->steps;
+    b.dim = h->dim;
+    b.prec = h->prec;
+    b.n_inst = h->n_inst;
+    b.cells = h->dim == 1 ? h->total_cells : h->cells;
+    b.x_elems = h->x_elems;
+    b.c_elems = h->c_elems;
+    b.stat_cells = h->d_s1 ? h->total_cells : 0;
+    b.cur = 0;
+    return b;
+}
+}  // namespace
+
+extern "C" she_status she_state_bytes(const she_handle *h, size_t *bytes)
+{
+    if (!h || !bytes) return SHE_EINVAL;
+    size_t t = sizeof(Blob);
+    for (const Section &s : sections(h)) t += s.bytes;
+    *bytes = t;
+    return SHE_OK;
+}
+
+extern "C" she_status she_get_state(she_handle *h, void *host, size_t bytes)
+{
+    size_t need = 0;
+    if (!h || !host) return fail(h, SHE_EINVAL, "NULL argument");
+    she_state_bytes(h, &need);
+    if (bytes < need) return fail(h, SHE_EINVAL, "buffer too small for the checkpoint");
+    Blob b = header(h);
+    char *p = static_cast<char *>(host);
+    std::memcpy(p, &b, sizeof b);
+    p += sizeof b;
+    for (const Section &s : sections(h)) {
+        SHE_HIP(h, hipMemcpyAsync(p, s.dev, s.bytes, hipMemcpyDeviceToHost, h->stream));
+        p += s.bytes;
+    }
+    SHE_HIP(h, hipStreamSynchronize(h->stream));
+    return SHE_OK;
+}
+
+extern "C" she_status she_set_state(she_handle *h, const void *host, size_t bytes)
+{
+    size_t need = 0;
+    if (!h || !host) return fail(h, SHE_EINVAL, "NULL argument");
+    she_state_bytes(h, &need);
+    if (bytes < need) return fail(h, SHE_ESTATE, "checkpoint smaller than this handle's state");
+    Blob b;
+    std::memcpy(&b, host, sizeof b);
+    Blob mine = header(h);
+    if (b.magic != kMagic || b.version != 1 || b.dim != mine.dim || b.prec != mine.prec ||
+        b.n_inst != mine.n_inst || b.cells != mine.cells || b.x_elems != mine.x_elems ||
+        b.c_elems != mine.c_elems || b.stat_cells != mine.stat_cells)
+        return fail(h, SHE_ESTATE, "checkpoint does not match this handle's layout");
+    const char *p = static_cast<const char *>(host) + sizeof b;
+    for (const Section &s : sections(h)) {
+        SHE_HIP(h, hipMemcpyAsync(s.dev, p, s.bytes, hipMemcpyHostToDevice, h->stream));
+        p += s.bytes;
+    }
+    SHE_HIP(h, hipStreamSynchronize(h->stream));
+    h->steps = b.steps;
+    return SHE_OK;
+}
+
+// ------------------------------------------------------------------ verification
+
+extern "C" she_status she_debug_philox(uint64_t seed, const uint32_t *ctr, int64_t count, uint32_t *out,
+                                       void *stream)
+{
+    if (!ctr || !out || count < 0) return fail(nullptr, SHE_EINVAL, "bad argument");
+    if (count == 0) return SHE_OK;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    uint32_t *dc = nullptr, *dout = nullptr;
+    hipError_t e = hipMalloc(&dc, sizeof(uint32_t) * 4 * count);
+    if (e == hipSuccess) e = hipMalloc(&dout, sizeof(uint32_t) * 4 * count);
+    if (e == hipSuccess) e = hipMemcpyAsync(dc, ctr, sizeof(uint32_t) * 4 * count, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = launch_debug_philox(s, seed, dc, count, dout);
+    if (e == hipSuccess) e = hipMemcpyAsync(out, dout, sizeof(uint32_t) * 4 * count, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    (void)hipFree(dc);
+    (void)hipFree(dout);
+    if (e != hipSuccess) return fail(nullptr, SHE_EDEVICE, std::string("debug_philox: ") + hipGetErrorString(e));
+    return SHE_OK;
+}
+
+extern "C" she_status she_debug_normals(uint64_t seed, uint32_t realisation, uint32_t tag, uint64_t step,
+                                        uint64_t face0, int64_t count, int32_t precision, double *out, void *stream)
+{
+    if (!out || count < 0 || (precision != SHE_F32 && precision != SHE_F64))
+        return fail(nullptr, SHE_EINVAL, "bad argument");
+    if (count == 0) return SHE_OK;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    double *dout = nullptr;
+    hipError_t e = hipMalloc(&dout, sizeof(double) * count);
+    if (e == hipSuccess) e = launch_debug_normals(s, precision, seed, realisation, tag, step, face0, count, dout);
+    if (e == hipSuccess) e = hipMemcpyAsync(out, dout, sizeof(double) * count, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    (void)hipFree(dout);
+    if (e != hipSuccess) return fail(nullptr, SHE_EDEVICE, std::string("debug_normals: ") + hipGetErrorString(e));
+    return SHE_OK;
+}

@@ -1,0 +1,111 @@
+// Internal types shared by the host runtime and the kernels of libshe.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace she {
+
+constexpr int kCorrBlock = 256;  // snapshots per X^T X block (MFMA K dimension)
+
+// One 1D instance in the ragged batch (device table entry).
+struct Inst1D {
+    int64_t off;        // first cell in the state pool / per-cell statistics
+    int64_t x_off;      // first element of this instance's 256 x N X block, -1: none
+    int64_t c_off;      // first element of this instance's N x N FP64 sum, -1: none
+    int32_t n;          // cells
+    int32_t bc;         // 0 periodic, 1 Dirichlet
+    int32_t scheme;     // 0 FE, 1 PC
+    int32_t noise;      // 0 instantaneous, 1 frozen, 2 off
+    int32_t eq;         // 0 heat, 1 species
+    uint32_t realisation;
+    uint64_t seed;
+    double r, sigma, u0, uL, uR;
+};
+
+// Per-instance accumulators that are not per cell (device).
+struct InstAcc {
+    int64_t n_samples;
+    int64_t clamp_count;
+    double sum_u;       // sum of U over the cells at the last sample / step
+    double sp_mean;     // sum over samples of the spatial mean of dU
+    double sp_sq;       // ... of the spatial mean of dU^2
+    double sp_var;      // ... of the spatial variance
+    int32_t nonfinite;
+    int32_t pad;
+};
+
+// Statistics buffers of the 1D kernel.
+struct Stats1D {
+    double *s1;         // per cell, or nullptr
+    double *s2;
+    void *xblk;         // X blocks (state type), 256 x N per instance
+    double *c;          // N x N per instance
+    InstAcc *acc;       // per instance
+};
+
+// Parameters of a homogeneous 2D/3D batch.
+struct ParamsND {
+    int32_t nx, ny, nz;     // nz = 1 in 2D
+    int32_t dim;
+    int32_t eq, scheme, noise;
+    int32_t n_inst;
+    int32_t chunk;          // rows (2D, along y) or planes (3D, along z) per march
+    int32_t pad;
+    double r, sigma, u0;
+    uint64_t seed;
+    const uint32_t *realisation;  // device, n_inst
+};
+
+}  // namespace she
+
+namespace she {
+
+// ---- launchers (defined next to their kernels) ----
+hipError_t launch_step1d(int prec, int block, int maxg, bool stats, int n_blocks, size_t smem,
+                         hipStream_t s, const Inst1D *tab, const int32_t *order, void *pool,
+                         int64_t step0, int32_t nsteps, int64_t burn_in, int32_t every,
+                         uint32_t mask, Stats1D st);
+// Initial state of 1D instances: steady profile + init_sd * N(tag 1, step 0, face = cell).
+hipError_t launch_init1d(int prec, int n_inst, int nmax, hipStream_t s, const Inst1D *tab,
+                         const double *init_sd, void *pool);
+// 1D finalisation of one instance into out (FP64):
+//   out[0..N) mean, [N..2N) var, [2N..2N+N^2) cov, then N S_k values, then
+//   N^2 scratch, then 1 value sum(U).
+hipError_t launch_fin1d(int prec, hipStream_t s, const Inst1D *tab, int inst, int n,
+                        const void *pool, const double *s1, const double *s2, const void *xblk,
+                        const double *c, int64_t n_samples, int partial_rows, bool corr,
+                        double *out);
+
+hipError_t launch_step2d(int prec, int cx, int eq, int scheme, int n_blocks, hipStream_t s,
+                         const ParamsND &p, const void *src, void *dst, int64_t step,
+                         int32_t sample, double *part, InstAcc *acc);
+hipError_t launch_step3d(int prec, int cx, int eq, int ty, int n_blocks, size_t smem,
+                         hipStream_t s, const ParamsND &p, const void *src, void *dst,
+                         int64_t step, int32_t sample, double *part, InstAcc *acc);
+hipError_t launch_reduce_parts(int n_inst, hipStream_t s, const double *part, int32_t nparts,
+                               double inv_cells, InstAcc *acc);
+// nD initial state: u0 + init_sd * N(tag 1, step 0, face = cell) per instance.
+hipError_t launch_initnd(int prec, hipStream_t s, const ParamsND &p, int64_t cells,
+                         double init_sd, void *field);
+// nD finalisation of one instance: out[0] spatial mean, out[1] spatial variance,
+// out[2] sum(U), then (nbins > 0) out[3 + b] the shell average of <|U_k|^2>.
+hipError_t launch_finnd(int prec, hipStream_t s, const ParamsND &p, int inst, int64_t cells,
+                        const void *field, const InstAcc *acc, const double *sk_sums,
+                        const double *sk_modes, int nbins, double *out);
+
+// Verification: raw Philox words / face normals on the device.
+hipError_t launch_debug_philox(hipStream_t s, uint64_t seed, const uint32_t *ctr, int64_t count,
+                               uint32_t *out);
+hipError_t launch_debug_normals(hipStream_t s, int prec, uint64_t seed, uint32_t realisation,
+                                uint32_t tag, uint64_t step, uint64_t face0, int64_t count,
+                                double *out);
+
+// 2D structure factor on a sample step: row FFTs, column FFTs + shell
+// binning into per-block partials, fixed-order reduction into sums
+// (n_inst x nbins FP64).  half: n_inst*ny*(nx/2+1) complex of the state type.
+hipError_t launch_sk2d(int prec, hipStream_t s, int n_inst, int nx, int ny, double u0, const void *field,
+                       void *half, double *part, int nbins, double *sums, const InstAcc *acc);
+int sk2d_groups(int prec, int nx, int ny);
+
+}  // namespace she

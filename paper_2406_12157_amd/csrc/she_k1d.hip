@@ -1,0 +1,558 @@
+// 1D step kernel: one workgroup owns one instance of a (possibly ragged) batch
+// and keeps its whole state in LDS for a chunk of steps.
+//
+// Scheme (Garcia et al., Sec. 3): face flux F_f = r (U_f - U_{f-1}) + w sigma A N_f
+// through the low face f of cell f, update U_i += F_{i+1} - F_i (FE), or the
+// predictor-corrector U = (U + U* + Delta(U*; same N)) / 2 (PC).  Dirichlet
+// walls: F_0 = 2 r (U_0 - U_L) + sqrt(2) sigma A(U_L) N_0 and mirrored at the
+// right wall (ghost stencil U_1 - 3U_0 + 2U_L of the Dirichlet paragraph).
+//
+// Work split: thread t owns Philox blocks g = t, t + BLOCK, ...; block g holds
+// faces 4g..4g+3, which are the low faces of cells 4g..4g+3, so one Philox
+// call and two Box-Muller pairs serve four cells and PC re-uses the numbers
+// from registers.  Neighbour values go through LDS; two barriers per FE step,
+// four per PC step.
+//
+// Statistics on sample steps: per-cell FP64 sums of dU and dU^2 kept in
+// registers for the whole launch, spatial sums reduced over the workgroup,
+// and (optionally) the shifted state written as one row of a 256-row X block;
+// a full block is contracted on the matrix cores, C += X^T X, with
+// v_mfma_f32_16x16x4f32 (FP32 state) or v_mfma_f64_16x16x4f64 (FP64 state),
+// and added to the FP64 N x N sum.
+#include "she_internal.hpp"
+#include "she_rng.hpp"
+
+namespace she {
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+template <typename T>
+__device__ __forceinline__ T face_amp(int eq, T v, uint32_t &clamps)
+{
+    if (eq == 0) return v;
+    if (v < T(0)) {
+        ++clamps;
+        return T(0);
+    }
+    return sqrt(v);
+}
+
+__device__ __forceinline__ f32x4 mfma16x16x4(float a, float b, f32x4 c)
+{
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+__device__ __forceinline__ f64x4 mfma16x16x4(double a, double b, f64x4 c)
+{
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+// C[N x N] += X^T X for a full block X[256 x N] (row = snapshot).  Tiles of
+// 16 x 16 over the upper triangle are spread over the waves; each lane
+// accumulates four outputs of its tile over K = 256 in the matrix-core
+// accumulator type and adds them to the FP64 sum (both triangles).
+// Operand layout of the 16x16x4 instructions: lane l supplies A[l%16][l/16]
+// and B[l/16][l%16]; output element v of lane l is D[4(l/16)+v][l%16].
+template <typename T>
+__device__ void xtx_block(const T *__restrict__ X, double *__restrict__ Cm, int N)
+{
+    using acc_t = typename std::conditional<std::is_same<T, float>::value, f32x4, f64x4>::type;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwave = blockDim.x >> 6;
+    const int nt = (N + 15) >> 4;
+    const int ntiles = nt * (nt + 1) / 2;
+    for (int t = wave; t < ntiles; t += nwave) {
+        int ti = 0, rem = t;
+        while (rem >= nt - ti) {
+            rem -= nt - ti;
+            ++ti;
+        }
+        const int tj = ti + rem;
+        const int i = 16 * ti + (lane & 15), j = 16 * tj + (lane & 15);
+        acc_t acc = {0, 0, 0, 0};
+        for (int k0 = 0; k0 < kCorrBlock; k0 += 4) {
+            const int k = k0 + (lane >> 4);
+            const T a = i < N ? X[(int64_t)k * N + i] : T(0);
+            const T b = j < N ? X[(int64_t)k * N + j] : T(0);
+            acc = mfma16x16x4(a, b, acc);
+        }
+        const int col = 16 * tj + (lane & 15);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int row = 16 * ti + 4 * (lane >> 4) + v;
+            if (row < N && col < N) {
+                const double val = static_cast<double>(acc[v]);
+                Cm[(int64_t)row * N + col] += val;
+                if (ti != tj) Cm[(int64_t)col * N + row] += val;
+            }
+        }
+    }
+}
+
+template <typename T, int BLOCK, int MAXG, bool STATS>
+__global__ void __launch_bounds__(BLOCK)
+    k_step1d(const Inst1D *__restrict__ tab, const int32_t *__restrict__ order, T *__restrict__ pool,
+             int64_t step0, int32_t nsteps, int64_t burn_in, int32_t every, uint32_t mask, Stats1D st)
+{
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    __shared__ double red[3][BLOCK / 64];
+    __shared__ int stop_flag;
+
+    const int inst = order[blockIdx.x];
+    const Inst1D d = tab[inst];
+    const int N = d.n;
+    const int nf = d.bc == 1 ? N + 1 : N;
+    const int nfg = (nf + 3) >> 2;
+    const int nmax_pad = (N + 4) & ~3;
+    T *U = reinterpret_cast<T *>(smem_raw);
+    T *F = U + nmax_pad;
+    T *Us = F + nmax_pad + 4;
+    const int tid = threadIdx.x;
+
+    InstAcc *acc = st.acc + inst;
+    if (acc->nonfinite) return;  // frozen after a non-finite sample
+
+    const T r = static_cast<T>(d.r);
+    const T sg = static_cast<T>(d.sigma);
+    const T sgw = static_cast<T>(d.sigma * 1.41421356237309504880);
+    const T uL = static_cast<T>(d.uL), uR = static_cast<T>(d.uR);
+    const int eq = d.eq, noise = d.noise;
+    const bool dir = d.bc == 1;
+    const PhiloxKey key = make_key(d.seed);
+    T *gU = pool + d.off;
+
+    for (int i = tid; i < N; i += BLOCK) U[i] = gU[i];
+
+    // frozen-mode face amplitudes
+    uint32_t clamps = 0;
+    const T amp_u0 = face_amp<T>(eq, static_cast<T>(d.u0), clamps);
+    const T amp_uL = face_amp<T>(eq, uL, clamps);
+    const T amp_uR = face_amp<T>(eq, uR, clamps);
+    clamps = 0;
+
+    double s1[MAXG][4], s2[MAXG][4];
+    const bool moments = STATS && (mask & 1u) && st.s1 != nullptr;
+    const bool corr = STATS && (mask & 2u) && d.x_off >= 0;
+    int64_t nsamp = STATS ? acc->n_samples : 0;
+#pragma unroll
+    for (int s = 0; s < MAXG; ++s)
+#pragma unroll
+        for (int l = 0; l < 4; ++l) {
+            const int i = 4 * (tid + s * BLOCK) + l;
+            s1[s][l] = (moments && i < N) ? st.s1[d.off + i] : 0.0;
+            s2[s][l] = (moments && i < N) ? st.s2[d.off + i] : 0.0;
+        }
+    __syncthreads();
+
+    auto flux_pass = [&](const T *V, const T (&z)[MAXG][4]) {
+#pragma unroll
+        for (int s = 0; s < MAXG; ++s) {
+            const int g = tid + s * BLOCK;
+            if (g >= nfg) continue;
+#pragma unroll
+            for (int l = 0; l < 4; ++l) {
+                const int f = 4 * g + l;
+                if (f >= nf) continue;
+                T fl;
+                if (dir && f == 0) {
+                    fl = T(2) * r * (V[0] - uL);
+                    if (noise != 2) fl += sgw * amp_uL * z[s][l];
+                } else if (dir && f == N) {
+                    fl = T(2) * r * (uR - V[N - 1]);
+                    if (noise != 2) fl += sgw * amp_uR * z[s][l];
+                } else {
+                    const int a = f == 0 ? N - 1 : f - 1;
+                    const T vl = V[a], vr = V[f];
+                    fl = r * (vr - vl);
+                    if (noise != 2) {
+                        T am;
+                        if (noise == 1)
+                            am = dir ? face_amp<T>(eq, uL + (uR - uL) * static_cast<T>(f) / static_cast<T>(N), clamps)
+                                     : amp_u0;
+                        else
+                            am = face_amp<T>(eq, T(0.5) * (vl + vr), clamps);
+                        fl += sg * am * z[s][l];
+                    }
+                }
+                F[f] = fl;
+            }
+        }
+    };
+
+    for (int k = 0; k < nsteps; ++k) {
+        const uint64_t n = static_cast<uint64_t>(step0 + k);
+        T z[MAXG][4];
+#pragma unroll
+        for (int s = 0; s < MAXG; ++s) {
+            const int g = tid + s * BLOCK;
+            if (noise != 2 && g < nfg) {
+                const Normals4<T> nz = block_normals<T>(static_cast<uint32_t>(g), static_cast<uint32_t>(n),
+                                                        ctr_word2(n, 0u), d.realisation, key);
+#pragma unroll
+                for (int l = 0; l < 4; ++l) z[s][l] = nz.z[l];
+            } else {
+#pragma unroll
+                for (int l = 0; l < 4; ++l) z[s][l] = T(0);
+            }
+        }
+        flux_pass(U, z);
+        __syncthreads();
+        if (d.scheme == 0) {
+            for (int i = tid; i < N; i += BLOCK) {
+                const int hi = (!dir && i + 1 == N) ? 0 : i + 1;
+                U[i] = U[i] + (F[hi] - F[i]);
+            }
+            __syncthreads();
+        } else {
+            for (int i = tid; i < N; i += BLOCK) {
+                const int hi = (!dir && i + 1 == N) ? 0 : i + 1;
+                Us[i] = U[i] + (F[hi] - F[i]);
+            }
+            __syncthreads();
+            flux_pass(Us, z);
+            __syncthreads();
+            for (int i = tid; i < N; i += BLOCK) {
+                const int hi = (!dir && i + 1 == N) ? 0 : i + 1;
+                U[i] = T(0.5) * ((U[i] + Us[i]) + (F[hi] - F[i]));
+            }
+            __syncthreads();
+        }
+
+        if (STATS) {
+            const int64_t t = step0 + k + 1;
+            if (t > burn_in && every > 0 && t % every == 0) {
+                double a = 0.0, b = 0.0;
+                int bad = 0;
+                const int row = static_cast<int>(nsamp % kCorrBlock);
+                T *X = corr ? static_cast<T *>(st.xblk) + d.x_off : nullptr;
+#pragma unroll
+                for (int s = 0; s < MAXG; ++s)
+#pragma unroll
+                    for (int l = 0; l < 4; ++l) {
+                        const int i = 4 * (tid + s * BLOCK) + l;
+                        if (i < N) {
+                            const T v = U[i];
+                            if (!isfinite(v)) bad = 1;
+                            const double ref = dir ? d.uL + (d.uR - d.uL) * (i + 0.5) / N : d.u0;
+                            const double del = static_cast<double>(v) - ref;
+                            s1[s][l] += del;
+                            s2[s][l] += del * del;
+                            a += del;
+                            b += del * del;
+                            if (corr) X[(int64_t)row * N + i] = static_cast<T>(del);
+                        }
+                    }
+                // workgroup reduction (fixed order)
+                for (int off = 32; off > 0; off >>= 1) {
+                    a += __shfl_xor(a, off, 64);
+                    b += __shfl_xor(b, off, 64);
+                    bad |= __shfl_xor(bad, off, 64);
+                }
+                if ((tid & 63) == 0) {
+                    red[0][tid >> 6] = a;
+                    red[1][tid >> 6] = b;
+                    red[2][tid >> 6] = static_cast<double>(bad);
+                }
+                __syncthreads();
+                if (tid == 0) {
+                    double ta = 0.0, tb = 0.0, tbad = 0.0;
+                    for (int w = 0; w < BLOCK / 64; ++w) {
+                        ta += red[0][w];
+                        tb += red[1][w];
+                        tbad += red[2][w];
+                    }
+                    if (tbad != 0.0) {
+                        acc->nonfinite = 1;
+                        stop_flag = 1;
+                    } else {
+                        ta /= N;
+                        tb /= N;
+                        acc->sp_mean += ta;
+                        acc->sp_sq += tb;
+                        acc->sp_var += tb - ta * ta;
+                        stop_flag = 0;
+                    }
+                }
+                __syncthreads();
+                if (stop_flag) {
+                    // a non-finite sample: keep the statistics as they were
+                    // before it and freeze the state
+                    for (int i = tid; i < N; i += BLOCK) gU[i] = U[i];
+                    if (tid == 0) acc->n_samples = nsamp;
+                    return;
+                }
+                ++nsamp;
+                if (corr && row == kCorrBlock - 1) {
+                    __threadfence_block();
+                    __syncthreads();
+                    xtx_block<T>(X, st.c + d.c_off, N);
+                    __syncthreads();
+                }
+            }
+        }
+    }
+
+    for (int i = tid; i < N; i += BLOCK) gU[i] = U[i];
+    if (moments) {
+#pragma unroll
+        for (int s = 0; s < MAXG; ++s)
+#pragma unroll
+            for (int l = 0; l < 4; ++l) {
+                const int i = 4 * (tid + s * BLOCK) + l;
+                if (i < N) {
+                    st.s1[d.off + i] = s1[s][l];
+                    st.s2[d.off + i] = s2[s][l];
+                }
+            }
+    }
+    if (STATS) {
+        if (clamps) atomicAdd(reinterpret_cast<unsigned long long *>(&acc->clamp_count),
+                              static_cast<unsigned long long>(clamps));
+        if (tid == 0) acc->n_samples = nsamp;
+    }
+}
+
+// ------------------------------------------------------------------ init
+
+template <typename T>
+__global__ void __launch_bounds__(256)
+    k_init1d(const Inst1D *__restrict__ tab, const double *__restrict__ init_sd, T *__restrict__ pool)
+{
+    const int inst = blockIdx.x;
+    const Inst1D d = tab[inst];
+    const int i = blockIdx.y * 256 + threadIdx.x;
+    if (i >= d.n) return;
+    const double ref = d.bc == 1 ? d.uL + (d.uR - d.uL) * (i + 0.5) / d.n : d.u0;
+    double v = ref;
+    const double sd = init_sd[inst];
+    if (sd > 0.0) {
+        const Normals4<double> nz = block_normals<double>(static_cast<uint32_t>(i >> 2), 0u, ctr_word2(0, 1u),
+                                                          d.realisation, make_key(d.seed));
+        v = ref + sd * nz.z[i & 3];
+    }
+    pool[d.off + i] = static_cast<T>(v);
+}
+
+// ------------------------------------------------------------------ finalisation
+
+// m2[i][j] = (C[i][j] + sum over the rows of the open block X_b,i X_b,j) / M
+template <typename T>
+__global__ void __launch_bounds__(256)
+    k_fin_m2(const T *__restrict__ X, int rows, const double *__restrict__ C, int N, int64_t M,
+             double *__restrict__ m2)
+{
+    const int64_t e = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
+    if (e >= static_cast<int64_t>(N) * N) return;
+    const int i = static_cast<int>(e / N), j = static_cast<int>(e - static_cast<int64_t>(i) * N);
+    double acc = C[e];
+    for (int b = 0; b < rows; ++b)
+        acc += static_cast<double>(X[static_cast<int64_t>(b) * N + i]) * static_cast<double>(X[static_cast<int64_t>(b) * N + j]);
+    m2[e] = acc / static_cast<double>(M);
+}
+
+// mean, variance per cell, sum(U) of the current field, covariance
+template <typename T>
+__global__ void __launch_bounds__(256)
+    k_fin_cells(const Inst1D *__restrict__ tab, int inst, const T *__restrict__ pool,
+                const double *__restrict__ s1, const double *__restrict__ s2, int64_t M, bool corr,
+                double *__restrict__ out)
+{
+    const Inst1D d = tab[inst];
+    const int N = d.n;
+    double *mean = out, *var = out + N, *cov = out + 2 * N, *m2 = out + 3 * N + static_cast<int64_t>(N) * N;
+    double *sum = m2 + static_cast<int64_t>(N) * N;
+    const double inv = M > 0 ? 1.0 / static_cast<double>(M) : 0.0;
+    for (int i = threadIdx.x; i < N; i += 256) {
+        const double ref = d.bc == 1 ? d.uL + (d.uR - d.uL) * (i + 0.5) / N : d.u0;
+        const double m = s1 ? s1[d.off + i] * inv : 0.0;
+        mean[i] = ref + m;
+        var[i] = s2 ? s2[d.off + i] * inv - m * m : 0.0;
+    }
+    if (corr) {
+        for (int64_t e = threadIdx.x; e < static_cast<int64_t>(N) * N; e += 256) {
+            const int i = static_cast<int>(e / N), j = static_cast<int>(e - static_cast<int64_t>(i) * N);
+            cov[e] = m2[e] - (s1[d.off + i] * inv) * (s1[d.off + j] * inv);
+        }
+    }
+    __shared__ double red[256];
+    double a = 0.0;
+    for (int i = threadIdx.x; i < N; i += 256) a += static_cast<double>(pool[d.off + i]);
+    red[threadIdx.x] = a;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *sum = red[0];
+}
+
+// <|U_k|^2> = |R_k|^2 + 2 Re(conj(R_k) sum_j m_j w^{jk}) + sum_ij m2_ij cos(2 pi k (i-j)/N),
+// R_k = DFT of the reference profile, m = E[dU], m2 = E[dU dU^T].
+__global__ void __launch_bounds__(256)
+    k_fin_sk(const Inst1D *__restrict__ tab, int inst, const double *__restrict__ s1, int64_t M,
+             double *__restrict__ out)
+{
+    const Inst1D d = tab[inst];
+    const int N = d.n;
+    const int k = blockIdx.x * 256 + threadIdx.x;
+    if (k >= N) return;
+    const double *m2 = out + 3 * N + static_cast<int64_t>(N) * N;
+    double *sk = out + 2 * N + static_cast<int64_t>(N) * N;
+    const double inv = 1.0 / static_cast<double>(M);
+    double rr = 0.0, ri = 0.0, mr = 0.0, mi = 0.0;
+    for (int j = 0; j < N; ++j) {
+        const int64_t idx = (static_cast<int64_t>(j) * k) % N;
+        double sn, cs;
+        sincospi(-2.0 * static_cast<double>(idx) / N, &sn, &cs);
+        const double ref = d.bc == 1 ? d.uL + (d.uR - d.uL) * (j + 0.5) / N : d.u0;
+        const double m = s1[d.off + j] * inv;
+        rr += ref * cs;
+        ri += ref * sn;
+        mr += m * cs;
+        mi += m * sn;
+    }
+    double q = 0.0;
+    for (int i = 0; i < N; ++i)
+        for (int j = 0; j < N; ++j) {
+            int64_t idx = (static_cast<int64_t>(k) * (i - j)) % N;
+            if (idx < 0) idx += N;
+            q += m2[static_cast<int64_t>(i) * N + j] * cospi(2.0 * static_cast<double>(idx) / N);
+        }
+    sk[k] = (rr * rr + ri * ri) + 2.0 * (rr * mr + ri * mi) + q;
+}
+
+// ------------------------------------------------------------------ launchers
+
+template <typename T, int BLOCK, int MAXG>
+static hipError_t step1d_t(bool stats, int n_blocks, size_t smem, hipStream_t s, const Inst1D *tab,
+                           const int32_t *order, void *pool, int64_t step0, int32_t nsteps, int64_t burn_in,
+                           int32_t every, uint32_t mask, Stats1D st)
+{
+    if (stats)
+        hipLaunchKernelGGL((k_step1d<T, BLOCK, MAXG, true>), dim3(n_blocks), dim3(BLOCK), smem, s, tab, order,
+                           static_cast<T *>(pool), step0, nsteps, burn_in, every, mask, st);
+    else
+        hipLaunchKernelGGL((k_step1d<T, BLOCK, MAXG, false>), dim3(n_blocks), dim3(BLOCK), smem, s, tab, order,
+                           static_cast<T *>(pool), step0, nsteps, burn_in, every, mask, st);
+    return hipGetLastError();
+}
+
+template <typename T, int BLOCK>
+static hipError_t step1d_b(int maxg, bool stats, int n_blocks, size_t smem, hipStream_t s, const Inst1D *tab,
+                           const int32_t *order, void *pool, int64_t step0, int32_t nsteps, int64_t burn_in,
+                           int32_t every, uint32_t mask, Stats1D st)
+{
+    switch (maxg) {
+    case 1: return step1d_t<T, BLOCK, 1>(stats, n_blocks, smem, s, tab, order, pool, step0, nsteps, burn_in, every, mask, st);
+    case 2: return step1d_t<T, BLOCK, 2>(stats, n_blocks, smem, s, tab, order, pool, step0, nsteps, burn_in, every, mask, st);
+    case 4: return step1d_t<T, BLOCK, 4>(stats, n_blocks, smem, s, tab, order, pool, step0, nsteps, burn_in, every, mask, st);
+    case 8: return step1d_t<T, BLOCK, 8>(stats, n_blocks, smem, s, tab, order, pool, step0, nsteps, burn_in, every, mask, st);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+template <typename T>
+static hipError_t step1d_p(int block, int maxg, bool stats, int n_blocks, size_t smem, hipStream_t s,
+                           const Inst1D *tab, const int32_t *order, void *pool, int64_t step0, int32_t nsteps,
+                           int64_t burn_in, int32_t every, uint32_t mask, Stats1D st)
+{
+    switch (block) {
+    case 64: return step1d_b<T, 64>(maxg, stats, n_blocks, smem, s, tab, order, pool, step0, nsteps, burn_in, every, mask, st);
+    case 256: return step1d_b<T, 256>(maxg, stats, n_blocks, smem, s, tab, order, pool, step0, nsteps, burn_in, every, mask, st);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_step1d(int prec, int block, int maxg, bool stats, int n_blocks, size_t smem, hipStream_t s,
+                         const Inst1D *tab, const int32_t *order, void *pool, int64_t step0, int32_t nsteps,
+                         int64_t burn_in, int32_t every, uint32_t mask, Stats1D st)
+{
+    if (prec == 0)
+        return step1d_p<float>(block, maxg, stats, n_blocks, smem, s, tab, order, pool, step0, nsteps, burn_in,
+                               every, mask, st);
+    return step1d_p<double>(block, maxg, stats, n_blocks, smem, s, tab, order, pool, step0, nsteps, burn_in,
+                            every, mask, st);
+}
+
+hipError_t launch_init1d(int prec, int n_inst, int nmax, hipStream_t s, const Inst1D *tab, const double *init_sd,
+                         void *pool)
+{
+    const dim3 grid(n_inst, (nmax + 255) / 256);
+    if (prec == 0)
+        hipLaunchKernelGGL(k_init1d<float>, grid, dim3(256), 0, s, tab, init_sd, static_cast<float *>(pool));
+    else
+        hipLaunchKernelGGL(k_init1d<double>, grid, dim3(256), 0, s, tab, init_sd, static_cast<double *>(pool));
+    return hipGetLastError();
+}
+
+hipError_t launch_fin1d(int prec, hipStream_t s, const Inst1D *tab, int inst, int n, const void *pool,
+                        const double *s1, const double *s2, const void *xblk, const double *c, int64_t n_samples,
+                        int partial_rows, bool corr, double *out)
+{
+    const int64_t nn = static_cast<int64_t>(n) * n;
+    double *m2 = out + 3 * n + nn;
+    const int64_t M = n_samples > 0 ? n_samples : 1;
+    if (corr) {
+        const int nb = static_cast<int>((nn + 255) / 256);
+        if (prec == 0)
+            hipLaunchKernelGGL(k_fin_m2<float>, dim3(nb), dim3(256), 0, s, static_cast<const float *>(xblk),
+                               partial_rows, c, n, M, m2);
+        else
+            hipLaunchKernelGGL(k_fin_m2<double>, dim3(nb), dim3(256), 0, s, static_cast<const double *>(xblk),
+                               partial_rows, c, n, M, m2);
+    }
+    if (prec == 0)
+        hipLaunchKernelGGL(k_fin_cells<float>, dim3(1), dim3(256), 0, s, tab, inst, static_cast<const float *>(pool),
+                           s1, s2, M, corr, out);
+    else
+        hipLaunchKernelGGL(k_fin_cells<double>, dim3(1), dim3(256), 0, s, tab, inst,
+                           static_cast<const double *>(pool), s1, s2, M, corr, out);
+    if (corr) hipLaunchKernelGGL(k_fin_sk, dim3((n + 255) / 256), dim3(256), 0, s, tab, inst, s1, M, out);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ verification
+
+__global__ void __launch_bounds__(256)
+    k_debug_philox(uint64_t seed, const uint32_t *__restrict__ ctr, int64_t count, uint32_t *__restrict__ out)
+{
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
+    if (i >= count) return;
+    const Words4 w = philox4x32_10(ctr[4 * i], ctr[4 * i + 1], ctr[4 * i + 2], ctr[4 * i + 3], make_key(seed));
+    for (int l = 0; l < 4; ++l) out[4 * i + l] = w.w[l];
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256)
+    k_debug_normals(uint64_t seed, uint32_t real, uint32_t tag, uint64_t step, uint64_t face0, int64_t count,
+                    double *__restrict__ out)
+{
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
+    if (i >= count) return;
+    const uint64_t f = face0 + static_cast<uint64_t>(i);
+    const Normals4<T> nz = block_normals<T>(static_cast<uint32_t>(f >> 2), static_cast<uint32_t>(step),
+                                            ctr_word2(step, tag), real, make_key(seed));
+    out[i] = static_cast<double>(nz.z[f & 3]);
+}
+
+hipError_t launch_debug_philox(hipStream_t s, uint64_t seed, const uint32_t *ctr, int64_t count, uint32_t *out)
+{
+    hipLaunchKernelGGL(k_debug_philox, dim3(static_cast<unsigned>((count + 255) / 256)), dim3(256), 0, s, seed, ctr,
+                       count, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_debug_normals(hipStream_t s, int prec, uint64_t seed, uint32_t realisation, uint32_t tag,
+                                uint64_t step, uint64_t face0, int64_t count, double *out)
+{
+    const dim3 grid(static_cast<unsigned>((count + 255) / 256));
+    if (prec == 0)
+        hipLaunchKernelGGL(k_debug_normals<float>, grid, dim3(256), 0, s, seed, realisation, tag, step, face0, count,
+                           out);
+    else
+        hipLaunchKernelGGL(k_debug_normals<double>, grid, dim3(256), 0, s, seed, realisation, tag, step, face0, count,
+                           out);
+    return hipGetLastError();
+}
+
+}  // namespace she

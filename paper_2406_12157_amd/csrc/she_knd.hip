@@ -1,0 +1,616 @@
+// 2D / 3D periodic step kernels (one launch per step, ping-pong buffers).
+//
+// Scheme (Garcia et al., Sec. 3, applied per direction with independent face
+// numbers, Sec. 2 eq. GWN): the low face of cell c in direction e carries
+// F = r (U_c - U_{c-e}) + sigma A N, A = (U_{c-e} + U_c)/2 (SHE) or
+// sqrt(max(., 0)) of it (Dean-Kawasaki, Sec. 4); U_c += sum_e F(c+e) - F(c).
+// PC (2D): U* = FE step, U = (U + U* + Delta(U*; same N)) / 2.
+//
+// Layout: realisation-major, x fastest, FP32 or FP64.  Face numbers
+// ((z*Ny + y)*dim + e)*Nx + x make the four faces of one Philox block four
+// consecutive x-cells of one direction, so a lane that owns CX consecutive
+// cells of a row needs CX/4 Philox calls per direction and uses every number.
+//
+// 2D: a "row group" of LX = Nx/CX lanes owns a full x-row and marches along y
+// over a chunk of rows.  The x-neighbours come from the adjacent lanes
+// (ds_bpermute shuffles inside the group, periodic wrap within the group);
+// the y-neighbours stay in registers from the previous row, so each cell is
+// read once and written once per step, and only the first row of a chunk
+// (FE) or its first three rows (PC) are computed twice.
+//
+// 3D: a workgroup of TY row groups owns TY consecutive rows in y and marches
+// along z.  Low y-face fluxes are exchanged between the rows through LDS (one
+// barrier per plane, double-buffered); the tile's top row computes the flux
+// through its high y-face itself (one extra Philox call per plane for that
+// row).  z-neighbours stay in registers.
+//
+// Sample steps: every lane adds dU = U - u0 and dU^2 of its output cells in
+// FP64; the group / workgroup sum is written to a per-chunk partial; a small
+// kernel reduces the partials per instance in a fixed order.
+#include "she_internal.hpp"
+#include "she_rng.hpp"
+
+namespace she {
+
+template <typename T, int EQ>
+__device__ __forceinline__ T amp_nd(T v, uint32_t &clamps)
+{
+    if constexpr (EQ == 0) {
+        return v;
+    } else {
+        if (v < T(0)) {
+            ++clamps;
+            return T(0);
+        }
+        return sqrt(v);
+    }
+}
+
+template <typename T, int EQ>
+__device__ __forceinline__ T face_flux(T lo, T hi, T z, T r, T sg, int noise, T amp0, uint32_t &clamps)
+{
+    T f = r * (hi - lo);
+    if (noise == 0) f += sg * amp_nd<T, EQ>(T(0.5) * (lo + hi), clamps) * z;
+    else if (noise == 1) f += sg * amp0 * z;
+    return f;
+}
+
+__device__ __forceinline__ int wrap(int i, int n)
+{
+    return i < 0 ? i + n : (i >= n ? i - n : i);
+}
+
+template <typename T, int CX>
+__device__ __forceinline__ void load_row(const T *__restrict__ p, T (&v)[CX])
+{
+#pragma unroll
+    for (int j = 0; j < CX; ++j) v[j] = p[j];
+}
+
+template <typename T, int CX>
+__device__ __forceinline__ void store_row(T *__restrict__ p, const T (&v)[CX])
+{
+#pragma unroll
+    for (int j = 0; j < CX; ++j) p[j] = v[j];
+}
+
+// Normals of one lane's CX faces of direction-row `drow` (= row*dim + e).
+template <typename T, int CX>
+__device__ __forceinline__ void row_normals(T (&z)[CX], uint32_t drow, uint32_t nq, uint32_t q0,
+                                            uint32_t slo, uint32_t w2, uint32_t real, PhiloxKey key, int noise)
+{
+    if (noise == 2) {
+#pragma unroll
+        for (int j = 0; j < CX; ++j) z[j] = T(0);
+        return;
+    }
+#pragma unroll
+    for (int c = 0; c < CX / 4; ++c) {
+        const Normals4<T> nz = block_normals<T>(drow * nq + q0 + c, slo, w2, real, key);
+#pragma unroll
+        for (int l = 0; l < 4; ++l) z[4 * c + l] = nz.z[l];
+    }
+}
+
+// x-fluxes of one row held by a group of LX lanes: Flo[j] is the flux through
+// the low face of the lane's cell j, Fhi the flux through the high face of its
+// last cell (= the next lane's Flo[0]).
+template <typename T, int CX, int EQ>
+__device__ __forceinline__ void row_xflux(const T (&v)[CX], const T (&z)[CX], T (&Flo)[CX], T &Fhi,
+                                          int lx, int LX, T r, T sg, int noise, T amp0, uint32_t &clamps)
+{
+    const int lane = threadIdx.x & 63;
+    const int gbase = lane - lx;
+    const int left = gbase + (lx == 0 ? LX - 1 : lx - 1);
+    const int right = gbase + (lx == LX - 1 ? 0 : lx + 1);
+    const T vleft = __shfl(v[CX - 1], left, 64);
+    Flo[0] = face_flux<T, EQ>(vleft, v[0], z[0], r, sg, noise, amp0, clamps);
+#pragma unroll
+    for (int j = 1; j < CX; ++j) Flo[j] = face_flux<T, EQ>(v[j - 1], v[j], z[j], r, sg, noise, amp0, clamps);
+    Fhi = __shfl(Flo[0], right, 64);
+}
+
+template <typename T, int CX>
+__device__ __forceinline__ T xdiv(const T (&Flo)[CX], T Fhi, int j)
+{
+    return (j + 1 < CX ? Flo[j + 1] : Fhi) - Flo[j];
+}
+
+// ------------------------------------------------------------------ 2D
+
+template <typename T, int CX, int EQ, int SCHEME>
+__global__ void __launch_bounds__(256)
+    k_step2d(ParamsND p, const T *__restrict__ src, T *__restrict__ dst, int64_t step, int32_t sample,
+             double *__restrict__ part, InstAcc *__restrict__ acc)
+{
+    const int LX = p.nx / CX;
+    const int lx = threadIdx.x % LX;
+    const int grp = threadIdx.x / LX;
+    const int gpb = blockDim.x / LX;
+    const int nchunks = (p.ny + p.chunk - 1) / p.chunk;
+    const int gchunk = blockIdx.x * gpb + grp;
+    if (gchunk >= p.n_inst * nchunks) return;
+    const int inst = gchunk / nchunks, ch = gchunk - inst * nchunks;
+    const int y0 = ch * p.chunk, y1 = min(y0 + p.chunk, p.ny);
+    const int64_t plane = static_cast<int64_t>(p.nx) * p.ny;
+    const T *S = src + inst * plane + CX * lx;
+    T *D = dst + inst * plane + CX * lx;
+
+    if (acc[inst].nonfinite) {  // frozen: carry the state over unchanged
+        for (int y = y0; y < y1; ++y) {
+            T v[CX];
+            load_row<T, CX>(S + static_cast<int64_t>(y) * p.nx, v);
+            store_row<T, CX>(D + static_cast<int64_t>(y) * p.nx, v);
+        }
+        return;
+    }
+
+    const T r = static_cast<T>(p.r), sg = static_cast<T>(p.sigma);
+    uint32_t clamps = 0;
+    const T amp0 = amp_nd<T, EQ>(static_cast<T>(p.u0), clamps);
+    clamps = 0;
+    const int noise = p.noise;
+    const uint32_t real = p.realisation[inst];
+    const PhiloxKey key = make_key(p.seed);
+    const uint32_t slo = static_cast<uint32_t>(step), w2 = ctr_word2(static_cast<uint64_t>(step), 0u);
+    const uint32_t nq = static_cast<uint32_t>(p.nx / 4), q0 = static_cast<uint32_t>((CX / 4) * lx);
+    const int ny = p.ny;
+    auto rowp = [&](int y) { return S + static_cast<int64_t>(wrap(y, ny)) * p.nx; };
+    auto drow = [&](int y, int e) { return static_cast<uint32_t>(wrap(y, ny) * 2 + e); };
+
+    double sa = 0.0, sb = 0.0;
+    const double u0d = p.u0;
+
+    if constexpr (SCHEME == 0) {
+        T tc[CX], tn[CX], zy[CX], zx[CX], fylo[CX], fyhi[CX], fxlo[CX], fxhi;
+        {
+            T tp[CX];
+            load_row<T, CX>(rowp(y0 - 1), tp);
+            load_row<T, CX>(rowp(y0), tc);
+            row_normals<T, CX>(zy, drow(y0, 1), nq, q0, slo, w2, real, key, noise);
+#pragma unroll
+            for (int j = 0; j < CX; ++j) fylo[j] = face_flux<T, EQ>(tp[j], tc[j], zy[j], r, sg, noise, amp0, clamps);
+        }
+        for (int y = y0; y < y1; ++y) {
+            load_row<T, CX>(rowp(y + 1), tn);
+            row_normals<T, CX>(zy, drow(y + 1, 1), nq, q0, slo, w2, real, key, noise);
+#pragma unroll
+            for (int j = 0; j < CX; ++j) fyhi[j] = face_flux<T, EQ>(tc[j], tn[j], zy[j], r, sg, noise, amp0, clamps);
+            row_normals<T, CX>(zx, drow(y, 0), nq, q0, slo, w2, real, key, noise);
+            row_xflux<T, CX, EQ>(tc, zx, fxlo, fxhi, lx, LX, r, sg, noise, amp0, clamps);
+            T out[CX];
+#pragma unroll
+            for (int j = 0; j < CX; ++j) {
+                out[j] = tc[j] + (xdiv<T, CX>(fxlo, fxhi, j) + (fyhi[j] - fylo[j]));
+                if (sample) {
+                    const double dl = static_cast<double>(out[j]) - u0d;
+                    sa += dl;
+                    sb += dl * dl;
+                }
+            }
+            store_row<T, CX>(D + static_cast<int64_t>(y) * p.nx, out);
+#pragma unroll
+            for (int j = 0; j < CX; ++j) {
+                tc[j] = tn[j];
+                fylo[j] = fyhi[j];
+            }
+        }
+    } else {
+        // Predictor-corrector.  Iteration k produces the predictor row k and
+        // the corrected row k-1.
+        T tm[CX], tc[CX], tn[CX];           // T rows k-1, k, k+1
+        T sm[CX], sc[CX];                   // predictor rows k-1, k
+        T zyc[CX], zyn[CX];                 // y numbers of rows k, k+1
+        T zxm[CX], zxc[CX];                 // x numbers of rows k-1, k
+        T fpc[CX], fpn[CX];                 // predictor low-y fluxes of rows k, k+1
+        T fcm[CX], fcc[CX];                 // corrector low-y fluxes of rows k-1, k
+        T fx[CX], fxh;
+        const int k0 = y0 - 1;
+        load_row<T, CX>(rowp(k0 - 1), tm);
+        load_row<T, CX>(rowp(k0), tc);
+        row_normals<T, CX>(zyc, drow(k0, 1), nq, q0, slo, w2, real, key, noise);
+#pragma unroll
+        for (int j = 0; j < CX; ++j) fpc[j] = face_flux<T, EQ>(tm[j], tc[j], zyc[j], r, sg, noise, amp0, clamps);
+        for (int k = k0; k <= y1; ++k) {
+            const int i = k - k0;
+            load_row<T, CX>(rowp(k + 1), tn);
+            row_normals<T, CX>(zyn, drow(k + 1, 1), nq, q0, slo, w2, real, key, noise);
+#pragma unroll
+            for (int j = 0; j < CX; ++j) fpn[j] = face_flux<T, EQ>(tc[j], tn[j], zyn[j], r, sg, noise, amp0, clamps);
+            row_normals<T, CX>(zxc, drow(k, 0), nq, q0, slo, w2, real, key, noise);
+            row_xflux<T, CX, EQ>(tc, zxc, fx, fxh, lx, LX, r, sg, noise, amp0, clamps);
+            T snew[CX];
+#pragma unroll
+            for (int j = 0; j < CX; ++j) snew[j] = tc[j] + (xdiv<T, CX>(fx, fxh, j) + (fpn[j] - fpc[j]));
+            if (i >= 1) {
+#pragma unroll
+                for (int j = 0; j < CX; ++j) fcc[j] = face_flux<T, EQ>(sc[j], snew[j], zyc[j], r, sg, noise, amp0, clamps);
+            }
+            if (i >= 2) {
+                // corrected row k-1 from predictor rows k-2 (fcm), k-1 (sc), k (snew)
+                row_xflux<T, CX, EQ>(sc, zxm, fx, fxh, lx, LX, r, sg, noise, amp0, clamps);
+                T out[CX];
+#pragma unroll
+                for (int j = 0; j < CX; ++j) {
+                    out[j] = T(0.5) * ((tm[j] + sc[j]) + (xdiv<T, CX>(fx, fxh, j) + (fcc[j] - fcm[j])));
+                    if (sample) {
+                        const double dl = static_cast<double>(out[j]) - u0d;
+                        sa += dl;
+                        sb += dl * dl;
+                    }
+                }
+                store_row<T, CX>(D + static_cast<int64_t>(k - 1) * p.nx, out);
+            }
+#pragma unroll
+            for (int j = 0; j < CX; ++j) {
+                tm[j] = tc[j];
+                tc[j] = tn[j];
+                sm[j] = sc[j];
+                sc[j] = snew[j];
+                zyc[j] = zyn[j];
+                zxm[j] = zxc[j];
+                fpc[j] = fpn[j];
+                fcm[j] = fcc[j];
+            }
+        }
+        (void)sm;
+    }
+
+    if (sample) {
+        for (int off = 1; off < LX; off <<= 1) {
+            sa += __shfl_xor(sa, off, 64);
+            sb += __shfl_xor(sb, off, 64);
+        }
+        if (lx == 0) {
+            part[2 * static_cast<int64_t>(gchunk)] = sa;
+            part[2 * static_cast<int64_t>(gchunk) + 1] = sb;
+        }
+    }
+    if (clamps) atomicAdd(reinterpret_cast<unsigned long long *>(&acc[inst].clamp_count),
+                          static_cast<unsigned long long>(clamps));
+}
+
+// ------------------------------------------------------------------ 3D (FE)
+
+template <typename T, int CX, int EQ>
+__global__ void __launch_bounds__(256)
+    k_step3d(ParamsND p, int32_t ty, const T *__restrict__ src, T *__restrict__ dst, int64_t step,
+             int32_t sample, double *__restrict__ part, InstAcc *__restrict__ acc)
+{
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const int LX = p.nx / CX;
+    const int lx = threadIdx.x % LX;
+    const int g = threadIdx.x / LX;                 // row within the tile
+    const int nyt = p.ny / ty, nzc = (p.nz + p.chunk - 1) / p.chunk;
+    const int tiles = nyt * nzc;
+    const int inst = blockIdx.x / tiles;
+    const int tile = blockIdx.x - inst * tiles;
+    const int yt = tile % nyt, zc = tile / nyt;
+    const int y = yt * ty + g;
+    const int z0 = zc * p.chunk, z1 = min(z0 + p.chunk, p.nz);
+    const int nx = p.nx, ny = p.ny, nz = p.nz;
+    const int64_t vol = static_cast<int64_t>(nx) * ny * nz;
+    const T *S = src + inst * vol + CX * lx;
+    T *D = dst + inst * vol + CX * lx;
+    auto rowp = [&](int yy, int zz) {
+        return static_cast<int64_t>(wrap(zz, nz) * ny + wrap(yy, ny)) * nx;
+    };
+
+    if (acc[inst].nonfinite) {
+        for (int zz = z0; zz < z1; ++zz) {
+            T v[CX];
+            load_row<T, CX>(S + rowp(y, zz), v);
+            store_row<T, CX>(D + rowp(y, zz), v);
+        }
+        return;
+    }
+
+    // LDS: T rows of the current plane and low-y fluxes, both double-buffered
+    T *tsh = reinterpret_cast<T *>(smem_raw);            // [2][ty][nx]
+    T *fsh = tsh + 2 * ty * nx;                           // [2][ty][nx]
+    const int cell0 = CX * lx;
+
+    const T r = static_cast<T>(p.r), sg = static_cast<T>(p.sigma);
+    uint32_t clamps = 0;
+    const T amp0 = amp_nd<T, EQ>(static_cast<T>(p.u0), clamps);
+    clamps = 0;
+    const int noise = p.noise;
+    const uint32_t real = p.realisation[inst];
+    const PhiloxKey key = make_key(p.seed);
+    const uint32_t slo = static_cast<uint32_t>(step), w2 = ctr_word2(static_cast<uint64_t>(step), 0u);
+    const uint32_t nq = static_cast<uint32_t>(nx / 4), q0 = static_cast<uint32_t>((CX / 4) * lx);
+    auto drow = [&](int yy, int zz, int e) {
+        return static_cast<uint32_t>((wrap(zz, nz) * ny + wrap(yy, ny)) * 3 + e);
+    };
+
+    T tc[CX], tn[CX], zz3[CX], fzlo[CX], fzhi[CX];
+    {
+        T tp[CX];
+        load_row<T, CX>(S + rowp(y, z0 - 1), tp);
+        load_row<T, CX>(S + rowp(y, z0), tc);
+        row_normals<T, CX>(zz3, drow(y, z0, 2), nq, q0, slo, w2, real, key, noise);
+#pragma unroll
+        for (int j = 0; j < CX; ++j) fzlo[j] = face_flux<T, EQ>(tp[j], tc[j], zz3[j], r, sg, noise, amp0, clamps);
+        T *dstp = tsh + ((z0 & 1) * ty + g) * nx + cell0;
+#pragma unroll
+        for (int j = 0; j < CX; ++j) dstp[j] = tc[j];
+    }
+    __syncthreads();
+
+    double sa = 0.0, sb = 0.0;
+    const double u0d = p.u0;
+    for (int zi = z0; zi < z1; ++zi) {
+        const int buf = zi & 1;
+        load_row<T, CX>(S + rowp(y, zi + 1), tn);
+        row_normals<T, CX>(zz3, drow(y, zi + 1, 2), nq, q0, slo, w2, real, key, noise);
+#pragma unroll
+        for (int j = 0; j < CX; ++j) fzhi[j] = face_flux<T, EQ>(tc[j], tn[j], zz3[j], r, sg, noise, amp0, clamps);
+
+        T zx[CX], fxlo[CX], fxhi;
+        row_normals<T, CX>(zx, drow(y, zi, 0), nq, q0, slo, w2, real, key, noise);
+        row_xflux<T, CX, EQ>(tc, zx, fxlo, fxhi, lx, LX, r, sg, noise, amp0, clamps);
+
+        T zy[CX], ylo[CX], fylo[CX];
+        row_normals<T, CX>(zy, drow(y, zi, 1), nq, q0, slo, w2, real, key, noise);
+        if (g > 0) {
+            const T *q = tsh + (buf * ty + g - 1) * nx + cell0;
+#pragma unroll
+            for (int j = 0; j < CX; ++j) ylo[j] = q[j];
+        } else {
+            load_row<T, CX>(S + rowp(y - 1, zi), ylo);
+        }
+#pragma unroll
+        for (int j = 0; j < CX; ++j) fylo[j] = face_flux<T, EQ>(ylo[j], tc[j], zy[j], r, sg, noise, amp0, clamps);
+        {
+            T *fp = fsh + (buf * ty + g) * nx + cell0;
+#pragma unroll
+            for (int j = 0; j < CX; ++j) fp[j] = fylo[j];
+            T *tp = tsh + (((zi + 1) & 1) * ty + g) * nx + cell0;
+#pragma unroll
+            for (int j = 0; j < CX; ++j) tp[j] = tn[j];
+        }
+        __syncthreads();
+        T fyhi[CX];
+        if (g + 1 < ty) {
+            const T *fp = fsh + (buf * ty + g + 1) * nx + cell0;
+#pragma unroll
+            for (int j = 0; j < CX; ++j) fyhi[j] = fp[j];
+        } else {
+            T yhi[CX], zyh[CX];
+            load_row<T, CX>(S + rowp(y + 1, zi), yhi);
+            row_normals<T, CX>(zyh, drow(y + 1, zi, 1), nq, q0, slo, w2, real, key, noise);
+#pragma unroll
+            for (int j = 0; j < CX; ++j) fyhi[j] = face_flux<T, EQ>(tc[j], yhi[j], zyh[j], r, sg, noise, amp0, clamps);
+        }
+        T out[CX];
+#pragma unroll
+        for (int j = 0; j < CX; ++j) {
+            out[j] = tc[j] + ((xdiv<T, CX>(fxlo, fxhi, j) + (fyhi[j] - fylo[j])) + (fzhi[j] - fzlo[j]));
+            if (sample) {
+                const double dl = static_cast<double>(out[j]) - u0d;
+                sa += dl;
+                sb += dl * dl;
+            }
+        }
+        store_row<T, CX>(D + rowp(y, zi), out);
+#pragma unroll
+        for (int j = 0; j < CX; ++j) {
+            tc[j] = tn[j];
+            fzlo[j] = fzhi[j];
+        }
+    }
+
+    if (sample) {
+        for (int off = 1; off < LX; off <<= 1) {
+            sa += __shfl_xor(sa, off, 64);
+            sb += __shfl_xor(sb, off, 64);
+        }
+        __syncthreads();
+        double *red = reinterpret_cast<double *>(smem_raw);
+        if (lx == 0) {
+            red[2 * g] = sa;
+            red[2 * g + 1] = sb;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double ta = 0.0, tb = 0.0;
+            for (int w = 0; w < ty; ++w) {
+                ta += red[2 * w];
+                tb += red[2 * w + 1];
+            }
+            part[2 * static_cast<int64_t>(blockIdx.x)] = ta;
+            part[2 * static_cast<int64_t>(blockIdx.x) + 1] = tb;
+        }
+    }
+    if (clamps) atomicAdd(reinterpret_cast<unsigned long long *>(&acc[inst].clamp_count),
+                          static_cast<unsigned long long>(clamps));
+}
+
+// Per-instance reduction of the sample partials, fixed order.
+__global__ void __launch_bounds__(64)
+    k_reduce_parts(const double *__restrict__ part, int32_t nparts, double inv_cells, InstAcc *__restrict__ acc)
+{
+    const int inst = blockIdx.x;
+    if (acc[inst].nonfinite) return;
+    const double *pp = part + 2 * static_cast<int64_t>(inst) * nparts;
+    double a = 0.0, b = 0.0;
+    for (int i = threadIdx.x; i < nparts; i += 64) {
+        a += pp[2 * i];
+        b += pp[2 * i + 1];
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        a += __shfl_xor(a, off, 64);
+        b += __shfl_xor(b, off, 64);
+    }
+    if (threadIdx.x == 0) {
+        if (!isfinite(a) || !isfinite(b)) {
+            acc[inst].nonfinite = 1;
+            return;
+        }
+        a *= inv_cells;
+        b *= inv_cells;
+        acc[inst].sp_mean += a;
+        acc[inst].sp_sq += b;
+        acc[inst].sp_var += b - a * a;
+        acc[inst].n_samples += 1;
+    }
+}
+
+// ------------------------------------------------------------------ init / finalisation
+
+template <typename T>
+__global__ void __launch_bounds__(256)
+    k_initnd(ParamsND p, int64_t cells, double init_sd, T *__restrict__ field)
+{
+    const int inst = blockIdx.y;
+    const int64_t c = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
+    if (c >= cells) return;
+    double v = p.u0;
+    if (init_sd > 0.0) {
+        const Normals4<double> nz = block_normals<double>(static_cast<uint32_t>(c >> 2), 0u, ctr_word2(0, 1u),
+                                                          p.realisation[inst], make_key(p.seed));
+        v += init_sd * nz.z[c & 3];
+    }
+    field[static_cast<int64_t>(inst) * cells + c] = static_cast<T>(v);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256)
+    k_finnd(ParamsND p, int inst, int64_t cells, const T *__restrict__ field, const InstAcc *__restrict__ acc,
+            const double *__restrict__ sk_sums, const double *__restrict__ sk_modes, int nbins,
+            double *__restrict__ out)
+{
+    __shared__ double red[256];
+    const T *f = field + static_cast<int64_t>(inst) * cells;
+    double a = 0.0;
+    for (int64_t c = threadIdx.x; c < cells; c += 256) a += static_cast<double>(f[c]);
+    red[threadIdx.x] = a;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const InstAcc q = acc[inst];
+        const double M = q.n_samples > 0 ? static_cast<double>(q.n_samples) : 1.0;
+        out[0] = p.u0 + q.sp_mean / M;
+        out[1] = q.sp_var / M;
+        out[2] = red[0];
+    }
+    // shell averages; the k = 0 mode of U = u0 + dU is
+    // sum_samples (N u0 + sum dU)^2 = M N^2 u0^2 + 2 N u0 (N sp_mean) + sum (sum dU)^2
+    if (nbins > 0) {
+        const InstAcc q = acc[inst];
+        const double M = q.n_samples > 0 ? static_cast<double>(q.n_samples) : 1.0;
+        const double N = static_cast<double>(cells);
+        const double *ss = sk_sums + static_cast<int64_t>(inst) * nbins;
+        for (int b = threadIdx.x; b < nbins; b += 256) {
+            double v = ss[b];
+            if (b == 0) v += M * N * N * p.u0 * p.u0 + 2.0 * N * p.u0 * (N * q.sp_mean);
+            out[3 + b] = sk_modes[b] > 0 ? v / (M * sk_modes[b]) : 0.0;
+        }
+    }
+}
+
+// ------------------------------------------------------------------ launchers
+
+template <typename T, int CX, int EQ>
+static hipError_t step2d_s(int scheme, int n_blocks, hipStream_t s, const ParamsND &p, const void *src, void *dst,
+                           int64_t step, int32_t sample, double *part, InstAcc *acc)
+{
+    if (scheme == 0)
+        hipLaunchKernelGGL((k_step2d<T, CX, EQ, 0>), dim3(n_blocks), dim3(256), 0, s, p,
+                           static_cast<const T *>(src), static_cast<T *>(dst), step, sample, part, acc);
+    else
+        hipLaunchKernelGGL((k_step2d<T, CX, EQ, 1>), dim3(n_blocks), dim3(256), 0, s, p,
+                           static_cast<const T *>(src), static_cast<T *>(dst), step, sample, part, acc);
+    return hipGetLastError();
+}
+
+template <typename T, int CX>
+static hipError_t step2d_e(int eq, int scheme, int n_blocks, hipStream_t s, const ParamsND &p, const void *src,
+                           void *dst, int64_t step, int32_t sample, double *part, InstAcc *acc)
+{
+    if (eq == 0) return step2d_s<T, CX, 0>(scheme, n_blocks, s, p, src, dst, step, sample, part, acc);
+    return step2d_s<T, CX, 1>(scheme, n_blocks, s, p, src, dst, step, sample, part, acc);
+}
+
+template <typename T>
+static hipError_t step2d_c(int cx, int eq, int scheme, int n_blocks, hipStream_t s, const ParamsND &p,
+                           const void *src, void *dst, int64_t step, int32_t sample, double *part, InstAcc *acc)
+{
+    switch (cx) {
+    case 4: return step2d_e<T, 4>(eq, scheme, n_blocks, s, p, src, dst, step, sample, part, acc);
+    case 8: return step2d_e<T, 8>(eq, scheme, n_blocks, s, p, src, dst, step, sample, part, acc);
+    case 16: return step2d_e<T, 16>(eq, scheme, n_blocks, s, p, src, dst, step, sample, part, acc);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_step2d(int prec, int cx, int eq, int scheme, int n_blocks, hipStream_t s, const ParamsND &p,
+                         const void *src, void *dst, int64_t step, int32_t sample, double *part, InstAcc *acc)
+{
+    if (prec == 0) return step2d_c<float>(cx, eq, scheme, n_blocks, s, p, src, dst, step, sample, part, acc);
+    return step2d_c<double>(cx, eq, scheme, n_blocks, s, p, src, dst, step, sample, part, acc);
+}
+
+template <typename T, int CX>
+static hipError_t step3d_e(int eq, int ty, int n_blocks, size_t smem, hipStream_t s, const ParamsND &p,
+                           const void *src, void *dst, int64_t step, int32_t sample, double *part, InstAcc *acc)
+{
+    const dim3 block((p.nx / CX) * ty);
+    if (eq == 0)
+        hipLaunchKernelGGL((k_step3d<T, CX, 0>), dim3(n_blocks), block, smem, s, p, ty, static_cast<const T *>(src),
+                           static_cast<T *>(dst), step, sample, part, acc);
+    else
+        hipLaunchKernelGGL((k_step3d<T, CX, 1>), dim3(n_blocks), block, smem, s, p, ty, static_cast<const T *>(src),
+                           static_cast<T *>(dst), step, sample, part, acc);
+    return hipGetLastError();
+}
+
+hipError_t launch_step3d(int prec, int cx, int eq, int ty, int n_blocks, size_t smem, hipStream_t s,
+                         const ParamsND &p, const void *src, void *dst, int64_t step, int32_t sample, double *part,
+                         InstAcc *acc)
+{
+    if (prec == 0) {
+        if (cx == 4) return step3d_e<float, 4>(eq, ty, n_blocks, smem, s, p, src, dst, step, sample, part, acc);
+        if (cx == 8) return step3d_e<float, 8>(eq, ty, n_blocks, smem, s, p, src, dst, step, sample, part, acc);
+        if (cx == 16) return step3d_e<float, 16>(eq, ty, n_blocks, smem, s, p, src, dst, step, sample, part, acc);
+    } else {
+        if (cx == 4) return step3d_e<double, 4>(eq, ty, n_blocks, smem, s, p, src, dst, step, sample, part, acc);
+        if (cx == 8) return step3d_e<double, 8>(eq, ty, n_blocks, smem, s, p, src, dst, step, sample, part, acc);
+        if (cx == 16) return step3d_e<double, 16>(eq, ty, n_blocks, smem, s, p, src, dst, step, sample, part, acc);
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_reduce_parts(int n_inst, hipStream_t s, const double *part, int32_t nparts, double inv_cells,
+                               InstAcc *acc)
+{
+    hipLaunchKernelGGL(k_reduce_parts, dim3(n_inst), dim3(64), 0, s, part, nparts, inv_cells, acc);
+    return hipGetLastError();
+}
+
+hipError_t launch_initnd(int prec, hipStream_t s, const ParamsND &p, int64_t cells, double init_sd, void *field)
+{
+    const dim3 grid(static_cast<unsigned>((cells + 255) / 256), p.n_inst);
+    if (prec == 0)
+        hipLaunchKernelGGL(k_initnd<float>, grid, dim3(256), 0, s, p, cells, init_sd, static_cast<float *>(field));
+    else
+        hipLaunchKernelGGL(k_initnd<double>, grid, dim3(256), 0, s, p, cells, init_sd, static_cast<double *>(field));
+    return hipGetLastError();
+}
+
+hipError_t launch_finnd(int prec, hipStream_t s, const ParamsND &p, int inst, int64_t cells, const void *field,
+                        const InstAcc *acc, const double *sk_sums, const double *sk_modes, int nbins, double *out)
+{
+    if (prec == 0)
+        hipLaunchKernelGGL(k_finnd<float>, dim3(1), dim3(256), 0, s, p, inst, cells,
+                           static_cast<const float *>(field), acc, sk_sums, sk_modes, nbins, out);
+    else
+        hipLaunchKernelGGL(k_finnd<double>, dim3(1), dim3(256), 0, s, p, inst, cells,
+                           static_cast<const double *>(field), acc, sk_sums, sk_modes, nbins, out);
+    return hipGetLastError();
+}
+
+}  // namespace she

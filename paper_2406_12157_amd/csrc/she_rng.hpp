@@ -1,0 +1,112 @@
+// Counter-based Gaussian noise for the step kernels (gfx950).
+//
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds; each round
+// forms the 64-bit products of words 0 and 2 with the two round multipliers and
+// recombines their halves with words 1 and 3 and the round key; the key is
+// advanced by the two Weyl increments between rounds.  The key is uniform over
+// a launch, so its schedule lives in scalar registers.
+//
+// Box-Muller: uniforms u = ((w >> 9) + 1/2) 2^-23 (exact in FP32 and FP64),
+// pairs (lane 0, lane 1) and (lane 2, lane 3); even lane
+// sqrt(-2 ln u_a) cos(2 pi u_b), odd lane sqrt(-2 ln u_a) sin(2 pi u_b).
+// The FP32 form uses the native v_log_f32 (log2), v_sqrt_f32 and
+// v_sin_f32 / v_cos_f32, whose argument is in revolutions, so 2 pi u_b
+// needs no multiply and no range reduction.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace she {
+
+struct PhiloxKey {
+    uint32_t k0, k1;
+};
+
+__host__ __device__ inline PhiloxKey make_key(uint64_t seed)
+{
+    return PhiloxKey{static_cast<uint32_t>(seed), static_cast<uint32_t>(seed >> 32)};
+}
+
+// Counter word 2 of step n for stream tag g.
+__host__ __device__ inline uint32_t ctr_word2(uint64_t step, uint32_t tag)
+{
+    return static_cast<uint32_t>((step >> 32) & 0xFFFFu) | (tag << 16);
+}
+
+struct Words4 {
+    uint32_t w[4];
+};
+
+__device__ __forceinline__ Words4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2,
+                                                 uint32_t c3, PhiloxKey key)
+{
+    uint32_t k0 = key.k0, k1 = key.k1;
+#pragma unroll
+    for (int round = 0; round < 10; ++round) {
+        const uint64_t p0 = static_cast<uint64_t>(0xD2511F53u) * c0;
+        const uint64_t p1 = static_cast<uint64_t>(0xCD9E8D57u) * c2;
+        const uint32_t hi0 = static_cast<uint32_t>(p0 >> 32), lo0 = static_cast<uint32_t>(p0);
+        const uint32_t hi1 = static_cast<uint32_t>(p1 >> 32), lo1 = static_cast<uint32_t>(p1);
+        // three-input xor in one v_bitop3_b32 (truth table 0x96)
+        c0 = __builtin_amdgcn_bitop3_b32(hi1, c1, k0, 0x96);
+        c1 = lo1;
+        c2 = __builtin_amdgcn_bitop3_b32(hi0, c3, k1, 0x96);
+        c3 = lo0;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    return Words4{{c0, c1, c2, c3}};
+}
+
+template <typename T>
+struct Normals4 {
+    T z[4];
+};
+
+__device__ __forceinline__ float unit_open_f32(uint32_t w)
+{
+    return __builtin_fmaf(static_cast<float>(w >> 9), 0x1p-23f, 0x1p-24f);
+}
+
+__device__ __forceinline__ double unit_open_f64(uint32_t w)
+{
+    return (static_cast<double>(w >> 9) + 0.5) * 0x1p-23;
+}
+
+__device__ __forceinline__ void box_muller(uint32_t wa, uint32_t wb, float &zc, float &zs)
+{
+    const float ua = unit_open_f32(wa);
+    const float ub = unit_open_f32(wb);
+    // -2 ln(u) = -2 ln(2) log2(u)
+    const float rho = __builtin_amdgcn_sqrtf(__builtin_amdgcn_logf(ua) * -1.38629436111989061883f);
+    zc = rho * __builtin_amdgcn_cosf(ub);
+    zs = rho * __builtin_amdgcn_sinf(ub);
+}
+
+__device__ __forceinline__ void box_muller(uint32_t wa, uint32_t wb, double &zc, double &zs)
+{
+    const double ua = unit_open_f64(wa);
+    const double ub = unit_open_f64(wb);
+    const double rho = sqrt(-2.0 * log(ua));
+    const double ang = (2.0 * 3.14159265358979323846) * ub;
+    double s, c;
+    sincos(ang, &s, &c);
+    zc = rho * c;
+    zs = rho * s;
+}
+
+// The four normals of Philox block `block` at step `step`.
+template <typename T>
+__device__ __forceinline__ Normals4<T> block_normals(uint32_t block, uint32_t step_lo,
+                                                     uint32_t w2, uint32_t realisation,
+                                                     PhiloxKey key)
+{
+    const Words4 x = philox4x32_10(block, step_lo, w2, realisation, key);
+    Normals4<T> n;
+    box_muller(x.w[0], x.w[1], n.z[0], n.z[1]);
+    box_muller(x.w[2], x.w[3], n.z[2], n.z[3]);
+    return n;
+}
+
+}  // namespace she

@@ -1,0 +1,83 @@
+"""CPU-side checks of the C ABI: the library loads, exports every function
+declared in include/she.h, and rejects invalid configurations before any
+device work (no GPU needed)."""
+import os
+import re
+
+import pytest
+
+from paper_2406_12157_amd import she
+from paper_2406_12157_amd import workloads as W
+from helpers import gpu_instance
+
+HEADER = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include", "she.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    decl = r"^(?:she_status|void|const char \*)\s*(she_[a-z_]+)\s*\("
+    return sorted(set(re.findall(decl, text, flags=re.M)))
+
+
+def test_header_and_binding_agree():
+    assert declared_functions() == sorted(she.EXPORTS)
+
+
+def test_library_exports_every_symbol():
+    lib = she.load()
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+
+
+def cfg_for(insts, **kw):
+    return [gpu_instance(she, i) for i in insts], kw
+
+
+@pytest.mark.parametrize("mutate,status", [
+    (dict(r=0.6), she.EUNSTABLE),
+    (dict(r=-0.1), she.EINVAL),
+    (dict(eps=-1.0), she.EINVAL),
+    (dict(u_left=1.0, u_right=2.0), she.EINVAL),        # gradient with periodic walls
+    (dict(n=(1,)), she.EINVAL),
+    (dict(scheme=7), she.EINVAL),
+    (dict(noise=3), she.EINVAL),
+])
+def test_invalid_1d_configs(mutate, status):
+    inst = W.instance((64,), r=0.2)
+    inst.update(mutate)
+    with pytest.raises(she.SheError) as e:
+        she.Handle.arena_bytes([gpu_instance(she, inst)])
+    assert e.value.status == status
+
+
+def test_invalid_nd_configs():
+    with pytest.raises(she.SheError) as e:
+        she.Handle.arena_bytes([gpu_instance(she, W.instance((48, 16), r=0.1))])
+    assert e.value.status == she.EUNSUPPORTED            # n[0] not a power of two
+    with pytest.raises(she.SheError) as e:
+        she.Handle.arena_bytes([gpu_instance(she, W.instance((64, 64), r=0.3))])
+    assert e.value.status == she.EUNSTABLE               # r > 1/4 in 2D
+    with pytest.raises(she.SheError) as e:
+        she.Handle.arena_bytes([gpu_instance(she, W.instance((64, 64), r=0.1, bc=W.DIRICHLET))])
+    assert e.value.status == she.EINVAL
+    a = W.instance((64, 64), r=0.1, realisation=0)
+    b = W.instance((64, 64), r=0.11, realisation=1)
+    with pytest.raises(she.SheError) as e:
+        she.Handle.arena_bytes([gpu_instance(she, a), gpu_instance(she, b)])
+    assert e.value.status == she.EUNSUPPORTED
+
+
+def test_arena_bytes_scale_with_problem():
+    small = she.Handle.arena_bytes([gpu_instance(she, W.instance((64, 64), r=0.1))])
+    big = she.Handle.arena_bytes([gpu_instance(she, W.instance((512, 512), r=0.1))])
+    assert big >= 2 * 4 * 512 * 512 > small
+    c3 = W.c3()
+    b = she.Handle.arena_bytes([gpu_instance(she, i) for i in c3["instances"]], stats=she.STAT_SPATIAL)
+    assert b >= 2 * 4 * 512 * 512 * 256
+
+
+def test_ragged_batch_plan_accepts_c4():
+    c4 = W.c4()
+    b = she.Handle.arena_bytes([gpu_instance(she, i) for i in c4["instances"]], stats=she.STAT_MOMENTS)
+    total = sum(i["n"][0] for i in c4["instances"])
+    assert b >= total * (4 + 16)

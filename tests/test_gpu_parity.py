@@ -1,0 +1,338 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle on
+identical noise, element by element.
+
+Bars (FP32 state): max relative state error <= 1e-5 after 1e4 steps; FP64
+state: <= 1e-12.  Philox words: bit-exact.  Statistics: <= 1e-3 relative
+(the two trajectories differ only by rounding, so the agreement is far
+tighter in practice).
+"""
+import numpy as np
+import pytest
+
+import oracle
+from helpers import gpu_instance, max_rel, oracle_desc
+from paper_2406_12157_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def she():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2406_12157_amd import she as mod
+    mod.load()
+    return mod
+
+
+def run_both(she, insts, steps, precision, **kw):
+    """Run the GPU batch and the oracle (per instance) from the GPU's initial
+    field; return lists of (gpu, oracle) fields."""
+    h = she.Handle([gpu_instance(she, i) for i in insts], precision=precision, **kw)
+    init = [h.read_field(q) for q in range(len(insts))]
+    h.step(steps)
+    got = [h.read_field(q) for q in range(len(insts))]
+    h.close()
+    want = []
+    for q, inst in enumerate(insts):
+        u = init[q].copy()
+        oracle.advance(oracle_desc(inst, precision), u, 0, steps)
+        want.append(u)
+    return init, got, want
+
+
+# ---------------------------------------------------------------- noise
+
+def test_philox_words_bit_exact(she):
+    rng = np.random.default_rng(7)
+    ctr = rng.integers(0, 2 ** 32, size=(2000, 4), dtype=np.uint64).astype(np.uint32)
+    ctr[0] = 0
+    ctr[1] = 0xFFFFFFFF
+    for seed in (0, 1, 0xDEADBEEFCAFEF00D):
+        got = she.debug_philox(seed, ctr)
+        want = np.array([oracle.philox(c, [seed & 0xFFFFFFFF, seed >> 32]) for c in ctr], dtype=np.uint32)
+        np.testing.assert_array_equal(got, want)
+
+
+@pytest.mark.parametrize("precision,tol", [(0, 2e-5), (1, 1e-13)])
+def test_face_normals(she, precision, tol):
+    for (seed, real, tag, step, face0) in [(0, 0, 0, 0, 0), (3, 17, 0, 123456789, 1001),
+                                           (0, 5, 1, 0, 0), (9, 2, 0, 2 ** 33 + 7, 2 ** 20)]:
+        got = she.debug_normals(seed, real, tag, step, face0, 4096, precision)
+        want = oracle.normals(seed, real, tag, step, face0, 4096)
+        err = np.max(np.abs(got - want) / np.maximum(1.0, np.abs(want)))
+        assert err < tol, (seed, real, tag, step, face0, err)
+
+
+# ---------------------------------------------------------------- 1D
+
+CASES_1D = [
+    # n, bc, scheme, eq, noise
+    ((64,), W.PERIODIC, W.EM, W.HEAT, 0),
+    ((37,), W.PERIODIC, W.HEUN, W.HEAT, 0),
+    ((128,), W.DIRICHLET, W.HEUN, W.HEAT, 0),
+    ((130,), W.DIRICHLET, W.EM, W.HEAT, 1),
+    ((256,), W.DIRICHLET, W.EM, W.HEAT, 0),
+    ((100,), W.PERIODIC, W.EM, W.SPECIES, 0),
+    ((61,), W.DIRICHLET, W.HEUN, W.SPECIES, 0),
+    ((1000,), W.DIRICHLET, W.HEUN, W.HEAT, 0),
+    ((2,), W.PERIODIC, W.EM, W.HEAT, 0),
+    ((1,), W.DIRICHLET, W.HEUN, W.HEAT, 0),
+]
+
+
+def inst1d(n, bc, scheme, eq, noise, realisation=0, seed=0):
+    if eq == W.HEAT:
+        ul, ur = (1.1, 0.9) if bc == W.DIRICHLET else (1.0, 1.0)
+        return W.instance(n, eq=eq, bc=bc, scheme=scheme, noise=noise, r=0.2 if scheme == W.EM else 0.05,
+                          eps=1e-2, u0=1.0, u_left=ul, u_right=ur, init_sd=0.1, seed=seed, realisation=realisation)
+    ul, ur = (120.0, 80.0) if bc == W.DIRICHLET else (100.0, 100.0)
+    return W.instance(n, eq=eq, bc=bc, scheme=scheme, noise=noise, r=0.1, eps=1.0, u0=100.0, u_left=ul,
+                      u_right=ur, init_sd=10.0, seed=seed, realisation=realisation)
+
+
+@pytest.mark.parametrize("case", CASES_1D, ids=lambda c: "n%d-bc%d-s%d-eq%d-nz%d" % ((c[0][0],) + tuple(c[1:])))
+def test_1d_fp32_state_parity(she, case):
+    inst = inst1d(*case)
+    _, got, want = run_both(she, [inst], 10000, 0)
+    err = max_rel(got[0], want[0])
+    assert err <= 1e-5, err
+
+
+@pytest.mark.parametrize("case", CASES_1D[:4], ids=lambda c: "n%d" % c[0][0])
+def test_1d_fp64_state_parity(she, case):
+    inst = inst1d(*case)
+    _, got, want = run_both(she, [inst], 10000, 1)
+    err = max_rel(got[0], want[0])
+    assert err <= 1e-12, err
+
+
+def test_1d_ragged_batch_and_independence(she):
+    insts = [inst1d(*c, realisation=q, seed=5) for q, c in enumerate(CASES_1D)]
+    _, got, want = run_both(she, insts, 3000, 0)
+    for q in range(len(insts)):
+        assert max_rel(got[q], want[q]) <= 1e-5, q
+    # an instance's trajectory does not depend on its neighbours in the batch
+    _, alone, _ = run_both(she, [insts[2]], 3000, 0)
+    np.testing.assert_array_equal(alone[0], got[2])
+
+
+def test_1d_launch_shape_invariance(she):
+    insts = [inst1d(*c, realisation=q) for q, c in enumerate(CASES_1D[:6])]
+    _, a, _ = run_both(she, insts, 2000, 0, block_threads=64)
+    _, b, _ = run_both(she, insts, 2000, 0, block_threads=256)
+    for x, y in zip(a, b):
+        np.testing.assert_array_equal(x, y)
+
+
+# ---------------------------------------------------------------- 2D / 3D
+
+CASES_2D = [((64, 48), W.EM, W.HEAT), ((64, 48), W.HEUN, W.HEAT), ((32, 32), W.EM, W.SPECIES),
+            ((128, 20), W.HEUN, W.SPECIES), ((512, 6), W.EM, W.HEAT), ((512, 5), W.HEUN, W.HEAT),
+            ((16, 16), W.HEUN, W.HEAT), ((1024, 3), W.EM, W.HEAT), ((8, 40), W.EM, W.HEAT)]
+
+
+def inst2d(n, scheme, eq, realisation=0):
+    if eq == W.HEAT:
+        return W.instance(n, eq=eq, scheme=scheme, r=0.1, eps=1e-2, u0=1.0, init_sd=0.1, realisation=realisation)
+    return W.instance(n, eq=eq, scheme=scheme, r=0.1, eps=1.0, u0=200.0, init_sd=14.0, realisation=realisation)
+
+
+@pytest.mark.parametrize("case", CASES_2D, ids=lambda c: "%dx%d-s%d-eq%d" % (c[0] + c[1:]))
+def test_2d_fp32_state_parity(she, case):
+    n, scheme, eq = case
+    insts = [inst2d(n, scheme, eq, realisation=q) for q in range(2)]
+    steps = 10000 if n[0] * n[1] <= 4096 else 2000
+    _, got, want = run_both(she, insts, steps, 0, rows_per_block=7)
+    for q in range(2):
+        err = max_rel(got[q], want[q])
+        assert err <= 1e-5, (q, err)
+
+
+def test_2d_fp64_state_parity(she):
+    insts = [inst2d((64, 24), W.HEUN, W.HEAT, realisation=q) for q in range(2)]
+    _, got, want = run_both(she, insts, 3000, 1)
+    for q in range(2):
+        assert max_rel(got[q], want[q]) <= 1e-12
+
+
+def test_2d_chunking_invariance(she):
+    insts = [inst2d((64, 48), s, W.HEAT, realisation=q) for q, s in enumerate((W.EM, W.HEUN))]
+    for inst in insts:
+        outs = []
+        for rpb in (1, 5, 16, 48):
+            _, got, _ = run_both(she, [inst], 500, 0, rows_per_block=rpb)
+            outs.append(got[0])
+        for o in outs[1:]:
+            np.testing.assert_array_equal(o, outs[0])
+
+
+CASES_3D = [((16, 8, 8), W.SPECIES), ((32, 4, 6), W.HEAT), ((64, 8, 5), W.SPECIES), ((256, 4, 3), W.SPECIES)]
+
+
+def inst3d(n, eq, realisation=0):
+    if eq == W.HEAT:
+        return W.instance(n, eq=eq, r=0.05, eps=1e-2, u0=1.0, init_sd=0.1, realisation=realisation)
+    return W.instance(n, eq=eq, r=0.05, eps=1.0, u0=1000.0, init_sd=31.6, realisation=realisation)
+
+
+@pytest.mark.parametrize("case", CASES_3D, ids=lambda c: "%dx%dx%d-eq%d" % (c[0] + c[1:]))
+def test_3d_fp32_state_parity(she, case):
+    n, eq = case
+    insts = [inst3d(n, eq, realisation=q) for q in range(2)]
+    steps = 2000 if np.prod(n) <= 2048 else 300
+    _, got, want = run_both(she, insts, steps, 0, rows_per_block=3)
+    for q in range(2):
+        err = max_rel(got[q], want[q])
+        assert err <= 1e-5, (q, err)
+
+
+def test_3d_tiling_invariance(she):
+    inst = inst3d((32, 8, 6), W.SPECIES)
+    outs = []
+    for rpb, rpg in ((1, 1), (4, 2), (6, 8), (2, 4)):
+        _, got, _ = run_both(she, [inst], 200, 0, rows_per_block=rpb, rows_per_group=rpg)
+        outs.append(got[0])
+    for o in outs[1:]:
+        np.testing.assert_array_equal(o, outs[0])
+
+
+# ---------------------------------------------------------------- statistics
+
+def oracle_stats_run(inst, precision, init, steps, burn_in, every, corr=False):
+    d = oracle_desc(inst, precision)
+    st = oracle.Stats(d, burn_in=burn_in, every=every, corr=corr, sk=corr)
+    u = init.copy()
+    oracle.advance(d, u, 0, steps, st)
+    return st, u
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_1d_statistics_parity(she, precision):
+    inst = inst1d((96,), W.DIRICHLET, W.HEUN, W.HEAT, 0)
+    h = she.Handle([gpu_instance(she, inst)], precision=precision, burn_in=300, sample_every=3,
+                   stats=she.STAT_MOMENTS | she.STAT_CORR)
+    init = h.read_field(0)
+    h.run(6000)            # 1900 samples: 7 full 256-row blocks + an open block
+    g = h.stats(0, corr=True, sk=True)
+    h.close()
+    st, _ = oracle_stats_run(inst, precision, init, 6000, 300, 3, corr=True)
+    assert g["n_samples"] == st.n_samples == 1900
+    tol = 1e-3 if precision == 0 else 1e-9
+    assert max_rel(g["mean"], st.mean()) < tol
+    assert max_rel(g["var"], st.var()) < tol
+    cov = st.cov()
+    scale = np.max(np.abs(cov))
+    assert np.max(np.abs(g["corr"] - cov)) < tol * scale
+    assert max_rel(g["sk"], st.structure_factor()) < tol
+
+
+def test_nd_spatial_statistics_parity(she):
+    insts = [inst2d((64, 32), W.EM, W.HEAT, realisation=q) for q in range(3)]
+    h = she.Handle([gpu_instance(she, i) for i in insts], precision=0, burn_in=100, sample_every=5,
+                   stats=she.STAT_SPATIAL)
+    init = [h.read_field(q) for q in range(3)]
+    h.run(1500)
+    for q in range(3):
+        g = h.stats(q)
+        st, u = oracle_stats_run(insts[q], 0, init[q], 1500, 100, 5)
+        assert g["n_samples"] == st.n_samples == 280
+        sp = st.spatial()
+        assert abs(g["var"][0] / sp[2] - 1) < 1e-3
+        assert abs(g["mean"][0] - (1.0 + sp[0])) < 1e-6
+        assert abs(g["sum_u"] / u.sum() - 1) < 1e-6
+    h.close()
+
+
+@pytest.mark.parametrize("shape,precision", [((32, 16), 0), ((8, 32), 0), ((64, 64), 0), ((512, 8), 0),
+                                             ((16, 16), 1)])
+def test_2d_radial_structure_factor_parity(she, shape, precision):
+    insts = [inst2d(shape, W.EM, W.HEAT, realisation=q) for q in range(2)]
+    h = she.Handle([gpu_instance(she, i) for i in insts], precision=precision, burn_in=20, sample_every=2,
+                   stats=she.STAT_SPATIAL | she.STAT_SK)
+    init = [h.read_field(q) for q in range(2)]
+    h.run(200)
+    tol = 1e-3 if precision == 0 else 1e-9
+    for q in range(2):
+        g = h.stats(q, sk=True)
+        d = oracle_desc(insts[q], precision)
+        st = oracle.Stats(d, burn_in=20, every=2, per_cell=False, sk=True)
+        u = init[q].copy()
+        oracle.advance(d, u, 0, 200, st)
+        assert g["n_samples"] == st.n_samples == 90
+        np.testing.assert_array_equal(g["sk_modes"], oracle.bin_modes(d))
+        want = st.structure_factor()
+        ok = g["sk_modes"] > 0
+        assert max_rel(g["sk"][ok], want[ok]) < tol, max_rel(g["sk"][ok], want[ok])
+    h.close()
+
+
+def test_c3_full_size_sampled_parity(she):
+    """512 x 512 x 256 realisations in the benchmark's launch configuration:
+    every realisation steps on the GPU; sampled realisations are checked
+    against the oracle field by field."""
+    cfg = W.c3()
+    insts = cfg["instances"]
+    h = she.Handle([gpu_instance(she, i) for i in insts], precision=0, burn_in=0, sample_every=10,
+                   stats=she.STAT_SPATIAL | she.STAT_SK)
+    picks = [0, 131, 255]
+    init = {q: h.read_field(q) for q in picks}
+    h.run(20)
+    for q in picks:
+        got = h.read_field(q)
+        u = init[q].copy()
+        oracle.advance(oracle_desc(insts[q], 0), u, 0, 20)
+        assert max_rel(got, u) <= 1e-5
+    h.close()
+
+
+# ---------------------------------------------------------------- runtime behaviour
+
+def test_checkpoint_resume_is_bit_exact(she):
+    for inst, prec in ((inst1d((128,), W.DIRICHLET, W.HEUN, W.HEAT, 0), 0), (inst2d((64, 16), W.EM, W.HEAT), 0)):
+        mask = she.STAT_MOMENTS | she.STAT_CORR if len(inst["n"]) == 1 else she.STAT_SPATIAL
+        a = she.Handle([gpu_instance(she, inst)], precision=prec, burn_in=0, sample_every=2, stats=mask)
+        a.run(700)
+        blob = a.get_state()
+        a.run(900)
+        fa, sa = a.read_field(0), a.stats(0)
+        b = she.Handle([gpu_instance(she, inst)], precision=prec, burn_in=0, sample_every=2, stats=mask)
+        b.set_state(blob)
+        assert b.steps == 700
+        b.run(900)
+        fb, sb = b.read_field(0), b.stats(0)
+        np.testing.assert_array_equal(fa, fb)
+        np.testing.assert_array_equal(sa["var"], sb["var"])
+        assert sa["n_samples"] == sb["n_samples"]
+        a.close()
+        b.close()
+
+
+def test_literal_eps_diverges_and_freezes(she):
+    cfg = W.c1(eps=100.0)
+    h = she.Handle([gpu_instance(she, i) for i in cfg["instances"]], precision=1, burn_in=0, sample_every=10,
+                   stats=she.STAT_MOMENTS)
+    h.run(20000)
+    with pytest.raises(she.SheError) as e:
+        h.stats(0)
+    assert e.value.status == she.ENONFINITE
+    s = h.stats(0, raise_nonfinite=False)
+    assert s["nonfinite"]
+    frozen = h.read_field(0)
+    h.run(100)
+    np.testing.assert_array_equal(h.read_field(0), frozen)
+    h.close()
+
+
+def test_write_field_roundtrip_and_noise_off_decay(she):
+    n, r, k = 64, 0.2, 3
+    inst = W.instance((n,), r=r, noise=2)
+    h = she.Handle([gpu_instance(she, inst)], precision=1)
+    x = (np.arange(n) + 0.5) / n
+    u = 1.0 + 0.1 * np.cos(2 * np.pi * k * x)
+    h.write_field(0, u)
+    np.testing.assert_array_equal(h.read_field(0), u)
+    h.step(50)
+    g = 1 - 4 * r * np.sin(np.pi * k / n) ** 2
+    np.testing.assert_allclose(h.read_field(0), 1.0 + 0.1 * g ** 50 * np.cos(2 * np.pi * k * x), atol=1e-13)
+    h.close()
