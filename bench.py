@@ -52,21 +52,27 @@ def make_handle(she, cfg, stats):
 
 def timed_run(torch, h, steps, every):
     """Wall time of `steps` sampled steps, plus HIP-event time of the step
-    kernel alone (events around each non-sample step on the library's stream)."""
+    kernel alone: in every sampling period one non-sample step is bracketed
+    by events on the library's stream (torch's current stream), the rest of
+    the period (including the sample step) is enqueued in one call."""
     ev = []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for k in range(steps):
+    done = 0
+    while done < steps:
         t = h.steps + 1
-        if t % every != 0 and len(ev) < 4096:
+        if t % every != 0 and steps - done >= 1:
             a = torch.cuda.Event(enable_timing=True)
             b = torch.cuda.Event(enable_timing=True)
             a.record()
             h.run(1)
             b.record()
             ev.append((a, b))
-        else:
-            h.run(1)
+            done += 1
+        rest = min(steps - done, every - (h.steps % every)) if every > 1 else steps - done
+        if rest > 0:
+            h.run(rest)
+            done += rest
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     kms = sum(a.elapsed_time(b) for a, b in ev) / max(1, len(ev))
@@ -139,6 +145,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-error", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run one 1 GiB device-to-device copy (reference for HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build runs on one GPU only (--gpus 1); the path would shard by realisation "
@@ -155,7 +163,7 @@ def main():
     cfg = W.c3(realisations=args.realisations, scheme=scheme)
     every = cfg["sample_every"]
 
-    h, insts = make_handle(she, cfg, she.STAT_SPATIAL)
+    h, insts = make_handle(she, cfg, she.STAT_SPATIAL | she.STAT_SK)
     cells = sum(i.ncells for i in insts)
     h.run(args.warmup)
     torch.cuda.synchronize()
@@ -177,12 +185,12 @@ def main():
            "vs_baseline": None, "dtype": "f32", "data": "synthetic",
            "config": {"workload": cfg["name"], "grid": [512, 512], "realisations": args.realisations,
                       "scheme": args.scheme, "r": 0.1, "eps": 1e-2, "sample_every": every,
-                      "stats": "spatial mean/variance per sample (FP64)", "parallelism": "single GPU"},
+                      "stats": "spatial mean/variance + radially binned S(k) per sample (FP64 sums)", "parallelism": "single GPU"},
            "roofline": roofline}
 
     if not args.no_plain:
         pcfg = W.c3(realisations=1, scheme=scheme)
-        ph, pinsts = make_handle(she, pcfg, she.STAT_SPATIAL)
+        ph, pinsts = make_handle(she, pcfg, she.STAT_SPATIAL | she.STAT_SK)
         ph.run(args.warmup)
         psteps = max(200, args.steps // 2)
         pwall, pkms, _ = timed_run(torch, ph, psteps, every)
@@ -198,6 +206,14 @@ def main():
                         "stats_samples": st0["n_samples"]}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(cfg, args.cpu_seconds)
+    if args.copy_calibration:
+        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        out["copy_calibration_bytes"] = {"read": src.numel() * 4, "write": dst.numel() * 4}
+        del src, dst
     print(json.dumps(out), flush=True)
 
 

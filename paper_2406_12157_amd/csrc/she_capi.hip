@@ -62,9 +62,11 @@ struct she_handle {
     size_t smem3d = 0;
     // 2D structure factor
     int nbins = 0, sk_groups = 0;
-    void *d_half = nullptr;
+    void *d_half = nullptr, *d_twx = nullptr, *d_twy = nullptr;
     double *d_skpart = nullptr, *d_sksum = nullptr, *d_skmodes = nullptr;
+    int32_t *d_sklo = nullptr;
     std::vector<double> skmodes;
+    std::vector<int32_t> sklo;
 
     void *field() const { return dim == 1 ? d_pool : (cur == 0 ? d_a : d_b); }
 };
@@ -251,8 +253,9 @@ static she_status plan_nd(she_handle *h, const she_config *cfg, Plan &plan)
     if (h->mask & (SHE_STAT_CORR | SHE_STAT_MOMENTS))
         return fail(nullptr, SHE_EUNSUPPORTED, "2D/3D statistics are SHE_STAT_SPATIAL (and SHE_STAT_SK)");
     if (h->mask & SHE_STAT_SK) {
-        if (d0.dim != 2 || !is_pow2(d0.n[1]) || d0.n[1] < 2)
-            return fail(nullptr, SHE_EUNSUPPORTED, "SHE_STAT_SK is provided for 2D grids with n[1] a power of two");
+        if (d0.dim != 2 || !is_pow2(d0.n[1]) || d0.n[1] < 2 || d0.n[1] > 1024)
+            return fail(nullptr, SHE_EUNSUPPORTED,
+                        "SHE_STAT_SK is provided for 2D grids with n[1] a power of two in [2, 1024]");
         h->mask |= SHE_STAT_SPATIAL;
     }
     int cx = 4;
@@ -271,6 +274,12 @@ static she_status plan_nd(she_handle *h, const she_config *cfg, Plan &plan)
     p.r = d0.r;
     p.sigma = std::sqrt(2.0 * d0.r * d0.eps);
     p.u0 = d0.u0;
+    if (d0.noise == SHE_NOISE_FROZEN)
+        p.ns = p.sigma * (d0.eq == SHE_HEAT ? d0.u0 : std::sqrt(std::max(d0.u0, 0.0)));
+    else if (d0.noise == SHE_NOISE_INSTANT)
+        p.ns = d0.eq == SHE_HEAT ? 0.5 * p.sigma : p.sigma * std::sqrt(0.5);
+    else
+        p.ns = 0.0;
     p.seed = d0.seed;
     h->cells = static_cast<int64_t>(p.nx) * p.ny * p.nz;
     if (d0.dim == 2) {
@@ -324,6 +333,11 @@ static she_status plan_nd(she_handle *h, const she_config *cfg, Plan &plan)
         h->sk_groups = sk2d_groups(h->prec, nx, p.ny);
         const size_t nh = static_cast<size_t>(nx / 2 + 1);
         plan.add(&h->d_half, 2 * es * nh * p.ny * h->n_inst);
+        plan.add(&h->d_twx, 2 * es * nx);
+        plan.add(&h->d_twy, 2 * es * p.ny);
+        h->sklo.assign(nh * (h->nbins + 1), 0);
+        sk2d_shell_table(nx, p.ny, h->nbins, h->sklo.data());
+        plan.add(reinterpret_cast<void **>(&h->d_sklo), sizeof(int32_t) * h->sklo.size());
         plan.add(reinterpret_cast<void **>(&h->d_skpart), sizeof(double) * h->n_inst * h->sk_groups * h->nbins);
         plan.add(reinterpret_cast<void **>(&h->d_sksum), sizeof(double) * h->n_inst * h->nbins);
         plan.add(reinterpret_cast<void **>(&h->d_skmodes), sizeof(double) * h->nbins);
@@ -449,9 +463,14 @@ extern "C" she_status she_create(const she_config *cfg, she_handle **out)
         for (int i = 0; i < h->n_inst; ++i) real[i] = h->inst[i].realisation;
         CREATE_HIP(hipMemcpyAsync(h->d_real, real.data(), sizeof(uint32_t) * h->n_inst, hipMemcpyHostToDevice, s));
         h->pnd.realisation = h->d_real;
-        if (h->d_skmodes)
+        if (h->d_skmodes) {
             CREATE_HIP(hipMemcpyAsync(h->d_skmodes, h->skmodes.data(), sizeof(double) * h->nbins,
                                       hipMemcpyHostToDevice, s));
+            CREATE_HIP(hipMemcpyAsync(h->d_sklo, h->sklo.data(), sizeof(int32_t) * h->sklo.size(),
+                                      hipMemcpyHostToDevice, s));
+            CREATE_HIP(launch_twiddles(h->prec, s, h->pnd.nx, h->d_twx));
+            CREATE_HIP(launch_twiddles(h->prec, s, h->pnd.ny, h->d_twy));
+        }
         CREATE_HIP(launch_initnd(h->prec, s, h->pnd, h->cells, h->inst[0].init_sd, h->d_a));
         h->cur = 0;
     }
@@ -519,7 +538,7 @@ static she_status advance(she_handle *h, int64_t nsteps, bool sampling)
             SHE_HIP(h, launch_reduce_parts(h->n_inst, s, h->d_part, h->nparts, inv_cells, h->d_acc));
             if (h->mask & SHE_STAT_SK)
                 SHE_HIP(h, launch_sk2d(h->prec, s, h->n_inst, h->pnd.nx, h->pnd.ny, h->pnd.u0, dst, h->d_half,
-                                       h->d_skpart, h->nbins, h->d_sksum, h->d_acc));
+                                       h->d_twx, h->d_twy, h->d_sklo, h->d_skpart, h->nbins, h->d_sksum, h->d_acc));
         }
         h->cur ^= 1;
         h->steps += 1;

@@ -53,7 +53,8 @@ __device__ __forceinline__ f64x4 mfma16x16x4(double a, double b, f64x4 c)
 // accumulates four outputs of its tile over K = 256 in the matrix-core
 // accumulator type and adds them to the FP64 sum (both triangles).
 // Operand layout of the 16x16x4 instructions: lane l supplies A[l%16][l/16]
-// and B[l/16][l%16]; output element v of lane l is D[4(l/16)+v][l%16].
+// and B[l/16][l%16]; output element v of lane l is D[4(l/16)+v][l%16] for
+// the FP32 form and D[(l/16)+4v][l%16] for the FP64 form.
 template <typename T>
 __device__ void xtx_block(const T *__restrict__ X, double *__restrict__ Cm, int N)
 {
@@ -79,7 +80,8 @@ __device__ void xtx_block(const T *__restrict__ X, double *__restrict__ Cm, int 
         const int col = 16 * tj + (lane & 15);
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-            const int row = 16 * ti + 4 * (lane >> 4) + v;
+            // output rows: FP32 form 4(l/16)+v, FP64 form (l/16)+4v (measured on gfx950)
+            const int row = 16 * ti + (std::is_same<T, float>::value ? 4 * (lane >> 4) + v : (lane >> 4) + 4 * v);
             if (row < N && col < N) {
                 const double val = static_cast<double>(acc[v]);
                 Cm[(int64_t)row * N + col] += val;

@@ -6,6 +6,11 @@
 // sqrt(max(., 0)) of it (Dean-Kawasaki, Sec. 4); U_c += sum_e F(c+e) - F(c).
 // PC (2D): U* = FE step, U = (U + U* + Delta(U*; same N)) / 2.
 //
+// The constant factors of the noise term are folded into the Box-Muller
+// radius: the kernels draw z = s N with s = sigma/2 (SHE: A z = (U_l + U_r) z),
+// s = sigma/sqrt(2) (DK: sqrt(U_l + U_r) z) or s = sigma A(u0) (deterministic
+// face value: the noise term is z), so a face costs sub, add, mul, fma.
+//
 // Layout: realisation-major, x fastest, FP32 or FP64.  Face numbers
 // ((z*Ny + y)*dim + e)*Nx + x make the four faces of one Philox block four
 // consecutive x-cells of one direction, so a lane that owns CX consecutive
@@ -14,15 +19,16 @@
 // 2D: a "row group" of LX = Nx/CX lanes owns a full x-row and marches along y
 // over a chunk of rows.  The x-neighbours come from the adjacent lanes
 // (ds_bpermute shuffles inside the group, periodic wrap within the group);
-// the y-neighbours stay in registers from the previous row, so each cell is
-// read once and written once per step, and only the first row of a chunk
-// (FE) or its first three rows (PC) are computed twice.
+// the y-neighbours stay in registers from the previous row, and the row two
+// ahead is prefetched, so each cell is read once and written once per step;
+// only the first row of a chunk (FE) or its first three rows (PC) are
+// computed twice.
 //
 // 3D: a workgroup of TY row groups owns TY consecutive rows in y and marches
 // along z.  Low y-face fluxes are exchanged between the rows through LDS (one
 // barrier per plane, double-buffered); the tile's top row computes the flux
 // through its high y-face itself (one extra Philox call per plane for that
-// row).  z-neighbours stay in registers.
+// row).  z-neighbours stay in registers; the plane two ahead is prefetched.
 //
 // Sample steps: every lane adds dU = U - u0 and dU^2 of its output cells in
 // FP64; the group / workgroup sum is written to a per-chunk partial; a small
@@ -32,26 +38,28 @@
 
 namespace she {
 
+// Flux through a face between cells with values lo (low side) and hi, for a
+// pre-scaled number zs (see above).
 template <typename T, int EQ>
-__device__ __forceinline__ T amp_nd(T v, uint32_t &clamps)
+__device__ __forceinline__ T face_flux(T lo, T hi, T zs, T r, int noise, uint32_t &clamps)
 {
-    if constexpr (EQ == 0) {
-        return v;
-    } else {
-        if (v < T(0)) {
-            ++clamps;
-            return T(0);
+    const T f = r * (hi - lo);
+    if (noise == 0) {
+        const T s = lo + hi;
+        T a;
+        if constexpr (EQ == 0) {
+            a = s;
+        } else {
+            if (s < T(0)) {
+                ++clamps;
+                a = T(0);
+            } else {
+                a = sqrt(s);
+            }
         }
-        return sqrt(v);
+        return f + a * zs;
     }
-}
-
-template <typename T, int EQ>
-__device__ __forceinline__ T face_flux(T lo, T hi, T z, T r, T sg, int noise, T amp0, uint32_t &clamps)
-{
-    T f = r * (hi - lo);
-    if (noise == 0) f += sg * amp_nd<T, EQ>(T(0.5) * (lo + hi), clamps) * z;
-    else if (noise == 1) f += sg * amp0 * z;
+    if (noise == 1) return f + zs;
     return f;
 }
 
@@ -74,10 +82,17 @@ __device__ __forceinline__ void store_row(T *__restrict__ p, const T (&v)[CX])
     for (int j = 0; j < CX; ++j) p[j] = v[j];
 }
 
-// Normals of one lane's CX faces of direction-row `drow` (= row*dim + e).
+template <typename T, int CX>
+__device__ __forceinline__ void copy_row(T (&d)[CX], const T (&s)[CX])
+{
+#pragma unroll
+    for (int j = 0; j < CX; ++j) d[j] = s[j];
+}
+
+// Scaled numbers of one lane's CX faces of direction-row `drow` (= row*dim + e).
 template <typename T, int CX>
 __device__ __forceinline__ void row_normals(T (&z)[CX], uint32_t drow, uint32_t nq, uint32_t q0,
-                                            uint32_t slo, uint32_t w2, uint32_t real, PhiloxKey key, int noise)
+                                            uint32_t slo, uint32_t w2, uint32_t real, PhiloxKey key, int noise, T rc)
 {
     if (noise == 2) {
 #pragma unroll
@@ -86,7 +101,7 @@ __device__ __forceinline__ void row_normals(T (&z)[CX], uint32_t drow, uint32_t 
     }
 #pragma unroll
     for (int c = 0; c < CX / 4; ++c) {
-        const Normals4<T> nz = block_normals<T>(drow * nq + q0 + c, slo, w2, real, key);
+        const Normals4<T> nz = block_normals_scaled<T>(drow * nq + q0 + c, slo, w2, real, key, rc);
 #pragma unroll
         for (int l = 0; l < 4; ++l) z[4 * c + l] = nz.z[l];
     }
@@ -96,17 +111,17 @@ __device__ __forceinline__ void row_normals(T (&z)[CX], uint32_t drow, uint32_t 
 // the low face of the lane's cell j, Fhi the flux through the high face of its
 // last cell (= the next lane's Flo[0]).
 template <typename T, int CX, int EQ>
-__device__ __forceinline__ void row_xflux(const T (&v)[CX], const T (&z)[CX], T (&Flo)[CX], T &Fhi,
-                                          int lx, int LX, T r, T sg, int noise, T amp0, uint32_t &clamps)
+__device__ __forceinline__ void row_xflux(const T (&v)[CX], const T (&z)[CX], T (&Flo)[CX], T &Fhi, int lx, int LX,
+                                          T r, int noise, uint32_t &clamps)
 {
     const int lane = threadIdx.x & 63;
     const int gbase = lane - lx;
     const int left = gbase + (lx == 0 ? LX - 1 : lx - 1);
     const int right = gbase + (lx == LX - 1 ? 0 : lx + 1);
     const T vleft = __shfl(v[CX - 1], left, 64);
-    Flo[0] = face_flux<T, EQ>(vleft, v[0], z[0], r, sg, noise, amp0, clamps);
+    Flo[0] = face_flux<T, EQ>(vleft, v[0], z[0], r, noise, clamps);
 #pragma unroll
-    for (int j = 1; j < CX; ++j) Flo[j] = face_flux<T, EQ>(v[j - 1], v[j], z[j], r, sg, noise, amp0, clamps);
+    for (int j = 1; j < CX; ++j) Flo[j] = face_flux<T, EQ>(v[j - 1], v[j], z[j], r, noise, clamps);
     Fhi = __shfl(Flo[0], right, 64);
 }
 
@@ -114,6 +129,17 @@ template <typename T, int CX>
 __device__ __forceinline__ T xdiv(const T (&Flo)[CX], T Fhi, int j)
 {
     return (j + 1 < CX ? Flo[j + 1] : Fhi) - Flo[j];
+}
+
+template <typename T, int CX>
+__device__ __forceinline__ void accumulate(const T (&out)[CX], double u0, double &sa, double &sb)
+{
+#pragma unroll
+    for (int j = 0; j < CX; ++j) {
+        const double dl = static_cast<double>(out[j]) - u0;
+        sa += dl;
+        sb += dl * dl;
+    }
 }
 
 // ------------------------------------------------------------------ 2D
@@ -145,10 +171,9 @@ __global__ void __launch_bounds__(256)
         return;
     }
 
-    const T r = static_cast<T>(p.r), sg = static_cast<T>(p.sigma);
+    const T r = static_cast<T>(p.r);
+    const T rc = radius_const<T>(p.ns);
     uint32_t clamps = 0;
-    const T amp0 = amp_nd<T, EQ>(static_cast<T>(p.u0), clamps);
-    clamps = 0;
     const int noise = p.noise;
     const uint32_t real = p.realisation[inst];
     const PhiloxKey key = make_key(p.seed);
@@ -162,44 +187,37 @@ __global__ void __launch_bounds__(256)
     const double u0d = p.u0;
 
     if constexpr (SCHEME == 0) {
-        T tc[CX], tn[CX], zy[CX], zx[CX], fylo[CX], fyhi[CX], fxlo[CX], fxhi;
+        T tc[CX], tn[CX], tq[CX], zy[CX], zx[CX], fylo[CX], fyhi[CX], fxlo[CX], fxhi;
         {
             T tp[CX];
             load_row<T, CX>(rowp(y0 - 1), tp);
             load_row<T, CX>(rowp(y0), tc);
-            row_normals<T, CX>(zy, drow(y0, 1), nq, q0, slo, w2, real, key, noise);
+            load_row<T, CX>(rowp(y0 + 1), tn);
+            row_normals<T, CX>(zy, drow(y0, 1), nq, q0, slo, w2, real, key, noise, rc);
 #pragma unroll
-            for (int j = 0; j < CX; ++j) fylo[j] = face_flux<T, EQ>(tp[j], tc[j], zy[j], r, sg, noise, amp0, clamps);
+            for (int j = 0; j < CX; ++j) fylo[j] = face_flux<T, EQ>(tp[j], tc[j], zy[j], r, noise, clamps);
         }
         for (int y = y0; y < y1; ++y) {
-            load_row<T, CX>(rowp(y + 1), tn);
-            row_normals<T, CX>(zy, drow(y + 1, 1), nq, q0, slo, w2, real, key, noise);
+            load_row<T, CX>(rowp(y + 2), tq);
+            row_normals<T, CX>(zy, drow(y + 1, 1), nq, q0, slo, w2, real, key, noise, rc);
 #pragma unroll
-            for (int j = 0; j < CX; ++j) fyhi[j] = face_flux<T, EQ>(tc[j], tn[j], zy[j], r, sg, noise, amp0, clamps);
-            row_normals<T, CX>(zx, drow(y, 0), nq, q0, slo, w2, real, key, noise);
-            row_xflux<T, CX, EQ>(tc, zx, fxlo, fxhi, lx, LX, r, sg, noise, amp0, clamps);
+            for (int j = 0; j < CX; ++j) fyhi[j] = face_flux<T, EQ>(tc[j], tn[j], zy[j], r, noise, clamps);
+            row_normals<T, CX>(zx, drow(y, 0), nq, q0, slo, w2, real, key, noise, rc);
+            row_xflux<T, CX, EQ>(tc, zx, fxlo, fxhi, lx, LX, r, noise, clamps);
             T out[CX];
 #pragma unroll
-            for (int j = 0; j < CX; ++j) {
-                out[j] = tc[j] + (xdiv<T, CX>(fxlo, fxhi, j) + (fyhi[j] - fylo[j]));
-                if (sample) {
-                    const double dl = static_cast<double>(out[j]) - u0d;
-                    sa += dl;
-                    sb += dl * dl;
-                }
-            }
+            for (int j = 0; j < CX; ++j) out[j] = tc[j] + (xdiv<T, CX>(fxlo, fxhi, j) + (fyhi[j] - fylo[j]));
+            if (sample) accumulate<T, CX>(out, u0d, sa, sb);
             store_row<T, CX>(D + static_cast<int64_t>(y) * p.nx, out);
-#pragma unroll
-            for (int j = 0; j < CX; ++j) {
-                tc[j] = tn[j];
-                fylo[j] = fyhi[j];
-            }
+            copy_row<T, CX>(tc, tn);
+            copy_row<T, CX>(tn, tq);
+            copy_row<T, CX>(fylo, fyhi);
         }
     } else {
         // Predictor-corrector.  Iteration k produces the predictor row k and
         // the corrected row k-1.
-        T tm[CX], tc[CX], tn[CX];           // T rows k-1, k, k+1
-        T sm[CX], sc[CX];                   // predictor rows k-1, k
+        T tm[CX], tc[CX], tn[CX], tq[CX];   // T rows k-1, k, k+1, k+2
+        T sc[CX];                           // predictor row k-1
         T zyc[CX], zyn[CX];                 // y numbers of rows k, k+1
         T zxm[CX], zxc[CX];                 // x numbers of rows k-1, k
         T fpc[CX], fpn[CX];                 // predictor low-y fluxes of rows k, k+1
@@ -208,52 +226,44 @@ __global__ void __launch_bounds__(256)
         const int k0 = y0 - 1;
         load_row<T, CX>(rowp(k0 - 1), tm);
         load_row<T, CX>(rowp(k0), tc);
-        row_normals<T, CX>(zyc, drow(k0, 1), nq, q0, slo, w2, real, key, noise);
+        load_row<T, CX>(rowp(k0 + 1), tn);
+        row_normals<T, CX>(zyc, drow(k0, 1), nq, q0, slo, w2, real, key, noise, rc);
 #pragma unroll
-        for (int j = 0; j < CX; ++j) fpc[j] = face_flux<T, EQ>(tm[j], tc[j], zyc[j], r, sg, noise, amp0, clamps);
+        for (int j = 0; j < CX; ++j) fpc[j] = face_flux<T, EQ>(tm[j], tc[j], zyc[j], r, noise, clamps);
         for (int k = k0; k <= y1; ++k) {
             const int i = k - k0;
-            load_row<T, CX>(rowp(k + 1), tn);
-            row_normals<T, CX>(zyn, drow(k + 1, 1), nq, q0, slo, w2, real, key, noise);
+            load_row<T, CX>(rowp(k + 2), tq);
+            row_normals<T, CX>(zyn, drow(k + 1, 1), nq, q0, slo, w2, real, key, noise, rc);
 #pragma unroll
-            for (int j = 0; j < CX; ++j) fpn[j] = face_flux<T, EQ>(tc[j], tn[j], zyn[j], r, sg, noise, amp0, clamps);
-            row_normals<T, CX>(zxc, drow(k, 0), nq, q0, slo, w2, real, key, noise);
-            row_xflux<T, CX, EQ>(tc, zxc, fx, fxh, lx, LX, r, sg, noise, amp0, clamps);
+            for (int j = 0; j < CX; ++j) fpn[j] = face_flux<T, EQ>(tc[j], tn[j], zyn[j], r, noise, clamps);
+            row_normals<T, CX>(zxc, drow(k, 0), nq, q0, slo, w2, real, key, noise, rc);
+            row_xflux<T, CX, EQ>(tc, zxc, fx, fxh, lx, LX, r, noise, clamps);
             T snew[CX];
 #pragma unroll
             for (int j = 0; j < CX; ++j) snew[j] = tc[j] + (xdiv<T, CX>(fx, fxh, j) + (fpn[j] - fpc[j]));
             if (i >= 1) {
 #pragma unroll
-                for (int j = 0; j < CX; ++j) fcc[j] = face_flux<T, EQ>(sc[j], snew[j], zyc[j], r, sg, noise, amp0, clamps);
+                for (int j = 0; j < CX; ++j) fcc[j] = face_flux<T, EQ>(sc[j], snew[j], zyc[j], r, noise, clamps);
             }
             if (i >= 2) {
                 // corrected row k-1 from predictor rows k-2 (fcm), k-1 (sc), k (snew)
-                row_xflux<T, CX, EQ>(sc, zxm, fx, fxh, lx, LX, r, sg, noise, amp0, clamps);
+                row_xflux<T, CX, EQ>(sc, zxm, fx, fxh, lx, LX, r, noise, clamps);
                 T out[CX];
 #pragma unroll
-                for (int j = 0; j < CX; ++j) {
+                for (int j = 0; j < CX; ++j)
                     out[j] = T(0.5) * ((tm[j] + sc[j]) + (xdiv<T, CX>(fx, fxh, j) + (fcc[j] - fcm[j])));
-                    if (sample) {
-                        const double dl = static_cast<double>(out[j]) - u0d;
-                        sa += dl;
-                        sb += dl * dl;
-                    }
-                }
+                if (sample) accumulate<T, CX>(out, u0d, sa, sb);
                 store_row<T, CX>(D + static_cast<int64_t>(k - 1) * p.nx, out);
             }
-#pragma unroll
-            for (int j = 0; j < CX; ++j) {
-                tm[j] = tc[j];
-                tc[j] = tn[j];
-                sm[j] = sc[j];
-                sc[j] = snew[j];
-                zyc[j] = zyn[j];
-                zxm[j] = zxc[j];
-                fpc[j] = fpn[j];
-                fcm[j] = fcc[j];
-            }
+            copy_row<T, CX>(tm, tc);
+            copy_row<T, CX>(tc, tn);
+            copy_row<T, CX>(tn, tq);
+            copy_row<T, CX>(sc, snew);
+            copy_row<T, CX>(zyc, zyn);
+            copy_row<T, CX>(zxm, zxc);
+            copy_row<T, CX>(fpc, fpn);
+            copy_row<T, CX>(fcm, fcc);
         }
-        (void)sm;
     }
 
     if (sample) {
@@ -310,10 +320,9 @@ __global__ void __launch_bounds__(256)
     T *fsh = tsh + 2 * ty * nx;                           // [2][ty][nx]
     const int cell0 = CX * lx;
 
-    const T r = static_cast<T>(p.r), sg = static_cast<T>(p.sigma);
+    const T r = static_cast<T>(p.r);
+    const T rc = radius_const<T>(p.ns);
     uint32_t clamps = 0;
-    const T amp0 = amp_nd<T, EQ>(static_cast<T>(p.u0), clamps);
-    clamps = 0;
     const int noise = p.noise;
     const uint32_t real = p.realisation[inst];
     const PhiloxKey key = make_key(p.seed);
@@ -323,14 +332,15 @@ __global__ void __launch_bounds__(256)
         return static_cast<uint32_t>((wrap(zz, nz) * ny + wrap(yy, ny)) * 3 + e);
     };
 
-    T tc[CX], tn[CX], zz3[CX], fzlo[CX], fzhi[CX];
+    T tc[CX], tn[CX], tq[CX], zz3[CX], fzlo[CX], fzhi[CX];
     {
         T tp[CX];
         load_row<T, CX>(S + rowp(y, z0 - 1), tp);
         load_row<T, CX>(S + rowp(y, z0), tc);
-        row_normals<T, CX>(zz3, drow(y, z0, 2), nq, q0, slo, w2, real, key, noise);
+        load_row<T, CX>(S + rowp(y, z0 + 1), tn);
+        row_normals<T, CX>(zz3, drow(y, z0, 2), nq, q0, slo, w2, real, key, noise, rc);
 #pragma unroll
-        for (int j = 0; j < CX; ++j) fzlo[j] = face_flux<T, EQ>(tp[j], tc[j], zz3[j], r, sg, noise, amp0, clamps);
+        for (int j = 0; j < CX; ++j) fzlo[j] = face_flux<T, EQ>(tp[j], tc[j], zz3[j], r, noise, clamps);
         T *dstp = tsh + ((z0 & 1) * ty + g) * nx + cell0;
 #pragma unroll
         for (int j = 0; j < CX; ++j) dstp[j] = tc[j];
@@ -341,17 +351,17 @@ __global__ void __launch_bounds__(256)
     const double u0d = p.u0;
     for (int zi = z0; zi < z1; ++zi) {
         const int buf = zi & 1;
-        load_row<T, CX>(S + rowp(y, zi + 1), tn);
-        row_normals<T, CX>(zz3, drow(y, zi + 1, 2), nq, q0, slo, w2, real, key, noise);
+        load_row<T, CX>(S + rowp(y, zi + 2), tq);
+        row_normals<T, CX>(zz3, drow(y, zi + 1, 2), nq, q0, slo, w2, real, key, noise, rc);
 #pragma unroll
-        for (int j = 0; j < CX; ++j) fzhi[j] = face_flux<T, EQ>(tc[j], tn[j], zz3[j], r, sg, noise, amp0, clamps);
+        for (int j = 0; j < CX; ++j) fzhi[j] = face_flux<T, EQ>(tc[j], tn[j], zz3[j], r, noise, clamps);
 
         T zx[CX], fxlo[CX], fxhi;
-        row_normals<T, CX>(zx, drow(y, zi, 0), nq, q0, slo, w2, real, key, noise);
-        row_xflux<T, CX, EQ>(tc, zx, fxlo, fxhi, lx, LX, r, sg, noise, amp0, clamps);
+        row_normals<T, CX>(zx, drow(y, zi, 0), nq, q0, slo, w2, real, key, noise, rc);
+        row_xflux<T, CX, EQ>(tc, zx, fxlo, fxhi, lx, LX, r, noise, clamps);
 
         T zy[CX], ylo[CX], fylo[CX];
-        row_normals<T, CX>(zy, drow(y, zi, 1), nq, q0, slo, w2, real, key, noise);
+        row_normals<T, CX>(zy, drow(y, zi, 1), nq, q0, slo, w2, real, key, noise, rc);
         if (g > 0) {
             const T *q = tsh + (buf * ty + g - 1) * nx + cell0;
 #pragma unroll
@@ -360,7 +370,7 @@ __global__ void __launch_bounds__(256)
             load_row<T, CX>(S + rowp(y - 1, zi), ylo);
         }
 #pragma unroll
-        for (int j = 0; j < CX; ++j) fylo[j] = face_flux<T, EQ>(ylo[j], tc[j], zy[j], r, sg, noise, amp0, clamps);
+        for (int j = 0; j < CX; ++j) fylo[j] = face_flux<T, EQ>(ylo[j], tc[j], zy[j], r, noise, clamps);
         {
             T *fp = fsh + (buf * ty + g) * nx + cell0;
 #pragma unroll
@@ -378,26 +388,19 @@ __global__ void __launch_bounds__(256)
         } else {
             T yhi[CX], zyh[CX];
             load_row<T, CX>(S + rowp(y + 1, zi), yhi);
-            row_normals<T, CX>(zyh, drow(y + 1, zi, 1), nq, q0, slo, w2, real, key, noise);
+            row_normals<T, CX>(zyh, drow(y + 1, zi, 1), nq, q0, slo, w2, real, key, noise, rc);
 #pragma unroll
-            for (int j = 0; j < CX; ++j) fyhi[j] = face_flux<T, EQ>(tc[j], yhi[j], zyh[j], r, sg, noise, amp0, clamps);
+            for (int j = 0; j < CX; ++j) fyhi[j] = face_flux<T, EQ>(tc[j], yhi[j], zyh[j], r, noise, clamps);
         }
         T out[CX];
 #pragma unroll
-        for (int j = 0; j < CX; ++j) {
+        for (int j = 0; j < CX; ++j)
             out[j] = tc[j] + ((xdiv<T, CX>(fxlo, fxhi, j) + (fyhi[j] - fylo[j])) + (fzhi[j] - fzlo[j]));
-            if (sample) {
-                const double dl = static_cast<double>(out[j]) - u0d;
-                sa += dl;
-                sb += dl * dl;
-            }
-        }
+        if (sample) accumulate<T, CX>(out, u0d, sa, sb);
         store_row<T, CX>(D + rowp(y, zi), out);
-#pragma unroll
-        for (int j = 0; j < CX; ++j) {
-            tc[j] = tn[j];
-            fzlo[j] = fzhi[j];
-        }
+        copy_row<T, CX>(tc, tn);
+        copy_row<T, CX>(tn, tq);
+        copy_row<T, CX>(fzlo, fzhi);
     }
 
     if (sample) {

@@ -109,4 +109,50 @@ __device__ __forceinline__ Normals4<T> block_normals(uint32_t block, uint32_t st
     return n;
 }
 
+// Scaled normals s*N for a fixed factor s >= 0, with the factor folded into
+// the Box-Muller radius: FP32 takes rc = -2 ln(2) s^2 and forms
+// sqrt(log2(u_a) rc); FP64 takes rc = s.
+__device__ __forceinline__ void box_muller_scaled(uint32_t wa, uint32_t wb, float rc, float &zc, float &zs)
+{
+    const float ua = unit_open_f32(wa);
+    const float ub = unit_open_f32(wb);
+    const float rho = __builtin_amdgcn_sqrtf(__builtin_amdgcn_logf(ua) * rc);
+    zc = rho * __builtin_amdgcn_cosf(ub);
+    zs = rho * __builtin_amdgcn_sinf(ub);
+}
+
+__device__ __forceinline__ void box_muller_scaled(uint32_t wa, uint32_t wb, double rc, double &zc, double &zs)
+{
+    double c, s;
+    box_muller(wa, wb, c, s);
+    zc = c * rc;
+    zs = s * rc;
+}
+
+template <typename T>
+__host__ __device__ inline T radius_const(double s);
+
+template <>
+__host__ __device__ inline float radius_const<float>(double s)
+{
+    return static_cast<float>(-1.38629436111989061883 * s * s);
+}
+
+template <>
+__host__ __device__ inline double radius_const<double>(double s)
+{
+    return s;
+}
+
+template <typename T>
+__device__ __forceinline__ Normals4<T> block_normals_scaled(uint32_t block, uint32_t step_lo, uint32_t w2,
+                                                            uint32_t realisation, PhiloxKey key, T rc)
+{
+    const Words4 x = philox4x32_10(block, step_lo, w2, realisation, key);
+    Normals4<T> n;
+    box_muller_scaled(x.w[0], x.w[1], rc, n.z[0], n.z[1]);
+    box_muller_scaled(x.w[2], x.w[3], rc, n.z[2], n.z[3]);
+    return n;
+}
+
 }  // namespace she
