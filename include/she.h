@@ -81,6 +81,14 @@ enum {
     SHE_STAT_SPATIAL = 8   /* per-instance spatial mean / variance per sample */
 };
 
+/* she_config.tuning_flags: launch-order choices (results are identical) */
+enum {
+    SHE_TUNE_XCD_ORDER = 1        /* 2D/3D: give each XCD a contiguous range of
+                                     workgroups (neighbouring chunks share an
+                                     L2) instead of the plain order; measured
+                                     no faster on MI355X, so off by default   */
+};
+
 /* One instance (realisation) of the scheme.  Dirichlet walls only in 1D. */
 typedef struct {
     int32_t dim;          /* 1, 2, 3                                          */
@@ -117,7 +125,13 @@ typedef struct {
     int32_t block_threads;        /* tuning: 1D threads per instance (0 auto) */
     int32_t rows_per_block;       /* tuning: 2D/3D march length (0 auto)      */
     int32_t rows_per_group;       /* tuning: 3D rows per workgroup (0 auto)   */
-    int32_t reserved;             /* must be 0                                 */
+    int32_t tuning_flags;         /* SHE_TUNE_* bits (0 = defaults)           */
+    int32_t graph_steps;          /* 2D/3D: record K >= 1 steps into a HIP
+                                     graph and replay it (K is rounded up to a
+                                     multiple of 2, and of sample_every for
+                                     she_run); 0 launches every step directly.
+                                     Results are identical.  Ignored in 1D.  */
+    int32_t reserved;             /* must be 0                                */
     void *stream;                 /* hipStream_t (e.g. torch's current stream)*/
     void *arena;                  /* optional device memory for all buffers   */
     size_t arena_bytes;

@@ -67,6 +67,13 @@ struct she_handle {
     int32_t *d_sklo = nullptr;
     std::vector<double> skmodes;
     std::vector<int32_t> sklo;
+    // captured step loops: [0] without, [1] with sample steps
+    int64_t *d_step = nullptr;    // device step counter read by replayed kernels
+    int64_t dev_step = -1;        // value *d_step holds once the stream is idle
+    int32_t graph_steps = 0;
+    hipStream_t cap_stream = nullptr;
+    hipGraphExec_t gexec[2] = {nullptr, nullptr};
+    int64_t gk[2] = {0, 0};
 
     void *field() const { return dim == 1 ? d_pool : (cur == 0 ? d_a : d_b); }
 };
@@ -126,7 +133,10 @@ she_status validate(const she_config *cfg, she_handle *h)
         return fail(nullptr, SHE_EINVAL, "precision must be SHE_F32 or SHE_F64");
     if (cfg->sample_every < 1) return fail(nullptr, SHE_EINVAL, "sample_every must be >= 1");
     if (cfg->burn_in < 0) return fail(nullptr, SHE_EINVAL, "burn_in must be >= 0");
-    if (cfg->reserved != 0) return fail(nullptr, SHE_EINVAL, "reserved field must be 0");
+    if (cfg->tuning_flags & ~SHE_TUNE_XCD_ORDER) return fail(nullptr, SHE_EINVAL, "unknown tuning_flags bits");
+    if (cfg->graph_steps < 0 || cfg->graph_steps > (1 << 16))
+        return fail(nullptr, SHE_EINVAL, "graph_steps must be in [0, 65536]");
+    if (cfg->reserved != 0) return fail(nullptr, SHE_EINVAL, "reserved must be 0");
     if (cfg->stats_mask & ~0xFu) return fail(nullptr, SHE_EINVAL, "unknown stats_mask bits");
     const int dim = cfg->inst[0].dim;
     for (int i = 0; i < cfg->n_instances; ++i) {
@@ -271,6 +281,7 @@ static she_status plan_nd(she_handle *h, const she_config *cfg, Plan &plan)
     p.scheme = d0.scheme;
     p.noise = d0.noise;
     p.n_inst = h->n_inst;
+    p.xcd_order = (cfg->tuning_flags & SHE_TUNE_XCD_ORDER) ? 1 : 0;
     p.r = d0.r;
     p.sigma = std::sqrt(2.0 * d0.r * d0.eps);
     p.u0 = d0.u0;
@@ -318,6 +329,8 @@ static she_status plan_nd(she_handle *h, const she_config *cfg, Plan &plan)
     plan.add(&h->d_b, fbytes);
     plan.add(reinterpret_cast<void **>(&h->d_real), sizeof(uint32_t) * h->n_inst);
     plan.add(reinterpret_cast<void **>(&h->d_part), 2 * sizeof(double) * h->nparts * h->n_inst);
+    plan.add(reinterpret_cast<void **>(&h->d_step), sizeof(int64_t));
+    h->graph_steps = cfg->graph_steps;
     h->fin_len = 8;
     if (h->mask & SHE_STAT_SK) {
         // shells round(|k|), signed k in [-N/2, N/2); mode counts per shell
@@ -489,10 +502,11 @@ extern "C" she_status she_create(const she_config *cfg, she_handle **out)
 extern "C" void she_destroy(she_handle *h)
 {
     if (!h) return;
-    if (h->own && h->base) {
-        (void)hipStreamSynchronize(h->stream);
-        (void)hipFree(h->base);
-    }
+    (void)hipStreamSynchronize(h->stream);
+    for (hipGraphExec_t &g : h->gexec)
+        if (g) (void)hipGraphExecDestroy(g);
+    if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
+    if (h->own && h->base) (void)hipFree(h->base);
     delete h;
 }
 
@@ -502,6 +516,69 @@ extern "C" const char *she_last_error(const she_handle *h)
 }
 
 // ------------------------------------------------------------------ stepping
+
+// Enqueue one 2D/3D step from buffer `cur` and, when it may sample, the
+// reduction of its partials and the structure factor of its output.
+static hipError_t nd_enqueue(she_handle *h, hipStream_t s, const StepArg &sa, int cur, bool may_sample)
+{
+    const void *src = cur == 0 ? h->d_a : h->d_b;
+    void *dst = cur == 0 ? h->d_b : h->d_a;
+    hipError_t e;
+    if (h->dim == 2)
+        e = launch_step2d(h->prec, h->cx, h->pnd.eq, h->pnd.scheme, h->nd_blocks, s, h->pnd, src, dst, sa, h->d_part,
+                          h->d_acc);
+    else
+        e = launch_step3d(h->prec, h->cx, h->pnd.eq, h->ty, h->nd_blocks, h->smem3d, s, h->pnd, src, dst, sa,
+                          h->d_part, h->d_acc);
+    if (e != hipSuccess || !may_sample) return e;
+    e = launch_reduce_parts(h->n_inst, s, sa, h->d_part, h->nparts, 1.0 / static_cast<double>(h->cells), h->d_acc);
+    if (e != hipSuccess || !(h->mask & SHE_STAT_SK)) return e;
+    return launch_sk2d(h->prec, s, sa, h->n_inst, h->pnd.nx, h->pnd.ny, h->pnd.u0, dst, h->d_half, h->d_twx, h->d_twy,
+                       h->d_sklo, h->d_skpart, h->nbins, h->d_sksum, h->d_acc);
+}
+
+static she_status nd_direct(she_handle *h, bool samp)
+{
+    const int64_t t = h->steps + 1;
+    const int sample = samp && t > h->burn_in && t % h->every == 0;
+    const StepArg sa{h->steps, nullptr, h->burn_in, h->every, sample};
+    SHE_HIP(h, nd_enqueue(h, h->stream, sa, h->cur, sample != 0));
+    h->cur ^= 1;
+    h->steps += 1;
+    return SHE_OK;
+}
+
+// Record K steps that start at a step index s0 = *d_step with s0 % L == 0 and
+// buffer 0 current (kind 1: s0 >= burn_in, positions with (j+1) % every == 0
+// sample; kind 0: none does), then *d_step += K.  Kernels of a replay read the
+// counter, so one graph serves every aligned start.
+static she_status record_graph(she_handle *h, int kind, int64_t K)
+{
+    if (h->gexec[kind]) {
+        SHE_HIP(h, hipGraphExecDestroy(h->gexec[kind]));
+        h->gexec[kind] = nullptr;
+    }
+    if (!h->cap_stream) SHE_HIP(h, hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking));
+    SHE_HIP(h, hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal));
+    hipError_t e = hipSuccess;
+    for (int64_t j = 0; j < K && e == hipSuccess; ++j) {
+        const int may = kind == 1 && (j + 1) % h->every == 0;
+        const StepArg sa{j, h->d_step, h->burn_in, h->every, may};
+        e = nd_enqueue(h, h->cap_stream, sa, static_cast<int>(j & 1), may != 0);
+    }
+    if (e == hipSuccess) e = launch_add_step(h->cap_stream, h->d_step, K);
+    hipGraph_t g = nullptr;
+    const hipError_t e_end = hipStreamEndCapture(h->cap_stream, &g);
+    if (e == hipSuccess) e = e_end;
+    if (e == hipSuccess) e = hipGraphInstantiate(&h->gexec[kind], g, nullptr, nullptr, 0);
+    if (g) (void)hipGraphDestroy(g);
+    if (e != hipSuccess) {
+        h->gexec[kind] = nullptr;
+        return hipfail(h, e, "recording the step graph");
+    }
+    h->gk[kind] = K;
+    return SHE_OK;
+}
 
 static she_status advance(she_handle *h, int64_t nsteps, bool sampling)
 {
@@ -522,26 +599,40 @@ static she_status advance(she_handle *h, int64_t nsteps, bool sampling)
         }
         return SHE_OK;
     }
-    const double inv_cells = 1.0 / static_cast<double>(h->cells);
-    for (int64_t k = 0; k < nsteps; ++k) {
-        const int64_t t = h->steps + 1;
-        const int sample = sampling && (h->mask & SHE_STAT_SPATIAL) && t > h->burn_in && t % h->every == 0;
-        const void *src = h->cur == 0 ? h->d_a : h->d_b;
-        void *dst = h->cur == 0 ? h->d_b : h->d_a;
-        if (h->dim == 2)
-            SHE_HIP(h, launch_step2d(h->prec, h->cx, h->pnd.eq, h->pnd.scheme, h->nd_blocks, s, h->pnd, src, dst,
-                                     h->steps, sample, h->d_part, h->d_acc));
-        else
-            SHE_HIP(h, launch_step3d(h->prec, h->cx, h->pnd.eq, h->ty, h->nd_blocks, h->smem3d, s, h->pnd, src, dst,
-                                     h->steps, sample, h->d_part, h->d_acc));
-        if (sample) {
-            SHE_HIP(h, launch_reduce_parts(h->n_inst, s, h->d_part, h->nparts, inv_cells, h->d_acc));
-            if (h->mask & SHE_STAT_SK)
-                SHE_HIP(h, launch_sk2d(h->prec, s, h->n_inst, h->pnd.nx, h->pnd.ny, h->pnd.u0, dst, h->d_half,
-                                       h->d_twx, h->d_twy, h->d_sklo, h->d_skpart, h->nbins, h->d_sksum, h->d_acc));
+    const bool samp = sampling && (h->mask & SHE_STAT_SPATIAL);
+    if (h->graph_steps > 0) {
+        // replay chunks of K steps that start at a step index aligned to L (so
+        // the buffers and the sample positions inside the chunk are those the
+        // graph was recorded with); direct steps before, between and after
+        const int64_t L = samp ? std::lcm<int64_t>(h->every, 2) : 2;
+        const int64_t K = (h->graph_steps + L - 1) / L * L;
+        while (nsteps > 0) {
+            int kind = -1;
+            if (h->steps % L == 0 && h->cur == 0 && nsteps >= K) {
+                if (!samp || h->steps + K <= h->burn_in) kind = 0;  // no step of the chunk samples
+                else if (h->steps >= h->burn_in) kind = 1;          // every aligned position samples
+            }
+            if (kind < 0) {
+                she_status st = nd_direct(h, samp);
+                if (st != SHE_OK) return st;
+                --nsteps;
+                continue;
+            }
+            if (!h->gexec[kind] || h->gk[kind] != K) {
+                she_status st = record_graph(h, kind, K);
+                if (st != SHE_OK) return st;
+            }
+            if (h->dev_step != h->steps) SHE_HIP(h, launch_set_step(s, h->d_step, h->steps));
+            SHE_HIP(h, hipGraphLaunch(h->gexec[kind], s));
+            h->steps += K;
+            h->dev_step = h->steps;
+            nsteps -= K;
         }
-        h->cur ^= 1;
-        h->steps += 1;
+        return SHE_OK;
+    }
+    for (int64_t k = 0; k < nsteps; ++k) {
+        she_status st = nd_direct(h, samp);
+        if (st != SHE_OK) return st;
     }
     return SHE_OK;
 }
@@ -764,6 +855,7 @@ extern "C" she_status she_set_state(she_handle *h, const void *host, size_t byte
         b.c_elems != mine.c_elems || b.stat_cells != mine.stat_cells)
         return fail(h, SHE_ESTATE, "checkpoint does not match this handle's layout");
     const char *p = static_cast<const char *>(host) + sizeof b;
+    if (h->dim > 1) h->cur = static_cast<int>(b.steps & 1);  // the buffer a step from b.steps reads
     for (const Section &s : sections(h)) {
         SHE_HIP(h, hipMemcpyAsync(s.dev, p, s.bytes, hipMemcpyHostToDevice, h->stream));
         p += s.bytes;

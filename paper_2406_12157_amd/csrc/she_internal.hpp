@@ -51,13 +51,38 @@ struct ParamsND {
     int32_t eq, scheme, noise;
     int32_t n_inst;
     int32_t chunk;          // rows (2D, along y) or planes (3D, along z) per march
-    int32_t pad;
+    int32_t xcd_order;      // 1: give each XCD a contiguous range of workgroups
     double r, sigma, u0;
     double ns;              // factor folded into the drawn numbers: sigma/2 (SHE),
                             // sigma/sqrt(2) (DK), sigma A(u0) (deterministic face value)
     uint64_t seed;
     const uint32_t *realisation;  // device, n_inst
 };
+
+// Step index and sampling decision of one 2D/3D step.  Launched directly,
+// `step` is the step index and `sample` says whether it is a sample step.
+// Inside a captured graph (`base` != nullptr) the index is *base + step, read
+// from device memory so that replays advance, and `sample` says whether the
+// step may sample; the kernels then decide with the burn-in / period rule.
+struct StepArg {
+    int64_t step;
+    const int64_t *base;
+    int64_t burn_in;
+    int32_t every;
+    int32_t sample;
+};
+
+__device__ __forceinline__ void resolve_step(const StepArg &a, int64_t &step, int &sample)
+{
+    if (a.base) {
+        step = *a.base + a.step;
+        const int64_t t = step + 1;
+        sample = a.sample && t > a.burn_in && a.every > 0 && t % a.every == 0;
+    } else {
+        step = a.step;
+        sample = a.sample;
+    }
+}
 
 }  // namespace she
 
@@ -80,13 +105,16 @@ hipError_t launch_fin1d(int prec, hipStream_t s, const Inst1D *tab, int inst, in
                         double *out);
 
 hipError_t launch_step2d(int prec, int cx, int eq, int scheme, int n_blocks, hipStream_t s,
-                         const ParamsND &p, const void *src, void *dst, int64_t step,
-                         int32_t sample, double *part, InstAcc *acc);
+                         const ParamsND &p, const void *src, void *dst, const StepArg &st,
+                         double *part, InstAcc *acc);
 hipError_t launch_step3d(int prec, int cx, int eq, int ty, int n_blocks, size_t smem,
                          hipStream_t s, const ParamsND &p, const void *src, void *dst,
-                         int64_t step, int32_t sample, double *part, InstAcc *acc);
-hipError_t launch_reduce_parts(int n_inst, hipStream_t s, const double *part, int32_t nparts,
-                               double inv_cells, InstAcc *acc);
+                         const StepArg &st, double *part, InstAcc *acc);
+hipError_t launch_reduce_parts(int n_inst, hipStream_t s, const StepArg &st, const double *part,
+                               int32_t nparts, double inv_cells, InstAcc *acc);
+// Device step counter of captured graphs: *ctr = value, *ctr += k.
+hipError_t launch_set_step(hipStream_t s, int64_t *ctr, int64_t value);
+hipError_t launch_add_step(hipStream_t s, int64_t *ctr, int64_t k);
 // nD initial state: u0 + init_sd * N(tag 1, step 0, face = cell) per instance.
 hipError_t launch_initnd(int prec, hipStream_t s, const ParamsND &p, int64_t cells,
                          double init_sd, void *field);
@@ -106,9 +134,9 @@ hipError_t launch_debug_normals(hipStream_t s, int prec, uint64_t seed, uint32_t
 // 2D structure factor on a sample step: row FFTs, column FFTs + shell
 // binning into per-block partials, fixed-order reduction into sums
 // (n_inst x nbins FP64).  half: n_inst*ny*(nx/2+1) complex of the state type.
-hipError_t launch_sk2d(int prec, hipStream_t s, int n_inst, int nx, int ny, double u0, const void *field,
-                       void *half, const void *twx, const void *twy, const int32_t *lo, double *part, int nbins,
-                       double *sums, const InstAcc *acc);
+hipError_t launch_sk2d(int prec, hipStream_t s, const StepArg &st, int n_inst, int nx, int ny, double u0,
+                       const void *field, void *half, const void *twx, const void *twy, const int32_t *lo,
+                       double *part, int nbins, double *sums, const InstAcc *acc);
 // Host: first |ky| of each shell per half-spectrum column, (nx/2+1) x (nbins+1).
 void sk2d_shell_table(int nx, int ny, int nbins, int32_t *lo);
 // exp(-2 pi i t/n), t < n/2, as complex pairs of the state type

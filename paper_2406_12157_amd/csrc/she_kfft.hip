@@ -129,9 +129,15 @@ __global__ void __launch_bounds__(256) k_twiddles(int n, cplx<T> *__restrict__ t
 // Output: half[inst][kx][y], kx = 0..nx/2.
 template <typename T, int LGX>
 __global__ void __launch_bounds__(256)
-    k_fft_rows(const T *__restrict__ field, int ny, int rp, double u0, const cplx<T> *__restrict__ twx,
+    k_fft_rows(StepArg sarg, const T *__restrict__ field, int ny, int rp, double u0, const cplx<T> *__restrict__ twx,
                cplx<T> *__restrict__ half)
 {
+    {
+        int64_t step;
+        int sample;
+        resolve_step(sarg, step, sample);
+        if (!sample) return;  // a non-sample step of a captured graph
+    }
     constexpr int nx = 1 << LGX;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     cplx<T> *buf = reinterpret_cast<cplx<T> *>(smem_raw);
@@ -173,9 +179,15 @@ __global__ void __launch_bounds__(256)
 // lo: nh x (nbins + 1) table of the first |ky| of each shell per column.
 template <typename T, int LGY>
 __global__ void __launch_bounds__(256)
-    k_fft_cols(const cplx<T> *__restrict__ half, int nx, int cw, int nbins, const cplx<T> *__restrict__ twy,
-               const int32_t *__restrict__ lo, double *__restrict__ part)
+    k_fft_cols(StepArg sarg, const cplx<T> *__restrict__ half, int nx, int cw, int nbins,
+               const cplx<T> *__restrict__ twy, const int32_t *__restrict__ lo, double *__restrict__ part)
 {
+    {
+        int64_t step;
+        int sample;
+        resolve_step(sarg, step, sample);
+        if (!sample) return;  // a non-sample step of a captured graph
+    }
     constexpr int ny = 1 << LGY;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     cplx<T> *buf = reinterpret_cast<cplx<T> *>(smem_raw);
@@ -253,9 +265,15 @@ __global__ void __launch_bounds__(256)
 }
 
 __global__ void __launch_bounds__(256)
-    k_bins_reduce(const double *__restrict__ part, int ngroups, int nbins, int n_inst, double *__restrict__ sums,
-                  const InstAcc *__restrict__ acc)
+    k_bins_reduce(StepArg sarg, const double *__restrict__ part, int ngroups, int nbins, int n_inst,
+                  double *__restrict__ sums, const InstAcc *__restrict__ acc)
 {
+    {
+        int64_t step;
+        int sample;
+        resolve_step(sarg, step, sample);
+        if (!sample) return;  // a non-sample step of a captured graph
+    }
     const int64_t e = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
     if (e >= static_cast<int64_t>(n_inst) * nbins) return;
     const int inst = static_cast<int>(e / nbins), b = static_cast<int>(e - static_cast<int64_t>(inst) * nbins);
@@ -319,25 +337,25 @@ hipError_t launch_twiddles(int prec, hipStream_t s, int n, void *tw)
 }
 
 template <typename T, int LGX, int LGY>
-static void sk2d_launch_t(hipStream_t s, dim3 g1, dim3 g2, size_t sm1, size_t sm2, int nx, int ny, int rp, int cw,
+static void sk2d_launch_t(hipStream_t s, const StepArg &sa, dim3 g1, dim3 g2, size_t sm1, size_t sm2, int nx, int ny, int rp, int cw,
                           int nbins, double u0, const void *field, void *half, const void *twx, const void *twy,
                           const int32_t *lo, double *part)
 {
     using C = cplx<T>;
-    hipLaunchKernelGGL((k_fft_rows<T, LGX>), g1, dim3(256), sm1, s, static_cast<const T *>(field), ny, rp, u0,
+    hipLaunchKernelGGL((k_fft_rows<T, LGX>), g1, dim3(256), sm1, s, sa, static_cast<const T *>(field), ny, rp, u0,
                        static_cast<const C *>(twx), static_cast<C *>(half));
-    hipLaunchKernelGGL((k_fft_cols<T, LGY>), g2, dim3(256), sm2, s, static_cast<const C *>(half), nx, cw, nbins,
+    hipLaunchKernelGGL((k_fft_cols<T, LGY>), g2, dim3(256), sm2, s, sa, static_cast<const C *>(half), nx, cw, nbins,
                        static_cast<const C *>(twy), lo, part);
 }
 
 template <typename T, int LGX>
-static bool sk2d_launch_y(int lgy, hipStream_t s, dim3 g1, dim3 g2, size_t sm1, size_t sm2, int nx, int ny, int rp,
+static bool sk2d_launch_y(int lgy, hipStream_t s, const StepArg &sa, dim3 g1, dim3 g2, size_t sm1, size_t sm2, int nx, int ny, int rp,
                           int cw, int nbins, double u0, const void *field, void *half, const void *twx,
                           const void *twy, const int32_t *lo, double *part)
 {
 #define SHE_SK_Y(L)                                                                                             \
     case L:                                                                                                     \
-        sk2d_launch_t<T, LGX, L>(s, g1, g2, sm1, sm2, nx, ny, rp, cw, nbins, u0, field, half, twx, twy, lo, part); \
+        sk2d_launch_t<T, LGX, L>(s, sa, g1, g2, sm1, sm2, nx, ny, rp, cw, nbins, u0, field, half, twx, twy, lo, part); \
         return true;
     switch (lgy) {
         SHE_SK_Y(1) SHE_SK_Y(2) SHE_SK_Y(3) SHE_SK_Y(4) SHE_SK_Y(5) SHE_SK_Y(6) SHE_SK_Y(7) SHE_SK_Y(8)
@@ -348,13 +366,13 @@ static bool sk2d_launch_y(int lgy, hipStream_t s, dim3 g1, dim3 g2, size_t sm1, 
 }
 
 template <typename T>
-static bool sk2d_launch(int lgx, int lgy, hipStream_t s, dim3 g1, dim3 g2, size_t sm1, size_t sm2, int nx, int ny,
+static bool sk2d_launch(int lgx, int lgy, hipStream_t s, const StepArg &sa, dim3 g1, dim3 g2, size_t sm1, size_t sm2, int nx, int ny,
                         int rp, int cw, int nbins, double u0, const void *field, void *half, const void *twx,
                         const void *twy, const int32_t *lo, double *part)
 {
 #define SHE_SK_X(L)                                                                                               \
     case L:                                                                                                       \
-        return sk2d_launch_y<T, L>(lgy, s, g1, g2, sm1, sm2, nx, ny, rp, cw, nbins, u0, field, half, twx, twy, lo, \
+        return sk2d_launch_y<T, L>(lgy, s, sa, g1, g2, sm1, sm2, nx, ny, rp, cw, nbins, u0, field, half, twx, twy, lo, \
                                    part);
     switch (lgx) {
         SHE_SK_X(3) SHE_SK_X(4) SHE_SK_X(5) SHE_SK_X(6) SHE_SK_X(7) SHE_SK_X(8) SHE_SK_X(9) SHE_SK_X(10)
@@ -363,7 +381,7 @@ static bool sk2d_launch(int lgx, int lgy, hipStream_t s, dim3 g1, dim3 g2, size_
 #undef SHE_SK_X
 }
 
-hipError_t launch_sk2d(int prec, hipStream_t s, int n_inst, int nx, int ny, double u0, const void *field, void *half,
+hipError_t launch_sk2d(int prec, hipStream_t s, const StepArg &sa, int n_inst, int nx, int ny, double u0, const void *field, void *half,
                        const void *twx, const void *twy, const int32_t *lo, double *part, int nbins, double *sums,
                        const InstAcc *acc)
 {
@@ -378,18 +396,18 @@ hipError_t launch_sk2d(int prec, hipStream_t s, int n_inst, int nx, int ny, doub
         const size_t es = sizeof(cplx<float>);
         const size_t sm1 = (static_cast<size_t>(rp) * nx + nx) * es;
         const size_t sm2 = (static_cast<size_t>(cw) * ny + ny) * es;
-        ok = sk2d_launch<float>(lgx, lgy, s, g1, g2, sm1, sm2, nx, ny, rp, cw, nbins, u0, field, half, twx, twy, lo,
+        ok = sk2d_launch<float>(lgx, lgy, s, sa, g1, g2, sm1, sm2, nx, ny, rp, cw, nbins, u0, field, half, twx, twy, lo,
                                 part);
     } else {
         const size_t es = sizeof(cplx<double>);
         const size_t sm1 = (static_cast<size_t>(rp) * nx + nx) * es;
         const size_t sm2 = (static_cast<size_t>(cw) * ny + ny) * es;
-        ok = sk2d_launch<double>(lgx, lgy, s, g1, g2, sm1, sm2, nx, ny, rp, cw, nbins, u0, field, half, twx, twy, lo,
+        ok = sk2d_launch<double>(lgx, lgy, s, sa, g1, g2, sm1, sm2, nx, ny, rp, cw, nbins, u0, field, half, twx, twy, lo,
                                  part);
     }
     if (!ok) return hipErrorInvalidValue;
     const int64_t tot = static_cast<int64_t>(n_inst) * nbins;
-    hipLaunchKernelGGL(k_bins_reduce, dim3(static_cast<unsigned>((tot + 255) / 256)), dim3(256), 0, s, part, ngroups,
+    hipLaunchKernelGGL(k_bins_reduce, dim3(static_cast<unsigned>((tot + 255) / 256)), dim3(256), 0, s, sa, part, ngroups,
                        nbins, n_inst, sums, acc);
     return hipGetLastError();
 }

@@ -125,6 +125,20 @@ __device__ __forceinline__ void row_xflux(const T (&v)[CX], const T (&z)[CX], T 
     Fhi = __shfl(Flo[0], right, 64);
 }
 
+// Workgroups are dispatched round-robin over the 8 XCDs, each with its own L2.
+// On request (SHE_TUNE_XCD_ORDER) they are renumbered so that XCD x runs a
+// contiguous range of logical blocks: neighbouring march chunks, which read
+// each other's halo rows, then share an L2.  A bijection on the first
+// 8*floor(n/8) blocks; the rest keep their index.  On MI355X this measured no
+// faster than the plain order, which is the default.
+__device__ __forceinline__ int xcd_block(int b, int n)
+{
+    constexpr int kXcd = 8;
+    const int per = n / kXcd;
+    if (b >= per * kXcd) return b;
+    return (b % kXcd) * per + b / kXcd;
+}
+
 template <typename T, int CX>
 __device__ __forceinline__ T xdiv(const T (&Flo)[CX], T Fhi, int j)
 {
@@ -146,15 +160,18 @@ __device__ __forceinline__ void accumulate(const T (&out)[CX], double u0, double
 
 template <typename T, int CX, int EQ, int SCHEME>
 __global__ void __launch_bounds__(256)
-    k_step2d(ParamsND p, const T *__restrict__ src, T *__restrict__ dst, int64_t step, int32_t sample,
-             double *__restrict__ part, InstAcc *__restrict__ acc)
+    k_step2d(ParamsND p, const T *__restrict__ src, T *__restrict__ dst, StepArg sarg, double *__restrict__ part,
+             InstAcc *__restrict__ acc)
 {
+    int64_t step;
+    int sample;
+    resolve_step(sarg, step, sample);
     const int LX = p.nx / CX;
     const int lx = threadIdx.x % LX;
     const int grp = threadIdx.x / LX;
     const int gpb = blockDim.x / LX;
     const int nchunks = (p.ny + p.chunk - 1) / p.chunk;
-    const int gchunk = blockIdx.x * gpb + grp;
+    const int gchunk = (p.xcd_order ? xcd_block(blockIdx.x, gridDim.x) : static_cast<int>(blockIdx.x)) * gpb + grp;
     if (gchunk >= p.n_inst * nchunks) return;
     const int inst = gchunk / nchunks, ch = gchunk - inst * nchunks;
     const int y0 = ch * p.chunk, y1 = min(y0 + p.chunk, p.ny);
@@ -284,17 +301,21 @@ __global__ void __launch_bounds__(256)
 
 template <typename T, int CX, int EQ>
 __global__ void __launch_bounds__(256)
-    k_step3d(ParamsND p, int32_t ty, const T *__restrict__ src, T *__restrict__ dst, int64_t step,
-             int32_t sample, double *__restrict__ part, InstAcc *__restrict__ acc)
+    k_step3d(ParamsND p, int32_t ty, const T *__restrict__ src, T *__restrict__ dst, StepArg sarg,
+             double *__restrict__ part, InstAcc *__restrict__ acc)
 {
+    int64_t step;
+    int sample;
+    resolve_step(sarg, step, sample);
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const int LX = p.nx / CX;
     const int lx = threadIdx.x % LX;
     const int g = threadIdx.x / LX;                 // row within the tile
     const int nyt = p.ny / ty, nzc = (p.nz + p.chunk - 1) / p.chunk;
     const int tiles = nyt * nzc;
-    const int inst = blockIdx.x / tiles;
-    const int tile = blockIdx.x - inst * tiles;
+    const int lblock = p.xcd_order ? xcd_block(blockIdx.x, gridDim.x) : static_cast<int>(blockIdx.x);
+    const int inst = lblock / tiles;
+    const int tile = lblock - inst * tiles;
     const int yt = tile % nyt, zc = tile / nyt;
     const int y = yt * ty + g;
     const int z0 = zc * p.chunk, z1 = min(z0 + p.chunk, p.nz);
@@ -421,8 +442,8 @@ __global__ void __launch_bounds__(256)
                 ta += red[2 * w];
                 tb += red[2 * w + 1];
             }
-            part[2 * static_cast<int64_t>(blockIdx.x)] = ta;
-            part[2 * static_cast<int64_t>(blockIdx.x) + 1] = tb;
+            part[2 * static_cast<int64_t>(lblock)] = ta;
+            part[2 * static_cast<int64_t>(lblock) + 1] = tb;
         }
     }
     if (clamps) atomicAdd(reinterpret_cast<unsigned long long *>(&acc[inst].clamp_count),
@@ -431,8 +452,13 @@ __global__ void __launch_bounds__(256)
 
 // Per-instance reduction of the sample partials, fixed order.
 __global__ void __launch_bounds__(64)
-    k_reduce_parts(const double *__restrict__ part, int32_t nparts, double inv_cells, InstAcc *__restrict__ acc)
+    k_reduce_parts(StepArg sarg, const double *__restrict__ part, int32_t nparts, double inv_cells,
+                   InstAcc *__restrict__ acc)
 {
+    int64_t step;
+    int sample;
+    resolve_step(sarg, step, sample);
+    if (!sample) return;
     const int inst = blockIdx.x;
     if (acc[inst].nonfinite) return;
     const double *pp = part + 2 * static_cast<int64_t>(inst) * nparts;
@@ -519,78 +545,100 @@ __global__ void __launch_bounds__(256)
 
 template <typename T, int CX, int EQ>
 static hipError_t step2d_s(int scheme, int n_blocks, hipStream_t s, const ParamsND &p, const void *src, void *dst,
-                           int64_t step, int32_t sample, double *part, InstAcc *acc)
+                           const StepArg &sa, double *part, InstAcc *acc)
 {
     if (scheme == 0)
         hipLaunchKernelGGL((k_step2d<T, CX, EQ, 0>), dim3(n_blocks), dim3(256), 0, s, p,
-                           static_cast<const T *>(src), static_cast<T *>(dst), step, sample, part, acc);
+                           static_cast<const T *>(src), static_cast<T *>(dst), sa, part, acc);
     else
         hipLaunchKernelGGL((k_step2d<T, CX, EQ, 1>), dim3(n_blocks), dim3(256), 0, s, p,
-                           static_cast<const T *>(src), static_cast<T *>(dst), step, sample, part, acc);
+                           static_cast<const T *>(src), static_cast<T *>(dst), sa, part, acc);
     return hipGetLastError();
 }
 
 template <typename T, int CX>
 static hipError_t step2d_e(int eq, int scheme, int n_blocks, hipStream_t s, const ParamsND &p, const void *src,
-                           void *dst, int64_t step, int32_t sample, double *part, InstAcc *acc)
+                           void *dst, const StepArg &sa, double *part, InstAcc *acc)
 {
-    if (eq == 0) return step2d_s<T, CX, 0>(scheme, n_blocks, s, p, src, dst, step, sample, part, acc);
-    return step2d_s<T, CX, 1>(scheme, n_blocks, s, p, src, dst, step, sample, part, acc);
+    if (eq == 0) return step2d_s<T, CX, 0>(scheme, n_blocks, s, p, src, dst, sa, part, acc);
+    return step2d_s<T, CX, 1>(scheme, n_blocks, s, p, src, dst, sa, part, acc);
 }
 
 template <typename T>
 static hipError_t step2d_c(int cx, int eq, int scheme, int n_blocks, hipStream_t s, const ParamsND &p,
-                           const void *src, void *dst, int64_t step, int32_t sample, double *part, InstAcc *acc)
+                           const void *src, void *dst, const StepArg &sa, double *part, InstAcc *acc)
 {
     switch (cx) {
-    case 4: return step2d_e<T, 4>(eq, scheme, n_blocks, s, p, src, dst, step, sample, part, acc);
-    case 8: return step2d_e<T, 8>(eq, scheme, n_blocks, s, p, src, dst, step, sample, part, acc);
-    case 16: return step2d_e<T, 16>(eq, scheme, n_blocks, s, p, src, dst, step, sample, part, acc);
+    case 4: return step2d_e<T, 4>(eq, scheme, n_blocks, s, p, src, dst, sa, part, acc);
+    case 8: return step2d_e<T, 8>(eq, scheme, n_blocks, s, p, src, dst, sa, part, acc);
+    case 16: return step2d_e<T, 16>(eq, scheme, n_blocks, s, p, src, dst, sa, part, acc);
     default: return hipErrorInvalidValue;
     }
 }
 
 hipError_t launch_step2d(int prec, int cx, int eq, int scheme, int n_blocks, hipStream_t s, const ParamsND &p,
-                         const void *src, void *dst, int64_t step, int32_t sample, double *part, InstAcc *acc)
+                         const void *src, void *dst, const StepArg &sa, double *part, InstAcc *acc)
 {
-    if (prec == 0) return step2d_c<float>(cx, eq, scheme, n_blocks, s, p, src, dst, step, sample, part, acc);
-    return step2d_c<double>(cx, eq, scheme, n_blocks, s, p, src, dst, step, sample, part, acc);
+    if (prec == 0) return step2d_c<float>(cx, eq, scheme, n_blocks, s, p, src, dst, sa, part, acc);
+    return step2d_c<double>(cx, eq, scheme, n_blocks, s, p, src, dst, sa, part, acc);
 }
 
 template <typename T, int CX>
 static hipError_t step3d_e(int eq, int ty, int n_blocks, size_t smem, hipStream_t s, const ParamsND &p,
-                           const void *src, void *dst, int64_t step, int32_t sample, double *part, InstAcc *acc)
+                           const void *src, void *dst, const StepArg &sa, double *part, InstAcc *acc)
 {
     const dim3 block((p.nx / CX) * ty);
     if (eq == 0)
         hipLaunchKernelGGL((k_step3d<T, CX, 0>), dim3(n_blocks), block, smem, s, p, ty, static_cast<const T *>(src),
-                           static_cast<T *>(dst), step, sample, part, acc);
+                           static_cast<T *>(dst), sa, part, acc);
     else
         hipLaunchKernelGGL((k_step3d<T, CX, 1>), dim3(n_blocks), block, smem, s, p, ty, static_cast<const T *>(src),
-                           static_cast<T *>(dst), step, sample, part, acc);
+                           static_cast<T *>(dst), sa, part, acc);
     return hipGetLastError();
 }
 
 hipError_t launch_step3d(int prec, int cx, int eq, int ty, int n_blocks, size_t smem, hipStream_t s,
-                         const ParamsND &p, const void *src, void *dst, int64_t step, int32_t sample, double *part,
+                         const ParamsND &p, const void *src, void *dst, const StepArg &sa, double *part,
                          InstAcc *acc)
 {
     if (prec == 0) {
-        if (cx == 4) return step3d_e<float, 4>(eq, ty, n_blocks, smem, s, p, src, dst, step, sample, part, acc);
-        if (cx == 8) return step3d_e<float, 8>(eq, ty, n_blocks, smem, s, p, src, dst, step, sample, part, acc);
-        if (cx == 16) return step3d_e<float, 16>(eq, ty, n_blocks, smem, s, p, src, dst, step, sample, part, acc);
+        if (cx == 4) return step3d_e<float, 4>(eq, ty, n_blocks, smem, s, p, src, dst, sa, part, acc);
+        if (cx == 8) return step3d_e<float, 8>(eq, ty, n_blocks, smem, s, p, src, dst, sa, part, acc);
+        if (cx == 16) return step3d_e<float, 16>(eq, ty, n_blocks, smem, s, p, src, dst, sa, part, acc);
     } else {
-        if (cx == 4) return step3d_e<double, 4>(eq, ty, n_blocks, smem, s, p, src, dst, step, sample, part, acc);
-        if (cx == 8) return step3d_e<double, 8>(eq, ty, n_blocks, smem, s, p, src, dst, step, sample, part, acc);
-        if (cx == 16) return step3d_e<double, 16>(eq, ty, n_blocks, smem, s, p, src, dst, step, sample, part, acc);
+        if (cx == 4) return step3d_e<double, 4>(eq, ty, n_blocks, smem, s, p, src, dst, sa, part, acc);
+        if (cx == 8) return step3d_e<double, 8>(eq, ty, n_blocks, smem, s, p, src, dst, sa, part, acc);
+        if (cx == 16) return step3d_e<double, 16>(eq, ty, n_blocks, smem, s, p, src, dst, sa, part, acc);
     }
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_reduce_parts(int n_inst, hipStream_t s, const double *part, int32_t nparts, double inv_cells,
-                               InstAcc *acc)
+hipError_t launch_reduce_parts(int n_inst, hipStream_t s, const StepArg &sa, const double *part, int32_t nparts,
+                               double inv_cells, InstAcc *acc)
 {
-    hipLaunchKernelGGL(k_reduce_parts, dim3(n_inst), dim3(64), 0, s, part, nparts, inv_cells, acc);
+    hipLaunchKernelGGL(k_reduce_parts, dim3(n_inst), dim3(64), 0, s, sa, part, nparts, inv_cells, acc);
+    return hipGetLastError();
+}
+
+__global__ void k_set_step(int64_t *ctr, int64_t value)
+{
+    if (threadIdx.x == 0) *ctr = value;
+}
+
+__global__ void k_add_step(int64_t *ctr, int64_t k)
+{
+    if (threadIdx.x == 0) *ctr += k;
+}
+
+hipError_t launch_set_step(hipStream_t s, int64_t *ctr, int64_t value)
+{
+    hipLaunchKernelGGL(k_set_step, dim3(1), dim3(64), 0, s, ctr, value);
+    return hipGetLastError();
+}
+
+hipError_t launch_add_step(hipStream_t s, int64_t *ctr, int64_t k)
+{
+    hipLaunchKernelGGL(k_add_step, dim3(1), dim3(64), 0, s, ctr, k);
     return hipGetLastError();
 }
 

@@ -22,6 +22,7 @@ EM, HEUN = 0, 1
 NOISE_INSTANT, NOISE_FROZEN, NOISE_OFF = 0, 1, 2
 F32, F64 = 0, 1
 STAT_MOMENTS, STAT_CORR, STAT_SK, STAT_SPATIAL = 1, 2, 4, 8
+TUNE_XCD_ORDER = 1
 
 OK, EINVAL, EUNSTABLE, ENOMEM, EDEVICE, ENONFINITE, ESTATE, EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6, -7
 _NAMES = {0: "SHE_OK", -1: "SHE_EINVAL", -2: "SHE_EUNSTABLE", -3: "SHE_ENOMEM", -4: "SHE_EDEVICE",
@@ -46,7 +47,8 @@ class Config(C.Structure):
     _fields_ = [("n_instances", C.c_int32), ("precision", C.c_int32), ("inst", C.POINTER(InstanceDesc)),
                 ("burn_in", C.c_int64), ("sample_every", C.c_int32), ("stats_mask", C.c_uint32),
                 ("block_threads", C.c_int32), ("rows_per_block", C.c_int32), ("rows_per_group", C.c_int32),
-                ("reserved", C.c_int32), ("stream", C.c_void_p), ("arena", C.c_void_p),
+                ("tuning_flags", C.c_int32), ("graph_steps", C.c_int32), ("reserved", C.c_int32),
+                ("stream", C.c_void_p), ("arena", C.c_void_p),
                 ("arena_bytes", C.c_size_t)]
 
 
@@ -167,7 +169,7 @@ class Handle:
 
     def __init__(self, instances, precision: int = F32, burn_in: int = 0, sample_every: int = 10,
                  stats: int = 0, stream=None, arena=None, block_threads: int = 0, rows_per_block: int = 0,
-                 rows_per_group: int = 0):
+                 rows_per_group: int = 0, tuning_flags: int = 0, graph_steps: int = 0):
         self.lib = load()
         self.instances = list(instances)
         self._descs = (InstanceDesc * len(self.instances))(*[i.c() for i in self.instances])
@@ -176,7 +178,7 @@ class Handle:
         self.stream = stream
         self._arena = arena
         cfg = Config(len(self.instances), precision, self._descs, burn_in, sample_every, stats,
-                     block_threads, rows_per_block, rows_per_group, 0,
+                     block_threads, rows_per_block, rows_per_group, tuning_flags, graph_steps, 0,
                      C.c_void_p(stream) if stream else None, None, 0)
         if arena is not None:
             cfg.arena = C.c_void_p(arena.data_ptr())
@@ -189,12 +191,12 @@ class Handle:
 
     @staticmethod
     def arena_bytes(instances, precision=F32, burn_in=0, sample_every=10, stats=0, block_threads=0,
-                    rows_per_block=0, rows_per_group=0) -> int:
+                    rows_per_block=0, rows_per_group=0, tuning_flags=0, graph_steps=0) -> int:
         lib = load()
         insts = list(instances)
         descs = (InstanceDesc * len(insts))(*[i.c() for i in insts])
         cfg = Config(len(insts), precision, descs, burn_in, sample_every, stats, block_threads,
-                     rows_per_block, rows_per_group, 0, None, None, 0)
+                     rows_per_block, rows_per_group, tuning_flags, graph_steps, 0, None, None, 0)
         out = C.c_size_t()
         _check(lib.she_arena_bytes(C.byref(cfg), C.byref(out)))
         return int(out.value)

@@ -67,6 +67,16 @@ def test_invalid_nd_configs():
     assert e.value.status == she.EUNSUPPORTED
 
 
+def test_invalid_tuning_and_graph_settings():
+    insts = [gpu_instance(she, W.instance((64, 64), r=0.1))]
+    for kw in (dict(tuning_flags=2), dict(graph_steps=-1), dict(graph_steps=(1 << 16) + 1)):
+        with pytest.raises(she.SheError) as e:
+            she.Handle.arena_bytes(insts, **kw)
+        assert e.value.status == she.EINVAL, kw
+    base = she.Handle.arena_bytes(insts)
+    assert she.Handle.arena_bytes(insts, graph_steps=64, tuning_flags=she.TUNE_XCD_ORDER) == base
+
+
 def test_arena_bytes_scale_with_problem():
     small = she.Handle.arena_bytes([gpu_instance(she, W.instance((64, 64), r=0.1))])
     big = she.Handle.arena_bytes([gpu_instance(she, W.instance((512, 512), r=0.1))])

@@ -1,0 +1,121 @@
+"""GPU parity at the benchmark configurations' full sizes.
+
+Where the oracle can follow the whole run it does (c1, c2); otherwise the
+full-size GPU run is compared on sampled instances / a few full-size steps
+(c4, c5) and on properties that hold at any size (conservation, the discrete
+closed-form variance, no density clamps).  The 2D batch (c3) at full size is
+covered in test_gpu_parity.py.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import theory
+from helpers import gpu_instance, max_rel, oracle_desc
+from paper_2406_12157_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def she():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2406_12157_amd import she as mod
+    mod.load()
+    return mod
+
+
+def test_c1_full_run(she):
+    """1D periodic FE FP64 N = 64, 1e5 steps, sampled every 10 after 1e4:
+    per-cell variance and S_k equal the oracle's, and the variance matches the
+    discrete closed form eps m^2 gamma / (1 - eps beta)."""
+    cfg = W.c1()
+    inst = cfg["instances"][0]
+    h = she.Handle([gpu_instance(she, inst)], precision=1, burn_in=cfg["burn_in"],
+                   sample_every=cfg["sample_every"], stats=she.STAT_MOMENTS | she.STAT_CORR)
+    u = h.read_field(0)
+    h.run(cfg["steps"])
+    g = h.stats(0, corr=True, sk=True)
+    h.close()
+    d = oracle_desc(inst, 1)
+    st = oracle.Stats(d, burn_in=cfg["burn_in"], every=cfg["sample_every"], corr=True, sk=True)
+    oracle.advance(d, u, 0, cfg["steps"], st)
+    assert g["n_samples"] == st.n_samples == 9000
+    assert max_rel(g["var"], st.var()) < 1e-9
+    assert max_rel(g["sk"], st.structure_factor()) < 1e-9
+    gamma, beta = theory.gamma_beta(inst["r"], (64,))
+    want = inst["eps"] * gamma / (1 - inst["eps"] * beta)
+    assert abs(np.mean(g["var"]) / want - 1) < 0.05
+    # the k != 0 structure factor follows N eps m^2 h_k / (1 - eps beta), not the flat value
+    sk_th = theory.sk_periodic(inst["r"], (64,), inst["eps"] / (1 - inst["eps"] * beta))
+    k = np.arange(1, 64)
+    assert np.mean(np.abs(g["sk"][k] / sk_th[k] - 1)) < 0.1
+
+
+def test_c2_full_run(she):
+    """1D Dirichlet PC, N = 128, FP32 state, 1e6 steps, 128 x 128 covariance
+    from the MFMA blocks: statistics equal the oracle's on the same noise."""
+    cfg = W.c2()
+    inst = cfg["instances"][0]
+    h = she.Handle([gpu_instance(she, inst)], precision=0, burn_in=cfg["burn_in"],
+                   sample_every=cfg["sample_every"], stats=she.STAT_MOMENTS | she.STAT_CORR)
+    u = h.read_field(0)
+    h.run(cfg["steps"])
+    g = h.stats(0, corr=True, sk=True)
+    final = h.read_field(0)
+    h.close()
+    d = oracle_desc(inst, 0)
+    st = oracle.Stats(d, burn_in=cfg["burn_in"], every=cfg["sample_every"], corr=True)
+    oracle.advance(d, u, 0, cfg["steps"], st)
+    assert g["n_samples"] == st.n_samples == 90000
+    assert max_rel(final, u) < 1e-4
+    assert max_rel(g["mean"], st.mean()) < 1e-5
+    assert max_rel(g["var"], st.var()) < 1e-3
+    cov = st.cov()
+    assert np.max(np.abs(g["corr"] - cov)) < 1e-3 * np.max(np.abs(np.diag(cov)))
+
+
+def test_c4_full_batch_sampled(she):
+    """1000 ragged 1D instances (N log-uniform in [64, 4096], FE or PC,
+    Dirichlet gradients) for 1e4 steps in one batch; sampled instances match
+    the oracle element by element."""
+    cfg = W.c4()
+    insts = cfg["instances"]
+    h = she.Handle([gpu_instance(she, i) for i in insts], precision=0)
+    ns = np.array([i["n"][0] for i in insts])
+    picks = sorted({int(np.argmax(ns)), int(np.argmin(ns)), 17, 503, 998})
+    init = {q: h.read_field(q) for q in picks}
+    h.step(cfg["steps"])
+    for q in picks:
+        got = h.read_field(q)
+        u = init[q].copy()
+        oracle.advance(oracle_desc(insts[q], 0), u, 0, cfg["steps"])
+        assert max_rel(got, u) <= 1e-5, (q, insts[q]["n"], insts[q]["scheme"])
+    h.close()
+
+
+def test_c5_full_size(she):
+    """3D Dean-Kawasaki 256^3 FE: three full-size steps match the oracle cell
+    by cell; over the full 1e3 steps mass is conserved, no density is
+    clamped, and the spatial variance matches the discrete closed form
+    (c0/dV) gamma_3D = 1182.7 rather than the naive c0/dV."""
+    cfg = W.c5()
+    inst = cfg["instances"][0]
+    h = she.Handle([gpu_instance(she, inst)], precision=0, burn_in=cfg["burn_in"],
+                   sample_every=cfg["sample_every"], stats=she.STAT_SPATIAL)
+    u = h.read_field(0)
+    mass0 = float(np.sum(u))
+    h.step(3)
+    got = h.read_field(0)
+    oracle.advance(oracle_desc(inst, 0), u, 0, 3)
+    assert max_rel(got, u) <= 1e-5
+    h.run(cfg["steps"] - 3)
+    g = h.stats(0)
+    h.close()
+    assert g["clamp_count"] == 0
+    assert abs(g["sum_u"] / mass0 - 1) < 1e-5
+    gamma, _ = theory.gamma_beta(inst["r"], (64, 64, 64))   # gamma is size-insensitive at 64^3 and above
+    want = inst["u0"] * inst["eps"] * gamma
+    assert abs(g["var"][0] / want - 1) < 0.01, (g["var"][0], want)
+    assert abs(g["var"][0] / (inst["u0"] * inst["eps"]) - 1) > 0.1

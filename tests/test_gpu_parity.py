@@ -190,11 +190,64 @@ def test_3d_fp32_state_parity(she, case):
 def test_3d_tiling_invariance(she):
     inst = inst3d((32, 8, 6), W.SPECIES)
     outs = []
-    for rpb, rpg in ((1, 1), (4, 2), (6, 8), (2, 4)):
-        _, got, _ = run_both(she, [inst], 200, 0, rows_per_block=rpb, rows_per_group=rpg)
+    for rpb, rpg, fl in ((1, 1, 0), (4, 2, 0), (6, 8, 0), (2, 4, 0), (1, 2, she.TUNE_XCD_ORDER)):
+        _, got, _ = run_both(she, [inst], 200, 0, rows_per_block=rpb, rows_per_group=rpg, tuning_flags=fl)
         outs.append(got[0])
     for o in outs[1:]:
         np.testing.assert_array_equal(o, outs[0])
+
+
+def test_workgroup_order_invariance(she):
+    insts = [inst2d((64, 32), W.EM, W.HEAT, realisation=q) for q in range(20)]
+    h1 = she.Handle([gpu_instance(she, i) for i in insts], precision=0, rows_per_block=2)
+    h2 = she.Handle([gpu_instance(she, i) for i in insts], precision=0, rows_per_block=2,
+                    tuning_flags=she.TUNE_XCD_ORDER)
+    h1.step(300)
+    h2.step(300)
+    for q in range(20):
+        np.testing.assert_array_equal(h1.read_field(q), h2.read_field(q))
+    h1.close()
+    h2.close()
+
+
+def test_graph_replay_matches_direct_launches(she):
+    """Steps replayed from recorded HIP graphs (graph_steps) give the bits of
+    one launch per step: 2D PC with sampling on both sides of the burn-in and
+    a 3D FE run, with eager work (field reads, unaligned she_run / she_step
+    calls) between the replays."""
+    insts = [inst2d((64, 32), W.HEUN, W.HEAT, realisation=q) for q in range(3)]
+    kw = dict(precision=0, burn_in=37, sample_every=3, stats=she.STAT_SPATIAL | she.STAT_SK)
+    a = she.Handle([gpu_instance(she, i) for i in insts], **kw)
+    b = she.Handle([gpu_instance(she, i) for i in insts], graph_steps=16, **kw)
+    plan = [("run", 5), ("run", 100), ("read",), ("step", 7), ("run", 61), ("read",), ("run", 48),
+            ("step", 40), ("run", 200)]
+    for op in plan:
+        if op[0] == "read":
+            for q in range(3):
+                np.testing.assert_array_equal(a.read_field(q), b.read_field(q))
+        else:
+            getattr(a, op[0])(op[1])
+            getattr(b, op[0])(op[1])
+    assert a.steps == b.steps == 461
+    for q in range(3):
+        np.testing.assert_array_equal(a.read_field(q), b.read_field(q))
+        ga, gb = a.stats(q, sk=True), b.stats(q, sk=True)
+        assert ga["n_samples"] == gb["n_samples"] == 125
+        for key in ("mean", "var", "sk"):
+            np.testing.assert_array_equal(ga[key], gb[key])
+        assert ga["sum_u"] == gb["sum_u"]
+    a.close()
+    b.close()
+    insts = [inst3d((32, 16, 8), W.SPECIES, realisation=q) for q in range(2)]
+    a = she.Handle([gpu_instance(she, i) for i in insts], precision=0)
+    b = she.Handle([gpu_instance(she, i) for i in insts], precision=0, graph_steps=10)
+    for k in (3, 50, 1, 33):
+        a.step(k)
+        b.step(k)
+        for q in range(2):
+            np.testing.assert_array_equal(a.read_field(q), b.read_field(q))
+    a.close()
+    b.close()
 
 
 # ---------------------------------------------------------------- statistics
