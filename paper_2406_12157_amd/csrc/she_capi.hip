@@ -64,9 +64,7 @@ struct she_handle {
     int nbins = 0, sk_groups = 0;
     void *d_half = nullptr, *d_twx = nullptr, *d_twy = nullptr;
     double *d_skpart = nullptr, *d_sksum = nullptr, *d_skmodes = nullptr;
-    int32_t *d_sklo = nullptr;
     std::vector<double> skmodes;
-    std::vector<int32_t> sklo;
     // captured step loops: [0] without, [1] with sample steps
     int64_t *d_step = nullptr;    // device step counter read by replayed kernels
     int64_t dev_step = -1;        // value *d_step holds once the stream is idle
@@ -343,14 +341,11 @@ static she_status plan_nd(she_handle *h, const she_config *cfg, Plan &plan)
                 const int b = static_cast<int>(std::floor(std::sqrt(sx * sx + sy * sy) + 0.5));
                 if (b < h->nbins) h->skmodes[b] += 1.0;
             }
-        h->sk_groups = sk2d_groups(h->prec, nx, p.ny);
+        h->sk_groups = sk2d_groups(h->prec, nx, p.ny, h->n_inst);
         const size_t nh = static_cast<size_t>(nx / 2 + 1);
         plan.add(&h->d_half, 2 * es * nh * p.ny * h->n_inst);
         plan.add(&h->d_twx, 2 * es * nx);
         plan.add(&h->d_twy, 2 * es * p.ny);
-        h->sklo.assign(nh * (h->nbins + 1), 0);
-        sk2d_shell_table(nx, p.ny, h->nbins, h->sklo.data());
-        plan.add(reinterpret_cast<void **>(&h->d_sklo), sizeof(int32_t) * h->sklo.size());
         plan.add(reinterpret_cast<void **>(&h->d_skpart), sizeof(double) * h->n_inst * h->sk_groups * h->nbins);
         plan.add(reinterpret_cast<void **>(&h->d_sksum), sizeof(double) * h->n_inst * h->nbins);
         plan.add(reinterpret_cast<void **>(&h->d_skmodes), sizeof(double) * h->nbins);
@@ -479,8 +474,6 @@ extern "C" she_status she_create(const she_config *cfg, she_handle **out)
         if (h->d_skmodes) {
             CREATE_HIP(hipMemcpyAsync(h->d_skmodes, h->skmodes.data(), sizeof(double) * h->nbins,
                                       hipMemcpyHostToDevice, s));
-            CREATE_HIP(hipMemcpyAsync(h->d_sklo, h->sklo.data(), sizeof(int32_t) * h->sklo.size(),
-                                      hipMemcpyHostToDevice, s));
             CREATE_HIP(launch_twiddles(h->prec, s, h->pnd.nx, h->d_twx));
             CREATE_HIP(launch_twiddles(h->prec, s, h->pnd.ny, h->d_twy));
         }
@@ -534,7 +527,7 @@ static hipError_t nd_enqueue(she_handle *h, hipStream_t s, const StepArg &sa, in
     e = launch_reduce_parts(h->n_inst, s, sa, h->d_part, h->nparts, 1.0 / static_cast<double>(h->cells), h->d_acc);
     if (e != hipSuccess || !(h->mask & SHE_STAT_SK)) return e;
     return launch_sk2d(h->prec, s, sa, h->n_inst, h->pnd.nx, h->pnd.ny, h->pnd.u0, dst, h->d_half, h->d_twx, h->d_twy,
-                       h->d_sklo, h->d_skpart, h->nbins, h->d_sksum, h->d_acc);
+                       h->d_skpart, h->nbins, h->d_sksum, h->d_acc);
 }
 
 static she_status nd_direct(she_handle *h, bool samp)

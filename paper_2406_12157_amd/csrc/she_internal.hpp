@@ -135,12 +135,10 @@ hipError_t launch_debug_normals(hipStream_t s, int prec, uint64_t seed, uint32_t
 // binning into per-block partials, fixed-order reduction into sums
 // (n_inst x nbins FP64).  half: n_inst*ny*(nx/2+1) complex of the state type.
 hipError_t launch_sk2d(int prec, hipStream_t s, const StepArg &st, int n_inst, int nx, int ny, double u0,
-                       const void *field, void *half, const void *twx, const void *twy, const int32_t *lo,
-                       double *part, int nbins, double *sums, const InstAcc *acc);
-// Host: first |ky| of each shell per half-spectrum column, (nx/2+1) x (nbins+1).
-void sk2d_shell_table(int nx, int ny, int nbins, int32_t *lo);
+                       const void *field, void *half, const void *twx, const void *twy, double *part, int nbins,
+                       double *sums, const InstAcc *acc);
 // exp(-2 pi i t/n), t < n/2, as complex pairs of the state type
 hipError_t launch_twiddles(int prec, hipStream_t s, int n, void *tw);
-int sk2d_groups(int prec, int nx, int ny);
+int sk2d_groups(int prec, int nx, int ny, int n_inst);
 
 }  // namespace she

@@ -6,27 +6,34 @@
 // field dU = U - u0 (which changes only the k = 0 mode; the finalisation
 // restores that mode exactly from the spatial sums), in the state's precision.
 //
-// 1. k_fft_rows: two real rows are packed as one complex sequence
-//    (dU_a + i dU_b), transformed along x in LDS, separated into the two half
-//    spectra A_k = (Z_k + conj Z_-k)/2, B_k = (Z_k - conj Z_-k)/(2i), and
-//    stored column-major (kx-major, y fastest) so that a block of 2*RP rows
-//    writes runs of 2*RP consecutive y per kx.
-// 2. k_fft_cols: CW half-spectrum columns (contiguous in memory) are
-//    transformed along y in LDS, the power |X|^2 is formed with weight 2 for
-//    0 < kx < Nx/2 (the mirrored half of the spectrum), and binned without
-//    atomics: per column a wave forms the FP64 prefix sum P(m) of the power
-//    over |ky| <= m (fixed-order scan), and thread b adds, column by column,
-//    P(hi-1) - P(lo-1) over the range [lo(kx, b), lo(kx, b+1)) of |ky| read
-//    from an integer table built from (2b-1)^2 <= 4(kx^2 + ky^2) < (2b+1)^2.
-//    The per-block shell sums go to a partial buffer.
+// 1. k_sk_rows: two real rows are packed as one complex sequence
+//    (dU_a + i dU_b) and transformed along x by one wave; the two half spectra
+//    A_k = (Z_k + conj Z_-k)/2, B_k = (Z_k - conj Z_-k)/(2i) are stored
+//    kx-major (y fastest), so that the waves of a block, which hold
+//    consecutive row pairs, write runs of consecutive y per kx.
+// 2. k_sk_cols: each wave transforms half-spectrum columns (contiguous in
+//    memory) along y, looping over the block's columns and loading the next
+//    column while it transforms the current one.  The power |X|^2 gets weight
+//    2 for 0 < kx < Nx/2 (the mirrored half of the spectrum) and is binned
+//    without atomics: per column the wave forms the FP64 prefix sum P(m) of
+//    the power over |ky| <= m (fixed-order scan), and lane b adds
+//    P(hi-1) - P(lo-1) over the range [lo(kx, b), lo(kx, b+1)) of |ky|, with
+//    lo(kx, b) the first |ky| in shell b: (2b-1)^2 <= 4(kx^2 + ky^2), exact in
+//    integers.  Only shells kx .. round(sqrt(kx^2 + (Ny/2)^2)) meet column kx.
+//    The waves' shell sums are added in a fixed order into one partial per
+//    block.
 // 3. k_bins_reduce: per instance and shell, the partials are added in a fixed
 //    order to the FP64 running sums.
 //
-// The transforms are Stockham autosort passes (radix 4, a final radix 2 for
-// odd log2 n; natural order in and out, so the LDS reads of a pass are
-// contiguous), with the twiddle table exp(-2 pi i t/n) precomputed once per
-// handle.
+// Transforms: Stockham autosort (decimation in frequency, natural order in
+// and out), radix 8 with a final radix 4 or 2, one wave per sequence (or per
+// group of short sequences).  A lane holds P points in registers; between
+// passes the wave exchanges them through its own LDS region, so a transform
+// needs no workgroup barrier.  The twiddle table exp(-2 pi i t/n) is
+// precomputed once per handle and staged in LDS.
 #include "she_internal.hpp"
+
+#include <algorithm>
 
 namespace she {
 
@@ -36,81 +43,205 @@ struct cplx {
 };
 
 template <typename T>
+__device__ __forceinline__ cplx<T> cadd(cplx<T> a, cplx<T> b)
+{
+    return cplx<T>{a.re + b.re, a.im + b.im};
+}
+
+template <typename T>
+__device__ __forceinline__ cplx<T> csub(cplx<T> a, cplx<T> b)
+{
+    return cplx<T>{a.re - b.re, a.im - b.im};
+}
+
+template <typename T>
 __device__ __forceinline__ cplx<T> cmul(cplx<T> a, cplx<T> w)
 {
     return cplx<T>{a.re * w.re - a.im * w.im, a.re * w.im + a.im * w.re};
 }
 
-// One pass of the Stockham autosort FFT (decimation in frequency, radix
-// R = 2^LR) over `count` sequences of length n = 2^lg stored contiguously in
-// LDS, natural order in and out.  Current sub-transform length 2^rem, stride
-// s = 2^(lg - rem), m = 2^(rem - LR): butterfly t = q + s p (q < s, p < m)
-// reads x[t + k n/R], forms the R-point DFT, multiplies output k by
-// exp(-2 pi i k p s / n) and writes it to x[q + s (R p + k)].  All reads of a
-// pass are staged in registers between two barriers, so one buffer serves.
-// tw holds exp(-2 pi i t/n), t < n.  At most kPts/R butterflies per thread.
-constexpr int kPts = 16;  // points staged per thread and pass
-
-template <typename T, int LG, int REM, int LR>
-__device__ __forceinline__ void stockham_pass(cplx<T> *buf, int count, const cplx<T> *tw)
+// Shape of the per-wave transform of length n = 2^lg: P points per lane,
+// S sequences per wave (64 P = S n), padded LDS entries per wave region.
+constexpr int wave_points(int lg)
 {
-    constexpr int R = 1 << LR;
-    constexpr int MAXB = kPts / R;
-    constexpr int lg = LG;
-    constexpr int n = 1 << lg;
-    constexpr int ls = lg - REM;
-    const int nbf = count << (lg - LR);
-    cplx<T> v[MAXB][R];
-#pragma unroll
-    for (int i = 0; i < MAXB; ++i) {
-        const int b = threadIdx.x + i * blockDim.x;
-        if (b < nbf) {
-            const int seq = b >> (lg - LR), t = b & ((n >> LR) - 1);
-            const cplx<T> *x = buf + (seq << lg);
-            cplx<T> a[R];
-#pragma unroll
-            for (int k = 0; k < R; ++k) a[k] = x[t + k * (n >> LR)];
-            const int p = t >> ls;
-            if constexpr (R == 4) {
-                const cplx<T> t0{a[0].re + a[2].re, a[0].im + a[2].im};
-                const cplx<T> t1{a[0].re - a[2].re, a[0].im - a[2].im};
-                const cplx<T> t2{a[1].re + a[3].re, a[1].im + a[3].im};
-                const cplx<T> t3{a[1].im - a[3].im, a[3].re - a[1].re};  // -i (a1 - a3)
-                v[i][0] = cplx<T>{t0.re + t2.re, t0.im + t2.im};
-                v[i][1] = cmul(cplx<T>{t1.re + t3.re, t1.im + t3.im}, tw[p << ls]);
-                v[i][2] = cmul(cplx<T>{t0.re - t2.re, t0.im - t2.im}, tw[(2 * p) << ls]);
-                v[i][3] = cmul(cplx<T>{t1.re - t3.re, t1.im - t3.im}, tw[(3 * p) << ls]);
-            } else {
-                v[i][0] = cplx<T>{a[0].re + a[1].re, a[0].im + a[1].im};
-                v[i][1] = cmul(cplx<T>{a[0].re - a[1].re, a[0].im - a[1].im}, tw[p << ls]);
-            }
-        }
-    }
-    __syncthreads();
-#pragma unroll
-    for (int i = 0; i < MAXB; ++i) {
-        const int b = threadIdx.x + i * blockDim.x;
-        if (b < nbf) {
-            const int seq = b >> (lg - LR), t = b & ((n >> LR) - 1);
-            const int q = t & ((1 << ls) - 1), p = t >> ls;
-            cplx<T> *x = buf + (seq << lg);
-#pragma unroll
-            for (int k = 0; k < R; ++k) x[q + ((R * p + k) << ls)] = v[i][k];
-        }
-    }
-    __syncthreads();
+    return (1 << lg) >= 512 ? (1 << lg) / 64 : ((1 << lg) >= 8 ? 8 : (1 << lg));
 }
 
-// FFTs of `count` contiguous sequences of length 2^LG in LDS, natural order
-// in and out; count << LG must not exceed kPts * blockDim.x.
-template <typename T, int LG, int REM = LG>
-__device__ __forceinline__ void fft_stockham(cplx<T> *buf, int count, const cplx<T> *tw)
+constexpr int wave_seqs(int lg)
 {
-    if constexpr (REM >= 2) {
-        stockham_pass<T, LG, REM, 2>(buf, count, tw);
-        fft_stockham<T, LG, REM - 2>(buf, count, tw);
-    } else if constexpr (REM == 1) {
-        stockham_pass<T, LG, 1, 1>(buf, count, tw);
+    return (64 * wave_points(lg)) >> lg;
+}
+
+constexpr int wave_lds(int lg)
+{
+    return (wave_seqs(lg) << lg) + (((wave_seqs(lg) << lg) - 1) >> 4) + 1;
+}
+
+// log2 of the radix of the pass at sub-transform length 2^rem: 8, then 4 or 2
+constexpr int pass_lr(int rem)
+{
+    return rem >= 3 ? 3 : rem;
+}
+
+// Twiddles per pass, laid out [p][k-1] (k = 1..R-1) so that the lanes of a
+// pass, which differ in p, read R-1 consecutive entries each (odd stride: no
+// bank conflicts).  A pass at sub-length 2^rem has 2^(rem - lr) values of p
+// and none when it is the last one.  Entries of the passes from 2^rem down:
+constexpr int tw_entries(int rem)
+{
+    return rem <= 0 ? 0
+                    : (rem > pass_lr(rem) ? (1 << (rem - pass_lr(rem))) * ((1 << pass_lr(rem)) - 1) : 0) +
+                          tw_entries(rem - pass_lr(rem));
+}
+
+template <int LG>
+struct WaveFft {
+    static constexpr int n = 1 << LG;
+    static constexpr int P = wave_points(LG);
+    static constexpr int S = wave_seqs(LG);
+    static constexpr int lds = wave_lds(LG);
+    static constexpr int tw = tw_entries(LG) > 0 ? tw_entries(LG) : 1;  // per-pass twiddle entries
+};
+
+// one pad entry per 16 spreads the strided exchange accesses over the banks
+__device__ __forceinline__ int pidx(int i)
+{
+    return i + (i >> 4);
+}
+
+// Order the LDS accesses of one wave (a wave's LDS operations complete in
+// issue order; this keeps the compiler from moving them across).
+__device__ __forceinline__ void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// In-register DFTs of length 2, 4, 8 (natural order in and out).
+template <typename T>
+__device__ __forceinline__ void dft2(cplx<T> *a)
+{
+    const cplx<T> t = a[0];
+    a[0] = cadd(t, a[1]);
+    a[1] = csub(t, a[1]);
+}
+
+template <typename T>
+__device__ __forceinline__ void dft4(cplx<T> &a0, cplx<T> &a1, cplx<T> &a2, cplx<T> &a3)
+{
+    const cplx<T> t0 = cadd(a0, a2), t1 = csub(a0, a2), t2 = cadd(a1, a3);
+    const cplx<T> d = csub(a1, a3);
+    const cplx<T> t3{d.im, -d.re};  // -i (a1 - a3)
+    a0 = cadd(t0, t2);
+    a1 = cadd(t1, t3);
+    a2 = csub(t0, t2);
+    a3 = csub(t1, t3);
+}
+
+template <typename T>
+__device__ __forceinline__ void dft8(cplx<T> *a)
+{
+    // even and odd halves, then w8^k on the odd outputs
+    dft4(a[0], a[2], a[4], a[6]);
+    dft4(a[1], a[3], a[5], a[7]);
+    const T c = static_cast<T>(0.70710678118654752440);
+    const cplx<T> o1{c * (a[3].re + a[3].im), c * (a[3].im - a[3].re)};  // (1 - i)/sqrt2
+    const cplx<T> o2{a[5].im, -a[5].re};                                 // -i
+    const cplx<T> o3{c * (a[7].im - a[7].re), -c * (a[7].re + a[7].im)}; // (-1 - i)/sqrt2
+    const cplx<T> e0 = a[0], e1 = a[2], e2 = a[4], e3 = a[6], o0 = a[1];
+    a[0] = cadd(e0, o0);
+    a[4] = csub(e0, o0);
+    a[1] = cadd(e1, o1);
+    a[5] = csub(e1, o1);
+    a[2] = cadd(e2, o2);
+    a[6] = csub(e2, o2);
+    a[3] = cadd(e3, o3);
+    a[7] = csub(e3, o3);
+}
+
+template <int REM>
+struct PassRadix {
+    static constexpr int LR = pass_lr(REM);
+};
+
+// Inputs of a pass of radix R = 2^LR: lane slot i*R + k holds element
+// t + k n/R of sequence seq, for butterfly b = lane + 64 i = seq (n/R) + t.
+template <int LG, int LR>
+__device__ __forceinline__ void pass_input(int lane, int i, int k, int &seq, int &idx)
+{
+    constexpr int n = 1 << LG;
+    const int b = lane + 64 * i;
+    seq = b >> (LG - LR);
+    idx = (b & ((n >> LR) - 1)) + k * (n >> LR);
+}
+
+// Remaining passes of the wave transform from sub-transform length 2^REM.
+// Butterfly t = q + s p (s = 2^(LG-REM), q < s) forms the R-point DFT of its
+// inputs, multiplies output k by exp(-2 pi i k p s / n) and writes it to
+// element q + s (R p + k).  After the last pass the wave's LDS region holds
+// the transforms in natural order.
+template <typename T, int LG, int REM>
+__device__ __forceinline__ void wave_fft(cplx<T> (&v)[WaveFft<LG>::P], cplx<T> *buf, const cplx<T> *tw, int lane)
+{
+    using F = WaveFft<LG>;
+    constexpr int LR = PassRadix<REM>::LR, R = 1 << LR, B = F::P / R, n = F::n;
+    constexpr int ls = LG - REM, s = 1 << ls;
+#pragma unroll
+    for (int i = 0; i < B; ++i) {
+        const int b = lane + 64 * i;
+        const int seq = b >> (LG - LR), t = b & ((n >> LR) - 1);
+        const int q = t & (s - 1), p = t >> ls;
+        cplx<T> *a = &v[i * R];
+        if constexpr (R == 8) dft8(a);
+        else if constexpr (R == 4) dft4(a[0], a[1], a[2], a[3]);
+        else dft2(a);
+        const int base = (seq << LG) + q + s * R * p;
+#pragma unroll
+        for (int k = 0; k < R; ++k) {
+            cplx<T> o = a[k];
+            if constexpr (REM > LR) {
+                if (k > 0) o = cmul(o, tw[(tw_entries(LG) - tw_entries(REM)) + p * (R - 1) + (k - 1)]);
+            }
+            buf[pidx(base + s * k)] = o;
+        }
+    }
+    wave_sync();
+    if constexpr (REM > LR) {
+        constexpr int REM2 = REM - LR, LR2 = PassRadix<REM2>::LR, R2 = 1 << LR2;
+#pragma unroll
+        for (int i = 0; i < F::P / R2; ++i) {
+#pragma unroll
+            for (int k = 0; k < R2; ++k) {
+                int seq, idx;
+                pass_input<LG, LR2>(lane, i, k, seq, idx);
+                v[i * R2 + k] = buf[pidx((seq << LG) + idx)];
+            }
+        }
+        wave_sync();
+        wave_fft<T, LG, REM2>(v, buf, tw, lane);
+    }
+}
+
+// Per-pass twiddle tables of a length-2^LG transform from the natural table
+// exp(-2 pi i t/n): pass at sub-length 2^rem, stride s = 2^(LG-rem), entry
+// (p, k) = exp(-2 pi i k p s / n).  Block-cooperative.
+template <typename T, int LG>
+__device__ __forceinline__ void fill_pass_twiddles(cplx<T> *dst, const cplx<T> *__restrict__ nat)
+{
+    constexpr int n = 1 << LG;
+    int off = 0;
+    for (int rem = LG; rem > 0;) {
+        const int lr = pass_lr(rem), r = 1 << lr;
+        if (rem > lr) {
+            const int m = 1 << (rem - lr), s = 1 << (LG - rem);
+            for (int e = threadIdx.x; e < m * (r - 1); e += blockDim.x) {
+                const int p = e / (r - 1), k = e - p * (r - 1) + 1;
+                dst[off + e] = nat[(k * p * s) & (n - 1)];
+            }
+            off += m * (r - 1);
+        }
+        rem -= lr;
     }
 }
 
@@ -125,142 +256,255 @@ __global__ void __launch_bounds__(256) k_twiddles(int n, cplx<T> *__restrict__ t
     tw[t] = cplx<T>{static_cast<T>(cs), static_cast<T>(sn)};
 }
 
-// grid: (ceil(ny/2 / rp), n_inst); block 256; LDS: rp*nx complex + nx twiddles.
-// Output: half[inst][kx][y], kx = 0..nx/2.
-template <typename T, int LGX>
-__global__ void __launch_bounds__(256)
-    k_fft_rows(StepArg sarg, const T *__restrict__ field, int ny, int rp, double u0, const cplx<T> *__restrict__ twx,
-               cplx<T> *__restrict__ half)
+constexpr int kLdsBudget = 64 * 1024;  // bytes of LDS per block
+
+// Waves per block of the row transform: as many as fit the LDS budget, up to
+// 8 (8 row pairs give 128-byte runs per kx in the kx-major store).
+template <typename T, int LG>
+constexpr int row_waves()
 {
-    {
-        int64_t step;
-        int sample;
-        resolve_step(sarg, step, sample);
-        if (!sample) return;  // a non-sample step of a captured graph
-    }
-    constexpr int nx = 1 << LGX;
+    using F = WaveFft<LG>;
+    constexpr int es = static_cast<int>(sizeof(cplx<T>));
+    return es * (F::tw + 8 * F::lds) <= kLdsBudget ? 8 : es * (F::tw + 4 * F::lds) <= kLdsBudget ? 4 : 2;
+}
+
+#define SHE_SAMPLE_GATE()                                                                          \
+    do {                                                                                           \
+        int64_t step_;                                                                             \
+        int sample_;                                                                               \
+        resolve_step(sarg, step_, sample_);                                                        \
+        if (!sample_) return; /* a non-sample step of a captured graph */                           \
+    } while (0)
+
+// grid: (ceil(ny/2 / (W S)), n_inst); block 64 W; LDS: pass twiddles + W regions.
+template <typename T, int LGX>
+__global__ void __launch_bounds__(512)
+    k_sk_rows(StepArg sarg, const T *__restrict__ field, int ny, double u0, const cplx<T> *__restrict__ twx,
+              cplx<T> *__restrict__ half)
+{
+    SHE_SAMPLE_GATE();
+    using F = WaveFft<LGX>;
+    constexpr int n = F::n, P = F::P, S = F::S, W = row_waves<T, LGX>();
+    constexpr int LR = PassRadix<LGX>::LR, R = 1 << LR;
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    cplx<T> *buf = reinterpret_cast<cplx<T> *>(smem_raw);
-    cplx<T> *tw = buf + rp * nx;
+    cplx<T> *tw = reinterpret_cast<cplx<T> *>(smem_raw);
+    cplx<T> *reg = tw + F::tw;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int inst = blockIdx.y;
-    const int pair0 = blockIdx.x * rp;
-    const int npairs = min(rp, ny / 2 - pair0);
-    constexpr int bits = LGX;
-    constexpr int nh = nx / 2 + 1;
-    for (int t = threadIdx.x; t < nx; t += blockDim.x) tw[t] = twx[t];
-    const T *f = field + static_cast<int64_t>(inst) * nx * ny;
+    const int pair0 = blockIdx.x * (W * S);
+    const int npairs = min(W * S, ny / 2 - pair0);
+    const T *f = field + static_cast<int64_t>(inst) * n * ny;
     const T su0 = static_cast<T>(u0);
-    for (int e = threadIdx.x; e < npairs * nx; e += blockDim.x) {
-        const int q = e >> bits, j = e & (nx - 1);
-        const int ya = 2 * (pair0 + q);
-        const T a = f[static_cast<int64_t>(ya) * nx + j] - su0;
-        const T b = f[static_cast<int64_t>(ya + 1) * nx + j] - su0;
-        buf[q * nx + j] = cplx<T>{a, b};
+    cplx<T> v[P];
+#pragma unroll
+    for (int i = 0; i < P / R; ++i) {
+#pragma unroll
+        for (int k = 0; k < R; ++k) {
+            int seq, x;
+            pass_input<LGX, LR>(lane, i, k, seq, x);
+            const int pair = wave * S + seq;
+            if (pair < npairs) {
+                const T *ra = f + static_cast<int64_t>(2 * (pair0 + pair)) * n;
+                v[i * R + k] = cplx<T>{ra[x] - su0, ra[n + x] - su0};
+            } else {
+                v[i * R + k] = cplx<T>{T(0), T(0)};
+            }
+        }
     }
+    fill_pass_twiddles<T, LGX>(tw, twx);
     __syncthreads();
-    fft_stockham<T, LGX>(buf, npairs, tw);
-    cplx<T> *h = half + static_cast<int64_t>(inst) * nh * ny;
-    const int nrow = 2 * npairs;  // a power of two (ny and rp are)
+    wave_fft<T, LGX, LGX>(v, reg + wave * F::lds, tw, lane);
+    __syncthreads();
+    // kx-major store: per kx a run of 2*npairs consecutive y (rows fastest)
+    constexpr int nh = n / 2 + 1;
+    const int nrow = 2 * npairs;  // a power of two (ny and W S are)
     const int lrow = 31 - __builtin_clz(nrow);
-    // thread e -> (k, row within the block), rows fastest: runs of nrow y per kx
+    constexpr int lS = 31 - __builtin_clz(S);
+    cplx<T> *h = half + static_cast<int64_t>(inst) * nh * ny + 2 * pair0;
     for (int e = threadIdx.x; e < nrow * nh; e += blockDim.x) {
         const int k = e >> lrow, rr = e & (nrow - 1);
-        const int q = rr >> 1;
-        const cplx<T> z = buf[q * nx + k];
-        const cplx<T> zm = buf[q * nx + ((nx - k) & (nx - 1))];
+        const int pair = rr >> 1;
+        const cplx<T> *z0 = reg + (pair >> lS) * F::lds;
+        const int sb = (pair & (S - 1)) << LGX;
+        const cplx<T> z = z0[pidx(sb + k)];
+        const cplx<T> zm = z0[pidx(sb + ((n - k) & (n - 1)))];
         // A = (z + conj zm)/2 (row 2q), B = (z - conj zm)/(2i) (row 2q+1)
-        const cplx<T> v = (rr & 1) ? cplx<T>{T(0.5) * (z.im + zm.im), T(-0.5) * (z.re - zm.re)}
+        const cplx<T> o = (rr & 1) ? cplx<T>{T(0.5) * (z.im + zm.im), T(-0.5) * (z.re - zm.re)}
                                    : cplx<T>{T(0.5) * (z.re + zm.re), T(0.5) * (z.im - zm.im)};
-        h[static_cast<int64_t>(k) * ny + 2 * pair0 + rr] = v;
+        h[static_cast<int64_t>(k) * ny + rr] = o;
     }
 }
 
-// grid: (ceil(nh / cw), n_inst); block 256; LDS: cw*ny complex + ny twiddles.
-// lo: nh x (nbins + 1) table of the first |ky| of each shell per column.
-template <typename T, int LGY>
-__global__ void __launch_bounds__(256)
-    k_fft_cols(StepArg sarg, const cplx<T> *__restrict__ half, int nx, int cw, int nbins,
-               const cplx<T> *__restrict__ twy, const int32_t *__restrict__ lo, double *__restrict__ part)
+// LDS bytes per wave of the column transform: its transform region and the
+// FP64 prefix sums of one column.
+constexpr int col_region(int es, int lg)
 {
-    {
-        int64_t step;
-        int sample;
-        resolve_step(sarg, step, sample);
-        if (!sample) return;  // a non-sample step of a captured graph
+    return es * wave_lds(lg) + 8 * ((1 << lg) / 2 + 1);
+}
+
+// Waves per block of the column transform: 4, or 2 where 4 regions and the
+// twiddles exceed the LDS budget (the largest FP64 columns).
+constexpr int col_waves(int es, int lg)
+{
+    return es * tw_entries(lg) + 4 * col_region(es, lg) <= kLdsBudget ? 4 : 2;
+}
+
+constexpr int kMaxBinIters = 12;  // shells per lane: nbins <= 64 * 12
+
+// One DPP move of a double (both halves with the same control); lanes with
+// no source, or outside the row / bank masks, receive 0.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ double dpp_move(double v)
+{
+    const long long u = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, static_cast<int>(u & 0xffffffffLL), CTRL, ROWS, 0xf, true);
+    const int hi = __builtin_amdgcn_update_dpp(0, static_cast<int>(u >> 32), CTRL, ROWS, 0xf, true);
+    return __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<unsigned>(lo));
+}
+
+// Inclusive prefix sum over the 64 lanes of a wave: shifts by 1, 2, 4, 8
+// within rows of 16, then the last lane of row 0 / 2 into row 1 / 3 and lane
+// 31 into rows 2 and 3.
+__device__ __forceinline__ double wave_inclusive_sum(double v)
+{
+    v += dpp_move<0x111, 0xf>(v);  // row_shr:1
+    v += dpp_move<0x112, 0xf>(v);  // row_shr:2
+    v += dpp_move<0x114, 0xf>(v);  // row_shr:4
+    v += dpp_move<0x118, 0xf>(v);  // row_shr:8
+    v += dpp_move<0x142, 0xa>(v);  // row_bcast:15
+    v += dpp_move<0x143, 0xc>(v);  // row_bcast:31
+    return v;
+}
+
+// First |ky| of shell b in column kx, clipped to [0, hy + 1]: the smallest
+// m >= 0 with 4 (kx^2 + m^2) >= (2b - 1)^2 (b = 0: m = 0).  The single
+// precision root is within one of the answer; the integer tests settle it.
+__device__ __forceinline__ int shell_first(int kx, int b, int hy)
+{
+    if (b == 0) return 0;
+    const int need = (2 * b - 1) * (2 * b - 1) - 4 * kx * kx;
+    if (need <= 0) return 0;
+    int m = static_cast<int>(ceilf(0.5f * sqrtf(static_cast<float>(need))));
+    if (4 * m * m < need) ++m;
+    else if (m > 0 && 4 * (m - 1) * (m - 1) >= need) --m;
+    return min(m, hy + 1);
+}
+
+// Loads the column group of one wave iteration (S columns from `g`) in the
+// first pass's order; columns beyond nh are zero.
+template <typename T, int LGY>
+__device__ __forceinline__ void load_cols(cplx<T> (&v)[WaveFft<LGY>::P], const cplx<T> *__restrict__ hc, int g,
+                                          int nh, int lane)
+{
+    using F = WaveFft<LGY>;
+    constexpr int LR = PassRadix<LGY>::LR, R = 1 << LR;
+#pragma unroll
+    for (int i = 0; i < F::P / R; ++i) {
+#pragma unroll
+        for (int k = 0; k < R; ++k) {
+            int seq, y;
+            pass_input<LGY, LR>(lane, i, k, seq, y);
+            v[i * R + k] = g + seq < nh ? hc[(static_cast<int64_t>(g + seq) << LGY) + y] : cplx<T>{T(0), T(0)};
+        }
     }
-    constexpr int ny = 1 << LGY;
+}
+
+// grid: (groups, n_inst); block 64 CW; wave w handles, in iteration it, the
+// S columns from cb + S (it CW + w).  LDS: pass twiddles, then
+// per wave `rs` bytes: the transform region, the FP64 prefix sums of one
+// column, and (after the loop) the wave's shell sums.
+template <typename T, int LGY, int NBJ>
+__global__ void __launch_bounds__(256)
+    k_sk_cols(StepArg sarg, const cplx<T> *__restrict__ half, int nx, int iters, int rs, int nbins,
+              const cplx<T> *__restrict__ twy, double *__restrict__ part)
+{
+    SHE_SAMPLE_GATE();
+    using F = WaveFft<LGY>;
+    constexpr int n = F::n, P = F::P, S = F::S, hy = n / 2;
+    constexpr int CW = col_waves(static_cast<int>(sizeof(cplx<T>)), LGY);
+    constexpr int per = (hy + 1 + 63) >> 6;
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    cplx<T> *buf = reinterpret_cast<cplx<T> *>(smem_raw);
-    cplx<T> *tw = buf + cw * ny;
+    cplx<T> *tw = reinterpret_cast<cplx<T> *>(smem_raw);
+    unsigned char *regions = smem_raw + sizeof(cplx<T>) * F::tw;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    cplx<T> *buf = reinterpret_cast<cplx<T> *>(regions + static_cast<size_t>(wave) * rs);
+    double *pre = reinterpret_cast<double *>(buf + F::lds);
     const int inst = blockIdx.y;
     const int nh = nx / 2 + 1;
-    const int c0 = blockIdx.x * cw;
-    const int ncol = min(cw, nh - c0);
-    constexpr int bits = LGY;
-    for (int t = threadIdx.x; t < ny; t += blockDim.x) tw[t] = twy[t];
-    const cplx<T> *h = half + (static_cast<int64_t>(inst) * nh + c0) * ny;
-    for (int e = threadIdx.x; e < ncol * ny; e += blockDim.x) buf[e] = h[e];
+    const int cb = blockIdx.x * (CW * S * iters);
+    const cplx<T> *hc = half + static_cast<int64_t>(inst) * nh * n;
+    fill_pass_twiddles<T, LGY>(tw, twy);
+    const int nbj = (nbins + 63) >> 6;
+    double acc[NBJ];
+#pragma unroll
+    for (int j = 0; j < NBJ; ++j) acc[j] = 0.0;
+    cplx<T> nxt[P];
+    load_cols<T, LGY>(nxt, hc, cb + S * wave, nh, lane);
     __syncthreads();
-    fft_stockham<T, LGY>(buf, ncol, tw);
-    // power with the mirror weight, in place (re := |X|^2 w)
-    for (int e = threadIdx.x; e < ncol * ny; e += blockDim.x) {
-        const int kx = c0 + (e >> bits);
-        const T w = (kx == 0 || kx == nx / 2) ? T(1) : T(2);
-        const cplx<T> v = buf[e];
-        buf[e].re = w * (v.re * v.re + v.im * v.im);
-    }
-    __syncthreads();
-    // Per column, P(m) = sum over |ky| <= m of the power (the +ky and -ky modes
-    // together), as an FP64 prefix sum: each wave scans one column at a time,
-    // lane l holding |ky| = l*per .. l*per + per - 1 (fixed order, no atomics).
-    // The column's prefix sums overwrite the column's own storage (the wave has
-    // read all of it into registers first; LDS accesses of a wave are ordered).
-    constexpr int hy = ny / 2;
-    {
-        const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwave = blockDim.x >> 6;
-        constexpr int per = (hy + 1 + 63) >> 6;
-        for (int c = wave; c < ncol; c += nwave) {
-            const T *col = &buf[c * ny].re;
+    for (int it = 0; it < iters; ++it) {
+        const int g = cb + S * (it * CW + wave);
+        if (g >= nh) break;  // wave-uniform; later iterations are further right
+        cplx<T> v[P];
+#pragma unroll
+        for (int j = 0; j < P; ++j) v[j] = nxt[j];
+        if (it + 1 < iters) load_cols<T, LGY>(nxt, hc, g + S * CW, nh, lane);
+        wave_fft<T, LGY, LGY>(v, buf, tw, lane);
+        for (int c = 0; c < S && g + c < nh; ++c) {
+            const int kx = g + c;
+            const T w = (kx == 0 || 2 * kx == nx) ? T(1) : T(2);
+            const cplx<T> *col = buf;
+            const int cbase = c << LGY;
             double loc[per];
             double run = 0.0;
 #pragma unroll
             for (int j = 0; j < per; ++j) {
                 const int m = lane * per + j;
-                double v = 0.0;
+                double e = 0.0;
                 if (m <= hy) {
-                    v = static_cast<double>(col[2 * m]);
-                    if (m != 0 && m != hy) v += static_cast<double>(col[2 * (ny - m)]);
+                    const cplx<T> a = col[pidx(cbase + m)];
+                    e = static_cast<double>(w * (a.re * a.re + a.im * a.im));
+                    if (m != 0 && m != hy) {
+                        const cplx<T> b = col[pidx(cbase + n - m)];
+                        e += static_cast<double>(w * (b.re * b.re + b.im * b.im));
+                    }
                 }
-                run += v;
+                run += e;
                 loc[j] = run;
             }
-            double incl = run;
-            for (int d = 1; d < 64; d <<= 1) {
-                const double o = __shfl_up(incl, d, 64);
-                if (lane >= d) incl += o;
-            }
-            const double excl = incl - run;
-            double *pref = reinterpret_cast<double *>(&buf[c * ny]);
+            const double excl = wave_inclusive_sum(run) - run;
 #pragma unroll
             for (int j = 0; j < per; ++j) {
                 const int m = lane * per + j;
-                if (m <= hy) pref[m] = excl + loc[j];
+                if (m <= hy) pre[m] = excl + loc[j];
             }
+            wave_sync();
+            // shells met by this column: kx .. round(sqrt(kx^2 + hy^2)) (bound by excess)
+            const int jlo = kx >> 6;
+            const int jhi = static_cast<int>(sqrtf(static_cast<float>(kx * kx + hy * hy)) + 1.5f) >> 6;
+#pragma unroll
+            for (int j = 0; j < NBJ; ++j) {
+                const int b = lane + 64 * j;
+                if (j >= jlo && j <= jhi && j < nbj && b < nbins) {
+                    const int m0 = shell_first(kx, b, hy), m1 = shell_first(kx, b + 1, hy);
+                    if (m1 > m0) acc[j] += pre[m1 - 1] - (m0 > 0 ? pre[m0 - 1] : 0.0);
+                }
+            }
+            wave_sync();
         }
+    }
+    __syncthreads();
+    double *mine = reinterpret_cast<double *>(regions + static_cast<size_t>(wave) * rs);
+#pragma unroll
+    for (int j = 0; j < NBJ; ++j) {
+        const int b = lane + 64 * j;
+        if (j < nbj && b < nbins) mine[b] = acc[j];
     }
     __syncthreads();
     double *pp = part + (static_cast<int64_t>(inst) * gridDim.x + blockIdx.x) * nbins;
     for (int b = threadIdx.x; b < nbins; b += blockDim.x) {
-        double acc = 0.0;
-        for (int c = 0; c < ncol; ++c) {
-            const int32_t *lc = lo + static_cast<int64_t>(c0 + c) * (nbins + 1);
-            const int m0 = lc[b], m1 = lc[b + 1];
-            if (m1 > m0) {
-                const double *pc = reinterpret_cast<const double *>(&buf[c * ny]);
-                acc += pc[m1 - 1] - (m0 > 0 ? pc[m0 - 1] : 0.0);
-            }
-        }
-        pp[b] = acc;
+        double s = 0.0;
+        for (int w = 0; w < CW; ++w) s += reinterpret_cast<const double *>(regions + static_cast<size_t>(w) * rs)[b];
+        pp[b] = s;
     }
 }
 
@@ -268,12 +512,7 @@ __global__ void __launch_bounds__(256)
     k_bins_reduce(StepArg sarg, const double *__restrict__ part, int ngroups, int nbins, int n_inst,
                   double *__restrict__ sums, const InstAcc *__restrict__ acc)
 {
-    {
-        int64_t step;
-        int sample;
-        resolve_step(sarg, step, sample);
-        if (!sample) return;  // a non-sample step of a captured graph
-    }
+    SHE_SAMPLE_GATE();
     const int64_t e = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
     if (e >= static_cast<int64_t>(n_inst) * nbins) return;
     const int inst = static_cast<int>(e / nbins), b = static_cast<int>(e - static_cast<int64_t>(inst) * nbins);
@@ -284,46 +523,39 @@ __global__ void __launch_bounds__(256)
     sums[e] += s;
 }
 
-// LDS-fitting shapes: row pairs per block and columns per block; each block
-// transforms at most kPts * 256 points (the registers of one pass).
-void sk2d_shape(int prec, int nx, int ny, int *rp, int *cw)
+// ------------------------------------------------------------------ host side
+
+namespace {
+
+int ilog2(int v)
 {
-    const size_t es = prec == 0 ? 2 * sizeof(float) : 2 * sizeof(double);
-    const size_t budget = 64 * 1024;
-    int r = 1;
-    while (r < 8 && r * 2 <= ny / 2 && 2 * r * nx <= kPts * 256 &&
-           (static_cast<size_t>(2 * r) * nx + nx) * es <= budget)
-        r *= 2;
-    int c = 1;
-    while (c < 64 && c * 2 <= nx / 2 + 1 && 2 * c * ny <= kPts * 256 &&
-           (static_cast<size_t>(2 * c) * ny + ny) * es <= budget)
-        c *= 2;
-    *rp = r;
-    *cw = c;
+    return 31 - __builtin_clz(v);
 }
 
-int sk2d_groups(int prec, int nx, int ny)
+int elem_bytes(int prec)
 {
-    int rp, cw;
-    sk2d_shape(prec, nx, ny, &rp, &cw);
-    return (nx / 2 + 1 + cw - 1) / cw;
+    return prec == 0 ? static_cast<int>(sizeof(cplx<float>)) : static_cast<int>(sizeof(cplx<double>));
 }
 
-// First |ky| of shell b in column kx (b = 0..nbins), clipped to [0, ny/2 + 1]:
-// the smallest m >= 0 with 4 (kx^2 + m^2) >= (2b - 1)^2 (b = 0: m = 0).
-void sk2d_shell_table(int nx, int ny, int nbins, int32_t *lo)
+// column iterations per wave: about 2048 blocks in flight over the batch
+int col_iters(int prec, int nx, int ny, int n_inst)
 {
-    const int nh = nx / 2 + 1, hy = ny / 2;
-    for (int kx = 0; kx < nh; ++kx) {
-        for (int b = 0; b <= nbins; ++b) {
-            int m = 0;
-            if (b > 0) {
-                const long long need = static_cast<long long>(2 * b - 1) * (2 * b - 1) - 4LL * kx * kx;
-                while (m <= hy && 4LL * m * m < need) ++m;
-            }
-            lo[static_cast<int64_t>(kx) * (nbins + 1) + b] = m > hy + 1 ? hy + 1 : m;
-        }
-    }
+    const int nh = nx / 2 + 1;
+    const int per_iter = col_waves(elem_bytes(prec), ilog2(ny)) * wave_seqs(ilog2(ny));
+    const int64_t groups = static_cast<int64_t>((nh + per_iter - 1) / per_iter) * n_inst;
+    int it = 1;
+    while (it < 8 && groups / (2 * it) >= 2048) it *= 2;
+    return it;
+}
+
+}  // namespace
+
+int sk2d_groups(int prec, int nx, int ny, int n_inst)
+{
+    const int nh = nx / 2 + 1;
+    const int per_block =
+        col_waves(elem_bytes(prec), ilog2(ny)) * wave_seqs(ilog2(ny)) * col_iters(prec, nx, ny, n_inst);
+    return (nh + per_block - 1) / per_block;
 }
 
 hipError_t launch_twiddles(int prec, hipStream_t s, int n, void *tw)
@@ -336,79 +568,96 @@ hipError_t launch_twiddles(int prec, hipStream_t s, int n, void *tw)
     return hipGetLastError();
 }
 
-template <typename T, int LGX, int LGY>
-static void sk2d_launch_t(hipStream_t s, const StepArg &sa, dim3 g1, dim3 g2, size_t sm1, size_t sm2, int nx, int ny, int rp, int cw,
-                          int nbins, double u0, const void *field, void *half, const void *twx, const void *twy,
-                          const int32_t *lo, double *part)
-{
-    using C = cplx<T>;
-    hipLaunchKernelGGL((k_fft_rows<T, LGX>), g1, dim3(256), sm1, s, sa, static_cast<const T *>(field), ny, rp, u0,
-                       static_cast<const C *>(twx), static_cast<C *>(half));
-    hipLaunchKernelGGL((k_fft_cols<T, LGY>), g2, dim3(256), sm2, s, sa, static_cast<const C *>(half), nx, cw, nbins,
-                       static_cast<const C *>(twy), lo, part);
-}
+namespace {
 
 template <typename T, int LGX>
-static bool sk2d_launch_y(int lgy, hipStream_t s, const StepArg &sa, dim3 g1, dim3 g2, size_t sm1, size_t sm2, int nx, int ny, int rp,
-                          int cw, int nbins, double u0, const void *field, void *half, const void *twx,
-                          const void *twy, const int32_t *lo, double *part)
+void rows_t(hipStream_t s, const StepArg &sa, int n_inst, int ny, double u0, const void *field, const void *twx,
+            void *half)
 {
-#define SHE_SK_Y(L)                                                                                             \
-    case L:                                                                                                     \
-        sk2d_launch_t<T, LGX, L>(s, sa, g1, g2, sm1, sm2, nx, ny, rp, cw, nbins, u0, field, half, twx, twy, lo, part); \
-        return true;
-    switch (lgy) {
-        SHE_SK_Y(1) SHE_SK_Y(2) SHE_SK_Y(3) SHE_SK_Y(4) SHE_SK_Y(5) SHE_SK_Y(6) SHE_SK_Y(7) SHE_SK_Y(8)
-        SHE_SK_Y(9) SHE_SK_Y(10)
-    default: return false;
-    }
-#undef SHE_SK_Y
+    using F = WaveFft<LGX>;
+    constexpr int W = row_waves<T, LGX>();
+    const int pairs = W * F::S;
+    const dim3 grid((ny / 2 + pairs - 1) / pairs, n_inst);
+    const size_t smem = sizeof(cplx<T>) * (F::tw + static_cast<size_t>(W) * F::lds);
+    static_assert(sizeof(cplx<T>) * (F::tw + W * F::lds) <= kLdsBudget, "row transform exceeds the LDS budget");
+    hipLaunchKernelGGL((k_sk_rows<T, LGX>), grid, dim3(64 * W), smem, s, sa, static_cast<const T *>(field), ny, u0,
+                       static_cast<const cplx<T> *>(twx), static_cast<cplx<T> *>(half));
+}
+
+template <typename T, int LGY>
+bool cols_t(hipStream_t s, const StepArg &sa, int n_inst, int nx, int nbins, const void *half, const void *twy,
+            double *part, int groups, int iters)
+{
+    using F = WaveFft<LGY>;
+    constexpr int CW = col_waves(static_cast<int>(sizeof(cplx<T>)), LGY);
+    size_t rs = col_region(static_cast<int>(sizeof(cplx<T>)), LGY);
+    rs = std::max(rs, sizeof(double) * static_cast<size_t>(nbins));
+    rs = (rs + 15) & ~static_cast<size_t>(15);
+    const size_t smem = sizeof(cplx<T>) * F::tw + CW * rs;
+    if (smem > kLdsBudget) return false;
+    if (nbins <= 64 * (kMaxBinIters / 2))
+        hipLaunchKernelGGL((k_sk_cols<T, LGY, kMaxBinIters / 2>), dim3(groups, n_inst), dim3(64 * CW), smem, s, sa,
+                           static_cast<const cplx<T> *>(half), nx, iters, static_cast<int>(rs), nbins,
+                           static_cast<const cplx<T> *>(twy), part);
+    else
+        hipLaunchKernelGGL((k_sk_cols<T, LGY, kMaxBinIters>), dim3(groups, n_inst), dim3(64 * CW), smem, s, sa,
+                           static_cast<const cplx<T> *>(half), nx, iters, static_cast<int>(rs), nbins,
+                           static_cast<const cplx<T> *>(twy), part);
+    return true;
 }
 
 template <typename T>
-static bool sk2d_launch(int lgx, int lgy, hipStream_t s, const StepArg &sa, dim3 g1, dim3 g2, size_t sm1, size_t sm2, int nx, int ny,
-                        int rp, int cw, int nbins, double u0, const void *field, void *half, const void *twx,
-                        const void *twy, const int32_t *lo, double *part)
+bool rows_dispatch(int lgx, hipStream_t s, const StepArg &sa, int n_inst, int ny, double u0, const void *field,
+                   const void *twx, void *half)
 {
-#define SHE_SK_X(L)                                                                                               \
-    case L:                                                                                                       \
-        return sk2d_launch_y<T, L>(lgy, s, sa, g1, g2, sm1, sm2, nx, ny, rp, cw, nbins, u0, field, half, twx, twy, lo, \
-                                   part);
+#define SHE_ROWS(L)                                                 \
+    case L:                                                         \
+        rows_t<T, L>(s, sa, n_inst, ny, u0, field, twx, half);      \
+        return true;
     switch (lgx) {
-        SHE_SK_X(3) SHE_SK_X(4) SHE_SK_X(5) SHE_SK_X(6) SHE_SK_X(7) SHE_SK_X(8) SHE_SK_X(9) SHE_SK_X(10)
+        SHE_ROWS(3) SHE_ROWS(4) SHE_ROWS(5) SHE_ROWS(6) SHE_ROWS(7) SHE_ROWS(8) SHE_ROWS(9) SHE_ROWS(10)
     default: return false;
     }
-#undef SHE_SK_X
+#undef SHE_ROWS
 }
 
-hipError_t launch_sk2d(int prec, hipStream_t s, const StepArg &sa, int n_inst, int nx, int ny, double u0, const void *field, void *half,
-                       const void *twx, const void *twy, const int32_t *lo, double *part, int nbins, double *sums,
-                       const InstAcc *acc)
+template <typename T>
+bool cols_dispatch(int lgy, hipStream_t s, const StepArg &sa, int n_inst, int nx, int nbins, const void *half,
+                   const void *twy, double *part, int groups, int iters)
 {
-    int rp, cw;
-    sk2d_shape(prec, nx, ny, &rp, &cw);
-    const int nh = nx / 2 + 1;
-    const int ngroups = (nh + cw - 1) / cw;
-    const int lgx = 31 - __builtin_clz(nx), lgy = 31 - __builtin_clz(ny);
-    const dim3 g1((ny / 2 + rp - 1) / rp, n_inst), g2(ngroups, n_inst);
+#define SHE_COLS(L)                                                                      \
+    case L:                                                                              \
+        return cols_t<T, L>(s, sa, n_inst, nx, nbins, half, twy, part, groups, iters);
+    switch (lgy) {
+        SHE_COLS(1) SHE_COLS(2) SHE_COLS(3) SHE_COLS(4) SHE_COLS(5) SHE_COLS(6) SHE_COLS(7) SHE_COLS(8)
+        SHE_COLS(9) SHE_COLS(10)
+    default: return false;
+    }
+#undef SHE_COLS
+}
+
+}  // namespace
+
+hipError_t launch_sk2d(int prec, hipStream_t s, const StepArg &sa, int n_inst, int nx, int ny, double u0,
+                       const void *field, void *half, const void *twx, const void *twy, double *part, int nbins,
+                       double *sums, const InstAcc *acc)
+{
+    if (nbins > 64 * kMaxBinIters) return hipErrorInvalidValue;
+    const int lgx = ilog2(nx), lgy = ilog2(ny);
+    const int iters = col_iters(prec, nx, ny, n_inst);
+    const int groups = sk2d_groups(prec, nx, ny, n_inst);
     bool ok;
     if (prec == 0) {
-        const size_t es = sizeof(cplx<float>);
-        const size_t sm1 = (static_cast<size_t>(rp) * nx + nx) * es;
-        const size_t sm2 = (static_cast<size_t>(cw) * ny + ny) * es;
-        ok = sk2d_launch<float>(lgx, lgy, s, sa, g1, g2, sm1, sm2, nx, ny, rp, cw, nbins, u0, field, half, twx, twy, lo,
-                                part);
+        ok = rows_dispatch<float>(lgx, s, sa, n_inst, ny, u0, field, twx, half) &&
+             cols_dispatch<float>(lgy, s, sa, n_inst, nx, nbins, half, twy, part, groups, iters);
     } else {
-        const size_t es = sizeof(cplx<double>);
-        const size_t sm1 = (static_cast<size_t>(rp) * nx + nx) * es;
-        const size_t sm2 = (static_cast<size_t>(cw) * ny + ny) * es;
-        ok = sk2d_launch<double>(lgx, lgy, s, sa, g1, g2, sm1, sm2, nx, ny, rp, cw, nbins, u0, field, half, twx, twy, lo,
-                                 part);
+        ok = rows_dispatch<double>(lgx, s, sa, n_inst, ny, u0, field, twx, half) &&
+             cols_dispatch<double>(lgy, s, sa, n_inst, nx, nbins, half, twy, part, groups, iters);
     }
     if (!ok) return hipErrorInvalidValue;
     const int64_t tot = static_cast<int64_t>(n_inst) * nbins;
-    hipLaunchKernelGGL(k_bins_reduce, dim3(static_cast<unsigned>((tot + 255) / 256)), dim3(256), 0, s, sa, part, ngroups,
-                       nbins, n_inst, sums, acc);
+    hipLaunchKernelGGL(k_bins_reduce, dim3(static_cast<unsigned>((tot + 255) / 256)), dim3(256), 0, s, sa, part,
+                       groups, nbins, n_inst, sums, acc);
     return hipGetLastError();
 }
 

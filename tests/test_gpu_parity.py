@@ -333,9 +333,16 @@ def test_c3_full_size_sampled_parity(she):
     h.run(20)
     for q in picks:
         got = h.read_field(q)
+        d = oracle_desc(insts[q], 0)
         u = init[q].copy()
-        oracle.advance(oracle_desc(insts[q], 0), u, 0, 20)
+        st = oracle.Stats(d, burn_in=0, every=10, per_cell=False, sk=True) if q == 131 else None
+        oracle.advance(d, u, 0, 20, st)
         assert max_rel(got, u) <= 1e-5
+        if st is not None:   # radial S(k) of the full-size transform (two samples)
+            g = h.stats(q, sk=True)
+            assert g["n_samples"] == st.n_samples == 2
+            ok = g["sk_modes"] > 0
+            assert max_rel(g["sk"][ok], st.structure_factor()[ok]) < 1e-3
     h.close()
 
 
