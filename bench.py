@@ -9,8 +9,9 @@ noise, face fluxes, divergence update, and the sampling on sample steps).
 Inputs are resident in HBM when the timed region starts.
 
 Printed: one JSON line with the throughput, the roofline of the step kernel
-(HIP-event timing of the kernel on its stream, algorithmic bytes 8 B per
-FP32 cell-update), the plain single-realisation rate (one launch per step),
+(HIP-event timing of its back-to-back launches on its stream inside the timed
+region, algorithmic bytes 8 B per FP32 cell-update), the plain
+single-realisation rate (one launch per step),
 the state error against the FP64 oracle on a sampled realisation, and the
 oracle's own rate on the host CPU.
 """
@@ -50,56 +51,35 @@ def make_handle(she, cfg, stats):
                       stats=stats), insts
 
 
-def timed_run_each(torch, h, steps, every):
-    """Wall time of `steps` sampled steps, plus HIP-event time of the step
-    kernel alone: every non-sample step is enqueued by its own call and
-    bracketed by events on the library's stream (torch's current stream);
-    the host runs ahead of the GPU, so the calls do not starve it."""
-    ev = []
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        if (h.steps + 1) % every != 0:
-            a = torch.cuda.Event(enable_timing=True)
-            b = torch.cuda.Event(enable_timing=True)
-            a.record()
-            h.run(1)
-            b.record()
-            ev.append((a, b))
-        else:
-            h.run(1)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    kms = sum(a.elapsed_time(b) for a, b in ev) / max(1, len(ev))
-    return wall, kms, len(ev)
-
-
-def timed_run(torch, h, steps, every):
-    """As timed_run_each, but only one non-sample step per sampling period is
-    bracketed and the rest of the period is enqueued in one call (for the
-    small single-realisation form, whose steps are shorter than a host call)."""
+def timed_region(torch, h, steps, every):
+    """Wall time of `steps` sampled steps (burn-in 0) and the HIP-event time of
+    the step kernel inside them: each sampling period's run of back-to-back
+    non-sample steps is one call bracketed by events on the library's stream
+    (torch's current stream); the sample step follows unbracketed.  Returns
+    (wall seconds, kernel ms per launch, launches timed)."""
     ev = []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     done = 0
     while done < steps:
-        t = h.steps + 1
-        if t % every != 0 and steps - done >= 1:
+        r = (every - h.steps % every) % every      # steps until the next sample step completes
+        plain = min(steps - done, (r if r > 0 else every) - 1)
+        if plain > 0:
             a = torch.cuda.Event(enable_timing=True)
             b = torch.cuda.Event(enable_timing=True)
             a.record()
-            h.run(1)
+            h.run(plain)
             b.record()
-            ev.append((a, b))
+            ev.append((a, b, plain))
+            done += plain
+        if done < steps:
+            h.run(1)
             done += 1
-        rest = min(steps - done, every - (h.steps % every)) if every > 1 else steps - done
-        if rest > 0:
-            h.run(rest)
-            done += rest
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    kms = sum(a.elapsed_time(b) for a, b in ev) / max(1, len(ev))
-    return wall, kms, len(ev)
+    n = sum(k for _, _, k in ev)
+    kms = sum(a.elapsed_time(b) for a, b, _ in ev) / max(1, n)
+    return wall, kms, n
 
 
 def state_error(she, torch, cfg, realisation, steps):
@@ -190,7 +170,7 @@ def main():
     cells = sum(i.ncells for i in insts)
     h.run(args.warmup)
     torch.cuda.synchronize()
-    wall, kms, nev = timed_run_each(torch, h, args.steps, every)
+    wall, kms, nev = timed_region(torch, h, args.steps, every)
     st0 = h.stats(0)
     h.close()
     value = cells * args.steps / wall
@@ -216,7 +196,7 @@ def main():
         ph, pinsts = make_handle(she, pcfg, she.STAT_SPATIAL | she.STAT_SK)
         ph.run(args.warmup)
         psteps = max(200, args.steps // 2)
-        pwall, pkms, _ = timed_run(torch, ph, psteps, every)
+        pwall, pkms, _ = timed_region(torch, ph, psteps, every)
         ph.close()
         out["plain"] = {"value": pinsts[0].ncells * psteps / pwall, "ms_per_step": pwall / psteps * 1e3,
                         "kernel_ms": pkms, "form": "1 realisation, one kernel launch per step, no graph"}
