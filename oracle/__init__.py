@@ -61,7 +61,8 @@ class _Stats(C.Structure):
                 ("n_bins", C.c_int32), ("pad_", C.c_int32),
                 ("sp_mean", C.c_double), ("sp_sq", C.c_double), ("sp_var", C.c_double),
                 ("clamp_count", C.c_int64), ("nonfinite", C.c_int32), ("pad2_", C.c_int32),
-                ("nonfinite_step", C.c_int64)]
+                ("nonfinite_step", C.c_int64), ("tc_lags", C.c_int64),
+                ("tc", C.POINTER(C.c_double)), ("tc_hist", C.POINTER(C.c_double))]
 
 
 def _load():
@@ -179,6 +180,7 @@ class Stats:
     per_cell: bool = True
     corr: bool = False
     sk: bool = False
+    tcorr_lags: int = 0
     _c: _Stats = field(default=None, repr=False)
 
     def __post_init__(self):
@@ -192,12 +194,18 @@ class Stats:
         else:
             self.nb, self.sk_sum = 0, None
         null = C.POINTER(C.c_double)()
+        L = int(self.tcorr_lags)
+        if L and self.d.dim != 1:
+            raise ValueError("the time correlation is 1D")
+        self.tc = np.zeros((L, nc)) if L else None
+        self.tc_hist = np.zeros((L, nc)) if L else None
         self._c = _Stats(self.burn_in, self.every, 0,
                          _dptr(self.s1) if self.per_cell else null,
                          _dptr(self.s2) if self.per_cell else null,
                          _dptr(self.m2) if self.corr else null,
                          _dptr(self.sk_sum) if self.sk else null,
-                         self.nb, 0, 0.0, 0.0, 0.0, 0, 0, 0, 0)
+                         self.nb, 0, 0.0, 0.0, 0.0, 0, 0, 0, 0, L,
+                         _dptr(self.tc) if L else null, _dptr(self.tc_hist) if L else null)
 
     @property
     def n_samples(self) -> int:
@@ -229,6 +237,18 @@ class Stats:
         modes = bin_modes(self.d)
         with np.errstate(invalid="ignore", divide="ignore"):
             return self.sk_sum / (self.n_samples * modes)
+
+    def time_corr(self) -> np.ndarray:
+        """(L, N): C_i(m) = <d_i(n) d_i(n-m)> - mu_i^2 over the sample pairs
+        n >= m (lag m in sampling intervals), mu_i the time mean of d_i;
+        NaN where fewer than m + 1 samples were taken."""
+        M = self.n_samples
+        mu = self.s1 / M
+        out = np.full(self.tc.shape, np.nan)
+        for m in range(self.tc.shape[0]):
+            if M > m:
+                out[m] = self.tc[m] / (M - m) - mu * mu
+        return out
 
     def spatial(self):
         """(mean of spatial-mean delta, mean of spatial-mean delta^2, mean spatial variance)."""

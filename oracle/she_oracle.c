@@ -23,7 +23,10 @@
  *     sigma*sqrt(n_face)*N with sigma = sqrt(2 r / dV);
  *   - time averages after a relaxation period (Sec. 3, time-average formula),
  *     variance, two-point correlation, and the structure factor
- *     S_k = <|sum_j T_j exp(-2 pi i j k/N)|^2> (Sec. 3, structure factor).
+ *     S_k = <|sum_j T_j exp(-2 pi i j k/N)|^2> (Sec. 3, structure factor);
+ *   - 1D time correlation <dT_i^n dT_i^(n-m)> over sample lags m (the first
+ *     of the suggested exercises, Sec. 6): sums over samples n >= m of
+ *     delta_i(n) delta_i(n-m), with the last L samples kept in a ring.
  *
  * Gaussian numbers: Philox4x32-10 (Salmon, Moraes, Dror, Shaw, "Parallel
  * random numbers: as easy as 1, 2, 3", SC'11) and the Box-Muller transform
@@ -87,6 +90,9 @@ typedef struct {
     int32_t nonfinite;
     int32_t pad2_;
     int64_t nonfinite_step;
+    int64_t tc_lags;     /* 1D: lags L of the time correlation (0 = off)      */
+    double *tc;          /* L*N sums over samples n >= m of d_i(n) d_i(n-m)   */
+    double *tc_hist;     /* L*N ring of the last L samples' delta             */
 } or_stats;
 
 /* ---------------------------------------------------------------- Philox */
@@ -438,6 +444,16 @@ static int take_sample(const or_desc *d, const double *u, const double *ref,
         for (int64_t i = 0; i < nc; ++i)
             for (int64_t j = 0; j < nc; ++j)
                 st->m2[i * nc + j] += (u[i] - ref[i]) * (u[j] - ref[j]);
+    }
+    if (st->tc && st->tc_lags > 0 && d->dim == 1) {
+        /* this sample is number n; sample n - m sits in ring slot (n - m) mod L */
+        const int64_t L = st->tc_lags, n = st->n_samples;
+        double *now = st->tc_hist + (n % L) * nc;
+        for (int64_t i = 0; i < nc; ++i) now[i] = u[i] - ref[i];
+        for (int64_t m = 0; m < L && m <= n; ++m) {
+            const double *past = st->tc_hist + ((n - m) % L) * nc;
+            for (int64_t i = 0; i < nc; ++i) st->tc[m * nc + i] += now[i] * past[i];
+        }
     }
     if (st->sk) {
         double *re = (double *)calloc((size_t)nc, sizeof(double));

@@ -207,3 +207,77 @@ def test_garcia_long_range_correlation_is_the_scheme_limit():
     far = np.abs(np.subtract.outer(np.arange(N), np.arange(N))) >= 4
     assert np.max(np.abs(S[far] - want[far])) < 0.05 * amp
     np.testing.assert_allclose(np.diag(S), np.diag(want), rtol=0.05)
+
+
+# ---------------------------------------------------------------- time correlation
+
+def test_time_correlation_estimator_matches_numpy():
+    N = 12
+    d = oracle.Desc(dim=1, n=(N, 1, 1), r=0.2, sigma=0.3, u0=1.0, init_sd=0.2, seed=4)
+    u = oracle.init(d)
+    st = oracle.Stats(d, burn_in=3, every=2, tcorr_lags=6)
+    traj = []
+    for t in range(60):
+        oracle.advance(d, u, t, 1, st)
+        if t + 1 > 3 and (t + 1) % 2 == 0:
+            traj.append(u.copy() - 1.0)
+    X = np.array(traj)
+    mu = X.mean(0)
+    got = st.time_corr()
+    for m in range(6):
+        want = (X[m:] * X[:len(X) - m]).mean(0) - mu * mu
+        np.testing.assert_allclose(got[m], want, atol=1e-14)
+
+
+@pytest.mark.parametrize("scheme", [0, 1])
+def test_time_correlation_of_a_decaying_mode(scheme):
+    """Noise off, one Fourier mode a cos(2 pi k (i+1/2)/N): the state after t
+    steps is the mode times G^t (G = g for FE, (1+g^2)/2 for PC, g = 1 - x_k),
+    so the lag sums are geometric series in closed form."""
+    N, r, k0, a, every, burn = 16, 0.15, 3, 0.4, 3, 7
+    d = oracle.Desc(dim=1, n=(N, 1, 1), r=r, sigma=0.0, u0=2.0, noise=2, scheme=scheme, seed=1)
+    c = np.cos(2 * np.pi * k0 * (np.arange(N) + 0.5) / N)
+    u = 2.0 + a * c
+    L, steps = 9, 200
+    st = oracle.Stats(d, burn_in=burn, every=every, tcorr_lags=L)
+    oracle.advance(d, u, 0, steps, st)
+    g = 1 - 4 * r * np.sin(np.pi * k0 / N) ** 2
+    G = g if scheme == 0 else 0.5 * (1 + g * g)
+    t_first = (burn // every + 1) * every          # first sample step
+    M = st.n_samples
+    assert M == (steps - t_first) // every + 1
+    for m in range(L):
+        # sum_{n=m}^{M-1} G^(t_n + t_(n-m)), t_n = t_first + n every
+        geo = sum(G ** (2 * t_first + (2 * n - m) * every) for n in range(m, M))
+        np.testing.assert_allclose(st.tc[m], a * a * c * c * geo, rtol=1e-10, atol=1e-300)
+
+
+@pytest.mark.parametrize("case", ["fe_instantaneous", "pc_frozen"])
+def test_time_correlation_closed_form(case):
+    """Periodic stationary state: <dU_i^(n+m) dU_i^n> = (1/N^2) sum_{k != 0}
+    G_k^m S_k.  The lag-m map of mode k is G_k^m and the noise of later steps
+    is uncorrelated with the earlier state (exact for FE also with the
+    state-dependent face amplitude, and for additive PC)."""
+    N, r, L = 16, 0.2, 24
+    if case == "fe_instantaneous":
+        eps, noise, scheme = 0.1, 0, 0
+    else:
+        eps, noise, scheme = 0.01, 1, 1
+    d = oracle.Desc(dim=1, n=(N, 1, 1), r=r, sigma=oracle.sigma_of(r, eps), u0=1.0, noise=noise,
+                    scheme=scheme, init_sd=np.sqrt(eps), seed=51)
+    sts = batch_run(d, 20, 20000, 2000, tcorr_lags=L)
+    m0 = batch_run.mean0
+    tc, se = mean_se([s.time_corr().mean(axis=1) for s in sts])
+    x = theory.mode_x(r, (N,))
+    g = 1 - x
+    if scheme == 0:
+        G, sk = g, theory.sk_periodic(r, (N,), theory.qbar_she_fe(eps, m0, r, (N,)), "fe")
+    else:
+        G, sk = 0.5 * (1 + g * g), theory.sk_periodic(r, (N,), eps * 1.0, "pc")
+    k = np.arange(1, N)
+    want = np.array([np.sum(G[k] ** m * sk[k]) / N ** 2 for m in range(L)])
+    z = (tc - want) / se
+    assert np.max(np.abs(z)) < 4.5, z
+    assert np.max(np.abs(tc[:8] / want[:8] - 1)) < 0.05
+    # the correlation decays: lag 23 keeps well under half of lag 0
+    assert want[L - 1] < 0.5 * want[0]
