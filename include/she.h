@@ -78,7 +78,10 @@ enum {
     SHE_STAT_CORR = 2,     /* 1D: full N x N covariance (MFMA X^T X blocks)   */
     SHE_STAT_SK = 4,       /* nD: radially binned S(k) (FFT per sample);
                               1D: S_k comes from the covariance (needs CORR)  */
-    SHE_STAT_SPATIAL = 8   /* per-instance spatial mean / variance per sample */
+    SHE_STAT_SPATIAL = 8,  /* per-instance spatial mean / variance per sample */
+    SHE_STAT_TCORR = 16    /* 1D: time correlation <dU_i^n dU_i^(n-m)> over
+                              sample lags m < tcorr_lags (first suggested
+                              exercise, Sec. 6); implies MOMENTS             */
 };
 
 /* she_config.tuning_flags: launch-order choices (results are identical) */
@@ -131,7 +134,8 @@ typedef struct {
                                      multiple of 2, and of sample_every for
                                      she_run); 0 launches every step directly.
                                      Results are identical.  Ignored in 1D.  */
-    int32_t reserved;             /* must be 0                                */
+    int32_t tcorr_lags;           /* TCORR: lags L in sampling intervals,
+                                     1..1024 (0 without TCORR)               */
     void *stream;                 /* hipStream_t (e.g. torch's current stream)*/
     void *arena;                  /* optional device memory for all buffers   */
     size_t arena_bytes;
@@ -155,6 +159,12 @@ typedef struct {
     int32_t nonfinite;            /* 1 if a sample met a non-finite value      */
     int32_t reserved;
     int64_t clamp_count;          /* DK: face evaluations with negative mean  */
+    double *tcorr;  int64_t tcorr_cap; /* 1D + TCORR: L*N values [m][i],
+                                          C_i(m) = S_i(m)/(M-m) - mu_i^2 with
+                                          S_i(m) the sum over sample pairs
+                                          (n, n-m) of dU_i(n) dU_i(n-m),
+                                          mu_i = S1_i/M, M samples; NaN for
+                                          m >= M                              */
 } she_stats_out;
 
 /* Validate cfg, allocate device buffers, write the initial state (steady

@@ -49,6 +49,13 @@ struct she_handle {
     double *d_c = nullptr;
     int64_t x_elems = 0, c_elems = 0;
     int block1d = 64, maxg = 1, nmax = 0;
+    // time correlation: history ring of hist_rows sample rows, L x N lag sums
+    int tc_lags = 0;
+    int32_t hist_rows = 0;
+    int64_t tc_samples = 0;       // samples taken (equal on every instance still sampling)
+    void *d_hist = nullptr;
+    double *d_tc = nullptr;
+    int64_t hist_elems = 0, tc_elems = 0;
     size_t smem1d = 0;
 
     // 2D / 3D
@@ -134,8 +141,14 @@ she_status validate(const she_config *cfg, she_handle *h)
     if (cfg->tuning_flags & ~SHE_TUNE_XCD_ORDER) return fail(nullptr, SHE_EINVAL, "unknown tuning_flags bits");
     if (cfg->graph_steps < 0 || cfg->graph_steps > (1 << 16))
         return fail(nullptr, SHE_EINVAL, "graph_steps must be in [0, 65536]");
-    if (cfg->reserved != 0) return fail(nullptr, SHE_EINVAL, "reserved must be 0");
-    if (cfg->stats_mask & ~0xFu) return fail(nullptr, SHE_EINVAL, "unknown stats_mask bits");
+    if (cfg->stats_mask & ~0x1Fu) return fail(nullptr, SHE_EINVAL, "unknown stats_mask bits");
+    if (cfg->stats_mask & SHE_STAT_TCORR) {
+        if (cfg->inst[0].dim != 1) return fail(nullptr, SHE_EUNSUPPORTED, "SHE_STAT_TCORR is provided for 1D");
+        if (cfg->tcorr_lags < 1 || cfg->tcorr_lags > 1024)
+            return fail(nullptr, SHE_EINVAL, "tcorr_lags must be in [1, 1024] with SHE_STAT_TCORR");
+    } else if (cfg->tcorr_lags != 0) {
+        return fail(nullptr, SHE_EINVAL, "tcorr_lags must be 0 without SHE_STAT_TCORR");
+    }
     const int dim = cfg->inst[0].dim;
     for (int i = 0; i < cfg->n_instances; ++i) {
         const she_instance_desc &d = cfg->inst[i];
@@ -180,6 +193,17 @@ static she_status plan_1d(she_handle *h, const she_config *cfg, Plan &plan)
     int64_t off = 0, xo = 0, co = 0;
     int nfg_max = 0;
     const bool corr = (h->mask & SHE_STAT_CORR) != 0;
+    const bool tcorr = (h->mask & SHE_STAT_TCORR) != 0;
+    int64_t cells = 0;
+    for (int i = 0; i < h->n_inst; ++i) cells += h->inst[i].n[0];
+    if (tcorr) {
+        // samples per launch: up to 4096, fewer for large batches (ring <= ~4 Mi
+        // cells x samples), plus the L - 1 older rows the lags reach back to
+        h->tc_lags = cfg->tcorr_lags;
+        const int64_t per = std::max<int64_t>(64, std::min<int64_t>(4096, (int64_t(1) << 22) / std::max<int64_t>(1, cells)));
+        h->hist_rows = static_cast<int32_t>(per + h->tc_lags);
+    }
+    int64_t ho = 0, to = 0;
     for (int i = 0; i < h->n_inst; ++i) {
         const she_instance_desc &d = h->inst[i];
         Inst1D &t = h->tab[i];
@@ -206,6 +230,15 @@ static she_status plan_1d(she_handle *h, const she_config *cfg, Plan &plan)
             t.x_off = -1;
             t.c_off = -1;
         }
+        if (tcorr) {
+            t.h_off = ho;
+            t.tc_off = to;
+            ho += static_cast<int64_t>(h->hist_rows) * d.n[0];
+            to += static_cast<int64_t>(h->tc_lags) * d.n[0];
+        } else {
+            t.h_off = -1;
+            t.tc_off = -1;
+        }
         off += d.n[0];
         h->nmax = std::max(h->nmax, d.n[0]);
         const int nf = d.bc == SHE_DIRICHLET ? d.n[0] + 1 : d.n[0];
@@ -214,6 +247,8 @@ static she_status plan_1d(she_handle *h, const she_config *cfg, Plan &plan)
     h->total_cells = off;
     h->x_elems = xo;
     h->c_elems = co;
+    h->hist_elems = ho;
+    h->tc_elems = to;
     // launch shape: threads per instance and Philox blocks per thread
     int block = cfg->block_threads;
     if (block == 0) block = nfg_max <= 128 ? 64 : 256;
@@ -232,7 +267,7 @@ static she_status plan_1d(she_handle *h, const she_config *cfg, Plan &plan)
     plan.add(reinterpret_cast<void **>(&h->d_tab), sizeof(Inst1D) * h->n_inst);
     plan.add(reinterpret_cast<void **>(&h->d_order), sizeof(int32_t) * h->n_inst);
     plan.add(&h->d_pool, es * off);
-    if (h->mask & (SHE_STAT_MOMENTS | SHE_STAT_CORR)) {
+    if (h->mask & (SHE_STAT_MOMENTS | SHE_STAT_CORR | SHE_STAT_TCORR)) {
         plan.add(reinterpret_cast<void **>(&h->d_s1), sizeof(double) * off);
         plan.add(reinterpret_cast<void **>(&h->d_s2), sizeof(double) * off);
     }
@@ -240,7 +275,12 @@ static she_status plan_1d(she_handle *h, const she_config *cfg, Plan &plan)
         plan.add(&h->d_x, es * xo);
         plan.add(reinterpret_cast<void **>(&h->d_c), sizeof(double) * co);
     }
-    h->fin_len = 4 * static_cast<size_t>(h->nmax) + 2 * static_cast<size_t>(h->nmax) * h->nmax + 8;
+    if (tcorr) {
+        plan.add(&h->d_hist, es * ho);
+        plan.add(reinterpret_cast<void **>(&h->d_tc), sizeof(double) * to);
+    }
+    h->fin_len = 4 * static_cast<size_t>(h->nmax) + 2 * static_cast<size_t>(h->nmax) * h->nmax + 8 +
+                 static_cast<size_t>(h->tc_lags) * h->nmax;
     return SHE_OK;
 }
 
@@ -364,7 +404,7 @@ static she_status build_plan(she_handle *h, const she_config *cfg, Plan &plan)
     h->burn_in = cfg->burn_in;
     h->every = cfg->sample_every;
     h->mask = cfg->stats_mask;
-    if (h->mask & SHE_STAT_CORR) h->mask |= SHE_STAT_MOMENTS;
+    if (h->mask & (SHE_STAT_CORR | SHE_STAT_TCORR)) h->mask |= SHE_STAT_MOMENTS;
     h->stream = static_cast<hipStream_t>(cfg->stream);
     she_status st = h->dim == 1 ? plan_1d(h, cfg, plan) : plan_nd(h, cfg, plan);
     if (st != SHE_OK) return st;
@@ -396,6 +436,8 @@ static she_status zero_stats(she_handle *h)
     if (h->d_x) SHE_HIP(h, hipMemsetAsync(h->d_x, 0, h->esz * h->x_elems, s));
     if (h->d_c) SHE_HIP(h, hipMemsetAsync(h->d_c, 0, sizeof(double) * h->c_elems, s));
     if (h->d_sksum) SHE_HIP(h, hipMemsetAsync(h->d_sksum, 0, sizeof(double) * h->n_inst * h->nbins, s));
+    if (h->d_tc) SHE_HIP(h, hipMemsetAsync(h->d_tc, 0, sizeof(double) * h->tc_elems, s));
+    h->tc_samples = 0;
     return SHE_OK;
 }
 
@@ -580,13 +622,33 @@ static she_status advance(she_handle *h, int64_t nsteps, bool sampling)
     if (nsteps == 0) return SHE_OK;
     hipStream_t s = h->stream;
     if (h->dim == 1) {
-        Stats1D st{h->d_s1, h->d_s2, h->d_x, h->d_c, h->d_acc};
+        Stats1D st{h->d_s1, h->d_s2, h->d_x, h->d_c, h->d_acc, h->d_hist, h->hist_rows, 0};
         const bool stats = sampling && h->mask != 0;
+        const bool tc = stats && (h->mask & SHE_STAT_TCORR);
         const int64_t chunk = 1 << 16;
+        // samples taken after completed steps (0, T]: multiples of `every` above burn_in
+        auto sampled_by = [&](int64_t T) -> int64_t {
+            return T > h->burn_in ? T / h->every - h->burn_in / h->every : 0;
+        };
         for (int64_t done = 0; done < nsteps;) {
-            const int32_t k = static_cast<int32_t>(std::min<int64_t>(chunk, nsteps - done));
+            int64_t k = std::min<int64_t>(chunk, nsteps - done);
+            if (tc) {
+                // at most hist_rows - L new samples per launch, so the ring still
+                // holds the older rows the lags of the new ones reach
+                const int64_t room = h->hist_rows - h->tc_lags;
+                const int64_t j0 = std::max(h->steps, h->burn_in) / h->every;
+                k = std::min<int64_t>(k, h->every * (j0 + room + 1) - 1 - h->steps);
+            }
             SHE_HIP(h, launch_step1d(h->prec, h->block1d, h->maxg, stats, h->n_inst, h->smem1d, s, h->d_tab,
-                                     h->d_order, h->d_pool, h->steps, k, h->burn_in, h->every, h->mask, st));
+                                     h->d_order, h->d_pool, h->steps, static_cast<int32_t>(k), h->burn_in, h->every,
+                                     h->mask, st));
+            if (tc) {
+                const int64_t cnt = sampled_by(h->steps + k) - sampled_by(h->steps);
+                if (cnt > 0)
+                    SHE_HIP(h, launch_tcorr1d(h->prec, h->n_inst, h->nmax, h->tc_lags, s, h->d_tab, h->d_hist,
+                                              h->hist_rows, h->tc_samples, cnt, h->d_tc, h->d_acc));
+                h->tc_samples += cnt;
+            }
             h->steps += k;
             done += k;
         }
@@ -691,6 +753,15 @@ extern "C" she_status she_stats(she_handle *h, int32_t instance, she_stats_out *
         if ((st = copy_out(h, out->corr, out->corr_cap, host.data() + 2 * N, nn, "corr")) != SHE_OK) return st;
         if ((st = copy_out(h, out->sk, out->sk_cap, host.data() + 2 * N + nn, N, "sk")) != SHE_OK) return st;
         out->sum_u = host[3 * N + 2 * nn];
+        if (out->tcorr) {
+            if (!h->d_tc) return fail(h, SHE_EINVAL, "tcorr needs SHE_STAT_TCORR");
+            const int64_t ln = static_cast<int64_t>(h->tc_lags) * N;
+            if (out->tcorr_cap < ln) return fail(h, SHE_EINVAL, "capacity too small for tcorr");
+            SHE_HIP(h, launch_fin_tc(s, N, h->tc_lags, h->d_s1 + h->tab[instance].off, h->d_tc + h->tab[instance].tc_off,
+                                     acc.n_samples, h->d_fin));
+            SHE_HIP(h, hipMemcpyAsync(out->tcorr, h->d_fin, sizeof(double) * ln, hipMemcpyDeviceToHost, s));
+            SHE_HIP(h, hipStreamSynchronize(s));
+        }
     } else {
         SHE_HIP(h, launch_finnd(h->prec, s, h->pnd, instance, h->cells, h->field(), h->d_acc, h->d_sksum,
                                 h->d_skmodes, h->nbins, h->d_fin));
@@ -700,7 +771,7 @@ extern "C" she_status she_stats(she_handle *h, int32_t instance, she_stats_out *
         she_status st;
         if ((st = copy_out(h, out->mean, out->mean_cap, host.data(), 1, "mean")) != SHE_OK) return st;
         if ((st = copy_out(h, out->var, out->var_cap, host.data() + 1, 1, "var")) != SHE_OK) return st;
-        if (out->corr) return fail(h, SHE_EINVAL, "corr is 1D only");
+        if (out->corr || out->tcorr) return fail(h, SHE_EINVAL, "corr / tcorr are 1D only");
         if ((out->sk || out->sk_modes) && h->nbins == 0) return fail(h, SHE_EINVAL, "sk needs SHE_STAT_SK (2D)");
         if ((st = copy_out(h, out->sk, out->sk_cap, host.data() + 3, h->nbins, "sk")) != SHE_OK) return st;
         if ((st = copy_out(h, out->sk_modes, out->sk_modes_cap, h->skmodes.data(), h->nbins, "sk_modes")) != SHE_OK)
@@ -764,6 +835,7 @@ struct Blob {
     int64_t steps;
     int64_t dim, prec, n_inst, cells, x_elems, c_elems, stat_cells;
     int64_t cur;
+    int64_t hist_elems, tc_elems, tc_samples;
 };
 constexpr uint64_t kMagic = 0x3153544b50454853ull;  // "SHEPKTS1"
 
@@ -781,6 +853,8 @@ std::vector<Section> sections(const she_handle *h)
         if (h->d_s2) v.push_back({h->d_s2, sizeof(double) * h->total_cells});
         if (h->d_x) v.push_back({h->d_x, h->esz * h->x_elems});
         if (h->d_c) v.push_back({h->d_c, sizeof(double) * h->c_elems});
+        if (h->d_hist) v.push_back({h->d_hist, h->esz * h->hist_elems});
+        if (h->d_tc) v.push_back({h->d_tc, sizeof(double) * h->tc_elems});
     } else {
         v.push_back({h->field(), h->esz * h->cells * h->n_inst});
         if (h->d_sksum) v.push_back({h->d_sksum, sizeof(double) * h->n_inst * h->nbins});
@@ -793,7 +867,7 @@ Blob header(const she_handle *h)
 {
     Blob b{};
     b.magic = kMagic;
-    b.version = 1;
+    b.version = 2;
     b.steps = h->steps;
     b.dim = h->dim;
     b.prec = h->prec;
@@ -803,6 +877,9 @@ Blob header(const she_handle *h)
     b.c_elems = h->c_elems;
     b.stat_cells = h->d_s1 ? h->total_cells : 0;
     b.cur = 0;
+    b.hist_elems = h->hist_elems;
+    b.tc_elems = h->tc_elems;
+    b.tc_samples = h->tc_samples;
     return b;
 }
 }  // namespace
@@ -843,9 +920,10 @@ extern "C" she_status she_set_state(she_handle *h, const void *host, size_t byte
     Blob b;
     std::memcpy(&b, host, sizeof b);
     Blob mine = header(h);
-    if (b.magic != kMagic || b.version != 1 || b.dim != mine.dim || b.prec != mine.prec ||
+    if (b.magic != kMagic || b.version != 2 || b.dim != mine.dim || b.prec != mine.prec ||
         b.n_inst != mine.n_inst || b.cells != mine.cells || b.x_elems != mine.x_elems ||
-        b.c_elems != mine.c_elems || b.stat_cells != mine.stat_cells)
+        b.c_elems != mine.c_elems || b.stat_cells != mine.stat_cells || b.hist_elems != mine.hist_elems ||
+        b.tc_elems != mine.tc_elems)
         return fail(h, SHE_ESTATE, "checkpoint does not match this handle's layout");
     const char *p = static_cast<const char *>(host) + sizeof b;
     if (h->dim > 1) h->cur = static_cast<int>(b.steps & 1);  // the buffer a step from b.steps reads
@@ -855,6 +933,7 @@ extern "C" she_status she_set_state(she_handle *h, const void *host, size_t byte
     }
     SHE_HIP(h, hipStreamSynchronize(h->stream));
     h->steps = b.steps;
+    h->tc_samples = b.tc_samples;
     return SHE_OK;
 }
 

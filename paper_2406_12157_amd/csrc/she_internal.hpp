@@ -13,6 +13,8 @@ struct Inst1D {
     int64_t off;        // first cell in the state pool / per-cell statistics
     int64_t x_off;      // first element of this instance's 256 x N X block, -1: none
     int64_t c_off;      // first element of this instance's N x N FP64 sum, -1: none
+    int64_t h_off;      // first element of this instance's sample history ring, -1: none
+    int64_t tc_off;     // first element of this instance's L x N FP64 lag sums, -1: none
     int32_t n;          // cells
     int32_t bc;         // 0 periodic, 1 Dirichlet
     int32_t scheme;     // 0 FE, 1 PC
@@ -42,6 +44,9 @@ struct Stats1D {
     void *xblk;         // X blocks (state type), 256 x N per instance
     double *c;          // N x N per instance
     InstAcc *acc;       // per instance
+    void *hist;         // sample history rings (state type), hist_rows x N per instance
+    int32_t hist_rows;
+    int32_t pad;
 };
 
 // Parameters of a homogeneous 2D/3D batch.
@@ -123,6 +128,16 @@ hipError_t launch_initnd(int prec, hipStream_t s, const ParamsND &p, int64_t cel
 hipError_t launch_finnd(int prec, hipStream_t s, const ParamsND &p, int inst, int64_t cells,
                         const void *field, const InstAcc *acc, const double *sk_sums,
                         const double *sk_modes, int nbins, double *out);
+
+// 1D time correlation: lag sums tc[m][i] += sum over the samples n in
+// [n0, min(n0 + count, n_samples)) with n >= m of h[n][i] h[n-m][i] (FP64),
+// rows of the history ring h taken mod hist_rows.
+hipError_t launch_tcorr1d(int prec, int n_inst, int nmax, int lags, hipStream_t s, const Inst1D *tab,
+                          const void *hist, int32_t hist_rows, int64_t n0, int64_t count, double *tc,
+                          const InstAcc *acc);
+// C_i(m) = tc[m][i]/(M-m) - (s1[i]/M)^2 (NaN for m >= M) of one instance into out[L*N].
+hipError_t launch_fin_tc(hipStream_t s, int n, int lags, const double *s1, const double *tc, int64_t M,
+                         double *out);
 
 // Verification: raw Philox words / face normals on the device.
 hipError_t launch_debug_philox(hipStream_t s, uint64_t seed, const uint32_t *ctr, int64_t count,

@@ -18,7 +18,9 @@
 // and (optionally) the shifted state written as one row of a 256-row X block;
 // a full block is contracted on the matrix cores, C += X^T X, with
 // v_mfma_f32_16x16x4f32 (FP32 state) or v_mfma_f64_16x16x4f64 (FP64 state),
-// and added to the FP64 N x N sum.
+// and added to the FP64 N x N sum.  For the time correlation each sample row
+// also goes to a per-instance history ring; after the launch, k_tcorr adds the
+// lag products of the new rows (one thread per cell and lag, FP64).
 #include "she_internal.hpp"
 #include "she_rng.hpp"
 
@@ -135,6 +137,7 @@ __global__ void __launch_bounds__(BLOCK)
     double s1[MAXG][4], s2[MAXG][4];
     const bool moments = STATS && (mask & 1u) && st.s1 != nullptr;
     const bool corr = STATS && (mask & 2u) && d.x_off >= 0;
+    const bool tcorr = STATS && (mask & 16u) && d.h_off >= 0;
     int64_t nsamp = STATS ? acc->n_samples : 0;
 #pragma unroll
     for (int s = 0; s < MAXG; ++s)
@@ -227,6 +230,7 @@ __global__ void __launch_bounds__(BLOCK)
                 int bad = 0;
                 const int row = static_cast<int>(nsamp % kCorrBlock);
                 T *X = corr ? static_cast<T *>(st.xblk) + d.x_off : nullptr;
+                T *Hrow = tcorr ? static_cast<T *>(st.hist) + d.h_off + (nsamp % st.hist_rows) * N : nullptr;
 #pragma unroll
                 for (int s = 0; s < MAXG; ++s)
 #pragma unroll
@@ -242,6 +246,7 @@ __global__ void __launch_bounds__(BLOCK)
                             a += del;
                             b += del * del;
                             if (corr) X[(int64_t)row * N + i] = static_cast<T>(del);
+                            if (tcorr) Hrow[i] = static_cast<T>(del);
                         }
                     }
                 // workgroup reduction (fixed order)
@@ -312,6 +317,75 @@ __global__ void __launch_bounds__(BLOCK)
                               static_cast<unsigned long long>(clamps));
         if (tid == 0) acc->n_samples = nsamp;
     }
+}
+
+// ------------------------------------------------------------------ time correlation
+
+// grid: (ceil(nmax L / 256), n_inst); thread (m, i) with i fastest, so the
+// ring rows are read coalesced.  Sample n sits in ring row n mod hist_rows;
+// the host keeps each launch's new samples plus L - 1 older ones in the ring.
+template <typename T>
+__global__ void __launch_bounds__(256)
+    k_tcorr(const Inst1D *__restrict__ tab, const T *__restrict__ hist, int32_t hist_rows, int32_t lags, int64_t n0,
+            int64_t count, double *__restrict__ tc, const InstAcc *__restrict__ acc)
+{
+    const int inst = blockIdx.y;
+    const Inst1D d = tab[inst];
+    if (d.h_off < 0) return;
+    const int N = d.n;
+    const int64_t e = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
+    if (e >= static_cast<int64_t>(N) * lags) return;
+    const int i = static_cast<int>(e % N), m = static_cast<int>(e / N);
+    const int64_t n1 = min(n0 + count, acc[inst].n_samples);  // a frozen instance stopped sampling
+    const int64_t nb = max(n0, static_cast<int64_t>(m));
+    if (nb >= n1) return;
+    const T *h = hist + d.h_off + i;
+    int64_t a = nb % hist_rows, b = (nb - m) % hist_rows;
+    double sum = 0.0;
+    for (int64_t n = nb; n < n1; ++n) {
+        sum += static_cast<double>(h[a * N]) * static_cast<double>(h[b * N]);
+        if (++a == hist_rows) a = 0;
+        if (++b == hist_rows) b = 0;
+    }
+    tc[d.tc_off + static_cast<int64_t>(m) * N + i] += sum;
+}
+
+__global__ void __launch_bounds__(256)
+    k_fin_tc(int n, int lags, const double *__restrict__ s1, const double *__restrict__ tc, int64_t M,
+             double *__restrict__ out)
+{
+    const int64_t e = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
+    if (e >= static_cast<int64_t>(n) * lags) return;
+    const int i = static_cast<int>(e % n), m = static_cast<int>(e / n);
+    if (M <= m) {
+        out[e] = __builtin_nan("");
+        return;
+    }
+    const double mu = s1[i] / static_cast<double>(M);
+    out[e] = tc[e] / static_cast<double>(M - m) - mu * mu;
+}
+
+hipError_t launch_tcorr1d(int prec, int n_inst, int nmax, int lags, hipStream_t s, const Inst1D *tab,
+                          const void *hist, int32_t hist_rows, int64_t n0, int64_t count, double *tc,
+                          const InstAcc *acc)
+{
+    const dim3 grid(static_cast<unsigned>((static_cast<int64_t>(nmax) * lags + 255) / 256), n_inst);
+    if (prec == 0)
+        hipLaunchKernelGGL(k_tcorr<float>, grid, dim3(256), 0, s, tab, static_cast<const float *>(hist), hist_rows,
+                           lags, n0, count, tc, acc);
+    else
+        hipLaunchKernelGGL(k_tcorr<double>, grid, dim3(256), 0, s, tab, static_cast<const double *>(hist),
+                           hist_rows, lags, n0, count, tc, acc);
+    return hipGetLastError();
+}
+
+hipError_t launch_fin_tc(hipStream_t s, int n, int lags, const double *s1, const double *tc, int64_t M,
+                         double *out)
+{
+    const int64_t tot = static_cast<int64_t>(n) * lags;
+    hipLaunchKernelGGL(k_fin_tc, dim3(static_cast<unsigned>((tot + 255) / 256)), dim3(256), 0, s, n, lags, s1, tc, M,
+                       out);
+    return hipGetLastError();
 }
 
 // ------------------------------------------------------------------ init

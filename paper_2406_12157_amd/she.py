@@ -21,7 +21,7 @@ PERIODIC, DIRICHLET = 0, 1
 EM, HEUN = 0, 1
 NOISE_INSTANT, NOISE_FROZEN, NOISE_OFF = 0, 1, 2
 F32, F64 = 0, 1
-STAT_MOMENTS, STAT_CORR, STAT_SK, STAT_SPATIAL = 1, 2, 4, 8
+STAT_MOMENTS, STAT_CORR, STAT_SK, STAT_SPATIAL, STAT_TCORR = 1, 2, 4, 8, 16
 TUNE_XCD_ORDER = 1
 
 OK, EINVAL, EUNSTABLE, ENOMEM, EDEVICE, ENONFINITE, ESTATE, EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6, -7
@@ -47,7 +47,7 @@ class Config(C.Structure):
     _fields_ = [("n_instances", C.c_int32), ("precision", C.c_int32), ("inst", C.POINTER(InstanceDesc)),
                 ("burn_in", C.c_int64), ("sample_every", C.c_int32), ("stats_mask", C.c_uint32),
                 ("block_threads", C.c_int32), ("rows_per_block", C.c_int32), ("rows_per_group", C.c_int32),
-                ("tuning_flags", C.c_int32), ("graph_steps", C.c_int32), ("reserved", C.c_int32),
+                ("tuning_flags", C.c_int32), ("graph_steps", C.c_int32), ("tcorr_lags", C.c_int32),
                 ("stream", C.c_void_p), ("arena", C.c_void_p),
                 ("arena_bytes", C.c_size_t)]
 
@@ -60,7 +60,7 @@ class StatsOut(C.Structure):
                 ("sk", C.POINTER(C.c_double)), ("sk_cap", C.c_int64),
                 ("sk_modes", C.POINTER(C.c_double)), ("sk_modes_cap", C.c_int64),
                 ("sum_u", C.c_double), ("nonfinite", C.c_int32), ("reserved", C.c_int32),
-                ("clamp_count", C.c_int64)]
+                ("clamp_count", C.c_int64), ("tcorr", C.POINTER(C.c_double)), ("tcorr_cap", C.c_int64)]
 
 
 EXPORTS = ["she_create", "she_arena_bytes", "she_step", "she_run", "she_stats", "she_reset_stats",
@@ -169,7 +169,7 @@ class Handle:
 
     def __init__(self, instances, precision: int = F32, burn_in: int = 0, sample_every: int = 10,
                  stats: int = 0, stream=None, arena=None, block_threads: int = 0, rows_per_block: int = 0,
-                 rows_per_group: int = 0, tuning_flags: int = 0, graph_steps: int = 0):
+                 rows_per_group: int = 0, tuning_flags: int = 0, graph_steps: int = 0, tcorr_lags: int = 0):
         self.lib = load()
         self.instances = list(instances)
         self._descs = (InstanceDesc * len(self.instances))(*[i.c() for i in self.instances])
@@ -178,7 +178,7 @@ class Handle:
         self.stream = stream
         self._arena = arena
         cfg = Config(len(self.instances), precision, self._descs, burn_in, sample_every, stats,
-                     block_threads, rows_per_block, rows_per_group, tuning_flags, graph_steps, 0,
+                     block_threads, rows_per_block, rows_per_group, tuning_flags, graph_steps, tcorr_lags,
                      C.c_void_p(stream) if stream else None, None, 0)
         if arena is not None:
             cfg.arena = C.c_void_p(arena.data_ptr())
@@ -188,15 +188,16 @@ class Handle:
         _check(self.lib.she_create(C.byref(cfg), C.byref(h)))
         self.h = h
         self.precision = precision
+        self.tcorr_lags = tcorr_lags
 
     @staticmethod
     def arena_bytes(instances, precision=F32, burn_in=0, sample_every=10, stats=0, block_threads=0,
-                    rows_per_block=0, rows_per_group=0, tuning_flags=0, graph_steps=0) -> int:
+                    rows_per_block=0, rows_per_group=0, tuning_flags=0, graph_steps=0, tcorr_lags=0) -> int:
         lib = load()
         insts = list(instances)
         descs = (InstanceDesc * len(insts))(*[i.c() for i in insts])
         cfg = Config(len(insts), precision, descs, burn_in, sample_every, stats, block_threads,
-                     rows_per_block, rows_per_group, tuning_flags, graph_steps, 0, None, None, 0)
+                     rows_per_block, rows_per_group, tuning_flags, graph_steps, tcorr_lags, None, None, 0)
         out = C.c_size_t()
         _check(lib.she_arena_bytes(C.byref(cfg), C.byref(out)))
         return int(out.value)
@@ -243,7 +244,8 @@ class Handle:
         v = np.ascontiguousarray(values, dtype=np.float64)
         _check(self.lib.she_write_field(self.h, i, _dptr(v), v.size), self.h)
 
-    def stats(self, i: int, corr: bool = False, sk: bool = False, raise_nonfinite: bool = True) -> dict:
+    def stats(self, i: int, corr: bool = False, sk: bool = False, tcorr: bool = False,
+              raise_nonfinite: bool = True) -> dict:
         inst = self.instances[i]
         n = inst.ncells if inst.dim == 1 else 1
         mean = np.zeros(n)
@@ -251,7 +253,10 @@ class Handle:
         out = StatsOut()
         out.mean, out.mean_cap = _dptr(mean), n
         out.var, out.var_cap = _dptr(var), n
-        cm = skv = modes = None
+        cm = skv = modes = tcv = None
+        if tcorr:
+            tcv = np.zeros(self.tcorr_lags * n)
+            out.tcorr, out.tcorr_cap = _dptr(tcv), tcv.size
         if corr:
             cm = np.zeros(n * n)
             out.corr, out.corr_cap = _dptr(cm), n * n
@@ -273,6 +278,8 @@ class Handle:
             res["sk"] = skv
         if modes is not None:
             res["sk_modes"] = modes
+        if tcv is not None:
+            res["tcorr"] = tcv.reshape(self.tcorr_lags, n)
         return res
 
     def state_bytes(self) -> int:

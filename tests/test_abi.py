@@ -77,6 +77,23 @@ def test_invalid_tuning_and_graph_settings():
     assert she.Handle.arena_bytes(insts, graph_steps=64, tuning_flags=she.TUNE_XCD_ORDER) == base
 
 
+def test_time_correlation_settings():
+    one = [gpu_instance(she, W.instance((64,), r=0.2))]
+    base = she.Handle.arena_bytes(one, stats=she.STAT_MOMENTS)
+    with_tc = she.Handle.arena_bytes(one, stats=she.STAT_TCORR, tcorr_lags=32)
+    assert with_tc >= base + 8 * 32 * 64            # FP64 lag sums at least
+    bad = [dict(stats=she.STAT_TCORR), dict(stats=she.STAT_TCORR, tcorr_lags=1025),
+           dict(stats=she.STAT_MOMENTS, tcorr_lags=8), dict(stats=32)]
+    for kw in bad:
+        with pytest.raises(she.SheError) as e:
+            she.Handle.arena_bytes(one, **kw)
+        assert e.value.status == she.EINVAL, kw
+    with pytest.raises(she.SheError) as e:
+        she.Handle.arena_bytes([gpu_instance(she, W.instance((64, 64), r=0.1))], stats=she.STAT_TCORR,
+                               tcorr_lags=8)
+    assert e.value.status == she.EUNSUPPORTED
+
+
 def test_arena_bytes_scale_with_problem():
     small = she.Handle.arena_bytes([gpu_instance(she, W.instance((64, 64), r=0.1))])
     big = she.Handle.arena_bytes([gpu_instance(she, W.instance((512, 512), r=0.1))])

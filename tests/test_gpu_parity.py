@@ -280,6 +280,33 @@ def test_1d_statistics_parity(she, precision):
     assert max_rel(g["sk"], st.structure_factor()) < tol
 
 
+@pytest.mark.parametrize("precision", [0, 1])
+def test_1d_time_correlation_parity(she, precision):
+    """Ragged batch, every step sampled after the burn-in, 40 lags: the lag
+    products span launches and the history ring wraps (9000 samples)."""
+    insts = [inst1d((96,), W.DIRICHLET, W.HEUN, W.HEAT, 0), inst1d((40,), W.PERIODIC, W.EM, W.HEAT, 1)]
+    L = 40
+    h = she.Handle([gpu_instance(she, i) for i in insts], precision=precision, burn_in=100, sample_every=1,
+                   stats=she.STAT_TCORR, tcorr_lags=L)
+    init = [h.read_field(q) for q in range(2)]
+    for k in (3000, 1, 777, 5322):
+        h.run(k)
+    tol = 1e-3 if precision == 0 else 1e-9
+    for q in range(2):
+        g = h.stats(q, tcorr=True)
+        d = oracle_desc(insts[q], precision)
+        st = oracle.Stats(d, burn_in=100, every=1, tcorr_lags=L)
+        u = init[q].copy()
+        oracle.advance(d, u, 0, 9100, st)
+        assert g["n_samples"] == st.n_samples == 9000
+        want = st.time_corr()
+        assert g["tcorr"].shape == (L, insts[q]["n"][0])
+        assert np.max(np.abs(g["tcorr"] - want)) < tol * np.max(np.abs(want))
+        # lag 0 is the per-cell variance (FP32: the ring holds deltas rounded to the state type)
+        np.testing.assert_allclose(g["tcorr"][0], g["var"], rtol=1e-6 if precision == 0 else 1e-12)
+    h.close()
+
+
 def test_nd_spatial_statistics_parity(she):
     insts = [inst2d((64, 32), W.EM, W.HEAT, realisation=q) for q in range(3)]
     h = she.Handle([gpu_instance(she, i) for i in insts], precision=0, burn_in=100, sample_every=5,
@@ -350,19 +377,25 @@ def test_c3_full_size_sampled_parity(she):
 
 def test_checkpoint_resume_is_bit_exact(she):
     for inst, prec in ((inst1d((128,), W.DIRICHLET, W.HEUN, W.HEAT, 0), 0), (inst2d((64, 16), W.EM, W.HEAT), 0)):
-        mask = she.STAT_MOMENTS | she.STAT_CORR if len(inst["n"]) == 1 else she.STAT_SPATIAL
-        a = she.Handle([gpu_instance(she, inst)], precision=prec, burn_in=0, sample_every=2, stats=mask)
+        one_d = len(inst["n"]) == 1
+        mask = she.STAT_MOMENTS | she.STAT_CORR | she.STAT_TCORR if one_d else she.STAT_SPATIAL
+        lags = 16 if one_d else 0
+        a = she.Handle([gpu_instance(she, inst)], precision=prec, burn_in=0, sample_every=2, stats=mask,
+                       tcorr_lags=lags)
         a.run(700)
         blob = a.get_state()
         a.run(900)
-        fa, sa = a.read_field(0), a.stats(0)
-        b = she.Handle([gpu_instance(she, inst)], precision=prec, burn_in=0, sample_every=2, stats=mask)
+        fa, sa = a.read_field(0), a.stats(0, tcorr=one_d)
+        b = she.Handle([gpu_instance(she, inst)], precision=prec, burn_in=0, sample_every=2, stats=mask,
+                       tcorr_lags=lags)
         b.set_state(blob)
         assert b.steps == 700
         b.run(900)
-        fb, sb = b.read_field(0), b.stats(0)
+        fb, sb = b.read_field(0), b.stats(0, tcorr=one_d)
         np.testing.assert_array_equal(fa, fb)
         np.testing.assert_array_equal(sa["var"], sb["var"])
+        if one_d:
+            np.testing.assert_array_equal(sa["tcorr"], sb["tcorr"])
         assert sa["n_samples"] == sb["n_samples"]
         a.close()
         b.close()
