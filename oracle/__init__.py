@@ -51,7 +51,9 @@ class _Desc(C.Structure):
                 ("r", C.c_double), ("sigma", C.c_double), ("u0", C.c_double),
                 ("u_left", C.c_double), ("u_right", C.c_double),
                 ("init_sd", C.c_double), ("seed", C.c_uint64),
-                ("realisation", C.c_uint32), ("pad_", C.c_uint32)]
+                ("realisation", C.c_uint32), ("pad_", C.c_uint32),
+                ("face_r", C.POINTER(C.c_double)), ("face_s", C.POINTER(C.c_double)),
+                ("cell_w", C.POINTER(C.c_double))]
 
 
 class _Stats(C.Structure):
@@ -114,12 +116,43 @@ class Desc:
     init_sd: float = 0.0
     seed: int = 0
     realisation: int = 0
+    cond: object = None    # 1D, optional: N conductivity ratios lambda_i / lambda_ref
+    cap: object = None     # 1D, optional: N heat-capacity ratios (rho c_V)_i / (rho c_V)_ref
+
+    def coefficients(self):
+        """Per-face conductance r_f and noise factor s_f, per-cell w_i of a rod
+        whose material varies along x (the composite-rod exercise): interior
+        faces take the harmonic mean of the two cells' conductivity (series
+        resistance of the two half cells), a wall face the adjacent cell's;
+        r_f = r lambda_f, s_f = sqrt(2 r_f eps) = sigma sqrt(lambda_f),
+        w_i = 1 / cap_i.  None when the rod is uniform."""
+        if self.cond is None and self.cap is None:
+            return None
+        N = int(self.n[0])
+        lam = np.ones(N) if self.cond is None else np.asarray(self.cond, dtype=np.float64)
+        cap = np.ones(N) if self.cap is None else np.asarray(self.cap, dtype=np.float64)
+        nf = N + 1 if self.bc == 1 else N
+        lf = np.empty(nf)
+        for f in range(nf):
+            if self.bc == 1 and f == 0:
+                lf[f] = lam[0]
+            elif self.bc == 1 and f == N:
+                lf[f] = lam[N - 1]
+            else:
+                a, b = lam[(f - 1) % N], lam[f % N]
+                lf[f] = 2.0 * a * b / (a + b)
+        return self.r * lf, self.sigma * np.sqrt(lf), 1.0 / cap
 
     def c(self) -> _Desc:
         n = tuple(self.n) + (1,) * (3 - len(self.n))
+        co = self.coefficients()
+        null = C.POINTER(C.c_double)()
+        if co is not None:
+            self._keep = [np.ascontiguousarray(a) for a in co]
+        ptrs = [_dptr(a) for a in self._keep] if co is not None else [null, null, null]
         return _Desc(self.dim, (C.c_int32 * 3)(*n), self.eq, self.bc, self.scheme,
                      self.noise, self.r, self.sigma, self.u0, self.u_left, self.u_right,
-                     self.init_sd, self.seed, self.realisation, 0)
+                     self.init_sd, self.seed, self.realisation, 0, *ptrs)
 
     @property
     def ncells(self) -> int:

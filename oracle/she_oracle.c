@@ -26,7 +26,11 @@
  *     S_k = <|sum_j T_j exp(-2 pi i j k/N)|^2> (Sec. 3, structure factor);
  *   - 1D time correlation <dT_i^n dT_i^(n-m)> over sample lags m (the first
  *     of the suggested exercises, Sec. 6): sums over samples n >= m of
- *     delta_i(n) delta_i(n-m), with the last L samples kept in a ring.
+ *     delta_i(n) delta_i(n-m), with the last L samples kept in a ring;
+ *   - 1D materials that vary along the rod (the composite-rod exercise,
+ *     Sec. 6): the conservative form rho c_V dT/dt = -d/dx(flux) of eq. SHE
+ *     with a conductance r_f and noise factor s_f per face and a factor
+ *     w_i = (rho c_V)_ref / (rho c_V)_i per cell, T_i += w_i (F_(i+1) - F_i).
  *
  * Gaussian numbers: Philox4x32-10 (Salmon, Moraes, Dror, Shaw, "Parallel
  * random numbers: as easy as 1, 2, 3", SC'11) and the Box-Muller transform
@@ -72,6 +76,9 @@ typedef struct {
     uint64_t seed;
     uint32_t realisation;
     uint32_t pad_;
+    const double *face_r;  /* 1D, optional: conductance per face (replaces r)  */
+    const double *face_s;  /* 1D, optional: noise factor per face (replaces sigma) */
+    const double *cell_w;  /* 1D, optional: capacity factor per cell (else 1)  */
 } or_desc;
 
 typedef struct {
@@ -218,6 +225,8 @@ static int check_desc(const or_desc *d)
     if (d->scheme != 0 && d->scheme != 1) return -1;
     if (d->noise < 0 || d->noise > 2) return -1;
     if (d->dim == 1 && d->bc == 0 && d->n[0] < 2) return -1;
+    if ((d->face_r || d->face_s || d->cell_w) && d->dim != 1) return -1;
+    if ((d->face_r != NULL) != (d->face_s != NULL)) return -1;
     return 0;
 }
 
@@ -272,23 +281,26 @@ static void divergence(const or_desc *d, const double *u, const double *z,
     const int noisy = d->noise != 2;
     if (d->dim == 1) {
         const int64_t N = d->n[0];
+        /* per-face conductance and noise factor (uniform unless given) */
+#define RF(f) (d->face_r ? d->face_r[f] : r)
+#define SF(f) (d->face_s ? d->face_s[f] : s)
         if (d->bc == 1) {
             const double wall = sqrt(2.0);
             for (int64_t f = 0; f <= N; ++f) {
                 double fl;
                 if (f == 0) {
-                    fl = 2.0 * r * (u[0] - d->u_left);
-                    if (noisy) fl += wall * s * amplitude(d, d->u_left, clamps) * z[0];
+                    fl = 2.0 * RF(0) * (u[0] - d->u_left);
+                    if (noisy) fl += wall * SF(0) * amplitude(d, d->u_left, clamps) * z[0];
                 } else if (f == N) {
-                    fl = 2.0 * r * (d->u_right - u[N - 1]);
-                    if (noisy) fl += wall * s * amplitude(d, d->u_right, clamps) * z[N];
+                    fl = 2.0 * RF(N) * (d->u_right - u[N - 1]);
+                    if (noisy) fl += wall * SF(N) * amplitude(d, d->u_right, clamps) * z[N];
                 } else {
-                    fl = r * (u[f] - u[f - 1]);
+                    fl = RF(f) * (u[f] - u[f - 1]);
                     if (noisy) {
                         double v = d->noise == 1
                                        ? d->u_left + (d->u_right - d->u_left) * (double)f / N
                                        : 0.5 * (u[f - 1] + u[f]);
-                        fl += s * amplitude(d, v, clamps) * z[f];
+                        fl += SF(f) * amplitude(d, v, clamps) * z[f];
                     }
                 }
                 flux[f] = fl;
@@ -297,15 +309,19 @@ static void divergence(const or_desc *d, const double *u, const double *z,
         } else {
             for (int64_t f = 0; f < N; ++f) {
                 int64_t a = (f + N - 1) % N;
-                double fl = r * (u[f] - u[a]);
+                double fl = RF(f) * (u[f] - u[a]);
                 if (noisy) {
                     double v = d->noise == 1 ? d->u0 : 0.5 * (u[a] + u[f]);
-                    fl += s * amplitude(d, v, clamps) * z[f];
+                    fl += SF(f) * amplitude(d, v, clamps) * z[f];
                 }
                 flux[f] = fl;
             }
             for (int64_t i = 0; i < N; ++i) out[i] = flux[(i + 1) % N] - flux[i];
         }
+#undef RF
+#undef SF
+        if (d->cell_w)
+            for (int64_t i = 0; i < N; ++i) out[i] = d->cell_w[i] * out[i];
         return;
     }
     /* 2D / 3D periodic */

@@ -125,3 +125,58 @@ def test_literal_large_eps_diverges_and_is_detected():
     st = oracle.Stats(d, burn_in=0, every=10)
     rc = oracle.advance(d, u, 0, 100000, st)
     assert rc == 1 and st.nonfinite
+
+
+# ---------------------------------------------------------------- composite rod
+
+HALF = 8
+COND = [1.0] * HALF + [3.0] * HALF       # conductivity ratio of the two materials
+CAP = [1.0] * HALF + [0.6] * HALF        # heat-capacity ratio
+
+
+@pytest.mark.parametrize("scheme", [0, 1])
+def test_composite_rod_conserves_energy_not_temperature_sum(scheme):
+    """Periodic composite rod with noise: sum_i (rho c_V)_i T_i is conserved
+    (the scheme is conservative in energy), while sum_i T_i is not."""
+    d = oracle.Desc(dim=1, n=(2 * HALF, 1, 1), r=0.08, sigma=0.05, u0=1.0, scheme=scheme, init_sd=0.05, seed=3,
+                    cond=COND, cap=CAP)
+    u = oracle.init(d)
+    e0, s0 = float(np.dot(CAP, u)), float(u.sum())
+    oracle.advance(d, u, 0, 2000)
+    assert abs(np.dot(CAP, u) - e0) < 1e-12 * abs(e0)
+    assert abs(u.sum() - s0) > 1e-4
+
+
+@pytest.mark.parametrize("scheme", [0, 1])
+def test_composite_rod_series_profile_is_fixed_point(scheme):
+    """Dirichlet walls with a gradient, noise off: the steady state carries one
+    flux J through conductances in series (half cells, walls at a half cell),
+    T_i - T_(i-1) = J / g_(i-1/2); it is an exact fixed point, the linear
+    profile is not."""
+    N, r, tl, tr = 2 * HALF, 0.08, 0.7, 1.3
+    lam = np.array(COND)
+    g = np.array([lam[0]] + [1.0 / (0.5 / lam[f - 1] + 0.5 / lam[f]) for f in range(1, N)] + [lam[-1]])
+    res = np.concatenate([[0.5 / g[0]], 1.0 / g[1:N], [0.5 / g[N]]])   # wall faces: half a cell
+    J = (tr - tl) / res.sum()
+    prof = tl + J * np.cumsum(res)[:N]
+    d = oracle.Desc(dim=1, n=(N, 1, 1), bc=1, r=r, sigma=0.0, u_left=tl, u_right=tr, noise=2, scheme=scheme,
+                    cond=COND, cap=CAP)
+    u = prof.copy()
+    oracle.advance(d, u, 0, 500)
+    np.testing.assert_allclose(u, prof, rtol=0, atol=1e-13)
+    lin = tl + (tr - tl) * (np.arange(N) + 0.5) / N
+    v = lin.copy()
+    oracle.advance(d, v, 0, 1)
+    assert np.max(np.abs(v - lin)) > 1e-3
+
+
+def test_composite_rod_with_unit_ratios_is_the_uniform_rod():
+    for bc in (0, 1):
+        kw = dict(dim=1, n=(12, 1, 1), bc=bc, r=0.2, sigma=0.1, u0=1.0, u_left=0.9, u_right=1.1 if bc else 0.9,
+                  init_sd=0.05, seed=7)
+        a = oracle.Desc(**kw)
+        b = oracle.Desc(**kw, cond=np.ones(12), cap=np.ones(12))
+        ua, ub = oracle.init(a), oracle.init(b)
+        oracle.advance(a, ua, 0, 300)
+        oracle.advance(b, ub, 0, 300)
+        np.testing.assert_array_equal(ua, ub)

@@ -281,3 +281,58 @@ def test_time_correlation_closed_form(case):
     assert np.max(np.abs(tc[:8] / want[:8] - 1)) < 0.05
     # the correlation decays: lag 23 keeps well under half of lag 0
     assert want[L - 1] < 0.5 * want[0]
+
+
+@pytest.mark.parametrize("scheme", ["fe", "pc"])
+def test_composite_rod_equilibrium_covariance(scheme):
+    """Iron-like / aluminium-like halves (conductivity ratio 3, heat-capacity
+    ratio 0.6), Dirichlet walls at the same temperature, face amplitude at that
+    temperature: the full covariance is the discrete Lyapunov solution of the
+    composite scheme's linear map."""
+    N, r, eps, t0 = 8, 0.05, 0.01, 1.0
+    cond, cap = [1.0] * 4 + [3.0] * 4, [1.0] * 4 + [0.6] * 4
+    sigma = oracle.sigma_of(r, eps)
+    d = oracle.Desc(dim=1, n=(N, 1, 1), bc=1, r=r, sigma=sigma, u_left=t0, u_right=t0, noise=1,
+                    scheme=0 if scheme == "fe" else 1, init_sd=np.sqrt(eps), seed=71, cond=cond, cap=cap)
+    sts = batch_run(d, 20, 20000, 2000, corr=True)
+    C, se = mean_se([s.cov() for s in sts])
+    G, B = theory.composite_operators(r, sigma, cond, cap, t0, t0, scheme)
+    want = theory.general_discrete_lyapunov(G, B)
+    assert np.max(np.abs((C - want) / se)) < 5.0
+    np.testing.assert_allclose(np.diag(C), np.diag(want), rtol=0.05)
+
+
+def test_composite_rod_equilibrium_variance_follows_heat_capacity():
+    """Exercise on the composite rod at equilibrium: the fluctuation-
+    dissipation balance gives <dT_i^2> = eps T^2 / cap_i, set by the local
+    heat capacity and not by the conductivity; the cross-correlations vanish.
+    Exact for the semi-discrete scheme (the continuous Lyapunov equation),
+    approached by the discrete schemes as r -> 0."""
+    N, eps, t0 = 8, 0.01, 1.0
+    cond, cap = [1.0] * 4 + [3.0] * 4, [1.0] * 4 + [0.6] * 4
+    sigma0 = oracle.sigma_of(1.0, eps)
+    # semi-discrete: (W A) C + C (W A)^T + B B^T = 0 at unit rate solves to eps T^2 W^-1
+    from scipy.linalg import solve_continuous_lyapunov
+    G, B = theory.composite_operators(1.0, sigma0, cond, cap, t0, t0, "fe")
+    cont = solve_continuous_lyapunov(G - np.eye(N), -B @ B.T)
+    np.testing.assert_allclose(cont, eps * t0 ** 2 * np.diag(1.0 / np.array(cap)), atol=1e-15)
+    # the discrete schemes approach it as r -> 0: error O(r) for FE, O(r^2) for PC
+    limit = eps * t0 ** 2 * np.diag(1.0 / np.array(cap))
+    for scheme, order in (("fe", 1), ("pc", 2)):
+        err = []
+        for r in (0.02, 0.01, 0.005):
+            G, B = theory.composite_operators(r, oracle.sigma_of(r, eps), cond, cap, t0, t0, scheme)
+            err.append(np.max(np.abs(theory.general_discrete_lyapunov(G, B) - limit)) / eps)
+        for a, b in zip(err, err[1:]):
+            assert 0.8 * 2 ** order < a / b < 1.25 * 2 ** order, (scheme, err)
+    # the oracle at r = 0.02 (PC, face amplitude at the equilibrium temperature)
+    r = 0.02
+    sigma = oracle.sigma_of(r, eps)
+    d = oracle.Desc(dim=1, n=(N, 1, 1), bc=1, r=r, sigma=sigma, u_left=t0, u_right=t0, scheme=1, noise=1,
+                    init_sd=np.sqrt(eps), seed=81, cond=cond, cap=cap)
+    sts = batch_run(d, 20, 30000, 5000, every=5)
+    v, se = mean_se([s.var() for s in sts])
+    G, B = theory.composite_operators(r, sigma, cond, cap, t0, t0, "pc")
+    want = np.diag(theory.general_discrete_lyapunov(G, B))
+    assert np.max(np.abs(v - want) / se) < 4.5, (v, want, se)
+    assert v[6] / v[1] > 1.4          # the low-capacity half fluctuates more

@@ -125,6 +125,55 @@ def discrete_lyapunov(G: np.ndarray, B: np.ndarray) -> np.ndarray:
     return V @ Ct @ V.T
 
 
+def composite_operators(r: float, sigma: float, cond, cap, t_left: float, t_right: float,
+                        scheme: str = "fe"):
+    """One-step map U' = G U + b + B z of a 1D Dirichlet rod whose material
+    varies along x, with the face amplitude taken from a uniform temperature
+    (equilibrium, t_left == t_right).  Energy balance of cell i:
+    (rho c_V)_i dT_i/dt = [J_(i+1/2) - J_(i-1/2)] / dx, with the flux through a
+    face driven by the conductance of the two half cells in series, and the
+    Dirichlet wall face seeing one half cell.  In units of the reference
+    material: conductance g_f / dx^2 * dt, and the noise of a face has
+    variance 2 k_B g_f T^2 (fluctuation-dissipation), times sqrt(2) at a wall
+    (its ghost-cell half spacing)."""
+    assert t_left == t_right, "the amplitude is the equilibrium temperature"
+    lam = np.asarray(cond, dtype=float)
+    cap = np.asarray(cap, dtype=float)
+    N = lam.size
+    # series conductance of faces 0..N: two half cells (interior), one half cell and the wall
+    g = np.empty(N + 1)
+    g[0], g[N] = lam[0], lam[N - 1]
+    for f in range(1, N):
+        g[f] = 1.0 / (0.5 / lam[f - 1] + 0.5 / lam[f])
+    A = np.zeros((N, N))
+    for i in range(N):
+        lo, hi = (2.0 * g[0] if i == 0 else g[i]), (2.0 * g[N] if i == N - 1 else g[i + 1])
+        A[i, i] = -(lo + hi)
+        if i > 0:
+            A[i, i - 1] = g[i]
+        if i < N - 1:
+            A[i, i + 1] = g[i + 1]
+    Winv = np.diag(1.0 / cap)
+    G = np.eye(N) + r * Winv @ A
+    wall = np.ones(N + 1)
+    wall[0] = wall[-1] = np.sqrt(2.0)
+    D = np.zeros((N, N + 1))
+    for i in range(N):
+        D[i, i], D[i, i + 1] = -1.0, 1.0
+    B = Winv @ D @ np.diag(wall * sigma * np.sqrt(g) * t_left)
+    if scheme == "pc":
+        I = np.eye(N)
+        B = 0.5 * (I + G) @ B
+        G = 0.5 * (I + G @ G)
+    return G, B
+
+
+def general_discrete_lyapunov(G: np.ndarray, B: np.ndarray) -> np.ndarray:
+    """Stationary covariance C = G C G^T + B B^T for any stable G."""
+    from scipy.linalg import solve_discrete_lyapunov
+    return solve_discrete_lyapunov(G, B @ B.T)
+
+
 def garcia_neq_correlation(N: int, eps_dv: float, t_mean: np.ndarray, grad_t: float,
                            ell: float = 1.0, area_eps: float | None = None) -> np.ndarray:
     """Paper's eq. TcorrNEQ in units where the length is ell and
