@@ -112,6 +112,23 @@ typedef struct {
     uint64_t seed;        /* Philox key                                        */
     uint32_t realisation; /* Philox counter word 3                             */
     uint32_t reserved;    /* must be 0                                         */
+    const double *cond;   /* 1D, optional (NULL = uniform): N conductivity
+                             ratios lambda_i / lambda_ref > 0 per cell, for a
+                             material that varies along the rod (composite
+                             rod exercise, Sec. 6).  r refers to lambda_ref;
+                             a face conducts like its two half cells in
+                             series, a wall face like its cell.  Read during
+                             she_create / she_arena_bytes only.              */
+    const double *cap;    /* 1D, optional: N heat-capacity ratios
+                             (rho c_V)_i / (rho c_V)_ref > 0; eps refers to
+                             the reference material.  With cond or cap the
+                             step is U_i += (F_(i+1) - F_i) / cap_i, F_f =
+                             r_f dU + sqrt(2 r_f eps) A_f N_f (r_f = r times
+                             the face conductivity ratio); FE stability needs
+                             max_i (sum of the conductances of row i) /
+                             cap_i <= 2, else SHE_EUNSTABLE.  Deterministic
+                             face values (SHE_NOISE_FROZEN) need
+                             u_left == u_right.                              */
 } she_instance_desc;
 
 typedef struct {

@@ -56,6 +56,10 @@ struct she_handle {
     void *d_hist = nullptr;
     double *d_tc = nullptr;
     int64_t hist_elems = 0, tc_elems = 0;
+    // material varying along the rod: r_f, s_f, w_i per instance (state type)
+    bool varc = false;
+    std::vector<double> coef_host;
+    void *d_coef = nullptr;
     size_t smem1d = 0;
 
     // 2D / 3D
@@ -108,6 +112,47 @@ she_status hipfail(she_handle *h, hipError_t e, const char *what)
     } while (0)
 
 bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
+
+// Face conductivity ratios of a 1D rod with cell ratios cond (NULL: 1): an
+// interior face conducts like its two half cells in series (harmonic mean),
+// a Dirichlet wall face like its cell.  Faces 0..N-1 (periodic) or 0..N.
+std::vector<double> face_conductivity(const she_instance_desc &d)
+{
+    const int N = d.n[0];
+    const bool dir = d.bc == SHE_DIRICHLET;
+    auto lam = [&](int i) { return d.cond ? d.cond[i] : 1.0; };
+    std::vector<double> lf(dir ? N + 1 : N);
+    for (int f = 0; f < static_cast<int>(lf.size()); ++f) {
+        if (dir && f == 0) lf[f] = lam(0);
+        else if (dir && f == N) lf[f] = lam(N - 1);
+        else {
+            const double a = lam((f - 1 + N) % N), b = lam(f % N);
+            lf[f] = 2.0 * a * b / (a + b);
+        }
+    }
+    return lf;
+}
+
+// Gershgorin bound of the FE operator w_i (sum of row i's conductances, the
+// Dirichlet wall face counted twice on the diagonal); the step is stable
+// when it is at most 2.
+double varc_row_bound(const she_instance_desc &d)
+{
+    const int N = d.n[0];
+    const bool dir = d.bc == SHE_DIRICHLET;
+    const std::vector<double> lf = face_conductivity(d);
+    double worst = 0.0;
+    for (int i = 0; i < N; ++i) {
+        const int hi = dir ? i + 1 : (i + 1) % N;
+        const double lo_c = (dir && i == 0) ? 2.0 * lf[0] : lf[i];
+        const double hi_c = (dir && i == N - 1) ? 2.0 * lf[N] : lf[hi];
+        const double lo_g = (dir && i == 0) ? 0.0 : lf[i];
+        const double hi_g = (dir && i == N - 1) ? 0.0 : lf[hi];
+        const double w = d.cap ? 1.0 / d.cap[i] : 1.0;
+        worst = std::max(worst, w * d.r * (lo_c + hi_c + lo_g + hi_g));
+    }
+    return worst;
+}
 
 size_t align256(size_t v) { return (v + 255) & ~static_cast<size_t>(255); }
 
@@ -177,6 +222,18 @@ she_status validate(const she_config *cfg, she_handle *h)
             return fail(nullptr, SHE_EINVAL, pre + "a wall gradient needs Dirichlet walls, not periodic");
         if (d.dim == 1 && d.bc == SHE_PERIODIC && d.n[0] < 2)
             return fail(nullptr, SHE_EINVAL, pre + "periodic 1D needs N >= 2");
+        if (d.cond || d.cap) {
+            if (d.dim != 1) return fail(nullptr, SHE_EUNSUPPORTED, pre + "cond / cap are provided for 1D rods");
+            for (int c = 0; c < d.n[0]; ++c)
+                if ((d.cond && !(d.cond[c] > 0.0 && std::isfinite(d.cond[c]))) ||
+                    (d.cap && !(d.cap[c] > 0.0 && std::isfinite(d.cap[c]))))
+                    return fail(nullptr, SHE_EINVAL, pre + "cond / cap must be finite and > 0");
+            if (d.noise == SHE_NOISE_FROZEN && d.u_left != d.u_right)
+                return fail(nullptr, SHE_EUNSUPPORTED,
+                            pre + "deterministic face values on a composite rod need u_left == u_right");
+            if (varc_row_bound(d) > 2.0)
+                return fail(nullptr, SHE_EUNSTABLE, pre + "composite rod above the explicit stability limit");
+        }
     }
     (void)h;
     return SHE_OK;
@@ -230,6 +287,21 @@ static she_status plan_1d(she_handle *h, const she_config *cfg, Plan &plan)
             t.x_off = -1;
             t.c_off = -1;
         }
+        if (d.cond || d.cap) {
+            // r_f, s_f (wall faces with their sqrt 2), w_i
+            const std::vector<double> lf = face_conductivity(d);
+            const int nf = static_cast<int>(lf.size());
+            t.k_off = static_cast<int64_t>(h->coef_host.size());
+            for (int f = 0; f < nf; ++f) h->coef_host.push_back(d.r * lf[f]);
+            for (int f = 0; f < nf; ++f) {
+                const bool wall = d.bc == SHE_DIRICHLET && (f == 0 || f == d.n[0]);
+                h->coef_host.push_back(std::sqrt(2.0 * d.r * lf[f] * d.eps) * (wall ? std::sqrt(2.0) : 1.0));
+            }
+            for (int c = 0; c < d.n[0]; ++c) h->coef_host.push_back(d.cap ? 1.0 / d.cap[c] : 1.0);
+            h->varc = true;
+        } else {
+            t.k_off = -1;
+        }
         if (tcorr) {
             t.h_off = ho;
             t.tc_off = to;
@@ -260,7 +332,7 @@ static she_status plan_1d(she_handle *h, const she_config *cfg, Plan &plan)
     h->block1d = block;
     h->maxg = maxg;
     const size_t nmax_pad = (h->nmax + 4) & ~3;
-    h->smem1d = (3 * nmax_pad + 8) * es;
+    h->smem1d = (3 * nmax_pad + 8) * es * (h->varc ? 2 : 1);
     if (h->smem1d > 64 * 1024)
         return fail(nullptr, SHE_EUNSUPPORTED, "1D instance too large for LDS (64 KB per workgroup)");
 
@@ -275,6 +347,7 @@ static she_status plan_1d(she_handle *h, const she_config *cfg, Plan &plan)
         plan.add(&h->d_x, es * xo);
         plan.add(reinterpret_cast<void **>(&h->d_c), sizeof(double) * co);
     }
+    if (h->varc) plan.add(&h->d_coef, es * h->coef_host.size());
     if (tcorr) {
         plan.add(&h->d_hist, es * ho);
         plan.add(reinterpret_cast<void **>(&h->d_tc), sizeof(double) * to);
@@ -407,6 +480,7 @@ static she_status build_plan(she_handle *h, const she_config *cfg, Plan &plan)
     if (h->mask & (SHE_STAT_CORR | SHE_STAT_TCORR)) h->mask |= SHE_STAT_MOMENTS;
     h->stream = static_cast<hipStream_t>(cfg->stream);
     she_status st = h->dim == 1 ? plan_1d(h, cfg, plan) : plan_nd(h, cfg, plan);
+    for (she_instance_desc &d : h->inst) d.cond = d.cap = nullptr;  // caller memory, read during planning only
     if (st != SHE_OK) return st;
     plan.add(reinterpret_cast<void **>(&h->d_acc), sizeof(InstAcc) * h->n_inst);
     plan.add(reinterpret_cast<void **>(&h->d_init_sd), sizeof(double) * h->n_inst);
@@ -484,7 +558,12 @@ extern "C" she_status she_create(const she_config *cfg, she_handle **out)
     plan.carve(h->base);
 
     hipStream_t s = h->stream;
+    // host sources of the asynchronous copies below; they live until the
+    // stream synchronisation at the end of creation
     std::vector<double> sd(h->n_inst);
+    std::vector<int32_t> order;
+    std::vector<float> coef32;
+    std::vector<uint32_t> real;
     for (int i = 0; i < h->n_inst; ++i) sd[i] = h->inst[i].init_sd;
 #define CREATE_HIP(call)                                          \
     do {                                                          \
@@ -498,7 +577,7 @@ extern "C" she_status she_create(const she_config *cfg, she_handle **out)
     CREATE_HIP(hipMemcpyAsync(h->d_init_sd, sd.data(), sizeof(double) * h->n_inst, hipMemcpyHostToDevice, s));
     if (h->dim == 1) {
         // largest instances first (longest-processing-time order of the workgroups)
-        std::vector<int32_t> order(h->n_inst);
+        order.resize(h->n_inst);
         std::iota(order.begin(), order.end(), 0);
         std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
             const int64_t wa = static_cast<int64_t>(h->tab[a].n) * (1 + h->tab[a].scheme);
@@ -507,9 +586,19 @@ extern "C" she_status she_create(const she_config *cfg, she_handle **out)
         });
         CREATE_HIP(hipMemcpyAsync(h->d_tab, h->tab.data(), sizeof(Inst1D) * h->n_inst, hipMemcpyHostToDevice, s));
         CREATE_HIP(hipMemcpyAsync(h->d_order, order.data(), sizeof(int32_t) * h->n_inst, hipMemcpyHostToDevice, s));
+        if (h->varc) {
+            if (h->prec == SHE_F32) {
+                coef32.assign(h->coef_host.begin(), h->coef_host.end());
+                CREATE_HIP(hipMemcpyAsync(h->d_coef, coef32.data(), sizeof(float) * coef32.size(),
+                                          hipMemcpyHostToDevice, s));
+            } else {
+                CREATE_HIP(hipMemcpyAsync(h->d_coef, h->coef_host.data(), sizeof(double) * h->coef_host.size(),
+                                          hipMemcpyHostToDevice, s));
+            }
+        }
         CREATE_HIP(launch_init1d(h->prec, h->n_inst, h->nmax, s, h->d_tab, h->d_init_sd, h->d_pool));
     } else {
-        std::vector<uint32_t> real(h->n_inst);
+        real.resize(h->n_inst);
         for (int i = 0; i < h->n_inst; ++i) real[i] = h->inst[i].realisation;
         CREATE_HIP(hipMemcpyAsync(h->d_real, real.data(), sizeof(uint32_t) * h->n_inst, hipMemcpyHostToDevice, s));
         h->pnd.realisation = h->d_real;
@@ -639,9 +728,9 @@ static she_status advance(she_handle *h, int64_t nsteps, bool sampling)
                 const int64_t j0 = std::max(h->steps, h->burn_in) / h->every;
                 k = std::min<int64_t>(k, h->every * (j0 + room + 1) - 1 - h->steps);
             }
-            SHE_HIP(h, launch_step1d(h->prec, h->block1d, h->maxg, stats, h->n_inst, h->smem1d, s, h->d_tab,
-                                     h->d_order, h->d_pool, h->steps, static_cast<int32_t>(k), h->burn_in, h->every,
-                                     h->mask, st));
+            SHE_HIP(h, launch_step1d(h->prec, h->block1d, h->maxg, stats, h->varc, h->n_inst, h->smem1d, s,
+                                     h->d_tab, h->d_order, h->d_pool, h->d_coef, h->steps, static_cast<int32_t>(k),
+                                     h->burn_in, h->every, h->mask, st));
             if (tc) {
                 const int64_t cnt = sampled_by(h->steps + k) - sampled_by(h->steps);
                 if (cnt > 0)

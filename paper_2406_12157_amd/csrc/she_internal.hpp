@@ -15,6 +15,8 @@ struct Inst1D {
     int64_t c_off;      // first element of this instance's N x N FP64 sum, -1: none
     int64_t h_off;      // first element of this instance's sample history ring, -1: none
     int64_t tc_off;     // first element of this instance's L x N FP64 lag sums, -1: none
+    int64_t k_off;      // material coefficients r_f[nf], s_f[nf] (wall sqrt 2 included), w_i[N]
+                        // in the state type, -1: uniform rod
     int32_t n;          // cells
     int32_t bc;         // 0 periodic, 1 Dirichlet
     int32_t scheme;     // 0 FE, 1 PC
@@ -94,9 +96,11 @@ __device__ __forceinline__ void resolve_step(const StepArg &a, int64_t &step, in
 namespace she {
 
 // ---- launchers (defined next to their kernels) ----
-hipError_t launch_step1d(int prec, int block, int maxg, bool stats, int n_blocks, size_t smem,
+// varc: some instance has material coefficients (k_off >= 0 in `coef`);
+// the kernel then stages r_f, s_f, w_i of every instance in LDS.
+hipError_t launch_step1d(int prec, int block, int maxg, bool stats, bool varc, int n_blocks, size_t smem,
                          hipStream_t s, const Inst1D *tab, const int32_t *order, void *pool,
-                         int64_t step0, int32_t nsteps, int64_t burn_in, int32_t every,
+                         const void *coef, int64_t step0, int32_t nsteps, int64_t burn_in, int32_t every,
                          uint32_t mask, Stats1D st);
 // Initial state of 1D instances: steady profile + init_sd * N(tag 1, step 0, face = cell).
 hipError_t launch_init1d(int prec, int n_inst, int nmax, hipStream_t s, const Inst1D *tab,

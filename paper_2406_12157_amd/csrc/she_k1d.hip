@@ -7,6 +7,12 @@
 // walls: F_0 = 2 r (U_0 - U_L) + sqrt(2) sigma A(U_L) N_0 and mirrored at the
 // right wall (ghost stencil U_1 - 3U_0 + 2U_L of the Dirichlet paragraph).
 //
+// Material varying along the rod (composite-rod exercise, Sec. 6; VARC): the
+// conservative form with a conductance r_f and noise factor s_f per face and
+// a factor w_i = (rho c_V)_ref / (rho c_V)_i per cell, U_i += w_i (F_(i+1) -
+// F_i), staged in LDS next to the state.  Uniform instances of such a batch
+// get uniform arrays (bit-identical to the uniform kernel).
+//
 // Work split: thread t owns Philox blocks g = t, t + BLOCK, ...; block g holds
 // faces 4g..4g+3, which are the low faces of cells 4g..4g+3, so one Philox
 // call and two Box-Muller pairs serve four cells and PC re-uses the numbers
@@ -93,10 +99,11 @@ __device__ void xtx_block(const T *__restrict__ X, double *__restrict__ Cm, int 
     }
 }
 
-template <typename T, int BLOCK, int MAXG, bool STATS>
+template <typename T, int BLOCK, int MAXG, bool STATS, bool VARC>
 __global__ void __launch_bounds__(BLOCK)
     k_step1d(const Inst1D *__restrict__ tab, const int32_t *__restrict__ order, T *__restrict__ pool,
-             int64_t step0, int32_t nsteps, int64_t burn_in, int32_t every, uint32_t mask, Stats1D st)
+             const T *__restrict__ coef, int64_t step0, int32_t nsteps, int64_t burn_in, int32_t every, uint32_t mask,
+             Stats1D st)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     __shared__ double red[3][BLOCK / 64];
@@ -111,6 +118,9 @@ __global__ void __launch_bounds__(BLOCK)
     T *U = reinterpret_cast<T *>(smem_raw);
     T *F = U + nmax_pad;
     T *Us = F + nmax_pad + 4;
+    T *Rf = Us + nmax_pad;       // VARC: conductance per face
+    T *Sf = Rf + nmax_pad + 4;   // VARC: noise factor per face (walls: sqrt 2 included)
+    T *Wc = Sf + nmax_pad + 4;   // VARC: capacity factor per cell
     const int tid = threadIdx.x;
 
     InstAcc *acc = st.acc + inst;
@@ -126,6 +136,22 @@ __global__ void __launch_bounds__(BLOCK)
     T *gU = pool + d.off;
 
     for (int i = tid; i < N; i += BLOCK) U[i] = gU[i];
+    if constexpr (VARC) {
+        if (d.k_off >= 0) {
+            const T *k = coef + d.k_off;
+            for (int f = tid; f < nf; f += BLOCK) {
+                Rf[f] = k[f];
+                Sf[f] = k[nf + f];
+            }
+            for (int i = tid; i < N; i += BLOCK) Wc[i] = k[2 * nf + i];
+        } else {
+            for (int f = tid; f < nf; f += BLOCK) {
+                Rf[f] = r;
+                Sf[f] = (dir && (f == 0 || f == N)) ? sgw : sg;
+            }
+            for (int i = tid; i < N; i += BLOCK) Wc[i] = T(1);
+        }
+    }
 
     // frozen-mode face amplitudes
     uint32_t clamps = 0;
@@ -159,16 +185,17 @@ __global__ void __launch_bounds__(BLOCK)
                 const int f = 4 * g + l;
                 if (f >= nf) continue;
                 T fl;
+                const T rf = VARC ? Rf[f] : r;
                 if (dir && f == 0) {
-                    fl = T(2) * r * (V[0] - uL);
-                    if (noise != 2) fl += sgw * amp_uL * z[s][l];
+                    fl = T(2) * rf * (V[0] - uL);
+                    if (noise != 2) fl += (VARC ? Sf[f] : sgw) * amp_uL * z[s][l];
                 } else if (dir && f == N) {
-                    fl = T(2) * r * (uR - V[N - 1]);
-                    if (noise != 2) fl += sgw * amp_uR * z[s][l];
+                    fl = T(2) * rf * (uR - V[N - 1]);
+                    if (noise != 2) fl += (VARC ? Sf[f] : sgw) * amp_uR * z[s][l];
                 } else {
                     const int a = f == 0 ? N - 1 : f - 1;
                     const T vl = V[a], vr = V[f];
-                    fl = r * (vr - vl);
+                    fl = rf * (vr - vl);
                     if (noise != 2) {
                         T am;
                         if (noise == 1)
@@ -176,7 +203,7 @@ __global__ void __launch_bounds__(BLOCK)
                                      : amp_u0;
                         else
                             am = face_amp<T>(eq, T(0.5) * (vl + vr), clamps);
-                        fl += sg * am * z[s][l];
+                        fl += (VARC ? Sf[f] : sg) * am * z[s][l];
                     }
                 }
                 F[f] = fl;
@@ -205,20 +232,20 @@ __global__ void __launch_bounds__(BLOCK)
         if (d.scheme == 0) {
             for (int i = tid; i < N; i += BLOCK) {
                 const int hi = (!dir && i + 1 == N) ? 0 : i + 1;
-                U[i] = U[i] + (F[hi] - F[i]);
+                U[i] = U[i] + (VARC ? Wc[i] * (F[hi] - F[i]) : (F[hi] - F[i]));
             }
             __syncthreads();
         } else {
             for (int i = tid; i < N; i += BLOCK) {
                 const int hi = (!dir && i + 1 == N) ? 0 : i + 1;
-                Us[i] = U[i] + (F[hi] - F[i]);
+                Us[i] = U[i] + (VARC ? Wc[i] * (F[hi] - F[i]) : (F[hi] - F[i]));
             }
             __syncthreads();
             flux_pass(Us, z);
             __syncthreads();
             for (int i = tid; i < N; i += BLOCK) {
                 const int hi = (!dir && i + 1 == N) ? 0 : i + 1;
-                U[i] = T(0.5) * ((U[i] + Us[i]) + (F[hi] - F[i]));
+                U[i] = T(0.5) * ((U[i] + Us[i]) + (VARC ? Wc[i] * (F[hi] - F[i]) : (F[hi] - F[i])));
             }
             __syncthreads();
         }
@@ -499,55 +526,67 @@ __global__ void __launch_bounds__(256)
 
 // ------------------------------------------------------------------ launchers
 
-template <typename T, int BLOCK, int MAXG>
-static hipError_t step1d_t(bool stats, int n_blocks, size_t smem, hipStream_t s, const Inst1D *tab,
-                           const int32_t *order, void *pool, int64_t step0, int32_t nsteps, int64_t burn_in,
-                           int32_t every, uint32_t mask, Stats1D st)
+struct Step1DLaunch {
+    int n_blocks;
+    size_t smem;
+    hipStream_t s;
+    const Inst1D *tab;
+    const int32_t *order;
+    void *pool;
+    const void *coef;
+    int64_t step0;
+    int32_t nsteps;
+    int64_t burn_in;
+    int32_t every;
+    uint32_t mask;
+    Stats1D st;
+};
+
+template <typename T, int BLOCK, int MAXG, bool STATS, bool VARC>
+static hipError_t step1d_k(const Step1DLaunch &a)
 {
-    if (stats)
-        hipLaunchKernelGGL((k_step1d<T, BLOCK, MAXG, true>), dim3(n_blocks), dim3(BLOCK), smem, s, tab, order,
-                           static_cast<T *>(pool), step0, nsteps, burn_in, every, mask, st);
-    else
-        hipLaunchKernelGGL((k_step1d<T, BLOCK, MAXG, false>), dim3(n_blocks), dim3(BLOCK), smem, s, tab, order,
-                           static_cast<T *>(pool), step0, nsteps, burn_in, every, mask, st);
+    hipLaunchKernelGGL((k_step1d<T, BLOCK, MAXG, STATS, VARC>), dim3(a.n_blocks), dim3(BLOCK), a.smem, a.s, a.tab,
+                       a.order, static_cast<T *>(a.pool), static_cast<const T *>(a.coef), a.step0, a.nsteps, a.burn_in,
+                       a.every, a.mask, a.st);
     return hipGetLastError();
 }
 
+template <typename T, int BLOCK, int MAXG>
+static hipError_t step1d_t(bool stats, bool varc, const Step1DLaunch &a)
+{
+    if (stats) return varc ? step1d_k<T, BLOCK, MAXG, true, true>(a) : step1d_k<T, BLOCK, MAXG, true, false>(a);
+    return varc ? step1d_k<T, BLOCK, MAXG, false, true>(a) : step1d_k<T, BLOCK, MAXG, false, false>(a);
+}
+
 template <typename T, int BLOCK>
-static hipError_t step1d_b(int maxg, bool stats, int n_blocks, size_t smem, hipStream_t s, const Inst1D *tab,
-                           const int32_t *order, void *pool, int64_t step0, int32_t nsteps, int64_t burn_in,
-                           int32_t every, uint32_t mask, Stats1D st)
+static hipError_t step1d_b(int maxg, bool stats, bool varc, const Step1DLaunch &a)
 {
     switch (maxg) {
-    case 1: return step1d_t<T, BLOCK, 1>(stats, n_blocks, smem, s, tab, order, pool, step0, nsteps, burn_in, every, mask, st);
-    case 2: return step1d_t<T, BLOCK, 2>(stats, n_blocks, smem, s, tab, order, pool, step0, nsteps, burn_in, every, mask, st);
-    case 4: return step1d_t<T, BLOCK, 4>(stats, n_blocks, smem, s, tab, order, pool, step0, nsteps, burn_in, every, mask, st);
-    case 8: return step1d_t<T, BLOCK, 8>(stats, n_blocks, smem, s, tab, order, pool, step0, nsteps, burn_in, every, mask, st);
+    case 1: return step1d_t<T, BLOCK, 1>(stats, varc, a);
+    case 2: return step1d_t<T, BLOCK, 2>(stats, varc, a);
+    case 4: return step1d_t<T, BLOCK, 4>(stats, varc, a);
+    case 8: return step1d_t<T, BLOCK, 8>(stats, varc, a);
     default: return hipErrorInvalidValue;
     }
 }
 
 template <typename T>
-static hipError_t step1d_p(int block, int maxg, bool stats, int n_blocks, size_t smem, hipStream_t s,
-                           const Inst1D *tab, const int32_t *order, void *pool, int64_t step0, int32_t nsteps,
-                           int64_t burn_in, int32_t every, uint32_t mask, Stats1D st)
+static hipError_t step1d_p(int block, int maxg, bool stats, bool varc, const Step1DLaunch &a)
 {
     switch (block) {
-    case 64: return step1d_b<T, 64>(maxg, stats, n_blocks, smem, s, tab, order, pool, step0, nsteps, burn_in, every, mask, st);
-    case 256: return step1d_b<T, 256>(maxg, stats, n_blocks, smem, s, tab, order, pool, step0, nsteps, burn_in, every, mask, st);
+    case 64: return step1d_b<T, 64>(maxg, stats, varc, a);
+    case 256: return step1d_b<T, 256>(maxg, stats, varc, a);
     default: return hipErrorInvalidValue;
     }
 }
 
-hipError_t launch_step1d(int prec, int block, int maxg, bool stats, int n_blocks, size_t smem, hipStream_t s,
-                         const Inst1D *tab, const int32_t *order, void *pool, int64_t step0, int32_t nsteps,
-                         int64_t burn_in, int32_t every, uint32_t mask, Stats1D st)
+hipError_t launch_step1d(int prec, int block, int maxg, bool stats, bool varc, int n_blocks, size_t smem,
+                         hipStream_t s, const Inst1D *tab, const int32_t *order, void *pool, const void *coef,
+                         int64_t step0, int32_t nsteps, int64_t burn_in, int32_t every, uint32_t mask, Stats1D st)
 {
-    if (prec == 0)
-        return step1d_p<float>(block, maxg, stats, n_blocks, smem, s, tab, order, pool, step0, nsteps, burn_in,
-                               every, mask, st);
-    return step1d_p<double>(block, maxg, stats, n_blocks, smem, s, tab, order, pool, step0, nsteps, burn_in,
-                            every, mask, st);
+    const Step1DLaunch a{n_blocks, smem, s, tab, order, pool, coef, step0, nsteps, burn_in, every, mask, st};
+    if (prec == 0) return step1d_p<float>(block, maxg, stats, varc, a);
+    return step1d_p<double>(block, maxg, stats, varc, a);
 }
 
 hipError_t launch_init1d(int prec, int n_inst, int nmax, hipStream_t s, const Inst1D *tab, const double *init_sd,

@@ -40,7 +40,7 @@ class InstanceDesc(C.Structure):
                 ("scheme", C.c_int32), ("noise", C.c_int32), ("r", C.c_double), ("eps", C.c_double),
                 ("u0", C.c_double), ("u_left", C.c_double), ("u_right", C.c_double),
                 ("init_sd", C.c_double), ("seed", C.c_uint64), ("realisation", C.c_uint32),
-                ("reserved", C.c_uint32)]
+                ("reserved", C.c_uint32), ("cond", C.POINTER(C.c_double)), ("cap", C.POINTER(C.c_double))]
 
 
 class Config(C.Structure):
@@ -147,6 +147,8 @@ class Instance:
     init_sd: float = 0.0
     seed: int = 0
     realisation: int = 0
+    cond: object = None      # 1D: N conductivity ratios (material varying along the rod)
+    cap: object = None       # 1D: N heat-capacity ratios
 
     @property
     def dim(self) -> int:
@@ -160,8 +162,13 @@ class Instance:
         n = tuple(self.n) + (1,) * (3 - len(self.n))
         ul = self.u0 if self.u_left is None else self.u_left
         ur = self.u0 if self.u_right is None else self.u_right
+        # the arrays are read during she_create / she_arena_bytes; the caller of
+        # c() keeps this object (and so the arrays) alive meanwhile
+        self._arrays = [None if a is None else np.ascontiguousarray(a, dtype=np.float64)
+                        for a in (self.cond, self.cap)]
+        ptrs = [C.POINTER(C.c_double)() if a is None else _dptr(a) for a in self._arrays]
         return InstanceDesc(len(self.n), (C.c_int32 * 3)(*n), self.eq, self.bc, self.scheme, self.noise,
-                            self.r, self.eps, self.u0, ul, ur, self.init_sd, self.seed, self.realisation, 0)
+                            self.r, self.eps, self.u0, ul, ur, self.init_sd, self.seed, self.realisation, 0, *ptrs)
 
 
 class Handle:

@@ -17,6 +17,10 @@ configurations:
       in [0, 0.3], FE or PC with probability 1/2 each, r = 0.1, eps = 1e-2
   c5  3D periodic Dean-Kawasaki 256^3, FE, D dt/dx^2 = 0.05, c0 = 1e3 per
       cell volume dV = 1, perturbed start
+  rod composite rod of the exercises: two materials, the first half with the
+      reference properties, the second with conductivity ratio `k_ratio` and
+      heat-capacity ratio `c_ratio` (parameters: the paper gives no values
+      for the second material), Dirichlet walls, equilibrium or a gradient
 """
 from __future__ import annotations
 
@@ -30,11 +34,26 @@ EM, HEUN = 0, 1
 
 
 def instance(n, eq=HEAT, bc=PERIODIC, scheme=EM, noise=0, r=0.2, eps=1e-2, u0=1.0, u_left=None,
-             u_right=None, init_sd=0.0, seed=0, realisation=0) -> dict:
+             u_right=None, init_sd=0.0, seed=0, realisation=0, cond=None, cap=None) -> dict:
     return dict(n=tuple(int(v) for v in n), eq=eq, bc=bc, scheme=scheme, noise=noise, r=float(r),
                 eps=float(eps), u0=float(u0), u_left=float(u0 if u_left is None else u_left),
                 u_right=float(u0 if u_right is None else u_right), init_sd=float(init_sd), seed=int(seed),
-                realisation=int(realisation))
+                realisation=int(realisation),
+                cond=None if cond is None else tuple(float(v) for v in cond),
+                cap=None if cap is None else tuple(float(v) for v in cap))
+
+
+def rod(n: int = 64, k_ratio: float = 3.0, c_ratio: float = 0.7, t_left: float = 1.1, t_right: float = 0.9,
+        scheme: int = EM, r: float = 0.05, eps: float = 1e-3, realisations: int = 1, steps: int = 100000) -> dict:
+    """Composite rod: cells [0, n/2) of the reference material, [n/2, n) of
+    the second one."""
+    cond = [1.0] * (n // 2) + [k_ratio] * (n - n // 2)
+    cap = [1.0] * (n // 2) + [c_ratio] * (n - n // 2)
+    t0 = 0.5 * (t_left + t_right)
+    insts = [instance((n,), bc=DIRICHLET, scheme=scheme, r=r, eps=eps, u0=t0, u_left=t_left, u_right=t_right,
+                      init_sd=math.sqrt(eps) * t0, realisation=q, cond=cond, cap=cap) for q in range(realisations)]
+    return dict(name="rod_composite_n%d" % n, precision=0, steps=steps, burn_in=steps // 10, sample_every=10,
+                instances=insts)
 
 
 def c1(eps: float = 1e-2) -> dict:

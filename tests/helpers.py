@@ -25,14 +25,15 @@ def oracle_desc(inst: dict, precision: int) -> oracle.Desc:
     return oracle.Desc(dim=len(inst["n"]), n=n, eq=inst["eq"], bc=inst["bc"], scheme=inst["scheme"],
                        noise=inst["noise"], r=r, sigma=s, u0=inst["u0"], u_left=inst["u_left"],
                        u_right=inst["u_right"], init_sd=inst["init_sd"], seed=inst["seed"],
-                       realisation=inst["realisation"])
+                       realisation=inst["realisation"], cond=inst.get("cond"), cap=inst.get("cap"))
 
 
 def gpu_instance(she, inst: dict):
     return she.Instance(n=tuple(inst["n"]), eq=inst["eq"], bc=inst["bc"], scheme=inst["scheme"],
                         noise=inst["noise"], r=inst["r"], eps=inst["eps"], u0=inst["u0"],
                         u_left=inst["u_left"], u_right=inst["u_right"], init_sd=inst["init_sd"],
-                        seed=inst["seed"], realisation=inst["realisation"])
+                        seed=inst["seed"], realisation=inst["realisation"], cond=inst.get("cond"),
+                        cap=inst.get("cap"))
 
 
 def max_rel(a: np.ndarray, b: np.ndarray) -> float:

@@ -94,6 +94,26 @@ def test_time_correlation_settings():
     assert e.value.status == she.EUNSUPPORTED
 
 
+def test_composite_rod_validation():
+    def arena(**kw):
+        return she.Handle.arena_bytes([gpu_instance(she, W.instance((16,), bc=W.DIRICHLET, r=0.1, **kw))])
+    base = arena()
+    assert arena(cond=[1.0] * 8 + [3.0] * 8, cap=[1.0] * 8 + [0.7] * 8) > base   # coefficient block
+    cases = [(dict(cond=[1.0] * 15 + [0.0]), she.EINVAL),
+             (dict(cap=[1.0] * 15 + [float("nan")]), she.EINVAL),
+             (dict(cond=[20.0] * 16), she.EUNSTABLE),
+             (dict(cap=[0.1] * 16), she.EUNSTABLE),
+             (dict(cond=[2.0] * 16, noise=1, u_left=1.0, u_right=2.0), she.EUNSUPPORTED)]
+    for kw, status in cases:
+        with pytest.raises(she.SheError) as e:
+            arena(**kw)
+        assert e.value.status == status, kw
+    arena(cond=[2.0] * 16, noise=1)                                 # equilibrium: allowed
+    with pytest.raises(she.SheError) as e:
+        she.Handle.arena_bytes([gpu_instance(she, W.instance((8, 8), r=0.1, cond=[1.0] * 64))])
+    assert e.value.status == she.EUNSUPPORTED
+
+
 def test_arena_bytes_scale_with_problem():
     small = she.Handle.arena_bytes([gpu_instance(she, W.instance((64, 64), r=0.1))])
     big = she.Handle.arena_bytes([gpu_instance(she, W.instance((512, 512), r=0.1))])

@@ -132,6 +132,49 @@ CASES_2D = [((64, 48), W.EM, W.HEAT), ((64, 48), W.HEUN, W.HEAT), ((32, 32), W.E
             ((16, 16), W.HEUN, W.HEAT), ((1024, 3), W.EM, W.HEAT), ((8, 40), W.EM, W.HEAT)]
 
 
+@pytest.mark.parametrize("precision,scheme", [(0, W.EM), (0, W.HEUN), (1, W.HEUN)])
+def test_composite_rod_state_parity(she, precision, scheme):
+    """A composite Dirichlet rod with a gradient and a periodic composite ring
+    share a batch with a uniform rod; each matches the oracle, and the
+    uniform rod is bit-identical to a batch of its own."""
+    rod = W.rod(n=64, scheme=scheme)["instances"][0]
+    ring = W.instance((32,), scheme=scheme, r=0.05, eps=1e-3, init_sd=0.03, realisation=2,
+                      cond=[1.0] * 16 + [2.5] * 16, cap=[1.0] * 16 + [0.8] * 16)
+    plain = inst1d((40,), W.PERIODIC, scheme, W.HEAT, 1)
+    insts = [rod, ring, plain]
+    h = she.Handle([gpu_instance(she, i) for i in insts], precision=precision)
+    init = [h.read_field(q) for q in range(3)]
+    steps = 10000 if precision == 0 else 3000
+    h.step(steps)
+    tol = 1e-5 if precision == 0 else 1e-12
+    for q in range(3):
+        u = init[q].copy()
+        oracle.advance(oracle_desc(insts[q], precision), u, 0, steps)
+        assert max_rel(h.read_field(q), u) <= tol, q
+    alone = she.Handle([gpu_instance(she, plain)], precision=precision)
+    alone.step(steps)
+    np.testing.assert_array_equal(alone.read_field(0), h.read_field(2))
+    alone.close()
+    h.close()
+
+
+def test_composite_rod_statistics_parity(she):
+    cfg = W.rod(n=48, steps=20000)
+    inst = cfg["instances"][0]
+    h = she.Handle([gpu_instance(she, inst)], precision=0, burn_in=2000, sample_every=10,
+                   stats=she.STAT_MOMENTS | she.STAT_CORR)
+    init = h.read_field(0)
+    h.run(20000)
+    g = h.stats(0, corr=True)
+    h.close()
+    st, _ = oracle_stats_run(inst, 0, init, 20000, 2000, 10, corr=True)
+    assert g["n_samples"] == st.n_samples == 1800
+    assert max_rel(g["mean"], st.mean()) < 1e-5
+    assert max_rel(g["var"], st.var()) < 1e-3
+    cov = st.cov()
+    assert np.max(np.abs(g["corr"] - cov)) < 1e-3 * np.max(np.abs(np.diag(cov)))
+
+
 def inst2d(n, scheme, eq, realisation=0):
     if eq == W.HEAT:
         return W.instance(n, eq=eq, scheme=scheme, r=0.1, eps=1e-2, u0=1.0, init_sd=0.1, realisation=realisation)
