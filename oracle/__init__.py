@@ -53,7 +53,7 @@ class _Desc(C.Structure):
                 ("init_sd", C.c_double), ("seed", C.c_uint64),
                 ("realisation", C.c_uint32), ("pad_", C.c_uint32),
                 ("face_r", C.POINTER(C.c_double)), ("face_s", C.POINTER(C.c_double)),
-                ("cell_w", C.POINTER(C.c_double))]
+                ("cell_w", C.POINTER(C.c_double)), ("nu", C.c_double)]
 
 
 class _Stats(C.Structure):
@@ -104,7 +104,7 @@ class Desc:
     """One instance of the scheme (field meanings as in ``she_oracle.c``)."""
     dim: int = 1
     n: tuple = (64, 1, 1)
-    eq: int = 0            # 0 heat, 1 Dean-Kawasaki
+    eq: int = 0            # 0 heat, 1 Dean-Kawasaki, 2 stochastic Burgers (1D)
     bc: int = 0            # 0 periodic, 1 Dirichlet (1D)
     scheme: int = 0        # 0 FE, 1 PC
     noise: int = 0         # 0 instantaneous, 1 deterministic face value, 2 off
@@ -118,6 +118,7 @@ class Desc:
     realisation: int = 0
     cond: object = None    # 1D, optional: N conductivity ratios lambda_i / lambda_ref
     cap: object = None     # 1D, optional: N heat-capacity ratios (rho c_V)_i / (rho c_V)_ref
+    nu: float = 0.0        # Burgers: Courant number a dt / dx
 
     def coefficients(self):
         """Per-face conductance r_f and noise factor s_f, per-cell w_i of a rod
@@ -152,7 +153,7 @@ class Desc:
         ptrs = [_dptr(a) for a in self._keep] if co is not None else [null, null, null]
         return _Desc(self.dim, (C.c_int32 * 3)(*n), self.eq, self.bc, self.scheme,
                      self.noise, self.r, self.sigma, self.u0, self.u_left, self.u_right,
-                     self.init_sd, self.seed, self.realisation, 0, *ptrs)
+                     self.init_sd, self.seed, self.realisation, 0, *ptrs, self.nu)
 
     @property
     def ncells(self) -> int:

@@ -27,6 +27,12 @@
  *   - 1D time correlation <dT_i^n dT_i^(n-m)> over sample lags m (the first
  *     of the suggested exercises, Sec. 6): sums over samples n >= m of
  *     delta_i(n) delta_i(n-m), with the last L samples kept in a ring;
+ *   - stochastic Burgers equation (Sec. 5, menagerie):
+ *     dc/dt = -d/dx( a c (1-c) - D dc/dx + sqrt(2 D c (1-c)) Z ), in the same
+ *     face-flux form: the face value is the arithmetic mean c_f, the flux
+ *     gains -nu c_f (1 - c_f) (nu = a dt/dx, centred) and the noise amplitude
+ *     is sqrt(max(c_f (1 - c_f), 0)); the paper gives no scheme for it, so
+ *     this is the SHE/DK framework of Sec. 3 applied to it (1D);
  *   - 1D materials that vary along the rod (the composite-rod exercise,
  *     Sec. 6): the conservative form rho c_V dT/dt = -d/dx(flux) of eq. SHE
  *     with a conductance r_f and noise factor s_f per face and a factor
@@ -62,7 +68,8 @@
 typedef struct {
     int32_t dim;         /* 1, 2 or 3                                         */
     int32_t n[3];        /* cells per axis (unused axes = 1)                  */
-    int32_t eq;          /* 0 = heat (T), 1 = species number density (DK)      */
+    int32_t eq;          /* 0 = heat (T), 1 = species number density (DK),
+                            2 = stochastic Burgers (c, 1D)                     */
     int32_t bc;          /* 0 = periodic, 1 = Dirichlet walls in x (1D only)  */
     int32_t scheme;      /* 0 = forward Euler, 1 = predictor-corrector        */
     int32_t noise;       /* 0 = instantaneous face value, 1 = deterministic
@@ -79,6 +86,7 @@ typedef struct {
     const double *face_r;  /* 1D, optional: conductance per face (replaces r)  */
     const double *face_s;  /* 1D, optional: noise factor per face (replaces sigma) */
     const double *cell_w;  /* 1D, optional: capacity factor per cell (else 1)  */
+    double nu;             /* Burgers: Courant number a dt / dx               */
 } or_desc;
 
 typedef struct {
@@ -221,7 +229,8 @@ static int check_desc(const or_desc *d)
     }
     if (d->bc == 1 && d->dim != 1) return -1;
     if (d->bc != 0 && d->bc != 1) return -1;
-    if (d->eq != 0 && d->eq != 1) return -1;
+    if (d->eq != 0 && d->eq != 1 && d->eq != 2) return -1;
+    if (d->eq == 2 && d->dim != 1) return -1;
     if (d->scheme != 0 && d->scheme != 1) return -1;
     if (d->noise < 0 || d->noise > 2) return -1;
     if (d->dim == 1 && d->bc == 0 && d->n[0] < 2) return -1;
@@ -264,11 +273,12 @@ int or_init(const or_desc *d, double *u)
 static double amplitude(const or_desc *d, double v, int64_t *clamps)
 {
     if (d->eq == 0) return v;
-    if (v < 0.0) {
+    const double q = d->eq == 2 ? v * (1.0 - v) : v;   /* Burgers: c (1 - c) */
+    if (q < 0.0) {
         if (clamps) ++*clamps;
         return 0.0;
     }
-    return sqrt(v);
+    return sqrt(q);
 }
 
 /* out[i] = sum over directions of (flux through the high face of i) minus
@@ -284,18 +294,20 @@ static void divergence(const or_desc *d, const double *u, const double *z,
         /* per-face conductance and noise factor (uniform unless given) */
 #define RF(f) (d->face_r ? d->face_r[f] : r)
 #define SF(f) (d->face_s ? d->face_s[f] : s)
+        /* Burgers hyperbolic flux through a face with value c (times nu) */
+#define HYP(c) (d->eq == 2 ? d->nu * (c) * (1.0 - (c)) : 0.0)
         if (d->bc == 1) {
             const double wall = sqrt(2.0);
             for (int64_t f = 0; f <= N; ++f) {
                 double fl;
                 if (f == 0) {
-                    fl = 2.0 * RF(0) * (u[0] - d->u_left);
+                    fl = 2.0 * RF(0) * (u[0] - d->u_left) - HYP(d->u_left);
                     if (noisy) fl += wall * SF(0) * amplitude(d, d->u_left, clamps) * z[0];
                 } else if (f == N) {
-                    fl = 2.0 * RF(N) * (d->u_right - u[N - 1]);
+                    fl = 2.0 * RF(N) * (d->u_right - u[N - 1]) - HYP(d->u_right);
                     if (noisy) fl += wall * SF(N) * amplitude(d, d->u_right, clamps) * z[N];
                 } else {
-                    fl = RF(f) * (u[f] - u[f - 1]);
+                    fl = RF(f) * (u[f] - u[f - 1]) - HYP(0.5 * (u[f - 1] + u[f]));
                     if (noisy) {
                         double v = d->noise == 1
                                        ? d->u_left + (d->u_right - d->u_left) * (double)f / N
@@ -309,7 +321,7 @@ static void divergence(const or_desc *d, const double *u, const double *z,
         } else {
             for (int64_t f = 0; f < N; ++f) {
                 int64_t a = (f + N - 1) % N;
-                double fl = RF(f) * (u[f] - u[a]);
+                double fl = RF(f) * (u[f] - u[a]) - HYP(0.5 * (u[a] + u[f]));
                 if (noisy) {
                     double v = d->noise == 1 ? d->u0 : 0.5 * (u[a] + u[f]);
                     fl += SF(f) * amplitude(d, v, clamps) * z[f];
@@ -320,6 +332,7 @@ static void divergence(const or_desc *d, const double *u, const double *z,
         }
 #undef RF
 #undef SF
+#undef HYP
         if (d->cell_w)
             for (int64_t i = 0; i < N; ++i) out[i] = d->cell_w[i] * out[i];
         return;
