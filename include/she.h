@@ -66,7 +66,10 @@ typedef enum {
     SHE_EUNSUPPORTED = -7  /* valid in the method, not provided by a kernel   */
 } she_status;
 
-enum { SHE_HEAT = 0, SHE_SPECIES = 1 };                       /* equation      */
+/* equation: SHE (Sec. 2 eq. SHE), Dean-Kawasaki species diffusion (Sec. 4
+ * eq. DK), stochastic Burgers (Sec. 5, 1D: hyperbolic flux a c (1-c), noise
+ * sqrt(2 D c (1-c)); the same face-flux scheme with the arithmetic face value) */
+enum { SHE_HEAT = 0, SHE_SPECIES = 1, SHE_BURGERS = 2 };
 enum { SHE_PERIODIC = 0, SHE_DIRICHLET = 1 };                 /* x boundary    */
 enum { SHE_EM = 0, SHE_HEUN = 1 };                            /* FE / PC       */
 enum { SHE_NOISE_INSTANT = 0, SHE_NOISE_FROZEN = 1, SHE_NOISE_OFF = 2 };
@@ -97,7 +100,7 @@ typedef struct {
     int32_t dim;          /* 1, 2, 3                                          */
     int32_t n[3];         /* cells per axis, unused axes = 1.  2D/3D: n[0] a
                              power of two in [8, 1024]                         */
-    int32_t eq;           /* SHE_HEAT or SHE_SPECIES                          */
+    int32_t eq;           /* SHE_HEAT, SHE_SPECIES or SHE_BURGERS (1D)        */
     int32_t bc;           /* SHE_PERIODIC or SHE_DIRICHLET (dim == 1)         */
     int32_t scheme;       /* SHE_EM or SHE_HEUN                               */
     int32_t noise;        /* SHE_NOISE_*: face amplitude from the current
@@ -129,6 +132,11 @@ typedef struct {
                              cap_i <= 2, else SHE_EUNSTABLE.  Deterministic
                              face values (SHE_NOISE_FROZEN) need
                              u_left == u_right.                              */
+    double nu;            /* SHE_BURGERS: Courant number a dt / dx (the flux
+                             gains -nu c_f (1 - c_f)); must be 0 otherwise.
+                             SHE_EUNSTABLE unless every mode's one-step factor
+                             of the linearised scheme, at the steepest slope
+                             |1 - 2c| = 1, has modulus <= 1.                 */
 } she_instance_desc;
 
 typedef struct {

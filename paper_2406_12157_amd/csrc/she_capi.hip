@@ -133,6 +133,25 @@ std::vector<double> face_conductivity(const she_instance_desc &d)
     return lf;
 }
 
+// Largest modulus over wavenumbers theta of the one-step factor of the
+// linearised Burgers scheme at the steepest slope |1 - 2c| = 1:
+// L = -4 r sin^2(theta/2) - i nu sin(theta), G = 1 + L (FE), 1 + L + L^2/2 (PC).
+double burgers_growth(double r, double nu, int scheme)
+{
+    double worst = 0.0;
+    for (int j = 0; j <= 4096; ++j) {
+        const double th = M_PI * j / 4096.0;
+        const double lr = -4.0 * r * std::sin(0.5 * th) * std::sin(0.5 * th), li = -nu * std::sin(th);
+        double gr = 1.0 + lr, gi = li;
+        if (scheme == SHE_HEUN) {
+            gr += 0.5 * (lr * lr - li * li);
+            gi += lr * li;
+        }
+        worst = std::max(worst, std::sqrt(gr * gr + gi * gi));
+    }
+    return worst;
+}
+
 // Gershgorin bound of the FE operator w_i (sum of row i's conductances, the
 // Dirichlet wall face counted twice on the diagonal); the step is stable
 // when it is at most 2.
@@ -206,7 +225,16 @@ she_status validate(const she_config *cfg, she_handle *h)
             if (a < d.dim && d.n[a] < 1) return fail(nullptr, SHE_EINVAL, pre + "cell counts must be >= 1");
             if (a >= d.dim && d.n[a] != 1) return fail(nullptr, SHE_EINVAL, pre + "unused axes must have n = 1");
         }
-        if (d.eq != SHE_HEAT && d.eq != SHE_SPECIES) return fail(nullptr, SHE_EINVAL, pre + "bad equation");
+        if (d.eq != SHE_HEAT && d.eq != SHE_SPECIES && d.eq != SHE_BURGERS)
+            return fail(nullptr, SHE_EINVAL, pre + "bad equation");
+        if (!std::isfinite(d.nu) || (d.nu != 0.0 && d.eq != SHE_BURGERS))
+            return fail(nullptr, SHE_EINVAL, pre + "nu must be finite, and 0 unless eq = SHE_BURGERS");
+        if (d.eq == SHE_BURGERS) {
+            if (d.dim != 1) return fail(nullptr, SHE_EUNSUPPORTED, pre + "SHE_BURGERS is provided for 1D");
+            if (d.cond || d.cap) return fail(nullptr, SHE_EUNSUPPORTED, pre + "SHE_BURGERS with cond / cap");
+            if (burgers_growth(d.r, d.nu, d.scheme) > 1.0 + 1e-12)
+                return fail(nullptr, SHE_EUNSTABLE, pre + "Burgers step amplifies a mode (reduce nu or r)");
+        }
         if (d.bc != SHE_PERIODIC && d.bc != SHE_DIRICHLET) return fail(nullptr, SHE_EINVAL, pre + "bad boundary");
         if (d.scheme != SHE_EM && d.scheme != SHE_HEUN) return fail(nullptr, SHE_EINVAL, pre + "bad scheme");
         if (d.noise < 0 || d.noise > 2) return fail(nullptr, SHE_EINVAL, pre + "bad noise mode");
@@ -277,6 +305,7 @@ static she_status plan_1d(she_handle *h, const she_config *cfg, Plan &plan)
         t.u0 = d.u0;
         t.uL = d.bc == SHE_DIRICHLET ? d.u_left : d.u0;
         t.uR = d.bc == SHE_DIRICHLET ? d.u_right : d.u0;
+        t.nu = d.nu;
         if (corr) {
             if (d.n[0] > 1024) return fail(nullptr, SHE_EUNSUPPORTED, "SHE_STAT_CORR needs N <= 1024");
             t.x_off = xo;

@@ -21,10 +21,11 @@ struct Inst1D {
     int32_t bc;         // 0 periodic, 1 Dirichlet
     int32_t scheme;     // 0 FE, 1 PC
     int32_t noise;      // 0 instantaneous, 1 frozen, 2 off
-    int32_t eq;         // 0 heat, 1 species
+    int32_t eq;         // 0 heat, 1 species, 2 Burgers
     uint32_t realisation;
     uint64_t seed;
     double r, sigma, u0, uL, uR;
+    double nu;          // Burgers: Courant number
 };
 
 // Per-instance accumulators that are not per cell (device).

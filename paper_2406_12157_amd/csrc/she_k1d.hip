@@ -35,15 +35,18 @@ namespace she {
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 
+// Noise amplitude of a face with value v: v (SHE), sqrt(v) (DK),
+// sqrt(v (1 - v)) (Burgers); a negative radicand is clamped and counted.
 template <typename T>
 __device__ __forceinline__ T face_amp(int eq, T v, uint32_t &clamps)
 {
     if (eq == 0) return v;
-    if (v < T(0)) {
+    const T q = eq == 2 ? v * (T(1) - v) : v;
+    if (q < T(0)) {
         ++clamps;
         return T(0);
     }
-    return sqrt(v);
+    return sqrt(q);
 }
 
 __device__ __forceinline__ f32x4 mfma16x16x4(float a, float b, f32x4 c)
@@ -131,6 +134,7 @@ __global__ void __launch_bounds__(BLOCK)
     const T sgw = static_cast<T>(d.sigma * 1.41421356237309504880);
     const T uL = static_cast<T>(d.uL), uR = static_cast<T>(d.uR);
     const int eq = d.eq, noise = d.noise;
+    const T nu = static_cast<T>(d.nu);  // Burgers hyperbolic flux nu c_f (1 - c_f), 0 otherwise
     const bool dir = d.bc == 1;
     const PhiloxKey key = make_key(d.seed);
     T *gU = pool + d.off;
@@ -188,14 +192,20 @@ __global__ void __launch_bounds__(BLOCK)
                 const T rf = VARC ? Rf[f] : r;
                 if (dir && f == 0) {
                     fl = T(2) * rf * (V[0] - uL);
+                    if (eq == 2) fl -= nu * uL * (T(1) - uL);
                     if (noise != 2) fl += (VARC ? Sf[f] : sgw) * amp_uL * z[s][l];
                 } else if (dir && f == N) {
                     fl = T(2) * rf * (uR - V[N - 1]);
+                    if (eq == 2) fl -= nu * uR * (T(1) - uR);
                     if (noise != 2) fl += (VARC ? Sf[f] : sgw) * amp_uR * z[s][l];
                 } else {
                     const int a = f == 0 ? N - 1 : f - 1;
                     const T vl = V[a], vr = V[f];
                     fl = rf * (vr - vl);
+                    if (eq == 2) {
+                        const T cf = T(0.5) * (vl + vr);
+                        fl -= nu * cf * (T(1) - cf);
+                    }
                     if (noise != 2) {
                         T am;
                         if (noise == 1)

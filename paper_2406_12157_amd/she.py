@@ -16,7 +16,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libshe.so")
 
-HEAT, SPECIES = 0, 1
+HEAT, SPECIES, BURGERS = 0, 1, 2
 PERIODIC, DIRICHLET = 0, 1
 EM, HEUN = 0, 1
 NOISE_INSTANT, NOISE_FROZEN, NOISE_OFF = 0, 1, 2
@@ -40,7 +40,8 @@ class InstanceDesc(C.Structure):
                 ("scheme", C.c_int32), ("noise", C.c_int32), ("r", C.c_double), ("eps", C.c_double),
                 ("u0", C.c_double), ("u_left", C.c_double), ("u_right", C.c_double),
                 ("init_sd", C.c_double), ("seed", C.c_uint64), ("realisation", C.c_uint32),
-                ("reserved", C.c_uint32), ("cond", C.POINTER(C.c_double)), ("cap", C.POINTER(C.c_double))]
+                ("reserved", C.c_uint32), ("cond", C.POINTER(C.c_double)), ("cap", C.POINTER(C.c_double)),
+                ("nu", C.c_double)]
 
 
 class Config(C.Structure):
@@ -149,6 +150,7 @@ class Instance:
     realisation: int = 0
     cond: object = None      # 1D: N conductivity ratios (material varying along the rod)
     cap: object = None       # 1D: N heat-capacity ratios
+    nu: float = 0.0          # BURGERS: Courant number a dt / dx
 
     @property
     def dim(self) -> int:
@@ -168,7 +170,8 @@ class Instance:
                         for a in (self.cond, self.cap)]
         ptrs = [C.POINTER(C.c_double)() if a is None else _dptr(a) for a in self._arrays]
         return InstanceDesc(len(self.n), (C.c_int32 * 3)(*n), self.eq, self.bc, self.scheme, self.noise,
-                            self.r, self.eps, self.u0, ul, ur, self.init_sd, self.seed, self.realisation, 0, *ptrs)
+                            self.r, self.eps, self.u0, ul, ur, self.init_sd, self.seed, self.realisation, 0, *ptrs,
+                            self.nu)
 
 
 class Handle:

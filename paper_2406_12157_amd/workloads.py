@@ -17,6 +17,9 @@ configurations:
       in [0, 0.3], FE or PC with probability 1/2 each, r = 0.1, eps = 1e-2
   c5  3D periodic Dean-Kawasaki 256^3, FE, D dt/dx^2 = 0.05, c0 = 1e3 per
       cell volume dV = 1, perturbed start
+  burgers  stochastic Burgers ring: N = 256 periodic, c0 = 0.15, r = 0.25,
+      Courant number 0.6, eps = 1/dV = 1e-4, perturbed start (batch of
+      realisations)
   rod composite rod of the exercises: two materials, the first half with the
       reference properties, the second with conductivity ratio `k_ratio` and
       heat-capacity ratio `c_ratio` (parameters: the paper gives no values
@@ -28,19 +31,27 @@ import math
 
 import numpy as np
 
-HEAT, SPECIES = 0, 1
+HEAT, SPECIES, BURGERS = 0, 1, 2
 PERIODIC, DIRICHLET = 0, 1
 EM, HEUN = 0, 1
 
 
 def instance(n, eq=HEAT, bc=PERIODIC, scheme=EM, noise=0, r=0.2, eps=1e-2, u0=1.0, u_left=None,
-             u_right=None, init_sd=0.0, seed=0, realisation=0, cond=None, cap=None) -> dict:
+             u_right=None, init_sd=0.0, seed=0, realisation=0, cond=None, cap=None, nu=0.0) -> dict:
     return dict(n=tuple(int(v) for v in n), eq=eq, bc=bc, scheme=scheme, noise=noise, r=float(r),
                 eps=float(eps), u0=float(u0), u_left=float(u0 if u_left is None else u_left),
                 u_right=float(u0 if u_right is None else u_right), init_sd=float(init_sd), seed=int(seed),
                 realisation=int(realisation),
                 cond=None if cond is None else tuple(float(v) for v in cond),
-                cap=None if cap is None else tuple(float(v) for v in cap))
+                cap=None if cap is None else tuple(float(v) for v in cap), nu=float(nu))
+
+
+def burgers(n: int = 256, realisations: int = 1, scheme: int = EM, c0: float = 0.15, nu: float = 0.6,
+            r: float = 0.25, eps: float = 1e-4, steps: int = 100000) -> dict:
+    insts = [instance((n,), eq=BURGERS, scheme=scheme, r=r, eps=eps, u0=c0, nu=nu,
+                      init_sd=math.sqrt(eps * c0 * (1 - c0)), realisation=q) for q in range(realisations)]
+    return dict(name="burgers_periodic_n%d_x%d" % (n, realisations), precision=0, steps=steps, burn_in=steps // 10,
+                sample_every=10, instances=insts)
 
 
 def rod(n: int = 64, k_ratio: float = 3.0, c_ratio: float = 0.7, t_left: float = 1.1, t_right: float = 0.9,

@@ -25,7 +25,8 @@ def oracle_desc(inst: dict, precision: int) -> oracle.Desc:
     return oracle.Desc(dim=len(inst["n"]), n=n, eq=inst["eq"], bc=inst["bc"], scheme=inst["scheme"],
                        noise=inst["noise"], r=r, sigma=s, u0=inst["u0"], u_left=inst["u_left"],
                        u_right=inst["u_right"], init_sd=inst["init_sd"], seed=inst["seed"],
-                       realisation=inst["realisation"], cond=inst.get("cond"), cap=inst.get("cap"))
+                       realisation=inst["realisation"], cond=inst.get("cond"), cap=inst.get("cap"),
+                       nu=f32(inst.get("nu", 0.0)) if precision == 0 else inst.get("nu", 0.0))
 
 
 def gpu_instance(she, inst: dict):
@@ -33,7 +34,7 @@ def gpu_instance(she, inst: dict):
                         noise=inst["noise"], r=inst["r"], eps=inst["eps"], u0=inst["u0"],
                         u_left=inst["u_left"], u_right=inst["u_right"], init_sd=inst["init_sd"],
                         seed=inst["seed"], realisation=inst["realisation"], cond=inst.get("cond"),
-                        cap=inst.get("cap"))
+                        cap=inst.get("cap"), nu=inst.get("nu", 0.0))
 
 
 def max_rel(a: np.ndarray, b: np.ndarray) -> float:

@@ -114,6 +114,20 @@ def test_composite_rod_validation():
     assert e.value.status == she.EUNSUPPORTED
 
 
+def test_burgers_validation():
+    ok = W.instance((64,), eq=W.BURGERS, r=0.25, eps=1e-4, u0=0.15, nu=0.6)
+    she.Handle.arena_bytes([gpu_instance(she, ok)])
+    cases = [(W.instance((64,), r=0.25, nu=0.3), she.EINVAL),                              # nu on the heat equation
+             (W.instance((64,), eq=W.BURGERS, r=0.05, u0=0.2, nu=0.9), she.EUNSTABLE),      # nu^2 > 2 r
+             (W.instance((16, 16), eq=W.BURGERS, r=0.1, u0=0.2, nu=0.1), she.EUNSUPPORTED),
+             (W.instance((64,), eq=W.BURGERS, r=0.25, u0=0.2, nu=0.3, cond=[1.0] * 64), she.EUNSUPPORTED),
+             (W.instance((64,), eq=3, r=0.1), she.EINVAL)]
+    for inst, status in cases:
+        with pytest.raises(she.SheError) as e:
+            she.Handle.arena_bytes([gpu_instance(she, inst)])
+        assert e.value.status == status, inst
+
+
 def test_arena_bytes_scale_with_problem():
     small = she.Handle.arena_bytes([gpu_instance(she, W.instance((64, 64), r=0.1))])
     big = she.Handle.arena_bytes([gpu_instance(she, W.instance((512, 512), r=0.1))])

@@ -175,6 +175,41 @@ def test_composite_rod_statistics_parity(she):
     assert np.max(np.abs(g["corr"] - cov)) < 1e-3 * np.max(np.abs(np.diag(cov)))
 
 
+@pytest.mark.parametrize("precision,scheme", [(0, W.EM), (0, W.HEUN), (1, W.EM)])
+def test_burgers_state_parity(she, precision, scheme):
+    """Stochastic Burgers: a periodic ring with strong advection and a
+    Dirichlet rod with wall densities 0.2 / 0.4, one batch."""
+    ring = W.burgers(n=128, scheme=scheme)["instances"][0]
+    rod = W.instance((96,), eq=W.BURGERS, bc=W.DIRICHLET, scheme=scheme, r=0.2, eps=1e-3, u0=0.3, u_left=0.2,
+                     u_right=0.4, nu=0.4, init_sd=0.01, realisation=5)
+    insts = [ring, rod]
+    h = she.Handle([gpu_instance(she, i) for i in insts], precision=precision)
+    init = [h.read_field(q) for q in range(2)]
+    steps = 10000 if precision == 0 else 3000
+    h.step(steps)
+    tol = 1e-5 if precision == 0 else 1e-12
+    for q in range(2):
+        u = init[q].copy()
+        oracle.advance(oracle_desc(insts[q], precision), u, 0, steps)
+        assert max_rel(h.read_field(q), u) <= tol, q
+    h.close()
+
+
+def test_burgers_statistics_parity(she):
+    inst = W.burgers(n=64)["instances"][0]
+    h = she.Handle([gpu_instance(she, inst)], precision=0, burn_in=1000, sample_every=5,
+                   stats=she.STAT_MOMENTS | she.STAT_CORR)
+    init = h.read_field(0)
+    h.run(12000)
+    g = h.stats(0, corr=True, sk=True)
+    h.close()
+    st, _ = oracle_stats_run(inst, 0, init, 12000, 1000, 5, corr=True)
+    assert g["n_samples"] == st.n_samples == 2200
+    assert max_rel(g["var"], st.var()) < 1e-3
+    assert max_rel(g["sk"][1:], st.structure_factor()[1:]) < 1e-3
+    assert g["clamp_count"] == st.clamp_count == 0
+
+
 def inst2d(n, scheme, eq, realisation=0):
     if eq == W.HEAT:
         return W.instance(n, eq=eq, scheme=scheme, r=0.1, eps=1e-2, u0=1.0, init_sd=0.1, realisation=realisation)
