@@ -106,7 +106,7 @@ class Desc:
     n: tuple = (64, 1, 1)
     eq: int = 0            # 0 heat, 1 Dean-Kawasaki, 2 stochastic Burgers (1D)
     bc: int = 0            # 0 periodic, 1 Dirichlet (1D)
-    scheme: int = 0        # 0 FE, 1 PC
+    scheme: int = 0        # 0 FE, 1 PC, 2 backward Euler, 3 Crank-Nicolson (1D)
     noise: int = 0         # 0 instantaneous, 1 deterministic face value, 2 off
     r: float = 0.2
     sigma: float = 0.0

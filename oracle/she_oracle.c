@@ -33,6 +33,13 @@
  *     gains -nu c_f (1 - c_f) (nu = a dt/dx, centred) and the noise amplitude
  *     is sqrt(max(c_f (1 - c_f), 0)); the paper gives no scheme for it, so
  *     this is the SHE/DK framework of Sec. 3 applied to it (1D);
+ *   - implicit diffusion (the implicit-scheme exercise, Sec. 6), 1D: backward
+ *     Euler (theta = 1) or Crank-Nicolson (theta = 1/2) for the deterministic
+ *     flux with the noise explicit (face amplitude of U^n):
+ *       (I - theta W A) U' = U + (1 - theta) W (A U + b) + theta W b + noise,
+ *     W (A U + b) being the noise-free divergence (b: Dirichlet wall terms);
+ *     solved with the Thomas algorithm, periodic rods with the
+ *     Sherman-Morrison correction of the cyclic system;
  *   - 1D materials that vary along the rod (the composite-rod exercise,
  *     Sec. 6): the conservative form rho c_V dT/dt = -d/dx(flux) of eq. SHE
  *     with a conductance r_f and noise factor s_f per face and a factor
@@ -71,7 +78,8 @@ typedef struct {
     int32_t eq;          /* 0 = heat (T), 1 = species number density (DK),
                             2 = stochastic Burgers (c, 1D)                     */
     int32_t bc;          /* 0 = periodic, 1 = Dirichlet walls in x (1D only)  */
-    int32_t scheme;      /* 0 = forward Euler, 1 = predictor-corrector        */
+    int32_t scheme;      /* 0 = forward Euler, 1 = predictor-corrector,
+                            2 = backward Euler, 3 = Crank-Nicolson (1D)       */
     int32_t noise;       /* 0 = instantaneous face value, 1 = deterministic
                             (steady-profile) face value, 2 = no noise         */
     double r;            /* kappa dt / dx^2 (heat) or D dt / dx^2 (species)  */
@@ -231,7 +239,9 @@ static int check_desc(const or_desc *d)
     if (d->bc != 0 && d->bc != 1) return -1;
     if (d->eq != 0 && d->eq != 1 && d->eq != 2) return -1;
     if (d->eq == 2 && d->dim != 1) return -1;
-    if (d->scheme != 0 && d->scheme != 1) return -1;
+    if (d->scheme < 0 || d->scheme > 3) return -1;
+    if (d->scheme >= 2 && (d->dim != 1 || d->eq == 2)) return -1;
+    if (d->scheme >= 2 && d->bc == 0 && d->n[0] < 3) return -1;
     if (d->noise < 0 || d->noise > 2) return -1;
     if (d->dim == 1 && d->bc == 0 && d->n[0] < 2) return -1;
     if ((d->face_r || d->face_s || d->cell_w) && d->dim != 1) return -1;
@@ -512,6 +522,65 @@ static int take_sample(const or_desc *d, const double *u, const double *ref,
 
 /* ---------------------------------------------------------------- stepping */
 
+/* Rows of M = I - theta W A for the 1D implicit schemes: lo[i], di[i], up[i]
+ * multiply U_(i-1), U_i, U_(i+1) (cyclic for periodic rods).  A U is the
+ * noise-free flux divergence without the wall terms: face conductances r_f,
+ * a Dirichlet wall face 2 r_f on the diagonal. */
+static void implicit_rows(const or_desc *d, double theta, double *lo, double *di, double *up)
+{
+    const int64_t N = d->n[0];
+    const int dir = d->bc == 1;
+    for (int64_t i = 0; i < N; ++i) {
+        const int64_t fl = i, fh = dir ? i + 1 : (i + 1) % N;
+        const double rl = d->face_r ? d->face_r[fl] : d->r;
+        const double rh = d->face_r ? d->face_r[fh] : d->r;
+        const double w = d->cell_w ? d->cell_w[i] : 1.0;
+        const double dl = (dir && i == 0) ? 2.0 * rl : rl;
+        const double dh = (dir && i == N - 1) ? 2.0 * rh : rh;
+        di[i] = 1.0 + theta * w * (dl + dh);
+        lo[i] = (dir && i == 0) ? 0.0 : -theta * w * rl;
+        up[i] = (dir && i == N - 1) ? 0.0 : -theta * w * rh;
+    }
+}
+
+/* Thomas algorithm for lo[i] x_(i-1) + di[i] x_i + up[i] x_(i+1) = rhs[i],
+ * lo[0] and up[N-1] unused.  work: N doubles. */
+static void thomas(int64_t N, const double *lo, const double *di, const double *up, const double *rhs,
+                   double *x, double *work)
+{
+    double den = di[0];
+    x[0] = rhs[0] / den;
+    for (int64_t i = 1; i < N; ++i) {
+        work[i] = up[i - 1] / den;
+        den = di[i] - lo[i] * work[i];
+        x[i] = (rhs[i] - lo[i] * x[i - 1]) / den;
+    }
+    for (int64_t i = N - 2; i >= 0; --i) x[i] -= work[i + 1] * x[i + 1];
+}
+
+/* Cyclic system (lo[0] couples x_(N-1), up[N-1] couples x_0): write it as a
+ * tridiagonal T plus the rank-one u v^T with u = (g, 0, .., 0, up[N-1]),
+ * v = (1, 0, .., 0, lo[0]/g), g = -di[0], and apply Sherman-Morrison:
+ * x = y - (v.y / (1 + v.z)) z with T y = rhs, T z = u.  work: 4N doubles. */
+static void cyclic_thomas(int64_t N, const double *lo, const double *di, const double *up, const double *rhs,
+                          double *x, double *work)
+{
+    double *dt = work, *uu = work + N, *zz = work + 2 * N, *w = work + 3 * N;
+    const double g = -di[0], alpha = up[N - 1], beta = lo[0];
+    for (int64_t i = 0; i < N; ++i) {
+        dt[i] = di[i];
+        uu[i] = 0.0;
+    }
+    dt[0] -= g;
+    dt[N - 1] -= alpha * beta / g;
+    uu[0] = g;
+    uu[N - 1] = alpha;
+    thomas(N, lo, dt, up, rhs, x, w);
+    thomas(N, lo, dt, up, uu, zz, w);
+    const double f = (x[0] + beta * x[N - 1] / g) / (1.0 + zz[0] + beta * zz[N - 1] / g);
+    for (int64_t i = 0; i < N; ++i) x[i] -= f * zz[i];
+}
+
 /* Advance u by nsteps steps; the step taken from completed-step count t uses
  * the noise of step t (tag 0).  With st != NULL the state is sampled after
  * every completed step t with t > burn_in and t % every == 0.  Returns 0, or
@@ -527,6 +596,21 @@ int or_advance(const or_desc *d, double *u, int64_t step0, int64_t nsteps, or_st
     double *us = (double *)malloc(sizeof(double) * (size_t)nc);
     double *ref = (double *)malloc(sizeof(double) * (size_t)nc);
     if (!z || !flux || !div || !us || !ref) return -2;
+    /* implicit schemes: matrix rows, noise-free divergence, right-hand side */
+    const int impl = d->scheme >= 2;
+    const double theta = d->scheme == 2 ? 1.0 : 0.5;
+    double *lo = NULL, *di = NULL, *up = NULL, *det = NULL, *work = NULL;
+    or_desc dq = *d;
+    dq.noise = 2;
+    if (impl) {
+        lo = (double *)malloc(sizeof(double) * (size_t)nc);
+        di = (double *)malloc(sizeof(double) * (size_t)nc);
+        up = (double *)malloc(sizeof(double) * (size_t)nc);
+        det = (double *)malloc(sizeof(double) * (size_t)nc);
+        work = (double *)malloc(sizeof(double) * 4 * (size_t)nc);
+        if (!lo || !di || !up || !det || !work) return -2;
+        implicit_rows(d, theta, lo, di, up);
+    }
     or_reference(d, ref);
     int64_t *clamps = st ? &st->clamp_count : NULL;
     int rc = 0;
@@ -534,7 +618,20 @@ int or_advance(const or_desc *d, double *u, int64_t step0, int64_t nsteps, or_st
         const uint64_t n = (uint64_t)(step0 + k);
         if (d->noise != 2) draw_faces(d, 0u, n, nf, z);
         divergence(d, u, z, flux, div, clamps);
-        if (d->scheme == 0) {
+        if (impl) {
+            /* rhs = U + full - theta det + theta W b (W b: the wall terms of det) */
+            const int64_t N = nc;
+            divergence(&dq, u, z, flux, det, NULL);
+            for (int64_t i = 0; i < N; ++i) us[i] = u[i] + div[i] - theta * det[i];
+            if (d->bc == 1) {
+                const double r0 = d->face_r ? d->face_r[0] : d->r, rN = d->face_r ? d->face_r[N] : d->r;
+                us[0] += theta * (d->cell_w ? d->cell_w[0] : 1.0) * 2.0 * r0 * d->u_left;
+                us[N - 1] += theta * (d->cell_w ? d->cell_w[N - 1] : 1.0) * 2.0 * rN * d->u_right;
+                thomas(N, lo, di, up, us, u, work);
+            } else {
+                cyclic_thomas(N, lo, di, up, us, u, work);
+            }
+        } else if (d->scheme == 0) {
             for (int64_t i = 0; i < nc; ++i) u[i] = u[i] + div[i];
         } else {
             for (int64_t i = 0; i < nc; ++i) us[i] = u[i] + div[i];
@@ -550,5 +647,6 @@ int or_advance(const or_desc *d, double *u, int64_t step0, int64_t nsteps, or_st
         }
     }
     free(z); free(flux); free(div); free(us); free(ref);
+    free(lo); free(di); free(up); free(det); free(work);
     return rc;
 }
