@@ -71,7 +71,10 @@ typedef enum {
  * sqrt(2 D c (1-c)); the same face-flux scheme with the arithmetic face value) */
 enum { SHE_HEAT = 0, SHE_SPECIES = 1, SHE_BURGERS = 2 };
 enum { SHE_PERIODIC = 0, SHE_DIRICHLET = 1 };                 /* x boundary    */
-enum { SHE_EM = 0, SHE_HEUN = 1 };                            /* FE / PC       */
+/* scheme: forward Euler, predictor-corrector (Sec. 3); backward Euler and
+ * Crank-Nicolson for the deterministic flux with the noise explicit (1D heat /
+ * species; the implicit-scheme exercise, Sec. 6): no stability limit on r */
+enum { SHE_EM = 0, SHE_HEUN = 1, SHE_BE = 2, SHE_CN = 3 };
 enum { SHE_NOISE_INSTANT = 0, SHE_NOISE_FROZEN = 1, SHE_NOISE_OFF = 2 };
 enum { SHE_F32 = 0, SHE_F64 = 1 };                            /* state type    */
 
@@ -102,7 +105,7 @@ typedef struct {
                              power of two in [8, 1024]                         */
     int32_t eq;           /* SHE_HEAT, SHE_SPECIES or SHE_BURGERS (1D)        */
     int32_t bc;           /* SHE_PERIODIC or SHE_DIRICHLET (dim == 1)         */
-    int32_t scheme;       /* SHE_EM or SHE_HEUN                               */
+    int32_t scheme;       /* SHE_EM, SHE_HEUN, SHE_BE or SHE_CN (1D)          */
     int32_t noise;        /* SHE_NOISE_*: face amplitude from the current
                              state (paper's practice), from the deterministic
                              profile (footnote of Sec. 2), or no noise        */

@@ -60,6 +60,8 @@ struct she_handle {
     bool varc = false;
     std::vector<double> coef_host;
     void *d_coef = nullptr;
+    std::vector<double> pcr_host;     // implicit schemes: FP64 reduction factors
+    double *d_pcr = nullptr;
     size_t smem1d = 0;
 
     // 2D / 3D
@@ -131,6 +133,80 @@ std::vector<double> face_conductivity(const she_instance_desc &d)
         }
     }
     return lf;
+}
+
+// Rows of M = I - theta W A of an implicit 1D step: lo[i], di[i], up[i]
+// multiply U_(i-1), U_i, U_(i+1) (cyclic for periodic rods); A is the
+// noise-free flux divergence with face conductances r_f (a Dirichlet wall
+// face twice on the diagonal), W the per-cell capacity factors.
+void implicit_rows(const she_instance_desc &d, double theta, std::vector<double> &lo, std::vector<double> &di,
+                   std::vector<double> &up)
+{
+    const int N = d.n[0];
+    const bool dir = d.bc == SHE_DIRICHLET;
+    const std::vector<double> lf = face_conductivity(d);
+    lo.assign(N, 0.0);
+    di.assign(N, 0.0);
+    up.assign(N, 0.0);
+    for (int i = 0; i < N; ++i) {
+        const double rl = d.r * lf[i], rh = d.r * lf[dir ? i + 1 : (i + 1) % N];
+        const double w = d.cap ? 1.0 / d.cap[i] : 1.0;
+        const double dl = (dir && i == 0) ? 2.0 * rl : rl, dh = (dir && i == N - 1) ? 2.0 * rh : rh;
+        di[i] = 1.0 + theta * w * (dl + dh);
+        lo[i] = (dir && i == 0) ? 0.0 : -theta * w * rl;
+        up[i] = (dir && i == N - 1) ? 0.0 : -theta * w * rh;
+    }
+}
+
+// Factors of parallel cyclic reduction for a x_(i-1) + b x_i + c x_(i+1) = d
+// with a_0 = c_(N-1) = 0: level l (stride s = 2^l) replaces row i by itself
+// minus k1 times row i-s minus k2 times row i+s (k1 = a_i / b_(i-s),
+// k2 = c_i / b_(i+s)), which leaves it coupled to rows i -+ 2s; after
+// ceil(log2 N) levels every row holds one unknown.  Appends k1[L][N],
+// k2[L][N], 1/b[N] to out and returns L.
+int pcr_factors(std::vector<double> a, std::vector<double> b, std::vector<double> c, std::vector<double> &out)
+{
+    const int N = static_cast<int>(b.size());
+    int L = 0;
+    while ((1 << L) < N) ++L;
+    std::vector<double> k1(static_cast<size_t>(L) * N), k2(static_cast<size_t>(L) * N);
+    for (int l = 0; l < L; ++l) {
+        const int s = 1 << l;
+        std::vector<double> na(N, 0.0), nb(N), nc(N, 0.0);
+        for (int i = 0; i < N; ++i) {
+            const double f1 = i - s >= 0 ? a[i] / b[i - s] : 0.0;
+            const double f2 = i + s < N ? c[i] / b[i + s] : 0.0;
+            nb[i] = b[i] - (i - s >= 0 ? f1 * c[i - s] : 0.0) - (i + s < N ? f2 * a[i + s] : 0.0);
+            if (i - s >= 0) na[i] = -f1 * a[i - s];
+            if (i + s < N) nc[i] = -f2 * c[i + s];
+            k1[static_cast<size_t>(l) * N + i] = f1;
+            k2[static_cast<size_t>(l) * N + i] = f2;
+        }
+        a.swap(na);
+        b.swap(nb);
+        c.swap(nc);
+    }
+    out.insert(out.end(), k1.begin(), k1.end());
+    out.insert(out.end(), k2.begin(), k2.end());
+    for (int i = 0; i < N; ++i) out.push_back(1.0 / b[i]);
+    return L;
+}
+
+// Thomas algorithm (host, FP64) for the Sherman-Morrison vector.
+std::vector<double> thomas_solve(const std::vector<double> &a, const std::vector<double> &b,
+                                 const std::vector<double> &c, std::vector<double> d)
+{
+    const int N = static_cast<int>(b.size());
+    std::vector<double> cp(N, 0.0);
+    double den = b[0];
+    d[0] /= den;
+    for (int i = 1; i < N; ++i) {
+        cp[i] = c[i - 1] / den;
+        den = b[i] - a[i] * cp[i];
+        d[i] = (d[i] - a[i] * d[i - 1]) / den;
+    }
+    for (int i = N - 2; i >= 0; --i) d[i] -= cp[i + 1] * d[i + 1];
+    return d;
 }
 
 // Largest modulus over wavenumbers theta of the one-step factor of the
@@ -236,13 +312,18 @@ she_status validate(const she_config *cfg, she_handle *h)
                 return fail(nullptr, SHE_EUNSTABLE, pre + "Burgers step amplifies a mode (reduce nu or r)");
         }
         if (d.bc != SHE_PERIODIC && d.bc != SHE_DIRICHLET) return fail(nullptr, SHE_EINVAL, pre + "bad boundary");
-        if (d.scheme != SHE_EM && d.scheme != SHE_HEUN) return fail(nullptr, SHE_EINVAL, pre + "bad scheme");
+        if (d.scheme < SHE_EM || d.scheme > SHE_CN) return fail(nullptr, SHE_EINVAL, pre + "bad scheme");
+        const bool implicit = d.scheme == SHE_BE || d.scheme == SHE_CN;
+        if (implicit && (d.dim != 1 || d.eq == SHE_BURGERS))
+            return fail(nullptr, SHE_EUNSUPPORTED, pre + "implicit schemes are provided for 1D heat / species");
+        if (implicit && d.bc == SHE_PERIODIC && d.n[0] < 3)
+            return fail(nullptr, SHE_EINVAL, pre + "implicit periodic rods need N >= 3");
         if (d.noise < 0 || d.noise > 2) return fail(nullptr, SHE_EINVAL, pre + "bad noise mode");
         if (d.reserved != 0) return fail(nullptr, SHE_EINVAL, pre + "reserved field must be 0");
         if (!(d.r >= 0.0) || !(d.eps >= 0.0) || !(d.init_sd >= 0.0) || !std::isfinite(d.u0) ||
             !std::isfinite(d.u_left) || !std::isfinite(d.u_right))
             return fail(nullptr, SHE_EINVAL, pre + "r, eps, init_sd must be >= 0 and values finite");
-        if (d.r > 0.5 / d.dim)
+        if (!implicit && d.r > 0.5 / d.dim)
             return fail(nullptr, SHE_EUNSTABLE, pre + "r above the explicit stability limit 1/(2 dim)");
         if (d.bc == SHE_DIRICHLET && d.dim != 1)
             return fail(nullptr, SHE_EINVAL, pre + "Dirichlet walls are provided in 1D only");
@@ -259,7 +340,7 @@ she_status validate(const she_config *cfg, she_handle *h)
             if (d.noise == SHE_NOISE_FROZEN && d.u_left != d.u_right)
                 return fail(nullptr, SHE_EUNSUPPORTED,
                             pre + "deterministic face values on a composite rod need u_left == u_right");
-            if (varc_row_bound(d) > 2.0)
+            if (!implicit && varc_row_bound(d) > 2.0)
                 return fail(nullptr, SHE_EUNSTABLE, pre + "composite rod above the explicit stability limit");
         }
     }
@@ -331,6 +412,37 @@ static she_status plan_1d(she_handle *h, const she_config *cfg, Plan &plan)
         } else {
             t.k_off = -1;
         }
+        t.p_off = -1;
+        t.pcr_levels = 0;
+        t.theta = 0.0;
+        if (d.scheme == SHE_BE || d.scheme == SHE_CN) {
+            // M = I - theta W A; periodic: M = T + u v^T with u = (g, 0.., up_(N-1)),
+            // v = (1, 0.., lo_0 / g), g = -di_0 (Sherman-Morrison), T tridiagonal
+            t.theta = d.scheme == SHE_BE ? 1.0 : 0.5;
+            std::vector<double> lo, di, up;
+            implicit_rows(d, t.theta, lo, di, up);
+            const int N = d.n[0];
+            const bool per = d.bc == SHE_PERIODIC;
+            const double g = -di[0], alpha = up[N - 1], beta = lo[0];
+            if (per) {
+                di[0] -= g;
+                di[N - 1] -= alpha * beta / g;
+                lo[0] = 0.0;
+                up[N - 1] = 0.0;
+            }
+            t.p_off = static_cast<int64_t>(h->pcr_host.size());
+            t.pcr_levels = pcr_factors(lo, di, up, h->pcr_host);
+            if (per) {
+                std::vector<double> u(N, 0.0);
+                u[0] = g;
+                u[N - 1] = alpha;
+                const std::vector<double> z = thomas_solve(lo, di, up, u);
+                h->pcr_host.insert(h->pcr_host.end(), z.begin(), z.end());
+                const double q = beta / g;
+                h->pcr_host.push_back(q);
+                h->pcr_host.push_back(1.0 / (1.0 + z[0] + q * z[N - 1]));
+            }
+        }
         if (tcorr) {
             t.h_off = ho;
             t.tc_off = to;
@@ -361,7 +473,7 @@ static she_status plan_1d(she_handle *h, const she_config *cfg, Plan &plan)
     h->block1d = block;
     h->maxg = maxg;
     const size_t nmax_pad = (h->nmax + 4) & ~3;
-    h->smem1d = (3 * nmax_pad + 8) * es * (h->varc ? 2 : 1);
+    h->smem1d = (3 * nmax_pad + 8) * es * ((h->varc || !h->pcr_host.empty()) ? 2 : 1);
     if (h->smem1d > 64 * 1024)
         return fail(nullptr, SHE_EUNSUPPORTED, "1D instance too large for LDS (64 KB per workgroup)");
 
@@ -376,7 +488,8 @@ static she_status plan_1d(she_handle *h, const she_config *cfg, Plan &plan)
         plan.add(&h->d_x, es * xo);
         plan.add(reinterpret_cast<void **>(&h->d_c), sizeof(double) * co);
     }
-    if (h->varc) plan.add(&h->d_coef, es * h->coef_host.size());
+    if (!h->coef_host.empty()) plan.add(&h->d_coef, es * h->coef_host.size());
+    if (!h->pcr_host.empty()) plan.add(reinterpret_cast<void **>(&h->d_pcr), sizeof(double) * h->pcr_host.size());
     if (tcorr) {
         plan.add(&h->d_hist, es * ho);
         plan.add(reinterpret_cast<void **>(&h->d_tc), sizeof(double) * to);
@@ -615,7 +728,10 @@ extern "C" she_status she_create(const she_config *cfg, she_handle **out)
         });
         CREATE_HIP(hipMemcpyAsync(h->d_tab, h->tab.data(), sizeof(Inst1D) * h->n_inst, hipMemcpyHostToDevice, s));
         CREATE_HIP(hipMemcpyAsync(h->d_order, order.data(), sizeof(int32_t) * h->n_inst, hipMemcpyHostToDevice, s));
-        if (h->varc) {
+        if (!h->pcr_host.empty())
+            CREATE_HIP(hipMemcpyAsync(h->d_pcr, h->pcr_host.data(), sizeof(double) * h->pcr_host.size(),
+                                      hipMemcpyHostToDevice, s));
+        if (!h->coef_host.empty()) {
             if (h->prec == SHE_F32) {
                 coef32.assign(h->coef_host.begin(), h->coef_host.end());
                 CREATE_HIP(hipMemcpyAsync(h->d_coef, coef32.data(), sizeof(float) * coef32.size(),
@@ -757,8 +873,10 @@ static she_status advance(she_handle *h, int64_t nsteps, bool sampling)
                 const int64_t j0 = std::max(h->steps, h->burn_in) / h->every;
                 k = std::min<int64_t>(k, h->every * (j0 + room + 1) - 1 - h->steps);
             }
-            SHE_HIP(h, launch_step1d(h->prec, h->block1d, h->maxg, stats, h->varc, h->n_inst, h->smem1d, s,
-                                     h->d_tab, h->d_order, h->d_pool, h->d_coef, h->steps, static_cast<int32_t>(k),
+            const int mode = !h->pcr_host.empty() ? 2 : (h->varc ? 1 : 0);
+            SHE_HIP(h, launch_step1d(h->prec, h->block1d, h->maxg, stats, mode, h->n_inst, h->smem1d, s,
+                                     h->d_tab, h->d_order, h->d_pool, h->d_coef, h->d_pcr, h->steps,
+                                     static_cast<int32_t>(k),
                                      h->burn_in, h->every, h->mask, st));
             if (tc) {
                 const int64_t cnt = sampled_by(h->steps + k) - sampled_by(h->steps);

@@ -19,13 +19,20 @@ struct Inst1D {
                         // in the state type, -1: uniform rod
     int32_t n;          // cells
     int32_t bc;         // 0 periodic, 1 Dirichlet
-    int32_t scheme;     // 0 FE, 1 PC
+    int32_t scheme;     // 0 FE, 1 PC, 2 backward Euler, 3 Crank-Nicolson
     int32_t noise;      // 0 instantaneous, 1 frozen, 2 off
     int32_t eq;         // 0 heat, 1 species, 2 Burgers
     uint32_t realisation;
     uint64_t seed;
     double r, sigma, u0, uL, uR;
     double nu;          // Burgers: Courant number
+    // implicit schemes: FP64 parallel-cyclic-reduction factors of M = I - theta W A
+    // at p_off of the reduction buffer: k1[L][N], k2[L][N], 1/b[N], then (periodic)
+    // the Sherman-Morrison vector z[N] and the scalars q, 1/(1 + z_0 + q z_(N-1))
+    int64_t p_off;
+    int32_t pcr_levels;
+    int32_t pad_;
+    double theta;
 };
 
 // Per-instance accumulators that are not per cell (device).
@@ -97,12 +104,13 @@ __device__ __forceinline__ void resolve_step(const StepArg &a, int64_t &step, in
 namespace she {
 
 // ---- launchers (defined next to their kernels) ----
-// varc: some instance has material coefficients (k_off >= 0 in `coef`);
-// the kernel then stages r_f, s_f, w_i of every instance in LDS.
-hipError_t launch_step1d(int prec, int block, int maxg, bool stats, bool varc, int n_blocks, size_t smem,
+// mode 0: uniform explicit batch; 1: some instance has material coefficients
+// (k_off >= 0 in `coef`; r_f, s_f, w_i of every instance staged in LDS);
+// 2: some instance is implicit (reduction factors in `pcr`; mode 1 included).
+hipError_t launch_step1d(int prec, int block, int maxg, bool stats, int mode, int n_blocks, size_t smem,
                          hipStream_t s, const Inst1D *tab, const int32_t *order, void *pool,
-                         const void *coef, int64_t step0, int32_t nsteps, int64_t burn_in, int32_t every,
-                         uint32_t mask, Stats1D st);
+                         const void *coef, const double *pcr, int64_t step0, int32_t nsteps, int64_t burn_in,
+                         int32_t every, uint32_t mask, Stats1D st);
 // Initial state of 1D instances: steady profile + init_sd * N(tag 1, step 0, face = cell).
 hipError_t launch_init1d(int prec, int n_inst, int nmax, hipStream_t s, const Inst1D *tab,
                          const double *init_sd, void *pool);

@@ -7,6 +7,17 @@
 // walls: F_0 = 2 r (U_0 - U_L) + sqrt(2) sigma A(U_L) N_0 and mirrored at the
 // right wall (ghost stencil U_1 - 3U_0 + 2U_L of the Dirichlet paragraph).
 //
+// Implicit schemes (backward Euler theta = 1, Crank-Nicolson theta = 1/2;
+// the implicit-scheme exercise, Sec. 6): the flux pass weights the
+// state-dependent deterministic flux by 1 - theta, giving the right-hand side
+// U + W [(1 - theta) A U + b + noise]; M = I - theta W A is constant, so the
+// host precomputes in FP64 the factors of parallel cyclic reduction (log2 N
+// levels of d_i -= k1 d_(i-s) + k2 d_(i+s), then d_i / b_i) and, for periodic
+// rods, the Sherman-Morrison vector of the cyclic part.  The reduction runs in
+// FP64 for either state type (an FP64 array over the flux and scratch LDS),
+// so only the final state is rounded: rounded factors would bias the
+// conserved sum a little every step.
+//
 // Material varying along the rod (composite-rod exercise, Sec. 6; VARC): the
 // conservative form with a conductance r_f and noise factor s_f per face and
 // a factor w_i = (rho c_V)_ref / (rho c_V)_i per cell, U_i += w_i (F_(i+1) -
@@ -102,12 +113,16 @@ __device__ void xtx_block(const T *__restrict__ X, double *__restrict__ Cm, int 
     }
 }
 
-template <typename T, int BLOCK, int MAXG, bool STATS, bool VARC>
+// MODE 0: uniform explicit batch; 1: material coefficients (VARC); 2: some
+// instance is implicit (material arrays available as well).  Each mode is
+// compiled separately so that a batch pays only for the paths it uses.
+template <typename T, int BLOCK, int MAXG, bool STATS, int MODE>
 __global__ void __launch_bounds__(BLOCK)
     k_step1d(const Inst1D *__restrict__ tab, const int32_t *__restrict__ order, T *__restrict__ pool,
-             const T *__restrict__ coef, int64_t step0, int32_t nsteps, int64_t burn_in, int32_t every, uint32_t mask,
-             Stats1D st)
+             const T *__restrict__ coef, const double *__restrict__ pcr, int64_t step0, int32_t nsteps,
+             int64_t burn_in, int32_t every, uint32_t mask, Stats1D st)
 {
+    constexpr bool VARC = MODE >= 1;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     __shared__ double red[3][BLOCK / 64];
     __shared__ int stop_flag;
@@ -179,6 +194,10 @@ __global__ void __launch_bounds__(BLOCK)
         }
     __syncthreads();
 
+    // implicit schemes: weight of the state-dependent deterministic flux
+    const bool impl = MODE == 2 && d.scheme >= 2;
+    const T ex = static_cast<T>(1.0 - d.theta);
+
     auto flux_pass = [&](const T *V, const T (&z)[MAXG][4]) {
 #pragma unroll
         for (int s = 0; s < MAXG; ++s) {
@@ -191,17 +210,17 @@ __global__ void __launch_bounds__(BLOCK)
                 T fl;
                 const T rf = VARC ? Rf[f] : r;
                 if (dir && f == 0) {
-                    fl = T(2) * rf * (V[0] - uL);
+                    fl = T(2) * rf * ((impl ? ex * V[0] : V[0]) - uL);
                     if (eq == 2) fl -= nu * uL * (T(1) - uL);
                     if (noise != 2) fl += (VARC ? Sf[f] : sgw) * amp_uL * z[s][l];
                 } else if (dir && f == N) {
-                    fl = T(2) * rf * (uR - V[N - 1]);
+                    fl = T(2) * rf * (uR - (impl ? ex * V[N - 1] : V[N - 1]));
                     if (eq == 2) fl -= nu * uR * (T(1) - uR);
                     if (noise != 2) fl += (VARC ? Sf[f] : sgw) * amp_uR * z[s][l];
                 } else {
                     const int a = f == 0 ? N - 1 : f - 1;
                     const T vl = V[a], vr = V[f];
-                    fl = rf * (vr - vl);
+                    fl = (impl ? ex * rf : rf) * (vr - vl);
                     if (eq == 2) {
                         const T cf = T(0.5) * (vl + vr);
                         fl -= nu * cf * (T(1) - cf);
@@ -239,7 +258,67 @@ __global__ void __launch_bounds__(BLOCK)
         }
         flux_pass(U, z);
         __syncthreads();
-        if (d.scheme == 0) {
+        if (MODE == 2 && impl) {
+            // right-hand side in FP64 registers, then M U' = rhs by parallel
+            // cyclic reduction in place on an FP64 array over F and Us
+            constexpr int MAXC = 4 * MAXG;  // cells per thread (N <= 4 BLOCK MAXG)
+            double x[MAXC];
+#pragma unroll
+            for (int j = 0; j < MAXC; ++j) {
+                const int i = tid + j * BLOCK;
+                if (i < N) {
+                    const int hi = (!dir && i + 1 == N) ? 0 : i + 1;
+                    x[j] = static_cast<double>(U[i] + (VARC ? Wc[i] * (F[hi] - F[i]) : (F[hi] - F[i])));
+                }
+            }
+            __syncthreads();
+            double *D = reinterpret_cast<double *>(F);
+#pragma unroll
+            for (int j = 0; j < MAXC; ++j)
+                if (tid + j * BLOCK < N) D[tid + j * BLOCK] = x[j];
+            __syncthreads();
+            const double *P = pcr + d.p_off;
+            const int L = d.pcr_levels;
+            for (int l = 0; l < L; ++l) {
+                const int s = 1 << l;
+                const double *k1 = P + static_cast<int64_t>(l) * N, *k2 = P + static_cast<int64_t>(L + l) * N;
+#pragma unroll
+                for (int j = 0; j < MAXC; ++j) {
+                    const int i = tid + j * BLOCK;
+                    if (i < N) {
+                        double v = D[i];
+                        if (i >= s) v -= k1[i] * D[i - s];
+                        if (i + s < N) v -= k2[i] * D[i + s];
+                        x[j] = v;
+                    }
+                }
+                __syncthreads();
+#pragma unroll
+                for (int j = 0; j < MAXC; ++j)
+                    if (tid + j * BLOCK < N) D[tid + j * BLOCK] = x[j];
+                __syncthreads();
+            }
+            const double *invb = P + static_cast<int64_t>(2 * L) * N;
+#pragma unroll
+            for (int j = 0; j < MAXC; ++j)
+                if (tid + j * BLOCK < N) x[j] *= invb[tid + j * BLOCK];
+            if (!dir) {
+                // cyclic part: x = y - f z, f = (y_0 + q y_(N-1)) / (1 + z_0 + q z_(N-1))
+#pragma unroll
+                for (int j = 0; j < MAXC; ++j)
+                    if (tid + j * BLOCK < N) D[tid + j * BLOCK] = x[j];
+                __syncthreads();
+                const double *zv = invb + N;
+                const double f = (D[0] + zv[N] * D[N - 1]) * zv[N + 1];
+#pragma unroll
+                for (int j = 0; j < MAXC; ++j)
+                    if (tid + j * BLOCK < N) x[j] -= f * zv[tid + j * BLOCK];
+            }
+#pragma unroll
+            for (int j = 0; j < MAXC; ++j)
+                if (tid + j * BLOCK < N) U[tid + j * BLOCK] = static_cast<T>(x[j]);
+            __syncthreads();
+        } else if (d.scheme == 0) {
             for (int i = tid; i < N; i += BLOCK) {
                 const int hi = (!dir && i + 1 == N) ? 0 : i + 1;
                 U[i] = U[i] + (VARC ? Wc[i] * (F[hi] - F[i]) : (F[hi] - F[i]));
@@ -544,6 +623,7 @@ struct Step1DLaunch {
     const int32_t *order;
     void *pool;
     const void *coef;
+    const double *pcr;
     int64_t step0;
     int32_t nsteps;
     int64_t burn_in;
@@ -552,51 +632,62 @@ struct Step1DLaunch {
     Stats1D st;
 };
 
-template <typename T, int BLOCK, int MAXG, bool STATS, bool VARC>
+template <typename T, int BLOCK, int MAXG, bool STATS, int MODE>
 static hipError_t step1d_k(const Step1DLaunch &a)
 {
-    hipLaunchKernelGGL((k_step1d<T, BLOCK, MAXG, STATS, VARC>), dim3(a.n_blocks), dim3(BLOCK), a.smem, a.s, a.tab,
-                       a.order, static_cast<T *>(a.pool), static_cast<const T *>(a.coef), a.step0, a.nsteps, a.burn_in,
-                       a.every, a.mask, a.st);
+    hipLaunchKernelGGL((k_step1d<T, BLOCK, MAXG, STATS, MODE>), dim3(a.n_blocks), dim3(BLOCK), a.smem, a.s, a.tab,
+                       a.order, static_cast<T *>(a.pool), static_cast<const T *>(a.coef), a.pcr, a.step0, a.nsteps,
+                       a.burn_in, a.every, a.mask, a.st);
     return hipGetLastError();
 }
 
-template <typename T, int BLOCK, int MAXG>
-static hipError_t step1d_t(bool stats, bool varc, const Step1DLaunch &a)
+template <typename T, int BLOCK, int MAXG, bool STATS>
+static hipError_t step1d_m(int mode, const Step1DLaunch &a)
 {
-    if (stats) return varc ? step1d_k<T, BLOCK, MAXG, true, true>(a) : step1d_k<T, BLOCK, MAXG, true, false>(a);
-    return varc ? step1d_k<T, BLOCK, MAXG, false, true>(a) : step1d_k<T, BLOCK, MAXG, false, false>(a);
+    switch (mode) {
+    case 0: return step1d_k<T, BLOCK, MAXG, STATS, 0>(a);
+    case 1: return step1d_k<T, BLOCK, MAXG, STATS, 1>(a);
+    case 2: return step1d_k<T, BLOCK, MAXG, STATS, 2>(a);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+template <typename T, int BLOCK, int MAXG>
+static hipError_t step1d_t(bool stats, int mode, const Step1DLaunch &a)
+{
+    return stats ? step1d_m<T, BLOCK, MAXG, true>(mode, a) : step1d_m<T, BLOCK, MAXG, false>(mode, a);
 }
 
 template <typename T, int BLOCK>
-static hipError_t step1d_b(int maxg, bool stats, bool varc, const Step1DLaunch &a)
+static hipError_t step1d_b(int maxg, bool stats, int mode, const Step1DLaunch &a)
 {
     switch (maxg) {
-    case 1: return step1d_t<T, BLOCK, 1>(stats, varc, a);
-    case 2: return step1d_t<T, BLOCK, 2>(stats, varc, a);
-    case 4: return step1d_t<T, BLOCK, 4>(stats, varc, a);
-    case 8: return step1d_t<T, BLOCK, 8>(stats, varc, a);
+    case 1: return step1d_t<T, BLOCK, 1>(stats, mode, a);
+    case 2: return step1d_t<T, BLOCK, 2>(stats, mode, a);
+    case 4: return step1d_t<T, BLOCK, 4>(stats, mode, a);
+    case 8: return step1d_t<T, BLOCK, 8>(stats, mode, a);
     default: return hipErrorInvalidValue;
     }
 }
 
 template <typename T>
-static hipError_t step1d_p(int block, int maxg, bool stats, bool varc, const Step1DLaunch &a)
+static hipError_t step1d_p(int block, int maxg, bool stats, int mode, const Step1DLaunch &a)
 {
     switch (block) {
-    case 64: return step1d_b<T, 64>(maxg, stats, varc, a);
-    case 256: return step1d_b<T, 256>(maxg, stats, varc, a);
+    case 64: return step1d_b<T, 64>(maxg, stats, mode, a);
+    case 256: return step1d_b<T, 256>(maxg, stats, mode, a);
     default: return hipErrorInvalidValue;
     }
 }
 
-hipError_t launch_step1d(int prec, int block, int maxg, bool stats, bool varc, int n_blocks, size_t smem,
+hipError_t launch_step1d(int prec, int block, int maxg, bool stats, int mode, int n_blocks, size_t smem,
                          hipStream_t s, const Inst1D *tab, const int32_t *order, void *pool, const void *coef,
-                         int64_t step0, int32_t nsteps, int64_t burn_in, int32_t every, uint32_t mask, Stats1D st)
+                         const double *pcr, int64_t step0, int32_t nsteps, int64_t burn_in, int32_t every,
+                         uint32_t mask, Stats1D st)
 {
-    const Step1DLaunch a{n_blocks, smem, s, tab, order, pool, coef, step0, nsteps, burn_in, every, mask, st};
-    if (prec == 0) return step1d_p<float>(block, maxg, stats, varc, a);
-    return step1d_p<double>(block, maxg, stats, varc, a);
+    const Step1DLaunch a{n_blocks, smem, s, tab, order, pool, coef, pcr, step0, nsteps, burn_in, every, mask, st};
+    if (prec == 0) return step1d_p<float>(block, maxg, stats, mode, a);
+    return step1d_p<double>(block, maxg, stats, mode, a);
 }
 
 hipError_t launch_init1d(int prec, int n_inst, int nmax, hipStream_t s, const Inst1D *tab, const double *init_sd,

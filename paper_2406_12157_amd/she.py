@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libshe.so")
 
 HEAT, SPECIES, BURGERS = 0, 1, 2
 PERIODIC, DIRICHLET = 0, 1
-EM, HEUN = 0, 1
+EM, HEUN, BE, CN = 0, 1, 2, 3
 NOISE_INSTANT, NOISE_FROZEN, NOISE_OFF = 0, 1, 2
 F32, F64 = 0, 1
 STAT_MOMENTS, STAT_CORR, STAT_SK, STAT_SPATIAL, STAT_TCORR = 1, 2, 4, 8, 16

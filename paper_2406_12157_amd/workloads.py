@@ -33,7 +33,7 @@ import numpy as np
 
 HEAT, SPECIES, BURGERS = 0, 1, 2
 PERIODIC, DIRICHLET = 0, 1
-EM, HEUN = 0, 1
+EM, HEUN, BE, CN = 0, 1, 2, 3
 
 
 def instance(n, eq=HEAT, bc=PERIODIC, scheme=EM, noise=0, r=0.2, eps=1e-2, u0=1.0, u_left=None,

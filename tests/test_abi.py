@@ -128,6 +128,21 @@ def test_burgers_validation():
         assert e.value.status == status, inst
 
 
+def test_implicit_scheme_validation():
+    for scheme in (W.BE, W.CN):
+        she.Handle.arena_bytes([gpu_instance(she, W.instance((64,), scheme=scheme, r=25.0))])   # no r limit
+        cases = [(W.instance((16, 16), scheme=scheme, r=0.1), she.EUNSUPPORTED),
+                 (W.instance((64,), eq=W.BURGERS, scheme=scheme, r=0.2, u0=0.3, nu=0.1), she.EUNSUPPORTED),
+                 (W.instance((2,), scheme=scheme, r=0.2), she.EINVAL)]
+        for inst, status in cases:
+            with pytest.raises(she.SheError) as e:
+                she.Handle.arena_bytes([gpu_instance(she, inst)])
+            assert e.value.status == status, inst
+    with pytest.raises(she.SheError) as e:
+        she.Handle.arena_bytes([gpu_instance(she, W.instance((64,), scheme=4, r=0.1))])
+    assert e.value.status == she.EINVAL
+
+
 def test_arena_bytes_scale_with_problem():
     small = she.Handle.arena_bytes([gpu_instance(she, W.instance((64, 64), r=0.1))])
     big = she.Handle.arena_bytes([gpu_instance(she, W.instance((512, 512), r=0.1))])

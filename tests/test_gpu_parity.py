@@ -210,6 +210,64 @@ def test_burgers_statistics_parity(she):
     assert g["clamp_count"] == st.clamp_count == 0
 
 
+@pytest.mark.parametrize("precision,scheme", [(0, W.BE), (0, W.CN), (1, W.BE), (1, W.CN)])
+def test_implicit_state_parity(she, precision, scheme):
+    """Backward Euler / Crank-Nicolson far beyond the explicit limit: a
+    periodic ring (r = 2), a Dirichlet rod with a gradient (r = 10), a
+    composite rod (r = 3) and a single-level periodic ring (N = 3), one batch."""
+    ring = W.instance((100,), scheme=scheme, r=2.0, eps=1e-2, init_sd=0.1, realisation=1)
+    rod = W.instance((257,), bc=W.DIRICHLET, scheme=scheme, r=10.0, eps=1e-3, u0=1.0, u_left=0.8, u_right=1.2,
+                     init_sd=0.03, realisation=2)
+    comp = W.instance((64,), bc=W.DIRICHLET, scheme=scheme, r=3.0, eps=1e-3, u0=1.0, u_left=1.1, u_right=0.9,
+                      init_sd=0.03, realisation=3, cond=[1.0] * 32 + [3.0] * 32, cap=[1.0] * 32 + [0.7] * 32)
+    # r = 0.9, not 1: at N = 3, r = 1 the inverse of M is dyadic, every new state
+    # lands on exact float ties, and the FP64 solve's last-bit error decides them
+    # all one way, so an FP32 state drifts by ulp/3 per step (FP64: test below)
+    tiny = W.instance((3,), scheme=scheme, r=0.9, eps=1e-2, init_sd=0.1, realisation=4)
+    insts = [ring, rod, comp, tiny]
+    h = she.Handle([gpu_instance(she, i) for i in insts], precision=precision)
+    init = [h.read_field(q) for q in range(len(insts))]
+    steps = 3000 if precision == 0 else 1000
+    h.step(steps)
+    tol = 1e-5 if precision == 0 else 1e-12
+    for q, inst in enumerate(insts):
+        u = init[q].copy()
+        oracle.advance(oracle_desc(inst, precision), u, 0, steps)
+        assert max_rel(h.read_field(q), u) <= tol, q
+    h.close()
+
+
+def test_implicit_periodic_conserves_the_sum(she):
+    """FP64 state: the implicit periodic solve (reduction + Sherman-Morrison)
+    keeps sum_i cap_i U_i to round-off with noise, also at the tie-prone
+    N = 3, r = 1 and on a composite ring."""
+    insts = [W.instance((3,), scheme=W.BE, r=1.0, eps=1e-2, init_sd=0.1),
+             W.instance((50,), scheme=W.CN, r=7.0, eps=1e-2, init_sd=0.1, realisation=1),
+             W.instance((40,), scheme=W.BE, r=2.0, eps=1e-2, init_sd=0.1, realisation=2,
+                        cond=[1.0] * 20 + [3.0] * 20, cap=[1.0] * 20 + [0.7] * 20)]
+    h = she.Handle([gpu_instance(she, i) for i in insts], precision=1)
+    cap = [np.ones(3), np.ones(50), np.array([1.0] * 20 + [0.7] * 20)]
+    e0 = [float(np.dot(cap[q], h.read_field(q))) for q in range(3)]
+    h.step(5000)
+    for q in range(3):
+        assert abs(np.dot(cap[q], h.read_field(q)) / e0[q] - 1) < 1e-11, q   # FP64 round-off over 5000 steps
+    h.close()
+
+
+def test_implicit_statistics_parity(she):
+    inst = W.instance((48,), scheme=W.CN, r=2.0, eps=1e-2, init_sd=0.1, noise=1)
+    h = she.Handle([gpu_instance(she, inst)], precision=0, burn_in=200, sample_every=2,
+                   stats=she.STAT_MOMENTS | she.STAT_CORR)
+    init = h.read_field(0)
+    h.run(8000)
+    g = h.stats(0, corr=True, sk=True)
+    h.close()
+    st, _ = oracle_stats_run(inst, 0, init, 8000, 200, 2, corr=True)
+    assert g["n_samples"] == st.n_samples == 3900
+    assert max_rel(g["var"], st.var()) < 1e-3
+    assert max_rel(g["sk"][1:], st.structure_factor()[1:]) < 1e-3
+
+
 def inst2d(n, scheme, eq, realisation=0):
     if eq == W.HEAT:
         return W.instance(n, eq=eq, scheme=scheme, r=0.1, eps=1e-2, u0=1.0, init_sd=0.1, realisation=realisation)
