@@ -7,6 +7,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <map>
 #include <cstdio>
 #include <cstring>
 #include <numeric>
@@ -370,6 +371,7 @@ static she_status plan_1d(she_handle *h, const she_config *cfg, Plan &plan)
         h->hist_rows = static_cast<int32_t>(per + h->tc_lags);
     }
     int64_t ho = 0, to = 0;
+    std::map<std::vector<double>, std::pair<int64_t, int32_t>> pcr_shared;  // matrix rows -> factor block
     for (int i = 0; i < h->n_inst; ++i) {
         const she_instance_desc &d = h->inst[i];
         Inst1D &t = h->tab[i];
@@ -423,24 +425,37 @@ static she_status plan_1d(she_handle *h, const she_config *cfg, Plan &plan)
             implicit_rows(d, t.theta, lo, di, up);
             const int N = d.n[0];
             const bool per = d.bc == SHE_PERIODIC;
-            const double g = -di[0], alpha = up[N - 1], beta = lo[0];
-            if (per) {
-                di[0] -= g;
-                di[N - 1] -= alpha * beta / g;
-                lo[0] = 0.0;
-                up[N - 1] = 0.0;
-            }
-            t.p_off = static_cast<int64_t>(h->pcr_host.size());
-            t.pcr_levels = pcr_factors(lo, di, up, h->pcr_host);
-            if (per) {
-                std::vector<double> u(N, 0.0);
-                u[0] = g;
-                u[N - 1] = alpha;
-                const std::vector<double> z = thomas_solve(lo, di, up, u);
-                h->pcr_host.insert(h->pcr_host.end(), z.begin(), z.end());
-                const double q = beta / g;
-                h->pcr_host.push_back(q);
-                h->pcr_host.push_back(1.0 / (1.0 + z[0] + q * z[N - 1]));
+            // instances with the same matrix share one block of factors (the
+            // reduction reads them every level; a shared block stays in L2)
+            std::vector<double> key(lo);
+            key.insert(key.end(), di.begin(), di.end());
+            key.insert(key.end(), up.begin(), up.end());
+            key.push_back(per ? 1.0 : 0.0);
+            const auto hit = pcr_shared.find(key);
+            if (hit != pcr_shared.end()) {
+                t.p_off = hit->second.first;
+                t.pcr_levels = hit->second.second;
+            } else {
+                const double g = -di[0], alpha = up[N - 1], beta = lo[0];
+                if (per) {
+                    di[0] -= g;
+                    di[N - 1] -= alpha * beta / g;
+                    lo[0] = 0.0;
+                    up[N - 1] = 0.0;
+                }
+                t.p_off = static_cast<int64_t>(h->pcr_host.size());
+                t.pcr_levels = pcr_factors(lo, di, up, h->pcr_host);
+                if (per) {
+                    std::vector<double> u(N, 0.0);
+                    u[0] = g;
+                    u[N - 1] = alpha;
+                    const std::vector<double> z = thomas_solve(lo, di, up, u);
+                    h->pcr_host.insert(h->pcr_host.end(), z.begin(), z.end());
+                    const double q = beta / g;
+                    h->pcr_host.push_back(q);
+                    h->pcr_host.push_back(1.0 / (1.0 + z[0] + q * z[N - 1]));
+                }
+                pcr_shared.emplace(std::move(key), std::make_pair(t.p_off, t.pcr_levels));
             }
         }
         if (tcorr) {

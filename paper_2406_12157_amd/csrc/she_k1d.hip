@@ -279,19 +279,32 @@ __global__ void __launch_bounds__(BLOCK)
             __syncthreads();
             const double *P = pcr + d.p_off;
             const int L = d.pcr_levels;
+            // factors of the current level in registers; the next level's are
+            // loaded before this level's barriers so their latency overlaps
+            double f1[MAXC], f2[MAXC];
+            auto load_level = [&](int l, double (&a)[MAXC], double (&b)[MAXC]) {
+                const double *k1 = P + static_cast<int64_t>(l) * N, *k2 = P + static_cast<int64_t>(L + l) * N;
+#pragma unroll
+                for (int j = 0; j < MAXC; ++j) {
+                    const int i = tid + j * BLOCK;
+                    a[j] = i < N ? k1[i] : 0.0;
+                    b[j] = i < N ? k2[i] : 0.0;
+                }
+            };
+            if (L > 0) load_level(0, f1, f2);
             for (int l = 0; l < L; ++l) {
                 const int s = 1 << l;
-                const double *k1 = P + static_cast<int64_t>(l) * N, *k2 = P + static_cast<int64_t>(L + l) * N;
 #pragma unroll
                 for (int j = 0; j < MAXC; ++j) {
                     const int i = tid + j * BLOCK;
                     if (i < N) {
                         double v = D[i];
-                        if (i >= s) v -= k1[i] * D[i - s];
-                        if (i + s < N) v -= k2[i] * D[i + s];
+                        if (i >= s) v -= f1[j] * D[i - s];
+                        if (i + s < N) v -= f2[j] * D[i + s];
                         x[j] = v;
                     }
                 }
+                if (l + 1 < L) load_level(l + 1, f1, f2);
                 __syncthreads();
 #pragma unroll
                 for (int j = 0; j < MAXC; ++j)
