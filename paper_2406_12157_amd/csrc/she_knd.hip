@@ -205,30 +205,63 @@ __global__ void __launch_bounds__(256)
 
     if constexpr (SCHEME == 0) {
         T tc[CX], tn[CX], tq[CX], zy[CX], zx[CX], fylo[CX], fyhi[CX], fxlo[CX], fxhi;
-        {
-            T tp[CX];
-            load_row<T, CX>(rowp(y0 - 1), tp);
-            load_row<T, CX>(rowp(y0), tc);
-            load_row<T, CX>(rowp(y0 + 1), tn);
-            row_normals<T, CX>(zy, drow(y0, 1), nq, q0, slo, w2, real, key, noise, rc);
+        if ((ch & 1) == 0) {
+            // upward march: the low-y flux of row y is carried from row y-1
+            {
+                T tp[CX];
+                load_row<T, CX>(rowp(y0 - 1), tp);
+                load_row<T, CX>(rowp(y0), tc);
+                load_row<T, CX>(rowp(y0 + 1), tn);
+                row_normals<T, CX>(zy, drow(y0, 1), nq, q0, slo, w2, real, key, noise, rc);
 #pragma unroll
-            for (int j = 0; j < CX; ++j) fylo[j] = face_flux<T, EQ>(tp[j], tc[j], zy[j], r, noise, clamps);
-        }
-        for (int y = y0; y < y1; ++y) {
-            load_row<T, CX>(rowp(y + 2), tq);
-            row_normals<T, CX>(zy, drow(y + 1, 1), nq, q0, slo, w2, real, key, noise, rc);
+                for (int j = 0; j < CX; ++j) fylo[j] = face_flux<T, EQ>(tp[j], tc[j], zy[j], r, noise, clamps);
+            }
+            for (int y = y0; y < y1; ++y) {
+                if (y + 2 <= y1) load_row<T, CX>(rowp(y + 2), tq);
+                row_normals<T, CX>(zy, drow(y + 1, 1), nq, q0, slo, w2, real, key, noise, rc);
 #pragma unroll
-            for (int j = 0; j < CX; ++j) fyhi[j] = face_flux<T, EQ>(tc[j], tn[j], zy[j], r, noise, clamps);
-            row_normals<T, CX>(zx, drow(y, 0), nq, q0, slo, w2, real, key, noise, rc);
-            row_xflux<T, CX, EQ>(tc, zx, fxlo, fxhi, lx, LX, r, noise, clamps);
-            T out[CX];
+                for (int j = 0; j < CX; ++j) fyhi[j] = face_flux<T, EQ>(tc[j], tn[j], zy[j], r, noise, clamps);
+                row_normals<T, CX>(zx, drow(y, 0), nq, q0, slo, w2, real, key, noise, rc);
+                row_xflux<T, CX, EQ>(tc, zx, fxlo, fxhi, lx, LX, r, noise, clamps);
+                T out[CX];
 #pragma unroll
-            for (int j = 0; j < CX; ++j) out[j] = tc[j] + (xdiv<T, CX>(fxlo, fxhi, j) + (fyhi[j] - fylo[j]));
-            if (sample) accumulate<T, CX>(out, u0d, sa, sb);
-            store_row<T, CX>(D + static_cast<int64_t>(y) * p.nx, out);
-            copy_row<T, CX>(tc, tn);
-            copy_row<T, CX>(tn, tq);
-            copy_row<T, CX>(fylo, fyhi);
+                for (int j = 0; j < CX; ++j) out[j] = tc[j] + (xdiv<T, CX>(fxlo, fxhi, j) + (fyhi[j] - fylo[j]));
+                if (sample) accumulate<T, CX>(out, u0d, sa, sb);
+                store_row<T, CX>(D + static_cast<int64_t>(y) * p.nx, out);
+                copy_row<T, CX>(tc, tn);
+                copy_row<T, CX>(tn, tq);
+                copy_row<T, CX>(fylo, fyhi);
+            }
+        } else {
+            // downward march (odd chunks): each chunk boundary is then read by
+            // both neighbours at the same end of their marches, so the second
+            // read of its rows can hit the cache.  The high-y flux of row y is
+            // carried from row y+1; every face gets the same value either way.
+            {
+                T tu[CX];
+                load_row<T, CX>(rowp(y1), tu);
+                load_row<T, CX>(rowp(y1 - 1), tc);
+                load_row<T, CX>(rowp(y1 - 2), tn);
+                row_normals<T, CX>(zy, drow(y1, 1), nq, q0, slo, w2, real, key, noise, rc);
+#pragma unroll
+                for (int j = 0; j < CX; ++j) fyhi[j] = face_flux<T, EQ>(tc[j], tu[j], zy[j], r, noise, clamps);
+            }
+            for (int y = y1 - 1; y >= y0; --y) {
+                if (y - 2 >= y0 - 1) load_row<T, CX>(rowp(y - 2), tq);
+                row_normals<T, CX>(zy, drow(y, 1), nq, q0, slo, w2, real, key, noise, rc);
+#pragma unroll
+                for (int j = 0; j < CX; ++j) fylo[j] = face_flux<T, EQ>(tn[j], tc[j], zy[j], r, noise, clamps);
+                row_normals<T, CX>(zx, drow(y, 0), nq, q0, slo, w2, real, key, noise, rc);
+                row_xflux<T, CX, EQ>(tc, zx, fxlo, fxhi, lx, LX, r, noise, clamps);
+                T out[CX];
+#pragma unroll
+                for (int j = 0; j < CX; ++j) out[j] = tc[j] + (xdiv<T, CX>(fxlo, fxhi, j) + (fyhi[j] - fylo[j]));
+                if (sample) accumulate<T, CX>(out, u0d, sa, sb);
+                store_row<T, CX>(D + static_cast<int64_t>(y) * p.nx, out);
+                copy_row<T, CX>(tc, tn);
+                copy_row<T, CX>(tn, tq);
+                copy_row<T, CX>(fyhi, fylo);
+            }
         }
     } else {
         // Predictor-corrector.  Iteration k produces the predictor row k and
