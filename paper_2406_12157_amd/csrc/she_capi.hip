@@ -478,13 +478,19 @@ static she_status plan_1d(she_handle *h, const she_config *cfg, Plan &plan)
     h->hist_elems = ho;
     h->tc_elems = to;
     // launch shape: threads per instance and Philox blocks per thread
+    // (auto: one wave up to 128 Philox blocks, else 256 threads up to 2 blocks
+    // each, else 1024 threads with one block each, so that the largest
+    // instance's per-step chain stays short and four waves per SIMD hide its
+    // latency; beyond that 256 threads with up to 8 blocks each)
     int block = cfg->block_threads;
-    if (block == 0) block = nfg_max <= 128 ? 64 : 256;
-    if (block != 64 && block != 256) return fail(nullptr, SHE_EINVAL, "block_threads must be 0, 64 or 256");
+    if (block == 0) block = nfg_max <= 128 ? 64 : nfg_max <= 512 ? 256 : nfg_max <= 1024 ? 1024 : 256;
+    if (block != 64 && block != 256 && block != 1024)
+        return fail(nullptr, SHE_EINVAL, "block_threads must be 0, 64, 256 or 1024");
     int g = (nfg_max + block - 1) / block;
     int maxg = 1;
     while (maxg < g) maxg *= 2;
-    if (maxg > 8) return fail(nullptr, SHE_EUNSUPPORTED, "1D instance too large for the resident kernel");
+    if (maxg > 8 || (block == 1024 && maxg > 1))
+        return fail(nullptr, SHE_EUNSUPPORTED, "1D instance too large for the resident kernel at this block size");
     h->block1d = block;
     h->maxg = maxg;
     const size_t nmax_pad = (h->nmax + 4) & ~3;

@@ -689,6 +689,8 @@ static hipError_t step1d_p(int block, int maxg, bool stats, int mode, const Step
     switch (block) {
     case 64: return step1d_b<T, 64>(maxg, stats, mode, a);
     case 256: return step1d_b<T, 256>(maxg, stats, mode, a);
+    case 1024:  // one Philox block per thread only (register budget of 16 waves)
+        return maxg == 1 ? step1d_t<T, 1024, 1>(stats, mode, a) : hipErrorInvalidValue;
     default: return hipErrorInvalidValue;
     }
 }

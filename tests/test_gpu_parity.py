@@ -121,8 +121,10 @@ def test_1d_launch_shape_invariance(she):
     insts = [inst1d(*c, realisation=q) for q, c in enumerate(CASES_1D[:6])]
     _, a, _ = run_both(she, insts, 2000, 0, block_threads=64)
     _, b, _ = run_both(she, insts, 2000, 0, block_threads=256)
-    for x, y in zip(a, b):
+    _, c, _ = run_both(she, insts, 2000, 0, block_threads=1024)
+    for x, y, z in zip(a, b, c):
         np.testing.assert_array_equal(x, y)
+        np.testing.assert_array_equal(x, z)
 
 
 # ---------------------------------------------------------------- 2D / 3D
