@@ -33,18 +33,23 @@
 // Sample steps: every lane adds dU = U - u0 and dU^2 of its output cells in
 // FP64; the group / workgroup sum is written to a per-chunk partial; a small
 // kernel reduces the partials per instance in a fixed order.
+#include <type_traits>
+
 #include "she_internal.hpp"
 #include "she_rng.hpp"
 
 namespace she {
 
 // Flux through a face between cells with values lo (low side) and hi, for a
-// pre-scaled number zs (see above).
-template <typename T, int EQ>
-__device__ __forceinline__ T face_flux(T lo, T hi, T zs, T r, int noise, uint32_t &clamps)
+// pre-scaled number zs (see above), in noise mode NZ (0 instantaneous,
+// 1 deterministic face value, 2 off).
+template <typename T, int EQ, int NZ>
+__device__ __forceinline__ T face_flux(T lo, T hi, T zs, T r, uint32_t &clamps)
 {
-    const T f = r * (hi - lo);
-    if (noise == 0) {
+    // the multiply-adds are written out so that every copy of this code
+    // rounds alike: a face computed in two places gets one value
+    const T d = hi - lo;
+    if constexpr (NZ == 0) {
         const T s = lo + hi;
         T a;
         if constexpr (EQ == 0) {
@@ -57,10 +62,12 @@ __device__ __forceinline__ T face_flux(T lo, T hi, T zs, T r, int noise, uint32_
                 a = sqrt(s);
             }
         }
-        return f + a * zs;
+        return fma(a, zs, r * d);
+    } else if constexpr (NZ == 1) {
+        return fma(r, d, zs);
+    } else {
+        return r * d;
     }
-    if (noise == 1) return f + zs;
-    return f;
 }
 
 __device__ __forceinline__ int wrap(int i, int n)
@@ -90,11 +97,11 @@ __device__ __forceinline__ void copy_row(T (&d)[CX], const T (&s)[CX])
 }
 
 // Scaled numbers of one lane's CX faces of direction-row `drow` (= row*dim + e).
-template <typename T, int CX>
+template <typename T, int CX, int NZ>
 __device__ __forceinline__ void row_normals(T (&z)[CX], uint32_t drow, uint32_t nq, uint32_t q0,
-                                            uint32_t slo, uint32_t w2, uint32_t real, PhiloxKey key, int noise, T rc)
+                                            uint32_t slo, uint32_t w2, uint32_t real, PhiloxKey key, T rc)
 {
-    if (noise == 2) {
+    if constexpr (NZ == 2) {
 #pragma unroll
         for (int j = 0; j < CX; ++j) z[j] = T(0);
         return;
@@ -110,18 +117,18 @@ __device__ __forceinline__ void row_normals(T (&z)[CX], uint32_t drow, uint32_t 
 // x-fluxes of one row held by a group of LX lanes: Flo[j] is the flux through
 // the low face of the lane's cell j, Fhi the flux through the high face of its
 // last cell (= the next lane's Flo[0]).
-template <typename T, int CX, int EQ>
+template <typename T, int CX, int EQ, int NZ>
 __device__ __forceinline__ void row_xflux(const T (&v)[CX], const T (&z)[CX], T (&Flo)[CX], T &Fhi, int lx, int LX,
-                                          T r, int noise, uint32_t &clamps)
+                                          T r, uint32_t &clamps)
 {
     const int lane = threadIdx.x & 63;
     const int gbase = lane - lx;
     const int left = gbase + (lx == 0 ? LX - 1 : lx - 1);
     const int right = gbase + (lx == LX - 1 ? 0 : lx + 1);
     const T vleft = __shfl(v[CX - 1], left, 64);
-    Flo[0] = face_flux<T, EQ>(vleft, v[0], z[0], r, noise, clamps);
+    Flo[0] = face_flux<T, EQ, NZ>(vleft, v[0], z[0], r, clamps);
 #pragma unroll
-    for (int j = 1; j < CX; ++j) Flo[j] = face_flux<T, EQ>(v[j - 1], v[j], z[j], r, noise, clamps);
+    for (int j = 1; j < CX; ++j) Flo[j] = face_flux<T, EQ, NZ>(v[j - 1], v[j], z[j], r, clamps);
     Fhi = __shfl(Flo[0], right, 64);
 }
 
@@ -203,119 +210,159 @@ __global__ void __launch_bounds__(256)
     double sa = 0.0, sb = 0.0;
     const double u0d = p.u0;
 
-    if constexpr (SCHEME == 0) {
-        T tc[CX], tn[CX], tq[CX], zy[CX], zx[CX], fylo[CX], fyhi[CX], fxlo[CX], fxhi;
-        if ((ch & 1) == 0) {
-            // upward march: the low-y flux of row y is carried from row y-1
-            {
-                T tp[CX];
-                load_row<T, CX>(rowp(y0 - 1), tp);
-                load_row<T, CX>(rowp(y0), tc);
-                load_row<T, CX>(rowp(y0 + 1), tn);
-                row_normals<T, CX>(zy, drow(y0, 1), nq, q0, slo, w2, real, key, noise, rc);
+    // The march loops are unrolled over the period of their register window
+    // (FE: three rows and two flux rows, period 6; PC: four rows and pairs,
+    // period 4); each unrolled copy names the buffers in rotated roles, so rows
+    // move through the window without register copies.
+    auto march = [&](auto nzc) __attribute__((always_inline)) {
+        constexpr int NZ = decltype(nzc)::value;
+        auto normals = [&](T (&z)[CX], uint32_t dr) __attribute__((always_inline)) {
+            row_normals<T, CX, NZ>(z, dr, nq, q0, slo, w2, real, key, rc);
+        };
+        auto flux = [&](T lo, T hi, T z) __attribute__((always_inline)) {
+            return face_flux<T, EQ, NZ>(lo, hi, z, r, clamps);
+        };
+        auto xflux = [&](const T (&v)[CX], const T (&z)[CX], T (&fx)[CX], T &fxh) __attribute__((always_inline)) {
+            row_xflux<T, CX, EQ, NZ>(v, z, fx, fxh, lx, LX, r, clamps);
+        };
+        auto emit = [&](const T (&out)[CX], int y) __attribute__((always_inline)) {
+            if (sample) accumulate<T, CX>(out, u0d, sa, sb);
+            store_row<T, CX>(D + static_cast<int64_t>(y) * p.nx, out);
+        };
+        const int rows = y1 - y0;
+        if constexpr (SCHEME == 0) {
+            T ra[CX], rb[CX], rq[CX], fa[CX], fb[CX];
+            // rows of the window: ra, rb, rq; flux rows: fa, fb
+            auto by6 = [&](auto &&row) __attribute__((always_inline)) {
+                for (int i = 0; i < rows; i += 6) {
+                    row(ra, rb, rq, fa, fb, i);
+                    if (i + 1 >= rows) break;
+                    row(rb, rq, ra, fb, fa, i + 1);
+                    if (i + 2 >= rows) break;
+                    row(rq, ra, rb, fa, fb, i + 2);
+                    if (i + 3 >= rows) break;
+                    row(ra, rb, rq, fb, fa, i + 3);
+                    if (i + 4 >= rows) break;
+                    row(rb, rq, ra, fa, fb, i + 4);
+                    if (i + 5 >= rows) break;
+                    row(rq, ra, rb, fb, fa, i + 5);
+                }
+            };
+            if ((ch & 1) == 0) {
+                // upward march: the low-y flux of row y is carried from row y-1
+                {
+                    T tp[CX], z[CX];
+                    load_row<T, CX>(rowp(y0 - 1), tp);
+                    load_row<T, CX>(rowp(y0), ra);
+                    load_row<T, CX>(rowp(y0 + 1), rb);
+                    normals(z, drow(y0, 1));
 #pragma unroll
-                for (int j = 0; j < CX; ++j) fylo[j] = face_flux<T, EQ>(tp[j], tc[j], zy[j], r, noise, clamps);
-            }
-            for (int y = y0; y < y1; ++y) {
-                if (y + 2 <= y1) load_row<T, CX>(rowp(y + 2), tq);
-                row_normals<T, CX>(zy, drow(y + 1, 1), nq, q0, slo, w2, real, key, noise, rc);
+                    for (int j = 0; j < CX; ++j) fa[j] = flux(tp[j], ra[j], z[j]);
+                }
+                // tc, tn: rows y, y+1; tq receives row y+2; flo: low-y flux of row y
+                by6([&](const T (&tc)[CX], const T (&tn)[CX], T (&tq)[CX], const T (&flo)[CX], T (&fhi)[CX],
+                        int i) __attribute__((always_inline)) {
+                    const int y = y0 + i;
+                    if (y + 2 <= y1) load_row<T, CX>(rowp(y + 2), tq);
+                    T z[CX], fx[CX], fxh, out[CX];
+                    normals(z, drow(y + 1, 1));
 #pragma unroll
-                for (int j = 0; j < CX; ++j) fyhi[j] = face_flux<T, EQ>(tc[j], tn[j], zy[j], r, noise, clamps);
-                row_normals<T, CX>(zx, drow(y, 0), nq, q0, slo, w2, real, key, noise, rc);
-                row_xflux<T, CX, EQ>(tc, zx, fxlo, fxhi, lx, LX, r, noise, clamps);
-                T out[CX];
+                    for (int j = 0; j < CX; ++j) fhi[j] = flux(tc[j], tn[j], z[j]);
+                    normals(z, drow(y, 0));
+                    xflux(tc, z, fx, fxh);
 #pragma unroll
-                for (int j = 0; j < CX; ++j) out[j] = tc[j] + (xdiv<T, CX>(fxlo, fxhi, j) + (fyhi[j] - fylo[j]));
-                if (sample) accumulate<T, CX>(out, u0d, sa, sb);
-                store_row<T, CX>(D + static_cast<int64_t>(y) * p.nx, out);
-                copy_row<T, CX>(tc, tn);
-                copy_row<T, CX>(tn, tq);
-                copy_row<T, CX>(fylo, fyhi);
+                    for (int j = 0; j < CX; ++j) out[j] = tc[j] + (xdiv<T, CX>(fx, fxh, j) + (fhi[j] - flo[j]));
+                    emit(out, y);
+                });
+            } else {
+                // downward march (odd chunks): each chunk boundary is then read by
+                // both neighbours at the same end of their marches, so the second
+                // read of its rows can hit the cache.  The high-y flux of row y is
+                // carried from row y+1; every face gets the same value either way.
+                {
+                    T tu[CX], z[CX];
+                    load_row<T, CX>(rowp(y1), tu);
+                    load_row<T, CX>(rowp(y1 - 1), ra);
+                    load_row<T, CX>(rowp(y1 - 2), rb);
+                    normals(z, drow(y1, 1));
+#pragma unroll
+                    for (int j = 0; j < CX; ++j) fa[j] = flux(ra[j], tu[j], z[j]);
+                }
+                // tc, tn: rows y, y-1; tq receives row y-2; fhi: high-y flux of row y
+                by6([&](const T (&tc)[CX], const T (&tn)[CX], T (&tq)[CX], const T (&fhi)[CX], T (&flo)[CX],
+                        int i) __attribute__((always_inline)) {
+                    const int y = y1 - 1 - i;
+                    if (y - 2 >= y0 - 1) load_row<T, CX>(rowp(y - 2), tq);
+                    T z[CX], fx[CX], fxh, out[CX];
+                    normals(z, drow(y, 1));
+#pragma unroll
+                    for (int j = 0; j < CX; ++j) flo[j] = flux(tn[j], tc[j], z[j]);
+                    normals(z, drow(y, 0));
+                    xflux(tc, z, fx, fxh);
+#pragma unroll
+                    for (int j = 0; j < CX; ++j) out[j] = tc[j] + (xdiv<T, CX>(fx, fxh, j) + (fhi[j] - flo[j]));
+                    emit(out, y);
+                });
             }
         } else {
-            // downward march (odd chunks): each chunk boundary is then read by
-            // both neighbours at the same end of their marches, so the second
-            // read of its rows can hit the cache.  The high-y flux of row y is
-            // carried from row y+1; every face gets the same value either way.
-            {
-                T tu[CX];
-                load_row<T, CX>(rowp(y1), tu);
-                load_row<T, CX>(rowp(y1 - 1), tc);
-                load_row<T, CX>(rowp(y1 - 2), tn);
-                row_normals<T, CX>(zy, drow(y1, 1), nq, q0, slo, w2, real, key, noise, rc);
+            // Predictor-corrector.  Iteration k produces the predictor row k and
+            // the corrected row k-1.  Per iteration: tm, tc, tn rows k-1..k+1 and
+            // tq receiving row k+2; sc the predictor row k-1, sn receiving row k;
+            // zyc, zyn the y numbers of rows k, k+1; zxm, zxc the x numbers of
+            // rows k-1, k; fpc, fpn the predictor low-y fluxes of rows k, k+1;
+            // fcm, fcc the corrector low-y fluxes of rows k-1, k.
+            T ta[CX], tb[CX], tcc[CX], td[CX], sa_[CX], sb_[CX], ya[CX], yb[CX], xa[CX], xb[CX], pa[CX], pb[CX],
+                ma[CX], mb[CX];
+            const int k0 = y0 - 1;
+            load_row<T, CX>(rowp(k0 - 1), ta);
+            load_row<T, CX>(rowp(k0), tb);
+            load_row<T, CX>(rowp(k0 + 1), tcc);
+            normals(ya, drow(k0, 1));
 #pragma unroll
-                for (int j = 0; j < CX; ++j) fyhi[j] = face_flux<T, EQ>(tc[j], tu[j], zy[j], r, noise, clamps);
-            }
-            for (int y = y1 - 1; y >= y0; --y) {
-                if (y - 2 >= y0 - 1) load_row<T, CX>(rowp(y - 2), tq);
-                row_normals<T, CX>(zy, drow(y, 1), nq, q0, slo, w2, real, key, noise, rc);
+            for (int j = 0; j < CX; ++j) pa[j] = flux(ta[j], tb[j], ya[j]);
+            auto row = [&](const T (&tm)[CX], const T (&tc)[CX], const T (&tn)[CX], T (&tq)[CX], const T (&sc)[CX],
+                           T (&sn)[CX], const T (&zyc)[CX], T (&zyn)[CX], const T (&zxm)[CX], T (&zxc)[CX],
+                           const T (&fpc)[CX], T (&fpn)[CX], const T (&fcm)[CX], T (&fcc)[CX],
+                           int i) __attribute__((always_inline)) {
+                const int k = k0 + i;
+                load_row<T, CX>(rowp(k + 2), tq);
+                normals(zyn, drow(k + 1, 1));
 #pragma unroll
-                for (int j = 0; j < CX; ++j) fylo[j] = face_flux<T, EQ>(tn[j], tc[j], zy[j], r, noise, clamps);
-                row_normals<T, CX>(zx, drow(y, 0), nq, q0, slo, w2, real, key, noise, rc);
-                row_xflux<T, CX, EQ>(tc, zx, fxlo, fxhi, lx, LX, r, noise, clamps);
-                T out[CX];
+                for (int j = 0; j < CX; ++j) fpn[j] = flux(tc[j], tn[j], zyn[j]);
+                normals(zxc, drow(k, 0));
+                T fx[CX], fxh;
+                xflux(tc, zxc, fx, fxh);
 #pragma unroll
-                for (int j = 0; j < CX; ++j) out[j] = tc[j] + (xdiv<T, CX>(fxlo, fxhi, j) + (fyhi[j] - fylo[j]));
-                if (sample) accumulate<T, CX>(out, u0d, sa, sb);
-                store_row<T, CX>(D + static_cast<int64_t>(y) * p.nx, out);
-                copy_row<T, CX>(tc, tn);
-                copy_row<T, CX>(tn, tq);
-                copy_row<T, CX>(fyhi, fylo);
+                for (int j = 0; j < CX; ++j) sn[j] = tc[j] + (xdiv<T, CX>(fx, fxh, j) + (fpn[j] - fpc[j]));
+                if (i >= 1) {
+#pragma unroll
+                    for (int j = 0; j < CX; ++j) fcc[j] = flux(sc[j], sn[j], zyc[j]);
+                }
+                if (i >= 2) {
+                    // corrected row k-1 from predictor rows k-2 (fcm), k-1 (sc), k (sn)
+                    xflux(sc, zxm, fx, fxh);
+                    T out[CX];
+#pragma unroll
+                    for (int j = 0; j < CX; ++j)
+                        out[j] = T(0.5) * ((tm[j] + sc[j]) + (xdiv<T, CX>(fx, fxh, j) + (fcc[j] - fcm[j])));
+                    emit(out, k - 1);
+                }
+            };
+            const int iters = rows + 2;  // k = y0-1 .. y1
+            for (int i = 0; i < iters; i += 4) {
+                row(ta, tb, tcc, td, sa_, sb_, ya, yb, xa, xb, pa, pb, ma, mb, i);
+                if (i + 1 >= iters) break;
+                row(tb, tcc, td, ta, sb_, sa_, yb, ya, xb, xa, pb, pa, mb, ma, i + 1);
+                if (i + 2 >= iters) break;
+                row(tcc, td, ta, tb, sa_, sb_, ya, yb, xa, xb, pa, pb, ma, mb, i + 2);
+                if (i + 3 >= iters) break;
+                row(td, ta, tb, tcc, sb_, sa_, yb, ya, xb, xa, pb, pa, mb, ma, i + 3);
             }
         }
-    } else {
-        // Predictor-corrector.  Iteration k produces the predictor row k and
-        // the corrected row k-1.
-        T tm[CX], tc[CX], tn[CX], tq[CX];   // T rows k-1, k, k+1, k+2
-        T sc[CX];                           // predictor row k-1
-        T zyc[CX], zyn[CX];                 // y numbers of rows k, k+1
-        T zxm[CX], zxc[CX];                 // x numbers of rows k-1, k
-        T fpc[CX], fpn[CX];                 // predictor low-y fluxes of rows k, k+1
-        T fcm[CX], fcc[CX];                 // corrector low-y fluxes of rows k-1, k
-        T fx[CX], fxh;
-        const int k0 = y0 - 1;
-        load_row<T, CX>(rowp(k0 - 1), tm);
-        load_row<T, CX>(rowp(k0), tc);
-        load_row<T, CX>(rowp(k0 + 1), tn);
-        row_normals<T, CX>(zyc, drow(k0, 1), nq, q0, slo, w2, real, key, noise, rc);
-#pragma unroll
-        for (int j = 0; j < CX; ++j) fpc[j] = face_flux<T, EQ>(tm[j], tc[j], zyc[j], r, noise, clamps);
-        for (int k = k0; k <= y1; ++k) {
-            const int i = k - k0;
-            load_row<T, CX>(rowp(k + 2), tq);
-            row_normals<T, CX>(zyn, drow(k + 1, 1), nq, q0, slo, w2, real, key, noise, rc);
-#pragma unroll
-            for (int j = 0; j < CX; ++j) fpn[j] = face_flux<T, EQ>(tc[j], tn[j], zyn[j], r, noise, clamps);
-            row_normals<T, CX>(zxc, drow(k, 0), nq, q0, slo, w2, real, key, noise, rc);
-            row_xflux<T, CX, EQ>(tc, zxc, fx, fxh, lx, LX, r, noise, clamps);
-            T snew[CX];
-#pragma unroll
-            for (int j = 0; j < CX; ++j) snew[j] = tc[j] + (xdiv<T, CX>(fx, fxh, j) + (fpn[j] - fpc[j]));
-            if (i >= 1) {
-#pragma unroll
-                for (int j = 0; j < CX; ++j) fcc[j] = face_flux<T, EQ>(sc[j], snew[j], zyc[j], r, noise, clamps);
-            }
-            if (i >= 2) {
-                // corrected row k-1 from predictor rows k-2 (fcm), k-1 (sc), k (snew)
-                row_xflux<T, CX, EQ>(sc, zxm, fx, fxh, lx, LX, r, noise, clamps);
-                T out[CX];
-#pragma unroll
-                for (int j = 0; j < CX; ++j)
-                    out[j] = T(0.5) * ((tm[j] + sc[j]) + (xdiv<T, CX>(fx, fxh, j) + (fcc[j] - fcm[j])));
-                if (sample) accumulate<T, CX>(out, u0d, sa, sb);
-                store_row<T, CX>(D + static_cast<int64_t>(k - 1) * p.nx, out);
-            }
-            copy_row<T, CX>(tm, tc);
-            copy_row<T, CX>(tc, tn);
-            copy_row<T, CX>(tn, tq);
-            copy_row<T, CX>(sc, snew);
-            copy_row<T, CX>(zyc, zyn);
-            copy_row<T, CX>(zxm, zxc);
-            copy_row<T, CX>(fpc, fpn);
-            copy_row<T, CX>(fcm, fcc);
-        }
-    }
-
+    };
+    if (noise == 0) march(std::integral_constant<int, 0>{});
+    else if (noise == 1) march(std::integral_constant<int, 1>{});
+    else march(std::integral_constant<int, 2>{});
     if (sample) {
         for (int off = 1; off < LX; off <<= 1) {
             sa += __shfl_xor(sa, off, 64);
@@ -386,77 +433,106 @@ __global__ void __launch_bounds__(256)
         return static_cast<uint32_t>((wrap(zz, nz) * ny + wrap(yy, ny)) * 3 + e);
     };
 
-    T tc[CX], tn[CX], tq[CX], zz3[CX], fzlo[CX], fzhi[CX];
-    {
-        T tp[CX];
-        load_row<T, CX>(S + rowp(y, z0 - 1), tp);
-        load_row<T, CX>(S + rowp(y, z0), tc);
-        load_row<T, CX>(S + rowp(y, z0 + 1), tn);
-        row_normals<T, CX>(zz3, drow(y, z0, 2), nq, q0, slo, w2, real, key, noise, rc);
-#pragma unroll
-        for (int j = 0; j < CX; ++j) fzlo[j] = face_flux<T, EQ>(tp[j], tc[j], zz3[j], r, noise, clamps);
-        T *dstp = tsh + ((z0 & 1) * ty + g) * nx + cell0;
-#pragma unroll
-        for (int j = 0; j < CX; ++j) dstp[j] = tc[j];
-    }
-    __syncthreads();
-
     double sa = 0.0, sb = 0.0;
     const double u0d = p.u0;
-    for (int zi = z0; zi < z1; ++zi) {
-        const int buf = zi & 1;
-        load_row<T, CX>(S + rowp(y, zi + 2), tq);
-        row_normals<T, CX>(zz3, drow(y, zi + 1, 2), nq, q0, slo, w2, real, key, noise, rc);
-#pragma unroll
-        for (int j = 0; j < CX; ++j) fzhi[j] = face_flux<T, EQ>(tc[j], tn[j], zz3[j], r, noise, clamps);
 
-        T zx[CX], fxlo[CX], fxhi;
-        row_normals<T, CX>(zx, drow(y, zi, 0), nq, q0, slo, w2, real, key, noise, rc);
-        row_xflux<T, CX, EQ>(tc, zx, fxlo, fxhi, lx, LX, r, noise, clamps);
-
-        T zy[CX], ylo[CX], fylo[CX];
-        row_normals<T, CX>(zy, drow(y, zi, 1), nq, q0, slo, w2, real, key, noise, rc);
-        if (g > 0) {
-            const T *q = tsh + (buf * ty + g - 1) * nx + cell0;
-#pragma unroll
-            for (int j = 0; j < CX; ++j) ylo[j] = q[j];
-        } else {
-            load_row<T, CX>(S + rowp(y - 1, zi), ylo);
-        }
-#pragma unroll
-        for (int j = 0; j < CX; ++j) fylo[j] = face_flux<T, EQ>(ylo[j], tc[j], zy[j], r, noise, clamps);
+    // As in 2D, the march is unrolled over the period of its register window
+    // (three planes of the row and two z-flux rows: period 6) and the noise
+    // mode is fixed per copy.
+    auto march = [&](auto nzc) __attribute__((always_inline)) {
+        constexpr int NZ = decltype(nzc)::value;
+        auto normals = [&](T (&z)[CX], uint32_t dr) __attribute__((always_inline)) {
+            row_normals<T, CX, NZ>(z, dr, nq, q0, slo, w2, real, key, rc);
+        };
+        auto flux = [&](T lo, T hi, T z) __attribute__((always_inline)) {
+            return face_flux<T, EQ, NZ>(lo, hi, z, r, clamps);
+        };
+        T ra[CX], rb[CX], rq[CX], fa[CX], fb[CX];
         {
-            T *fp = fsh + (buf * ty + g) * nx + cell0;
+            T tp[CX], z[CX];
+            load_row<T, CX>(S + rowp(y, z0 - 1), tp);
+            load_row<T, CX>(S + rowp(y, z0), ra);
+            load_row<T, CX>(S + rowp(y, z0 + 1), rb);
+            normals(z, drow(y, z0, 2));
 #pragma unroll
-            for (int j = 0; j < CX; ++j) fp[j] = fylo[j];
-            T *tp = tsh + (((zi + 1) & 1) * ty + g) * nx + cell0;
+            for (int j = 0; j < CX; ++j) fa[j] = flux(tp[j], ra[j], z[j]);
+            T *dstp = tsh + ((z0 & 1) * ty + g) * nx + cell0;
 #pragma unroll
-            for (int j = 0; j < CX; ++j) tp[j] = tn[j];
+            for (int j = 0; j < CX; ++j) dstp[j] = ra[j];
         }
         __syncthreads();
-        T fyhi[CX];
-        if (g + 1 < ty) {
-            const T *fp = fsh + (buf * ty + g + 1) * nx + cell0;
+        // tc, tn: planes zi, zi+1 of the row; tq receives plane zi+2; fzlo: the
+        // low-z flux of plane zi
+        auto plane = [&](const T (&tc)[CX], const T (&tn)[CX], T (&tq)[CX], const T (&fzlo)[CX], T (&fzhi)[CX],
+                         int zi) __attribute__((always_inline)) {
+            const int buf = zi & 1;
+            load_row<T, CX>(S + rowp(y, zi + 2), tq);
+            T z[CX];
+            normals(z, drow(y, zi + 1, 2));
 #pragma unroll
-            for (int j = 0; j < CX; ++j) fyhi[j] = fp[j];
-        } else {
-            T yhi[CX], zyh[CX];
-            load_row<T, CX>(S + rowp(y + 1, zi), yhi);
-            row_normals<T, CX>(zyh, drow(y + 1, zi, 1), nq, q0, slo, w2, real, key, noise, rc);
-#pragma unroll
-            for (int j = 0; j < CX; ++j) fyhi[j] = face_flux<T, EQ>(tc[j], yhi[j], zyh[j], r, noise, clamps);
-        }
-        T out[CX];
-#pragma unroll
-        for (int j = 0; j < CX; ++j)
-            out[j] = tc[j] + ((xdiv<T, CX>(fxlo, fxhi, j) + (fyhi[j] - fylo[j])) + (fzhi[j] - fzlo[j]));
-        if (sample) accumulate<T, CX>(out, u0d, sa, sb);
-        store_row<T, CX>(D + rowp(y, zi), out);
-        copy_row<T, CX>(tc, tn);
-        copy_row<T, CX>(tn, tq);
-        copy_row<T, CX>(fzlo, fzhi);
-    }
+            for (int j = 0; j < CX; ++j) fzhi[j] = flux(tc[j], tn[j], z[j]);
 
+            T fxlo[CX], fxhi;
+            normals(z, drow(y, zi, 0));
+            row_xflux<T, CX, EQ, NZ>(tc, z, fxlo, fxhi, lx, LX, r, clamps);
+
+            T ylo[CX], fylo[CX];
+            normals(z, drow(y, zi, 1));
+            if (g > 0) {
+                const T *q = tsh + (buf * ty + g - 1) * nx + cell0;
+#pragma unroll
+                for (int j = 0; j < CX; ++j) ylo[j] = q[j];
+            } else {
+                load_row<T, CX>(S + rowp(y - 1, zi), ylo);
+            }
+#pragma unroll
+            for (int j = 0; j < CX; ++j) fylo[j] = flux(ylo[j], tc[j], z[j]);
+            {
+                T *fp = fsh + (buf * ty + g) * nx + cell0;
+#pragma unroll
+                for (int j = 0; j < CX; ++j) fp[j] = fylo[j];
+                T *tp = tsh + (((zi + 1) & 1) * ty + g) * nx + cell0;
+#pragma unroll
+                for (int j = 0; j < CX; ++j) tp[j] = tn[j];
+            }
+            __syncthreads();
+            T fyhi[CX];
+            if (g + 1 < ty) {
+                const T *fp = fsh + (buf * ty + g + 1) * nx + cell0;
+#pragma unroll
+                for (int j = 0; j < CX; ++j) fyhi[j] = fp[j];
+            } else {
+                T yhi[CX];
+                load_row<T, CX>(S + rowp(y + 1, zi), yhi);
+                normals(z, drow(y + 1, zi, 1));
+#pragma unroll
+                for (int j = 0; j < CX; ++j) fyhi[j] = flux(tc[j], yhi[j], z[j]);
+            }
+            T out[CX];
+#pragma unroll
+            for (int j = 0; j < CX; ++j)
+                out[j] = tc[j] + ((xdiv<T, CX>(fxlo, fxhi, j) + (fyhi[j] - fylo[j])) + (fzhi[j] - fzlo[j]));
+            if (sample) accumulate<T, CX>(out, u0d, sa, sb);
+            store_row<T, CX>(D + rowp(y, zi), out);
+        };
+        const int planes = z1 - z0;
+        for (int i = 0; i < planes; i += 6) {
+            plane(ra, rb, rq, fa, fb, z0 + i);
+            if (i + 1 >= planes) break;
+            plane(rb, rq, ra, fb, fa, z0 + i + 1);
+            if (i + 2 >= planes) break;
+            plane(rq, ra, rb, fa, fb, z0 + i + 2);
+            if (i + 3 >= planes) break;
+            plane(ra, rb, rq, fb, fa, z0 + i + 3);
+            if (i + 4 >= planes) break;
+            plane(rb, rq, ra, fa, fb, z0 + i + 4);
+            if (i + 5 >= planes) break;
+            plane(rq, ra, rb, fb, fa, z0 + i + 5);
+        }
+    };
+    if (noise == 0) march(std::integral_constant<int, 0>{});
+    else if (noise == 1) march(std::integral_constant<int, 1>{});
+    else march(std::integral_constant<int, 2>{});
     if (sample) {
         for (int off = 1; off < LX; off <<= 1) {
             sa += __shfl_xor(sa, off, 64);
