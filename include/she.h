@@ -153,9 +153,10 @@ typedef struct {
                                      t > burn_in and t % sample_every == 0    */
     int32_t sample_every;         /* >= 1                                      */
     uint32_t stats_mask;          /* SHE_STAT_* bits                           */
-    int32_t block_threads;        /* tuning: 1D threads per instance: 0 (auto),
-                                     64, 256 or 1024 (one Philox block of four
-                                     faces per thread at most)              */
+    int32_t block_threads;        /* tuning: 1D threads per workgroup: 0 (auto),
+                                     64, 256 or 512; an instance takes whole
+                                     waves of a workgroup, small instances
+                                     share one                              */
     int32_t rows_per_block;       /* tuning: 2D/3D march length (0 auto)      */
     int32_t rows_per_group;       /* tuning: 3D rows per workgroup (0 auto)   */
     int32_t tuning_flags;         /* SHE_TUNE_* bits (0 = defaults)           */

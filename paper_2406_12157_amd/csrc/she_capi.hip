@@ -41,7 +41,9 @@ struct she_handle {
 
     // 1D
     Inst1D *d_tab = nullptr;
-    int32_t *d_order = nullptr;
+    Seg1D *d_segs = nullptr;      // per wave of the 1D launch
+    std::vector<Seg1D> segs_host;
+    int blocks1d = 0;             // workgroups of the 1D launch
     void *d_pool = nullptr;
     std::vector<Inst1D> tab;
     int64_t total_cells = 0;
@@ -477,29 +479,70 @@ static she_status plan_1d(she_handle *h, const she_config *cfg, Plan &plan)
     h->c_elems = co;
     h->hist_elems = ho;
     h->tc_elems = to;
-    // launch shape: threads per instance and Philox blocks per thread
-    // (auto: one wave up to 128 Philox blocks, else 256 threads up to 2 blocks
-    // each, else 1024 threads with one block each, so that the largest
-    // instance's per-step chain stays short and four waves per SIMD hide its
-    // latency; beyond that 256 threads with up to 8 blocks each)
-    int block = cfg->block_threads;
-    if (block == 0) block = nfg_max <= 128 ? 64 : nfg_max <= 512 ? 256 : nfg_max <= 1024 ? 1024 : 256;
-    if (block != 64 && block != 256 && block != 1024)
-        return fail(nullptr, SHE_EINVAL, "block_threads must be 0, 64, 256 or 1024");
-    int g = (nfg_max + block - 1) / block;
-    int maxg = 1;
-    while (maxg < g) maxg *= 2;
-    if (maxg > 8 || (block == 1024 && maxg > 1))
+    // Launch shape: threads per workgroup and Philox blocks per thread.  Auto:
+    // the smallest shape whose workgroup holds the largest instance with at
+    // most one block per thread up to 512 threads (64 x 1, 64 x 2, 256 x 1,
+    // 512 x 1), then 512 threads with 2 or 4 blocks each.
+    const int mode = !h->pcr_host.empty() ? 2 : (h->varc ? 1 : 0);
+    int block = cfg->block_threads, maxg = 1;
+    if (block == 0) {
+        if (nfg_max <= 64) block = 64;
+        else if (nfg_max <= 128) block = 64, maxg = 2;
+        else if (nfg_max <= 256) block = 256;
+        else block = 512, maxg = nfg_max <= 512 ? 1 : (nfg_max <= 1024 ? 2 : 4);
+    } else {
+        if (block != 64 && block != 256 && block != 512)
+            return fail(nullptr, SHE_EINVAL, "block_threads must be 0, 64, 256 or 512");
+        const int g = (nfg_max + block - 1) / block;
+        while (maxg < g) maxg *= 2;
+    }
+    if (maxg > (block == 512 ? 4 : 2))
         return fail(nullptr, SHE_EUNSUPPORTED, "1D instance too large for the resident kernel at this block size");
     h->block1d = block;
     h->maxg = maxg;
-    const size_t nmax_pad = (h->nmax + 4) & ~3;
-    h->smem1d = (3 * nmax_pad + 8) * es * ((h->varc || !h->pcr_host.empty()) ? 2 : 1);
-    if (h->smem1d > 64 * 1024)
-        return fail(nullptr, SHE_EUNSUPPORTED, "1D instance too large for LDS (64 KB per workgroup)");
+    // Instances take whole waves (as many as they have Philox blocks, up to
+    // the workgroup) and are packed first-fit, largest first, into
+    // workgroups of block / 64 waves and at most 64 KB of LDS.
+    {
+        const int W = block / 64;
+        constexpr int kLdsCap = 64 * 1024;
+        std::vector<int> nw(h->n_inst), bytes(h->n_inst), idx(h->n_inst);
+        for (int i = 0; i < h->n_inst; ++i) {
+            const int n = h->tab[i].n, nf = h->tab[i].bc == SHE_DIRICHLET ? n + 1 : n;
+            const int nfg = (nf + 3) / 4;
+            nw[i] = std::min(W, (nfg + 63) / 64);
+            bytes[i] = seg_lds(n, nf, static_cast<int32_t>(es), mode).total;
+            if (bytes[i] > kLdsCap)
+                return fail(nullptr, SHE_EUNSUPPORTED, "1D instance too large for LDS (64 KB per workgroup)");
+            idx[i] = i;
+        }
+        std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) {
+            if (nw[a] != nw[b]) return nw[a] > nw[b];
+            const int64_t wa = static_cast<int64_t>(h->tab[a].n) * (1 + h->tab[a].scheme);
+            const int64_t wb = static_cast<int64_t>(h->tab[b].n) * (1 + h->tab[b].scheme);
+            return wa > wb;
+        });
+        std::vector<int> used_w, used_b;
+        h->segs_host.clear();
+        for (int i : idx) {
+            size_t bin = 0;
+            while (bin < used_w.size() && (used_w[bin] + nw[i] > W || used_b[bin] + bytes[i] > kLdsCap)) ++bin;
+            if (bin == used_w.size()) {
+                used_w.push_back(0);
+                used_b.push_back(0);
+                h->segs_host.resize(h->segs_host.size() + W, Seg1D{-1, 0, 0, 0});
+            }
+            for (int w = 0; w < nw[i]; ++w)
+                h->segs_host[bin * W + used_w[bin] + w] = Seg1D{i, used_w[bin], nw[i], used_b[bin]};
+            used_w[bin] += nw[i];
+            used_b[bin] += bytes[i];
+        }
+        h->blocks1d = static_cast<int>(used_w.size());
+        h->smem1d = static_cast<size_t>(*std::max_element(used_b.begin(), used_b.end()));
+    }
 
     plan.add(reinterpret_cast<void **>(&h->d_tab), sizeof(Inst1D) * h->n_inst);
-    plan.add(reinterpret_cast<void **>(&h->d_order), sizeof(int32_t) * h->n_inst);
+    plan.add(reinterpret_cast<void **>(&h->d_segs), sizeof(Seg1D) * h->segs_host.size());
     plan.add(&h->d_pool, es * off);
     if (h->mask & (SHE_STAT_MOMENTS | SHE_STAT_CORR | SHE_STAT_TCORR)) {
         plan.add(reinterpret_cast<void **>(&h->d_s1), sizeof(double) * off);
@@ -724,7 +767,6 @@ extern "C" she_status she_create(const she_config *cfg, she_handle **out)
     // host sources of the asynchronous copies below; they live until the
     // stream synchronisation at the end of creation
     std::vector<double> sd(h->n_inst);
-    std::vector<int32_t> order;
     std::vector<float> coef32;
     std::vector<uint32_t> real;
     for (int i = 0; i < h->n_inst; ++i) sd[i] = h->inst[i].init_sd;
@@ -739,16 +781,9 @@ extern "C" she_status she_create(const she_config *cfg, she_handle **out)
     } while (0)
     CREATE_HIP(hipMemcpyAsync(h->d_init_sd, sd.data(), sizeof(double) * h->n_inst, hipMemcpyHostToDevice, s));
     if (h->dim == 1) {
-        // largest instances first (longest-processing-time order of the workgroups)
-        order.resize(h->n_inst);
-        std::iota(order.begin(), order.end(), 0);
-        std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
-            const int64_t wa = static_cast<int64_t>(h->tab[a].n) * (1 + h->tab[a].scheme);
-            const int64_t wb = static_cast<int64_t>(h->tab[b].n) * (1 + h->tab[b].scheme);
-            return wa > wb;
-        });
         CREATE_HIP(hipMemcpyAsync(h->d_tab, h->tab.data(), sizeof(Inst1D) * h->n_inst, hipMemcpyHostToDevice, s));
-        CREATE_HIP(hipMemcpyAsync(h->d_order, order.data(), sizeof(int32_t) * h->n_inst, hipMemcpyHostToDevice, s));
+        CREATE_HIP(hipMemcpyAsync(h->d_segs, h->segs_host.data(), sizeof(Seg1D) * h->segs_host.size(),
+                                  hipMemcpyHostToDevice, s));
         if (!h->pcr_host.empty())
             CREATE_HIP(hipMemcpyAsync(h->d_pcr, h->pcr_host.data(), sizeof(double) * h->pcr_host.size(),
                                       hipMemcpyHostToDevice, s));
@@ -895,8 +930,8 @@ static she_status advance(she_handle *h, int64_t nsteps, bool sampling)
                 k = std::min<int64_t>(k, h->every * (j0 + room + 1) - 1 - h->steps);
             }
             const int mode = !h->pcr_host.empty() ? 2 : (h->varc ? 1 : 0);
-            SHE_HIP(h, launch_step1d(h->prec, h->block1d, h->maxg, stats, mode, h->n_inst, h->smem1d, s,
-                                     h->d_tab, h->d_order, h->d_pool, h->d_coef, h->d_pcr, h->steps,
+            SHE_HIP(h, launch_step1d(h->prec, h->block1d, h->maxg, stats, mode, h->blocks1d, h->smem1d, s,
+                                     h->d_tab, h->d_segs, h->d_pool, h->d_coef, h->d_pcr, h->steps,
                                      static_cast<int32_t>(k),
                                      h->burn_in, h->every, h->mask, st));
             if (tc) {

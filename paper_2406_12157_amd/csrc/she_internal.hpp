@@ -59,6 +59,55 @@ struct Stats1D {
     int32_t pad;
 };
 
+// One wave's place in a 1D launch: waves [w0, w0 + nw) of a workgroup serve
+// instance `inst` (-1: the wave is idle and exits); the instance's LDS region
+// starts `lds` bytes into the workgroup's dynamic LDS.  Several instances
+// can share a workgroup; each keeps to its own waves and region.
+struct Seg1D {
+    int32_t inst;
+    int32_t w0;
+    int32_t nw;
+    int32_t lds;
+};
+
+// LDS region of one 1D instance (byte offsets, 16-byte aligned parts):
+// exchange arrays [2 buffers][first value, last value, face-0 number][nfg
+// rounded up to 4] of the state type; the statistics reduction (3 x 16
+// doubles and a flag); with material arrays (mode >= 1) r_f and s_f [nf + 4]
+// and w_i [n + 4] of the state type; for implicit schemes (mode 2) an FP64
+// array [n] for the reduction.
+struct SegLds {
+    int32_t xch, red, rf, sf, wc, pd, total;
+};
+
+__host__ __device__ inline int32_t lds_align16(int32_t b) { return (b + 15) & ~15; }
+
+__host__ __device__ inline SegLds seg_lds(int32_t n, int32_t nf, int32_t es, int32_t mode)
+{
+    SegLds l{};
+    const int32_t nfg = (nf + 3) >> 2, nfgp = (nfg + 3) & ~3;
+    int32_t o = 0;
+    l.xch = o;
+    o = lds_align16(o + 6 * nfgp * es);
+    l.red = o;
+    o = lds_align16(o + 3 * 16 * 8 + 4);
+    l.rf = l.sf = l.wc = l.pd = -1;
+    if (mode >= 1) {
+        l.rf = o;
+        o = lds_align16(o + (nf + 4) * es);
+        l.sf = o;
+        o = lds_align16(o + (nf + 4) * es);
+        l.wc = o;
+        o = lds_align16(o + (n + 4) * es);
+    }
+    if (mode == 2) {
+        l.pd = o;
+        o = lds_align16(o + n * 8);
+    }
+    l.total = o;
+    return l;
+}
+
 // Parameters of a homogeneous 2D/3D batch.
 struct ParamsND {
     int32_t nx, ny, nz;     // nz = 1 in 2D
@@ -107,8 +156,9 @@ namespace she {
 // mode 0: uniform explicit batch; 1: some instance has material coefficients
 // (k_off >= 0 in `coef`; r_f, s_f, w_i of every instance staged in LDS);
 // 2: some instance is implicit (reduction factors in `pcr`; mode 1 included).
+// segs: n_blocks * block / 64 wave entries.
 hipError_t launch_step1d(int prec, int block, int maxg, bool stats, int mode, int n_blocks, size_t smem,
-                         hipStream_t s, const Inst1D *tab, const int32_t *order, void *pool,
+                         hipStream_t s, const Inst1D *tab, const Seg1D *segs, void *pool,
                          const void *coef, const double *pcr, int64_t step0, int32_t nsteps, int64_t burn_in,
                          int32_t every, uint32_t mask, Stats1D st);
 // Initial state of 1D instances: steady profile + init_sd * N(tag 1, step 0, face = cell).

@@ -24,11 +24,13 @@
 // F_i), staged in LDS next to the state.  Uniform instances of such a batch
 // get uniform arrays (bit-identical to the uniform kernel).
 //
-// Work split: thread t owns Philox blocks g = t, t + BLOCK, ...; block g holds
-// faces 4g..4g+3, which are the low faces of cells 4g..4g+3, so one Philox
-// call and two Box-Muller pairs serve four cells and PC re-uses the numbers
-// from registers.  Neighbour values go through LDS; two barriers per FE step,
-// four per PC step.
+// Work split: an instance is served by a run of whole waves of a workgroup
+// (small instances share a workgroup, each with its own waves and LDS
+// region); its thread t owns Philox blocks g = t, t + TS, ... (TS threads);
+// block g holds faces 4g..4g+3, which are the low faces of cells 4g..4g+3,
+// so one Philox call and two Box-Muller pairs serve four cells and PC re-uses
+// the numbers from registers.  The state stays in registers for the whole
+// launch; one LDS exchange and one barrier per FE step, two per PC step.
 //
 // Statistics on sample steps: per-cell FP64 sums of dU and dU^2 kept in
 // registers for the whole launch, spatial sums reduced over the workgroup,
@@ -38,6 +40,8 @@
 // and added to the FP64 N x N sum.  For the time correlation each sample row
 // also goes to a per-instance history ring; after the launch, k_tcorr adds the
 // lag products of the new rows (one thread per cell and lag, FP64).
+#include <type_traits>
+
 #include "she_internal.hpp"
 #include "she_rng.hpp"
 
@@ -60,6 +64,15 @@ __device__ __forceinline__ T face_amp(int eq, T v, uint32_t &clamps)
     return sqrt(q);
 }
 
+// Value of the last of the first `m` (1..4) entries, chosen among values
+// (a select of array elements as lvalues would become an address select and
+// move the array to private memory).
+template <typename T>
+__device__ __forceinline__ T last_of(int m, T a0, T a1, T a2, T a3)
+{
+    return m >= 4 ? a3 : (m == 3 ? a2 : (m == 2 ? a1 : a0));
+}
+
 __device__ __forceinline__ f32x4 mfma16x16x4(float a, float b, f32x4 c)
 {
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
@@ -71,17 +84,18 @@ __device__ __forceinline__ f64x4 mfma16x16x4(double a, double b, f64x4 c)
 }
 
 // C[N x N] += X^T X for a full block X[256 x N] (row = snapshot).  Tiles of
-// 16 x 16 over the upper triangle are spread over the waves; each lane
-// accumulates four outputs of its tile over K = 256 in the matrix-core
-// accumulator type and adds them to the FP64 sum (both triangles).
+// 16 x 16 over the upper triangle are spread over the instance's waves
+// (wave = 0 .. nwave-1); each lane accumulates four outputs of its tile over
+// K = 256 in the matrix-core accumulator type and adds them to the FP64 sum
+// (both triangles).
 // Operand layout of the 16x16x4 instructions: lane l supplies A[l%16][l/16]
 // and B[l/16][l%16]; output element v of lane l is D[4(l/16)+v][l%16] for
 // the FP32 form and D[(l/16)+4v][l%16] for the FP64 form.
 template <typename T>
-__device__ void xtx_block(const T *__restrict__ X, double *__restrict__ Cm, int N)
+__device__ void xtx_block(const T *__restrict__ X, double *__restrict__ Cm, int N, int wave, int nwave)
 {
     using acc_t = typename std::conditional<std::is_same<T, float>::value, f32x4, f64x4>::type;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwave = blockDim.x >> 6;
+    const int lane = threadIdx.x & 63;
     const int nt = (N + 15) >> 4;
     const int ntiles = nt * (nt + 1) / 2;
     for (int t = wave; t < ntiles; t += nwave) {
@@ -116,65 +130,95 @@ __device__ void xtx_block(const T *__restrict__ X, double *__restrict__ Cm, int 
 // MODE 0: uniform explicit batch; 1: material coefficients (VARC); 2: some
 // instance is implicit (material arrays available as well).  Each mode is
 // compiled separately so that a batch pays only for the paths it uses.
+//
+// Thread t of an instance's waves owns Philox blocks g = t + s TS (s < MAXG,
+// TS the instance's thread count): the faces 4g..4g+3 and the cells 4g..4g+3,
+// whose values stay in registers.  A stage (the FE step, or either half of a
+// PC step) publishes each block's first and last cell value (and, once per
+// step, the number of its face 4g) in LDS, passes one barrier, reads the
+// values next to its block and computes five fluxes: its own four faces and
+// the face after its last cell, which the next block computes as its face 0
+// as well (same inputs, same code, so the two agree bit for bit and the sum
+// is conserved).  The exchange arrays alternate between two buffers, so one
+// barrier per stage suffices.
 template <typename T, int BLOCK, int MAXG, bool STATS, int MODE>
 __global__ void __launch_bounds__(BLOCK)
-    k_step1d(const Inst1D *__restrict__ tab, const int32_t *__restrict__ order, T *__restrict__ pool,
+    k_step1d(const Inst1D *__restrict__ tab, const Seg1D *__restrict__ segs, T *__restrict__ pool,
              const T *__restrict__ coef, const double *__restrict__ pcr, int64_t step0, int32_t nsteps,
              int64_t burn_in, int32_t every, uint32_t mask, Stats1D st)
 {
     constexpr bool VARC = MODE >= 1;
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    __shared__ double red[3][BLOCK / 64];
-    __shared__ int stop_flag;
-
-    const int inst = order[blockIdx.x];
+    const int wave = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x >> 6));
+    const Seg1D seg = segs[static_cast<int64_t>(blockIdx.x) * (BLOCK / 64) + wave];
+    if (seg.inst < 0) return;  // idle wave (barriers count the waves still running)
+    const int inst = seg.inst;
     const Inst1D d = tab[inst];
-    const int N = d.n;
-    const int nf = d.bc == 1 ? N + 1 : N;
-    const int nfg = (nf + 3) >> 2;
-    const int nmax_pad = (N + 4) & ~3;
-    T *U = reinterpret_cast<T *>(smem_raw);
-    T *F = U + nmax_pad;
-    T *Us = F + nmax_pad + 4;
-    T *Rf = Us + nmax_pad;       // VARC: conductance per face
-    T *Sf = Rf + nmax_pad + 4;   // VARC: noise factor per face (walls: sqrt 2 included)
-    T *Wc = Sf + nmax_pad + 4;   // VARC: capacity factor per cell
-    const int tid = threadIdx.x;
-
     InstAcc *acc = st.acc + inst;
     if (acc->nonfinite) return;  // frozen after a non-finite sample
+
+    const int N = d.n;
+    const bool dir = d.bc == 1;
+    const int nf = dir ? N + 1 : N;
+    const int nfg = (nf + 3) >> 2, nfgp = (nfg + 3) & ~3;
+    const int glast = (N - 1) >> 2;  // block of the last cell
+    const int TS = 64 * seg.nw;
+    const int t = static_cast<int>(threadIdx.x) - 64 * seg.w0;
+    const int lw = wave - seg.w0;
+    const SegLds lay = seg_lds(N, nf, static_cast<int32_t>(sizeof(T)), MODE);
+    unsigned char *base = smem_raw + seg.lds;
+    T *xch = reinterpret_cast<T *>(base + lay.xch);
+    double *red = reinterpret_cast<double *>(base + lay.red);  // [3][16]
+    int *stop_flag = reinterpret_cast<int *>(base + lay.red + 3 * 16 * 8);
+    T *Rf = reinterpret_cast<T *>(base + lay.rf);  // VARC: conductance per face (periodic: [N] = [0])
+    T *Sf = reinterpret_cast<T *>(base + lay.sf);  // VARC: noise factor per face (walls: sqrt 2 included)
+    T *Wc = reinterpret_cast<T *>(base + lay.wc);  // VARC: capacity factor per cell
+    double *PD = reinterpret_cast<double *>(base + lay.pd);  // implicit: FP64 reduction array
 
     const T r = static_cast<T>(d.r);
     const T sg = static_cast<T>(d.sigma);
     const T sgw = static_cast<T>(d.sigma * 1.41421356237309504880);
-    const T uL = static_cast<T>(d.uL), uR = static_cast<T>(d.uR);
+    const T uL = static_cast<T>(d.uL), uR = static_cast<T>(d.uR), u0 = static_cast<T>(d.u0);
     const int eq = d.eq, noise = d.noise;
-    const T nu = static_cast<T>(d.nu);  // Burgers hyperbolic flux nu c_f (1 - c_f), 0 otherwise
-    const bool dir = d.bc == 1;
+    const T nu = static_cast<T>(eq == 2 ? d.nu : 0.0);  // Burgers hyperbolic flux nu c_f (1 - c_f)
     const PhiloxKey key = make_key(d.seed);
     T *gU = pool + d.off;
 
-    for (int i = tid; i < N; i += BLOCK) U[i] = gU[i];
+    T u[MAXG][4];
+#pragma unroll
+    for (int s = 0; s < MAXG; ++s)
+#pragma unroll
+        for (int l = 0; l < 4; ++l) {
+            const int i = 4 * (t + s * TS) + l;
+            u[s][l] = i < N ? gU[i] : T(0);
+        }
     if constexpr (VARC) {
         if (d.k_off >= 0) {
             const T *k = coef + d.k_off;
-            for (int f = tid; f < nf; f += BLOCK) {
+            for (int f = t; f < nf; f += TS) {
                 Rf[f] = k[f];
                 Sf[f] = k[nf + f];
             }
-            for (int i = tid; i < N; i += BLOCK) Wc[i] = k[2 * nf + i];
+            for (int i = t; i < N; i += TS) Wc[i] = k[2 * nf + i];
+            if (!dir && t == 0) {
+                Rf[N] = k[0];
+                Sf[N] = k[nf];
+            }
         } else {
-            for (int f = tid; f < nf; f += BLOCK) {
+            for (int f = t; f < nf; f += TS) {
                 Rf[f] = r;
                 Sf[f] = (dir && (f == 0 || f == N)) ? sgw : sg;
             }
-            for (int i = tid; i < N; i += BLOCK) Wc[i] = T(1);
+            for (int i = t; i < N; i += TS) Wc[i] = T(1);
+            if (!dir && t == 0) {
+                Rf[N] = r;
+                Sf[N] = sg;
+            }
         }
     }
 
-    // frozen-mode face amplitudes
+    // wall amplitudes (deterministic)
     uint32_t clamps = 0;
-    const T amp_u0 = face_amp<T>(eq, static_cast<T>(d.u0), clamps);
     const T amp_uL = face_amp<T>(eq, uL, clamps);
     const T amp_uR = face_amp<T>(eq, uR, clamps);
     clamps = 0;
@@ -188,7 +232,7 @@ __global__ void __launch_bounds__(BLOCK)
     for (int s = 0; s < MAXG; ++s)
 #pragma unroll
         for (int l = 0; l < 4; ++l) {
-            const int i = 4 * (tid + s * BLOCK) + l;
+            const int i = 4 * (t + s * TS) + l;
             s1[s][l] = (moments && i < N) ? st.s1[d.off + i] : 0.0;
             s2[s][l] = (moments && i < N) ? st.s2[d.off + i] : 0.0;
         }
@@ -196,47 +240,130 @@ __global__ void __launch_bounds__(BLOCK)
 
     // implicit schemes: weight of the state-dependent deterministic flux
     const bool impl = MODE == 2 && d.scheme >= 2;
-    const T ex = static_cast<T>(1.0 - d.theta);
+    const T ex = static_cast<T>(impl ? 1.0 - d.theta : 1.0);
+    const T rex = r * ex;
+    // face kinds: 0 heat with instantaneous noise; 1 deterministic or no
+    // noise (any equation); 2 Dean-Kawasaki; 3 Burgers (both instantaneous)
+    const int kind = noise != 0 ? 1 : (eq == 0 ? 0 : eq + 1);
 
-    auto flux_pass = [&](const T *V, const T (&z)[MAXG][4]) {
+    int ph = 0;  // exchange buffer of the next stage
+    // Flux divergence dv of the state V (registers) for every owned cell.
+    // first: the stage that also exchanges the face-0 numbers (rnz: the
+    // number of the face after each block, kept for the second PC stage).
+    auto stage = [&](const T (&V)[MAXG][4], const T (&z)[MAXG][4], T (&rnz)[MAXG], T (&dv)[MAXG][4],
+                     bool first) __attribute__((always_inline)) {
+        T *Uf = xch + (3 * ph) * nfgp, *Ul = Uf + nfgp, *Zf = Ul + nfgp;
+        ph ^= 1;
 #pragma unroll
         for (int s = 0; s < MAXG; ++s) {
-            const int g = tid + s * BLOCK;
-            if (g >= nfg) continue;
+            const int g = t + s * TS;
+            if (g < nfg) {
+                const int nc = N - 4 * g;
+                Uf[g] = V[s][0];
+                Ul[g] = last_of<T>(nc, V[s][0], V[s][1], V[s][2], V[s][3]);
+                if (first) Zf[g] = z[s][0];
+            }
+        }
+        __syncthreads();
+        auto faces = [&](auto kc) __attribute__((always_inline)) {
+            constexpr int K = decltype(kc)::value;
 #pragma unroll
-            for (int l = 0; l < 4; ++l) {
-                const int f = 4 * g + l;
-                if (f >= nf) continue;
-                T fl;
-                const T rf = VARC ? Rf[f] : r;
-                if (dir && f == 0) {
-                    fl = T(2) * rf * ((impl ? ex * V[0] : V[0]) - uL);
-                    if (eq == 2) fl -= nu * uL * (T(1) - uL);
-                    if (noise != 2) fl += (VARC ? Sf[f] : sgw) * amp_uL * z[s][l];
-                } else if (dir && f == N) {
-                    fl = T(2) * rf * (uR - (impl ? ex * V[N - 1] : V[N - 1]));
-                    if (eq == 2) fl -= nu * uR * (T(1) - uR);
-                    if (noise != 2) fl += (VARC ? Sf[f] : sgw) * amp_uR * z[s][l];
-                } else {
-                    const int a = f == 0 ? N - 1 : f - 1;
-                    const T vl = V[a], vr = V[f];
-                    fl = (impl ? ex * rf : rf) * (vr - vl);
-                    if (eq == 2) {
-                        const T cf = T(0.5) * (vl + vr);
-                        fl -= nu * cf * (T(1) - cf);
-                    }
-                    if (noise != 2) {
-                        T am;
-                        if (noise == 1)
-                            am = dir ? face_amp<T>(eq, uL + (uR - uL) * static_cast<T>(f) / static_cast<T>(N), clamps)
-                                     : amp_u0;
-                        else
-                            am = face_amp<T>(eq, T(0.5) * (vl + vr), clamps);
-                        fl += (VARC ? Sf[f] : sg) * am * z[s][l];
+            for (int s = 0; s < MAXG; ++s) {
+                const int g = t + s * TS;
+                const int nc = N - 4 * g;  // cells from this block's first on
+                if (nc <= 0) continue;     // no cells (a Dirichlet block holding only face N)
+                const bool inner = nc > 4;
+                const T lnb = Ul[g == 0 ? glast : g - 1];
+                const T left = (dir && g == 0) ? uL : lnb;
+                const T rnb = Uf[inner ? g + 1 : 0];
+                const T right = (dir && !inner) ? uR : rnb;
+                if (first) {
+                    const T zn = Zf[inner || (dir && nc == 4) ? g + 1 : 0];
+                    // Dirichlet, N not a multiple of 4: face N is this block's own
+                    rnz[s] = (dir && nc < 4) ? last_of<T>(nc + 1, z[s][0], z[s][1], z[s][2], z[s][3]) : zn;
+                }
+                T lo[5], hi[5], zz[5];
+                lo[0] = left;
+#pragma unroll
+                for (int l = 0; l < 4; ++l) {
+                    lo[l + 1] = V[s][l];
+                    hi[l] = V[s][l];
+                    zz[l] = z[s][l];
+                }
+                hi[4] = right;
+                zz[4] = rnz[s];
+                if (nc < 4) {  // the block of the last cell when 4 does not divide N
+#pragma unroll
+                    for (int l = 1; l < 4; ++l)
+                        if (l >= nc) {
+                            hi[l] = right;
+                            zz[l] = rnz[s];
+                        }
+                }
+                T F[5];
+#pragma unroll
+                for (int l = 0; l < 5; ++l) {
+                    const int f = 4 * g + l;
+                    const T rf = VARC ? Rf[f] * ex : rex;
+                    const T sf = VARC ? Sf[f] : sg;
+                    const T df = hi[l] - lo[l];
+                    const T cf = T(0.5) * (lo[l] + hi[l]);
+                    // clamps are counted on the faces this block owns
+                    const bool own = l < 4 && l < nc && !(dir && f == 0);
+                    if constexpr (K == 0) {
+                        F[l] = fma(sf * cf, zz[l], rf * df);
+                    } else if constexpr (K == 1) {
+                        T am = T(0);
+                        if (noise == 1) {
+                            const T v = dir ? uL + (uR - uL) * static_cast<T>(f) / static_cast<T>(N) : u0;
+                            uint32_t c = 0;
+                            am = face_amp<T>(eq, v, c);
+                            if (own) clamps += c;
+                        }
+                        F[l] = fma(sf * am, zz[l], fma(-nu * cf, T(1) - cf, rf * df));
+                    } else if constexpr (K == 2) {
+                        const bool neg = cf < T(0);
+                        if (own && neg) ++clamps;
+                        const T am = neg ? T(0) : sqrt(cf);
+                        F[l] = fma(sf * am, zz[l], rf * df);
+                    } else {
+                        const T q = cf * (T(1) - cf);
+                        const bool neg = q < T(0);
+                        if (own && neg) ++clamps;
+                        const T am = neg ? T(0) : sqrt(q);
+                        F[l] = fma(sf * am, zz[l], fma(-nu, q, rf * df));
                     }
                 }
-                F[f] = fl;
+                if (dir) {
+                    // walls: F_0 = 2 r (U_0 - U_L) + sqrt 2 sigma A(U_L) N_0, mirrored at
+                    // face N (the state term weighted by 1 - theta in implicit schemes)
+                    if (g == 0) {
+                        const T rw = VARC ? Rf[0] : r;
+                        const T sw = VARC ? Sf[0] : sgw;
+                        const T dwl = fma(-nu * uL, T(1) - uL, T(2) * rw * (ex * V[s][0] - uL));
+                        F[0] = noise != 2 ? fma(sw * amp_uL, zz[0], dwl) : dwl;
+                    }
+                    if (!inner) {
+                        const int m = nc < 4 ? nc : 4;
+                        const T vl = last_of<T>(m, V[s][0], V[s][1], V[s][2], V[s][3]);
+                        const T rw = VARC ? Rf[N] : r;
+                        const T sw = VARC ? Sf[N] : sgw;
+                        const T dwr = fma(-nu * uR, T(1) - uR, T(2) * rw * (uR - ex * vl));
+                        const T w = noise != 2 ? fma(sw * amp_uR, rnz[s], dwr) : dwr;
+#pragma unroll
+                        for (int l = 1; l < 5; ++l)
+                            if (l == m) F[l] = w;
+                    }
+                }
+#pragma unroll
+                for (int l = 0; l < 4; ++l) dv[s][l] = VARC ? Wc[4 * g + l] * (F[l + 1] - F[l]) : F[l + 1] - F[l];
             }
+        };
+        switch (kind) {
+        case 0: faces(std::integral_constant<int, 0>{}); break;
+        case 1: faces(std::integral_constant<int, 1>{}); break;
+        case 2: faces(std::integral_constant<int, 2>{}); break;
+        default: faces(std::integral_constant<int, 3>{}); break;
         }
     };
 
@@ -245,7 +372,7 @@ __global__ void __launch_bounds__(BLOCK)
         T z[MAXG][4];
 #pragma unroll
         for (int s = 0; s < MAXG; ++s) {
-            const int g = tid + s * BLOCK;
+            const int g = t + s * TS;
             if (noise != 2 && g < nfg) {
                 const Normals4<T> nz = block_normals<T>(static_cast<uint32_t>(g), static_cast<uint32_t>(n),
                                                         ctr_word2(n, 0u), d.realisation, key);
@@ -256,105 +383,118 @@ __global__ void __launch_bounds__(BLOCK)
                 for (int l = 0; l < 4; ++l) z[s][l] = T(0);
             }
         }
-        flux_pass(U, z);
-        __syncthreads();
+        T rnz[MAXG], dv[MAXG][4];
+#pragma unroll
+        for (int s = 0; s < MAXG; ++s) rnz[s] = T(0);
+        stage(u, z, rnz, dv, true);
         if (MODE == 2 && impl) {
-            // right-hand side in FP64 registers, then M U' = rhs by parallel
-            // cyclic reduction in place on an FP64 array over F and Us
-            constexpr int MAXC = 4 * MAXG;  // cells per thread (N <= 4 BLOCK MAXG)
-            double x[MAXC];
+            // right-hand side in FP64, then M U' = rhs by parallel cyclic
+            // reduction in the FP64 LDS array (same cells per thread)
+            double x[MAXG][4];
 #pragma unroll
-            for (int j = 0; j < MAXC; ++j) {
-                const int i = tid + j * BLOCK;
-                if (i < N) {
-                    const int hi = (!dir && i + 1 == N) ? 0 : i + 1;
-                    x[j] = static_cast<double>(U[i] + (VARC ? Wc[i] * (F[hi] - F[i]) : (F[hi] - F[i])));
+            for (int s = 0; s < MAXG; ++s)
+#pragma unroll
+                for (int l = 0; l < 4; ++l) {
+                    const int i = 4 * (t + s * TS) + l;
+                    x[s][l] = static_cast<double>(u[s][l] + dv[s][l]);
+                    if (i < N) PD[i] = x[s][l];
                 }
-            }
-            __syncthreads();
-            double *D = reinterpret_cast<double *>(F);
-#pragma unroll
-            for (int j = 0; j < MAXC; ++j)
-                if (tid + j * BLOCK < N) D[tid + j * BLOCK] = x[j];
-            __syncthreads();
             const double *P = pcr + d.p_off;
             const int L = d.pcr_levels;
             // factors of the current level in registers; the next level's are
             // loaded before this level's barriers so their latency overlaps
-            double f1[MAXC], f2[MAXC];
-            auto load_level = [&](int l, double (&a)[MAXC], double (&b)[MAXC]) {
-                const double *k1 = P + static_cast<int64_t>(l) * N, *k2 = P + static_cast<int64_t>(L + l) * N;
+            double f1[MAXG][4], f2[MAXG][4];
+            auto load_level = [&](int lv, double (&a)[MAXG][4], double (&b)[MAXG][4]) __attribute__((always_inline)) {
+                const double *k1 = P + static_cast<int64_t>(lv) * N, *k2 = P + static_cast<int64_t>(L + lv) * N;
 #pragma unroll
-                for (int j = 0; j < MAXC; ++j) {
-                    const int i = tid + j * BLOCK;
-                    a[j] = i < N ? k1[i] : 0.0;
-                    b[j] = i < N ? k2[i] : 0.0;
-                }
+                for (int s = 0; s < MAXG; ++s)
+#pragma unroll
+                    for (int l = 0; l < 4; ++l) {
+                        const int i = 4 * (t + s * TS) + l;
+                        a[s][l] = i < N ? k1[i] : 0.0;
+                        b[s][l] = i < N ? k2[i] : 0.0;
+                    }
             };
             if (L > 0) load_level(0, f1, f2);
-            for (int l = 0; l < L; ++l) {
-                const int s = 1 << l;
+            __syncthreads();
+            for (int lv = 0; lv < L; ++lv) {
+                const int sh = 1 << lv;
 #pragma unroll
-                for (int j = 0; j < MAXC; ++j) {
-                    const int i = tid + j * BLOCK;
-                    if (i < N) {
-                        double v = D[i];
-                        if (i >= s) v -= f1[j] * D[i - s];
-                        if (i + s < N) v -= f2[j] * D[i + s];
-                        x[j] = v;
+                for (int s = 0; s < MAXG; ++s)
+#pragma unroll
+                    for (int l = 0; l < 4; ++l) {
+                        const int i = 4 * (t + s * TS) + l;
+                        if (i < N) {
+                            double v = PD[i];
+                            if (i >= sh) v -= f1[s][l] * PD[i - sh];
+                            if (i + sh < N) v -= f2[s][l] * PD[i + sh];
+                            x[s][l] = v;
+                        }
                     }
-                }
-                if (l + 1 < L) load_level(l + 1, f1, f2);
+                if (lv + 1 < L) load_level(lv + 1, f1, f2);
                 __syncthreads();
 #pragma unroll
-                for (int j = 0; j < MAXC; ++j)
-                    if (tid + j * BLOCK < N) D[tid + j * BLOCK] = x[j];
+                for (int s = 0; s < MAXG; ++s)
+#pragma unroll
+                    for (int l = 0; l < 4; ++l) {
+                        const int i = 4 * (t + s * TS) + l;
+                        if (i < N) PD[i] = x[s][l];
+                    }
                 __syncthreads();
             }
             const double *invb = P + static_cast<int64_t>(2 * L) * N;
 #pragma unroll
-            for (int j = 0; j < MAXC; ++j)
-                if (tid + j * BLOCK < N) x[j] *= invb[tid + j * BLOCK];
+            for (int s = 0; s < MAXG; ++s)
+#pragma unroll
+                for (int l = 0; l < 4; ++l) {
+                    const int i = 4 * (t + s * TS) + l;
+                    if (i < N) x[s][l] *= invb[i];
+                }
             if (!dir) {
                 // cyclic part: x = y - f z, f = (y_0 + q y_(N-1)) / (1 + z_0 + q z_(N-1))
 #pragma unroll
-                for (int j = 0; j < MAXC; ++j)
-                    if (tid + j * BLOCK < N) D[tid + j * BLOCK] = x[j];
+                for (int s = 0; s < MAXG; ++s)
+#pragma unroll
+                    for (int l = 0; l < 4; ++l) {
+                        const int i = 4 * (t + s * TS) + l;
+                        if (i < N) PD[i] = x[s][l];
+                    }
                 __syncthreads();
                 const double *zv = invb + N;
-                const double f = (D[0] + zv[N] * D[N - 1]) * zv[N + 1];
+                const double f = (PD[0] + zv[N] * PD[N - 1]) * zv[N + 1];
 #pragma unroll
-                for (int j = 0; j < MAXC; ++j)
-                    if (tid + j * BLOCK < N) x[j] -= f * zv[tid + j * BLOCK];
+                for (int s = 0; s < MAXG; ++s)
+#pragma unroll
+                    for (int l = 0; l < 4; ++l) {
+                        const int i = 4 * (t + s * TS) + l;
+                        if (i < N) x[s][l] -= f * zv[i];
+                    }
             }
 #pragma unroll
-            for (int j = 0; j < MAXC; ++j)
-                if (tid + j * BLOCK < N) U[tid + j * BLOCK] = static_cast<T>(x[j]);
-            __syncthreads();
+            for (int s = 0; s < MAXG; ++s)
+#pragma unroll
+                for (int l = 0; l < 4; ++l) u[s][l] = static_cast<T>(x[s][l]);
         } else if (d.scheme == 0) {
-            for (int i = tid; i < N; i += BLOCK) {
-                const int hi = (!dir && i + 1 == N) ? 0 : i + 1;
-                U[i] = U[i] + (VARC ? Wc[i] * (F[hi] - F[i]) : (F[hi] - F[i]));
-            }
-            __syncthreads();
+#pragma unroll
+            for (int s = 0; s < MAXG; ++s)
+#pragma unroll
+                for (int l = 0; l < 4; ++l) u[s][l] = u[s][l] + dv[s][l];
         } else {
-            for (int i = tid; i < N; i += BLOCK) {
-                const int hi = (!dir && i + 1 == N) ? 0 : i + 1;
-                Us[i] = U[i] + (VARC ? Wc[i] * (F[hi] - F[i]) : (F[hi] - F[i]));
-            }
-            __syncthreads();
-            flux_pass(Us, z);
-            __syncthreads();
-            for (int i = tid; i < N; i += BLOCK) {
-                const int hi = (!dir && i + 1 == N) ? 0 : i + 1;
-                U[i] = T(0.5) * ((U[i] + Us[i]) + (VARC ? Wc[i] * (F[hi] - F[i]) : (F[hi] - F[i])));
-            }
-            __syncthreads();
+            T us[MAXG][4];
+#pragma unroll
+            for (int s = 0; s < MAXG; ++s)
+#pragma unroll
+                for (int l = 0; l < 4; ++l) us[s][l] = u[s][l] + dv[s][l];
+            stage(us, z, rnz, dv, false);
+#pragma unroll
+            for (int s = 0; s < MAXG; ++s)
+#pragma unroll
+                for (int l = 0; l < 4; ++l) u[s][l] = T(0.5) * ((u[s][l] + us[s][l]) + dv[s][l]);
         }
 
         if (STATS) {
-            const int64_t t = step0 + k + 1;
-            if (t > burn_in && every > 0 && t % every == 0) {
+            const int64_t tt = step0 + k + 1;
+            if (tt > burn_in && every > 0 && tt % every == 0) {
                 double a = 0.0, b = 0.0;
                 int bad = 0;
                 const int row = static_cast<int>(nsamp % kCorrBlock);
@@ -364,9 +504,9 @@ __global__ void __launch_bounds__(BLOCK)
                 for (int s = 0; s < MAXG; ++s)
 #pragma unroll
                     for (int l = 0; l < 4; ++l) {
-                        const int i = 4 * (tid + s * BLOCK) + l;
+                        const int i = 4 * (t + s * TS) + l;
                         if (i < N) {
-                            const T v = U[i];
+                            const T v = u[s][l];
                             if (!isfinite(v)) bad = 1;
                             const double ref = dir ? d.uL + (d.uR - d.uL) * (i + 0.5) / N : d.u0;
                             const double del = static_cast<double>(v) - ref;
@@ -378,63 +518,75 @@ __global__ void __launch_bounds__(BLOCK)
                             if (tcorr) Hrow[i] = static_cast<T>(del);
                         }
                     }
-                // workgroup reduction (fixed order)
+                // reduction over the instance's waves (fixed order)
                 for (int off = 32; off > 0; off >>= 1) {
                     a += __shfl_xor(a, off, 64);
                     b += __shfl_xor(b, off, 64);
                     bad |= __shfl_xor(bad, off, 64);
                 }
-                if ((tid & 63) == 0) {
-                    red[0][tid >> 6] = a;
-                    red[1][tid >> 6] = b;
-                    red[2][tid >> 6] = static_cast<double>(bad);
+                if ((t & 63) == 0) {
+                    red[lw] = a;
+                    red[16 + lw] = b;
+                    red[32 + lw] = static_cast<double>(bad);
                 }
                 __syncthreads();
-                if (tid == 0) {
+                if (t == 0) {
                     double ta = 0.0, tb = 0.0, tbad = 0.0;
-                    for (int w = 0; w < BLOCK / 64; ++w) {
-                        ta += red[0][w];
-                        tb += red[1][w];
-                        tbad += red[2][w];
+                    for (int w = 0; w < seg.nw; ++w) {
+                        ta += red[w];
+                        tb += red[16 + w];
+                        tbad += red[32 + w];
                     }
                     if (tbad != 0.0) {
                         acc->nonfinite = 1;
-                        stop_flag = 1;
+                        *stop_flag = 1;
                     } else {
                         ta /= N;
                         tb /= N;
                         acc->sp_mean += ta;
                         acc->sp_sq += tb;
                         acc->sp_var += tb - ta * ta;
-                        stop_flag = 0;
+                        *stop_flag = 0;
                     }
                 }
                 __syncthreads();
-                if (stop_flag) {
+                if (*stop_flag) {
                     // a non-finite sample: keep the statistics as they were
                     // before it and freeze the state
-                    for (int i = tid; i < N; i += BLOCK) gU[i] = U[i];
-                    if (tid == 0) acc->n_samples = nsamp;
+#pragma unroll
+                    for (int s = 0; s < MAXG; ++s)
+#pragma unroll
+                        for (int l = 0; l < 4; ++l) {
+                            const int i = 4 * (t + s * TS) + l;
+                            if (i < N) gU[i] = u[s][l];
+                        }
+                    if (t == 0) acc->n_samples = nsamp;
                     return;
                 }
                 ++nsamp;
                 if (corr && row == kCorrBlock - 1) {
                     __threadfence_block();
                     __syncthreads();
-                    xtx_block<T>(X, st.c + d.c_off, N);
+                    xtx_block<T>(X, st.c + d.c_off, N, lw, seg.nw);
                     __syncthreads();
                 }
             }
         }
     }
 
-    for (int i = tid; i < N; i += BLOCK) gU[i] = U[i];
+#pragma unroll
+    for (int s = 0; s < MAXG; ++s)
+#pragma unroll
+        for (int l = 0; l < 4; ++l) {
+            const int i = 4 * (t + s * TS) + l;
+            if (i < N) gU[i] = u[s][l];
+        }
     if (moments) {
 #pragma unroll
         for (int s = 0; s < MAXG; ++s)
 #pragma unroll
             for (int l = 0; l < 4; ++l) {
-                const int i = 4 * (tid + s * BLOCK) + l;
+                const int i = 4 * (t + s * TS) + l;
                 if (i < N) {
                     st.s1[d.off + i] = s1[s][l];
                     st.s2[d.off + i] = s2[s][l];
@@ -444,7 +596,7 @@ __global__ void __launch_bounds__(BLOCK)
     if (STATS) {
         if (clamps) atomicAdd(reinterpret_cast<unsigned long long *>(&acc->clamp_count),
                               static_cast<unsigned long long>(clamps));
-        if (tid == 0) acc->n_samples = nsamp;
+        if (t == 0) acc->n_samples = nsamp;
     }
 }
 
@@ -633,7 +785,7 @@ struct Step1DLaunch {
     size_t smem;
     hipStream_t s;
     const Inst1D *tab;
-    const int32_t *order;
+    const Seg1D *segs;
     void *pool;
     const void *coef;
     const double *pcr;
@@ -649,7 +801,7 @@ template <typename T, int BLOCK, int MAXG, bool STATS, int MODE>
 static hipError_t step1d_k(const Step1DLaunch &a)
 {
     hipLaunchKernelGGL((k_step1d<T, BLOCK, MAXG, STATS, MODE>), dim3(a.n_blocks), dim3(BLOCK), a.smem, a.s, a.tab,
-                       a.order, static_cast<T *>(a.pool), static_cast<const T *>(a.coef), a.pcr, a.step0, a.nsteps,
+                       a.segs, static_cast<T *>(a.pool), static_cast<const T *>(a.coef), a.pcr, a.step0, a.nsteps,
                        a.burn_in, a.every, a.mask, a.st);
     return hipGetLastError();
 }
@@ -671,36 +823,27 @@ static hipError_t step1d_t(bool stats, int mode, const Step1DLaunch &a)
     return stats ? step1d_m<T, BLOCK, MAXG, true>(mode, a) : step1d_m<T, BLOCK, MAXG, false>(mode, a);
 }
 
-template <typename T, int BLOCK>
-static hipError_t step1d_b(int maxg, bool stats, int mode, const Step1DLaunch &a)
-{
-    switch (maxg) {
-    case 1: return step1d_t<T, BLOCK, 1>(stats, mode, a);
-    case 2: return step1d_t<T, BLOCK, 2>(stats, mode, a);
-    case 4: return step1d_t<T, BLOCK, 4>(stats, mode, a);
-    case 8: return step1d_t<T, BLOCK, 8>(stats, mode, a);
-    default: return hipErrorInvalidValue;
-    }
-}
-
+// Launch shapes (threads per workgroup, Philox blocks per thread) the
+// planner chooses: 64 x {1, 2}, 256 x {1, 2}, 512 x {1, 2, 4}.
 template <typename T>
 static hipError_t step1d_p(int block, int maxg, bool stats, int mode, const Step1DLaunch &a)
 {
-    switch (block) {
-    case 64: return step1d_b<T, 64>(maxg, stats, mode, a);
-    case 256: return step1d_b<T, 256>(maxg, stats, mode, a);
-    case 1024:  // one Philox block per thread only (register budget of 16 waves)
-        return maxg == 1 ? step1d_t<T, 1024, 1>(stats, mode, a) : hipErrorInvalidValue;
-    default: return hipErrorInvalidValue;
-    }
+    if (block == 64 && maxg == 1) return step1d_t<T, 64, 1>(stats, mode, a);
+    if (block == 64 && maxg == 2) return step1d_t<T, 64, 2>(stats, mode, a);
+    if (block == 256 && maxg == 1) return step1d_t<T, 256, 1>(stats, mode, a);
+    if (block == 256 && maxg == 2) return step1d_t<T, 256, 2>(stats, mode, a);
+    if (block == 512 && maxg == 1) return step1d_t<T, 512, 1>(stats, mode, a);
+    if (block == 512 && maxg == 2) return step1d_t<T, 512, 2>(stats, mode, a);
+    if (block == 512 && maxg == 4) return step1d_t<T, 512, 4>(stats, mode, a);
+    return hipErrorInvalidValue;
 }
 
 hipError_t launch_step1d(int prec, int block, int maxg, bool stats, int mode, int n_blocks, size_t smem,
-                         hipStream_t s, const Inst1D *tab, const int32_t *order, void *pool, const void *coef,
+                         hipStream_t s, const Inst1D *tab, const Seg1D *segs, void *pool, const void *coef,
                          const double *pcr, int64_t step0, int32_t nsteps, int64_t burn_in, int32_t every,
                          uint32_t mask, Stats1D st)
 {
-    const Step1DLaunch a{n_blocks, smem, s, tab, order, pool, coef, pcr, step0, nsteps, burn_in, every, mask, st};
+    const Step1DLaunch a{n_blocks, smem, s, tab, segs, pool, coef, pcr, step0, nsteps, burn_in, every, mask, st};
     if (prec == 0) return step1d_p<float>(block, maxg, stats, mode, a);
     return step1d_p<double>(block, maxg, stats, mode, a);
 }

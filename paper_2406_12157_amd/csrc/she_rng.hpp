@@ -64,9 +64,12 @@ struct Normals4 {
     T z[4];
 };
 
+// FP32: the bits of 1 + m 2^-23 (m = w >> 9) come from one funnel shift of
+// (0x7F, w) by 9; subtracting 1 - 2^-24 is exact (the operands are within a
+// factor of two), leaving (m + 1/2) 2^-23.
 __device__ __forceinline__ float unit_open_f32(uint32_t w)
 {
-    return __builtin_fmaf(static_cast<float>(w >> 9), 0x1p-23f, 0x1p-24f);
+    return __uint_as_float(__builtin_amdgcn_alignbit(0x7Fu, w, 9)) - 0x1.fffffep-1f;
 }
 
 __device__ __forceinline__ double unit_open_f64(uint32_t w)

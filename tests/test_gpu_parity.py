@@ -118,13 +118,26 @@ def test_1d_ragged_batch_and_independence(she):
 
 
 def test_1d_launch_shape_invariance(she):
+    # 64 threads: one instance per workgroup, up to two Philox blocks per
+    # thread; 256 and 512: instances packed several to a workgroup
     insts = [inst1d(*c, realisation=q) for q, c in enumerate(CASES_1D[:6])]
     _, a, _ = run_both(she, insts, 2000, 0, block_threads=64)
     _, b, _ = run_both(she, insts, 2000, 0, block_threads=256)
-    _, c, _ = run_both(she, insts, 2000, 0, block_threads=1024)
+    _, c, _ = run_both(she, insts, 2000, 0, block_threads=512)
     for x, y, z in zip(a, b, c):
         np.testing.assert_array_equal(x, y)
         np.testing.assert_array_equal(x, z)
+
+
+@pytest.mark.parametrize("scheme", [W.EM, W.HEUN])
+def test_1d_large_instance_parity(she, scheme):
+    # N = 5001: 1251 Philox blocks, four per thread of a 512-thread workgroup,
+    # and a last block holding one cell; a small instance shares the launch
+    insts = [inst1d((5001,), W.DIRICHLET, scheme, W.HEAT, 0, realisation=0),
+             inst1d((70,), W.PERIODIC, scheme, W.HEAT, 0, realisation=1)]
+    _, got, want = run_both(she, insts, 300, 0)
+    for q in range(len(insts)):
+        assert max_rel(got[q], want[q]) <= 1e-5, q
 
 
 # ---------------------------------------------------------------- 2D / 3D
