@@ -72,8 +72,8 @@ struct Seg1D {
 
 // LDS region of one 1D instance (byte offsets, 16-byte aligned parts):
 // exchange arrays [2 buffers][first value, last value, face-0 number][nfg
-// rounded up to 4] of the state type; the statistics reduction (3 x 16
-// doubles and a flag); with material arrays (mode >= 1) r_f and s_f [nf + 4]
+// rounded up to 4] of the state type; the wave sums of a sample (3 x 16
+// doubles); with material arrays (mode >= 1) r_f and s_f [nf + 4]
 // and w_i [n + 4] of the state type; for implicit schemes (mode 2) an FP64
 // array [n] for the reduction.
 struct SegLds {
@@ -90,7 +90,7 @@ __host__ __device__ inline SegLds seg_lds(int32_t n, int32_t nf, int32_t es, int
     l.xch = o;
     o = lds_align16(o + 6 * nfgp * es);
     l.red = o;
-    o = lds_align16(o + 3 * 16 * 8 + 4);
+    o = lds_align16(o + 3 * 16 * 8);
     l.rf = l.sf = l.wc = l.pd = -1;
     if (mode >= 1) {
         l.rf = o;

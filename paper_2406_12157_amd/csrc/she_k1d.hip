@@ -44,6 +44,7 @@
 
 #include "she_internal.hpp"
 #include "she_rng.hpp"
+#include "she_wave.hpp"
 
 namespace she {
 
@@ -107,11 +108,19 @@ __device__ void xtx_block(const T *__restrict__ X, double *__restrict__ Cm, int 
         const int tj = ti + rem;
         const int i = 16 * ti + (lane & 15), j = 16 * tj + (lane & 15);
         acc_t acc = {0, 0, 0, 0};
-        for (int k0 = 0; k0 < kCorrBlock; k0 += 4) {
-            const int k = k0 + (lane >> 4);
-            const T a = i < N ? X[(int64_t)k * N + i] : T(0);
-            const T b = j < N ? X[(int64_t)k * N + j] : T(0);
-            acc = mfma16x16x4(a, b, acc);
+        // eight K-steps of operands are loaded before their eight products, so
+        // the loads overlap instead of each product waiting for its own
+        constexpr int kB = 8;
+        for (int k0 = 0; k0 < kCorrBlock; k0 += 4 * kB) {
+            T a[kB], b[kB];
+#pragma unroll
+            for (int q = 0; q < kB; ++q) {
+                const int k = k0 + 4 * q + (lane >> 4);
+                a[q] = i < N ? X[(int64_t)k * N + i] : T(0);
+                b[q] = j < N ? X[(int64_t)k * N + j] : T(0);
+            }
+#pragma unroll
+            for (int q = 0; q < kB; ++q) acc = mfma16x16x4(a[q], b[q], acc);
         }
         const int col = 16 * tj + (lane & 15);
 #pragma unroll
@@ -168,8 +177,7 @@ __global__ void __launch_bounds__(BLOCK)
     const SegLds lay = seg_lds(N, nf, static_cast<int32_t>(sizeof(T)), MODE);
     unsigned char *base = smem_raw + seg.lds;
     T *xch = reinterpret_cast<T *>(base + lay.xch);
-    double *red = reinterpret_cast<double *>(base + lay.red);  // [3][16]
-    int *stop_flag = reinterpret_cast<int *>(base + lay.red + 3 * 16 * 8);
+    double *red = reinterpret_cast<double *>(base + lay.red);  // [3][16] wave sums of a sample
     T *Rf = reinterpret_cast<T *>(base + lay.rf);  // VARC: conductance per face (periodic: [N] = [0])
     T *Sf = reinterpret_cast<T *>(base + lay.sf);  // VARC: noise factor per face (walls: sqrt 2 included)
     T *Wc = reinterpret_cast<T *>(base + lay.wc);  // VARC: capacity factor per cell
@@ -223,18 +231,36 @@ __global__ void __launch_bounds__(BLOCK)
     const T amp_uR = face_amp<T>(eq, uR, clamps);
     clamps = 0;
 
+    // Per-cell sums of dU and dU^2: in registers for the launch with one
+    // Philox block per thread; with more, updated in memory on each sample
+    // (registers for the stage matter more there: they set how many
+    // workgroups of a packed batch are resident at once).
+    constexpr bool kRegSums = MAXG == 1;
     double s1[MAXG][4], s2[MAXG][4];
     const bool moments = STATS && (mask & 1u) && st.s1 != nullptr;
     const bool corr = STATS && (mask & 2u) && d.x_off >= 0;
     const bool tcorr = STATS && (mask & 16u) && d.h_off >= 0;
     int64_t nsamp = STATS ? acc->n_samples : 0;
+    // spatial sums of the instance, carried in registers over the launch
+    double sp_mean = STATS ? acc->sp_mean : 0.0, sp_sq = STATS ? acc->sp_sq : 0.0,
+           sp_var = STATS ? acc->sp_var : 0.0;
+    // first sample of the launch: the smallest t > burn_in, t > step0 with
+    // t % every == 0 (t = steps completed); later ones follow every `every`
+    int64_t t_next = -1;
+    if (STATS && every > 0) {
+        const int64_t a0 = (step0 > burn_in ? step0 : burn_in) + 1;
+        const int64_t rm = a0 % every;
+        t_next = rm == 0 ? a0 : a0 + (every - rm);
+    }
+    // reference profile of the deviations: u0, or the linear wall profile
+    const double ref0 = dir ? d.uL : d.u0, ref_slope = dir ? (d.uR - d.uL) / N : 0.0;
 #pragma unroll
     for (int s = 0; s < MAXG; ++s)
 #pragma unroll
         for (int l = 0; l < 4; ++l) {
             const int i = 4 * (t + s * TS) + l;
-            s1[s][l] = (moments && i < N) ? st.s1[d.off + i] : 0.0;
-            s2[s][l] = (moments && i < N) ? st.s2[d.off + i] : 0.0;
+            s1[s][l] = (kRegSums && moments && i < N) ? st.s1[d.off + i] : 0.0;
+            s2[s][l] = (kRegSums && moments && i < N) ? st.s2[d.off + i] : 0.0;
         }
     __syncthreads();
 
@@ -493,10 +519,11 @@ __global__ void __launch_bounds__(BLOCK)
         }
 
         if (STATS) {
-            const int64_t tt = step0 + k + 1;
-            if (tt > burn_in && every > 0 && tt % every == 0) {
+            if (step0 + k + 1 == t_next) {
+                t_next += every;
                 double a = 0.0, b = 0.0;
                 int bad = 0;
+                double del[MAXG][4];
                 const int row = static_cast<int>(nsamp % kCorrBlock);
                 T *X = corr ? static_cast<T *>(st.xblk) + d.x_off : nullptr;
                 T *Hrow = tcorr ? static_cast<T *>(st.hist) + d.h_off + (nsamp % st.hist_rows) * N : nullptr;
@@ -505,52 +532,44 @@ __global__ void __launch_bounds__(BLOCK)
 #pragma unroll
                     for (int l = 0; l < 4; ++l) {
                         const int i = 4 * (t + s * TS) + l;
+                        del[s][l] = 0.0;
                         if (i < N) {
                             const T v = u[s][l];
                             if (!isfinite(v)) bad = 1;
-                            const double ref = dir ? d.uL + (d.uR - d.uL) * (i + 0.5) / N : d.u0;
-                            const double del = static_cast<double>(v) - ref;
-                            s1[s][l] += del;
-                            s2[s][l] += del * del;
-                            a += del;
-                            b += del * del;
-                            if (corr) X[(int64_t)row * N + i] = static_cast<T>(del);
-                            if (tcorr) Hrow[i] = static_cast<T>(del);
+                            const double dl = static_cast<double>(v) - fma(ref_slope, i + 0.5, ref0);
+                            del[s][l] = dl;
+                            if (kRegSums) {
+                                s1[s][l] += dl;
+                                s2[s][l] += dl * dl;
+                            }
+                            a += dl;
+                            b += dl * dl;
+                            if (corr) X[(int64_t)row * N + i] = static_cast<T>(dl);
+                            if (tcorr) Hrow[i] = static_cast<T>(dl);
                         }
                     }
-                // reduction over the instance's waves (fixed order)
-                for (int off = 32; off > 0; off >>= 1) {
-                    a += __shfl_xor(a, off, 64);
-                    b += __shfl_xor(b, off, 64);
-                    bad |= __shfl_xor(bad, off, 64);
-                }
-                if ((t & 63) == 0) {
-                    red[lw] = a;
-                    red[16 + lw] = b;
-                    red[32 + lw] = static_cast<double>(bad);
-                }
-                __syncthreads();
-                if (t == 0) {
-                    double ta = 0.0, tb = 0.0, tbad = 0.0;
+                // sums over the instance (fixed order): DPP within each wave,
+                // then (several waves) the wave sums through LDS, added by every
+                // thread in the same order
+                a = wave_total(a);
+                b = wave_total(b);
+                bad = __any(bad) ? 1 : 0;
+                if (seg.nw > 1) {
+                    if ((t & 63) == 0) {
+                        red[lw] = a;
+                        red[16 + lw] = b;
+                        red[32 + lw] = static_cast<double>(bad);
+                    }
+                    __syncthreads();
+                    a = b = 0.0;
+                    bad = 0;
                     for (int w = 0; w < seg.nw; ++w) {
-                        ta += red[w];
-                        tb += red[16 + w];
-                        tbad += red[32 + w];
-                    }
-                    if (tbad != 0.0) {
-                        acc->nonfinite = 1;
-                        *stop_flag = 1;
-                    } else {
-                        ta /= N;
-                        tb /= N;
-                        acc->sp_mean += ta;
-                        acc->sp_sq += tb;
-                        acc->sp_var += tb - ta * ta;
-                        *stop_flag = 0;
+                        a += red[w];
+                        b += red[16 + w];
+                        bad |= red[32 + w] != 0.0;
                     }
                 }
-                __syncthreads();
-                if (*stop_flag) {
+                if (bad) {
                     // a non-finite sample: keep the statistics as they were
                     // before it and freeze the state
 #pragma unroll
@@ -560,8 +579,31 @@ __global__ void __launch_bounds__(BLOCK)
                             const int i = 4 * (t + s * TS) + l;
                             if (i < N) gU[i] = u[s][l];
                         }
-                    if (t == 0) acc->n_samples = nsamp;
+                    if (t == 0) {
+                        acc->nonfinite = 1;
+                        acc->n_samples = nsamp;
+                        acc->sp_mean = sp_mean;
+                        acc->sp_sq = sp_sq;
+                        acc->sp_var = sp_var;
+                    }
                     return;
+                }
+                a /= N;
+                b /= N;
+                sp_mean += a;
+                sp_sq += b;
+                sp_var += b - a * a;
+                if (!kRegSums && moments) {
+#pragma unroll
+                    for (int s = 0; s < MAXG; ++s)
+#pragma unroll
+                        for (int l = 0; l < 4; ++l) {
+                            const int i = 4 * (t + s * TS) + l;
+                            if (i < N) {
+                                st.s1[d.off + i] += del[s][l];
+                                st.s2[d.off + i] += del[s][l] * del[s][l];
+                            }
+                        }
                 }
                 ++nsamp;
                 if (corr && row == kCorrBlock - 1) {
@@ -581,7 +623,7 @@ __global__ void __launch_bounds__(BLOCK)
             const int i = 4 * (t + s * TS) + l;
             if (i < N) gU[i] = u[s][l];
         }
-    if (moments) {
+    if (kRegSums && moments) {
 #pragma unroll
         for (int s = 0; s < MAXG; ++s)
 #pragma unroll
@@ -596,7 +638,12 @@ __global__ void __launch_bounds__(BLOCK)
     if (STATS) {
         if (clamps) atomicAdd(reinterpret_cast<unsigned long long *>(&acc->clamp_count),
                               static_cast<unsigned long long>(clamps));
-        if (t == 0) acc->n_samples = nsamp;
+        if (t == 0) {
+            acc->n_samples = nsamp;
+            acc->sp_mean = sp_mean;
+            acc->sp_sq = sp_sq;
+            acc->sp_var = sp_var;
+        }
     }
 }
 
