@@ -92,10 +92,12 @@ enum {
 
 /* she_config.tuning_flags: launch-order choices (results are identical) */
 enum {
-    SHE_TUNE_XCD_ORDER = 1        /* 2D/3D: give each XCD a contiguous range of
+    SHE_TUNE_XCD_ORDER = 1,       /* 2D/3D: give each XCD a contiguous range of
                                      workgroups (neighbouring chunks share an
                                      L2) instead of the plain order; measured
                                      no faster on MI355X, so off by default   */
+    SHE_TUNE_SEARCH = 2           /* she_create runs she_tune first and uses
+                                     its choice (not with an arena)          */
 };
 
 /* One instance (realisation) of the scheme.  Dirichlet walls only in 1D. */
@@ -154,9 +156,11 @@ typedef struct {
     int32_t sample_every;         /* >= 1                                      */
     uint32_t stats_mask;          /* SHE_STAT_* bits                           */
     int32_t block_threads;        /* tuning: 1D threads per workgroup: 0 (auto),
-                                     64, 256 or 512; an instance takes whole
-                                     waves of a workgroup, small instances
-                                     share one                              */
+                                     64, 256 or 512, or 1024 for an FP32
+                                     batch of FE/PC instances with uniform
+                                     material and stats_mask 0; an instance
+                                     takes whole waves of a workgroup, small
+                                     instances share one                    */
     int32_t rows_per_block;       /* tuning: 2D/3D march length (0 auto)      */
     int32_t rows_per_group;       /* tuning: 3D rows per workgroup (0 auto)   */
     int32_t tuning_flags;         /* SHE_TUNE_* bits (0 = defaults)           */
@@ -206,6 +210,18 @@ she_status she_create(const she_config *cfg, she_handle **out);
 
 /* Bytes of device memory she_create needs for cfg (for a caller arena). */
 she_status she_arena_bytes(const she_config *cfg, size_t *bytes);
+
+/* Autotuner: time the launch shapes valid for cfg and write cfg with the
+ * fastest into *tuned (block_threads for 1D; rows_per_block for 2D;
+ * rows_per_block x rows_per_group for 3D).  Each candidate is a trial handle
+ * (she_create without cfg->arena: it allocates), warmed up and then timed
+ * over `steps` steps of she_step with events on cfg->stream (steps <= 0:
+ * 2000 in 1D, 20 in 2D/3D); shapes the batch rejects are skipped.  Results
+ * are identical for every shape; only the time differs.  A choice is cached
+ * for the process, keyed by precision, stats_mask and each instance's sizes,
+ * boundary, scheme, equation, noise mode and material; a cached key returns
+ * at once.  Synchronises cfg->stream.  SHE_EUNSUPPORTED if no shape runs. */
+she_status she_tune(const she_config *cfg, int32_t steps, she_config *tuned);
 
 /* Advance every instance by nsteps steps without sampling.  Async. */
 she_status she_step(she_handle *h, int64_t nsteps);

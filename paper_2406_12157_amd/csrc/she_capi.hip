@@ -8,6 +8,7 @@
 #include <algorithm>
 #include <cmath>
 #include <map>
+#include <mutex>
 #include <cstdio>
 #include <cstring>
 #include <numeric>
@@ -281,7 +282,11 @@ she_status validate(const she_config *cfg, she_handle *h)
         return fail(nullptr, SHE_EINVAL, "precision must be SHE_F32 or SHE_F64");
     if (cfg->sample_every < 1) return fail(nullptr, SHE_EINVAL, "sample_every must be >= 1");
     if (cfg->burn_in < 0) return fail(nullptr, SHE_EINVAL, "burn_in must be >= 0");
-    if (cfg->tuning_flags & ~SHE_TUNE_XCD_ORDER) return fail(nullptr, SHE_EINVAL, "unknown tuning_flags bits");
+    if (cfg->tuning_flags & ~(SHE_TUNE_XCD_ORDER | SHE_TUNE_SEARCH))
+        return fail(nullptr, SHE_EINVAL, "unknown tuning_flags bits");
+    if ((cfg->tuning_flags & SHE_TUNE_SEARCH) && cfg->arena)
+        return fail(nullptr, SHE_EINVAL, "SHE_TUNE_SEARCH allocates trial handles: tune with she_tune, then "
+                                         "size the arena for the tuned configuration");
     if (cfg->graph_steps < 0 || cfg->graph_steps > (1 << 16))
         return fail(nullptr, SHE_EINVAL, "graph_steps must be in [0, 65536]");
     if (cfg->stats_mask & ~0x1Fu) return fail(nullptr, SHE_EINVAL, "unknown stats_mask bits");
@@ -354,6 +359,62 @@ she_status validate(const she_config *cfg, she_handle *h)
 }  // namespace
 
 // ------------------------------------------------------------------ create
+
+// Instances take whole waves (as many as they have Philox blocks, up to the
+// workgroup) and are packed first-fit, largest first, into workgroups of
+// block / 64 waves and at most 64 KB of LDS.  Returns an error text, or null.
+static const char *pack_1d(const std::vector<Inst1D> &tab, int block, int32_t es, int mode,
+                           std::vector<Seg1D> &segs, int &n_blocks, size_t &smem)
+{
+    const int W = block / 64;
+    constexpr int kLdsCap = 64 * 1024;
+    const int n_inst = static_cast<int>(tab.size());
+    std::vector<int> nw(n_inst), bytes(n_inst), idx(n_inst);
+    for (int i = 0; i < n_inst; ++i) {
+        const int n = tab[i].n, nf = tab[i].bc == SHE_DIRICHLET ? n + 1 : n;
+        const int nfg = (nf + 3) / 4;
+        nw[i] = std::min(W, (nfg + 63) / 64);
+        bytes[i] = seg_lds(n, nf, es, mode).total;
+        if (bytes[i] > kLdsCap) return "1D instance too large for LDS (64 KB per workgroup)";
+        idx[i] = i;
+    }
+    std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) {
+        if (nw[a] != nw[b]) return nw[a] > nw[b];
+        const int64_t wa = static_cast<int64_t>(tab[a].n) * (1 + tab[a].scheme);
+        const int64_t wb = static_cast<int64_t>(tab[b].n) * (1 + tab[b].scheme);
+        return wa > wb;
+    });
+    std::vector<int> used_w, used_b;
+    segs.clear();
+    for (int i : idx) {
+        size_t bin = 0;
+        while (bin < used_w.size() && (used_w[bin] + nw[i] > W || used_b[bin] + bytes[i] > kLdsCap)) ++bin;
+        if (bin == used_w.size()) {
+            used_w.push_back(0);
+            used_b.push_back(0);
+            segs.resize(segs.size() + W, Seg1D{-1, 0, 0, 0});
+        }
+        for (int w = 0; w < nw[i]; ++w) segs[bin * W + used_w[bin] + w] = Seg1D{i, used_w[bin], nw[i], used_b[bin]};
+        used_w[bin] += nw[i];
+        used_b[bin] += bytes[i];
+    }
+    n_blocks = static_cast<int>(used_w.size());
+    smem = static_cast<size_t>(*std::max_element(used_b.begin(), used_b.end()));
+    return nullptr;
+}
+
+// Compute units of the current device (the planner also runs without one:
+// then 256, MI355X's count).
+static int device_cus()
+{
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0) {
+        (void)hipGetLastError();
+        return 256;
+    }
+    return cus;
+}
 
 static she_status plan_1d(she_handle *h, const she_config *cfg, Plan &plan)
 {
@@ -484,61 +545,41 @@ static she_status plan_1d(she_handle *h, const she_config *cfg, Plan &plan)
     // most one block per thread up to 512 threads (64 x 1, 64 x 2, 256 x 1,
     // 512 x 1), then 512 threads with 2 or 4 blocks each.
     const int mode = !h->pcr_host.empty() ? 2 : (h->varc ? 1 : 0);
+    // A uniform explicit FP32 batch without statistics whose largest instance
+    // has 513..1024 blocks takes 1024 threads with one block each (a kernel
+    // held to 64 VGPRs, two workgroups per CU).
+    const bool wide_ok = h->prec == SHE_F32 && mode == 0 && h->mask == 0;
     int block = cfg->block_threads, maxg = 1;
     if (block == 0) {
         if (nfg_max <= 64) block = 64;
         else if (nfg_max <= 128) block = 64, maxg = 2;
         else if (nfg_max <= 256) block = 256;
-        else block = 512, maxg = nfg_max <= 512 ? 1 : (nfg_max <= 1024 ? 2 : 4);
+        else if (nfg_max <= 512) block = 512;
+        else block = 512, maxg = nfg_max <= 1024 ? 2 : 4;
+        if (wide_ok && nfg_max > 512 && nfg_max <= 1024) {
+            // 1024 x 1 halves the largest instances' chain, but its workgroups
+            // are resident together only up to one per CU (measured: a c4-like
+            // batch of 282 such workgroups ran slower than 471 of 512 x 2)
+            std::vector<Seg1D> sg;
+            int nb = 0;
+            size_t sm = 0;
+            if (!pack_1d(h->tab, 1024, static_cast<int32_t>(es), mode, sg, nb, sm) && nb <= device_cus())
+                block = 1024, maxg = 1;
+        }
     } else {
-        if (block != 64 && block != 256 && block != 512)
-            return fail(nullptr, SHE_EINVAL, "block_threads must be 0, 64, 256 or 512");
+        if (block != 64 && block != 256 && block != 512 && !(block == 1024 && wide_ok))
+            return fail(nullptr, SHE_EINVAL,
+                        "block_threads must be 0, 64, 256, 512, or 1024 (FP32, uniform explicit, no statistics)");
         const int g = (nfg_max + block - 1) / block;
         while (maxg < g) maxg *= 2;
     }
-    if (maxg > (block == 512 ? 4 : 2))
+    if (maxg > (block == 512 ? 4 : (block == 1024 ? 1 : 2)))
         return fail(nullptr, SHE_EUNSUPPORTED, "1D instance too large for the resident kernel at this block size");
     h->block1d = block;
     h->maxg = maxg;
-    // Instances take whole waves (as many as they have Philox blocks, up to
-    // the workgroup) and are packed first-fit, largest first, into
-    // workgroups of block / 64 waves and at most 64 KB of LDS.
     {
-        const int W = block / 64;
-        constexpr int kLdsCap = 64 * 1024;
-        std::vector<int> nw(h->n_inst), bytes(h->n_inst), idx(h->n_inst);
-        for (int i = 0; i < h->n_inst; ++i) {
-            const int n = h->tab[i].n, nf = h->tab[i].bc == SHE_DIRICHLET ? n + 1 : n;
-            const int nfg = (nf + 3) / 4;
-            nw[i] = std::min(W, (nfg + 63) / 64);
-            bytes[i] = seg_lds(n, nf, static_cast<int32_t>(es), mode).total;
-            if (bytes[i] > kLdsCap)
-                return fail(nullptr, SHE_EUNSUPPORTED, "1D instance too large for LDS (64 KB per workgroup)");
-            idx[i] = i;
-        }
-        std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) {
-            if (nw[a] != nw[b]) return nw[a] > nw[b];
-            const int64_t wa = static_cast<int64_t>(h->tab[a].n) * (1 + h->tab[a].scheme);
-            const int64_t wb = static_cast<int64_t>(h->tab[b].n) * (1 + h->tab[b].scheme);
-            return wa > wb;
-        });
-        std::vector<int> used_w, used_b;
-        h->segs_host.clear();
-        for (int i : idx) {
-            size_t bin = 0;
-            while (bin < used_w.size() && (used_w[bin] + nw[i] > W || used_b[bin] + bytes[i] > kLdsCap)) ++bin;
-            if (bin == used_w.size()) {
-                used_w.push_back(0);
-                used_b.push_back(0);
-                h->segs_host.resize(h->segs_host.size() + W, Seg1D{-1, 0, 0, 0});
-            }
-            for (int w = 0; w < nw[i]; ++w)
-                h->segs_host[bin * W + used_w[bin] + w] = Seg1D{i, used_w[bin], nw[i], used_b[bin]};
-            used_w[bin] += nw[i];
-            used_b[bin] += bytes[i];
-        }
-        h->blocks1d = static_cast<int>(used_w.size());
-        h->smem1d = static_cast<size_t>(*std::max_element(used_b.begin(), used_b.end()));
+        const char *why = pack_1d(h->tab, block, static_cast<int32_t>(es), mode, h->segs_host, h->blocks1d, h->smem1d);
+        if (why) return fail(nullptr, SHE_EUNSUPPORTED, why);
     }
 
     plan.add(reinterpret_cast<void **>(&h->d_tab), sizeof(Inst1D) * h->n_inst);
@@ -721,12 +762,114 @@ static she_status zero_stats(she_handle *h)
     return SHE_OK;
 }
 
+// ------------------------------------------------------------------ autotuning
+
+// Choices measured before in this process, keyed by what decides the launch
+// shapes: precision, statistics mask, and per instance the sizes, boundary,
+// scheme, equation, noise mode and whether material arrays are given.
+struct TuneChoice {
+    int32_t block_threads, rows_per_block, rows_per_group;
+};
+static std::mutex g_tune_mu;
+static std::map<std::string, TuneChoice> g_tune_cache;
+
+static std::string tune_key(const she_config *cfg)
+{
+    std::string k;
+    char buf[128];
+    std::snprintf(buf, sizeof buf, "p%d m%u f%d|", cfg->precision, cfg->stats_mask,
+                  cfg->tuning_flags & SHE_TUNE_XCD_ORDER);
+    k += buf;
+    for (int i = 0; i < cfg->n_instances; ++i) {
+        const she_instance_desc &d = cfg->inst[i];
+        std::snprintf(buf, sizeof buf, "%d:%dx%dx%d:%d%d%d%d%d;", d.dim, d.n[0], d.n[1], d.n[2], d.bc, d.scheme, d.eq,
+                      d.noise, (d.cond || d.cap) ? 1 : 0);
+        k += buf;
+    }
+    return k;
+}
+
+extern "C" she_status she_tune(const she_config *cfg, int32_t steps, she_config *tuned)
+{
+    if (!tuned) return fail(nullptr, SHE_EINVAL, "tuned is NULL");
+    she_status st = validate(cfg, nullptr);
+    if (st != SHE_OK) return st;
+    *tuned = *cfg;
+    tuned->tuning_flags &= ~SHE_TUNE_SEARCH;
+    const std::string key = tune_key(cfg);
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        const auto it = g_tune_cache.find(key);
+        if (it != g_tune_cache.end()) {
+            tuned->block_threads = it->second.block_threads;
+            tuned->rows_per_block = it->second.rows_per_block;
+            tuned->rows_per_group = it->second.rows_per_group;
+            return SHE_OK;
+        }
+    }
+    const int dim = cfg->inst[0].dim;
+    std::vector<TuneChoice> cand;
+    if (dim == 1) {
+        for (int b : {64, 256, 512, 1024}) cand.push_back({b, cfg->rows_per_block, cfg->rows_per_group});
+    } else if (dim == 2) {
+        for (int c : {4, 8, 16, 32, 64}) cand.push_back({cfg->block_threads, c, cfg->rows_per_group});
+    } else {
+        for (int c : {4, 8, 16})
+            for (int g : {1, 2, 4, 8}) cand.push_back({cfg->block_threads, c, g});
+    }
+    if (steps <= 0) steps = dim == 1 ? 2000 : 20;
+    hipStream_t s = static_cast<hipStream_t>(cfg->stream);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+        if (e0) (void)hipEventDestroy(e0);
+        return fail(nullptr, SHE_EDEVICE, "she_tune: hipEventCreate failed");
+    }
+    double best = 1e300;
+    TuneChoice pick{};
+    bool any = false;
+    for (const TuneChoice &c : cand) {
+        she_config t = *tuned;
+        t.block_threads = c.block_threads;
+        t.rows_per_block = c.rows_per_block;
+        t.rows_per_group = c.rows_per_group;
+        t.arena = nullptr;
+        t.arena_bytes = 0;
+        she_handle *h = nullptr;
+        if (she_create(&t, &h) != SHE_OK) continue;  // shape not valid for this batch
+        float ms = 0.0f;
+        const bool ok = she_step(h, std::max(1, steps / 4)) == SHE_OK && hipEventRecord(e0, s) == hipSuccess &&
+                        she_step(h, steps) == SHE_OK && hipEventRecord(e1, s) == hipSuccess &&
+                        hipEventSynchronize(e1) == hipSuccess && hipEventElapsedTime(&ms, e0, e1) == hipSuccess;
+        she_destroy(h);
+        if (ok && ms < best) {
+            best = ms;
+            pick = c;
+            any = true;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (!any) return fail(nullptr, SHE_EUNSUPPORTED, "she_tune: no candidate launch shape ran for this configuration");
+    tuned->block_threads = pick.block_threads;
+    tuned->rows_per_block = pick.rows_per_block;
+    tuned->rows_per_group = pick.rows_per_group;
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune_cache[key] = pick;
+    return SHE_OK;
+}
+
 extern "C" she_status she_create(const she_config *cfg, she_handle **out)
 {
     if (!out) return fail(nullptr, SHE_EINVAL, "out is NULL");
     *out = nullptr;
     she_status st = validate(cfg, nullptr);
     if (st != SHE_OK) return st;
+    if (cfg->tuning_flags & SHE_TUNE_SEARCH) {
+        she_config tuned;
+        st = she_tune(cfg, 0, &tuned);
+        if (st != SHE_OK) return st;
+        return she_create(&tuned, out);
+    }
     she_handle *h = new she_handle();
     Plan plan;
     st = build_plan(h, cfg, plan);

@@ -151,10 +151,10 @@ __device__ void xtx_block(const T *__restrict__ X, double *__restrict__ Cm, int 
 // is conserved).  The exchange arrays alternate between two buffers, so one
 // barrier per stage suffices.
 template <typename T, int BLOCK, int MAXG, bool STATS, int MODE>
-__global__ void __launch_bounds__(BLOCK)
-    k_step1d(const Inst1D *__restrict__ tab, const Seg1D *__restrict__ segs, T *__restrict__ pool,
-             const T *__restrict__ coef, const double *__restrict__ pcr, int64_t step0, int32_t nsteps,
-             int64_t burn_in, int32_t every, uint32_t mask, Stats1D st)
+__device__ __forceinline__ void step1d_body(const Inst1D *__restrict__ tab, const Seg1D *__restrict__ segs,
+                                            T *__restrict__ pool, const T *__restrict__ coef,
+                                            const double *__restrict__ pcr, int64_t step0, int32_t nsteps,
+                                            int64_t burn_in, int32_t every, uint32_t mask, Stats1D st)
 {
     constexpr bool VARC = MODE >= 1;
     extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -647,6 +647,28 @@ __global__ void __launch_bounds__(BLOCK)
     }
 }
 
+template <typename T, int BLOCK, int MAXG, bool STATS, int MODE>
+__global__ void __launch_bounds__(BLOCK)
+    k_step1d(const Inst1D *__restrict__ tab, const Seg1D *__restrict__ segs, T *__restrict__ pool,
+             const T *__restrict__ coef, const double *__restrict__ pcr, int64_t step0, int32_t nsteps,
+             int64_t burn_in, int32_t every, uint32_t mask, Stats1D st)
+{
+    step1d_body<T, BLOCK, MAXG, STATS, MODE>(tab, segs, pool, coef, pcr, step0, nsteps, burn_in, every, mask, st);
+}
+
+// 1024 threads with one Philox block each, for a uniform explicit FP32 batch
+// with no statistics, held to 64 VGPRs so that two workgroups (32 waves) fit on a
+// CU: a packed batch of instances up to 4096 Philox blocks stays resident in
+// one round while its largest instances keep one block per thread.
+template <typename T>
+__global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8)))
+    k_step1d_wide(const Inst1D *__restrict__ tab, const Seg1D *__restrict__ segs, T *__restrict__ pool,
+                  const T *__restrict__ coef, const double *__restrict__ pcr, int64_t step0, int32_t nsteps,
+                  int64_t burn_in, int32_t every, uint32_t mask, Stats1D st)
+{
+    step1d_body<T, 1024, 1, false, 0>(tab, segs, pool, coef, pcr, step0, nsteps, burn_in, every, mask, st);
+}
+
 // ------------------------------------------------------------------ time correlation
 
 // grid: (ceil(nmax L / 256), n_inst); thread (m, i) with i fastest, so the
@@ -871,7 +893,8 @@ static hipError_t step1d_t(bool stats, int mode, const Step1DLaunch &a)
 }
 
 // Launch shapes (threads per workgroup, Philox blocks per thread) the
-// planner chooses: 64 x {1, 2}, 256 x {1, 2}, 512 x {1, 2, 4}.
+// planner chooses: 64 x {1, 2}, 256 x {1, 2}, 512 x {1, 2, 4}, and 1024 x 1
+// for uniform explicit batches without statistics.
 template <typename T>
 static hipError_t step1d_p(int block, int maxg, bool stats, int mode, const Step1DLaunch &a)
 {
@@ -882,6 +905,14 @@ static hipError_t step1d_p(int block, int maxg, bool stats, int mode, const Step
     if (block == 512 && maxg == 1) return step1d_t<T, 512, 1>(stats, mode, a);
     if (block == 512 && maxg == 2) return step1d_t<T, 512, 2>(stats, mode, a);
     if (block == 512 && maxg == 4) return step1d_t<T, 512, 4>(stats, mode, a);
+    if constexpr (std::is_same<T, float>::value) {
+        if (block == 1024 && maxg == 1 && !stats && mode == 0) {
+            hipLaunchKernelGGL((k_step1d_wide<T>), dim3(a.n_blocks), dim3(1024), a.smem, a.s, a.tab, a.segs,
+                               static_cast<T *>(a.pool), static_cast<const T *>(a.coef), a.pcr, a.step0,
+                               a.nsteps, a.burn_in, a.every, a.mask, a.st);
+            return hipGetLastError();
+        }
+    }
     return hipErrorInvalidValue;
 }
 

@@ -23,6 +23,7 @@ NOISE_INSTANT, NOISE_FROZEN, NOISE_OFF = 0, 1, 2
 F32, F64 = 0, 1
 STAT_MOMENTS, STAT_CORR, STAT_SK, STAT_SPATIAL, STAT_TCORR = 1, 2, 4, 8, 16
 TUNE_XCD_ORDER = 1
+TUNE_SEARCH = 2
 
 OK, EINVAL, EUNSTABLE, ENOMEM, EDEVICE, ENONFINITE, ESTATE, EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6, -7
 _NAMES = {0: "SHE_OK", -1: "SHE_EINVAL", -2: "SHE_EUNSTABLE", -3: "SHE_ENOMEM", -4: "SHE_EDEVICE",
@@ -64,7 +65,7 @@ class StatsOut(C.Structure):
                 ("clamp_count", C.c_int64), ("tcorr", C.POINTER(C.c_double)), ("tcorr_cap", C.c_int64)]
 
 
-EXPORTS = ["she_create", "she_arena_bytes", "she_step", "she_run", "she_stats", "she_reset_stats",
+EXPORTS = ["she_create", "she_arena_bytes", "she_tune", "she_step", "she_run", "she_stats", "she_reset_stats",
            "she_read_field", "she_write_field", "she_get_step", "she_state_bytes", "she_get_state",
            "she_set_state", "she_last_error", "she_destroy", "she_debug_philox", "she_debug_normals"]
 
@@ -82,6 +83,7 @@ def load(path: str = LIB_PATH):
     P = C.POINTER
     lib.she_create.argtypes = [P(Config), P(C.c_void_p)]
     lib.she_arena_bytes.argtypes = [P(Config), P(C.c_size_t)]
+    lib.she_tune.argtypes = [P(Config), C.c_int32, P(Config)]
     lib.she_step.argtypes = [C.c_void_p, C.c_int64]
     lib.she_run.argtypes = [C.c_void_p, C.c_int64]
     lib.she_stats.argtypes = [C.c_void_p, C.c_int32, P(StatsOut)]
@@ -211,6 +213,23 @@ class Handle:
         out = C.c_size_t()
         _check(lib.she_arena_bytes(C.byref(cfg), C.byref(out)))
         return int(out.value)
+
+    @staticmethod
+    def tune(instances, precision=F32, stats=0, stream=None, block_threads=0, rows_per_block=0,
+             rows_per_group=0, tuning_flags=0, steps: int = 0) -> dict:
+        """she_tune: the fastest launch shape for this batch, as keyword
+        arguments for Handle (block_threads, rows_per_block, rows_per_group)."""
+        lib = load()
+        insts = list(instances)
+        descs = (InstanceDesc * len(insts))(*[i.c() for i in insts])
+        if stream is None:
+            stream = current_stream()
+        cfg = Config(len(insts), precision, descs, 0, 10, stats, block_threads, rows_per_block, rows_per_group,
+                     tuning_flags, 0, 0, C.c_void_p(stream) if stream else None, None, 0)
+        out = Config()
+        _check(lib.she_tune(C.byref(cfg), int(steps), C.byref(out)))
+        return dict(block_threads=int(out.block_threads), rows_per_block=int(out.rows_per_block),
+                    rows_per_group=int(out.rows_per_group))
 
     def close(self):
         if getattr(self, "h", None):

@@ -69,12 +69,20 @@ def test_invalid_nd_configs():
 
 def test_invalid_tuning_and_graph_settings():
     insts = [gpu_instance(she, W.instance((64, 64), r=0.1))]
-    for kw in (dict(tuning_flags=2), dict(graph_steps=-1), dict(graph_steps=(1 << 16) + 1)):
+    for kw in (dict(tuning_flags=4), dict(graph_steps=-1), dict(graph_steps=(1 << 16) + 1)):
         with pytest.raises(she.SheError) as e:
             she.Handle.arena_bytes(insts, **kw)
         assert e.value.status == she.EINVAL, kw
     base = she.Handle.arena_bytes(insts)
     assert she.Handle.arena_bytes(insts, graph_steps=64, tuning_flags=she.TUNE_XCD_ORDER) == base
+    assert she.Handle.arena_bytes(insts, tuning_flags=she.TUNE_SEARCH) == base
+    # the autotuner allocates trial handles, so it refuses a caller arena (checked
+    # before any device work)
+    import torch
+    arena = torch.empty(base, dtype=torch.uint8)
+    with pytest.raises(she.SheError) as e:
+        she.Handle(insts, arena=arena, tuning_flags=she.TUNE_SEARCH, stream=0)
+    assert e.value.status == she.EINVAL
 
 
 def test_time_correlation_settings():

@@ -119,14 +119,38 @@ def test_1d_ragged_batch_and_independence(she):
 
 def test_1d_launch_shape_invariance(she):
     # 64 threads: one instance per workgroup, up to two Philox blocks per
-    # thread; 256 and 512: instances packed several to a workgroup
+    # thread; 256, 512 and 1024 (the 64-VGPR kernel for plain FP32 batches):
+    # instances packed several to a workgroup
     insts = [inst1d(*c, realisation=q) for q, c in enumerate(CASES_1D[:6])]
     _, a, _ = run_both(she, insts, 2000, 0, block_threads=64)
-    _, b, _ = run_both(she, insts, 2000, 0, block_threads=256)
-    _, c, _ = run_both(she, insts, 2000, 0, block_threads=512)
-    for x, y, z in zip(a, b, c):
-        np.testing.assert_array_equal(x, y)
-        np.testing.assert_array_equal(x, z)
+    for bt in (256, 512, 1024):
+        _, b, _ = run_both(she, insts, 2000, 0, block_threads=bt)
+        for x, y in zip(a, b):
+            np.testing.assert_array_equal(x, y)
+
+
+def test_autotuner_picks_a_valid_shape_with_identical_results(she):
+    # 1D: a ragged batch; 2D: one field.  The tuned handle (SHE_TUNE_SEARCH)
+    # must reproduce the default handle bit for bit: shapes change time only.
+    cases = [([inst1d(*c, realisation=q) for q, c in enumerate(CASES_1D[:6])], 1),
+             ([inst2d((64, 48), W.EM, W.HEAT, realisation=q) for q in range(3)], 2)]
+    for insts, dim in cases:
+        g = [gpu_instance(she, i) for i in insts]
+        t = she.Handle.tune(g, steps=50)
+        if dim == 1:
+            assert t["block_threads"] in (64, 256, 512, 1024)
+        else:
+            assert t["rows_per_block"] in (4, 8, 16, 32, 64)
+        assert she.Handle.tune(g, steps=50) == t          # cached for the process
+        outs = []
+        for kw in (dict(), dict(tuning_flags=she.TUNE_SEARCH), t):
+            h = she.Handle(g, precision=0, **kw)
+            h.step(300)
+            outs.append([h.read_field(q) for q in range(len(insts))])
+            h.close()
+        for o in outs[1:]:
+            for x, y in zip(outs[0], o):
+                np.testing.assert_array_equal(x, y)
 
 
 @pytest.mark.parametrize("scheme", [W.EM, W.HEUN])
