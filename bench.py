@@ -34,8 +34,9 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_step2d_c3.json")
 
 
 def kernel_hash() -> str:
+    # the kernel's sources and the host code that picks its launch shape
     h = hashlib.sha256()
-    for name in ("she_knd.hip", "she_rng.hpp", "she_internal.hpp"):
+    for name in ("she_knd.hip", "she_rng.hpp", "she_internal.hpp", "she_capi.hip"):
         with open(os.path.join(ROOT, "paper_2406_12157_amd", "csrc", name), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]

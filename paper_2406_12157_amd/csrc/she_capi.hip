@@ -652,9 +652,17 @@ static she_status plan_nd(she_handle *h, const she_config *cfg, Plan &plan)
     p.seed = d0.seed;
     h->cells = static_cast<int64_t>(p.nx) * p.ny * p.nz;
     if (d0.dim == 2) {
-        // default march length: about 4096 row groups in flight, 1..32 rows each
+        // Default march length.  FE: about 16384 row groups in flight, 1..8 rows
+        // each (short marches keep more loads in flight; the halo row a chunk
+        // re-reads mostly hits the cache).  PC recomputes three rows per chunk,
+        // so it takes about 4096 groups of up to 32 rows.  Measured at
+        // 512 x 512 x 256: FE 0.1115 ms per step at 8 rows vs 0.1182 at 32; PC
+        // 0.1364 at 32 vs 0.1577 at 8.
         int chunk = cfg->rows_per_block;
-        if (chunk <= 0) chunk = std::max(1, std::min(32, static_cast<int>(static_cast<int64_t>(h->n_inst) * p.ny / 4096)));
+        const int64_t rows_all = static_cast<int64_t>(h->n_inst) * p.ny;
+        if (chunk <= 0)
+            chunk = d0.scheme == SHE_EM ? static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(8, rows_all / 16384)))
+                                        : static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(32, rows_all / 4096)));
         chunk = std::min(chunk, p.ny);
         p.chunk = chunk;
         const int nchunks = (p.ny + chunk - 1) / chunk;
