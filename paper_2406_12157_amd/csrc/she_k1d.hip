@@ -400,8 +400,8 @@ __device__ __forceinline__ void step1d_body(const Inst1D *__restrict__ tab, cons
         for (int s = 0; s < MAXG; ++s) {
             const int g = t + s * TS;
             if (noise != 2 && g < nfg) {
-                const Normals4<T> nz = block_normals<T>(static_cast<uint32_t>(g), static_cast<uint32_t>(n),
-                                                        ctr_word2(n, 0u), d.realisation, key);
+                const Normals4<T> nz = block_normals<T, true>(static_cast<uint32_t>(g), static_cast<uint32_t>(n),
+                                                              ctr_word2(n, 0u), d.realisation, key);
 #pragma unroll
                 for (int l = 0; l < 4; ++l) z[s][l] = nz.z[l];
             } else {

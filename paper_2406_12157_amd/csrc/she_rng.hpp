@@ -38,10 +38,16 @@ struct Words4 {
     uint32_t w[4];
 };
 
+// LIVE_KEY: the key passes through an empty asm statement, so the compiler
+// forms the round keys inside each call (two scalar adds per round) instead
+// of holding all twenty in scalar registers across an enclosing loop; for
+// kernels whose loops are short of scalar registers.
+template <bool LIVE_KEY = false>
 __device__ __forceinline__ Words4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2,
                                                  uint32_t c3, PhiloxKey key)
 {
     uint32_t k0 = key.k0, k1 = key.k1;
+    if constexpr (LIVE_KEY) asm volatile("" : "+s"(k0), "+s"(k1));
 #pragma unroll
     for (int round = 0; round < 10; ++round) {
         const uint64_t p0 = static_cast<uint64_t>(0xD2511F53u) * c0;
@@ -100,12 +106,12 @@ __device__ __forceinline__ void box_muller(uint32_t wa, uint32_t wb, double &zc,
 }
 
 // The four normals of Philox block `block` at step `step`.
-template <typename T>
+template <typename T, bool LIVE_KEY = false>
 __device__ __forceinline__ Normals4<T> block_normals(uint32_t block, uint32_t step_lo,
                                                      uint32_t w2, uint32_t realisation,
                                                      PhiloxKey key)
 {
-    const Words4 x = philox4x32_10(block, step_lo, w2, realisation, key);
+    const Words4 x = philox4x32_10<LIVE_KEY>(block, step_lo, w2, realisation, key);
     Normals4<T> n;
     box_muller(x.w[0], x.w[1], n.z[0], n.z[1]);
     box_muller(x.w[2], x.w[3], n.z[2], n.z[3]);
