@@ -129,6 +129,29 @@ def test_1d_launch_shape_invariance(she):
             np.testing.assert_array_equal(x, y)
 
 
+def test_1d_packed_edge_sizes(she):
+    # Instance sizes around the four-cell Philox blocks (partial last blocks,
+    # the extra block of a Dirichlet rod whose N is a multiple of 4) and around
+    # wave boundaries, mixed boundaries / schemes / equations / noise modes,
+    # packed several to a workgroup: each against the oracle, and bit-identical
+    # over every launch shape.
+    sizes = [1, 2, 3, 4, 5, 7, 8, 9, 63, 64, 65, 255, 256, 257]
+    insts = []
+    for q, n in enumerate(sizes):
+        bc = W.DIRICHLET if (q % 2 == 0 or n == 1) else W.PERIODIC
+        scheme = W.HEUN if q % 3 == 1 else W.EM
+        eq = W.SPECIES if q % 4 == 3 else W.HEAT
+        noise = 1 if q % 5 == 4 else 0
+        insts.append(inst1d((n,), bc, scheme, eq, noise, realisation=q))
+    _, got, want = run_both(she, insts, 1500, 0)
+    for q in range(len(insts)):
+        assert max_rel(got[q], want[q]) <= 1e-5, (q, sizes[q])
+    for bt in (64, 256, 512, 1024):
+        _, other, _ = run_both(she, insts, 1500, 0, block_threads=bt)
+        for q in range(len(insts)):
+            np.testing.assert_array_equal(other[q], got[q])
+
+
 def test_autotuner_picks_a_valid_shape_with_identical_results(she):
     # 1D: a ragged batch; 2D: one field.  The tuned handle (SHE_TUNE_SEARCH)
     # must reproduce the default handle bit for bit: shapes change time only.
