@@ -157,8 +157,9 @@ typedef struct {
     uint32_t stats_mask;          /* SHE_STAT_* bits                           */
     int32_t block_threads;        /* tuning: 1D threads per workgroup: 0 (auto),
                                      64, 256 or 512, or 1024 for an FP32
-                                     batch of FE/PC instances with uniform
-                                     material and stats_mask 0; an instance
+                                     batch of FE/PC heat instances with
+                                     instantaneous noise, uniform material
+                                     and stats_mask 0; an instance
                                      takes whole waves of a workgroup, small
                                      instances share one                    */
     int32_t rows_per_block;       /* tuning: 2D/3D march length (0 auto)      */

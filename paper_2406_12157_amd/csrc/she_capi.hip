@@ -545,10 +545,13 @@ static she_status plan_1d(she_handle *h, const she_config *cfg, Plan &plan)
     // most one block per thread up to 512 threads (64 x 1, 64 x 2, 256 x 1,
     // 512 x 1), then 512 threads with 2 or 4 blocks each.
     const int mode = !h->pcr_host.empty() ? 2 : (h->varc ? 1 : 0);
-    // A uniform explicit FP32 batch without statistics whose largest instance
-    // has 513..1024 blocks takes 1024 threads with one block each (a kernel
-    // held to 64 VGPRs, two workgroups per CU).
-    const bool wide_ok = h->prec == SHE_F32 && mode == 0 && h->mask == 0;
+    // A uniform explicit FP32 batch of heat instances with instantaneous noise
+    // and no statistics whose largest instance has 513..1024 blocks may take
+    // 1024 threads with one block each (a kernel compiled for that face path
+    // only, 38 VGPRs, two workgroups per CU).
+    bool wide_ok = h->prec == SHE_F32 && mode == 0 && h->mask == 0;
+    for (int i = 0; i < h->n_inst && wide_ok; ++i)
+        wide_ok = h->tab[i].eq == SHE_HEAT && h->tab[i].noise == SHE_NOISE_INSTANT;
     int block = cfg->block_threads, maxg = 1;
     if (block == 0) {
         if (nfg_max <= 64) block = 64;
@@ -569,7 +572,8 @@ static she_status plan_1d(she_handle *h, const she_config *cfg, Plan &plan)
     } else {
         if (block != 64 && block != 256 && block != 512 && !(block == 1024 && wide_ok))
             return fail(nullptr, SHE_EINVAL,
-                        "block_threads must be 0, 64, 256, 512, or 1024 (FP32, uniform explicit, no statistics)");
+                        "block_threads must be 0, 64, 256, 512, or 1024 (FP32 heat with instantaneous noise, "
+                        "uniform material, explicit, no statistics)");
         const int g = (nfg_max + block - 1) / block;
         while (maxg < g) maxg *= 2;
     }

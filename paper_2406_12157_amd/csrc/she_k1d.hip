@@ -150,7 +150,7 @@ __device__ void xtx_block(const T *__restrict__ X, double *__restrict__ Cm, int 
 // as well (same inputs, same code, so the two agree bit for bit and the sum
 // is conserved).  The exchange arrays alternate between two buffers, so one
 // barrier per stage suffices.
-template <typename T, int BLOCK, int MAXG, bool STATS, int MODE>
+template <typename T, int BLOCK, int MAXG, bool STATS, int MODE, bool HEAT_ONLY = false>
 __device__ __forceinline__ void step1d_body(const Inst1D *__restrict__ tab, const Seg1D *__restrict__ segs,
                                             T *__restrict__ pool, const T *__restrict__ coef,
                                             const double *__restrict__ pcr, int64_t step0, int32_t nsteps,
@@ -385,11 +385,15 @@ __device__ __forceinline__ void step1d_body(const Inst1D *__restrict__ tab, cons
                 for (int l = 0; l < 4; ++l) dv[s][l] = VARC ? Wc[4 * g + l] * (F[l + 1] - F[l]) : F[l + 1] - F[l];
             }
         };
-        switch (kind) {
-        case 0: faces(std::integral_constant<int, 0>{}); break;
-        case 1: faces(std::integral_constant<int, 1>{}); break;
-        case 2: faces(std::integral_constant<int, 2>{}); break;
-        default: faces(std::integral_constant<int, 3>{}); break;
+        if constexpr (HEAT_ONLY) {
+            faces(std::integral_constant<int, 0>{});
+        } else {
+            switch (kind) {
+            case 0: faces(std::integral_constant<int, 0>{}); break;
+            case 1: faces(std::integral_constant<int, 1>{}); break;
+            case 2: faces(std::integral_constant<int, 2>{}); break;
+            default: faces(std::integral_constant<int, 3>{}); break;
+            }
         }
     };
 
@@ -657,7 +661,8 @@ __global__ void __launch_bounds__(BLOCK)
 }
 
 // 1024 threads with one Philox block each, for a uniform explicit FP32 batch
-// with no statistics, held to 64 VGPRs so that two workgroups (32 waves) fit on a
+// of heat instances with instantaneous noise and no statistics (only that
+// face path is compiled), held to 64 VGPRs so that two workgroups (32 waves) fit on a
 // CU: a packed batch of instances up to 4096 Philox blocks stays resident in
 // one round while its largest instances keep one block per thread.
 template <typename T>
@@ -666,7 +671,7 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8)))
                   const T *__restrict__ coef, const double *__restrict__ pcr, int64_t step0, int32_t nsteps,
                   int64_t burn_in, int32_t every, uint32_t mask, Stats1D st)
 {
-    step1d_body<T, 1024, 1, false, 0>(tab, segs, pool, coef, pcr, step0, nsteps, burn_in, every, mask, st);
+    step1d_body<T, 1024, 1, false, 0, true>(tab, segs, pool, coef, pcr, step0, nsteps, burn_in, every, mask, st);
 }
 
 // ------------------------------------------------------------------ time correlation

@@ -124,9 +124,11 @@ def test_1d_launch_shape_invariance(she):
     insts = [inst1d(*c, realisation=q) for q, c in enumerate(CASES_1D[:6])]
     _, a, _ = run_both(she, insts, 2000, 0, block_threads=64)
     for bt in (256, 512, 1024):
-        _, b, _ = run_both(she, insts, 2000, 0, block_threads=bt)
-        for x, y in zip(a, b):
-            np.testing.assert_array_equal(x, y)
+        # 1024 compiles only the heat face with instantaneous noise
+        sel = [q for q, i in enumerate(insts) if bt < 1024 or (i["eq"] == W.HEAT and i["noise"] == 0)]
+        _, b, _ = run_both(she, [insts[q] for q in sel], 2000, 0, block_threads=bt)
+        for q, y in zip(sel, b):
+            np.testing.assert_array_equal(a[q], y)
 
 
 def test_1d_packed_edge_sizes(she):
@@ -147,9 +149,10 @@ def test_1d_packed_edge_sizes(she):
     for q in range(len(insts)):
         assert max_rel(got[q], want[q]) <= 1e-5, (q, sizes[q])
     for bt in (64, 256, 512, 1024):
-        _, other, _ = run_both(she, insts, 1500, 0, block_threads=bt)
-        for q in range(len(insts)):
-            np.testing.assert_array_equal(other[q], got[q])
+        sel = [q for q, i in enumerate(insts) if bt < 1024 or (i["eq"] == W.HEAT and i["noise"] == 0)]
+        _, other, _ = run_both(she, [insts[q] for q in sel], 1500, 0, block_threads=bt)
+        for q, y in zip(sel, other):
+            np.testing.assert_array_equal(y, got[q])
 
 
 def test_autotuner_picks_a_valid_shape_with_identical_results(she):
