@@ -45,6 +45,7 @@ struct she_handle {
     Seg1D *d_segs = nullptr;      // per wave of the 1D launch
     std::vector<Seg1D> segs_host;
     int blocks1d = 0;             // workgroups of the 1D launch
+    int mode1d = 0;               // kernel mode (see launch_step1d)
     void *d_pool = nullptr;
     std::vector<Inst1D> tab;
     int64_t total_cells = 0;
@@ -544,14 +545,16 @@ static she_status plan_1d(she_handle *h, const she_config *cfg, Plan &plan)
     // the smallest shape whose workgroup holds the largest instance with at
     // most one block per thread up to 512 threads (64 x 1, 64 x 2, 256 x 1,
     // 512 x 1), then 512 threads with 2 or 4 blocks each.
-    const int mode = !h->pcr_host.empty() ? 2 : (h->varc ? 1 : 0);
+    bool heat_only = true;
+    for (int i = 0; i < h->n_inst; ++i)
+        heat_only = heat_only && h->tab[i].eq == SHE_HEAT && h->tab[i].noise == SHE_NOISE_INSTANT;
+    const int mode = !h->pcr_host.empty() ? 2 : (h->varc ? 1 : (heat_only ? 3 : 0));
+    h->mode1d = mode;
     // A uniform explicit FP32 batch of heat instances with instantaneous noise
     // and no statistics whose largest instance has 513..1024 blocks may take
     // 1024 threads with one block each (a kernel compiled for that face path
     // only, 38 VGPRs, two workgroups per CU).
-    bool wide_ok = h->prec == SHE_F32 && mode == 0 && h->mask == 0;
-    for (int i = 0; i < h->n_inst && wide_ok; ++i)
-        wide_ok = h->tab[i].eq == SHE_HEAT && h->tab[i].noise == SHE_NOISE_INSTANT;
+    const bool wide_ok = h->prec == SHE_F32 && mode == 3 && h->mask == 0;
     int block = cfg->block_threads, maxg = 1;
     if (block == 0) {
         if (nfg_max <= 64) block = 64;
@@ -1084,8 +1087,7 @@ static she_status advance(she_handle *h, int64_t nsteps, bool sampling)
                 const int64_t j0 = std::max(h->steps, h->burn_in) / h->every;
                 k = std::min<int64_t>(k, h->every * (j0 + room + 1) - 1 - h->steps);
             }
-            const int mode = !h->pcr_host.empty() ? 2 : (h->varc ? 1 : 0);
-            SHE_HIP(h, launch_step1d(h->prec, h->block1d, h->maxg, stats, mode, h->blocks1d, h->smem1d, s,
+            SHE_HIP(h, launch_step1d(h->prec, h->block1d, h->maxg, stats, h->mode1d, h->blocks1d, h->smem1d, s,
                                      h->d_tab, h->d_segs, h->d_pool, h->d_coef, h->d_pcr, h->steps,
                                      static_cast<int32_t>(k),
                                      h->burn_in, h->every, h->mask, st));

@@ -73,7 +73,7 @@ struct Seg1D {
 // LDS region of one 1D instance (byte offsets, 16-byte aligned parts):
 // exchange arrays [2 buffers][first value, last value, face-0 number][nfg
 // rounded up to 4] of the state type; the wave sums of a sample (3 x 16
-// doubles); with material arrays (mode >= 1) r_f and s_f [nf + 4]
+// doubles); with material arrays (mode 1 or 2) r_f and s_f [nf + 4]
 // and w_i [n + 4] of the state type; for implicit schemes (mode 2) an FP64
 // array [n] for the reduction.
 struct SegLds {
@@ -92,7 +92,7 @@ __host__ __device__ inline SegLds seg_lds(int32_t n, int32_t nf, int32_t es, int
     l.red = o;
     o = lds_align16(o + 3 * 16 * 8);
     l.rf = l.sf = l.wc = l.pd = -1;
-    if (mode >= 1) {
+    if (mode == 1 || mode == 2) {
         l.rf = o;
         o = lds_align16(o + (nf + 4) * es);
         l.sf = o;
@@ -153,7 +153,9 @@ __device__ __forceinline__ void resolve_step(const StepArg &a, int64_t &step, in
 namespace she {
 
 // ---- launchers (defined next to their kernels) ----
-// mode 0: uniform explicit batch; 1: some instance has material coefficients
+// mode 0: uniform explicit batch; 3: the same with every instance a heat
+// equation with instantaneous noise (only that face path compiled);
+// 1: some instance has material coefficients
 // (k_off >= 0 in `coef`; r_f, s_f, w_i of every instance staged in LDS);
 // 2: some instance is implicit (reduction factors in `pcr`; mode 1 included).
 // segs: n_blocks * block / 64 wave entries.

@@ -136,7 +136,9 @@ __device__ void xtx_block(const T *__restrict__ X, double *__restrict__ Cm, int 
     }
 }
 
-// MODE 0: uniform explicit batch; 1: material coefficients (VARC); 2: some
+// MODE 0: uniform explicit batch; 3: the same with every instance a heat
+// equation with instantaneous noise (only that face path is compiled: fewer
+// registers and a shorter loop); 1: material coefficients (VARC); 2: some
 // instance is implicit (material arrays available as well).  Each mode is
 // compiled separately so that a batch pays only for the paths it uses.
 //
@@ -150,13 +152,14 @@ __device__ void xtx_block(const T *__restrict__ X, double *__restrict__ Cm, int 
 // as well (same inputs, same code, so the two agree bit for bit and the sum
 // is conserved).  The exchange arrays alternate between two buffers, so one
 // barrier per stage suffices.
-template <typename T, int BLOCK, int MAXG, bool STATS, int MODE, bool HEAT_ONLY = false>
+template <typename T, int BLOCK, int MAXG, bool STATS, int MODE>
 __device__ __forceinline__ void step1d_body(const Inst1D *__restrict__ tab, const Seg1D *__restrict__ segs,
                                             T *__restrict__ pool, const T *__restrict__ coef,
                                             const double *__restrict__ pcr, int64_t step0, int32_t nsteps,
                                             int64_t burn_in, int32_t every, uint32_t mask, Stats1D st)
 {
-    constexpr bool VARC = MODE >= 1;
+    constexpr bool VARC = MODE == 1 || MODE == 2;
+    constexpr bool HEAT_ONLY = MODE == 3;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const int wave = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x >> 6));
     const Seg1D seg = segs[static_cast<int64_t>(blockIdx.x) * (BLOCK / 64) + wave];
@@ -671,7 +674,7 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8)))
                   const T *__restrict__ coef, const double *__restrict__ pcr, int64_t step0, int32_t nsteps,
                   int64_t burn_in, int32_t every, uint32_t mask, Stats1D st)
 {
-    step1d_body<T, 1024, 1, false, 0, true>(tab, segs, pool, coef, pcr, step0, nsteps, burn_in, every, mask, st);
+    step1d_body<T, 1024, 1, false, 3>(tab, segs, pool, coef, pcr, step0, nsteps, burn_in, every, mask, st);
 }
 
 // ------------------------------------------------------------------ time correlation
@@ -887,6 +890,7 @@ static hipError_t step1d_m(int mode, const Step1DLaunch &a)
     case 0: return step1d_k<T, BLOCK, MAXG, STATS, 0>(a);
     case 1: return step1d_k<T, BLOCK, MAXG, STATS, 1>(a);
     case 2: return step1d_k<T, BLOCK, MAXG, STATS, 2>(a);
+    case 3: return step1d_k<T, BLOCK, MAXG, STATS, 3>(a);
     default: return hipErrorInvalidValue;
     }
 }
@@ -911,7 +915,7 @@ static hipError_t step1d_p(int block, int maxg, bool stats, int mode, const Step
     if (block == 512 && maxg == 2) return step1d_t<T, 512, 2>(stats, mode, a);
     if (block == 512 && maxg == 4) return step1d_t<T, 512, 4>(stats, mode, a);
     if constexpr (std::is_same<T, float>::value) {
-        if (block == 1024 && maxg == 1 && !stats && mode == 0) {
+        if (block == 1024 && maxg == 1 && !stats && mode == 3) {
             hipLaunchKernelGGL((k_step1d_wide<T>), dim3(a.n_blocks), dim3(1024), a.smem, a.s, a.tab, a.segs,
                                static_cast<T *>(a.pool), static_cast<const T *>(a.coef), a.pcr, a.step0,
                                a.nsteps, a.burn_in, a.every, a.mask, a.st);
