@@ -276,10 +276,13 @@ def test_burgers_statistics_parity(she):
 
 
 @pytest.mark.parametrize("precision,scheme", [(0, W.BE), (0, W.CN), (1, W.BE), (1, W.CN)])
-def test_implicit_state_parity(she, precision, scheme):
+@pytest.mark.parametrize("block_threads", [0, 256, 512])
+def test_implicit_state_parity(she, precision, scheme, block_threads):
     """Backward Euler / Crank-Nicolson far beyond the explicit limit: a
     periodic ring (r = 2), a Dirichlet rod with a gradient (r = 10), a
-    composite rod (r = 3) and a single-level periodic ring (N = 3), one batch."""
+    composite rod (r = 3), a single-level periodic ring (N = 3) and an
+    explicit rod, one batch.  At 256 and 512 threads the instances share
+    workgroups while running different numbers of reduction levels."""
     ring = W.instance((100,), scheme=scheme, r=2.0, eps=1e-2, init_sd=0.1, realisation=1)
     rod = W.instance((257,), bc=W.DIRICHLET, scheme=scheme, r=10.0, eps=1e-3, u0=1.0, u_left=0.8, u_right=1.2,
                      init_sd=0.03, realisation=2)
@@ -289,8 +292,10 @@ def test_implicit_state_parity(she, precision, scheme):
     # lands on exact float ties, and the FP64 solve's last-bit error decides them
     # all one way, so an FP32 state drifts by ulp/3 per step (FP64: test below)
     tiny = W.instance((3,), scheme=scheme, r=0.9, eps=1e-2, init_sd=0.1, realisation=4)
-    insts = [ring, rod, comp, tiny]
-    h = she.Handle([gpu_instance(she, i) for i in insts], precision=precision)
+    fe = W.instance((50,), bc=W.DIRICHLET, scheme=W.HEUN, r=0.05, eps=1e-3, u0=1.0, u_left=1.1, u_right=0.9,
+                    init_sd=0.03, realisation=5)
+    insts = [ring, rod, comp, tiny, fe]
+    h = she.Handle([gpu_instance(she, i) for i in insts], precision=precision, block_threads=block_threads)
     init = [h.read_field(q) for q in range(len(insts))]
     steps = 3000 if precision == 0 else 1000
     h.step(steps)
