@@ -138,6 +138,43 @@ def read_traffic(cells_per_launch):
     return t.get("hbm_bytes_per_launch")
 
 
+def other_workload(args, torch, she, W):
+    """Throughput of c1, c2, c4 or c5 with the statistics its configuration
+    names, timed over `--steps` steps after `--warmup` (she_run, burn-in 0).
+    The 1D workloads keep their state in registers, so they are bound by the
+    per-step latency of the resident kernel, not by HBM; c5 gets the HBM
+    roofline of its step kernel as c3 does."""
+    cfg = {"c1": W.c1, "c2": W.c2, "c4": W.c4, "c5": W.c5}[args.workload]()
+    stats = {"c1": she.STAT_MOMENTS | she.STAT_CORR, "c2": she.STAT_MOMENTS | she.STAT_CORR, "c4": 0,
+             "c5": she.STAT_SPATIAL}[args.workload]
+    h, insts = make_handle(she, cfg, stats)
+    cells = sum(i.ncells for i in insts)
+    h.run(args.warmup)
+    torch.cuda.synchronize()
+    roofline = None
+    if args.workload == "c5":
+        wall, kms, nev = timed_region(torch, h, args.steps, cfg["sample_every"])
+        bpl = 8.0 * cells
+        ach = bpl / (kms * 1e-3) / 1e9
+        roofline = dict(bound="hbm", achieved=ach, peak=HBM_PEAK_GBS, unit="GB/s", frac=ach / HBM_PEAK_GBS,
+                        traffic=None, kernel="k_step3d<float,4,dk>", kernel_ms=kms, kernel_launches_timed=nev,
+                        algorithmic_bytes_per_launch=bpl)
+    else:
+        t0 = time.perf_counter()
+        h.run(args.steps)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+    h.close()
+    out = {"metric": METRIC, "value": cells * args.steps / wall, "unit": "cell-updates/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": wall / args.steps * 1e3,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f64" if cfg["precision"] == 1 else "f32", "data": "synthetic",
+           "config": {"workload": cfg["name"], "instances": len(insts), "cells": cells,
+                      "sample_every": cfg["sample_every"], "stats_mask": int(stats), "parallelism": "single GPU"},
+           "roofline": roofline}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -151,6 +188,9 @@ def main():
     ap.add_argument("--no-error", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one 1 GiB device-to-device copy (reference for HBM counters)")
+    ap.add_argument("--workload", choices=["c3", "c1", "c2", "c4", "c5"], default="c3",
+                    help="c3 (default): the benchmark line; the others: a throughput line of that "
+                         "workload with its statistics, for profiling")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build runs on one GPU only (--gpus 1); the path would shard by realisation "
@@ -163,6 +203,9 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
     she.load()
+    if args.workload != "c3":
+        other_workload(args, torch, she, W)
+        return
     scheme = W.EM if args.scheme == "fe" else W.HEUN
     cfg = W.c3(realisations=args.realisations, scheme=scheme)
     every = cfg["sample_every"]
