@@ -33,12 +33,26 @@ KERNEL_SRC = os.path.join(ROOT, "paper_2406_12157_amd", "csrc", "she_knd.hip")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_step2d_c3.json")
 
 
+def _section(text: str, start: str, end: str) -> str:
+    i = text.index(start)
+    return text[i:text.index(end, i) + len(end)]
+
+
 def kernel_hash() -> str:
-    # the kernel's sources and the host code that picks its launch shape
+    """Hash of what decides the 2D step kernel's HBM traffic: its source, the
+    noise header, the host function that picks its launch shape (plan_nd) and
+    the parameter structs it takes; edits elsewhere leave it unchanged."""
+    csrc = os.path.join(ROOT, "paper_2406_12157_amd", "csrc")
     h = hashlib.sha256()
-    for name in ("she_knd.hip", "she_rng.hpp", "she_internal.hpp", "she_capi.hip"):
-        with open(os.path.join(ROOT, "paper_2406_12157_amd", "csrc", name), "rb") as f:
+    for name in ("she_knd.hip", "she_rng.hpp"):
+        with open(os.path.join(csrc, name), "rb") as f:
             h.update(f.read())
+    with open(os.path.join(csrc, "she_capi.hip")) as f:
+        h.update(_section(f.read(), "static she_status plan_nd(", "\n}\n").encode())
+    with open(os.path.join(csrc, "she_internal.hpp")) as f:
+        t = f.read()
+    for start in ("struct ParamsND {", "struct StepArg {"):
+        h.update(_section(t, start, "\n};\n").encode())
     return h.hexdigest()[:16]
 
 
