@@ -62,7 +62,7 @@ __device__ __forceinline__ T face_amp(int eq, T v, uint32_t &clamps)
         ++clamps;
         return T(0);
     }
-    return sqrt(q);
+    return amp_sqrt(q);
 }
 
 // Value of the last of the first `m` (1..4) entries, chosen among values
@@ -353,13 +353,13 @@ __device__ __forceinline__ void step1d_body(const Inst1D *__restrict__ tab, cons
                     } else if constexpr (K == 2) {
                         const bool neg = cf < T(0);
                         if (own && neg) ++clamps;
-                        const T am = neg ? T(0) : sqrt(cf);
+                        const T am = neg ? T(0) : amp_sqrt(cf);
                         F[l] = fma(sf * am, zz[l], rf * df);
                     } else {
                         const T q = cf * (T(1) - cf);
                         const bool neg = q < T(0);
                         if (own && neg) ++clamps;
-                        const T am = neg ? T(0) : sqrt(q);
+                        const T am = neg ? T(0) : amp_sqrt(q);
                         F[l] = fma(sf * am, zz[l], fma(-nu, q, rf * df));
                     }
                 }

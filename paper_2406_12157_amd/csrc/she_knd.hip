@@ -59,7 +59,7 @@ __device__ __forceinline__ T face_flux(T lo, T hi, T zs, T r, uint32_t &clamps)
                 ++clamps;
                 a = T(0);
             } else {
-                a = sqrt(s);
+                a = amp_sqrt(s);
             }
         }
         return fma(a, zs, r * d);

@@ -138,6 +138,12 @@ __device__ __forceinline__ void box_muller_scaled(uint32_t wa, uint32_t wb, doub
     zs = s * rc;
 }
 
+// Square root of a noise amplitude: FP32 takes the native v_sqrt_f32 (about
+// one ulp, one instruction; the library form adds a denormal-scaling and
+// rounding-correction sequence), FP64 the correctly rounded library sqrt.
+__device__ __forceinline__ float amp_sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+__device__ __forceinline__ double amp_sqrt(double x) { return sqrt(x); }
+
 template <typename T>
 __host__ __device__ inline T radius_const(double s);
 
