@@ -623,6 +623,37 @@ def test_literal_eps_diverges_and_freezes(she):
     h.close()
 
 
+def test_freeze_inside_a_shared_workgroup(she):
+    """The literal c1 instance (eps = 100) diverges and freezes at a sample
+    while a healthy rod shares its workgroup (256 threads: both packed in one).
+    The frozen instance's waves stop; the rod keeps stepping through the same
+    workgroup barriers and still matches the oracle, and the frozen field and
+    sample count equal those of the diverging instance run alone."""
+    bad = W.c1(eps=100.0)["instances"][0]
+    good = W.instance((96,), bc=W.DIRICHLET, scheme=W.HEUN, r=0.05, eps=1e-3, u0=1.0, u_left=1.1, u_right=0.9,
+                      init_sd=0.03, realisation=7)
+    steps = 20000
+    alone = she.Handle([gpu_instance(she, bad)], precision=1, burn_in=0, sample_every=10, stats=she.STAT_MOMENTS)
+    alone.run(steps)
+    s_alone = alone.stats(0, raise_nonfinite=False)
+    f_alone = alone.read_field(0)
+    alone.close()
+    assert s_alone["nonfinite"]
+    h = she.Handle([gpu_instance(she, bad), gpu_instance(she, good)], precision=1, burn_in=0, sample_every=10,
+                   stats=she.STAT_MOMENTS, block_threads=256)
+    init = h.read_field(1)
+    h.run(steps)
+    s_bad = h.stats(0, raise_nonfinite=False)
+    assert s_bad["nonfinite"] and s_bad["n_samples"] == s_alone["n_samples"] < steps // 10
+    np.testing.assert_array_equal(h.read_field(0), f_alone)
+    s_good = h.stats(1)
+    assert s_good["n_samples"] == steps // 10 and not s_good["nonfinite"]
+    u = init.copy()
+    oracle.advance(oracle_desc(good, 1), u, 0, steps)
+    assert max_rel(h.read_field(1), u) <= 1e-12
+    h.close()
+
+
 def test_write_field_roundtrip_and_noise_off_decay(she):
     n, r, k = 64, 0.2, 3
     inst = W.instance((n,), r=r, noise=2)
