@@ -73,6 +73,7 @@ struct she_handle {
     ParamsND pnd{};
     int64_t cells = 0;            // per instance
     void *d_a = nullptr, *d_b = nullptr;
+    void *d_pred = nullptr;       // 3D PC: predictor field
     int cur = 0;                  // 0: state in d_a
     uint32_t *d_real = nullptr;
     double *d_part = nullptr;
@@ -677,7 +678,8 @@ static she_status plan_nd(she_handle *h, const she_config *cfg, Plan &plan)
         const int gpb = 256 / LX;
         h->nd_blocks = (h->n_inst * nchunks + gpb - 1) / gpb;
     } else {
-        if (d0.scheme != SHE_EM) return fail(nullptr, SHE_EUNSUPPORTED, "3D kernel provides the FE scheme only");
+        if (d0.scheme != SHE_EM && d0.scheme != SHE_HEUN)
+            return fail(nullptr, SHE_EUNSUPPORTED, "3D provides the FE and PC schemes");
         int ty = cfg->rows_per_group;
         if (ty == 0) {
             ty = 1;
@@ -700,6 +702,7 @@ static she_status plan_nd(she_handle *h, const she_config *cfg, Plan &plan)
     const size_t fbytes = es * static_cast<size_t>(h->cells) * h->n_inst;
     plan.add(&h->d_a, fbytes);
     plan.add(&h->d_b, fbytes);
+    if (d0.dim == 3 && d0.scheme == SHE_HEUN) plan.add(&h->d_pred, fbytes);
     plan.add(reinterpret_cast<void **>(&h->d_real), sizeof(uint32_t) * h->n_inst);
     plan.add(reinterpret_cast<void **>(&h->d_part), 2 * sizeof(double) * h->nparts * h->n_inst);
     plan.add(reinterpret_cast<void **>(&h->d_step), sizeof(int64_t));
@@ -1010,9 +1013,19 @@ static hipError_t nd_enqueue(she_handle *h, hipStream_t s, const StepArg &sa, in
     if (h->dim == 2)
         e = launch_step2d(h->prec, h->cx, h->pnd.eq, h->pnd.scheme, h->nd_blocks, s, h->pnd, src, dst, sa, h->d_part,
                           h->d_acc);
-    else
-        e = launch_step3d(h->prec, h->cx, h->pnd.eq, h->ty, h->nd_blocks, h->smem3d, s, h->pnd, src, dst, sa,
-                          h->d_part, h->d_acc);
+    else if (h->pnd.scheme == SHE_EM)
+        e = launch_step3d(h->prec, h->cx, h->pnd.eq, 0, h->ty, h->nd_blocks, h->smem3d, s, h->pnd, src, nullptr, dst,
+                          sa, h->d_part, h->d_acc);
+    else {
+        // PC: predictor into the scratch field (no sampling), then the corrector
+        StepArg pa = sa;
+        pa.sample = 0;
+        e = launch_step3d(h->prec, h->cx, h->pnd.eq, 0, h->ty, h->nd_blocks, h->smem3d, s, h->pnd, src, nullptr,
+                          h->d_pred, pa, h->d_part, h->d_acc);
+        if (e == hipSuccess)
+            e = launch_step3d(h->prec, h->cx, h->pnd.eq, 1, h->ty, h->nd_blocks, h->smem3d, s, h->pnd, h->d_pred,
+                              src, dst, sa, h->d_part, h->d_acc);
+    }
     if (e != hipSuccess || !may_sample) return e;
     e = launch_reduce_parts(h->n_inst, s, sa, h->d_part, h->nparts, 1.0 / static_cast<double>(h->cells), h->d_acc);
     if (e != hipSuccess || !(h->mask & SHE_STAT_SK)) return e;

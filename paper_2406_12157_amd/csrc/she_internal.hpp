@@ -177,8 +177,10 @@ hipError_t launch_fin1d(int prec, hipStream_t s, const Inst1D *tab, int inst, in
 hipError_t launch_step2d(int prec, int cx, int eq, int scheme, int n_blocks, hipStream_t s,
                          const ParamsND &p, const void *src, void *dst, const StepArg &st,
                          double *part, InstAcc *acc);
-hipError_t launch_step3d(int prec, int cx, int eq, int ty, int n_blocks, size_t smem,
-                         hipStream_t s, const ParamsND &p, const void *src, void *dst,
+// stage 0: dst = src + Delta(src) (FE, or the PC predictor); stage 1: the PC
+// corrector dst = (base + src + Delta(src)) / 2 with src the predictor.
+hipError_t launch_step3d(int prec, int cx, int eq, int stage, int ty, int n_blocks, size_t smem,
+                         hipStream_t s, const ParamsND &p, const void *src, const void *base, void *dst,
                          const StepArg &st, double *part, InstAcc *acc);
 hipError_t launch_reduce_parts(int n_inst, hipStream_t s, const StepArg &st, const double *part,
                                int32_t nparts, double inv_cells, InstAcc *acc);

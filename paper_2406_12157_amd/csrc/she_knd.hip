@@ -29,6 +29,9 @@
 // barrier per plane, double-buffered); the tile's top row computes the flux
 // through its high y-face itself (one extra Philox call per plane for that
 // row).  z-neighbours stay in registers; the plane two ahead is prefetched.
+// PC runs as two passes of the same kernel: the predictor U* = U + Delta(U)
+// into a scratch field, then the corrector (U + U* + Delta(U*)) / 2, whose
+// numbers are drawn again from the same counters.
 //
 // Sample steps: every lane adds dU = U - u0 and dU^2 of its output cells in
 // FP64; the group / workgroup sum is written to a per-chunk partial; a small
@@ -377,12 +380,15 @@ __global__ void __launch_bounds__(256)
                           static_cast<unsigned long long>(clamps));
 }
 
-// ------------------------------------------------------------------ 3D (FE)
+// ------------------------------------------------------------------ 3D (FE; PC in two passes)
 
-template <typename T, int CX, int EQ>
+// STAGE 0: FE step (or a PC predictor) dst = src + Delta(src);
+// STAGE 1: PC corrector dst = (base + src + Delta(src)) / 2, with src the
+// predictor and base the state it was taken from (same step, same numbers).
+template <typename T, int CX, int EQ, int STAGE>
 __global__ void __launch_bounds__(256)
-    k_step3d(ParamsND p, int32_t ty, const T *__restrict__ src, T *__restrict__ dst, StepArg sarg,
-             double *__restrict__ part, InstAcc *__restrict__ acc)
+    k_step3d(ParamsND p, int32_t ty, const T *__restrict__ src, const T *__restrict__ base, T *__restrict__ dst,
+             StepArg sarg, double *__restrict__ part, InstAcc *__restrict__ acc)
 {
     int64_t step;
     int sample;
@@ -402,15 +408,17 @@ __global__ void __launch_bounds__(256)
     const int nx = p.nx, ny = p.ny, nz = p.nz;
     const int64_t vol = static_cast<int64_t>(nx) * ny * nz;
     const T *S = src + inst * vol + CX * lx;
+    const T *B = STAGE == 1 ? base + inst * vol + CX * lx : nullptr;
     T *D = dst + inst * vol + CX * lx;
     auto rowp = [&](int yy, int zz) {
         return static_cast<int64_t>(wrap(zz, nz) * ny + wrap(yy, ny)) * nx;
     };
 
-    if (acc[inst].nonfinite) {
+    if (acc[inst].nonfinite) {  // frozen: carry the state over unchanged
+        const T *F = STAGE == 1 ? B : S;
         for (int zz = z0; zz < z1; ++zz) {
             T v[CX];
-            load_row<T, CX>(S + rowp(y, zz), v);
+            load_row<T, CX>(F + rowp(y, zz), v);
             store_row<T, CX>(D + rowp(y, zz), v);
         }
         return;
@@ -509,9 +517,18 @@ __global__ void __launch_bounds__(256)
                 for (int j = 0; j < CX; ++j) fyhi[j] = flux(tc[j], yhi[j], z[j]);
             }
             T out[CX];
+            if constexpr (STAGE == 0) {
 #pragma unroll
-            for (int j = 0; j < CX; ++j)
-                out[j] = tc[j] + ((xdiv<T, CX>(fxlo, fxhi, j) + (fyhi[j] - fylo[j])) + (fzhi[j] - fzlo[j]));
+                for (int j = 0; j < CX; ++j)
+                    out[j] = tc[j] + ((xdiv<T, CX>(fxlo, fxhi, j) + (fyhi[j] - fylo[j])) + (fzhi[j] - fzlo[j]));
+            } else {
+                T ub[CX];
+                load_row<T, CX>(B + rowp(y, zi), ub);
+#pragma unroll
+                for (int j = 0; j < CX; ++j)
+                    out[j] = T(0.5) * ((ub[j] + tc[j]) +
+                                       ((xdiv<T, CX>(fxlo, fxhi, j) + (fyhi[j] - fylo[j])) + (fzhi[j] - fzlo[j])));
+            }
             if (sample) accumulate<T, CX>(out, u0d, sa, sb);
             store_row<T, CX>(D + rowp(y, zi), out);
         };
@@ -692,32 +709,45 @@ hipError_t launch_step2d(int prec, int cx, int eq, int scheme, int n_blocks, hip
     return step2d_c<double>(cx, eq, scheme, n_blocks, s, p, src, dst, sa, part, acc);
 }
 
-template <typename T, int CX>
-static hipError_t step3d_e(int eq, int ty, int n_blocks, size_t smem, hipStream_t s, const ParamsND &p,
-                           const void *src, void *dst, const StepArg &sa, double *part, InstAcc *acc)
+template <typename T, int CX, int EQ>
+static hipError_t step3d_s(int stage, int ty, int n_blocks, size_t smem, hipStream_t s, const ParamsND &p,
+                           const void *src, const void *base, void *dst, const StepArg &sa, double *part,
+                           InstAcc *acc)
 {
     const dim3 block((p.nx / CX) * ty);
-    if (eq == 0)
-        hipLaunchKernelGGL((k_step3d<T, CX, 0>), dim3(n_blocks), block, smem, s, p, ty, static_cast<const T *>(src),
-                           static_cast<T *>(dst), sa, part, acc);
+    if (stage == 0)
+        hipLaunchKernelGGL((k_step3d<T, CX, EQ, 0>), dim3(n_blocks), block, smem, s, p, ty,
+                           static_cast<const T *>(src), static_cast<const T *>(base), static_cast<T *>(dst), sa,
+                           part, acc);
     else
-        hipLaunchKernelGGL((k_step3d<T, CX, 1>), dim3(n_blocks), block, smem, s, p, ty, static_cast<const T *>(src),
-                           static_cast<T *>(dst), sa, part, acc);
+        hipLaunchKernelGGL((k_step3d<T, CX, EQ, 1>), dim3(n_blocks), block, smem, s, p, ty,
+                           static_cast<const T *>(src), static_cast<const T *>(base), static_cast<T *>(dst), sa,
+                           part, acc);
     return hipGetLastError();
 }
 
-hipError_t launch_step3d(int prec, int cx, int eq, int ty, int n_blocks, size_t smem, hipStream_t s,
-                         const ParamsND &p, const void *src, void *dst, const StepArg &sa, double *part,
-                         InstAcc *acc)
+template <typename T, int CX>
+static hipError_t step3d_e(int eq, int stage, int ty, int n_blocks, size_t smem, hipStream_t s, const ParamsND &p,
+                           const void *src, const void *base, void *dst, const StepArg &sa, double *part,
+                           InstAcc *acc)
+{
+    if (eq == 0) return step3d_s<T, CX, 0>(stage, ty, n_blocks, smem, s, p, src, base, dst, sa, part, acc);
+    return step3d_s<T, CX, 1>(stage, ty, n_blocks, smem, s, p, src, base, dst, sa, part, acc);
+}
+
+hipError_t launch_step3d(int prec, int cx, int eq, int stage, int ty, int n_blocks, size_t smem, hipStream_t s,
+                         const ParamsND &p, const void *src, const void *base, void *dst, const StepArg &sa,
+                         double *part, InstAcc *acc)
 {
     if (prec == 0) {
-        if (cx == 4) return step3d_e<float, 4>(eq, ty, n_blocks, smem, s, p, src, dst, sa, part, acc);
-        if (cx == 8) return step3d_e<float, 8>(eq, ty, n_blocks, smem, s, p, src, dst, sa, part, acc);
-        if (cx == 16) return step3d_e<float, 16>(eq, ty, n_blocks, smem, s, p, src, dst, sa, part, acc);
+        if (cx == 4) return step3d_e<float, 4>(eq, stage, ty, n_blocks, smem, s, p, src, base, dst, sa, part, acc);
+        if (cx == 8) return step3d_e<float, 8>(eq, stage, ty, n_blocks, smem, s, p, src, base, dst, sa, part, acc);
+        if (cx == 16) return step3d_e<float, 16>(eq, stage, ty, n_blocks, smem, s, p, src, base, dst, sa, part, acc);
     } else {
-        if (cx == 4) return step3d_e<double, 4>(eq, ty, n_blocks, smem, s, p, src, dst, sa, part, acc);
-        if (cx == 8) return step3d_e<double, 8>(eq, ty, n_blocks, smem, s, p, src, dst, sa, part, acc);
-        if (cx == 16) return step3d_e<double, 16>(eq, ty, n_blocks, smem, s, p, src, dst, sa, part, acc);
+        if (cx == 4) return step3d_e<double, 4>(eq, stage, ty, n_blocks, smem, s, p, src, base, dst, sa, part, acc);
+        if (cx == 8) return step3d_e<double, 8>(eq, stage, ty, n_blocks, smem, s, p, src, base, dst, sa, part, acc);
+        if (cx == 16)
+            return step3d_e<double, 16>(eq, stage, ty, n_blocks, smem, s, p, src, base, dst, sa, part, acc);
     }
     return hipErrorInvalidValue;
 }

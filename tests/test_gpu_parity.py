@@ -376,10 +376,10 @@ def test_2d_chunking_invariance(she):
 CASES_3D = [((16, 8, 8), W.SPECIES), ((32, 4, 6), W.HEAT), ((64, 8, 5), W.SPECIES), ((256, 4, 3), W.SPECIES)]
 
 
-def inst3d(n, eq, realisation=0):
+def inst3d(n, eq, realisation=0, scheme=W.EM):
     if eq == W.HEAT:
-        return W.instance(n, eq=eq, r=0.05, eps=1e-2, u0=1.0, init_sd=0.1, realisation=realisation)
-    return W.instance(n, eq=eq, r=0.05, eps=1.0, u0=1000.0, init_sd=31.6, realisation=realisation)
+        return W.instance(n, eq=eq, scheme=scheme, r=0.05, eps=1e-2, u0=1.0, init_sd=0.1, realisation=realisation)
+    return W.instance(n, eq=eq, scheme=scheme, r=0.05, eps=1.0, u0=1000.0, init_sd=31.6, realisation=realisation)
 
 
 @pytest.mark.parametrize("case", CASES_3D, ids=lambda c: "%dx%dx%d-eq%d" % (c[0] + c[1:]))
@@ -393,8 +393,35 @@ def test_3d_fp32_state_parity(she, case):
         assert err <= 1e-5, (q, err)
 
 
-def test_3d_tiling_invariance(she):
-    inst = inst3d((32, 8, 6), W.SPECIES)
+@pytest.mark.parametrize("case", CASES_3D, ids=lambda c: "%dx%dx%d-eq%d" % (c[0] + c[1:]))
+def test_3d_pc_state_parity(she, case):
+    # predictor-corrector: predictor pass into a scratch field, corrector pass
+    # drawing the same numbers again from the step's counters
+    n, eq = case
+    insts = [inst3d(n, eq, realisation=q, scheme=W.HEUN) for q in range(2)]
+    steps = 2000 if np.prod(n) <= 2048 else 300
+    _, got, want = run_both(she, insts, steps, 0, rows_per_block=3)
+    for q in range(2):
+        err = max_rel(got[q], want[q])
+        assert err <= 1e-5, (q, err)
+
+
+def test_3d_pc_fp64_parity_and_graph_replay(she):
+    inst = inst3d((16, 8, 8), W.SPECIES, scheme=W.HEUN)
+    _, got, want = run_both(she, [inst], 500, 1)
+    assert max_rel(got[0], want[0]) <= 1e-12
+    outs = []
+    for gs in (0, 8):
+        h = she.Handle([gpu_instance(she, inst)], precision=0, graph_steps=gs)
+        h.step(101)
+        outs.append(h.read_field(0))
+        h.close()
+    np.testing.assert_array_equal(outs[0], outs[1])
+
+
+@pytest.mark.parametrize("scheme", [W.EM, W.HEUN])
+def test_3d_tiling_invariance(she, scheme):
+    inst = inst3d((32, 8, 6), W.SPECIES, scheme=scheme)
     outs = []
     for rpb, rpg, fl in ((1, 1, 0), (4, 2, 0), (6, 8, 0), (2, 4, 0), (1, 2, she.TUNE_XCD_ORDER)):
         _, got, _ = run_both(she, [inst], 200, 0, rows_per_block=rpb, rows_per_group=rpg, tuning_flags=fl)
