@@ -38,8 +38,11 @@
 
 namespace she {
 
+// Aligned to its size, so that one lane's point moves in one 64-bit (FP32)
+// or 128-bit (FP64) LDS access; at the alignment of T every exchange store
+// and load splits into two, and the transforms are bound by the LDS.
 template <typename T>
-struct cplx {
+struct alignas(2 * sizeof(T)) cplx {
     T re, im;
 };
 
@@ -188,6 +191,18 @@ __device__ __forceinline__ void wave_fft(cplx<T> (&v)[WaveFft<LG>::P], cplx<T> *
     using F = WaveFft<LG>;
     constexpr int LR = PassRadix<REM>::LR, R = 1 << LR, B = F::P / R, n = F::n;
     constexpr int ls = LG - REM, s = 1 << ls;
+    // this pass's twiddles first, all of them: read between the region
+    // stores they would each wait for the stores before them
+    constexpr int NW = REM > LR ? R - 1 : 0;
+    cplx<T> wt[B][NW > 0 ? NW : 1];
+    if constexpr (NW > 0) {
+#pragma unroll
+        for (int i = 0; i < B; ++i) {
+            const int p = ((lane + 64 * i) & ((n >> LR) - 1)) >> ls;
+#pragma unroll
+            for (int k = 0; k < NW; ++k) wt[i][k] = tw[(tw_entries(LG) - tw_entries(REM)) + p * NW + k];
+        }
+    }
 #pragma unroll
     for (int i = 0; i < B; ++i) {
         const int b = lane + 64 * i;
@@ -201,8 +216,8 @@ __device__ __forceinline__ void wave_fft(cplx<T> (&v)[WaveFft<LG>::P], cplx<T> *
 #pragma unroll
         for (int k = 0; k < R; ++k) {
             cplx<T> o = a[k];
-            if constexpr (REM > LR) {
-                if (k > 0) o = cmul(o, tw[(tw_entries(LG) - tw_entries(REM)) + p * (R - 1) + (k - 1)]);
+            if constexpr (NW > 0) {
+                if (k > 0) o = cmul(o, wt[i][k - 1]);
             }
             buf[pidx(base + s * k)] = o;
         }
@@ -337,10 +352,12 @@ __global__ void __launch_bounds__(512)
 }
 
 // LDS bytes per wave of the column transform: its transform region and the
-// FP64 prefix sums of one column.
+// FP64 prefix sums of one column.  A wave that holds one column per
+// transform (S = 1) writes the prefix sums over that column once it has read
+// it, so they need no room of their own.
 constexpr int col_region(int es, int lg)
 {
-    return es * wave_lds(lg) + 8 * ((1 << lg) / 2 + 1);
+    return es * wave_lds(lg) + (wave_seqs(lg) == 1 ? 0 : 8 * ((1 << lg) / 2 + 1));
 }
 
 // Waves per block of the column transform: 4, or 2 where 4 regions and the
@@ -353,17 +370,23 @@ constexpr int col_waves(int es, int lg)
 constexpr int kMaxBinIters = 12;  // shells per lane: nbins <= 64 * 12
 
 // First |ky| of shell b in column kx, clipped to [0, hy + 1]: the smallest
-// m >= 0 with 4 (kx^2 + m^2) >= (2b - 1)^2 (b = 0: m = 0).  The single
-// precision root is within one of the answer; the integer tests settle it.
-__device__ __forceinline__ int shell_first(int kx, int b, int hy)
+// m >= 0 with 4 (kx^2 + m^2) >= (2b - 1)^2 (b = 0: m = 0), given kx4 = 4 kx^2.
+// The native single precision root is within one of the answer and the
+// integer tests settle it.  The factors are below 2^24 (b <= 768, m <= 769),
+// and masked to say so, which lets the products use 24-bit multiplies.
+__device__ __forceinline__ unsigned sq24(int v)
 {
-    if (b == 0) return 0;
-    const int need = (2 * b - 1) * (2 * b - 1) - 4 * kx * kx;
-    if (need <= 0) return 0;
-    int m = static_cast<int>(ceilf(0.5f * sqrtf(static_cast<float>(need))));
-    if (4 * m * m < need) ++m;
-    else if (m > 0 && 4 * (m - 1) * (m - 1) >= need) --m;
-    return min(m, hy + 1);
+    const unsigned u = static_cast<unsigned>(v) & 0xffffffu;
+    return u * u;
+}
+
+__device__ __forceinline__ int shell_first(int kx4, int b, int hy)
+{
+    const int need = static_cast<int>(sq24(2 * b - 1)) - kx4;
+    int m = static_cast<int>(ceilf(0.5f * __builtin_amdgcn_sqrtf(static_cast<float>(max(need, 0)))));
+    if (4 * static_cast<int>(sq24(m)) < need) ++m;
+    else if (m > 0 && 4 * static_cast<int>(sq24(m - 1)) >= need) --m;
+    return (b == 0 || need <= 0) ? 0 : min(m, hy + 1);
 }
 
 // Loads the column group of one wave iteration (S columns from `g`) in the
@@ -388,7 +411,8 @@ __device__ __forceinline__ void load_cols(cplx<T> (&v)[WaveFft<LGY>::P], const c
 // grid: (groups, n_inst); block 64 CW; wave w handles, in iteration it, the
 // S columns from cb + S (it CW + w).  LDS: pass twiddles, then
 // per wave `rs` bytes: the transform region, the FP64 prefix sums of one
-// column, and (after the loop) the wave's shell sums.
+// column (within the transform region when S = 1), and (after the loop) the
+// wave's shell sums.
 template <typename T, int LGY, int NBJ>
 __global__ void __launch_bounds__(256)
     k_sk_cols(StepArg sarg, const cplx<T> *__restrict__ half, int nx, int iters, int rs, int nbins,
@@ -404,7 +428,7 @@ __global__ void __launch_bounds__(256)
     unsigned char *regions = smem_raw + sizeof(cplx<T>) * F::tw;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     cplx<T> *buf = reinterpret_cast<cplx<T> *>(regions + static_cast<size_t>(wave) * rs);
-    double *pre = reinterpret_cast<double *>(buf + F::lds);
+    double *pre = S == 1 ? reinterpret_cast<double *>(buf) : reinterpret_cast<double *>(buf + F::lds);
     const int inst = blockIdx.y;
     const int nh = nx / 2 + 1;
     const int cb = blockIdx.x * (CW * S * iters);
@@ -427,42 +451,50 @@ __global__ void __launch_bounds__(256)
         wave_fft<T, LGY, LGY>(v, buf, tw, lane);
         for (int c = 0; c < S && g + c < nh; ++c) {
             const int kx = g + c;
-            const T w = (kx == 0 || 2 * kx == nx) ? T(1) : T(2);
+            // mirrored half of the spectrum: weight 2 off the kx = 0 and Nx/2
+            // columns, applied to the shell sums (an exact scaling)
+            const double w = (kx == 0 || 2 * kx == nx) ? 1.0 : 2.0;
             const cplx<T> *col = buf;
             const int cbase = c << LGY;
             double loc[per];
             double run = 0.0;
 #pragma unroll
             for (int j = 0; j < per; ++j) {
+                // power at |ky| = m: X(m), plus X(-m) for 0 < m < hy; m > hy is
+                // padding (both reads stay inside the column, masked after)
                 const int m = lane * per + j;
-                double e = 0.0;
-                if (m <= hy) {
-                    const cplx<T> a = col[pidx(cbase + m)];
-                    e = static_cast<double>(w * (a.re * a.re + a.im * a.im));
-                    if (m != 0 && m != hy) {
-                        const cplx<T> b = col[pidx(cbase + n - m)];
-                        e += static_cast<double>(w * (b.re * b.re + b.im * b.im));
-                    }
-                }
-                run += e;
+                const cplx<T> a = col[pidx(cbase + min(m, hy))];
+                const cplx<T> b = col[pidx(cbase + ((n - m) & (n - 1)))];
+                const T ea = m <= hy ? a.re * a.re + a.im * a.im : T(0);
+                const T eb = (m != 0 && m < hy) ? b.re * b.re + b.im * b.im : T(0);
+                run += static_cast<double>(ea) + static_cast<double>(eb);
                 loc[j] = run;
             }
             const double excl = wave_inclusive_sum(run) - run;
+            if (S == 1) wave_sync();  // the prefix sums overwrite the column just read
 #pragma unroll
             for (int j = 0; j < per; ++j) {
                 const int m = lane * per + j;
                 if (m <= hy) pre[m] = excl + loc[j];
             }
             wave_sync();
-            // shells met by this column: kx .. round(sqrt(kx^2 + hy^2)) (bound by excess)
+            // shells met by this column: kx .. round(sqrt(kx^2 + hy^2)) (bound by
+            // excess).  Lane b takes the end of its shell, first(b + 1); the start,
+            // first(b), is the end of lane b - 1 (a whole-wave shift by one lane),
+            // and for lane 0 the end of lane 63 in the previous group (0 for the
+            // first group met: its shells lie below kx).
+            const int kx4 = 4 * kx * kx;
             const int jlo = kx >> 6;
-            const int jhi = static_cast<int>(sqrtf(static_cast<float>(kx * kx + hy * hy)) + 1.5f) >> 6;
+            const int jhi = static_cast<int>(__builtin_amdgcn_sqrtf(static_cast<float>(kx * kx + hy * hy)) + 1.5f) >> 6;
+            int carry = 0;
 #pragma unroll
             for (int j = 0; j < NBJ; ++j) {
-                const int b = lane + 64 * j;
-                if (j >= jlo && j <= jhi && j < nbj && b < nbins) {
-                    const int m0 = shell_first(kx, b, hy), m1 = shell_first(kx, b + 1, hy);
-                    if (m1 > m0) acc[j] += pre[m1 - 1] - (m0 > 0 ? pre[m0 - 1] : 0.0);
+                if (j >= jlo && j <= jhi && j < nbj) {
+                    const int b = lane + 64 * j;
+                    const int m1 = shell_first(kx4, b + 1, hy);
+                    const int m0 = __builtin_amdgcn_update_dpp(carry, m1, 0x138, 0xf, 0xf, false);  // wave_shr:1
+                    carry = __builtin_amdgcn_readlane(m1, 63);
+                    if (b < nbins && m1 > m0) acc[j] += w * (pre[m1 - 1] - (m0 > 0 ? pre[m0 - 1] : 0.0));
                 }
             }
             wave_sync();

@@ -558,7 +558,7 @@ def test_nd_spatial_statistics_parity(she):
 
 
 @pytest.mark.parametrize("shape,precision", [((32, 16), 0), ((8, 32), 0), ((64, 64), 0), ((512, 8), 0),
-                                             ((16, 16), 1)])
+                                             ((16, 16), 1), ((1024, 8), 0), ((8, 1024), 0), ((16, 512), 1)])
 def test_2d_radial_structure_factor_parity(she, shape, precision):
     insts = [inst2d(shape, W.EM, W.HEAT, realisation=q) for q in range(2)]
     h = she.Handle([gpu_instance(she, i) for i in insts], precision=precision, burn_in=20, sample_every=2,
