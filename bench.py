@@ -31,6 +31,8 @@ METRIC = "cell-updates/s (incl. RNG) + % HBM roofline, batched FP32 vs plain, at
 HBM_PEAK_GBS = 8000.0
 KERNEL_SRC = os.path.join(ROOT, "paper_2406_12157_amd", "csrc", "she_knd.hip")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_step2d_c3.json")
+VALU_FILE = os.path.join(ROOT, "profiles", "valu_step2d_c3.json")
+PEAK_CLOCK_GHZ = 2.4
 
 
 def _section(text: str, start: str, end: str) -> str:
@@ -152,6 +154,29 @@ def read_traffic(cells_per_launch):
     return t.get("hbm_bytes_per_launch")
 
 
+def read_valu(kernel_ms, every):
+    """VALU occupancy of the 2D step kernel: the counted VALU quad-cycles per
+    launch (SQ_ACTIVE_INST_VALU from a committed counter pass, weighted by one
+    sample launch in `every`), as cycles per SIMD over the live kernel time at
+    the 2.4 GHz peak clock.  None once the kernel differs from the one
+    counted."""
+    try:
+        with open(VALU_FILE) as f:
+            v = json.load(f)
+    except Exception:
+        return None
+    if v.get("kernel_hash") != kernel_hash():
+        return None
+    q = v["valu_active_quad_cycles_per_launch"]
+    qs = v.get("sample_valu_active_quad_cycles_per_launch") or q
+    quads = ((every - 1) * q + qs) / every
+    cycles = quads * 4 / v["simds"]
+    return dict(active_cycles_per_simd=cycles, peak_clock_ghz=PEAK_CLOCK_GHZ,
+                frac=cycles / (PEAK_CLOCK_GHZ * 1e9 * kernel_ms * 1e-3),
+                clock_ghz_under_profiler=v.get("clock_ghz_under_profiler_median"),
+                source="profiles/valu_step2d_c3.json")
+
+
 def other_workload(args, torch, she, W):
     """Throughput of c1, c2, c4 or c5 with the statistics its configuration
     names, timed over `--steps` steps after `--warmup` (she_run, burn-in 0).
@@ -236,10 +261,11 @@ def main():
 
     bytes_per_launch = 8.0 * cells
     achieved = bytes_per_launch / (kms * 1e-3) / 1e9
-    traffic = read_traffic(cells)
+    traffic = read_traffic(cells) if args.scheme == "fe" else None  # counted on the FE kernel
     roofline = dict(bound="hbm", achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s", frac=achieved / HBM_PEAK_GBS,
                     traffic=traffic, kernel="k_step2d<float,8,heat,%s>" % args.scheme,
-                    kernel_ms=kms, kernel_launches_timed=nev, algorithmic_bytes_per_launch=bytes_per_launch)
+                    kernel_ms=kms, kernel_launches_timed=nev, algorithmic_bytes_per_launch=bytes_per_launch,
+                    valu=read_valu(kms, every) if args.scheme == "fe" else None)
 
     out = {"metric": METRIC, "value": value, "unit": "cell-updates/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
