@@ -50,6 +50,12 @@ def test_invalid_1d_configs(mutate, status):
     assert e.value.status == status
 
 
+def test_empty_batch_is_rejected():
+    with pytest.raises(she.SheError) as e:
+        she.Handle.arena_bytes([])
+    assert e.value.status == she.EINVAL
+
+
 def test_invalid_nd_configs():
     with pytest.raises(she.SheError) as e:
         she.Handle.arena_bytes([gpu_instance(she, W.instance((48, 16), r=0.1))])

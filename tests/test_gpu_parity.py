@@ -693,3 +693,27 @@ def test_write_field_roundtrip_and_noise_off_decay(she):
     g = 1 - 4 * r * np.sin(np.pi * k / n) ** 2
     np.testing.assert_allclose(h.read_field(0), 1.0 + 0.1 * g ** 50 * np.cos(2 * np.pi * k * x), atol=1e-13)
     h.close()
+
+
+@pytest.mark.parametrize("n", [(64,), (64, 32), (32, 16, 8)], ids=["1d", "2d", "3d"])
+@pytest.mark.parametrize("scheme", [W.EM, W.HEUN])
+@pytest.mark.parametrize("eq", [W.HEAT, W.SPECIES])
+def test_degenerate_parameters(she, n, scheme, eq):
+    """The degenerate cases of the scheme: r = 0 moves nothing (no flux, and
+    sigma = sqrt(2 r eps) = 0 leaves no noise), so the field stays bit for
+    bit; eps = 0 leaves the instant noise at zero, so a run follows the
+    noise-off run."""
+    u0, sd = (1.0, 0.05) if eq == W.HEAT else (100.0, 5.0)
+    base = dict(eq=eq, scheme=scheme, u0=u0, init_sd=sd, realisation=3)
+    h = she.Handle([gpu_instance(she, W.instance(n, r=0.0, eps=1e-2, **base))], precision=0)
+    f0 = h.read_field(0)
+    h.step(25)
+    np.testing.assert_array_equal(h.read_field(0), f0)
+    h.close()
+    runs = []
+    for kw in (dict(eps=0.0), dict(eps=1e-2, noise=2)):
+        h = she.Handle([gpu_instance(she, W.instance(n, r=0.1, **kw, **base))], precision=0)
+        h.step(40)
+        runs.append(h.read_field(0))
+        h.close()
+    np.testing.assert_allclose(runs[0], runs[1], rtol=1e-6, atol=0)
