@@ -58,22 +58,24 @@ def kernel_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def make_handle(she, cfg, stats):
+def make_handle(she, cfg, stats, tuning_flags=0):
     from paper_2406_12157_amd import workloads as W  # noqa: F401
     insts = [she.Instance(n=i["n"], eq=i["eq"], bc=i["bc"], scheme=i["scheme"], noise=i["noise"], r=i["r"],
                           eps=i["eps"], u0=i["u0"], u_left=i["u_left"], u_right=i["u_right"],
                           init_sd=i["init_sd"], seed=i["seed"], realisation=i["realisation"])
              for i in cfg["instances"]]
     return she.Handle(insts, precision=cfg["precision"], burn_in=0, sample_every=cfg["sample_every"],
-                      stats=stats), insts
+                      stats=stats, tuning_flags=tuning_flags), insts
 
 
 def timed_region(torch, h, steps, every):
     """Wall time of `steps` sampled steps (burn-in 0) and the HIP-event time of
     the step kernel inside them: each sampling period's run of back-to-back
-    non-sample steps is one call bracketed by events on the library's stream
-    (torch's current stream); the sample step follows unbracketed.  Returns
-    (wall seconds, kernel ms per launch, launches timed)."""
+    non-sample steps, an even number of them (2D FE takes two steps per
+    launch), is one call bracketed by events on the library's stream (torch's
+    current stream); the remaining one or two steps, ending with the sample
+    step, follow unbracketed.  Returns (wall seconds, kernel ms per step,
+    steps timed)."""
     ev = []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -81,6 +83,7 @@ def timed_region(torch, h, steps, every):
     while done < steps:
         r = (every - h.steps % every) % every      # steps until the next sample step completes
         plain = min(steps - done, (r if r > 0 else every) - 1)
+        plain -= plain % 2
         if plain > 0:
             a = torch.cuda.Event(enable_timing=True)
             b = torch.cuda.Event(enable_timing=True)
@@ -90,8 +93,9 @@ def timed_region(torch, h, steps, every):
             ev.append((a, b, plain))
             done += plain
         if done < steps:
-            h.run(1)
-            done += 1
+            rest = min(steps - done, (r if r > 0 else every) - plain)
+            h.run(rest)
+            done += rest
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     n = sum(k for _, _, k in ev)
@@ -154,12 +158,12 @@ def read_traffic(cells_per_launch):
     return t.get("hbm_bytes_per_launch")
 
 
-def read_valu(kernel_ms, every):
+def read_valu(kernel_ms, per_period):
     """VALU occupancy of the 2D step kernel: the counted VALU quad-cycles per
     launch (SQ_ACTIVE_INST_VALU from a committed counter pass, weighted by one
-    sample launch in `every`), as cycles per SIMD over the live kernel time at
-    the 2.4 GHz peak clock.  None once the kernel differs from the one
-    counted."""
+    sample launch in the `per_period` launches of a sampling period), as
+    cycles per SIMD over the live launch time at the 2.4 GHz peak clock.
+    None once the kernel differs from the one counted."""
     try:
         with open(VALU_FILE) as f:
             v = json.load(f)
@@ -169,7 +173,7 @@ def read_valu(kernel_ms, every):
         return None
     q = v["valu_active_quad_cycles_per_launch"]
     qs = v.get("sample_valu_active_quad_cycles_per_launch") or q
-    quads = ((every - 1) * q + qs) / every
+    quads = ((per_period - 1) * q + qs) / per_period
     cycles = quads * 4 / v["simds"]
     return dict(active_cycles_per_simd=cycles, peak_clock_ghz=PEAK_CLOCK_GHZ,
                 frac=cycles / (PEAK_CLOCK_GHZ * 1e9 * kernel_ms * 1e-3),
@@ -259,13 +263,18 @@ def main():
     value = cells * args.steps / wall
     ms_per_step = wall / args.steps * 1e3
 
-    bytes_per_launch = 8.0 * cells
-    achieved = bytes_per_launch / (kms * 1e-3) / 1e9
+    # FE runs two steps per launch (every sampling period here is even), PC one;
+    # the algorithmic bytes are 8 B per cell-update either way
+    per_launch = 2 if args.scheme == "fe" else 1
+    launch_ms = kms * per_launch
+    bytes_per_launch = 8.0 * cells * per_launch
+    achieved = bytes_per_launch / (launch_ms * 1e-3) / 1e9
     traffic = read_traffic(cells) if args.scheme == "fe" else None  # counted on the FE kernel
     roofline = dict(bound="hbm", achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s", frac=achieved / HBM_PEAK_GBS,
-                    traffic=traffic, kernel="k_step2d<float,8,heat,%s>" % args.scheme,
-                    kernel_ms=kms, kernel_launches_timed=nev, algorithmic_bytes_per_launch=bytes_per_launch,
-                    valu=read_valu(kms, every) if args.scheme == "fe" else None)
+                    traffic=traffic, kernel="k_step2d<float,8,heat,%s>" % ("fe x2" if per_launch == 2 else args.scheme),
+                    kernel_ms=launch_ms, kernel_launches_timed=nev // per_launch,
+                    cell_updates_per_launch=cells * per_launch, algorithmic_bytes_per_launch=bytes_per_launch,
+                    valu=read_valu(launch_ms, every // per_launch) if args.scheme == "fe" else None)
 
     out = {"metric": METRIC, "value": value, "unit": "cell-updates/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
@@ -277,7 +286,7 @@ def main():
 
     if not args.no_plain:
         pcfg = W.c3(realisations=1, scheme=scheme)
-        ph, pinsts = make_handle(she, pcfg, she.STAT_SPATIAL | she.STAT_SK)
+        ph, pinsts = make_handle(she, pcfg, she.STAT_SPATIAL | she.STAT_SK, tuning_flags=she.TUNE_SINGLE_STEP)
         ph.run(args.warmup)
         psteps = max(200, args.steps // 2)
         pwall, pkms, _ = timed_region(torch, ph, psteps, every)

@@ -96,8 +96,13 @@ enum {
                                      workgroups (neighbouring chunks share an
                                      L2) instead of the plain order; measured
                                      no faster on MI355X, so off by default   */
-    SHE_TUNE_SEARCH = 2           /* she_create runs she_tune first and uses
+    SHE_TUNE_SEARCH = 2,          /* she_create runs she_tune first and uses
                                      its choice (not with an arena)          */
+    SHE_TUNE_SINGLE_STEP = 4      /* 2D FE: one step per launch.  By default
+                                     direct (not graph-replayed) steps go two
+                                     per launch wherever the first of the two
+                                     does not sample, the intermediate field
+                                     kept on chip; results are the same bits */
 };
 
 /* One instance (realisation) of the scheme.  Dirichlet walls only in 1D. */

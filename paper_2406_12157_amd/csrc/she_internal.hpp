@@ -174,6 +174,8 @@ hipError_t launch_fin1d(int prec, hipStream_t s, const Inst1D *tab, int inst, in
                         const double *c, int64_t n_samples, int partial_rows, bool corr,
                         double *out);
 
+// scheme: 0 FE, 1 PC, 2 two FE steps in one pass (steps st.step and
+// st.step + 1; the spatial partials are those of the second)
 hipError_t launch_step2d(int prec, int cx, int eq, int scheme, int n_blocks, hipStream_t s,
                          const ParamsND &p, const void *src, void *dst, const StepArg &st,
                          double *part, InstAcc *acc);

@@ -205,6 +205,8 @@ __global__ void __launch_bounds__(256)
     const uint32_t real = p.realisation[inst];
     const PhiloxKey key = make_key(p.seed);
     const uint32_t slo = static_cast<uint32_t>(step), w2 = ctr_word2(static_cast<uint64_t>(step), 0u);
+    // counter words of the following step (the second stage of a two-step march)
+    const uint32_t slo1 = static_cast<uint32_t>(step + 1), w21 = ctr_word2(static_cast<uint64_t>(step + 1), 0u);
     const uint32_t nq = static_cast<uint32_t>(p.nx / 4), q0 = static_cast<uint32_t>((CX / 4) * lx);
     const int ny = p.ny;
     auto rowp = [&](int y) { return S + static_cast<int64_t>(wrap(y, ny)) * p.nx; };
@@ -306,6 +308,71 @@ __global__ void __launch_bounds__(256)
                     for (int j = 0; j < CX; ++j) out[j] = tc[j] + (xdiv<T, CX>(fx, fxh, j) + (fhi[j] - flo[j]));
                     emit(out, y);
                 });
+            }
+        } else if constexpr (SCHEME == 2) {
+            // Two FE steps in one pass (steps n and n+1 of the counter): the
+            // intermediate field U1 lives only in registers.  Iteration k forms
+            // row k of U1 = FE(U0) and row k-1 of U2 = FE(U1), with the same
+            // face and update expressions as the one-step march, so U2 is the
+            // field two single steps give, bit for bit.  tc, tn: U0 rows k,
+            // k+1, tq receiving row k+2; sc, sn: U1 rows k-1, k; fpc, fpn: the
+            // step-n low-y fluxes of rows k, k+1; fcm, fcc: the step-(n+1)
+            // low-y fluxes of U1 rows k-1, k.  Each chunk recomputes the U1
+            // rows on both sides of it.
+            auto normals1 = [&](T (&z)[CX], uint32_t dr) __attribute__((always_inline)) {
+                row_normals<T, CX, NZ>(z, dr, nq, q0, slo1, w21, real, key, rc);
+            };
+            T ta[CX], tb[CX], tcc[CX], sa_[CX], sb_[CX], pa[CX], pb[CX], ma[CX], mb[CX];
+            const int k0 = y0 - 1;
+            {
+                T tp[CX], z[CX];
+                load_row<T, CX>(rowp(k0 - 1), tp);
+                load_row<T, CX>(rowp(k0), ta);
+                load_row<T, CX>(rowp(k0 + 1), tb);
+                normals(z, drow(k0, 1));
+#pragma unroll
+                for (int j = 0; j < CX; ++j) pa[j] = flux(tp[j], ta[j], z[j]);
+            }
+            auto row = [&](const T (&tc)[CX], const T (&tn)[CX], T (&tq)[CX], const T (&sc)[CX], T (&sn)[CX],
+                           const T (&fpc)[CX], T (&fpn)[CX], const T (&fcm)[CX], T (&fcc)[CX],
+                           int i) __attribute__((always_inline)) {
+                const int k = k0 + i;
+                load_row<T, CX>(rowp(k + 2), tq);
+                T z[CX], fx[CX], fxh;
+                normals(z, drow(k + 1, 1));
+#pragma unroll
+                for (int j = 0; j < CX; ++j) fpn[j] = flux(tc[j], tn[j], z[j]);
+                normals(z, drow(k, 0));
+                xflux(tc, z, fx, fxh);
+#pragma unroll
+                for (int j = 0; j < CX; ++j) sn[j] = tc[j] + (xdiv<T, CX>(fx, fxh, j) + (fpn[j] - fpc[j]));
+                if (i >= 1) {
+                    normals1(z, drow(k, 1));
+#pragma unroll
+                    for (int j = 0; j < CX; ++j) fcc[j] = flux(sc[j], sn[j], z[j]);
+                }
+                if (i >= 2) {
+                    normals1(z, drow(k - 1, 0));
+                    xflux(sc, z, fx, fxh);
+                    T out[CX];
+#pragma unroll
+                    for (int j = 0; j < CX; ++j) out[j] = sc[j] + (xdiv<T, CX>(fx, fxh, j) + (fcc[j] - fcm[j]));
+                    emit(out, k - 1);
+                }
+            };
+            const int iters = rows + 2;  // k = y0-1 .. y1
+            for (int i = 0; i < iters; i += 6) {
+                row(ta, tb, tcc, sa_, sb_, pa, pb, ma, mb, i);
+                if (i + 1 >= iters) break;
+                row(tb, tcc, ta, sb_, sa_, pb, pa, mb, ma, i + 1);
+                if (i + 2 >= iters) break;
+                row(tcc, ta, tb, sa_, sb_, pa, pb, ma, mb, i + 2);
+                if (i + 3 >= iters) break;
+                row(ta, tb, tcc, sb_, sa_, pb, pa, mb, ma, i + 3);
+                if (i + 4 >= iters) break;
+                row(tb, tcc, ta, sa_, sb_, pa, pb, ma, mb, i + 4);
+                if (i + 5 >= iters) break;
+                row(tcc, ta, tb, sb_, sa_, pb, pa, mb, ma, i + 5);
             }
         } else {
             // Predictor-corrector.  Iteration k produces the predictor row k and
@@ -676,8 +743,11 @@ static hipError_t step2d_s(int scheme, int n_blocks, hipStream_t s, const Params
     if (scheme == 0)
         hipLaunchKernelGGL((k_step2d<T, CX, EQ, 0>), dim3(n_blocks), dim3(256), 0, s, p,
                            static_cast<const T *>(src), static_cast<T *>(dst), sa, part, acc);
-    else
+    else if (scheme == 1)
         hipLaunchKernelGGL((k_step2d<T, CX, EQ, 1>), dim3(n_blocks), dim3(256), 0, s, p,
+                           static_cast<const T *>(src), static_cast<T *>(dst), sa, part, acc);
+    else
+        hipLaunchKernelGGL((k_step2d<T, CX, EQ, 2>), dim3(n_blocks), dim3(256), 0, s, p,
                            static_cast<const T *>(src), static_cast<T *>(dst), sa, part, acc);
     return hipGetLastError();
 }

@@ -24,6 +24,7 @@ F32, F64 = 0, 1
 STAT_MOMENTS, STAT_CORR, STAT_SK, STAT_SPATIAL, STAT_TCORR = 1, 2, 4, 8, 16
 TUNE_XCD_ORDER = 1
 TUNE_SEARCH = 2
+TUNE_SINGLE_STEP = 4
 
 OK, EINVAL, EUNSTABLE, ENOMEM, EDEVICE, ENONFINITE, ESTATE, EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6, -7
 _NAMES = {0: "SHE_OK", -1: "SHE_EINVAL", -2: "SHE_EUNSTABLE", -3: "SHE_ENOMEM", -4: "SHE_EDEVICE",

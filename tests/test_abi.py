@@ -50,6 +50,16 @@ def test_invalid_1d_configs(mutate, status):
     assert e.value.status == status
 
 
+def test_grids_too_small_for_the_marches_are_rejected():
+    # 2D PC reads two rows beyond a march chunk, 3D one plane beyond the next
+    for inst in (W.instance((64, 2), r=0.1, scheme=W.HEUN), W.instance((32, 8, 1), r=0.1)):
+        with pytest.raises(she.SheError) as e:
+            she.Handle.arena_bytes([gpu_instance(she, inst)])
+        assert e.value.status == she.EUNSUPPORTED
+    she.Handle.arena_bytes([gpu_instance(she, W.instance((64, 2), r=0.1))])       # 2D FE: one step per launch
+    she.Handle.arena_bytes([gpu_instance(she, W.instance((64, 3), r=0.1, scheme=W.HEUN))])
+
+
 def test_empty_batch_is_rejected():
     with pytest.raises(she.SheError) as e:
         she.Handle.arena_bytes([])
@@ -75,7 +85,7 @@ def test_invalid_nd_configs():
 
 def test_invalid_tuning_and_graph_settings():
     insts = [gpu_instance(she, W.instance((64, 64), r=0.1))]
-    for kw in (dict(tuning_flags=4), dict(graph_steps=-1), dict(graph_steps=(1 << 16) + 1)):
+    for kw in (dict(tuning_flags=8), dict(graph_steps=-1), dict(graph_steps=(1 << 16) + 1)):
         with pytest.raises(she.SheError) as e:
             she.Handle.arena_bytes(insts, **kw)
         assert e.value.status == she.EINVAL, kw

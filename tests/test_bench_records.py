@@ -17,13 +17,13 @@ def test_valu_record_scales_counted_cycles_to_the_live_kernel_time(tmp_path, mon
            "sample_valu_active_quad_cycles_per_launch": 1024 * 70000.0, "simds": 1024,
            "clock_ghz_under_profiler_median": 2.3}
     monkeypatch.setattr(bench, "VALU_FILE", _write(tmp_path, "v.json", rec))
-    v = bench.read_valu(kernel_ms=0.1, every=10)
+    v = bench.read_valu(kernel_ms=0.1, per_period=10)
     # one sample launch in ten: 61000 quad-cycles = 244000 cycles per SIMD
     assert v["active_cycles_per_simd"] == 244000.0
     assert abs(v["frac"] - 244000.0 / (2.4e9 * 1e-4)) < 1e-12
     rec["kernel_hash"] = "0" * 16
     monkeypatch.setattr(bench, "VALU_FILE", _write(tmp_path, "w.json", rec))
-    assert bench.read_valu(kernel_ms=0.1, every=10) is None
+    assert bench.read_valu(kernel_ms=0.1, per_period=10) is None
 
 
 def test_traffic_record_is_dropped_when_the_kernel_changed(tmp_path, monkeypatch):

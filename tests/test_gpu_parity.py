@@ -373,6 +373,33 @@ def test_2d_chunking_invariance(she):
             np.testing.assert_array_equal(o, outs[0])
 
 
+def test_two_step_launches_match_single_steps(she):
+    """2D FE steps go two per launch by default (the intermediate field stays
+    on chip) and give the bits of one step per launch (SHE_TUNE_SINGLE_STEP):
+    heat and species, FP32 and FP64, ragged march chunks, odd and even step
+    counts, and an odd sampling period, so that paired and single launches
+    mix and a sample falls on either step of a pair."""
+    for eq, prec, rpb in ((W.HEAT, 0, 0), (W.SPECIES, 0, 12), (W.HEAT, 1, 5), (W.HEAT, 0, 32)):
+        insts = [inst2d((64, 32), W.EM, eq, realisation=q) for q in range(3)]
+        kw = dict(precision=prec, burn_in=7, sample_every=3, stats=she.STAT_SPATIAL | she.STAT_SK,
+                  rows_per_block=rpb)
+        a = she.Handle([gpu_instance(she, i) for i in insts], tuning_flags=she.TUNE_SINGLE_STEP, **kw)
+        b = she.Handle([gpu_instance(she, i) for i in insts], **kw)
+        for op in (("run", 1), ("run", 40), ("step", 5), ("run", 33), ("step", 2), ("run", 9)):
+            getattr(a, op[0])(op[1])
+            getattr(b, op[0])(op[1])
+            for q in (0, 2):
+                np.testing.assert_array_equal(a.read_field(q), b.read_field(q))
+        for q in range(3):
+            ga, gb = a.stats(q, sk=True), b.stats(q, sk=True)
+            assert ga["n_samples"] == gb["n_samples"] == 25
+            for key in ("mean", "var", "sk"):
+                np.testing.assert_array_equal(ga[key], gb[key])
+            assert ga["sum_u"] == gb["sum_u"]
+        a.close()
+        b.close()
+
+
 CASES_3D = [((16, 8, 8), W.SPECIES), ((32, 4, 6), W.HEAT), ((64, 8, 5), W.SPECIES), ((256, 4, 3), W.SPECIES)]
 
 
