@@ -42,15 +42,18 @@ def _section(text: str, start: str, end: str) -> str:
 
 def kernel_hash() -> str:
     """Hash of what decides the 2D step kernel's HBM traffic: its source, the
-    noise header, the host function that picks its launch shape (plan_nd) and
-    the parameter structs it takes; edits elsewhere leave it unchanged."""
+    noise header, the host functions that pick its launch shapes (plan_nd,
+    and build_plan for the two-step march) and the parameter structs it
+    takes; edits elsewhere leave it unchanged."""
     csrc = os.path.join(ROOT, "paper_2406_12157_amd", "csrc")
     h = hashlib.sha256()
     for name in ("she_knd.hip", "she_rng.hpp"):
         with open(os.path.join(csrc, name), "rb") as f:
             h.update(f.read())
     with open(os.path.join(csrc, "she_capi.hip")) as f:
-        h.update(_section(f.read(), "static she_status plan_nd(", "\n}\n").encode())
+        t = f.read()
+    for start in ("static she_status plan_nd(", "static she_status build_plan("):
+        h.update(_section(t, start, "\n}\n").encode())
     with open(os.path.join(csrc, "she_internal.hpp")) as f:
         t = f.read()
     for start in ("struct ParamsND {", "struct StepArg {"):
@@ -159,11 +162,13 @@ def read_traffic(cells_per_launch):
 
 
 def read_valu(kernel_ms, per_period):
-    """VALU occupancy of the 2D step kernel: the counted VALU quad-cycles per
-    launch (SQ_ACTIVE_INST_VALU from a committed counter pass, weighted by one
-    sample launch in the `per_period` launches of a sampling period), as
-    cycles per SIMD over the live launch time at the 2.4 GHz peak clock.
-    None once the kernel differs from the one counted."""
+    """VALU issue of the 2D step kernel: the VALU instructions one launch
+    executes (SQ_INSTS_VALU from a committed counter pass, weighted by one
+    sample launch in the `per_period` launches of a sampling period), at four
+    cycles per wave64 instruction, as cycles per SIMD over the live launch
+    time at the 2.4 GHz peak clock.  A lower bound on the VALU's busy share:
+    transcendental and 64-bit integer instructions hold it longer.  None once
+    the kernel differs from the one counted."""
     try:
         with open(VALU_FILE) as f:
             v = json.load(f)
@@ -171,14 +176,12 @@ def read_valu(kernel_ms, per_period):
         return None
     if v.get("kernel_hash") != kernel_hash():
         return None
-    q = v["valu_active_quad_cycles_per_launch"]
-    qs = v.get("sample_valu_active_quad_cycles_per_launch") or q
-    quads = ((per_period - 1) * q + qs) / per_period
-    cycles = quads * 4 / v["simds"]
-    return dict(active_cycles_per_simd=cycles, peak_clock_ghz=PEAK_CLOCK_GHZ,
-                frac=cycles / (PEAK_CLOCK_GHZ * 1e9 * kernel_ms * 1e-3),
-                clock_ghz_under_profiler=v.get("clock_ghz_under_profiler_median"),
-                source="profiles/valu_step2d_c3.json")
+    q = v["valu_insts_per_launch"]
+    qs = v.get("sample_valu_insts_per_launch") or q
+    insts = ((per_period - 1) * q + qs) / per_period
+    cycles = insts * 4 / v["simds"]
+    return dict(insts_per_launch=insts, issue_cycles_per_simd=cycles, peak_clock_ghz=PEAK_CLOCK_GHZ,
+                frac=cycles / (PEAK_CLOCK_GHZ * 1e9 * kernel_ms * 1e-3), source="profiles/valu_step2d_c3.json")
 
 
 def other_workload(args, torch, she, W):

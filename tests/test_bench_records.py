@@ -12,14 +12,13 @@ def _write(tmp_path, name, rec):
     return str(p)
 
 
-def test_valu_record_scales_counted_cycles_to_the_live_kernel_time(tmp_path, monkeypatch):
-    rec = {"kernel_hash": bench.kernel_hash(), "valu_active_quad_cycles_per_launch": 1024 * 60000.0,
-           "sample_valu_active_quad_cycles_per_launch": 1024 * 70000.0, "simds": 1024,
-           "clock_ghz_under_profiler_median": 2.3}
+def test_valu_record_scales_counted_instructions_to_the_live_kernel_time(tmp_path, monkeypatch):
+    rec = {"kernel_hash": bench.kernel_hash(), "valu_insts_per_launch": 1024 * 60000.0,
+           "sample_valu_insts_per_launch": 1024 * 70000.0, "simds": 1024}
     monkeypatch.setattr(bench, "VALU_FILE", _write(tmp_path, "v.json", rec))
     v = bench.read_valu(kernel_ms=0.1, per_period=10)
-    # one sample launch in ten: 61000 quad-cycles = 244000 cycles per SIMD
-    assert v["active_cycles_per_simd"] == 244000.0
+    # one sample launch in ten: 61000 wave64 instructions per SIMD, 4 cycles each
+    assert v["issue_cycles_per_simd"] == 244000.0
     assert abs(v["frac"] - 244000.0 / (2.4e9 * 1e-4)) < 1e-12
     rec["kernel_hash"] = "0" * 16
     monkeypatch.setattr(bench, "VALU_FILE", _write(tmp_path, "w.json", rec))
