@@ -47,10 +47,13 @@ namespace she {
 // pre-scaled number zs (see above), in noise mode NZ (0 instantaneous,
 // 1 deterministic face value, 2 off).
 template <typename T, int EQ, int NZ>
-__device__ __forceinline__ T face_flux(T lo, T hi, T zs, T r, uint32_t &clamps)
+__device__ __forceinline__ T face_flux(T lo, T hi, T zs, uint32_t &clamps)
 {
-    // the multiply-adds are written out so that every copy of this code
-    // rounds alike: a face computed in two places gets one value
+    // The face flux divided by r: the difference hi - lo plus the noise term,
+    // whose scale carries 1/r (the caller multiplies the divergence by r once
+    // per cell, which saves a multiply per face).  The multiply-add is written
+    // out so that every copy of this code rounds alike: a face computed in two
+    // places gets one value.
     const T d = hi - lo;
     if constexpr (NZ == 0) {
         const T s = lo + hi;
@@ -65,12 +68,20 @@ __device__ __forceinline__ T face_flux(T lo, T hi, T zs, T r, uint32_t &clamps)
                 a = amp_sqrt(s);
             }
         }
-        return fma(a, zs, r * d);
+        return fma(a, zs, d);
     } else if constexpr (NZ == 1) {
-        return fma(r, d, zs);
+        return d + zs;
     } else {
-        return r * d;
+        return d;
     }
+}
+
+// Box-Muller radius constant of the normals a face flux takes: the noise
+// scale over r (the fluxes are carried divided by r; r = 0 has no noise).
+template <typename T>
+__device__ __forceinline__ T flux_radius(const ParamsND &p)
+{
+    return radius_const<T>(p.r > 0.0 ? p.ns / p.r : 0.0);
 }
 
 __device__ __forceinline__ int wrap(int i, int n)
@@ -122,16 +133,16 @@ __device__ __forceinline__ void row_normals(T (&z)[CX], uint32_t drow, uint32_t 
 // last cell (= the next lane's Flo[0]).
 template <typename T, int CX, int EQ, int NZ>
 __device__ __forceinline__ void row_xflux(const T (&v)[CX], const T (&z)[CX], T (&Flo)[CX], T &Fhi, int lx, int LX,
-                                          T r, uint32_t &clamps)
+                                          uint32_t &clamps)
 {
     const int lane = threadIdx.x & 63;
     const int gbase = lane - lx;
     const int left = gbase + (lx == 0 ? LX - 1 : lx - 1);
     const int right = gbase + (lx == LX - 1 ? 0 : lx + 1);
     const T vleft = __shfl(v[CX - 1], left, 64);
-    Flo[0] = face_flux<T, EQ, NZ>(vleft, v[0], z[0], r, clamps);
+    Flo[0] = face_flux<T, EQ, NZ>(vleft, v[0], z[0], clamps);
 #pragma unroll
-    for (int j = 1; j < CX; ++j) Flo[j] = face_flux<T, EQ, NZ>(v[j - 1], v[j], z[j], r, clamps);
+    for (int j = 1; j < CX; ++j) Flo[j] = face_flux<T, EQ, NZ>(v[j - 1], v[j], z[j], clamps);
     Fhi = __shfl(Flo[0], right, 64);
 }
 
@@ -199,7 +210,7 @@ __global__ void __launch_bounds__(256)
     }
 
     const T r = static_cast<T>(p.r);
-    const T rc = radius_const<T>(p.ns);
+    const T rc = flux_radius<T>(p);
     uint32_t clamps = 0;
     const int noise = p.noise;
     const uint32_t real = p.realisation[inst];
@@ -225,10 +236,10 @@ __global__ void __launch_bounds__(256)
             row_normals<T, CX, NZ>(z, dr, nq, q0, slo, w2, real, key, rc);
         };
         auto flux = [&](T lo, T hi, T z) __attribute__((always_inline)) {
-            return face_flux<T, EQ, NZ>(lo, hi, z, r, clamps);
+            return face_flux<T, EQ, NZ>(lo, hi, z, clamps);
         };
         auto xflux = [&](const T (&v)[CX], const T (&z)[CX], T (&fx)[CX], T &fxh) __attribute__((always_inline)) {
-            row_xflux<T, CX, EQ, NZ>(v, z, fx, fxh, lx, LX, r, clamps);
+            row_xflux<T, CX, EQ, NZ>(v, z, fx, fxh, lx, LX, clamps);
         };
         auto emit = [&](const T (&out)[CX], int y) __attribute__((always_inline)) {
             if (sample) accumulate<T, CX>(out, u0d, sa, sb);
@@ -276,7 +287,7 @@ __global__ void __launch_bounds__(256)
                     normals(z, drow(y, 0));
                     xflux(tc, z, fx, fxh);
 #pragma unroll
-                    for (int j = 0; j < CX; ++j) out[j] = tc[j] + (xdiv<T, CX>(fx, fxh, j) + (fhi[j] - flo[j]));
+                    for (int j = 0; j < CX; ++j) out[j] = fma(r, xdiv<T, CX>(fx, fxh, j) + (fhi[j] - flo[j]), tc[j]);
                     emit(out, y);
                 });
             } else {
@@ -305,7 +316,7 @@ __global__ void __launch_bounds__(256)
                     normals(z, drow(y, 0));
                     xflux(tc, z, fx, fxh);
 #pragma unroll
-                    for (int j = 0; j < CX; ++j) out[j] = tc[j] + (xdiv<T, CX>(fx, fxh, j) + (fhi[j] - flo[j]));
+                    for (int j = 0; j < CX; ++j) out[j] = fma(r, xdiv<T, CX>(fx, fxh, j) + (fhi[j] - flo[j]), tc[j]);
                     emit(out, y);
                 });
             }
@@ -345,7 +356,7 @@ __global__ void __launch_bounds__(256)
                 normals(z, drow(k, 0));
                 xflux(tc, z, fx, fxh);
 #pragma unroll
-                for (int j = 0; j < CX; ++j) sn[j] = tc[j] + (xdiv<T, CX>(fx, fxh, j) + (fpn[j] - fpc[j]));
+                for (int j = 0; j < CX; ++j) sn[j] = fma(r, xdiv<T, CX>(fx, fxh, j) + (fpn[j] - fpc[j]), tc[j]);
                 if (i >= 1) {
                     normals1(z, drow(k, 1));
 #pragma unroll
@@ -356,7 +367,7 @@ __global__ void __launch_bounds__(256)
                     xflux(sc, z, fx, fxh);
                     T out[CX];
 #pragma unroll
-                    for (int j = 0; j < CX; ++j) out[j] = sc[j] + (xdiv<T, CX>(fx, fxh, j) + (fcc[j] - fcm[j]));
+                    for (int j = 0; j < CX; ++j) out[j] = fma(r, xdiv<T, CX>(fx, fxh, j) + (fcc[j] - fcm[j]), sc[j]);
                     emit(out, k - 1);
                 }
             };
@@ -403,7 +414,7 @@ __global__ void __launch_bounds__(256)
                 T fx[CX], fxh;
                 xflux(tc, zxc, fx, fxh);
 #pragma unroll
-                for (int j = 0; j < CX; ++j) sn[j] = tc[j] + (xdiv<T, CX>(fx, fxh, j) + (fpn[j] - fpc[j]));
+                for (int j = 0; j < CX; ++j) sn[j] = fma(r, xdiv<T, CX>(fx, fxh, j) + (fpn[j] - fpc[j]), tc[j]);
                 if (i >= 1) {
 #pragma unroll
                     for (int j = 0; j < CX; ++j) fcc[j] = flux(sc[j], sn[j], zyc[j]);
@@ -414,7 +425,7 @@ __global__ void __launch_bounds__(256)
                     T out[CX];
 #pragma unroll
                     for (int j = 0; j < CX; ++j)
-                        out[j] = T(0.5) * ((tm[j] + sc[j]) + (xdiv<T, CX>(fx, fxh, j) + (fcc[j] - fcm[j])));
+                        out[j] = T(0.5) * fma(r, xdiv<T, CX>(fx, fxh, j) + (fcc[j] - fcm[j]), tm[j] + sc[j]);
                     emit(out, k - 1);
                 }
             };
@@ -497,7 +508,7 @@ __global__ void __launch_bounds__(256)
     const int cell0 = CX * lx;
 
     const T r = static_cast<T>(p.r);
-    const T rc = radius_const<T>(p.ns);
+    const T rc = flux_radius<T>(p);
     uint32_t clamps = 0;
     const int noise = p.noise;
     const uint32_t real = p.realisation[inst];
@@ -520,7 +531,7 @@ __global__ void __launch_bounds__(256)
             row_normals<T, CX, NZ>(z, dr, nq, q0, slo, w2, real, key, rc);
         };
         auto flux = [&](T lo, T hi, T z) __attribute__((always_inline)) {
-            return face_flux<T, EQ, NZ>(lo, hi, z, r, clamps);
+            return face_flux<T, EQ, NZ>(lo, hi, z, clamps);
         };
         T ra[CX], rb[CX], rq[CX], fa[CX], fb[CX];
         {
@@ -549,7 +560,7 @@ __global__ void __launch_bounds__(256)
 
             T fxlo[CX], fxhi;
             normals(z, drow(y, zi, 0));
-            row_xflux<T, CX, EQ, NZ>(tc, z, fxlo, fxhi, lx, LX, r, clamps);
+            row_xflux<T, CX, EQ, NZ>(tc, z, fxlo, fxhi, lx, LX, clamps);
 
             T ylo[CX], fylo[CX];
             normals(z, drow(y, zi, 1));
@@ -587,14 +598,14 @@ __global__ void __launch_bounds__(256)
             if constexpr (STAGE == 0) {
 #pragma unroll
                 for (int j = 0; j < CX; ++j)
-                    out[j] = tc[j] + ((xdiv<T, CX>(fxlo, fxhi, j) + (fyhi[j] - fylo[j])) + (fzhi[j] - fzlo[j]));
+                    out[j] = fma(r, (xdiv<T, CX>(fxlo, fxhi, j) + (fyhi[j] - fylo[j])) + (fzhi[j] - fzlo[j]), tc[j]);
             } else {
                 T ub[CX];
                 load_row<T, CX>(B + rowp(y, zi), ub);
 #pragma unroll
                 for (int j = 0; j < CX; ++j)
-                    out[j] = T(0.5) * ((ub[j] + tc[j]) +
-                                       ((xdiv<T, CX>(fxlo, fxhi, j) + (fyhi[j] - fylo[j])) + (fzhi[j] - fzlo[j])));
+                    out[j] = T(0.5) * fma(r, (xdiv<T, CX>(fxlo, fxhi, j) + (fyhi[j] - fylo[j])) + (fzhi[j] - fzlo[j]),
+                                          ub[j] + tc[j]);
             }
             if (sample) accumulate<T, CX>(out, u0d, sa, sb);
             store_row<T, CX>(D + rowp(y, zi), out);
