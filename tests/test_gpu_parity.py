@@ -355,6 +355,20 @@ def test_2d_fp32_state_parity(she, case):
         assert err <= 1e-5, (q, err)
 
 
+@pytest.mark.parametrize("n", [(64, 24), (32, 8, 6)], ids=["2d", "3d"])
+@pytest.mark.parametrize("noise", [1, 2], ids=["frozen", "off"])
+@pytest.mark.parametrize("scheme", [W.EM, W.HEUN])
+def test_nd_noise_modes_state_parity(she, n, noise, scheme):
+    """Frozen noise (deterministic face temperature in the amplitude) and
+    noise off, in 2D (FE two steps per launch) and 3D, against the oracle."""
+    eq = W.SPECIES if len(n) == 3 else W.HEAT
+    base = inst3d(n, eq, scheme=scheme) if len(n) == 3 else inst2d(n, scheme, eq)
+    insts = [dict(base, noise=noise, realisation=q) for q in range(2)]
+    _, got, want = run_both(she, insts, 1500, 0)
+    for q in range(2):
+        assert max_rel(got[q], want[q]) <= 1e-5, q
+
+
 def test_2d_fp64_state_parity(she):
     insts = [inst2d((64, 24), W.HEUN, W.HEAT, realisation=q) for q in range(2)]
     _, got, want = run_both(she, insts, 3000, 1)
