@@ -224,8 +224,9 @@ she_status she_arena_bytes(const she_config *cfg, size_t *bytes);
  * over `steps` steps of she_step with events on cfg->stream (steps <= 0:
  * 2000 in 1D, 20 in 2D/3D); shapes the batch rejects are skipped.  Results
  * are identical for every shape; only the time differs.  A choice is cached
- * for the process, keyed by precision, stats_mask and each instance's sizes,
- * boundary, scheme, equation, noise mode and material; a cached key returns
+ * for the process, keyed by precision, stats_mask, the XCD-order and
+ * single-step flags and each instance's sizes, boundary, scheme, equation,
+ * noise mode and material; a cached key returns
  * at once.  Synchronises cfg->stream.  SHE_EUNSUPPORTED if no shape runs. */
 she_status she_tune(const she_config *cfg, int32_t steps, she_config *tuned);
 

@@ -822,7 +822,7 @@ static std::string tune_key(const she_config *cfg)
     std::string k;
     char buf[128];
     std::snprintf(buf, sizeof buf, "p%d m%u f%d|", cfg->precision, cfg->stats_mask,
-                  cfg->tuning_flags & SHE_TUNE_XCD_ORDER);
+                  cfg->tuning_flags & (SHE_TUNE_XCD_ORDER | SHE_TUNE_SINGLE_STEP));
     k += buf;
     for (int i = 0; i < cfg->n_instances; ++i) {
         const she_instance_desc &d = cfg->inst[i];
