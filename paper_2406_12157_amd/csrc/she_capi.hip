@@ -759,14 +759,15 @@ static she_status build_plan(she_handle *h, const she_config *cfg, Plan &plan)
     if (st != SHE_OK) return st;
     if (h->dim == 2 && h->pnd.scheme == SHE_EM && h->pnd.ny >= 3 && !(cfg->tuning_flags & SHE_TUNE_SINGLE_STEP)) {
         // Two FE steps per launch (n[1] >= 3: the march reads two rows beyond
-        // its chunk): each march chunk recomputes the intermediate rows on
-        // both sides of it, so the chunks are longer,
-        // about 4096 of up to 32 rows (measured at 512 x 512 x 256: 0.0857 ms
-        // per step against 0.1095 one step per launch).  Never shorter than
+        // its chunk).  Each march chunk recomputes the intermediate rows on
+        // both sides of it, so the chunks are longer: about 2048 of up to 32
+        // rows.  Measured on 512 x 512 fields, ms per step, one step per launch
+        // vs two: 256 realisations 0.1113 vs 0.0855, 64: 0.0326 vs 0.0232,
+        // 16: 0.0131 vs 0.0090, 1: 0.0041 vs 0.0033.  Never shorter than
         // the one-step chunks, whose partials buffer this reuses.
         const ParamsND &p = h->pnd;
         const int64_t rows_all = static_cast<int64_t>(h->n_inst) * p.ny;
-        const int c2 = static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(32, rows_all / 4096)));
+        const int c2 = static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(32, rows_all / 2048)));
         h->chunk2 = std::min(std::max(c2, p.chunk), p.ny);
         h->nparts2 = (p.ny + h->chunk2 - 1) / h->chunk2;
         const int gpb = 256 / (p.nx / h->cx);
