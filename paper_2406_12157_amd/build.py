@@ -2,7 +2,10 @@
 
 Every HIP source under csrc/ is compiled to an object under _build/ in
 parallel and linked into paper_2406_12157_amd/libshe.so.  Packed FP32 VALU
-forms are disabled for all device code.
+forms are disabled for all device code.  ``build()`` compiles everything;
+``build(incremental=True)`` (``python -m paper_2406_12157_amd.build -i``)
+recompiles only the sources newer than their object, a header counting as
+newer for every source.
 """
 from __future__ import annotations
 
@@ -38,13 +41,25 @@ def _compile(src: str) -> str:
     return obj
 
 
-def build(jobs: int | None = None) -> str:
-    """Compile every source and link libshe.so; returns the library path."""
+def _stale(src: str, newest_header: float) -> bool:
+    obj = os.path.join(BUILD, os.path.basename(src) + ".o")
+    if not os.path.exists(obj):
+        return True
+    t = os.path.getmtime(obj)
+    return t < os.path.getmtime(src) or t < newest_header
+
+
+def build(jobs: int | None = None, incremental: bool = False) -> str:
+    """Compile the sources and link libshe.so; returns the library path."""
     os.makedirs(BUILD, exist_ok=True)
     srcs = sorted(glob.glob(os.path.join(CSRC, "*.hip")))
-    jobs = jobs or min(8, len(srcs))
+    headers = glob.glob(os.path.join(CSRC, "*.hpp")) + glob.glob(os.path.join(INCLUDE, "*.h"))
+    newest = max(os.path.getmtime(h) for h in headers)
+    todo = [s for s in srcs if not incremental or _stale(s, newest)]
+    jobs = jobs or min(8, max(1, len(todo)))
     with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
-        objs = list(ex.map(_compile, srcs))
+        list(ex.map(_compile, todo))
+    objs = [os.path.join(BUILD, os.path.basename(s) + ".o") for s in srcs]
     tmp = LIB + ".tmp%d" % os.getpid()
     cmd = [hipcc(), "-shared", "-o", tmp, "--offload-arch=" + ARCH] + objs
     r = subprocess.run(cmd, capture_output=True, text=True)
@@ -55,4 +70,6 @@ def build(jobs: int | None = None) -> str:
 
 
 if __name__ == "__main__":
-    print(build())
+    import sys
+
+    print(build(incremental="-i" in sys.argv[1:]))

@@ -1,0 +1,11 @@
+// 3D step kernels, state type float, 4, 8 and 16 cells per lane.
+#include "she_step_nd.hpp"
+
+namespace she {
+template hipError_t step3d_e<float, 4>(int, int, int, int, size_t, hipStream_t, const ParamsND &, const void *,
+                                      const void *, void *, const StepArg &, double *, InstAcc *);
+template hipError_t step3d_e<float, 8>(int, int, int, int, size_t, hipStream_t, const ParamsND &, const void *,
+                                      const void *, void *, const StepArg &, double *, InstAcc *);
+template hipError_t step3d_e<float, 16>(int, int, int, int, size_t, hipStream_t, const ParamsND &, const void *,
+                                       const void *, void *, const StepArg &, double *, InstAcc *);
+}  // namespace she

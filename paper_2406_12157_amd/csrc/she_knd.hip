@@ -1,657 +1,52 @@
-// 2D / 3D periodic step kernels (one launch per step, ping-pong buffers).
-//
-// Scheme (Garcia et al., Sec. 3, applied per direction with independent face
-// numbers, Sec. 2 eq. GWN): the low face of cell c in direction e carries
-// F = r (U_c - U_{c-e}) + sigma A N, A = (U_{c-e} + U_c)/2 (SHE) or
-// sqrt(max(., 0)) of it (Dean-Kawasaki, Sec. 4); U_c += sum_e F(c+e) - F(c).
-// PC (2D): U* = FE step, U = (U + U* + Delta(U*; same N)) / 2.
-//
-// The constant factors of the noise term are folded into the Box-Muller
-// radius: the kernels draw z = s N with s = sigma/2 (SHE: A z = (U_l + U_r) z),
-// s = sigma/sqrt(2) (DK: sqrt(U_l + U_r) z) or s = sigma A(u0) (deterministic
-// face value: the noise term is z), so a face costs sub, add, mul, fma.
-//
-// Layout: realisation-major, x fastest, FP32 or FP64.  Face numbers
-// ((z*Ny + y)*dim + e)*Nx + x make the four faces of one Philox block four
-// consecutive x-cells of one direction, so a lane that owns CX consecutive
-// cells of a row needs CX/4 Philox calls per direction and uses every number.
-//
-// 2D: a "row group" of LX = Nx/CX lanes owns a full x-row and marches along y
-// over a chunk of rows.  The x-neighbours come from the adjacent lanes
-// (ds_bpermute shuffles inside the group, periodic wrap within the group);
-// the y-neighbours stay in registers from the previous row, and the row two
-// ahead is prefetched, so each cell is read once and written once per step;
-// only the first row of a chunk (FE) or its first three rows (PC) are
-// computed twice.
-//
-// 3D: a workgroup of TY row groups owns TY consecutive rows in y and marches
-// along z.  Low y-face fluxes are exchanged between the rows through LDS (one
-// barrier per plane, double-buffered); the tile's top row computes the flux
-// through its high y-face itself (one extra Philox call per plane for that
-// row).  z-neighbours stay in registers; the plane two ahead is prefetched.
-// PC runs as two passes of the same kernel: the predictor U* = U + Delta(U)
-// into a scratch field, then the corrector (U + U* + Delta(U*)) / 2, whose
-// numbers are drawn again from the same counters.
-//
-// Sample steps: every lane adds dU = U - u0 and dU^2 of its output cells in
-// FP64; the group / workgroup sum is written to a per-chunk partial; a small
-// kernel reduces the partials per instance in a fixed order.
-#include <type_traits>
-
+// 2D / 3D periodic grids: launch dispatch, sample reductions, initial state
+// and finalisation.  The step kernels themselves are in she_step_nd.hpp.
 #include "she_internal.hpp"
 #include "she_rng.hpp"
 
 namespace she {
 
-// Flux through a face between cells with values lo (low side) and hi, for a
-// pre-scaled number zs (see above), in noise mode NZ (0 instantaneous,
-// 1 deterministic face value, 2 off).
-template <typename T, int EQ, int NZ>
-__device__ __forceinline__ T face_flux(T lo, T hi, T zs, uint32_t &clamps)
-{
-    // The face flux divided by r: the difference hi - lo plus the noise term,
-    // whose scale carries 1/r (the caller multiplies the divergence by r once
-    // per cell, which saves a multiply per face).  The multiply-add is written
-    // out so that every copy of this code rounds alike: a face computed in two
-    // places gets one value.
-    const T d = hi - lo;
-    if constexpr (NZ == 0) {
-        const T s = lo + hi;
-        T a;
-        if constexpr (EQ == 0) {
-            a = s;
-        } else {
-            if (s < T(0)) {
-                ++clamps;
-                a = T(0);
-            } else {
-                a = amp_sqrt(s);
-            }
-        }
-        return fma(a, zs, d);
-    } else if constexpr (NZ == 1) {
-        return d + zs;
-    } else {
-        return d;
-    }
-}
+// Typed launchers, instantiated in she_k2d_*.hip / she_k3d_*.hip.
+template <typename T, int CX>
+hipError_t step2d_e(int eq, int scheme, int n_blocks, hipStream_t s, const ParamsND &p, const void *src,
+                    void *dst, const StepArg &sa, double *part, InstAcc *acc);
+template <typename T, int CX>
+hipError_t step3d_e(int eq, int stage, int ty, int n_blocks, size_t smem, hipStream_t s, const ParamsND &p,
+                    const void *src, const void *base, void *dst, const StepArg &sa, double *part, InstAcc *acc);
 
-// Box-Muller radius constant of the normals a face flux takes: the noise
-// scale over r (the fluxes are carried divided by r; r = 0 has no noise).
 template <typename T>
-__device__ __forceinline__ T flux_radius(const ParamsND &p)
+static hipError_t step2d_c(int cx, int eq, int scheme, int n_blocks, hipStream_t s, const ParamsND &p,
+                           const void *src, void *dst, const StepArg &sa, double *part, InstAcc *acc)
 {
-    return radius_const<T>(p.r > 0.0 ? p.ns / p.r : 0.0);
-}
-
-__device__ __forceinline__ int wrap(int i, int n)
-{
-    return i < 0 ? i + n : (i >= n ? i - n : i);
-}
-
-template <typename T, int CX>
-__device__ __forceinline__ void load_row(const T *__restrict__ p, T (&v)[CX])
-{
-#pragma unroll
-    for (int j = 0; j < CX; ++j) v[j] = p[j];
-}
-
-template <typename T, int CX>
-__device__ __forceinline__ void store_row(T *__restrict__ p, const T (&v)[CX])
-{
-#pragma unroll
-    for (int j = 0; j < CX; ++j) p[j] = v[j];
-}
-
-template <typename T, int CX>
-__device__ __forceinline__ void copy_row(T (&d)[CX], const T (&s)[CX])
-{
-#pragma unroll
-    for (int j = 0; j < CX; ++j) d[j] = s[j];
-}
-
-// Scaled numbers of one lane's CX faces of direction-row `drow` (= row*dim + e).
-template <typename T, int CX, int NZ>
-__device__ __forceinline__ void row_normals(T (&z)[CX], uint32_t drow, uint32_t nq, uint32_t q0,
-                                            uint32_t slo, uint32_t w2, uint32_t real, PhiloxKey key, T rc)
-{
-    if constexpr (NZ == 2) {
-#pragma unroll
-        for (int j = 0; j < CX; ++j) z[j] = T(0);
-        return;
-    }
-#pragma unroll
-    for (int c = 0; c < CX / 4; ++c) {
-        const Normals4<T> nz = block_normals_scaled<T>(drow * nq + q0 + c, slo, w2, real, key, rc);
-#pragma unroll
-        for (int l = 0; l < 4; ++l) z[4 * c + l] = nz.z[l];
+    switch (cx) {
+    case 4: return step2d_e<T, 4>(eq, scheme, n_blocks, s, p, src, dst, sa, part, acc);
+    case 8: return step2d_e<T, 8>(eq, scheme, n_blocks, s, p, src, dst, sa, part, acc);
+    case 16: return step2d_e<T, 16>(eq, scheme, n_blocks, s, p, src, dst, sa, part, acc);
+    default: return hipErrorInvalidValue;
     }
 }
 
-// x-fluxes of one row held by a group of LX lanes: Flo[j] is the flux through
-// the low face of the lane's cell j, Fhi the flux through the high face of its
-// last cell (= the next lane's Flo[0]).
-template <typename T, int CX, int EQ, int NZ>
-__device__ __forceinline__ void row_xflux(const T (&v)[CX], const T (&z)[CX], T (&Flo)[CX], T &Fhi, int lx, int LX,
-                                          uint32_t &clamps)
+hipError_t launch_step2d(int prec, int cx, int eq, int scheme, int n_blocks, hipStream_t s, const ParamsND &p,
+                         const void *src, void *dst, const StepArg &sa, double *part, InstAcc *acc)
 {
-    const int lane = threadIdx.x & 63;
-    const int gbase = lane - lx;
-    const int left = gbase + (lx == 0 ? LX - 1 : lx - 1);
-    const int right = gbase + (lx == LX - 1 ? 0 : lx + 1);
-    const T vleft = __shfl(v[CX - 1], left, 64);
-    Flo[0] = face_flux<T, EQ, NZ>(vleft, v[0], z[0], clamps);
-#pragma unroll
-    for (int j = 1; j < CX; ++j) Flo[j] = face_flux<T, EQ, NZ>(v[j - 1], v[j], z[j], clamps);
-    Fhi = __shfl(Flo[0], right, 64);
+    if (prec == 0) return step2d_c<float>(cx, eq, scheme, n_blocks, s, p, src, dst, sa, part, acc);
+    return step2d_c<double>(cx, eq, scheme, n_blocks, s, p, src, dst, sa, part, acc);
 }
 
-// Workgroups are dispatched round-robin over the 8 XCDs, each with its own L2.
-// On request (SHE_TUNE_XCD_ORDER) they are renumbered so that XCD x runs a
-// contiguous range of logical blocks: neighbouring march chunks, which read
-// each other's halo rows, then share an L2.  A bijection on the first
-// 8*floor(n/8) blocks; the rest keep their index.  On MI355X this measured no
-// faster than the plain order, which is the default.
-__device__ __forceinline__ int xcd_block(int b, int n)
+hipError_t launch_step3d(int prec, int cx, int eq, int stage, int ty, int n_blocks, size_t smem, hipStream_t s,
+                         const ParamsND &p, const void *src, const void *base, void *dst, const StepArg &sa,
+                         double *part, InstAcc *acc)
 {
-    constexpr int kXcd = 8;
-    const int per = n / kXcd;
-    if (b >= per * kXcd) return b;
-    return (b % kXcd) * per + b / kXcd;
-}
-
-template <typename T, int CX>
-__device__ __forceinline__ T xdiv(const T (&Flo)[CX], T Fhi, int j)
-{
-    return (j + 1 < CX ? Flo[j + 1] : Fhi) - Flo[j];
-}
-
-template <typename T, int CX>
-__device__ __forceinline__ void accumulate(const T (&out)[CX], double u0, double &sa, double &sb)
-{
-#pragma unroll
-    for (int j = 0; j < CX; ++j) {
-        const double dl = static_cast<double>(out[j]) - u0;
-        sa += dl;
-        sb += dl * dl;
+    if (prec == 0) {
+        if (cx == 4) return step3d_e<float, 4>(eq, stage, ty, n_blocks, smem, s, p, src, base, dst, sa, part, acc);
+        if (cx == 8) return step3d_e<float, 8>(eq, stage, ty, n_blocks, smem, s, p, src, base, dst, sa, part, acc);
+        if (cx == 16) return step3d_e<float, 16>(eq, stage, ty, n_blocks, smem, s, p, src, base, dst, sa, part, acc);
+    } else {
+        if (cx == 4) return step3d_e<double, 4>(eq, stage, ty, n_blocks, smem, s, p, src, base, dst, sa, part, acc);
+        if (cx == 8) return step3d_e<double, 8>(eq, stage, ty, n_blocks, smem, s, p, src, base, dst, sa, part, acc);
+        if (cx == 16)
+            return step3d_e<double, 16>(eq, stage, ty, n_blocks, smem, s, p, src, base, dst, sa, part, acc);
     }
-}
-
-// ------------------------------------------------------------------ 2D
-
-template <typename T, int CX, int EQ, int SCHEME>
-__global__ void __launch_bounds__(256)
-    k_step2d(ParamsND p, const T *__restrict__ src, T *__restrict__ dst, StepArg sarg, double *__restrict__ part,
-             InstAcc *__restrict__ acc)
-{
-    int64_t step;
-    int sample;
-    resolve_step(sarg, step, sample);
-    const int LX = p.nx / CX;
-    const int lx = threadIdx.x % LX;
-    const int grp = threadIdx.x / LX;
-    const int gpb = blockDim.x / LX;
-    const int nchunks = (p.ny + p.chunk - 1) / p.chunk;
-    const int gchunk = (p.xcd_order ? xcd_block(blockIdx.x, gridDim.x) : static_cast<int>(blockIdx.x)) * gpb + grp;
-    if (gchunk >= p.n_inst * nchunks) return;
-    const int inst = gchunk / nchunks, ch = gchunk - inst * nchunks;
-    const int y0 = ch * p.chunk, y1 = min(y0 + p.chunk, p.ny);
-    const int64_t plane = static_cast<int64_t>(p.nx) * p.ny;
-    const T *S = src + inst * plane + CX * lx;
-    T *D = dst + inst * plane + CX * lx;
-
-    if (acc[inst].nonfinite) {  // frozen: carry the state over unchanged
-        for (int y = y0; y < y1; ++y) {
-            T v[CX];
-            load_row<T, CX>(S + static_cast<int64_t>(y) * p.nx, v);
-            store_row<T, CX>(D + static_cast<int64_t>(y) * p.nx, v);
-        }
-        return;
-    }
-
-    const T r = static_cast<T>(p.r);
-    const T rc = flux_radius<T>(p);
-    uint32_t clamps = 0;
-    const int noise = p.noise;
-    const uint32_t real = p.realisation[inst];
-    const PhiloxKey key = make_key(p.seed);
-    const uint32_t slo = static_cast<uint32_t>(step), w2 = ctr_word2(static_cast<uint64_t>(step), 0u);
-    // counter words of the following step (the second stage of a two-step march)
-    const uint32_t slo1 = static_cast<uint32_t>(step + 1), w21 = ctr_word2(static_cast<uint64_t>(step + 1), 0u);
-    const uint32_t nq = static_cast<uint32_t>(p.nx / 4), q0 = static_cast<uint32_t>((CX / 4) * lx);
-    const int ny = p.ny;
-    auto rowp = [&](int y) { return S + static_cast<int64_t>(wrap(y, ny)) * p.nx; };
-    auto drow = [&](int y, int e) { return static_cast<uint32_t>(wrap(y, ny) * 2 + e); };
-
-    double sa = 0.0, sb = 0.0;
-    const double u0d = p.u0;
-
-    // The march loops are unrolled over the period of their register window
-    // (FE: three rows and two flux rows, period 6; PC: four rows and pairs,
-    // period 4); each unrolled copy names the buffers in rotated roles, so rows
-    // move through the window without register copies.
-    auto march = [&](auto nzc) __attribute__((always_inline)) {
-        constexpr int NZ = decltype(nzc)::value;
-        auto normals = [&](T (&z)[CX], uint32_t dr) __attribute__((always_inline)) {
-            row_normals<T, CX, NZ>(z, dr, nq, q0, slo, w2, real, key, rc);
-        };
-        auto flux = [&](T lo, T hi, T z) __attribute__((always_inline)) {
-            return face_flux<T, EQ, NZ>(lo, hi, z, clamps);
-        };
-        auto xflux = [&](const T (&v)[CX], const T (&z)[CX], T (&fx)[CX], T &fxh) __attribute__((always_inline)) {
-            row_xflux<T, CX, EQ, NZ>(v, z, fx, fxh, lx, LX, clamps);
-        };
-        auto emit = [&](const T (&out)[CX], int y) __attribute__((always_inline)) {
-            if (sample) accumulate<T, CX>(out, u0d, sa, sb);
-            store_row<T, CX>(D + static_cast<int64_t>(y) * p.nx, out);
-        };
-        const int rows = y1 - y0;
-        if constexpr (SCHEME == 0) {
-            T ra[CX], rb[CX], rq[CX], fa[CX], fb[CX];
-            // rows of the window: ra, rb, rq; flux rows: fa, fb
-            auto by6 = [&](auto &&row) __attribute__((always_inline)) {
-                for (int i = 0; i < rows; i += 6) {
-                    row(ra, rb, rq, fa, fb, i);
-                    if (i + 1 >= rows) break;
-                    row(rb, rq, ra, fb, fa, i + 1);
-                    if (i + 2 >= rows) break;
-                    row(rq, ra, rb, fa, fb, i + 2);
-                    if (i + 3 >= rows) break;
-                    row(ra, rb, rq, fb, fa, i + 3);
-                    if (i + 4 >= rows) break;
-                    row(rb, rq, ra, fa, fb, i + 4);
-                    if (i + 5 >= rows) break;
-                    row(rq, ra, rb, fb, fa, i + 5);
-                }
-            };
-            if ((ch & 1) == 0) {
-                // upward march: the low-y flux of row y is carried from row y-1
-                {
-                    T tp[CX], z[CX];
-                    load_row<T, CX>(rowp(y0 - 1), tp);
-                    load_row<T, CX>(rowp(y0), ra);
-                    load_row<T, CX>(rowp(y0 + 1), rb);
-                    normals(z, drow(y0, 1));
-#pragma unroll
-                    for (int j = 0; j < CX; ++j) fa[j] = flux(tp[j], ra[j], z[j]);
-                }
-                // tc, tn: rows y, y+1; tq receives row y+2; flo: low-y flux of row y
-                by6([&](const T (&tc)[CX], const T (&tn)[CX], T (&tq)[CX], const T (&flo)[CX], T (&fhi)[CX],
-                        int i) __attribute__((always_inline)) {
-                    const int y = y0 + i;
-                    if (y + 2 <= y1) load_row<T, CX>(rowp(y + 2), tq);
-                    T z[CX], fx[CX], fxh, out[CX];
-                    normals(z, drow(y + 1, 1));
-#pragma unroll
-                    for (int j = 0; j < CX; ++j) fhi[j] = flux(tc[j], tn[j], z[j]);
-                    normals(z, drow(y, 0));
-                    xflux(tc, z, fx, fxh);
-#pragma unroll
-                    for (int j = 0; j < CX; ++j) out[j] = fma(r, xdiv<T, CX>(fx, fxh, j) + (fhi[j] - flo[j]), tc[j]);
-                    emit(out, y);
-                });
-            } else {
-                // downward march (odd chunks): each chunk boundary is then read by
-                // both neighbours at the same end of their marches, so the second
-                // read of its rows can hit the cache.  The high-y flux of row y is
-                // carried from row y+1; every face gets the same value either way.
-                {
-                    T tu[CX], z[CX];
-                    load_row<T, CX>(rowp(y1), tu);
-                    load_row<T, CX>(rowp(y1 - 1), ra);
-                    load_row<T, CX>(rowp(y1 - 2), rb);
-                    normals(z, drow(y1, 1));
-#pragma unroll
-                    for (int j = 0; j < CX; ++j) fa[j] = flux(ra[j], tu[j], z[j]);
-                }
-                // tc, tn: rows y, y-1; tq receives row y-2; fhi: high-y flux of row y
-                by6([&](const T (&tc)[CX], const T (&tn)[CX], T (&tq)[CX], const T (&fhi)[CX], T (&flo)[CX],
-                        int i) __attribute__((always_inline)) {
-                    const int y = y1 - 1 - i;
-                    if (y - 2 >= y0 - 1) load_row<T, CX>(rowp(y - 2), tq);
-                    T z[CX], fx[CX], fxh, out[CX];
-                    normals(z, drow(y, 1));
-#pragma unroll
-                    for (int j = 0; j < CX; ++j) flo[j] = flux(tn[j], tc[j], z[j]);
-                    normals(z, drow(y, 0));
-                    xflux(tc, z, fx, fxh);
-#pragma unroll
-                    for (int j = 0; j < CX; ++j) out[j] = fma(r, xdiv<T, CX>(fx, fxh, j) + (fhi[j] - flo[j]), tc[j]);
-                    emit(out, y);
-                });
-            }
-        } else if constexpr (SCHEME == 2) {
-            // Two FE steps in one pass (steps n and n+1 of the counter): the
-            // intermediate field U1 lives only in registers.  Iteration k forms
-            // row k of U1 = FE(U0) and row k-1 of U2 = FE(U1), with the same
-            // face and update expressions as the one-step march, so U2 is the
-            // field two single steps give, bit for bit.  tc, tn: U0 rows k,
-            // k+1, tq receiving row k+2; sc, sn: U1 rows k-1, k; fpc, fpn: the
-            // step-n low-y fluxes of rows k, k+1; fcm, fcc: the step-(n+1)
-            // low-y fluxes of U1 rows k-1, k.  Each chunk recomputes the U1
-            // rows on both sides of it.
-            auto normals1 = [&](T (&z)[CX], uint32_t dr) __attribute__((always_inline)) {
-                row_normals<T, CX, NZ>(z, dr, nq, q0, slo1, w21, real, key, rc);
-            };
-            T ta[CX], tb[CX], tcc[CX], sa_[CX], sb_[CX], pa[CX], pb[CX], ma[CX], mb[CX];
-            const int k0 = y0 - 1;
-            {
-                T tp[CX], z[CX];
-                load_row<T, CX>(rowp(k0 - 1), tp);
-                load_row<T, CX>(rowp(k0), ta);
-                load_row<T, CX>(rowp(k0 + 1), tb);
-                normals(z, drow(k0, 1));
-#pragma unroll
-                for (int j = 0; j < CX; ++j) pa[j] = flux(tp[j], ta[j], z[j]);
-            }
-            auto row = [&](const T (&tc)[CX], const T (&tn)[CX], T (&tq)[CX], const T (&sc)[CX], T (&sn)[CX],
-                           const T (&fpc)[CX], T (&fpn)[CX], const T (&fcm)[CX], T (&fcc)[CX],
-                           int i) __attribute__((always_inline)) {
-                const int k = k0 + i;
-                load_row<T, CX>(rowp(k + 2), tq);
-                T z[CX], fx[CX], fxh;
-                normals(z, drow(k + 1, 1));
-#pragma unroll
-                for (int j = 0; j < CX; ++j) fpn[j] = flux(tc[j], tn[j], z[j]);
-                normals(z, drow(k, 0));
-                xflux(tc, z, fx, fxh);
-#pragma unroll
-                for (int j = 0; j < CX; ++j) sn[j] = fma(r, xdiv<T, CX>(fx, fxh, j) + (fpn[j] - fpc[j]), tc[j]);
-                if (i >= 1) {
-                    normals1(z, drow(k, 1));
-#pragma unroll
-                    for (int j = 0; j < CX; ++j) fcc[j] = flux(sc[j], sn[j], z[j]);
-                }
-                if (i >= 2) {
-                    normals1(z, drow(k - 1, 0));
-                    xflux(sc, z, fx, fxh);
-                    T out[CX];
-#pragma unroll
-                    for (int j = 0; j < CX; ++j) out[j] = fma(r, xdiv<T, CX>(fx, fxh, j) + (fcc[j] - fcm[j]), sc[j]);
-                    emit(out, k - 1);
-                }
-            };
-            const int iters = rows + 2;  // k = y0-1 .. y1
-            for (int i = 0; i < iters; i += 6) {
-                row(ta, tb, tcc, sa_, sb_, pa, pb, ma, mb, i);
-                if (i + 1 >= iters) break;
-                row(tb, tcc, ta, sb_, sa_, pb, pa, mb, ma, i + 1);
-                if (i + 2 >= iters) break;
-                row(tcc, ta, tb, sa_, sb_, pa, pb, ma, mb, i + 2);
-                if (i + 3 >= iters) break;
-                row(ta, tb, tcc, sb_, sa_, pb, pa, mb, ma, i + 3);
-                if (i + 4 >= iters) break;
-                row(tb, tcc, ta, sa_, sb_, pa, pb, ma, mb, i + 4);
-                if (i + 5 >= iters) break;
-                row(tcc, ta, tb, sb_, sa_, pb, pa, mb, ma, i + 5);
-            }
-        } else {
-            // Predictor-corrector.  Iteration k produces the predictor row k and
-            // the corrected row k-1.  Per iteration: tm, tc, tn rows k-1..k+1 and
-            // tq receiving row k+2; sc the predictor row k-1, sn receiving row k;
-            // zyc, zyn the y numbers of rows k, k+1; zxm, zxc the x numbers of
-            // rows k-1, k; fpc, fpn the predictor low-y fluxes of rows k, k+1;
-            // fcm, fcc the corrector low-y fluxes of rows k-1, k.
-            T ta[CX], tb[CX], tcc[CX], td[CX], sa_[CX], sb_[CX], ya[CX], yb[CX], xa[CX], xb[CX], pa[CX], pb[CX],
-                ma[CX], mb[CX];
-            const int k0 = y0 - 1;
-            load_row<T, CX>(rowp(k0 - 1), ta);
-            load_row<T, CX>(rowp(k0), tb);
-            load_row<T, CX>(rowp(k0 + 1), tcc);
-            normals(ya, drow(k0, 1));
-#pragma unroll
-            for (int j = 0; j < CX; ++j) pa[j] = flux(ta[j], tb[j], ya[j]);
-            auto row = [&](const T (&tm)[CX], const T (&tc)[CX], const T (&tn)[CX], T (&tq)[CX], const T (&sc)[CX],
-                           T (&sn)[CX], const T (&zyc)[CX], T (&zyn)[CX], const T (&zxm)[CX], T (&zxc)[CX],
-                           const T (&fpc)[CX], T (&fpn)[CX], const T (&fcm)[CX], T (&fcc)[CX],
-                           int i) __attribute__((always_inline)) {
-                const int k = k0 + i;
-                load_row<T, CX>(rowp(k + 2), tq);
-                normals(zyn, drow(k + 1, 1));
-#pragma unroll
-                for (int j = 0; j < CX; ++j) fpn[j] = flux(tc[j], tn[j], zyn[j]);
-                normals(zxc, drow(k, 0));
-                T fx[CX], fxh;
-                xflux(tc, zxc, fx, fxh);
-#pragma unroll
-                for (int j = 0; j < CX; ++j) sn[j] = fma(r, xdiv<T, CX>(fx, fxh, j) + (fpn[j] - fpc[j]), tc[j]);
-                if (i >= 1) {
-#pragma unroll
-                    for (int j = 0; j < CX; ++j) fcc[j] = flux(sc[j], sn[j], zyc[j]);
-                }
-                if (i >= 2) {
-                    // corrected row k-1 from predictor rows k-2 (fcm), k-1 (sc), k (sn)
-                    xflux(sc, zxm, fx, fxh);
-                    T out[CX];
-#pragma unroll
-                    for (int j = 0; j < CX; ++j)
-                        out[j] = T(0.5) * fma(r, xdiv<T, CX>(fx, fxh, j) + (fcc[j] - fcm[j]), tm[j] + sc[j]);
-                    emit(out, k - 1);
-                }
-            };
-            const int iters = rows + 2;  // k = y0-1 .. y1
-            for (int i = 0; i < iters; i += 4) {
-                row(ta, tb, tcc, td, sa_, sb_, ya, yb, xa, xb, pa, pb, ma, mb, i);
-                if (i + 1 >= iters) break;
-                row(tb, tcc, td, ta, sb_, sa_, yb, ya, xb, xa, pb, pa, mb, ma, i + 1);
-                if (i + 2 >= iters) break;
-                row(tcc, td, ta, tb, sa_, sb_, ya, yb, xa, xb, pa, pb, ma, mb, i + 2);
-                if (i + 3 >= iters) break;
-                row(td, ta, tb, tcc, sb_, sa_, yb, ya, xb, xa, pb, pa, mb, ma, i + 3);
-            }
-        }
-    };
-    if (noise == 0) march(std::integral_constant<int, 0>{});
-    else if (noise == 1) march(std::integral_constant<int, 1>{});
-    else march(std::integral_constant<int, 2>{});
-    if (sample) {
-        for (int off = 1; off < LX; off <<= 1) {
-            sa += __shfl_xor(sa, off, 64);
-            sb += __shfl_xor(sb, off, 64);
-        }
-        if (lx == 0) {
-            part[2 * static_cast<int64_t>(gchunk)] = sa;
-            part[2 * static_cast<int64_t>(gchunk) + 1] = sb;
-        }
-    }
-    if (clamps) atomicAdd(reinterpret_cast<unsigned long long *>(&acc[inst].clamp_count),
-                          static_cast<unsigned long long>(clamps));
-}
-
-// ------------------------------------------------------------------ 3D (FE; PC in two passes)
-
-// STAGE 0: FE step (or a PC predictor) dst = src + Delta(src);
-// STAGE 1: PC corrector dst = (base + src + Delta(src)) / 2, with src the
-// predictor and base the state it was taken from (same step, same numbers).
-template <typename T, int CX, int EQ, int STAGE>
-__global__ void __launch_bounds__(256)
-    k_step3d(ParamsND p, int32_t ty, const T *__restrict__ src, const T *__restrict__ base, T *__restrict__ dst,
-             StepArg sarg, double *__restrict__ part, InstAcc *__restrict__ acc)
-{
-    int64_t step;
-    int sample;
-    resolve_step(sarg, step, sample);
-    extern __shared__ __align__(16) unsigned char smem_raw[];
-    const int LX = p.nx / CX;
-    const int lx = threadIdx.x % LX;
-    const int g = threadIdx.x / LX;                 // row within the tile
-    const int nyt = p.ny / ty, nzc = (p.nz + p.chunk - 1) / p.chunk;
-    const int tiles = nyt * nzc;
-    const int lblock = p.xcd_order ? xcd_block(blockIdx.x, gridDim.x) : static_cast<int>(blockIdx.x);
-    const int inst = lblock / tiles;
-    const int tile = lblock - inst * tiles;
-    const int yt = tile % nyt, zc = tile / nyt;
-    const int y = yt * ty + g;
-    const int z0 = zc * p.chunk, z1 = min(z0 + p.chunk, p.nz);
-    const int nx = p.nx, ny = p.ny, nz = p.nz;
-    const int64_t vol = static_cast<int64_t>(nx) * ny * nz;
-    const T *S = src + inst * vol + CX * lx;
-    const T *B = STAGE == 1 ? base + inst * vol + CX * lx : nullptr;
-    T *D = dst + inst * vol + CX * lx;
-    auto rowp = [&](int yy, int zz) {
-        return static_cast<int64_t>(wrap(zz, nz) * ny + wrap(yy, ny)) * nx;
-    };
-
-    if (acc[inst].nonfinite) {  // frozen: carry the state over unchanged
-        const T *F = STAGE == 1 ? B : S;
-        for (int zz = z0; zz < z1; ++zz) {
-            T v[CX];
-            load_row<T, CX>(F + rowp(y, zz), v);
-            store_row<T, CX>(D + rowp(y, zz), v);
-        }
-        return;
-    }
-
-    // LDS: T rows of the current plane and low-y fluxes, both double-buffered
-    T *tsh = reinterpret_cast<T *>(smem_raw);            // [2][ty][nx]
-    T *fsh = tsh + 2 * ty * nx;                           // [2][ty][nx]
-    const int cell0 = CX * lx;
-
-    const T r = static_cast<T>(p.r);
-    const T rc = flux_radius<T>(p);
-    uint32_t clamps = 0;
-    const int noise = p.noise;
-    const uint32_t real = p.realisation[inst];
-    const PhiloxKey key = make_key(p.seed);
-    const uint32_t slo = static_cast<uint32_t>(step), w2 = ctr_word2(static_cast<uint64_t>(step), 0u);
-    const uint32_t nq = static_cast<uint32_t>(nx / 4), q0 = static_cast<uint32_t>((CX / 4) * lx);
-    auto drow = [&](int yy, int zz, int e) {
-        return static_cast<uint32_t>((wrap(zz, nz) * ny + wrap(yy, ny)) * 3 + e);
-    };
-
-    double sa = 0.0, sb = 0.0;
-    const double u0d = p.u0;
-
-    // As in 2D, the march is unrolled over the period of its register window
-    // (three planes of the row and two z-flux rows: period 6) and the noise
-    // mode is fixed per copy.
-    auto march = [&](auto nzc) __attribute__((always_inline)) {
-        constexpr int NZ = decltype(nzc)::value;
-        auto normals = [&](T (&z)[CX], uint32_t dr) __attribute__((always_inline)) {
-            row_normals<T, CX, NZ>(z, dr, nq, q0, slo, w2, real, key, rc);
-        };
-        auto flux = [&](T lo, T hi, T z) __attribute__((always_inline)) {
-            return face_flux<T, EQ, NZ>(lo, hi, z, clamps);
-        };
-        T ra[CX], rb[CX], rq[CX], fa[CX], fb[CX];
-        {
-            T tp[CX], z[CX];
-            load_row<T, CX>(S + rowp(y, z0 - 1), tp);
-            load_row<T, CX>(S + rowp(y, z0), ra);
-            load_row<T, CX>(S + rowp(y, z0 + 1), rb);
-            normals(z, drow(y, z0, 2));
-#pragma unroll
-            for (int j = 0; j < CX; ++j) fa[j] = flux(tp[j], ra[j], z[j]);
-            T *dstp = tsh + ((z0 & 1) * ty + g) * nx + cell0;
-#pragma unroll
-            for (int j = 0; j < CX; ++j) dstp[j] = ra[j];
-        }
-        __syncthreads();
-        // tc, tn: planes zi, zi+1 of the row; tq receives plane zi+2; fzlo: the
-        // low-z flux of plane zi
-        auto plane = [&](const T (&tc)[CX], const T (&tn)[CX], T (&tq)[CX], const T (&fzlo)[CX], T (&fzhi)[CX],
-                         int zi) __attribute__((always_inline)) {
-            const int buf = zi & 1;
-            load_row<T, CX>(S + rowp(y, zi + 2), tq);
-            T z[CX];
-            normals(z, drow(y, zi + 1, 2));
-#pragma unroll
-            for (int j = 0; j < CX; ++j) fzhi[j] = flux(tc[j], tn[j], z[j]);
-
-            T fxlo[CX], fxhi;
-            normals(z, drow(y, zi, 0));
-            row_xflux<T, CX, EQ, NZ>(tc, z, fxlo, fxhi, lx, LX, clamps);
-
-            T ylo[CX], fylo[CX];
-            normals(z, drow(y, zi, 1));
-            if (g > 0) {
-                const T *q = tsh + (buf * ty + g - 1) * nx + cell0;
-#pragma unroll
-                for (int j = 0; j < CX; ++j) ylo[j] = q[j];
-            } else {
-                load_row<T, CX>(S + rowp(y - 1, zi), ylo);
-            }
-#pragma unroll
-            for (int j = 0; j < CX; ++j) fylo[j] = flux(ylo[j], tc[j], z[j]);
-            {
-                T *fp = fsh + (buf * ty + g) * nx + cell0;
-#pragma unroll
-                for (int j = 0; j < CX; ++j) fp[j] = fylo[j];
-                T *tp = tsh + (((zi + 1) & 1) * ty + g) * nx + cell0;
-#pragma unroll
-                for (int j = 0; j < CX; ++j) tp[j] = tn[j];
-            }
-            __syncthreads();
-            T fyhi[CX];
-            if (g + 1 < ty) {
-                const T *fp = fsh + (buf * ty + g + 1) * nx + cell0;
-#pragma unroll
-                for (int j = 0; j < CX; ++j) fyhi[j] = fp[j];
-            } else {
-                T yhi[CX];
-                load_row<T, CX>(S + rowp(y + 1, zi), yhi);
-                normals(z, drow(y + 1, zi, 1));
-#pragma unroll
-                for (int j = 0; j < CX; ++j) fyhi[j] = flux(tc[j], yhi[j], z[j]);
-            }
-            T out[CX];
-            if constexpr (STAGE == 0) {
-#pragma unroll
-                for (int j = 0; j < CX; ++j)
-                    out[j] = fma(r, (xdiv<T, CX>(fxlo, fxhi, j) + (fyhi[j] - fylo[j])) + (fzhi[j] - fzlo[j]), tc[j]);
-            } else {
-                T ub[CX];
-                load_row<T, CX>(B + rowp(y, zi), ub);
-#pragma unroll
-                for (int j = 0; j < CX; ++j)
-                    out[j] = T(0.5) * fma(r, (xdiv<T, CX>(fxlo, fxhi, j) + (fyhi[j] - fylo[j])) + (fzhi[j] - fzlo[j]),
-                                          ub[j] + tc[j]);
-            }
-            if (sample) accumulate<T, CX>(out, u0d, sa, sb);
-            store_row<T, CX>(D + rowp(y, zi), out);
-        };
-        const int planes = z1 - z0;
-        for (int i = 0; i < planes; i += 6) {
-            plane(ra, rb, rq, fa, fb, z0 + i);
-            if (i + 1 >= planes) break;
-            plane(rb, rq, ra, fb, fa, z0 + i + 1);
-            if (i + 2 >= planes) break;
-            plane(rq, ra, rb, fa, fb, z0 + i + 2);
-            if (i + 3 >= planes) break;
-            plane(ra, rb, rq, fb, fa, z0 + i + 3);
-            if (i + 4 >= planes) break;
-            plane(rb, rq, ra, fa, fb, z0 + i + 4);
-            if (i + 5 >= planes) break;
-            plane(rq, ra, rb, fb, fa, z0 + i + 5);
-        }
-    };
-    if (noise == 0) march(std::integral_constant<int, 0>{});
-    else if (noise == 1) march(std::integral_constant<int, 1>{});
-    else march(std::integral_constant<int, 2>{});
-    if (sample) {
-        for (int off = 1; off < LX; off <<= 1) {
-            sa += __shfl_xor(sa, off, 64);
-            sb += __shfl_xor(sb, off, 64);
-        }
-        __syncthreads();
-        double *red = reinterpret_cast<double *>(smem_raw);
-        if (lx == 0) {
-            red[2 * g] = sa;
-            red[2 * g + 1] = sb;
-        }
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            double ta = 0.0, tb = 0.0;
-            for (int w = 0; w < ty; ++w) {
-                ta += red[2 * w];
-                tb += red[2 * w + 1];
-            }
-            part[2 * static_cast<int64_t>(lblock)] = ta;
-            part[2 * static_cast<int64_t>(lblock) + 1] = tb;
-        }
-    }
-    if (clamps) atomicAdd(reinterpret_cast<unsigned long long *>(&acc[inst].clamp_count),
-                          static_cast<unsigned long long>(clamps));
+    return hipErrorInvalidValue;
 }
 
 // Per-instance reduction of the sample partials, fixed order.
@@ -746,92 +141,6 @@ __global__ void __launch_bounds__(256)
 }
 
 // ------------------------------------------------------------------ launchers
-
-template <typename T, int CX, int EQ>
-static hipError_t step2d_s(int scheme, int n_blocks, hipStream_t s, const ParamsND &p, const void *src, void *dst,
-                           const StepArg &sa, double *part, InstAcc *acc)
-{
-    if (scheme == 0)
-        hipLaunchKernelGGL((k_step2d<T, CX, EQ, 0>), dim3(n_blocks), dim3(256), 0, s, p,
-                           static_cast<const T *>(src), static_cast<T *>(dst), sa, part, acc);
-    else if (scheme == 1)
-        hipLaunchKernelGGL((k_step2d<T, CX, EQ, 1>), dim3(n_blocks), dim3(256), 0, s, p,
-                           static_cast<const T *>(src), static_cast<T *>(dst), sa, part, acc);
-    else
-        hipLaunchKernelGGL((k_step2d<T, CX, EQ, 2>), dim3(n_blocks), dim3(256), 0, s, p,
-                           static_cast<const T *>(src), static_cast<T *>(dst), sa, part, acc);
-    return hipGetLastError();
-}
-
-template <typename T, int CX>
-static hipError_t step2d_e(int eq, int scheme, int n_blocks, hipStream_t s, const ParamsND &p, const void *src,
-                           void *dst, const StepArg &sa, double *part, InstAcc *acc)
-{
-    if (eq == 0) return step2d_s<T, CX, 0>(scheme, n_blocks, s, p, src, dst, sa, part, acc);
-    return step2d_s<T, CX, 1>(scheme, n_blocks, s, p, src, dst, sa, part, acc);
-}
-
-template <typename T>
-static hipError_t step2d_c(int cx, int eq, int scheme, int n_blocks, hipStream_t s, const ParamsND &p,
-                           const void *src, void *dst, const StepArg &sa, double *part, InstAcc *acc)
-{
-    switch (cx) {
-    case 4: return step2d_e<T, 4>(eq, scheme, n_blocks, s, p, src, dst, sa, part, acc);
-    case 8: return step2d_e<T, 8>(eq, scheme, n_blocks, s, p, src, dst, sa, part, acc);
-    case 16: return step2d_e<T, 16>(eq, scheme, n_blocks, s, p, src, dst, sa, part, acc);
-    default: return hipErrorInvalidValue;
-    }
-}
-
-hipError_t launch_step2d(int prec, int cx, int eq, int scheme, int n_blocks, hipStream_t s, const ParamsND &p,
-                         const void *src, void *dst, const StepArg &sa, double *part, InstAcc *acc)
-{
-    if (prec == 0) return step2d_c<float>(cx, eq, scheme, n_blocks, s, p, src, dst, sa, part, acc);
-    return step2d_c<double>(cx, eq, scheme, n_blocks, s, p, src, dst, sa, part, acc);
-}
-
-template <typename T, int CX, int EQ>
-static hipError_t step3d_s(int stage, int ty, int n_blocks, size_t smem, hipStream_t s, const ParamsND &p,
-                           const void *src, const void *base, void *dst, const StepArg &sa, double *part,
-                           InstAcc *acc)
-{
-    const dim3 block((p.nx / CX) * ty);
-    if (stage == 0)
-        hipLaunchKernelGGL((k_step3d<T, CX, EQ, 0>), dim3(n_blocks), block, smem, s, p, ty,
-                           static_cast<const T *>(src), static_cast<const T *>(base), static_cast<T *>(dst), sa,
-                           part, acc);
-    else
-        hipLaunchKernelGGL((k_step3d<T, CX, EQ, 1>), dim3(n_blocks), block, smem, s, p, ty,
-                           static_cast<const T *>(src), static_cast<const T *>(base), static_cast<T *>(dst), sa,
-                           part, acc);
-    return hipGetLastError();
-}
-
-template <typename T, int CX>
-static hipError_t step3d_e(int eq, int stage, int ty, int n_blocks, size_t smem, hipStream_t s, const ParamsND &p,
-                           const void *src, const void *base, void *dst, const StepArg &sa, double *part,
-                           InstAcc *acc)
-{
-    if (eq == 0) return step3d_s<T, CX, 0>(stage, ty, n_blocks, smem, s, p, src, base, dst, sa, part, acc);
-    return step3d_s<T, CX, 1>(stage, ty, n_blocks, smem, s, p, src, base, dst, sa, part, acc);
-}
-
-hipError_t launch_step3d(int prec, int cx, int eq, int stage, int ty, int n_blocks, size_t smem, hipStream_t s,
-                         const ParamsND &p, const void *src, const void *base, void *dst, const StepArg &sa,
-                         double *part, InstAcc *acc)
-{
-    if (prec == 0) {
-        if (cx == 4) return step3d_e<float, 4>(eq, stage, ty, n_blocks, smem, s, p, src, base, dst, sa, part, acc);
-        if (cx == 8) return step3d_e<float, 8>(eq, stage, ty, n_blocks, smem, s, p, src, base, dst, sa, part, acc);
-        if (cx == 16) return step3d_e<float, 16>(eq, stage, ty, n_blocks, smem, s, p, src, base, dst, sa, part, acc);
-    } else {
-        if (cx == 4) return step3d_e<double, 4>(eq, stage, ty, n_blocks, smem, s, p, src, base, dst, sa, part, acc);
-        if (cx == 8) return step3d_e<double, 8>(eq, stage, ty, n_blocks, smem, s, p, src, base, dst, sa, part, acc);
-        if (cx == 16)
-            return step3d_e<double, 16>(eq, stage, ty, n_blocks, smem, s, p, src, base, dst, sa, part, acc);
-    }
-    return hipErrorInvalidValue;
-}
 
 hipError_t launch_reduce_parts(int n_inst, hipStream_t s, const StepArg &sa, const double *part, int32_t nparts,
                                double inv_cells, InstAcc *acc)
