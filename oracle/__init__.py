@@ -35,11 +35,12 @@ _lib = None
 
 
 def build(force: bool = False) -> str:
-    """Compile she_oracle.c into liboracle.so (gcc, -O2 -ffp-contract=off)."""
+    """Compile she_oracle.c into liboracle.so (gcc, -O2 -ffp-contract=off,
+    OpenMP over independent faces and cells)."""
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
         tmp = _LIB + ".tmp%d" % os.getpid()
         subprocess.check_call(
-            ["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math",
+            ["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fopenmp",
              "-fPIC", "-shared", "-o", tmp, _SRC, "-lm"])
         os.replace(tmp, _LIB)
     return _LIB
@@ -87,6 +88,8 @@ def _load():
         lib.or_reference.argtypes = [C.POINTER(_Desc), C.POINTER(C.c_double)]
         lib.or_init.restype = C.c_int
         lib.or_init.argtypes = [C.POINTER(_Desc), C.POINTER(C.c_double)]
+        lib.or_set_threads.argtypes = [C.c_int]
+        lib.or_get_threads.restype = C.c_int
         lib.or_advance.restype = C.c_int
         lib.or_advance.argtypes = [C.POINTER(_Desc), C.POINTER(C.c_double), C.c_int64,
                                    C.c_int64, C.POINTER(_Stats)]
@@ -158,6 +161,16 @@ class Desc:
     @property
     def ncells(self) -> int:
         return int(np.prod(self.n))
+
+
+def set_threads(n: int) -> None:
+    """Threads of the oracle's parallel loops (n < 1: every core).  Results
+    do not depend on it."""
+    _load().or_set_threads(int(n))
+
+
+def get_threads() -> int:
+    return int(_load().or_get_threads())
 
 
 def philox(ctr, key) -> np.ndarray:

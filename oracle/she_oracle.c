@@ -61,12 +61,19 @@
  * (periodic) or 0..N (Dirichlet, face N = right wall).  In 2D/3D the low face
  * of cell (x,y,z) in direction e is  f = ((z*Ny + y)*dim + e)*Nx + x.
  *
- * Compiled with -ffp-contract=off; everything in IEEE double.
+ * Compiled with -ffp-contract=off; everything in IEEE double.  Loops whose
+ * iterations are independent (one Philox block, one face flux, one cell
+ * update, one DFT line each) run on OpenMP threads; every sum over cells or
+ * samples stays a sequential loop, so the results do not depend on the
+ * thread count.
  */
 #include <math.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #ifndef M_PI
 #define M_PI 3.14159265358979323846
@@ -199,12 +206,35 @@ void or_normals(uint64_t seed, uint32_t realisation, uint32_t tag, uint64_t step
         out[i] = or_normal(seed, realisation, tag, step, face0 + (uint64_t)i);
 }
 
+/* Threads of the parallel loops (n < 1: all the runtime offers). */
+void or_set_threads(int n)
+{
+#ifdef _OPENMP
+    omp_set_num_threads(n > 0 ? n : omp_get_num_procs());
+#else
+    (void)n;
+#endif
+}
+
+int or_get_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
+/* loops shorter than this run on one thread (fork/join costs more) */
+#define OR_PAR_MIN 4096
+
 /* All faces 0..nfaces-1 of one step: each Philox block is evaluated once and
  * its four lanes handed to the four faces it covers. */
 static void draw_faces(const or_desc *d, uint32_t tag, uint64_t step,
                        int64_t nfaces, double *z)
 {
     int64_t nblocks = (nfaces + 3) / 4;
+#pragma omp parallel for schedule(static) if (nfaces >= OR_PAR_MIN)
     for (int64_t b = 0; b < nblocks; ++b) {
         uint32_t x[4];
         double g[4];
@@ -351,6 +381,8 @@ static void divergence(const or_desc *d, const double *u, const double *z,
     const int dim = d->dim;
     const int64_t nx = d->n[0], ny = d->n[1], nz = d->n[2];
     const int64_t nc = nx * ny * nz;
+    int64_t ncl = 0;   /* clamps of this call (integer sum: order-free) */
+#pragma omp parallel for collapse(2) schedule(static) reduction(+ : ncl) if (nc >= OR_PAR_MIN)
     for (int64_t zc = 0; zc < nz; ++zc)
         for (int64_t yc = 0; yc < ny; ++yc)
             for (int64_t xc = 0; xc < nx; ++xc) {
@@ -365,11 +397,13 @@ static void divergence(const or_desc *d, const double *u, const double *z,
                     if (noisy) {
                         int64_t face = ((zc * ny + yc) * dim + e) * nx + xc;
                         double v = d->noise == 1 ? d->u0 : 0.5 * (u[a] + u[c]);
-                        fl += s * amplitude(d, v, clamps) * z[face];
+                        fl += s * amplitude(d, v, clamps ? &ncl : NULL) * z[face];
                     }
                     flux[c * dim + e] = fl;
                 }
             }
+    if (clamps) *clamps += ncl;
+#pragma omp parallel for collapse(2) schedule(static) if (nc >= OR_PAR_MIN)
     for (int64_t zc = 0; zc < nz; ++zc)
         for (int64_t yc = 0; yc < ny; ++yc)
             for (int64_t xc = 0; xc < nx; ++xc) {
@@ -427,32 +461,41 @@ void or_bin_modes(const or_desc *d, double *modes)
 
 /* In-place DFT X_k = sum_j x_j exp(-2 pi i j k / n) along one axis of a
  * complex field (re, im), evaluated by its definition. */
-static void dft_axis(const or_desc *d, int axis, double *re, double *im, double *tr, double *ti)
+static void dft_axis(const or_desc *d, int axis, double *re, double *im)
 {
     const int64_t nx = d->n[0], ny = d->n[1], nz = d->n[2];
     const int64_t n = d->n[axis];
     const int64_t stride = axis == 0 ? 1 : (axis == 1 ? nx : nx * ny);
-    for (int64_t zc = 0; zc < (axis == 2 ? 1 : nz); ++zc)
-        for (int64_t yc = 0; yc < (axis == 1 ? 1 : ny); ++yc)
-            for (int64_t xc = 0; xc < (axis == 0 ? 1 : nx); ++xc) {
-                int64_t base = (zc * ny + yc) * nx + xc;
-                for (int64_t k = 0; k < n; ++k) {
-                    double sr = 0.0, si = 0.0;
-                    for (int64_t j = 0; j < n; ++j) {
-                        double ang = -2.0 * M_PI * (double)((j * k) % n) / (double)n;
-                        double c = cos(ang), s = sin(ang);
-                        double xr = re[base + j * stride], xi = im[base + j * stride];
-                        sr += xr * c - xi * s;
-                        si += xr * s + xi * c;
+    const int64_t l0 = axis == 2 ? 1 : nz, l1 = axis == 1 ? 1 : ny, l2 = axis == 0 ? 1 : nx;
+#pragma omp parallel if (l0 * l1 * l2 * n >= OR_PAR_MIN)
+    {
+        double *tr = (double *)malloc(sizeof(double) * (size_t)n);
+        double *ti = (double *)malloc(sizeof(double) * (size_t)n);
+#pragma omp for collapse(3) schedule(static)
+        for (int64_t zc = 0; zc < l0; ++zc)
+            for (int64_t yc = 0; yc < l1; ++yc)
+                for (int64_t xc = 0; xc < l2; ++xc) {
+                    int64_t base = (zc * ny + yc) * nx + xc;
+                    for (int64_t k = 0; k < n; ++k) {
+                        double sr = 0.0, si = 0.0;
+                        for (int64_t j = 0; j < n; ++j) {
+                            double ang = -2.0 * M_PI * (double)((j * k) % n) / (double)n;
+                            double c = cos(ang), s = sin(ang);
+                            double xr = re[base + j * stride], xi = im[base + j * stride];
+                            sr += xr * c - xi * s;
+                            si += xr * s + xi * c;
+                        }
+                        tr[k] = sr;
+                        ti[k] = si;
                     }
-                    tr[k] = sr;
-                    ti[k] = si;
+                    for (int64_t k = 0; k < n; ++k) {
+                        re[base + k * stride] = tr[k];
+                        im[base + k * stride] = ti[k];
+                    }
                 }
-                for (int64_t k = 0; k < n; ++k) {
-                    re[base + k * stride] = tr[k];
-                    im[base + k * stride] = ti[k];
-                }
-            }
+        free(tr);
+        free(ti);
+    }
 }
 
 /* Returns 1 if the state holds a non-finite value (then nothing is added). */
@@ -497,12 +540,8 @@ static int take_sample(const or_desc *d, const double *u, const double *ref,
     if (st->sk) {
         double *re = (double *)calloc((size_t)nc, sizeof(double));
         double *im = (double *)calloc((size_t)nc, sizeof(double));
-        int64_t nmax = d->n[0] > d->n[1] ? d->n[0] : d->n[1];
-        if (d->n[2] > nmax) nmax = d->n[2];
-        double *tr = (double *)malloc(sizeof(double) * (size_t)nmax);
-        double *ti = (double *)malloc(sizeof(double) * (size_t)nmax);
         for (int64_t i = 0; i < nc; ++i) re[i] = u[i];
-        for (int axis = 0; axis < d->dim; ++axis) dft_axis(d, axis, re, im, tr, ti);
+        for (int axis = 0; axis < d->dim; ++axis) dft_axis(d, axis, re, im);
         if (d->dim == 1) {
             for (int64_t k = 0; k < nc; ++k) st->sk[k] += re[k] * re[k] + im[k] * im[k];
         } else {
@@ -514,7 +553,7 @@ static int take_sample(const or_desc *d, const double *u, const double *ref,
                         if (b2 < st->n_bins) st->sk[b2] += re[i] * re[i] + im[i] * im[i];
                     }
         }
-        free(re); free(im); free(tr); free(ti);
+        free(re); free(im);
     }
     st->n_samples += 1;
     return 0;
@@ -632,10 +671,13 @@ int or_advance(const or_desc *d, double *u, int64_t step0, int64_t nsteps, or_st
                 cyclic_thomas(N, lo, di, up, us, u, work);
             }
         } else if (d->scheme == 0) {
+#pragma omp parallel for schedule(static) if (nc >= OR_PAR_MIN)
             for (int64_t i = 0; i < nc; ++i) u[i] = u[i] + div[i];
         } else {
+#pragma omp parallel for schedule(static) if (nc >= OR_PAR_MIN)
             for (int64_t i = 0; i < nc; ++i) us[i] = u[i] + div[i];
             divergence(d, us, z, flux, div, clamps);
+#pragma omp parallel for schedule(static) if (nc >= OR_PAR_MIN)
             for (int64_t i = 0; i < nc; ++i) u[i] = 0.5 * (u[i] + us[i] + div[i]);
         }
         const int64_t t = step0 + k + 1;
