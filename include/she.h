@@ -105,6 +105,15 @@ enum {
                                      kept on chip; results are the same bits */
 };
 
+/* she_config.flags */
+enum {
+    SHE_ALLOW_UNSTABLE = 1        /* create instances whose second moment grows
+                                     without bound (see she_create); their runs
+                                     end in a non-finite sample, SHE_ENONFINITE
+                                     and a frozen state.  For tests of that
+                                     path.                                    */
+};
+
 /* One instance (realisation) of the scheme.  Dirichlet walls only in 1D. */
 typedef struct {
     int32_t dim;          /* 1, 2, 3                                          */
@@ -154,8 +163,9 @@ typedef struct {
     int32_t precision;            /* SHE_F32 or SHE_F64 for the state         */
     const she_instance_desc *inst;/* n_instances entries, copied at create.
                                      1D instances may differ in every field;
-                                     2D/3D instances must share all fields
-                                     except seed and realisation              */
+                                     2D/3D instances must share the grid,
+                                     eq, scheme, noise, r, u0 and seed (eps,
+                                     init_sd and realisation may differ)     */
     int64_t burn_in;              /* sample after completed step t when
                                      t > burn_in and t % sample_every == 0    */
     int32_t sample_every;         /* >= 1                                      */
@@ -177,6 +187,15 @@ typedef struct {
                                      Results are identical.  Ignored in 1D.  */
     int32_t tcorr_lags;           /* TCORR: lags L in sampling intervals,
                                      1..1024 (0 without TCORR)               */
+    int32_t batch_samples;        /* batch-means error bars: samples per batch
+                                     L >= 1 (0: none).  Samples 1..L form batch
+                                     0, L+1..2L batch 1, ...; each statistic is
+                                     also formed per complete batch, and its
+                                     standard error is the standard deviation
+                                     of the B batch values (divisor B - 1) over
+                                     sqrt(B) (time averages after relaxation,
+                                     Sec. 3).  Needs stats_mask != 0.         */
+    uint32_t flags;               /* SHE_ALLOW_UNSTABLE, or 0                 */
     void *stream;                 /* hipStream_t (e.g. torch's current stream)*/
     void *arena;                  /* optional device memory for all buffers   */
     size_t arena_bytes;
@@ -206,12 +225,36 @@ typedef struct {
                                           (n, n-m) of dU_i(n) dU_i(n-m),
                                           mu_i = S1_i/M, M samples; NaN for
                                           m >= M                              */
+    /* Batch-means standard errors (she_config.batch_samples = L > 0): B =
+     * floor(M / L) complete batches, SE = sqrt(sum_b (x_b - xbar)^2 /
+     * (B (B - 1))) over the batch values x_b of the statistic, each formed
+     * like the statistic itself from the L samples of its batch; NaN while
+     * B < 2.  The statistics above use all M samples, the error bars the
+     * complete batches. */
+    int64_t n_batches;
+    double *mean_se; int64_t mean_se_cap; /* 1D + MOMENTS: N; nD: 1           */
+    double *var_se;  int64_t var_se_cap;  /* 1D + MOMENTS: N; nD: 1           */
+    double *sk_se;   int64_t sk_se_cap;   /* 1D + CORR: N; nD + SK: shells     */
+    double spatial_var;           /* time average over the samples of the
+                                     spatial variance of U (every dim; nD: =
+                                     var[0]): (1/n) sum_i dU_i^2 - ((1/n)
+                                     sum_i dU_i)^2 per sample, n cells       */
+    double spatial_var_se;        /* its standard error (NaN: no batches)      */
 } she_stats_out;
 
 /* Validate cfg, allocate device buffers, write the initial state (steady
- * profile + init_sd * N(tag 1)).  r > 1/(2 dim) is SHE_EUNSTABLE; periodic
- * with u_left != u_right or Dirichlet in 2D/3D is SHE_EINVAL (the paper's
- * program refuses a gradient with periodic walls). */
+ * profile + init_sd * N(tag 1)).  Errors:
+ *   - r > 1/(2 dim) (explicit schemes): SHE_EUNSTABLE;
+ *   - a periodic FE heat instance with instantaneous noise whose second
+ *     moment has no stationary value, eps * beta >= 1 with beta = (1/n)
+ *     sum over the modes k != 0 of h_k cos^2(pi k_x / n_x), h_k = 1 / (1 -
+ *     x_k / 2), x_k = 4 r sum_d sin^2(pi k_d / n_d) (n cells; the face
+ *     temperature's variance feeds the noise, stationary variance eps m^2
+ *     gamma / (1 - eps beta): FE scheme and noise of Sec. 3):
+ *     SHE_EUNSTABLE unless flags has SHE_ALLOW_UNSTABLE (other schemes and
+ *     boundaries are not checked; their divergence ends in SHE_ENONFINITE);
+ *   - periodic with u_left != u_right, or Dirichlet in 2D/3D: SHE_EINVAL
+ *     (the paper's program refuses a gradient with periodic walls). */
 she_status she_create(const she_config *cfg, she_handle **out);
 
 /* Bytes of device memory she_create needs for cfg (for a caller arena). */

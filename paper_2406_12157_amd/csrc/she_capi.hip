@@ -75,7 +75,8 @@ struct she_handle {
     void *d_a = nullptr, *d_b = nullptr;
     void *d_pred = nullptr;       // 3D PC: predictor field
     int cur = 0;                  // 0: state in d_a
-    uint32_t *d_real = nullptr;
+    InstND *d_ip = nullptr;       // per-instance parameters
+    std::vector<InstND> ip_host;
     double *d_part = nullptr;
     int nparts = 0, cx = 4, ty = 1, nd_blocks = 0;
     size_t smem3d = 0;
@@ -259,6 +260,37 @@ double varc_row_bound(const she_instance_desc &d)
     return worst;
 }
 
+// beta = (1/n) sum over the modes k != 0 of h_k cos^2(pi k_x / n_x) of a
+// periodic grid, h_k = 1 / (1 - x_k / 2), x_k = 4 r sum_d sin^2(pi k_d / n_d):
+// the face temperature's share of the FE stationary spectrum N eps m^2 h_k /
+// (1 - eps beta) that feeds the instantaneous noise back into itself (the
+// face value is the mean of the two cells, whose spectrum weight is
+// cos^2(pi k_x / n_x) for an x-face).  Modes k and n - k give the same
+// terms, so each axis runs over k <= n/2 with multiplicity 1 or 2.  Infinite
+// when a mode has x_k >= 2 (FE amplification -1: no damping at all).
+double fe_beta(const she_instance_desc &d)
+{
+    std::vector<double> s2[3], mult[3];
+    for (int a = 0; a < 3; ++a) {
+        const int n = a < d.dim ? d.n[a] : 1;
+        for (int k = 0; 2 * k <= n; ++k) {
+            const double s = std::sin(M_PI * k / n);
+            s2[a].push_back(s * s);
+            mult[a].push_back((k == 0 || 2 * k == n) ? 1.0 : 2.0);
+        }
+    }
+    double sum = 0.0;
+    for (size_t kz = 0; kz < s2[2].size(); ++kz)
+        for (size_t ky = 0; ky < s2[1].size(); ++ky)
+            for (size_t kx = 0; kx < s2[0].size(); ++kx) {
+                if (kx == 0 && ky == 0 && kz == 0) continue;
+                const double x = 4.0 * d.r * (s2[0][kx] + s2[1][ky] + s2[2][kz]);
+                if (x >= 2.0) return HUGE_VAL;
+                sum += mult[0][kx] * mult[1][ky] * mult[2][kz] * (1.0 - s2[0][kx]) / (1.0 - 0.5 * x);
+            }
+    return sum / (static_cast<double>(d.n[0]) * d.n[1] * d.n[2]);
+}
+
 size_t align256(size_t v) { return (v + 255) & ~static_cast<size_t>(255); }
 
 // Memory plan: a list of (pointer slot, bytes); carved in order from one block.
@@ -295,6 +327,10 @@ she_status validate(const she_config *cfg, she_handle *h)
                                          "size the arena for the tuned configuration");
     if (cfg->graph_steps < 0 || cfg->graph_steps > (1 << 16))
         return fail(nullptr, SHE_EINVAL, "graph_steps must be in [0, 65536]");
+    if (cfg->flags & ~static_cast<uint32_t>(SHE_ALLOW_UNSTABLE)) return fail(nullptr, SHE_EINVAL, "unknown flags bits");
+    if (cfg->batch_samples < 0) return fail(nullptr, SHE_EINVAL, "batch_samples must be >= 0");
+    if (cfg->batch_samples > 0 && cfg->stats_mask == 0)
+        return fail(nullptr, SHE_EINVAL, "batch_samples needs statistics (stats_mask != 0)");
     if (cfg->stats_mask & ~0x1Fu) return fail(nullptr, SHE_EINVAL, "unknown stats_mask bits");
     if (cfg->stats_mask & SHE_STAT_TCORR) {
         if (cfg->inst[0].dim != 1) return fail(nullptr, SHE_EUNSUPPORTED, "SHE_STAT_TCORR is provided for 1D");
@@ -304,6 +340,8 @@ she_status validate(const she_config *cfg, she_handle *h)
         return fail(nullptr, SHE_EINVAL, "tcorr_lags must be 0 without SHE_STAT_TCORR");
     }
     const int dim = cfg->inst[0].dim;
+    double beta_r = -1.0, beta_v = 0.0;     // last fe_beta: instances of a batch often share r and n
+    int beta_n[3] = {0, 0, 0};
     for (int i = 0; i < cfg->n_instances; ++i) {
         const she_instance_desc &d = cfg->inst[i];
         char buf[160];
@@ -339,6 +377,22 @@ she_status validate(const she_config *cfg, she_handle *h)
             return fail(nullptr, SHE_EINVAL, pre + "r, eps, init_sd must be >= 0 and values finite");
         if (!implicit && d.r > 0.5 / d.dim)
             return fail(nullptr, SHE_EUNSTABLE, pre + "r above the explicit stability limit 1/(2 dim)");
+        if (d.eq == SHE_HEAT && d.scheme == SHE_EM && d.bc == SHE_PERIODIC && d.noise == SHE_NOISE_INSTANT &&
+            d.eps > 0.0 && !d.cond && !d.cap && !(cfg->flags & SHE_ALLOW_UNSTABLE)) {
+            if (d.r != beta_r || d.n[0] != beta_n[0] || d.n[1] != beta_n[1] || d.n[2] != beta_n[2]) {
+                beta_v = fe_beta(d);
+                beta_r = d.r;
+                for (int a = 0; a < 3; ++a) beta_n[a] = d.n[a];
+            }
+            const double eb = d.eps * beta_v;
+            if (!(eb < 1.0)) {
+                char buf[200];
+                std::snprintf(buf, sizeof buf,
+                              "eps * beta = %.4g >= 1: the second moment of the FE scheme with instantaneous "
+                              "noise grows without bound (SHE_ALLOW_UNSTABLE to run it anyway)", eb);
+                return fail(nullptr, SHE_EUNSTABLE, pre + buf);
+            }
+        }
         if (d.bc == SHE_DIRICHLET && d.dim != 1)
             return fail(nullptr, SHE_EINVAL, pre + "Dirichlet walls are provided in 1D only");
         // the 2D predictor-corrector march reads two rows beyond its chunk and
@@ -628,10 +682,10 @@ static she_status plan_nd(she_handle *h, const she_config *cfg, Plan &plan)
     for (int i = 1; i < h->n_inst; ++i) {
         const she_instance_desc &d = h->inst[i];
         if (d.n[0] != d0.n[0] || d.n[1] != d0.n[1] || d.n[2] != d0.n[2] || d.eq != d0.eq || d.scheme != d0.scheme ||
-            d.noise != d0.noise || d.r != d0.r || d.eps != d0.eps || d.u0 != d0.u0 || d.init_sd != d0.init_sd ||
-            d.seed != d0.seed)
+            d.noise != d0.noise || d.r != d0.r || d.u0 != d0.u0 || d.seed != d0.seed)
             return fail(nullptr, SHE_EUNSUPPORTED,
-                        "2D/3D batches must share every field except the realisation number");
+                        "2D/3D batches must share the grid, equation, scheme, noise mode, r, u0 and seed "
+                        "(eps, init_sd and the realisation may differ)");
     }
     const int nx = d0.n[0];
     if (!is_pow2(nx) || nx < 8 || nx > 1024)
@@ -659,15 +713,23 @@ static she_status plan_nd(she_handle *h, const she_config *cfg, Plan &plan)
     p.n_inst = h->n_inst;
     p.xcd_order = (cfg->tuning_flags & SHE_TUNE_XCD_ORDER) ? 1 : 0;
     p.r = d0.r;
-    p.sigma = std::sqrt(2.0 * d0.r * d0.eps);
     p.u0 = d0.u0;
-    if (d0.noise == SHE_NOISE_FROZEN)
-        p.ns = p.sigma * (d0.eq == SHE_HEAT ? d0.u0 : std::sqrt(std::max(d0.u0, 0.0)));
-    else if (d0.noise == SHE_NOISE_INSTANT)
-        p.ns = d0.eq == SHE_HEAT ? 0.5 * p.sigma : p.sigma * std::sqrt(0.5);
-    else
-        p.ns = 0.0;
     p.seed = d0.seed;
+    h->ip_host.resize(h->n_inst);
+    for (int i = 0; i < h->n_inst; ++i) {
+        const she_instance_desc &d = h->inst[i];
+        const double sigma = std::sqrt(2.0 * d.r * d.eps);
+        InstND &q = h->ip_host[i];
+        if (d.noise == SHE_NOISE_FROZEN)
+            q.ns = sigma * (d.eq == SHE_HEAT ? d.u0 : std::sqrt(std::max(d.u0, 0.0)));
+        else if (d.noise == SHE_NOISE_INSTANT)
+            q.ns = d.eq == SHE_HEAT ? 0.5 * sigma : sigma * std::sqrt(0.5);
+        else
+            q.ns = 0.0;
+        q.init_sd = d.init_sd;
+        q.realisation = d.realisation;
+        q.pad = 0;
+    }
     h->cells = static_cast<int64_t>(p.nx) * p.ny * p.nz;
     if (d0.dim == 2) {
         // Default march length.  FE: about 16384 row groups in flight, 1..8 rows
@@ -713,7 +775,7 @@ static she_status plan_nd(she_handle *h, const she_config *cfg, Plan &plan)
     plan.add(&h->d_a, fbytes);
     plan.add(&h->d_b, fbytes);
     if (d0.dim == 3 && d0.scheme == SHE_HEUN) plan.add(&h->d_pred, fbytes);
-    plan.add(reinterpret_cast<void **>(&h->d_real), sizeof(uint32_t) * h->n_inst);
+    plan.add(reinterpret_cast<void **>(&h->d_ip), sizeof(InstND) * h->n_inst);
     plan.add(reinterpret_cast<void **>(&h->d_part), 2 * sizeof(double) * h->nparts * h->n_inst);
     plan.add(reinterpret_cast<void **>(&h->d_step), sizeof(int64_t));
     h->graph_steps = cfg->graph_steps;
@@ -956,7 +1018,6 @@ extern "C" she_status she_create(const she_config *cfg, she_handle **out)
     // stream synchronisation at the end of creation
     std::vector<double> sd(h->n_inst);
     std::vector<float> coef32;
-    std::vector<uint32_t> real;
     for (int i = 0; i < h->n_inst; ++i) sd[i] = h->inst[i].init_sd;
 #define CREATE_HIP(call)                                          \
     do {                                                          \
@@ -987,17 +1048,15 @@ extern "C" she_status she_create(const she_config *cfg, she_handle **out)
         }
         CREATE_HIP(launch_init1d(h->prec, h->n_inst, h->nmax, s, h->d_tab, h->d_init_sd, h->d_pool));
     } else {
-        real.resize(h->n_inst);
-        for (int i = 0; i < h->n_inst; ++i) real[i] = h->inst[i].realisation;
-        CREATE_HIP(hipMemcpyAsync(h->d_real, real.data(), sizeof(uint32_t) * h->n_inst, hipMemcpyHostToDevice, s));
-        h->pnd.realisation = h->d_real;
+        CREATE_HIP(hipMemcpyAsync(h->d_ip, h->ip_host.data(), sizeof(InstND) * h->n_inst, hipMemcpyHostToDevice, s));
+        h->pnd.ip = h->d_ip;
         if (h->d_skmodes) {
             CREATE_HIP(hipMemcpyAsync(h->d_skmodes, h->skmodes.data(), sizeof(double) * h->nbins,
                                       hipMemcpyHostToDevice, s));
             CREATE_HIP(launch_twiddles(h->prec, s, h->pnd.nx, h->d_twx));
             CREATE_HIP(launch_twiddles(h->prec, s, h->pnd.ny, h->d_twy));
         }
-        CREATE_HIP(launch_initnd(h->prec, s, h->pnd, h->cells, h->inst[0].init_sd, h->d_a));
+        CREATE_HIP(launch_initnd(h->prec, s, h->pnd, h->cells, h->d_a));
         h->cur = 0;
     }
     // staged host copies must stay valid until the stream has consumed them

@@ -108,7 +108,18 @@ __host__ __device__ inline SegLds seg_lds(int32_t n, int32_t nf, int32_t es, int
     return l;
 }
 
-// Parameters of a homogeneous 2D/3D batch.
+// Per-instance parameters of a 2D/3D batch (device table).
+struct InstND {
+    double ns;              // factor folded into the drawn numbers: sigma/2 (SHE),
+                            // sigma/sqrt(2) (DK), sigma A(u0) (deterministic face
+                            // value), 0 without noise; sigma = sqrt(2 r eps)
+    double init_sd;         // std. dev. of the initial perturbation
+    uint32_t realisation;   // Philox counter word 3
+    uint32_t pad;
+};
+
+// Parameters of a 2D/3D batch: one grid, scheme, r and u0; eps, init_sd
+// and the realisation per instance.
 struct ParamsND {
     int32_t nx, ny, nz;     // nz = 1 in 2D
     int32_t dim;
@@ -116,11 +127,9 @@ struct ParamsND {
     int32_t n_inst;
     int32_t chunk;          // rows (2D, along y) or planes (3D, along z) per march
     int32_t xcd_order;      // 1: give each XCD a contiguous range of workgroups
-    double r, sigma, u0;
-    double ns;              // factor folded into the drawn numbers: sigma/2 (SHE),
-                            // sigma/sqrt(2) (DK), sigma A(u0) (deterministic face value)
+    double r, u0;
     uint64_t seed;
-    const uint32_t *realisation;  // device, n_inst
+    const InstND *ip;       // device, n_inst
 };
 
 // Step index and sampling decision of one 2D/3D step.  Launched directly,
@@ -190,8 +199,7 @@ hipError_t launch_reduce_parts(int n_inst, hipStream_t s, const StepArg &st, con
 hipError_t launch_set_step(hipStream_t s, int64_t *ctr, int64_t value);
 hipError_t launch_add_step(hipStream_t s, int64_t *ctr, int64_t k);
 // nD initial state: u0 + init_sd * N(tag 1, step 0, face = cell) per instance.
-hipError_t launch_initnd(int prec, hipStream_t s, const ParamsND &p, int64_t cells,
-                         double init_sd, void *field);
+hipError_t launch_initnd(int prec, hipStream_t s, const ParamsND &p, int64_t cells, void *field);
 // nD finalisation of one instance: out[0] spatial mean, out[1] spatial variance,
 // out[2] sum(U), then (nbins > 0) out[3 + b] the shell average of <|U_k|^2>.
 hipError_t launch_finnd(int prec, hipStream_t s, const ParamsND &p, int inst, int64_t cells,

@@ -88,16 +88,17 @@ __global__ void __launch_bounds__(64)
 
 template <typename T>
 __global__ void __launch_bounds__(256)
-    k_initnd(ParamsND p, int64_t cells, double init_sd, T *__restrict__ field)
+    k_initnd(ParamsND p, int64_t cells, T *__restrict__ field)
 {
     const int inst = blockIdx.y;
     const int64_t c = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
     if (c >= cells) return;
     double v = p.u0;
-    if (init_sd > 0.0) {
+    const InstND ipar = p.ip[inst];
+    if (ipar.init_sd > 0.0) {
         const Normals4<double> nz = block_normals<double>(static_cast<uint32_t>(c >> 2), 0u, ctr_word2(0, 1u),
-                                                          p.realisation[inst], make_key(p.seed));
-        v += init_sd * nz.z[c & 3];
+                                                          ipar.realisation, make_key(p.seed));
+        v += ipar.init_sd * nz.z[c & 3];
     }
     field[static_cast<int64_t>(inst) * cells + c] = static_cast<T>(v);
 }
@@ -171,13 +172,13 @@ hipError_t launch_add_step(hipStream_t s, int64_t *ctr, int64_t k)
     return hipGetLastError();
 }
 
-hipError_t launch_initnd(int prec, hipStream_t s, const ParamsND &p, int64_t cells, double init_sd, void *field)
+hipError_t launch_initnd(int prec, hipStream_t s, const ParamsND &p, int64_t cells, void *field)
 {
     const dim3 grid(static_cast<unsigned>((cells + 255) / 256), p.n_inst);
     if (prec == 0)
-        hipLaunchKernelGGL(k_initnd<float>, grid, dim3(256), 0, s, p, cells, init_sd, static_cast<float *>(field));
+        hipLaunchKernelGGL(k_initnd<float>, grid, dim3(256), 0, s, p, cells, static_cast<float *>(field));
     else
-        hipLaunchKernelGGL(k_initnd<double>, grid, dim3(256), 0, s, p, cells, init_sd, static_cast<double *>(field));
+        hipLaunchKernelGGL(k_initnd<double>, grid, dim3(256), 0, s, p, cells, static_cast<double *>(field));
     return hipGetLastError();
 }
 

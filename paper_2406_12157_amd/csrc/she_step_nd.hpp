@@ -81,11 +81,12 @@ __device__ __forceinline__ T face_flux(T lo, T hi, T zs, uint32_t &clamps)
 }
 
 // Box-Muller radius constant of the normals a face flux takes: the noise
-// scale over r (the fluxes are carried divided by r; r = 0 has no noise).
+// scale ns of the instance over r (the fluxes are carried divided by r; r = 0
+// has no noise).
 template <typename T>
-__device__ __forceinline__ T flux_radius(const ParamsND &p)
+__device__ __forceinline__ T flux_radius(const ParamsND &p, double ns)
 {
-    return radius_const<T>(p.r > 0.0 ? p.ns / p.r : 0.0);
+    return radius_const<T>(p.r > 0.0 ? ns / p.r : 0.0);
 }
 
 __device__ __forceinline__ int wrap(int i, int n)
@@ -214,10 +215,11 @@ __global__ void __launch_bounds__(256)
     }
 
     const T r = static_cast<T>(p.r);
-    const T rc = flux_radius<T>(p);
+    const InstND ipar = p.ip[inst];
+    const T rc = flux_radius<T>(p, ipar.ns);
     uint32_t clamps = 0;
     const int noise = p.noise;
-    const uint32_t real = p.realisation[inst];
+    const uint32_t real = ipar.realisation;
     const PhiloxKey key = make_key(p.seed);
     const uint32_t slo = static_cast<uint32_t>(step), w2 = ctr_word2(static_cast<uint64_t>(step), 0u);
     // counter words of the following step (the second stage of a two-step march)
@@ -239,11 +241,20 @@ __global__ void __launch_bounds__(256)
         auto normals = [&](T (&z)[CX], uint32_t dr) __attribute__((always_inline)) {
             row_normals<T, CX, NZ>(z, dr, nq, q0, slo, w2, real, key, rc);
         };
-        auto flux = [&](T lo, T hi, T z) __attribute__((always_inline)) {
-            return face_flux<T, EQ, NZ>(lo, hi, z, clamps);
+        // Density clamps are counted once per face and stage, by the chunk that
+        // owns the face (the low faces of its rows); faces a chunk recomputes
+        // for its halo (own = false) are not counted.
+        auto flux = [&](T lo, T hi, T z, bool own = true) __attribute__((always_inline)) {
+            uint32_t c = 0;
+            const T f = face_flux<T, EQ, NZ>(lo, hi, z, c);
+            clamps += own ? c : 0u;
+            return f;
         };
-        auto xflux = [&](const T (&v)[CX], const T (&z)[CX], T (&fx)[CX], T &fxh) __attribute__((always_inline)) {
-            row_xflux<T, CX, EQ, NZ>(v, z, fx, fxh, lx, LX, clamps);
+        auto xflux = [&](const T (&v)[CX], const T (&z)[CX], T (&fx)[CX], T &fxh,
+                         bool own = true) __attribute__((always_inline)) {
+            uint32_t c = 0;
+            row_xflux<T, CX, EQ, NZ>(v, z, fx, fxh, lx, LX, c);
+            clamps += own ? c : 0u;
         };
         auto emit = [&](const T (&out)[CX], int y) __attribute__((always_inline)) {
             if (sample) accumulate<T, CX>(out, u0d, sa, sb);
@@ -287,7 +298,7 @@ __global__ void __launch_bounds__(256)
                     T z[CX], fx[CX], fxh, out[CX];
                     normals(z, drow(y + 1, 1));
 #pragma unroll
-                    for (int j = 0; j < CX; ++j) fhi[j] = flux(tc[j], tn[j], z[j]);
+                    for (int j = 0; j < CX; ++j) fhi[j] = flux(tc[j], tn[j], z[j], y + 1 < y1);
                     normals(z, drow(y, 0));
                     xflux(tc, z, fx, fxh);
 #pragma unroll
@@ -306,7 +317,7 @@ __global__ void __launch_bounds__(256)
                     load_row<T, CX>(rowp(y1 - 2), rb);
                     normals(z, drow(y1, 1));
 #pragma unroll
-                    for (int j = 0; j < CX; ++j) fa[j] = flux(ra[j], tu[j], z[j]);
+                    for (int j = 0; j < CX; ++j) fa[j] = flux(ra[j], tu[j], z[j], false);
                 }
                 // tc, tn: rows y, y-1; tq receives row y-2; fhi: high-y flux of row y
                 by6([&](const T (&tc)[CX], const T (&tn)[CX], T (&tq)[CX], const T (&fhi)[CX], T (&flo)[CX],
@@ -346,7 +357,7 @@ __global__ void __launch_bounds__(256)
                 load_row<T, CX>(rowp(k0 + 1), tb);
                 normals(z, drow(k0, 1));
 #pragma unroll
-                for (int j = 0; j < CX; ++j) pa[j] = flux(tp[j], ta[j], z[j]);
+                for (int j = 0; j < CX; ++j) pa[j] = flux(tp[j], ta[j], z[j], false);
             }
             auto row = [&](const T (&tc)[CX], const T (&tn)[CX], T (&tq)[CX], const T (&sc)[CX], T (&sn)[CX],
                            const T (&fpc)[CX], T (&fpn)[CX], const T (&fcm)[CX], T (&fcc)[CX],
@@ -356,15 +367,15 @@ __global__ void __launch_bounds__(256)
                 T z[CX], fx[CX], fxh;
                 normals(z, drow(k + 1, 1));
 #pragma unroll
-                for (int j = 0; j < CX; ++j) fpn[j] = flux(tc[j], tn[j], z[j]);
+                for (int j = 0; j < CX; ++j) fpn[j] = flux(tc[j], tn[j], z[j], k + 1 < y1);
                 normals(z, drow(k, 0));
-                xflux(tc, z, fx, fxh);
+                xflux(tc, z, fx, fxh, k >= y0 && k < y1);
 #pragma unroll
                 for (int j = 0; j < CX; ++j) sn[j] = fma(r, xdiv<T, CX>(fx, fxh, j) + (fpn[j] - fpc[j]), tc[j]);
                 if (i >= 1) {
                     normals1(z, drow(k, 1));
 #pragma unroll
-                    for (int j = 0; j < CX; ++j) fcc[j] = flux(sc[j], sn[j], z[j]);
+                    for (int j = 0; j < CX; ++j) fcc[j] = flux(sc[j], sn[j], z[j], k < y1);
                 }
                 if (i >= 2) {
                     normals1(z, drow(k - 1, 0));
@@ -404,7 +415,7 @@ __global__ void __launch_bounds__(256)
             load_row<T, CX>(rowp(k0 + 1), tcc);
             normals(ya, drow(k0, 1));
 #pragma unroll
-            for (int j = 0; j < CX; ++j) pa[j] = flux(ta[j], tb[j], ya[j]);
+            for (int j = 0; j < CX; ++j) pa[j] = flux(ta[j], tb[j], ya[j], false);
             auto row = [&](const T (&tm)[CX], const T (&tc)[CX], const T (&tn)[CX], T (&tq)[CX], const T (&sc)[CX],
                            T (&sn)[CX], const T (&zyc)[CX], T (&zyn)[CX], const T (&zxm)[CX], T (&zxc)[CX],
                            const T (&fpc)[CX], T (&fpn)[CX], const T (&fcm)[CX], T (&fcc)[CX],
@@ -413,15 +424,15 @@ __global__ void __launch_bounds__(256)
                 load_row<T, CX>(rowp(k + 2), tq);
                 normals(zyn, drow(k + 1, 1));
 #pragma unroll
-                for (int j = 0; j < CX; ++j) fpn[j] = flux(tc[j], tn[j], zyn[j]);
+                for (int j = 0; j < CX; ++j) fpn[j] = flux(tc[j], tn[j], zyn[j], k + 1 >= y0 && k + 1 < y1);
                 normals(zxc, drow(k, 0));
                 T fx[CX], fxh;
-                xflux(tc, zxc, fx, fxh);
+                xflux(tc, zxc, fx, fxh, k >= y0 && k < y1);
 #pragma unroll
                 for (int j = 0; j < CX; ++j) sn[j] = fma(r, xdiv<T, CX>(fx, fxh, j) + (fpn[j] - fpc[j]), tc[j]);
                 if (i >= 1) {
 #pragma unroll
-                    for (int j = 0; j < CX; ++j) fcc[j] = flux(sc[j], sn[j], zyc[j]);
+                    for (int j = 0; j < CX; ++j) fcc[j] = flux(sc[j], sn[j], zyc[j], k < y1);
                 }
                 if (i >= 2) {
                     // corrected row k-1 from predictor rows k-2 (fcm), k-1 (sc), k (sn)
@@ -512,10 +523,11 @@ __global__ void __launch_bounds__(256)
     const int cell0 = CX * lx;
 
     const T r = static_cast<T>(p.r);
-    const T rc = flux_radius<T>(p);
+    const InstND ipar = p.ip[inst];
+    const T rc = flux_radius<T>(p, ipar.ns);
     uint32_t clamps = 0;
     const int noise = p.noise;
-    const uint32_t real = p.realisation[inst];
+    const uint32_t real = ipar.realisation;
     const PhiloxKey key = make_key(p.seed);
     const uint32_t slo = static_cast<uint32_t>(step), w2 = ctr_word2(static_cast<uint64_t>(step), 0u);
     const uint32_t nq = static_cast<uint32_t>(nx / 4), q0 = static_cast<uint32_t>((CX / 4) * lx);
@@ -534,8 +546,13 @@ __global__ void __launch_bounds__(256)
         auto normals = [&](T (&z)[CX], uint32_t dr) __attribute__((always_inline)) {
             row_normals<T, CX, NZ>(z, dr, nq, q0, slo, w2, real, key, rc);
         };
-        auto flux = [&](T lo, T hi, T z) __attribute__((always_inline)) {
-            return face_flux<T, EQ, NZ>(lo, hi, z, clamps);
+        // clamps counted by the owner of each face (the low faces of the
+        // tile's rows and planes), as in 2D
+        auto flux = [&](T lo, T hi, T z, bool own = true) __attribute__((always_inline)) {
+            uint32_t c = 0;
+            const T f = face_flux<T, EQ, NZ>(lo, hi, z, c);
+            clamps += own ? c : 0u;
+            return f;
         };
         T ra[CX], rb[CX], rq[CX], fa[CX], fb[CX];
         {
@@ -560,7 +577,7 @@ __global__ void __launch_bounds__(256)
             T z[CX];
             normals(z, drow(y, zi + 1, 2));
 #pragma unroll
-            for (int j = 0; j < CX; ++j) fzhi[j] = flux(tc[j], tn[j], z[j]);
+            for (int j = 0; j < CX; ++j) fzhi[j] = flux(tc[j], tn[j], z[j], zi + 1 < z1);
 
             T fxlo[CX], fxhi;
             normals(z, drow(y, zi, 0));
@@ -596,7 +613,7 @@ __global__ void __launch_bounds__(256)
                 load_row<T, CX>(S + rowp(y + 1, zi), yhi);
                 normals(z, drow(y + 1, zi, 1));
 #pragma unroll
-                for (int j = 0; j < CX; ++j) fyhi[j] = flux(tc[j], yhi[j], z[j]);
+                for (int j = 0; j < CX; ++j) fyhi[j] = flux(tc[j], yhi[j], z[j], false);
             }
             T out[CX];
             if constexpr (STAGE == 0) {

@@ -25,6 +25,7 @@ STAT_MOMENTS, STAT_CORR, STAT_SK, STAT_SPATIAL, STAT_TCORR = 1, 2, 4, 8, 16
 TUNE_XCD_ORDER = 1
 TUNE_SEARCH = 2
 TUNE_SINGLE_STEP = 4
+ALLOW_UNSTABLE = 1
 
 OK, EINVAL, EUNSTABLE, ENOMEM, EDEVICE, ENONFINITE, ESTATE, EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6, -7
 _NAMES = {0: "SHE_OK", -1: "SHE_EINVAL", -2: "SHE_EUNSTABLE", -3: "SHE_ENOMEM", -4: "SHE_EDEVICE",
@@ -51,6 +52,7 @@ class Config(C.Structure):
                 ("burn_in", C.c_int64), ("sample_every", C.c_int32), ("stats_mask", C.c_uint32),
                 ("block_threads", C.c_int32), ("rows_per_block", C.c_int32), ("rows_per_group", C.c_int32),
                 ("tuning_flags", C.c_int32), ("graph_steps", C.c_int32), ("tcorr_lags", C.c_int32),
+                ("batch_samples", C.c_int32), ("flags", C.c_uint32),
                 ("stream", C.c_void_p), ("arena", C.c_void_p),
                 ("arena_bytes", C.c_size_t)]
 
@@ -63,7 +65,12 @@ class StatsOut(C.Structure):
                 ("sk", C.POINTER(C.c_double)), ("sk_cap", C.c_int64),
                 ("sk_modes", C.POINTER(C.c_double)), ("sk_modes_cap", C.c_int64),
                 ("sum_u", C.c_double), ("nonfinite", C.c_int32), ("reserved", C.c_int32),
-                ("clamp_count", C.c_int64), ("tcorr", C.POINTER(C.c_double)), ("tcorr_cap", C.c_int64)]
+                ("clamp_count", C.c_int64), ("tcorr", C.POINTER(C.c_double)), ("tcorr_cap", C.c_int64),
+                ("n_batches", C.c_int64),
+                ("mean_se", C.POINTER(C.c_double)), ("mean_se_cap", C.c_int64),
+                ("var_se", C.POINTER(C.c_double)), ("var_se_cap", C.c_int64),
+                ("sk_se", C.POINTER(C.c_double)), ("sk_se_cap", C.c_int64),
+                ("spatial_var", C.c_double), ("spatial_var_se", C.c_double)]
 
 
 EXPORTS = ["she_create", "she_arena_bytes", "she_tune", "she_step", "she_run", "she_stats", "she_reset_stats",
@@ -182,7 +189,8 @@ class Handle:
 
     def __init__(self, instances, precision: int = F32, burn_in: int = 0, sample_every: int = 10,
                  stats: int = 0, stream=None, arena=None, block_threads: int = 0, rows_per_block: int = 0,
-                 rows_per_group: int = 0, tuning_flags: int = 0, graph_steps: int = 0, tcorr_lags: int = 0):
+                 rows_per_group: int = 0, tuning_flags: int = 0, graph_steps: int = 0, tcorr_lags: int = 0,
+                 batch_samples: int = 0, flags: int = 0):
         self.lib = load()
         self.instances = list(instances)
         self._descs = (InstanceDesc * len(self.instances))(*[i.c() for i in self.instances])
@@ -192,7 +200,7 @@ class Handle:
         self._arena = arena
         cfg = Config(len(self.instances), precision, self._descs, burn_in, sample_every, stats,
                      block_threads, rows_per_block, rows_per_group, tuning_flags, graph_steps, tcorr_lags,
-                     C.c_void_p(stream) if stream else None, None, 0)
+                     batch_samples, flags, C.c_void_p(stream) if stream else None, None, 0)
         if arena is not None:
             cfg.arena = C.c_void_p(arena.data_ptr())
             cfg.arena_bytes = arena.numel() * arena.element_size()
@@ -205,12 +213,14 @@ class Handle:
 
     @staticmethod
     def arena_bytes(instances, precision=F32, burn_in=0, sample_every=10, stats=0, block_threads=0,
-                    rows_per_block=0, rows_per_group=0, tuning_flags=0, graph_steps=0, tcorr_lags=0) -> int:
+                    rows_per_block=0, rows_per_group=0, tuning_flags=0, graph_steps=0, tcorr_lags=0,
+                    batch_samples=0, flags=0) -> int:
         lib = load()
         insts = list(instances)
         descs = (InstanceDesc * len(insts))(*[i.c() for i in insts])
         cfg = Config(len(insts), precision, descs, burn_in, sample_every, stats, block_threads,
-                     rows_per_block, rows_per_group, tuning_flags, graph_steps, tcorr_lags, None, None, 0)
+                     rows_per_block, rows_per_group, tuning_flags, graph_steps, tcorr_lags, batch_samples, flags,
+                     None, None, 0)
         out = C.c_size_t()
         _check(lib.she_arena_bytes(C.byref(cfg), C.byref(out)))
         return int(out.value)
@@ -226,7 +236,7 @@ class Handle:
         if stream is None:
             stream = current_stream()
         cfg = Config(len(insts), precision, descs, 0, 10, stats, block_threads, rows_per_block, rows_per_group,
-                     tuning_flags, 0, 0, C.c_void_p(stream) if stream else None, None, 0)
+                     tuning_flags, 0, 0, 0, 0, C.c_void_p(stream) if stream else None, None, 0)
         out = Config()
         _check(lib.she_tune(C.byref(cfg), int(steps), C.byref(out)))
         return dict(block_threads=int(out.block_threads), rows_per_block=int(out.rows_per_block),

@@ -181,3 +181,50 @@ def test_ragged_batch_plan_accepts_c4():
     b = she.Handle.arena_bytes([gpu_instance(she, i) for i in c4["instances"]], stats=she.STAT_MOMENTS)
     total = sum(i["n"][0] for i in c4["instances"])
     assert b >= total * (4 + 16)
+
+
+def test_second_moment_stability_check_at_create():
+    """A periodic FE heat instance with instantaneous noise has a stationary
+    variance only while eps * beta < 1 (beta: the face temperature's share of
+    the FE spectrum, computed here by theory.gamma_beta over the full mode
+    grid).  The literal c1 (eps = 100) is refused with SHE_EUNSTABLE unless
+    SHE_ALLOW_UNSTABLE is set; eps on either side of 1/beta decides it, in
+    1D, 2D and 3D.  PC, Dirichlet and species instances are not checked."""
+    import theory
+    lit = W.c1(eps=100.0)["instances"][0]
+    with pytest.raises(she.SheError) as e:
+        she.Handle.arena_bytes([gpu_instance(she, lit)])
+    assert e.value.status == she.EUNSTABLE
+    she.Handle.arena_bytes([gpu_instance(she, lit)], flags=she.ALLOW_UNSTABLE)
+    she.Handle.arena_bytes([gpu_instance(she, W.c1()["instances"][0])])            # eps = 1e-2
+    for n, r in (((64,), 0.2), ((32, 16), 0.1), ((16, 8, 8), 0.05)):
+        _, beta = theory.gamma_beta(r, n)
+        she.Handle.arena_bytes([gpu_instance(she, W.instance(n, r=r, eps=0.999 / beta))])
+        with pytest.raises(she.SheError) as e:
+            she.Handle.arena_bytes([gpu_instance(she, W.instance(n, r=r, eps=1.001 / beta))])
+        assert e.value.status == she.EUNSTABLE, n
+    for kw in (dict(scheme=W.HEUN), dict(eq=W.SPECIES, u0=100.0), dict(noise=1), dict(noise=2)):
+        she.Handle.arena_bytes([gpu_instance(she, W.instance((64,), r=0.2, eps=100.0, **kw))])
+    she.Handle.arena_bytes([gpu_instance(she, W.instance((64,), bc=W.DIRICHLET, r=0.2, eps=100.0))])
+    with pytest.raises(she.SheError) as e:
+        she.Handle.arena_bytes([gpu_instance(she, W.c1()["instances"][0])], flags=2)
+    assert e.value.status == she.EINVAL
+
+
+def test_nd_batches_may_differ_in_eps_and_init_sd_only():
+    a = W.instance((64, 32), r=0.1, eps=1e-2, init_sd=0.1, realisation=0)
+    ok = [a, dict(a, eps=3e-2, realisation=1), dict(a, init_sd=0.0, realisation=2)]
+    she.Handle.arena_bytes([gpu_instance(she, i) for i in ok])
+    for bad in (dict(a, u0=2.0, u_left=2.0, u_right=2.0), dict(a, seed=4), dict(a, noise=1), dict(a, scheme=W.HEUN)):
+        with pytest.raises(she.SheError) as e:
+            she.Handle.arena_bytes([gpu_instance(she, a), gpu_instance(she, bad)])
+        assert e.value.status == she.EUNSUPPORTED, bad
+
+
+def test_batch_samples_settings():
+    one = [gpu_instance(she, W.instance((64,), r=0.2))]
+    she.Handle.arena_bytes(one, stats=she.STAT_MOMENTS, batch_samples=100)
+    for kw in (dict(stats=she.STAT_MOMENTS, batch_samples=-1), dict(batch_samples=10)):
+        with pytest.raises(she.SheError) as e:
+            she.Handle.arena_bytes(one, **kw)
+        assert e.value.status == she.EINVAL, kw

@@ -119,3 +119,25 @@ def test_c5_full_size(she):
     want = inst["u0"] * inst["eps"] * gamma
     assert abs(g["var"][0] / want - 1) < 0.01, (g["var"][0], want)
     assert abs(g["var"][0] / (inst["u0"] * inst["eps"]) - 1) > 0.1
+
+
+def test_c3_benchmark_launch_state_after_1e4_steps(she):
+    """The benchmark's own handle (bench.make_handle: 512 x 512 x 256
+    realisations, two FE steps per launch in 32-row march chunks, spatial
+    statistics and S(k) every 10 steps) runs the stated 1e4 steps; the last
+    realisation's field then matches the FP64 oracle started from the same
+    field, cell by cell (state max-rel <= 1e-5 after 1e4 steps)."""
+    import bench
+    oracle.set_threads(0)
+    cfg = W.c3()
+    h, _ = bench.make_handle(she, cfg, she.STAT_SPATIAL | she.STAT_SK)
+    q = len(cfg["instances"]) - 1
+    u = h.read_field(q)
+    h.run(cfg["steps"])
+    got = h.read_field(q)
+    assert h.stats(q)["n_samples"] == cfg["steps"] // cfg["sample_every"]
+    h.close()
+    oracle.advance(oracle_desc(cfg["instances"][q], 0), u, 0, cfg["steps"])
+    err = max_rel(got, u)
+    print("c3 realisation %d after %d steps: max-rel %.3e" % (q, cfg["steps"], err), flush=True)
+    assert err <= 1e-5

@@ -427,8 +427,7 @@ def inst3d(n, eq, realisation=0, scheme=W.EM):
 def test_3d_fp32_state_parity(she, case):
     n, eq = case
     insts = [inst3d(n, eq, realisation=q) for q in range(2)]
-    steps = 2000 if np.prod(n) <= 2048 else 300
-    _, got, want = run_both(she, insts, steps, 0, rows_per_block=3)
+    _, got, want = run_both(she, insts, 10000, 0, rows_per_block=3)
     for q in range(2):
         err = max_rel(got[q], want[q])
         assert err <= 1e-5, (q, err)
@@ -440,8 +439,7 @@ def test_3d_pc_state_parity(she, case):
     # drawing the same numbers again from the step's counters
     n, eq = case
     insts = [inst3d(n, eq, realisation=q, scheme=W.HEUN) for q in range(2)]
-    steps = 2000 if np.prod(n) <= 2048 else 300
-    _, got, want = run_both(she, insts, steps, 0, rows_per_block=3)
+    _, got, want = run_both(she, insts, 10000, 0, rows_per_block=3)
     for q in range(2):
         err = max_rel(got[q], want[q])
         assert err <= 1e-5, (q, err)
@@ -449,7 +447,7 @@ def test_3d_pc_state_parity(she, case):
 
 def test_3d_pc_fp64_parity_and_graph_replay(she):
     inst = inst3d((16, 8, 8), W.SPECIES, scheme=W.HEUN)
-    _, got, want = run_both(she, [inst], 500, 1)
+    _, got, want = run_both(she, [inst], 10000, 1)
     assert max_rel(got[0], want[0]) <= 1e-12
     outs = []
     for gs in (0, 8):
@@ -678,7 +676,7 @@ def test_checkpoint_resume_is_bit_exact(she):
 def test_literal_eps_diverges_and_freezes(she):
     cfg = W.c1(eps=100.0)
     h = she.Handle([gpu_instance(she, i) for i in cfg["instances"]], precision=1, burn_in=0, sample_every=10,
-                   stats=she.STAT_MOMENTS)
+                   stats=she.STAT_MOMENTS, flags=she.ALLOW_UNSTABLE)
     h.run(20000)
     with pytest.raises(she.SheError) as e:
         h.stats(0)
@@ -701,14 +699,15 @@ def test_freeze_inside_a_shared_workgroup(she):
     good = W.instance((96,), bc=W.DIRICHLET, scheme=W.HEUN, r=0.05, eps=1e-3, u0=1.0, u_left=1.1, u_right=0.9,
                       init_sd=0.03, realisation=7)
     steps = 20000
-    alone = she.Handle([gpu_instance(she, bad)], precision=1, burn_in=0, sample_every=10, stats=she.STAT_MOMENTS)
+    alone = she.Handle([gpu_instance(she, bad)], precision=1, burn_in=0, sample_every=10, stats=she.STAT_MOMENTS,
+                       flags=she.ALLOW_UNSTABLE)
     alone.run(steps)
     s_alone = alone.stats(0, raise_nonfinite=False)
     f_alone = alone.read_field(0)
     alone.close()
     assert s_alone["nonfinite"]
     h = she.Handle([gpu_instance(she, bad), gpu_instance(she, good)], precision=1, burn_in=0, sample_every=10,
-                   stats=she.STAT_MOMENTS, block_threads=256)
+                   stats=she.STAT_MOMENTS, block_threads=256, flags=she.ALLOW_UNSTABLE)
     init = h.read_field(1)
     h.run(steps)
     s_bad = h.stats(0, raise_nonfinite=False)
@@ -758,3 +757,119 @@ def test_degenerate_parameters(she, n, scheme, eq):
         runs.append(h.read_field(0))
         h.close()
     np.testing.assert_allclose(runs[0], runs[1], rtol=1e-6, atol=0)
+
+
+# ---------------------------------------------------------------- initial state, freeze, clamps
+
+INIT_CASES = [
+    # (n, bc, eq, u_left, u_right, u0, init_sd per instance)
+    ((97,), W.PERIODIC, W.HEAT, 1.0, 1.0, 1.0, (0.1, 0.02)),
+    ((130,), W.DIRICHLET, W.HEAT, 1.1, 0.9, 1.0, (0.03, 0.0)),
+    ((5001,), W.DIRICHLET, W.SPECIES, 80.0, 130.0, 100.0, (10.0, 3.0)),
+    ((64, 48), W.PERIODIC, W.HEAT, 1.0, 1.0, 1.0, (0.1, 0.05)),
+    ((32, 16), W.PERIODIC, W.SPECIES, 200.0, 200.0, 200.0, (14.0, 0.0)),
+    ((16, 8, 8), W.PERIODIC, W.SPECIES, 1000.0, 1000.0, 1000.0, (31.6, 10.0)),
+    ((32, 4, 6), W.PERIODIC, W.HEAT, 1.0, 1.0, 1.0, (0.1, 0.2)),
+]
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+@pytest.mark.parametrize("case", INIT_CASES, ids=lambda c: "x".join(map(str, c[0])) + "-bc%d-eq%d" % c[1:3])
+def test_gpu_init_matches_oracle(she, case, precision):
+    """The field straight after she_create is the steady profile (u0, or the
+    linear Dirichlet profile) plus init_sd N(tag 1, step 0, face = cell),
+    element by element against the oracle's initial state: FP64 to 1e-15
+    relative; FP32 equal to the FP64 value rounded to FP32 (within one FP32
+    ulp, where the two FP64 values straddle a rounding boundary)."""
+    n, bc, eq, ul, ur, u0, sds = case
+    insts = [W.instance(n, eq=eq, bc=bc, r=0.05, eps=1e-2 if eq == W.HEAT else 1.0, u0=u0, u_left=ul, u_right=ur,
+                        init_sd=sd, seed=11 + (q if len(n) == 1 else 0), realisation=3 + 5 * q)
+             for q, sd in enumerate(sds)]
+    h = she.Handle([gpu_instance(she, i) for i in insts], precision=precision)
+    for q, inst in enumerate(insts):
+        got = h.read_field(q)
+        want = oracle.init(oracle_desc(inst, 1))
+        if inst["init_sd"] > 0:
+            assert np.std(want - oracle.reference(oracle_desc(inst, 1))) > 0.5 * inst["init_sd"]
+        if precision == 1:
+            assert max_rel(got, want) <= 1e-15, (q, max_rel(got, want))
+        else:
+            w32 = want.astype(np.float32)
+            ulps = np.abs(got.astype(np.float32).view(np.int32) - w32.view(np.int32))
+            assert ulps.max() <= 1, q
+            assert np.mean(ulps == 0) > 0.999, q
+    h.close()
+
+
+@pytest.mark.parametrize("n,scheme", [((64, 32), W.EM), ((32, 16), W.HEUN), ((16, 8, 8), W.EM),
+                                      ((16, 8, 8), W.HEUN)], ids=["2d-fe", "2d-pc", "3d-fe", "3d-pc"])
+def test_nd_freeze_beside_healthy_instances(she, n, scheme):
+    """A 2D / 3D instance with a large eps (eps beta >> 1, SHE_ALLOW_UNSTABLE)
+    diverges and freezes at the first sample that meets a non-finite value:
+    SHE_ENONFINITE, its samples stop, and later steps leave its field as it
+    was.  The healthy instances of the same batch step on through the frozen
+    one's launches and match the oracle; the frozen field and sample count
+    equal those of the diverging instance run alone."""
+    base = (inst2d(n, scheme, W.HEAT) if len(n) == 2 else inst3d(n, W.HEAT, scheme=scheme))
+    good = [dict(base, realisation=q) for q in (0, 2)]
+    bad = dict(base, eps=40.0, realisation=1)
+    steps, every = 1500, 5
+    kw = dict(precision=0, burn_in=0, sample_every=every, stats=she.STAT_SPATIAL, flags=she.ALLOW_UNSTABLE)
+    alone = she.Handle([gpu_instance(she, bad)], **kw)
+    alone.run(steps)
+    s_alone = alone.stats(0, raise_nonfinite=False)
+    f_alone = alone.read_field(0)
+    alone.close()
+    assert s_alone["nonfinite"] and 0 < s_alone["n_samples"] < steps // every
+    assert not np.all(np.isfinite(f_alone))
+    insts = [good[0], bad, good[1]]
+    h = she.Handle([gpu_instance(she, i) for i in insts], **kw)
+    init = [h.read_field(q) for q in range(3)]
+    h.run(steps)
+    with pytest.raises(she.SheError) as e:
+        h.stats(1)
+    assert e.value.status == she.ENONFINITE
+    s_bad = h.stats(1, raise_nonfinite=False)
+    assert s_bad["n_samples"] == s_alone["n_samples"]
+    frozen = h.read_field(1)
+    np.testing.assert_array_equal(frozen, f_alone)
+    for q in (0, 2):
+        g = h.stats(q)
+        assert not g["nonfinite"] and g["n_samples"] == steps // every
+        u = init[q].copy()
+        oracle.advance(oracle_desc(insts[q], 0), u, 0, steps)
+        assert max_rel(h.read_field(q), u) <= 1e-5, q
+    h.run(40)
+    np.testing.assert_array_equal(h.read_field(1), frozen)
+    assert h.stats(1, raise_nonfinite=False)["n_samples"] == s_alone["n_samples"]
+    h.close()
+
+
+@pytest.mark.parametrize("n,scheme", [((32, 24), W.EM), ((32, 24), W.HEUN), ((16, 8, 6), W.EM),
+                                      ((16, 8, 6), W.HEUN)], ids=["2d-fe", "2d-pc", "3d-fe", "3d-pc"])
+def test_nd_clamp_count_matches_oracle(she, n, scheme):
+    """Dean-Kawasaki at a low density (u0 = 2 per cell, eps = 1/dV = 1) has
+    negative face means: every face and stage that meets one is clamped and
+    counted once, as the oracle counts them, whatever the march length,
+    tiling or number of steps per launch (FP64 state: the same signs)."""
+    inst = W.instance(n, eq=W.SPECIES, scheme=scheme, r=0.05, eps=1.0, u0=2.0, init_sd=1.0, realisation=4)
+    steps = 120
+    u = None
+    counts = []
+    shapes = [dict(rows_per_block=1), dict(rows_per_block=5), dict(), dict(tuning_flags=she.TUNE_SINGLE_STEP)]
+    if len(n) == 3:
+        shapes = [dict(rows_per_block=1, rows_per_group=1), dict(rows_per_block=4, rows_per_group=2),
+                  dict(rows_per_block=3, rows_per_group=8), dict()]
+    for kw in shapes:
+        h = she.Handle([gpu_instance(she, inst)], precision=1, **kw)
+        if u is None:
+            u = h.read_field(0)
+        for k in (7, 50, 63):
+            h.step(k)
+        counts.append(h.stats(0)["clamp_count"])
+        h.close()
+    d = oracle_desc(inst, 1)
+    st = oracle.Stats(d, burn_in=steps, every=1, per_cell=False)
+    oracle.advance(d, u, 0, steps, st)
+    assert st.clamp_count > 100
+    assert counts == [st.clamp_count] * len(shapes), (counts, st.clamp_count)
