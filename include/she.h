@@ -320,6 +320,20 @@ she_status she_debug_normals(uint64_t seed, uint32_t realisation, uint32_t tag,
                              uint64_t step, uint64_t face0, int64_t count,
                              int32_t precision, double *out, void *stream);
 
+/* she_debug_normals without any device allocation, for callers that cannot
+ * allocate (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc): the numbers are staged in a fixed device array of
+ * SHE_NOALLOC_MAX_NORMALS doubles that the library holds on each GPU it runs
+ * on until the process ends, instead of a buffer allocated per call.  Same
+ * arguments, same values bit for bit; count > SHE_NOALLOC_MAX_NORMALS is
+ * SHE_EINVAL.  Every call on one GPU shares that array (the last call's
+ * numbers stay in it): calls that overlap on one GPU, from several threads
+ * or on several streams, race; serialise them.  Synchronises `stream`. */
+#define SHE_NOALLOC_MAX_NORMALS (1 << 20)
+she_status she_debug_normals_noalloc(uint64_t seed, uint32_t realisation, uint32_t tag,
+                                     uint64_t step, uint64_t face0, int64_t count,
+                                     int32_t precision, double *out, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -1525,6 +1525,63 @@ extern "C" she_status she_debug_philox(uint64_t seed, const uint32_t *ctr, int64
     return SHE_OK;
 }
 
+// Staging array of she_debug_normals_noalloc: one per GPU for the life of the
+// process.  Host code never uses its name as an address; it takes the device
+// address from hipGetSymbolAddress, once per device, with that device current.
+static __device__ __align__(256) double scratch[SHE_NOALLOC_MAX_NORMALS];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device (nullptr with *err set).
+void *scratch_address(hipError_t *err)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) {
+        *err = e;
+        return nullptr;
+    }
+    if (dev < 0 || dev >= kMaxDevices) {
+        *err = hipErrorInvalidDevice;
+        return nullptr;
+    }
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            *err = e != hipSuccess ? e : hipErrorInvalidSymbol;
+            return nullptr;
+        }
+        g_scratch_ptr[dev] = p;
+    }
+    return g_scratch_ptr[dev];
+}
+}  // namespace
+
+extern "C" she_status she_debug_normals_noalloc(uint64_t seed, uint32_t realisation, uint32_t tag, uint64_t step,
+                                                uint64_t face0, int64_t count, int32_t precision, double *out,
+                                                void *stream)
+{
+    if (!out || count < 0 || (precision != SHE_F32 && precision != SHE_F64))
+        return fail(nullptr, SHE_EINVAL, "bad argument");
+    if (count > SHE_NOALLOC_MAX_NORMALS)
+        return fail(nullptr, SHE_EINVAL, "she_debug_normals_noalloc: count above SHE_NOALLOC_MAX_NORMALS");
+    if (count == 0) return SHE_OK;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipError_t e = hipSuccess;
+    double *dout = static_cast<double *>(scratch_address(&e));
+    if (dout) e = launch_debug_normals(s, precision, seed, realisation, tag, step, face0, count, dout);
+    if (e == hipSuccess) e = hipMemcpyAsync(out, dout, sizeof(double) * count, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess)
+        return fail(nullptr, SHE_EDEVICE, std::string("debug_normals_noalloc: ") + hipGetErrorString(e));
+    return SHE_OK;
+}
+
 extern "C" she_status she_debug_normals(uint64_t seed, uint32_t realisation, uint32_t tag, uint64_t step,
                                         uint64_t face0, int64_t count, int32_t precision, double *out, void *stream)
 {

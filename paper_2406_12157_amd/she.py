@@ -75,7 +75,9 @@ class StatsOut(C.Structure):
 
 EXPORTS = ["she_create", "she_arena_bytes", "she_tune", "she_step", "she_run", "she_stats", "she_reset_stats",
            "she_read_field", "she_write_field", "she_get_step", "she_state_bytes", "she_get_state",
-           "she_set_state", "she_last_error", "she_destroy", "she_debug_philox", "she_debug_normals"]
+           "she_set_state", "she_last_error", "she_destroy", "she_debug_philox", "she_debug_normals",
+           "she_debug_normals_noalloc"]
+NOALLOC_MAX_NORMALS = 1 << 20
 
 _lib = None
 
@@ -109,6 +111,7 @@ def load(path: str = LIB_PATH):
     lib.she_debug_philox.argtypes = [C.c_uint64, P(C.c_uint32), C.c_int64, P(C.c_uint32), C.c_void_p]
     lib.she_debug_normals.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint64, C.c_uint64, C.c_int64,
                                       C.c_int32, P(C.c_double), C.c_void_p]
+    lib.she_debug_normals_noalloc.argtypes = lib.she_debug_normals.argtypes
     for name in EXPORTS:
         if name not in ("she_last_error", "she_destroy"):
             getattr(lib, name).restype = C.c_int
@@ -354,4 +357,16 @@ def debug_normals(seed: int, realisation: int, tag: int, step: int, face0: int, 
     out = np.zeros(count)
     _check(lib.she_debug_normals(seed, realisation, tag, step, face0, count, precision, _dptr(out),
                                  C.c_void_p(stream) if stream else None))
+    return out
+
+
+def debug_normals_noalloc(seed: int, realisation: int, tag: int, step: int, face0: int, count: int,
+                          precision: int = F32, stream=None) -> np.ndarray:
+    """she_debug_normals_noalloc: the same numbers, staged in the library's
+    fixed per-GPU array (count <= NOALLOC_MAX_NORMALS) instead of an
+    allocation."""
+    lib = load()
+    out = np.zeros(count)
+    _check(lib.she_debug_normals_noalloc(seed, realisation, tag, step, face0, count, precision, _dptr(out),
+                                         C.c_void_p(stream) if stream else None))
     return out
