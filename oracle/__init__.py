@@ -65,7 +65,10 @@ class _Stats(C.Structure):
                 ("sp_mean", C.c_double), ("sp_sq", C.c_double), ("sp_var", C.c_double),
                 ("clamp_count", C.c_int64), ("nonfinite", C.c_int32), ("pad2_", C.c_int32),
                 ("nonfinite_step", C.c_int64), ("tc_lags", C.c_int64),
-                ("tc", C.POINTER(C.c_double)), ("tc_hist", C.POINTER(C.c_double))]
+                ("tc", C.POINTER(C.c_double)), ("tc_hist", C.POINTER(C.c_double)),
+                ("batch_len", C.c_int64), ("batch_cap", C.c_int64),
+                ("b_s1", C.POINTER(C.c_double)), ("b_s2", C.POINTER(C.c_double)),
+                ("b_sk", C.POINTER(C.c_double)), ("b_sp", C.POINTER(C.c_double))]
 
 
 def _load():
@@ -228,6 +231,8 @@ class Stats:
     corr: bool = False
     sk: bool = False
     tcorr_lags: int = 0
+    batch: int = 0          # samples per batch of the batch-means error bars (0: none)
+    max_batches: int = 0    # batches kept (0: 64)
     _c: _Stats = field(default=None, repr=False)
 
     def __post_init__(self):
@@ -246,13 +251,23 @@ class Stats:
             raise ValueError("the time correlation is 1D")
         self.tc = np.zeros((L, nc)) if L else None
         self.tc_hist = np.zeros((L, nc)) if L else None
+        B = (self.max_batches or 64) if self.batch > 0 else 0
+        self.b_s1 = np.zeros((B, nc))
+        self.b_s2 = np.zeros((B, nc))
+        self.b_sk = np.zeros((B, self.nb))
+        self.b_sp = np.zeros((B, 3))
         self._c = _Stats(self.burn_in, self.every, 0,
                          _dptr(self.s1) if self.per_cell else null,
                          _dptr(self.s2) if self.per_cell else null,
                          _dptr(self.m2) if self.corr else null,
                          _dptr(self.sk_sum) if self.sk else null,
                          self.nb, 0, 0.0, 0.0, 0.0, 0, 0, 0, 0, L,
-                         _dptr(self.tc) if L else null, _dptr(self.tc_hist) if L else null)
+                         _dptr(self.tc) if L else null, _dptr(self.tc_hist) if L else null,
+                         int(self.batch), B,
+                         _dptr(self.b_s1) if B and self.per_cell else null,
+                         _dptr(self.b_s2) if B and self.per_cell else null,
+                         _dptr(self.b_sk) if B and self.sk else null,
+                         _dptr(self.b_sp) if B else null)
 
     @property
     def n_samples(self) -> int:
@@ -301,6 +316,44 @@ class Stats:
         """(mean of spatial-mean delta, mean of spatial-mean delta^2, mean spatial variance)."""
         n = self.n_samples
         return self._c.sp_mean / n, self._c.sp_sq / n, self._c.sp_var / n
+
+    # ---- batch means (samples 0..L-1 form batch 0, L..2L-1 batch 1, ...)
+
+    @property
+    def n_batches(self) -> int:
+        """Complete batches (only the kept ones count)."""
+        if self.batch <= 0:
+            return 0
+        return min(self.n_samples // self.batch, self.b_sp.shape[0])
+
+    def batch_values(self) -> dict:
+        """Each statistic formed from the samples of each complete batch alone,
+        as the whole-run statistic is formed from all samples: per-cell mean and
+        (population) variance, structure factor (1D per k, nD per shell),
+        spatial variance.  Arrays with the batch as their first axis."""
+        B, L = self.n_batches, float(self.batch)
+        m1 = self.b_s1[:B] / L
+        out = dict(mean=reference(self.d) + m1, var=self.b_s2[:B] / L - m1 * m1,
+                   spatial_var=self.b_sp[:B, 2] / L, spatial_mean=self.b_sp[:B, 0] / L)
+        if self.sk:
+            if self.d.dim == 1:
+                out["sk"] = self.b_sk[:B] / L
+            else:
+                with np.errstate(invalid="ignore", divide="ignore"):
+                    out["sk"] = self.b_sk[:B] / (L * bin_modes(self.d))
+        return out
+
+    def se(self) -> dict:
+        """Batch-means standard errors: the sample standard deviation of the B
+        batch values (divisor B - 1) over sqrt(B); NaN while B < 2."""
+        B = self.n_batches
+        out = {}
+        for k, v in self.batch_values().items():
+            if B < 2:
+                out[k] = np.full(np.shape(v)[1:], np.nan)
+            else:
+                out[k] = np.std(v, axis=0, ddof=1) / np.sqrt(B)
+        return out
 
 
 def advance(d: Desc, u: np.ndarray, step0: int, nsteps: int, stats: Stats | None = None) -> int:

@@ -123,6 +123,14 @@ typedef struct {
     int64_t tc_lags;     /* 1D: lags L of the time correlation (0 = off)      */
     double *tc;          /* L*N sums over samples n >= m of d_i(n) d_i(n-m)   */
     double *tc_hist;     /* L*N ring of the last L samples' delta             */
+    /* batch means (Sec. 3 time averages, split into consecutive batches):
+     * sample n (0-based) belongs to batch n / batch_len; each batch keeps
+     * its own sums of the same quantities as the totals above           */
+    int64_t batch_len;   /* samples per batch (0: no batch sums)              */
+    int64_t batch_cap;   /* batches the arrays below hold                     */
+    double *b_s1, *b_s2; /* [batch_cap][nc] sums of delta, delta^2, or NULL   */
+    double *b_sk;        /* [batch_cap][n_bins (nD) or N (1D)], or NULL       */
+    double *b_sp;        /* [batch_cap][3]: spatial mean, mean square, variance */
 } or_stats;
 
 /* ---------------------------------------------------------------- Philox */
@@ -509,11 +517,16 @@ static int take_sample(const or_desc *d, const double *u, const double *ref,
             st->nonfinite_step = t;
             return 1;
         }
+    /* the batch this sample belongs to (-1: none kept) */
+    int64_t bs = -1;
+    if (st->batch_len > 0 && st->n_samples / st->batch_len < st->batch_cap) bs = st->n_samples / st->batch_len;
     double a = 0.0, b = 0.0;
     for (int64_t i = 0; i < nc; ++i) {
         double del = u[i] - ref[i];
         if (st->s1) st->s1[i] += del;
         if (st->s2) st->s2[i] += del * del;
+        if (bs >= 0 && st->b_s1) st->b_s1[bs * nc + i] += del;
+        if (bs >= 0 && st->b_s2) st->b_s2[bs * nc + i] += del * del;
         a += del;
         b += del * del;
     }
@@ -522,6 +535,11 @@ static int take_sample(const or_desc *d, const double *u, const double *ref,
     st->sp_mean += a;
     st->sp_sq += b;
     st->sp_var += b - a * a;
+    if (bs >= 0 && st->b_sp) {
+        st->b_sp[bs * 3 + 0] += a;
+        st->b_sp[bs * 3 + 1] += b;
+        st->b_sp[bs * 3 + 2] += b - a * a;
+    }
     if (st->m2 && d->dim == 1) {
         for (int64_t i = 0; i < nc; ++i)
             for (int64_t j = 0; j < nc; ++j)
@@ -542,15 +560,22 @@ static int take_sample(const or_desc *d, const double *u, const double *ref,
         double *im = (double *)calloc((size_t)nc, sizeof(double));
         for (int64_t i = 0; i < nc; ++i) re[i] = u[i];
         for (int axis = 0; axis < d->dim; ++axis) dft_axis(d, axis, re, im);
+        double *bsk = (bs >= 0 && st->b_sk) ? st->b_sk + bs * (d->dim == 1 ? nc : st->n_bins) : NULL;
         if (d->dim == 1) {
-            for (int64_t k = 0; k < nc; ++k) st->sk[k] += re[k] * re[k] + im[k] * im[k];
+            for (int64_t k = 0; k < nc; ++k) {
+                st->sk[k] += re[k] * re[k] + im[k] * im[k];
+                if (bsk) bsk[k] += re[k] * re[k] + im[k] * im[k];
+            }
         } else {
             for (int64_t kz = 0; kz < d->n[2]; ++kz)
                 for (int64_t ky = 0; ky < d->n[1]; ++ky)
                     for (int64_t kx = 0; kx < d->n[0]; ++kx) {
                         int64_t b2 = mode_bin(d, kx, ky, kz);
                         int64_t i = (kz * d->n[1] + ky) * d->n[0] + kx;
-                        if (b2 < st->n_bins) st->sk[b2] += re[i] * re[i] + im[i] * im[i];
+                        if (b2 < st->n_bins) {
+                            st->sk[b2] += re[i] * re[i] + im[i] * im[i];
+                            if (bsk) bsk[b2] += re[i] * re[i] + im[i] * im[i];
+                        }
                     }
         }
         free(re); free(im);

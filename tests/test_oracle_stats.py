@@ -336,3 +336,83 @@ def test_composite_rod_equilibrium_variance_follows_heat_capacity():
     want = np.diag(theory.general_discrete_lyapunov(G, B))
     assert np.max(np.abs(v - want) / se) < 4.5, (v, want, se)
     assert v[6] / v[1] > 1.4          # the low-capacity half fluctuates more
+
+
+# ---------------------------------------------------------------- batch-means error bars
+
+@pytest.mark.parametrize("dim", [1, 2])
+def test_batch_means_match_numpy_on_a_recorded_trajectory(dim):
+    """The oracle's per-batch statistics and standard errors against numpy on
+    the recorded samples of the same run: the samples reshaped into B
+    consecutive batches of L, each statistic formed per batch (per-cell mean
+    and population variance, |DFT|^2 per k or shell average, spatial
+    variance), SE = std over batches (ddof 1) / sqrt(B); the samples of an
+    incomplete last batch enter the totals only."""
+    if dim == 1:
+        d = oracle.Desc(dim=1, n=(12, 1, 1), bc=1, scheme=1, r=0.2, sigma=0.3, u0=1.0, u_left=1.2, u_right=0.9,
+                        init_sd=0.2, seed=4)
+    else:
+        d = oracle.Desc(dim=2, n=(8, 6, 1), r=0.1, sigma=0.2, u0=1.0, init_sd=0.3, seed=6)
+    L, every, burn = 7, 2, 5
+    u = oracle.init(d)
+    st = oracle.Stats(d, burn_in=burn, every=every, sk=True, batch=L)
+    ref = oracle.reference(d)
+    traj = []
+    for t in range(2 * (burn + 3 * L + 4 * L + 3)):
+        oracle.advance(d, u, t, 1, st)
+        if t + 1 > burn and (t + 1) % every == 0:
+            traj.append(u.copy())
+    X = np.array(traj)
+    M = len(traj)
+    B = M // L
+    assert st.n_samples == M and st.n_batches == B >= 6 and M % L != 0
+    Xb = X[:B * L].reshape(B, L, -1)
+    D = Xb - ref
+    bv = st.batch_values()
+    np.testing.assert_allclose(bv["mean"], Xb.mean(axis=1), rtol=1e-13)
+    np.testing.assert_allclose(bv["var"], D.var(axis=1), atol=1e-14)
+    np.testing.assert_allclose(bv["spatial_var"], D.var(axis=2).mean(axis=1), atol=1e-14)
+    if dim == 1:
+        skb = (np.abs(np.fft.fft(Xb, axis=2)) ** 2).mean(axis=1)
+    else:
+        p = (np.abs(np.fft.fft2(Xb.reshape(B, L, d.n[1], d.n[0]))) ** 2).mean(axis=1)   # [B][ky][kx]
+        modes = theory.radial_average(np.ones((d.n[0], d.n[1])), (d.n[0], d.n[1]))[1]
+        ok = modes > 0
+        skb = np.array([theory.radial_average(p[b].T, (d.n[0], d.n[1]))[0][ok] / modes[ok] for b in range(B)])
+        bv["sk"] = bv["sk"][:, ok]
+    np.testing.assert_allclose(bv["sk"], skb, rtol=1e-11)
+    se = st.se()
+    np.testing.assert_allclose(se["var"], D.var(axis=1).std(axis=0, ddof=1) / np.sqrt(B), rtol=1e-10)
+    np.testing.assert_allclose(se["spatial_var"], D.var(axis=2).mean(axis=1).std(ddof=1) / np.sqrt(B), rtol=1e-10)
+    # the whole-run statistics still use every sample
+    np.testing.assert_allclose(st.spatial()[2], (X - ref).var(axis=1).mean(), atol=1e-14)
+
+
+def test_batch_means_error_is_the_spread_of_independent_runs():
+    """The batch-means SE estimates the standard deviation of a run's time
+    average: over 40 independent realisations of the same periodic FE run
+    (correlated samples: the slowest mode decays over ~33 steps, samples every
+    25), the spread of their spatial-variance estimates agrees with the mean
+    reported SE (a mis-scaled SE, e.g. without the 1/sqrt(B), is off by 4.5x),
+    and fewer than two complete batches give NaN."""
+    N, r = 16, 0.2
+    est, ses = [], []
+    for q in range(40):
+        # no initial perturbation: the conserved mean, and with it the
+        # stationary variance eps m^2 gamma / (1 - eps beta), is the same in
+        # every realisation, so their spread is the sampling error alone
+        d = oracle.Desc(dim=1, n=(N, 1, 1), r=r, sigma=oracle.sigma_of(r, 1e-2), u0=1.0, realisation=q, seed=21)
+        u = oracle.init(d)
+        oracle.advance(d, u, 0, 500)
+        st = oracle.Stats(d, burn_in=500, every=25, per_cell=False, batch=30, max_batches=20)
+        oracle.advance(d, u, 500, 500 + 25 * 600, st)
+        assert st.n_batches == 20
+        est.append(st.spatial()[2])
+        ses.append(st.se()["spatial_var"])
+    spread = np.std(est, ddof=1)
+    ratio = spread / np.mean(ses)
+    assert 0.7 < ratio < 1.4, ratio
+    d = oracle.Desc(dim=1, n=(N, 1, 1), r=r, sigma=0.1, u0=1.0)
+    st = oracle.Stats(d, burn_in=0, every=1, batch=10)
+    oracle.advance(d, oracle.init(d), 0, 15, st)
+    assert st.n_batches == 1 and np.all(np.isnan(st.se()["var"]))
