@@ -61,14 +61,15 @@ def kernel_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def make_handle(she, cfg, stats, tuning_flags=0):
-    from paper_2406_12157_amd import workloads as W  # noqa: F401
+def make_handle(she, cfg, stats, tuning_flags=0, burn_in=0, batch_samples=0):
+    """The handle the benchmark times (burn-in and batch length change what
+    is sampled, not the launch shapes)."""
     insts = [she.Instance(n=i["n"], eq=i["eq"], bc=i["bc"], scheme=i["scheme"], noise=i["noise"], r=i["r"],
                           eps=i["eps"], u0=i["u0"], u_left=i["u_left"], u_right=i["u_right"],
                           init_sd=i["init_sd"], seed=i["seed"], realisation=i["realisation"])
              for i in cfg["instances"]]
-    return she.Handle(insts, precision=cfg["precision"], burn_in=0, sample_every=cfg["sample_every"],
-                      stats=stats, tuning_flags=tuning_flags), insts
+    return she.Handle(insts, precision=cfg["precision"], burn_in=burn_in, sample_every=cfg["sample_every"],
+                      stats=stats, tuning_flags=tuning_flags, batch_samples=batch_samples), insts
 
 
 def timed_region(torch, h, steps, every):

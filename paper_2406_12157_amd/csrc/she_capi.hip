@@ -57,7 +57,7 @@ struct she_handle {
     // time correlation: history ring of hist_rows sample rows, L x N lag sums
     int tc_lags = 0;
     int32_t hist_rows = 0;
-    int64_t tc_samples = 0;       // samples taken (equal on every instance still sampling)
+    int64_t samples = 0;          // 1D: samples since create / reset (equal on every instance still sampling)
     void *d_hist = nullptr;
     double *d_tc = nullptr;
     int64_t hist_elems = 0, tc_elems = 0;
@@ -68,6 +68,11 @@ struct she_handle {
     std::vector<double> pcr_host;     // implicit schemes: FP64 reduction factors
     double *d_pcr = nullptr;
     size_t smem1d = 0;
+
+    // batch means: samples per batch (0: none) and their arrays
+    int32_t batch_len = 0;
+    double *d_bcell = nullptr, *d_csnap = nullptr, *d_skw1 = nullptr;      // 1D (Batch1D)
+    double *d_sksnap = nullptr, *d_skwm = nullptr, *d_skwm2 = nullptr;     // 2D S(k) (BatchSk)
 
     // 2D / 3D
     ParamsND pnd{};
@@ -98,6 +103,8 @@ struct she_handle {
     int chunk2 = 0, nparts2 = 0, nd_blocks2 = 0;
 
     void *field() const { return dim == 1 ? d_pool : (cur == 0 ? d_a : d_b); }
+    // 1D: per-cell sums are kept (and so per-cell batch means)
+    bool d_s1_planned() const { return (mask & (SHE_STAT_MOMENTS | SHE_STAT_CORR | SHE_STAT_TCORR)) != 0; }
 };
 
 static thread_local std::string g_create_err;
@@ -671,6 +678,13 @@ static she_status plan_1d(she_handle *h, const she_config *cfg, Plan &plan)
         plan.add(&h->d_hist, es * ho);
         plan.add(reinterpret_cast<void **>(&h->d_tc), sizeof(double) * to);
     }
+    if (h->batch_len > 0 && h->d_s1_planned()) {
+        plan.add(reinterpret_cast<void **>(&h->d_bcell), sizeof(double) * 6 * off);
+        if (corr) {
+            plan.add(reinterpret_cast<void **>(&h->d_csnap), sizeof(double) * co);
+            plan.add(reinterpret_cast<void **>(&h->d_skw1), sizeof(double) * 2 * off);
+        }
+    }
     h->fin_len = 4 * static_cast<size_t>(h->nmax) + 2 * static_cast<size_t>(h->nmax) * h->nmax + 8 +
                  static_cast<size_t>(h->tc_lags) * h->nmax;
     return SHE_OK;
@@ -799,6 +813,12 @@ static she_status plan_nd(she_handle *h, const she_config *cfg, Plan &plan)
         plan.add(reinterpret_cast<void **>(&h->d_skpart), sizeof(double) * h->n_inst * h->sk_groups * h->nbins);
         plan.add(reinterpret_cast<void **>(&h->d_sksum), sizeof(double) * h->n_inst * h->nbins);
         plan.add(reinterpret_cast<void **>(&h->d_skmodes), sizeof(double) * h->nbins);
+        if (h->batch_len > 0) {
+            const size_t nb = sizeof(double) * h->n_inst * h->nbins;
+            plan.add(reinterpret_cast<void **>(&h->d_sksnap), nb);
+            plan.add(reinterpret_cast<void **>(&h->d_skwm), nb);
+            plan.add(reinterpret_cast<void **>(&h->d_skwm2), nb);
+        }
         h->fin_len = 3 + h->nbins;
     }
     return SHE_OK;
@@ -815,6 +835,7 @@ static she_status build_plan(she_handle *h, const she_config *cfg, Plan &plan)
     h->every = cfg->sample_every;
     h->mask = cfg->stats_mask;
     if (h->mask & (SHE_STAT_CORR | SHE_STAT_TCORR)) h->mask |= SHE_STAT_MOMENTS;
+    h->batch_len = cfg->batch_samples;
     h->stream = static_cast<hipStream_t>(cfg->stream);
     she_status st = h->dim == 1 ? plan_1d(h, cfg, plan) : plan_nd(h, cfg, plan);
     for (she_instance_desc &d : h->inst) d.cond = d.cap = nullptr;  // caller memory, read during planning only
@@ -865,7 +886,12 @@ static she_status zero_stats(she_handle *h)
     if (h->d_c) SHE_HIP(h, hipMemsetAsync(h->d_c, 0, sizeof(double) * h->c_elems, s));
     if (h->d_sksum) SHE_HIP(h, hipMemsetAsync(h->d_sksum, 0, sizeof(double) * h->n_inst * h->nbins, s));
     if (h->d_tc) SHE_HIP(h, hipMemsetAsync(h->d_tc, 0, sizeof(double) * h->tc_elems, s));
-    h->tc_samples = 0;
+    if (h->d_bcell) SHE_HIP(h, hipMemsetAsync(h->d_bcell, 0, sizeof(double) * 6 * h->total_cells, s));
+    if (h->d_csnap) SHE_HIP(h, hipMemsetAsync(h->d_csnap, 0, sizeof(double) * h->c_elems, s));
+    if (h->d_skw1) SHE_HIP(h, hipMemsetAsync(h->d_skw1, 0, sizeof(double) * 2 * h->total_cells, s));
+    for (double *p : {h->d_sksnap, h->d_skwm, h->d_skwm2})
+        if (p) SHE_HIP(h, hipMemsetAsync(p, 0, sizeof(double) * h->n_inst * h->nbins, s));
+    h->samples = 0;
     return SHE_OK;
 }
 
@@ -1123,10 +1149,12 @@ static hipError_t nd_enqueue(she_handle *h, hipStream_t s, const StepArg &sa, in
     }
     if (e != hipSuccess || !may_sample) return e;
     e = launch_reduce_parts(h->n_inst, s, sa, h->d_part, two ? h->nparts2 : h->nparts,
-                            1.0 / static_cast<double>(h->cells), h->d_acc);
+                            1.0 / static_cast<double>(h->cells), h->batch_len, h->d_acc);
     if (e != hipSuccess || !(h->mask & SHE_STAT_SK)) return e;
+    const BatchSk bk{h->d_sksnap, h->d_skwm, h->d_skwm2, h->d_skmodes, static_cast<double>(h->cells), h->pnd.u0,
+                     h->d_sksnap ? h->batch_len : 0, 0};
     return launch_sk2d(h->prec, s, sa, h->n_inst, h->pnd.nx, h->pnd.ny, h->pnd.u0, dst, h->d_half, h->d_twx, h->d_twy,
-                       h->d_skpart, h->nbins, h->d_sksum, h->d_acc);
+                       h->d_skpart, h->nbins, h->d_sksum, h->d_acc, bk);
 }
 
 // Whether completed step t samples.
@@ -1205,16 +1233,31 @@ static she_status advance(she_handle *h, int64_t nsteps, bool sampling)
                 const int64_t j0 = std::max(h->steps, h->burn_in) / h->every;
                 k = std::min<int64_t>(k, h->every * (j0 + room + 1) - 1 - h->steps);
             }
+            // batch means: a launch ends at the step whose sample completes the
+            // current batch, and the fold kernels follow it.  The j-th sample
+            // after step t completes at every * (max(t, burn_in) / every + j).
+            bool fold = false;
+            if (stats && h->batch_len > 0) {
+                const int64_t need = (h->samples / h->batch_len + 1) * h->batch_len - h->samples;
+                const int64_t t_end = h->every * (std::max(h->steps, h->burn_in) / h->every + need);
+                if (t_end - h->steps <= k) {
+                    k = t_end - h->steps;
+                    fold = true;
+                }
+            }
             SHE_HIP(h, launch_step1d(h->prec, h->block1d, h->maxg, stats, h->mode1d, h->blocks1d, h->smem1d, s,
                                      h->d_tab, h->d_segs, h->d_pool, h->d_coef, h->d_pcr, h->steps,
                                      static_cast<int32_t>(k),
                                      h->burn_in, h->every, h->mask, st));
-            if (tc) {
-                const int64_t cnt = sampled_by(h->steps + k) - sampled_by(h->steps);
-                if (cnt > 0)
-                    SHE_HIP(h, launch_tcorr1d(h->prec, h->n_inst, h->nmax, h->tc_lags, s, h->d_tab, h->d_hist,
-                                              h->hist_rows, h->tc_samples, cnt, h->d_tc, h->d_acc));
-                h->tc_samples += cnt;
+            const int64_t cnt = stats ? sampled_by(h->steps + k) - sampled_by(h->steps) : 0;
+            if (tc && cnt > 0)
+                SHE_HIP(h, launch_tcorr1d(h->prec, h->n_inst, h->nmax, h->tc_lags, s, h->d_tab, h->d_hist,
+                                          h->hist_rows, h->samples, cnt, h->d_tc, h->d_acc));
+            h->samples += cnt;
+            if (fold) {
+                const Batch1D bk{h->d_bcell, h->d_csnap, h->d_skw1, h->total_cells, h->batch_len, 0};
+                SHE_HIP(h, launch_fold1d(h->prec, h->n_inst, h->nmax, s, h->d_tab, h->d_x, h->d_c, h->d_s1, h->d_s2,
+                                         h->d_acc, bk));
             }
             h->steps += k;
             done += k;
@@ -1298,6 +1341,55 @@ extern "C" she_status she_stats(she_handle *h, int32_t instance, she_stats_out *
     out->steps = h->steps;
     out->nonfinite = acc.nonfinite;
     out->clamp_count = acc.clamp_count;
+    // batch-means error bars: SE = sqrt(M2 / (B (B - 1))) from the Welford
+    // M2 of the B complete batches' values; NaN while B < 2
+    out->n_batches = acc.n_batches;
+    const double nbat = static_cast<double>(acc.n_batches);
+    auto se_of = [&](double m2) { return acc.n_batches >= 2 ? std::sqrt(m2 / (nbat * (nbat - 1.0))) : NAN; };
+    out->spatial_var = acc.n_samples > 0 ? acc.sp_var / static_cast<double>(acc.n_samples) : 0.0;
+    out->spatial_var_se = se_of(acc.wv_m2);
+    // n values into dst from the device M2 array m2 (null: no batch arrays: NaN)
+    auto se_array = [&](double *dst, int64_t cap, int64_t n, const double *m2, const char *what) -> she_status {
+        if (!dst) return SHE_OK;
+        if (cap < n) return fail(h, SHE_EINVAL, std::string("capacity too small for ") + what);
+        if (!m2) {
+            for (int64_t i = 0; i < n; ++i) dst[i] = NAN;
+            return SHE_OK;
+        }
+        SHE_HIP(h, hipMemcpyAsync(dst, m2, sizeof(double) * n, hipMemcpyDeviceToHost, s));
+        SHE_HIP(h, hipStreamSynchronize(s));
+        for (int64_t i = 0; i < n; ++i) dst[i] = se_of(dst[i]);
+        return SHE_OK;
+    };
+    {
+        she_status st;
+        if (h->dim == 1) {
+            const int64_t N = h->tab[instance].n, off = h->tab[instance].off, tc = h->total_cells;
+            if ((st = se_array(out->mean_se, out->mean_se_cap, N, h->d_bcell ? h->d_bcell + 3 * tc + off : nullptr,
+                               "mean_se")) != SHE_OK)
+                return st;
+            if ((st = se_array(out->var_se, out->var_se_cap, N, h->d_bcell ? h->d_bcell + 5 * tc + off : nullptr,
+                               "var_se")) != SHE_OK)
+                return st;
+            const bool corr_i = h->tab[instance].c_off >= 0;
+            if ((st = se_array(out->sk_se, out->sk_se_cap, N, (h->d_skw1 && corr_i) ? h->d_skw1 + tc + off : nullptr,
+                               "sk_se")) != SHE_OK)
+                return st;
+        } else {
+            if (out->mean_se) {
+                if (out->mean_se_cap < 1) return fail(h, SHE_EINVAL, "capacity too small for mean_se");
+                out->mean_se[0] = se_of(acc.wm_m2);
+            }
+            if (out->var_se) {
+                if (out->var_se_cap < 1) return fail(h, SHE_EINVAL, "capacity too small for var_se");
+                out->var_se[0] = se_of(acc.wv_m2);
+            }
+            if ((st = se_array(out->sk_se, out->sk_se_cap, h->nbins,
+                               h->d_skwm2 ? h->d_skwm2 + static_cast<int64_t>(instance) * h->nbins : nullptr,
+                               "sk_se")) != SHE_OK)
+                return st;
+        }
+    }
     if (h->dim == 1) {
         const int N = h->tab[instance].n;
         const bool corr = h->tab[instance].x_off >= 0;
@@ -1403,6 +1495,7 @@ struct Blob {
     int64_t dim, prec, n_inst, cells, x_elems, c_elems, stat_cells;
     int64_t cur;
     int64_t hist_elems, tc_elems, tc_samples;
+    int64_t batch_len;
 };
 constexpr uint64_t kMagic = 0x3153544b50454853ull;  // "SHEPKTS1"
 
@@ -1422,9 +1515,14 @@ std::vector<Section> sections(const she_handle *h)
         if (h->d_c) v.push_back({h->d_c, sizeof(double) * h->c_elems});
         if (h->d_hist) v.push_back({h->d_hist, h->esz * h->hist_elems});
         if (h->d_tc) v.push_back({h->d_tc, sizeof(double) * h->tc_elems});
+        if (h->d_bcell) v.push_back({h->d_bcell, sizeof(double) * 6 * h->total_cells});
+        if (h->d_csnap) v.push_back({h->d_csnap, sizeof(double) * h->c_elems});
+        if (h->d_skw1) v.push_back({h->d_skw1, sizeof(double) * 2 * h->total_cells});
     } else {
         v.push_back({h->field(), h->esz * h->cells * h->n_inst});
         if (h->d_sksum) v.push_back({h->d_sksum, sizeof(double) * h->n_inst * h->nbins});
+        for (double *p : {h->d_sksnap, h->d_skwm, h->d_skwm2})
+            if (p) v.push_back({p, sizeof(double) * h->n_inst * h->nbins});
     }
     v.push_back({h->d_acc, sizeof(InstAcc) * h->n_inst});
     return v;
@@ -1434,7 +1532,8 @@ Blob header(const she_handle *h)
 {
     Blob b{};
     b.magic = kMagic;
-    b.version = 2;
+    b.version = 3;
+    b.batch_len = h->batch_len;
     b.steps = h->steps;
     b.dim = h->dim;
     b.prec = h->prec;
@@ -1446,7 +1545,7 @@ Blob header(const she_handle *h)
     b.cur = 0;
     b.hist_elems = h->hist_elems;
     b.tc_elems = h->tc_elems;
-    b.tc_samples = h->tc_samples;
+    b.tc_samples = h->samples;
     return b;
 }
 }  // namespace
@@ -1487,7 +1586,7 @@ extern "C" she_status she_set_state(she_handle *h, const void *host, size_t byte
     Blob b;
     std::memcpy(&b, host, sizeof b);
     Blob mine = header(h);
-    if (b.magic != kMagic || b.version != 2 || b.dim != mine.dim || b.prec != mine.prec ||
+    if (b.magic != kMagic || b.version != 3 || b.batch_len != mine.batch_len || b.dim != mine.dim || b.prec != mine.prec ||
         b.n_inst != mine.n_inst || b.cells != mine.cells || b.x_elems != mine.x_elems ||
         b.c_elems != mine.c_elems || b.stat_cells != mine.stat_cells || b.hist_elems != mine.hist_elems ||
         b.tc_elems != mine.tc_elems)
@@ -1500,7 +1599,7 @@ extern "C" she_status she_set_state(she_handle *h, const void *host, size_t byte
     }
     SHE_HIP(h, hipStreamSynchronize(h->stream));
     h->steps = b.steps;
-    h->tc_samples = b.tc_samples;
+    h->samples = b.tc_samples;
     return SHE_OK;
 }
 

@@ -45,6 +45,67 @@ struct InstAcc {
     double sp_var;      // ... of the spatial variance
     int32_t nonfinite;
     int32_t pad;
+    // batch means (samples per batch L): complete batches folded so far, the
+    // spatial sums at the end of the last folded batch, the FP64 Welford
+    // mean / M2 over batches of the batch's spatial mean and spatial
+    // variance, and the spatial-mean sum of the batch folded last
+    int64_t n_batches;
+    double bsp_mean, bsp_var;
+    double wm_mean, wm_m2;
+    double wv_mean, wv_m2;
+    double batch_sp_mean;
+};
+
+// One step of Welford's update of (mean, M2) with the b-th value x (b >= 1):
+// M2 / (b - 1) is the sample variance of the b values.
+__host__ __device__ inline void welford(double x, double b, double &mean, double &m2)
+{
+    const double d = x - mean;
+    mean += d / b;
+    m2 += d * (x - mean);
+}
+
+// Fold a completed batch of `len` samples into an instance's spatial
+// batch-means accumulators (the batch statistic is the sum over its samples
+// divided by len; the sums at its start are the snapshots).
+__host__ __device__ inline void fold_spatial(InstAcc &q, int32_t len)
+{
+    const double b = static_cast<double>(q.n_batches + 1);
+    const double bm = q.sp_mean - q.bsp_mean;
+    welford(bm / len, b, q.wm_mean, q.wm_m2);
+    welford((q.sp_var - q.bsp_var) / len, b, q.wv_mean, q.wv_m2);
+    q.batch_sp_mean = bm;
+    q.bsp_mean = q.sp_mean;
+    q.bsp_var = q.sp_var;
+    q.n_batches += 1;
+}
+
+// Batch-means arrays of a 1D batch (device; null when not kept).  cell:
+// [6][total_cells] = snapshots of s1 and s2 at the end of the last folded
+// batch, Welford (mean, M2) of the batch means of dU, of the batch
+// variances; csnap: the covariance sums at that point (c_off layout); skw:
+// [2][total_cells] Welford (mean, M2) of the batch S_k (at the instance's off).
+struct Batch1D {
+    double *cell;
+    double *csnap;
+    double *skw;
+    int64_t total_cells;
+    int32_t len;
+    int32_t pad;
+};
+
+// Batch-means arrays of the 2D structure factor (device; null when not
+// kept): the shell sums at the end of the last folded batch and the Welford
+// (mean, M2) of the batch shell averages, n_inst x nbins each.
+struct BatchSk {
+    double *snap;
+    double *wmean;
+    double *wm2;
+    const double *modes;
+    double cells;
+    double u0;
+    int32_t len;
+    int32_t pad;
 };
 
 // Statistics buffers of the 1D kernel.
@@ -193,8 +254,10 @@ hipError_t launch_step2d(int prec, int cx, int eq, int scheme, int n_blocks, hip
 hipError_t launch_step3d(int prec, int cx, int eq, int stage, int ty, int n_blocks, size_t smem,
                          hipStream_t s, const ParamsND &p, const void *src, const void *base, void *dst,
                          const StepArg &st, double *part, InstAcc *acc);
+// With batch_len > 0 a sample that completes a batch also folds it
+// (fold_spatial).
 hipError_t launch_reduce_parts(int n_inst, hipStream_t s, const StepArg &st, const double *part,
-                               int32_t nparts, double inv_cells, InstAcc *acc);
+                               int32_t nparts, double inv_cells, int32_t batch_len, InstAcc *acc);
 // Device step counter of captured graphs: *ctr = value, *ctr += k.
 hipError_t launch_set_step(hipStream_t s, int64_t *ctr, int64_t value);
 hipError_t launch_add_step(hipStream_t s, int64_t *ctr, int64_t k);
@@ -212,6 +275,12 @@ hipError_t launch_finnd(int prec, hipStream_t s, const ParamsND &p, int inst, in
 hipError_t launch_tcorr1d(int prec, int n_inst, int nmax, int lags, hipStream_t s, const Inst1D *tab,
                           const void *hist, int32_t hist_rows, int64_t n0, int64_t count, double *tc,
                           const InstAcc *acc);
+// Fold the batch that the last launch completed (acc n_samples = (n_batches
+// + 1) len) into the 1D batch-means arrays: S_k (instances with CORR), the
+// per-cell means and variances (bk.cell), then the spatial sums and
+// n_batches.  Instances that have not completed the batch (frozen) are left.
+hipError_t launch_fold1d(int prec, int n_inst, int nmax, hipStream_t s, const Inst1D *tab, const void *xblk,
+                         const double *c, const double *s1, const double *s2, InstAcc *acc, const Batch1D &bk);
 // C_i(m) = tc[m][i]/(M-m) - (s1[i]/M)^2 (NaN for m >= M) of one instance into out[L*N].
 hipError_t launch_fin_tc(hipStream_t s, int n, int lags, const double *s1, const double *tc, int64_t M,
                          double *out);
@@ -228,7 +297,7 @@ hipError_t launch_debug_normals(hipStream_t s, int prec, uint64_t seed, uint32_t
 // (n_inst x nbins FP64).  half: n_inst*ny*(nx/2+1) complex of the state type.
 hipError_t launch_sk2d(int prec, hipStream_t s, const StepArg &st, int n_inst, int nx, int ny, double u0,
                        const void *field, void *half, const void *twx, const void *twy, double *part, int nbins,
-                       double *sums, const InstAcc *acc);
+                       double *sums, const InstAcc *acc, const BatchSk &bk);
 // exp(-2 pi i t/n), t < n/2, as complex pairs of the state type
 hipError_t launch_twiddles(int prec, hipStream_t s, int n, void *tw);
 int sk2d_groups(int prec, int nx, int ny, int n_inst);

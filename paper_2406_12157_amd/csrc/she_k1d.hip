@@ -855,6 +855,128 @@ __global__ void __launch_bounds__(256)
     sk[k] = (rr * rr + ri * ri) + 2.0 * (rr * mr + ri * mi) + q;
 }
 
+// ------------------------------------------------------------------ batch means
+
+// Whether the last launch completed batch n_batches + 1 of this instance.
+__device__ __forceinline__ bool batch_done(const InstAcc &q, int32_t len)
+{
+    return len > 0 && !q.nonfinite && q.n_samples >= (q.n_batches + 1) * static_cast<int64_t>(len);
+}
+
+// S_k of the batch, from its covariance sums: Cb = (C + the open X rows) -
+// csnap, its circulant sums c(d) = sum_i Cb[i][(i - d) mod N] (so that
+// sum_ij Cb_ij cos(2 pi k (i - j)/N) = sum_d c(d) cos(2 pi k d/N)), and the
+// batch mean m_b of dU: S_k = |R_k|^2 + 2 Re(conj(R_k) DFT(m_b)_k) +
+// sum_d c(d) cos(2 pi k d/N) / L, R the DFT of the reference profile (the
+// formula of k_fin_sk for one batch).  Then csnap takes the current sums.
+// One block per instance; runs before k_fold_cells1d (it reads the s1
+// snapshot that kernel moves on).
+template <typename T>
+__global__ void __launch_bounds__(256)
+    k_fold_sk1d(const Inst1D *__restrict__ tab, const T *__restrict__ xblk, const double *__restrict__ c,
+                const double *__restrict__ s1, const InstAcc *__restrict__ acc, Batch1D bk)
+{
+    const int inst = blockIdx.x;
+    const Inst1D d = tab[inst];
+    const InstAcc q = acc[inst];
+    if (d.c_off < 0 || !batch_done(q, bk.len)) return;
+    __shared__ double cd[1024], mb[1024];
+    const int N = d.n;
+    const int rows = static_cast<int>(q.n_samples % kCorrBlock);  // open rows of the X block
+    const T *X = xblk + d.x_off;
+    const double *C = c + d.c_off;
+    double *Cs = bk.csnap + d.c_off;
+    const double *s1s = bk.cell;
+    const double L = static_cast<double>(bk.len);
+    auto ctot = [&](int i, int j) {
+        double v = C[static_cast<int64_t>(i) * N + j];
+        for (int r = 0; r < rows; ++r)
+            v += static_cast<double>(X[static_cast<int64_t>(r) * N + i]) * static_cast<double>(X[static_cast<int64_t>(r) * N + j]);
+        return v;
+    };
+    for (int dd = threadIdx.x; dd < N; dd += 256) {
+        double a = 0.0;
+        for (int i = 0; i < N; ++i) {
+            const int j = i - dd < 0 ? i - dd + N : i - dd;
+            a += ctot(i, j) - Cs[static_cast<int64_t>(i) * N + j];
+        }
+        cd[dd] = a;
+    }
+    for (int i = threadIdx.x; i < N; i += 256) mb[i] = (s1[d.off + i] - s1s[d.off + i]) / L;
+    __syncthreads();
+    for (int64_t e = threadIdx.x; e < static_cast<int64_t>(N) * N; e += 256) {
+        const int i = static_cast<int>(e / N), j = static_cast<int>(e - static_cast<int64_t>(i) * N);
+        Cs[e] = ctot(i, j);
+    }
+    const double b = static_cast<double>(q.n_batches + 1);
+    for (int k = threadIdx.x; k < N; k += 256) {
+        double rr = 0.0, ri = 0.0, mr = 0.0, mi = 0.0, qq = 0.0;
+        for (int j = 0; j < N; ++j) {
+            const int64_t idx = (static_cast<int64_t>(j) * k) % N;
+            double sn, cs;
+            sincospi(-2.0 * static_cast<double>(idx) / N, &sn, &cs);
+            const double ref = d.bc == 1 ? d.uL + (d.uR - d.uL) * (j + 0.5) / N : d.u0;
+            rr += ref * cs;
+            ri += ref * sn;
+            mr += mb[j] * cs;
+            mi += mb[j] * sn;
+            qq += cd[j] * cs;   // cos(2 pi k d / N) for d = j
+        }
+        const double x = (rr * rr + ri * ri) + 2.0 * (rr * mr + ri * mi) + qq / L;
+        welford(x, b, bk.skw[d.off + k], bk.skw[bk.total_cells + d.off + k]);
+    }
+}
+
+// Per-cell batch mean and variance of dU, folded into their Welford sums;
+// the s1 / s2 snapshots move to the current sums.
+__global__ void __launch_bounds__(256)
+    k_fold_cells1d(const Inst1D *__restrict__ tab, const double *__restrict__ s1, const double *__restrict__ s2,
+                   const InstAcc *__restrict__ acc, Batch1D bk)
+{
+    const int inst = blockIdx.x;
+    const Inst1D d = tab[inst];
+    const InstAcc q = acc[inst];
+    const int i = blockIdx.y * 256 + threadIdx.x;
+    if (i >= d.n || !batch_done(q, bk.len)) return;
+    const int64_t tc = bk.total_cells, e = d.off + i;
+    double *cl = bk.cell;
+    const double L = static_cast<double>(bk.len), b = static_cast<double>(q.n_batches + 1);
+    const double m = (s1[e] - cl[e]) / L;
+    const double v = (s2[e] - cl[tc + e]) / L - m * m;
+    welford(m, b, cl[2 * tc + e], cl[3 * tc + e]);
+    welford(v, b, cl[4 * tc + e], cl[5 * tc + e]);
+    cl[e] = s1[e];
+    cl[tc + e] = s2[e];
+}
+
+// Spatial statistics of the batch and the batch count (last of the folds).
+__global__ void __launch_bounds__(64) k_fold_acc1d(int n_inst, InstAcc *__restrict__ acc, int32_t len)
+{
+    const int inst = blockIdx.x * 64 + threadIdx.x;
+    if (inst >= n_inst) return;
+    InstAcc q = acc[inst];
+    if (!batch_done(q, len)) return;
+    fold_spatial(q, len);
+    acc[inst] = q;
+}
+
+hipError_t launch_fold1d(int prec, int n_inst, int nmax, hipStream_t s, const Inst1D *tab, const void *xblk,
+                         const double *c, const double *s1, const double *s2, InstAcc *acc, const Batch1D &bk)
+{
+    if (bk.csnap) {
+        if (prec == 0)
+            hipLaunchKernelGGL(k_fold_sk1d<float>, dim3(n_inst), dim3(256), 0, s, tab,
+                               static_cast<const float *>(xblk), c, s1, acc, bk);
+        else
+            hipLaunchKernelGGL(k_fold_sk1d<double>, dim3(n_inst), dim3(256), 0, s, tab,
+                               static_cast<const double *>(xblk), c, s1, acc, bk);
+    }
+    if (bk.cell)
+        hipLaunchKernelGGL(k_fold_cells1d, dim3(n_inst, (nmax + 255) / 256), dim3(256), 0, s, tab, s1, s2, acc, bk);
+    hipLaunchKernelGGL(k_fold_acc1d, dim3((n_inst + 63) / 64), dim3(64), 0, s, n_inst, acc, bk.len);
+    return hipGetLastError();
+}
+
 // ------------------------------------------------------------------ launchers
 
 struct Step1DLaunch {

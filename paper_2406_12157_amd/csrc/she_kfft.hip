@@ -518,17 +518,30 @@ __global__ void __launch_bounds__(256)
 
 __global__ void __launch_bounds__(256)
     k_bins_reduce(StepArg sarg, const double *__restrict__ part, int ngroups, int nbins, int n_inst,
-                  double *__restrict__ sums, const InstAcc *__restrict__ acc)
+                  double *__restrict__ sums, const InstAcc *__restrict__ acc, BatchSk bk)
 {
     SHE_SAMPLE_GATE();
     const int64_t e = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
     if (e >= static_cast<int64_t>(n_inst) * nbins) return;
     const int inst = static_cast<int>(e / nbins), b = static_cast<int>(e - static_cast<int64_t>(inst) * nbins);
-    if (acc[inst].nonfinite) return;
+    const InstAcc q = acc[inst];
+    if (q.nonfinite) return;
     const double *pp = part + static_cast<int64_t>(inst) * ngroups * nbins + b;
     double s = 0.0;
     for (int g = 0; g < ngroups; ++g) s += pp[static_cast<int64_t>(g) * nbins];
-    sums[e] += s;
+    const double tot = sums[e] + s;
+    sums[e] = tot;
+    // The sample reduction ran first and folded the spatial sums of a batch
+    // this sample completed; fold the shells' batch averages too (the k = 0
+    // shell restored from the batch's spatial-mean sum, as at finalisation).
+    if (bk.len > 0 && q.n_samples % bk.len == 0) {
+        const double L = static_cast<double>(bk.len), N = bk.cells;
+        double v = tot - bk.snap[e];
+        if (b == 0) v += L * N * N * bk.u0 * bk.u0 + 2.0 * N * bk.u0 * (N * q.batch_sp_mean);
+        const double x = bk.modes[b] > 0 ? v / (L * bk.modes[b]) : 0.0;
+        welford(x, static_cast<double>(q.n_batches), bk.wmean[e], bk.wm2[e]);
+        bk.snap[e] = tot;
+    }
 }
 
 // ------------------------------------------------------------------ host side
@@ -648,7 +661,7 @@ bool cols_dispatch(int lgy, hipStream_t s, const StepArg &sa, int n_inst, int nx
 
 hipError_t launch_sk2d(int prec, hipStream_t s, const StepArg &sa, int n_inst, int nx, int ny, double u0,
                        const void *field, void *half, const void *twx, const void *twy, double *part, int nbins,
-                       double *sums, const InstAcc *acc)
+                       double *sums, const InstAcc *acc, const BatchSk &bk)
 {
     if (nbins > 64 * kMaxBinIters) return hipErrorInvalidValue;
     const int lgx = ilog2(nx), lgy = ilog2(ny);
@@ -665,7 +678,7 @@ hipError_t launch_sk2d(int prec, hipStream_t s, const StepArg &sa, int n_inst, i
     if (!ok) return hipErrorInvalidValue;
     const int64_t tot = static_cast<int64_t>(n_inst) * nbins;
     hipLaunchKernelGGL(k_bins_reduce, dim3(static_cast<unsigned>((tot + 255) / 256)), dim3(256), 0, s, sa, part,
-                       groups, nbins, n_inst, sums, acc);
+                       groups, nbins, n_inst, sums, acc, bk);
     return hipGetLastError();
 }
 

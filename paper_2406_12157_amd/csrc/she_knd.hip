@@ -52,7 +52,7 @@ hipError_t launch_step3d(int prec, int cx, int eq, int stage, int ty, int n_bloc
 // Per-instance reduction of the sample partials, fixed order.
 __global__ void __launch_bounds__(64)
     k_reduce_parts(StepArg sarg, const double *__restrict__ part, int32_t nparts, double inv_cells,
-                   InstAcc *__restrict__ acc)
+                   int32_t batch_len, InstAcc *__restrict__ acc)
 {
     int64_t step;
     int sample;
@@ -77,10 +77,14 @@ __global__ void __launch_bounds__(64)
         }
         a *= inv_cells;
         b *= inv_cells;
-        acc[inst].sp_mean += a;
-        acc[inst].sp_sq += b;
-        acc[inst].sp_var += b - a * a;
-        acc[inst].n_samples += 1;
+        InstAcc q = acc[inst];
+        q.sp_mean += a;
+        q.sp_sq += b;
+        q.sp_var += b - a * a;
+        q.n_samples += 1;
+        // a sample that completes a batch folds it
+        if (batch_len > 0 && q.n_samples % batch_len == 0) fold_spatial(q, batch_len);
+        acc[inst] = q;
     }
 }
 
@@ -144,9 +148,9 @@ __global__ void __launch_bounds__(256)
 // ------------------------------------------------------------------ launchers
 
 hipError_t launch_reduce_parts(int n_inst, hipStream_t s, const StepArg &sa, const double *part, int32_t nparts,
-                               double inv_cells, InstAcc *acc)
+                               double inv_cells, int32_t batch_len, InstAcc *acc)
 {
-    hipLaunchKernelGGL(k_reduce_parts, dim3(n_inst), dim3(64), 0, s, sa, part, nparts, inv_cells, acc);
+    hipLaunchKernelGGL(k_reduce_parts, dim3(n_inst), dim3(64), 0, s, sa, part, nparts, inv_cells, batch_len, acc);
     return hipGetLastError();
 }
 

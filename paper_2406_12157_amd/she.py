@@ -288,7 +288,7 @@ class Handle:
         _check(self.lib.she_write_field(self.h, i, _dptr(v), v.size), self.h)
 
     def stats(self, i: int, corr: bool = False, sk: bool = False, tcorr: bool = False,
-              raise_nonfinite: bool = True) -> dict:
+              raise_nonfinite: bool = True, se: bool = False) -> dict:
         inst = self.instances[i]
         n = inst.ncells if inst.dim == 1 else 1
         mean = np.zeros(n)
@@ -310,11 +310,23 @@ class Handle:
             if inst.dim > 1:
                 modes = np.zeros(nb)
                 out.sk_modes, out.sk_modes_cap = _dptr(modes), nb
+        ses = {}
+        if se:
+            ses["mean_se"] = np.zeros(n)
+            ses["var_se"] = np.zeros(n)
+            out.mean_se, out.mean_se_cap = _dptr(ses["mean_se"]), n
+            out.var_se, out.var_se_cap = _dptr(ses["var_se"]), n
+            if sk:
+                ses["sk_se"] = np.zeros(skv.size)
+                out.sk_se, out.sk_se_cap = _dptr(ses["sk_se"]), skv.size
         st = self.lib.she_stats(self.h, i, C.byref(out))
         if st != OK and not (st == ENONFINITE and not raise_nonfinite):
             _check(st, self.h)
         res = dict(n_samples=int(out.n_samples), steps=int(out.steps), mean=mean, var=var,
-                   sum_u=float(out.sum_u), nonfinite=bool(out.nonfinite), clamp_count=int(out.clamp_count))
+                   sum_u=float(out.sum_u), nonfinite=bool(out.nonfinite), clamp_count=int(out.clamp_count),
+                   n_batches=int(out.n_batches), spatial_var=float(out.spatial_var),
+                   spatial_var_se=float(out.spatial_var_se))
+        res.update(ses)
         if cm is not None:
             res["corr"] = cm.reshape(n, n)
         if skv is not None:

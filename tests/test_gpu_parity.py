@@ -873,3 +873,119 @@ def test_nd_clamp_count_matches_oracle(she, n, scheme):
     oracle.advance(d, u, 0, steps, st)
     assert st.clamp_count > 100
     assert counts == [st.clamp_count] * len(shapes), (counts, st.clamp_count)
+
+
+# ---------------------------------------------------------------- batch-means error bars
+
+def se_close(got, want, tol):
+    got, want = np.asarray(got, dtype=float), np.asarray(want, dtype=float)
+    assert got.shape == want.shape
+    return float(np.max(np.abs(got - want) / np.maximum(np.abs(want), 1e-300)))
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_1d_batch_means_parity(she, precision):
+    """A ragged 1D batch (Dirichlet PC rod with the full covariance, periodic
+    FE ring): 1900 samples in batches of 90, so 21 complete batches and an
+    incomplete one; she_run calls of odd lengths put batch ends inside
+    launches and on call boundaries.  Batch count, per-cell mean / variance
+    SE, S_k SE (from the batch covariance) and the spatial variance with its
+    SE equal the oracle's batch statistics (FP32 1e-3, FP64 1e-9)."""
+    insts = [inst1d((96,), W.DIRICHLET, W.HEUN, W.HEAT, 0), inst1d((40,), W.PERIODIC, W.EM, W.HEAT, 1)]
+    L, burn, every, steps = 90, 300, 3, 6000
+    h = she.Handle([gpu_instance(she, i) for i in insts], precision=precision, burn_in=burn, sample_every=every,
+                   stats=she.STAT_MOMENTS | she.STAT_CORR, batch_samples=L)
+    init = [h.read_field(q) for q in range(2)]
+    for k in (1000, 1, 777, 2222, 2000):
+        h.run(k)
+    tol = 1e-3 if precision == 0 else 1e-9
+    for q in range(2):
+        g = h.stats(q, corr=True, sk=True, se=True)
+        d = oracle_desc(insts[q], precision)
+        st = oracle.Stats(d, burn_in=burn, every=every, corr=True, sk=True, batch=L)
+        u = init[q].copy()
+        oracle.advance(d, u, 0, steps, st)
+        assert g["n_samples"] == st.n_samples == 1900
+        assert g["n_batches"] == st.n_batches == 21
+        se = st.se()
+        for key in ("mean", "var"):
+            err = se_close(g[key + "_se"], se[key], tol)
+            assert err < tol, (q, key, err)
+        # periodic rings conserve sum U, so |U_0|^2 is the same in every batch:
+        # its SE is round-off on both sides, compared on the scale of S_0
+        k0 = 1 if insts[q]["bc"] == W.PERIODIC else 0
+        err = se_close(g["sk_se"][k0:], se["sk"][k0:], tol)
+        assert err < tol, (q, "sk", err)
+        assert g["sk_se"][0] <= max(1e-6 * g["sk"][0], 1.1 * se["sk"][0])
+        assert abs(g["spatial_var"] / st.spatial()[2] - 1) < tol
+        assert abs(g["spatial_var_se"] / se["spatial_var"] - 1) < tol
+    h.close()
+
+
+@pytest.mark.parametrize("n,scheme,graph", [((32, 16), W.EM, 0), ((32, 16), W.HEUN, 0), ((32, 16), W.EM, 12),
+                                            ((16, 8, 6), W.EM, 0), ((16, 8, 6), W.HEUN, 0)],
+                         ids=["2d-fe", "2d-pc", "2d-fe-graph", "3d-fe", "3d-pc"])
+def test_nd_batch_means_parity(she, n, scheme, graph):
+    """2D / 3D: the spatial mean and variance (and in 2D every S(k) shell)
+    folded per batch on the device at the sample that completes it, also
+    inside replayed graphs: batch count and SE equal the oracle's (FP32,
+    1e-3), with 22 complete batches and an incomplete one."""
+    two = len(n) == 2
+    insts = [inst2d(n, scheme, W.HEAT, realisation=q) if two else inst3d(n, W.SPECIES, realisation=q, scheme=scheme)
+             for q in range(2)]
+    L, burn, every, steps = 9, 20, 2, 420
+    mask = she.STAT_SPATIAL | (she.STAT_SK if two else 0)
+    h = she.Handle([gpu_instance(she, i) for i in insts], precision=0, burn_in=burn, sample_every=every, stats=mask,
+                   batch_samples=L, graph_steps=graph)
+    init = [h.read_field(q) for q in range(2)]
+    for k in (33, 200, 1, 186):
+        h.run(k)
+    for q in range(2):
+        g = h.stats(q, sk=two, se=True)
+        d = oracle_desc(insts[q], 0)
+        st = oracle.Stats(d, burn_in=burn, every=every, per_cell=False, sk=two, batch=L)
+        u = init[q].copy()
+        oracle.advance(d, u, 0, steps, st)
+        assert g["n_samples"] == st.n_samples == 200
+        assert g["n_batches"] == st.n_batches == 22
+        se = st.se()
+        assert se_close(g["var_se"][0], se["spatial_var"], 1e-3) < 1e-3
+        assert se_close(g["spatial_var_se"], se["spatial_var"], 1e-3) < 1e-3
+        # the spatial mean is conserved (periodic): its batch values agree to
+        # round-off and their SE is round-off, on the scale of u0
+        u0 = insts[q]["u0"]
+        assert g["mean_se"][0] < 1e-6 * u0 and se["spatial_mean"] < 1e-12 * u0
+        if two:
+            ok = g["sk_modes"] > 0
+            ok[0] = False                 # |sum U|^2: conserved, as the mean
+            assert se_close(g["sk_se"][ok], se["sk"][ok], 1e-3) < 1e-3
+    h.close()
+
+
+def test_batch_means_checkpoint_and_reset(she):
+    """Checkpoints carry the batch accumulators (resume is bit-exact, error
+    bars included); she_reset_stats restarts the batches with the samples."""
+    for inst in (inst1d((64,), W.DIRICHLET, W.HEUN, W.HEAT, 0), inst2d((32, 16), W.EM, W.HEAT)):
+        one_d = len(inst["n"]) == 1
+        mask = she.STAT_MOMENTS | she.STAT_CORR if one_d else she.STAT_SPATIAL | she.STAT_SK
+        kw = dict(precision=0, burn_in=0, sample_every=2, stats=mask, batch_samples=25)
+        a = she.Handle([gpu_instance(she, inst)], **kw)
+        a.run(700)
+        blob = a.get_state()
+        a.run(913)
+        sa = a.stats(0, sk=True, se=True)
+        b = she.Handle([gpu_instance(she, inst)], **kw)
+        b.set_state(blob)
+        b.run(913)
+        sb = b.stats(0, sk=True, se=True)
+        for key in ("var_se", "mean_se", "sk_se"):
+            np.testing.assert_array_equal(sa[key], sb[key])
+        assert sa["n_batches"] == sb["n_batches"] == 806 // 25
+        a.reset_stats()
+        a.run(101)                         # even steps 1614 .. 1714: 51 samples
+        s = a.stats(0, se=True)
+        assert s["n_samples"] == 51 and s["n_batches"] == 2 and np.all(np.isfinite(s["var_se"]))
+        a.run(1)
+        assert a.stats(0, se=True)["n_batches"] == 2
+        a.close()
+        b.close()
