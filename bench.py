@@ -58,13 +58,14 @@ def _section(text: str, start: str, end: str) -> str:
 
 def kernel_hash(variant: str) -> str:
     """Hash of what decides a step kernel's instruction stream and HBM
-    traffic: the kernel header, the noise header, the translation unit that
+    traffic: the kernel header, the transform header (the row transforms of
+    sample launches), the noise header, the translation unit that
     instantiates the kernel (variant: she_k2d_f32x8.hip for c3, she_k3d_f32.hip
     for c5), the host functions that pick its launch shapes and the parameter
     structs it takes.  Counter records carry it; a record whose hash differs
     is stale and not used."""
     h = hashlib.sha256()
-    for name in ("she_step_nd.hpp", "she_rng.hpp", variant):
+    for name in ("she_step_nd.hpp", "she_fft.hpp", "she_rng.hpp", variant):
         with open(os.path.join(CSRC, name), "rb") as f:
             h.update(f.read())
     with open(os.path.join(CSRC, "she_capi.hip")) as f:
@@ -282,11 +283,13 @@ def cpu_baseline(cfg, seconds: float):
 # ---------------------------------------------------------------- roofline
 
 def roofline(kms_per_step, cells, per_launch, every, kernel, variant, valu_file, traffic_file):
-    """Roofline of a step kernel from its HIP-event time per step.  Bound: the
-    VALU issue when a counter record for this kernel exists (achieved =
-    lane-instructions per launch, SQ_INSTS_VALU x 64 weighted by one sample
-    launch per sampling period, over the launch time; peak = non-packed
-    issue of 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz), else HBM.  The HBM
+    """Roofline of a step kernel from its HIP-event time per step, which
+    brackets the launches outside sample steps only.  Bound: the VALU issue
+    when a counter record for this kernel exists (achieved = lane-instructions
+    of such a launch, SQ_INSTS_VALU x 64, over the launch time; peak =
+    non-packed issue of 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz), else HBM.
+    The sample launches' count (which includes the row transforms of S(k)
+    in 2D) is reported beside it.  The HBM
     side is reported either way: algorithmic bytes (8 B per FP32
     cell-update) and, from a FETCH_SIZE / WRITE_SIZE record, the bus bytes."""
     launch_ms = kms_per_step * per_launch
@@ -305,15 +308,13 @@ def roofline(kms_per_step, cells, per_launch, every, kernel, variant, valu_file,
     out = dict(kernel=kernel, kernel_ms=launch_ms, cell_updates_per_launch=cu, traffic=traffic, hbm=hbm)
     v = read_record(valu_file, variant) if valu_file else None
     if v:
-        per_period = max(1, every // per_launch)
         q = v["valu_insts_per_launch"]
         qs = v.get("sample_valu_insts_per_launch") or q
-        insts = ((per_period - 1) * q + qs) / per_period
-        lane = insts * 64
+        lane = q * 64
         ach = lane / (launch_ms * 1e-3) / 1e12
         out.update(bound="alu", achieved=ach, peak=VALU_PEAK_TLANE, unit="Tlane-instr/s", frac=ach / VALU_PEAK_TLANE,
                    lane_instr_per_launch=lane, lane_instr_per_cell_update=lane / cu,
-                   valu_source="profiles/" + valu_file)
+                   sample_lane_instr_per_launch=qs * 64, valu_source="profiles/" + valu_file)
     else:
         out.update(bound="hbm", achieved=alg_gbs, peak=HBM_PEAK_GBS, unit="GB/s", frac=alg_gbs / HBM_PEAK_GBS)
     return out

@@ -88,6 +88,7 @@ struct she_handle {
     // 2D structure factor
     int nbins = 0, sk_groups = 0;
     void *d_half = nullptr, *d_twx = nullptr, *d_twy = nullptr;
+    uint16_t *d_shells = nullptr;  // first |ky| of each shell per column (shell_table)
     double *d_skpart = nullptr, *d_sksum = nullptr, *d_skmodes = nullptr;
     std::vector<double> skmodes;
     // captured step loops: [0] without, [1] with sample steps
@@ -101,6 +102,9 @@ struct she_handle {
     // march chunks of chunk2 rows
     bool two_step = false;
     int chunk2 = 0, nparts2 = 0, nd_blocks2 = 0;
+    // 2D FE with S(k): the two-step sample launches transform their rows
+    // themselves (one row per wave, even march chunks)
+    bool sk_fused = false;
 
     void *field() const { return dim == 1 ? d_pool : (cur == 0 ? d_a : d_b); }
     // 1D: per-cell sums are kept (and so per-cell batch means)
@@ -806,10 +810,12 @@ static she_status plan_nd(she_handle *h, const she_config *cfg, Plan &plan)
                 if (b < h->nbins) h->skmodes[b] += 1.0;
             }
         h->sk_groups = sk2d_groups(h->prec, nx, p.ny, h->n_inst);
-        const size_t nh = static_cast<size_t>(nx / 2 + 1);
-        plan.add(&h->d_half, 2 * es * nh * p.ny * h->n_inst);
+        const int ltc = half_tile_log2(h->prec, p.ny);
+        plan.add(&h->d_half, 2 * es * (static_cast<size_t>(half_tiles(nx, ltc)) << ltc) * p.ny * h->n_inst);
         plan.add(&h->d_twx, 2 * es * nx);
         plan.add(&h->d_twy, 2 * es * p.ny);
+        plan.add(reinterpret_cast<void **>(&h->d_shells),
+                 sizeof(uint16_t) * static_cast<size_t>(nx / 2 + 1) * (h->nbins + 1));
         plan.add(reinterpret_cast<void **>(&h->d_skpart), sizeof(double) * h->n_inst * h->sk_groups * h->nbins);
         plan.add(reinterpret_cast<void **>(&h->d_sksum), sizeof(double) * h->n_inst * h->nbins);
         plan.add(reinterpret_cast<void **>(&h->d_skmodes), sizeof(double) * h->nbins);
@@ -856,6 +862,13 @@ static she_status build_plan(she_handle *h, const she_config *cfg, Plan &plan)
         const int gpb = 256 / (p.nx / h->cx);
         h->nd_blocks2 = (h->n_inst * h->nparts2 + gpb - 1) / gpb;
         h->two_step = true;
+        if ((h->mask & SHE_STAT_SK) && sk_rows_fusable(h->prec, p.nx) && p.ny % 2 == 0) {
+            // row pairs must not straddle march chunks
+            h->chunk2 += h->chunk2 & 1;
+            h->nparts2 = (p.ny + h->chunk2 - 1) / h->chunk2;
+            h->nd_blocks2 = (h->n_inst * h->nparts2 + gpb - 1) / gpb;
+            h->sk_fused = true;
+        }
     }
     plan.add(reinterpret_cast<void **>(&h->d_acc), sizeof(InstAcc) * h->n_inst);
     plan.add(reinterpret_cast<void **>(&h->d_init_sd), sizeof(double) * h->n_inst);
@@ -1081,6 +1094,7 @@ extern "C" she_status she_create(const she_config *cfg, she_handle **out)
                                       hipMemcpyHostToDevice, s));
             CREATE_HIP(launch_twiddles(h->prec, s, h->pnd.nx, h->d_twx));
             CREATE_HIP(launch_twiddles(h->prec, s, h->pnd.ny, h->d_twy));
+            CREATE_HIP(launch_shell_table(s, h->pnd.nx, h->pnd.ny, h->nbins, h->d_shells));
         }
         CREATE_HIP(launch_initnd(h->prec, s, h->pnd, h->cells, h->d_a));
         h->cur = 0;
@@ -1124,12 +1138,17 @@ static hipError_t nd_enqueue(she_handle *h, hipStream_t s, const StepArg &sa, in
     const void *src = cur == 0 ? h->d_a : h->d_b;
     void *dst = cur == 0 ? h->d_b : h->d_a;
     hipError_t e;
+    const bool fused = two && may_sample && h->sk_fused;
     if (two) {
         // the handle's parameters (with their device pointers) and the
-        // two-step march length
+        // two-step march length; on sample launches with S(k), the row
+        // transforms of the new field as well
         ParamsND p2 = h->pnd;
         p2.chunk = h->chunk2;
-        e = launch_step2d(h->prec, h->cx, p2.eq, 2, h->nd_blocks2, s, p2, src, dst, sa, h->d_part, h->d_acc);
+        const int ltc = half_tile_log2(h->prec, p2.ny);
+        const SkRows skr{h->d_half, h->d_twx, ltc, half_tiles(p2.nx, ltc)};
+        e = launch_step2d(h->prec, h->cx, p2.eq, 2, h->nd_blocks2, s, p2, src, dst, sa, h->d_part, h->d_acc,
+                          fused ? &skr : nullptr);
     }
     else if (h->dim == 2)
         e = launch_step2d(h->prec, h->cx, h->pnd.eq, h->pnd.scheme, h->nd_blocks, s, h->pnd, src, dst, sa, h->d_part,
@@ -1154,7 +1173,7 @@ static hipError_t nd_enqueue(she_handle *h, hipStream_t s, const StepArg &sa, in
     const BatchSk bk{h->d_sksnap, h->d_skwm, h->d_skwm2, h->d_skmodes, static_cast<double>(h->cells), h->pnd.u0,
                      h->d_sksnap ? h->batch_len : 0, 0};
     return launch_sk2d(h->prec, s, sa, h->n_inst, h->pnd.nx, h->pnd.ny, h->pnd.u0, dst, h->d_half, h->d_twx, h->d_twy,
-                       h->d_skpart, h->nbins, h->d_sksum, h->d_acc, bk);
+                       h->d_shells, h->d_skpart, h->nbins, h->d_sksum, h->d_acc, bk, fused);
 }
 
 // Whether completed step t samples.

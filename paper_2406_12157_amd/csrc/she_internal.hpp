@@ -244,11 +244,27 @@ hipError_t launch_fin1d(int prec, hipStream_t s, const Inst1D *tab, int inst, in
                         const double *c, int64_t n_samples, int partial_rows, bool corr,
                         double *out);
 
+// Where a sample launch of the two-step 2D FE march puts the row transforms
+// of the rows it writes (the first stage of the structure factor).
+struct SkRows {
+    void *half;             // column-tiled half spectrum (half_index), complex state type
+    const void *tw;         // natural twiddles exp(-2 pi i t / nx), complex state type
+    int32_t ltc;            // log2 of the columns per tile
+    int32_t nkb;            // tiles per instance
+};
+
+// Whether the two-step march can transform its sample rows itself: one row
+// per wave (nx = 512 or 1024) and the LDS of four waves' transforms within
+// 64 KB (FP32, or FP64 at nx = 512).
+inline bool sk_rows_fusable(int prec, int nx) { return nx == 512 || (nx == 1024 && prec == 0); }
+
 // scheme: 0 FE, 1 PC, 2 two FE steps in one pass (steps st.step and
-// st.step + 1; the spatial partials are those of the second)
+// st.step + 1; the spatial partials are those of the second).  skr
+// (scheme 2, a sample launch, sk_rows_fusable, even march chunks): also
+// write the row transforms of the sampled field.
 hipError_t launch_step2d(int prec, int cx, int eq, int scheme, int n_blocks, hipStream_t s,
                          const ParamsND &p, const void *src, void *dst, const StepArg &st,
-                         double *part, InstAcc *acc);
+                         double *part, InstAcc *acc, const SkRows *skr = nullptr);
 // stage 0: dst = src + Delta(src) (FE, or the PC predictor); stage 1: the PC
 // corrector dst = (base + src + Delta(src)) / 2 with src the predictor.
 hipError_t launch_step3d(int prec, int cx, int eq, int stage, int ty, int n_blocks, size_t smem,
@@ -292,12 +308,29 @@ hipError_t launch_debug_normals(hipStream_t s, int prec, uint64_t seed, uint32_t
                                 uint32_t tag, uint64_t step, uint64_t face0, int64_t count,
                                 double *out);
 
-// 2D structure factor on a sample step: row FFTs, column FFTs + shell
-// binning into per-block partials, fixed-order reduction into sums
-// (n_inst x nbins FP64).  half: n_inst*ny*(nx/2+1) complex of the state type.
+// Column-tiled half spectrum of 2D fields: the columns kx = 0..nx/2 of each
+// instance in tiles of 2^ltc (nkb tiles, the last one padded); a tile holds
+// rows y = 0..ny-1 of its columns row-major, so a row's piece of a tile is
+// one contiguous run and a tile is one contiguous block.
+__host__ __device__ inline int64_t half_index(int inst, int y, int kx, int ny, int ltc, int nkb)
+{
+    return (((static_cast<int64_t>(inst) * nkb + (kx >> ltc)) * ny + y) << ltc) | (kx & ((1 << ltc) - 1));
+}
+// log2 of the columns per tile (those the column transform takes at once)
+int half_tile_log2(int prec, int ny);
+inline int half_tiles(int nx, int ltc) { return (nx / 2 + 1 + (1 << ltc) - 1) >> ltc; }
+
+// 2D structure factor on a sample step: row FFTs into the column-tiled half
+// spectrum (skipped with rows_done: the step kernel wrote it), column FFTs +
+// shell binning into per-block partials, fixed-order reduction into sums
+// (n_inst x nbins FP64).  half: n_inst * ny * (half_tiles << ltc) complex of
+// the state type.
 hipError_t launch_sk2d(int prec, hipStream_t s, const StepArg &st, int n_inst, int nx, int ny, double u0,
-                       const void *field, void *half, const void *twx, const void *twy, double *part, int nbins,
-                       double *sums, const InstAcc *acc, const BatchSk &bk);
+                       const void *field, void *half, const void *twx, const void *twy, const uint16_t *shells,
+                       double *part, int nbins, double *sums, const InstAcc *acc, const BatchSk &bk, bool rows_done);
+// shells[kx (nbins + 1) + b], kx = 0..nx/2, b = 0..nbins: the first |ky| of
+// shell b in column kx (the range of |ky| in shell b is [first(b), first(b+1)))
+hipError_t launch_shell_table(hipStream_t s, int nx, int ny, int nbins, uint16_t *shells);
 // exp(-2 pi i t/n), t < n/2, as complex pairs of the state type
 hipError_t launch_twiddles(int prec, hipStream_t s, int n, void *tw);
 int sk2d_groups(int prec, int nx, int ny, int n_inst);

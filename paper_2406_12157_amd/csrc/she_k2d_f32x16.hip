@@ -3,5 +3,5 @@
 
 namespace she {
 template hipError_t step2d_e<float, 16>(int, int, int, hipStream_t, const ParamsND &, const void *, void *,
-                                        const StepArg &, double *, InstAcc *);
+                                        const StepArg &, double *, InstAcc *, const SkRows *);
 }  // namespace she

@@ -3,9 +3,9 @@
 
 namespace she {
 template hipError_t step2d_e<double, 4>(int, int, int, hipStream_t, const ParamsND &, const void *, void *,
-                                        const StepArg &, double *, InstAcc *);
+                                        const StepArg &, double *, InstAcc *, const SkRows *);
 template hipError_t step2d_e<double, 8>(int, int, int, hipStream_t, const ParamsND &, const void *, void *,
-                                        const StepArg &, double *, InstAcc *);
+                                        const StepArg &, double *, InstAcc *, const SkRows *);
 template hipError_t step2d_e<double, 16>(int, int, int, hipStream_t, const ParamsND &, const void *, void *,
-                                         const StepArg &, double *, InstAcc *);
+                                         const StepArg &, double *, InstAcc *, const SkRows *);
 }  // namespace she

@@ -6,14 +6,17 @@
 // field dU = U - u0 (which changes only the k = 0 mode; the finalisation
 // restores that mode exactly from the spatial sums), in the state's precision.
 //
-// 1. k_sk_rows: two real rows are packed as one complex sequence
+// 1. Row transforms: two real rows are packed as one complex sequence
 //    (dU_a + i dU_b) and transformed along x by one wave; the two half spectra
-//    A_k = (Z_k + conj Z_-k)/2, B_k = (Z_k - conj Z_-k)/(2i) are stored
-//    kx-major (y fastest), so that the waves of a block, which hold
-//    consecutive row pairs, write runs of consecutive y per kx.
-// 2. k_sk_cols: each wave transforms half-spectrum columns (contiguous in
-//    memory) along y, looping over the block's columns and loading the next
-//    column while it transforms the current one.  The power |X|^2 gets weight
+//    A_k = (Z_k + conj Z_-k)/2, B_k = (Z_k - conj Z_-k)/(2i), kx = 0..Nx/2,
+//    are stored column-tiled: tiles of the columns one column-transform block
+//    takes, each tile Ny rows of its columns, row-major and contiguous.  On the sample launches of
+//    the two-step 2D FE march the step kernel does this itself for the rows
+//    it has just written (she_step_nd.hpp); otherwise k_sk_rows reads the
+//    field back.
+// 2. k_sk_colt: a block streams a tile of columns of the half spectrum into
+//    its waves' LDS regions (the transpose), and each wave transforms its
+//    columns along y.  The power |X|^2 gets weight
 //    2 for 0 < kx < Nx/2 (the mirrored half of the spectrum) and is binned
 //    without atomics: per column the wave forms the FP64 prefix sum P(m) of
 //    the power over |ky| <= m (fixed-order scan), and lane b adds
@@ -31,235 +34,14 @@
 // passes the wave exchanges them through its own LDS region, so a transform
 // needs no workgroup barrier.  The twiddle table exp(-2 pi i t/n) is
 // precomputed once per handle and staged in LDS.
+#include "she_fft.hpp"
 #include "she_internal.hpp"
 #include "she_wave.hpp"
 
 #include <algorithm>
+#include <cmath>
 
 namespace she {
-
-// Aligned to its size, so that one lane's point moves in one 64-bit (FP32)
-// or 128-bit (FP64) LDS access; at the alignment of T every exchange store
-// and load splits into two, and the transforms are bound by the LDS.
-template <typename T>
-struct alignas(2 * sizeof(T)) cplx {
-    T re, im;
-};
-
-template <typename T>
-__device__ __forceinline__ cplx<T> cadd(cplx<T> a, cplx<T> b)
-{
-    return cplx<T>{a.re + b.re, a.im + b.im};
-}
-
-template <typename T>
-__device__ __forceinline__ cplx<T> csub(cplx<T> a, cplx<T> b)
-{
-    return cplx<T>{a.re - b.re, a.im - b.im};
-}
-
-template <typename T>
-__device__ __forceinline__ cplx<T> cmul(cplx<T> a, cplx<T> w)
-{
-    return cplx<T>{a.re * w.re - a.im * w.im, a.re * w.im + a.im * w.re};
-}
-
-// Shape of the per-wave transform of length n = 2^lg: P points per lane,
-// S sequences per wave (64 P = S n), padded LDS entries per wave region.
-constexpr int wave_points(int lg)
-{
-    return (1 << lg) >= 512 ? (1 << lg) / 64 : ((1 << lg) >= 8 ? 8 : (1 << lg));
-}
-
-constexpr int wave_seqs(int lg)
-{
-    return (64 * wave_points(lg)) >> lg;
-}
-
-constexpr int wave_lds(int lg)
-{
-    return (wave_seqs(lg) << lg) + (((wave_seqs(lg) << lg) - 1) >> 4) + 1;
-}
-
-// log2 of the radix of the pass at sub-transform length 2^rem: 8, then 4 or 2
-constexpr int pass_lr(int rem)
-{
-    return rem >= 3 ? 3 : rem;
-}
-
-// Twiddles per pass, laid out [p][k-1] (k = 1..R-1) so that the lanes of a
-// pass, which differ in p, read R-1 consecutive entries each (odd stride: no
-// bank conflicts).  A pass at sub-length 2^rem has 2^(rem - lr) values of p
-// and none when it is the last one.  Entries of the passes from 2^rem down:
-constexpr int tw_entries(int rem)
-{
-    return rem <= 0 ? 0
-                    : (rem > pass_lr(rem) ? (1 << (rem - pass_lr(rem))) * ((1 << pass_lr(rem)) - 1) : 0) +
-                          tw_entries(rem - pass_lr(rem));
-}
-
-template <int LG>
-struct WaveFft {
-    static constexpr int n = 1 << LG;
-    static constexpr int P = wave_points(LG);
-    static constexpr int S = wave_seqs(LG);
-    static constexpr int lds = wave_lds(LG);
-    static constexpr int tw = tw_entries(LG) > 0 ? tw_entries(LG) : 1;  // per-pass twiddle entries
-};
-
-// one pad entry per 16 spreads the strided exchange accesses over the banks
-__device__ __forceinline__ int pidx(int i)
-{
-    return i + (i >> 4);
-}
-
-// Order the LDS accesses of one wave (a wave's LDS operations complete in
-// issue order; this keeps the compiler from moving them across).
-__device__ __forceinline__ void wave_sync()
-{
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
-// In-register DFTs of length 2, 4, 8 (natural order in and out).
-template <typename T>
-__device__ __forceinline__ void dft2(cplx<T> *a)
-{
-    const cplx<T> t = a[0];
-    a[0] = cadd(t, a[1]);
-    a[1] = csub(t, a[1]);
-}
-
-template <typename T>
-__device__ __forceinline__ void dft4(cplx<T> &a0, cplx<T> &a1, cplx<T> &a2, cplx<T> &a3)
-{
-    const cplx<T> t0 = cadd(a0, a2), t1 = csub(a0, a2), t2 = cadd(a1, a3);
-    const cplx<T> d = csub(a1, a3);
-    const cplx<T> t3{d.im, -d.re};  // -i (a1 - a3)
-    a0 = cadd(t0, t2);
-    a1 = cadd(t1, t3);
-    a2 = csub(t0, t2);
-    a3 = csub(t1, t3);
-}
-
-template <typename T>
-__device__ __forceinline__ void dft8(cplx<T> *a)
-{
-    // even and odd halves, then w8^k on the odd outputs
-    dft4(a[0], a[2], a[4], a[6]);
-    dft4(a[1], a[3], a[5], a[7]);
-    const T c = static_cast<T>(0.70710678118654752440);
-    const cplx<T> o1{c * (a[3].re + a[3].im), c * (a[3].im - a[3].re)};  // (1 - i)/sqrt2
-    const cplx<T> o2{a[5].im, -a[5].re};                                 // -i
-    const cplx<T> o3{c * (a[7].im - a[7].re), -c * (a[7].re + a[7].im)}; // (-1 - i)/sqrt2
-    const cplx<T> e0 = a[0], e1 = a[2], e2 = a[4], e3 = a[6], o0 = a[1];
-    a[0] = cadd(e0, o0);
-    a[4] = csub(e0, o0);
-    a[1] = cadd(e1, o1);
-    a[5] = csub(e1, o1);
-    a[2] = cadd(e2, o2);
-    a[6] = csub(e2, o2);
-    a[3] = cadd(e3, o3);
-    a[7] = csub(e3, o3);
-}
-
-template <int REM>
-struct PassRadix {
-    static constexpr int LR = pass_lr(REM);
-};
-
-// Inputs of a pass of radix R = 2^LR: lane slot i*R + k holds element
-// t + k n/R of sequence seq, for butterfly b = lane + 64 i = seq (n/R) + t.
-template <int LG, int LR>
-__device__ __forceinline__ void pass_input(int lane, int i, int k, int &seq, int &idx)
-{
-    constexpr int n = 1 << LG;
-    const int b = lane + 64 * i;
-    seq = b >> (LG - LR);
-    idx = (b & ((n >> LR) - 1)) + k * (n >> LR);
-}
-
-// Remaining passes of the wave transform from sub-transform length 2^REM.
-// Butterfly t = q + s p (s = 2^(LG-REM), q < s) forms the R-point DFT of its
-// inputs, multiplies output k by exp(-2 pi i k p s / n) and writes it to
-// element q + s (R p + k).  After the last pass the wave's LDS region holds
-// the transforms in natural order.
-template <typename T, int LG, int REM>
-__device__ __forceinline__ void wave_fft(cplx<T> (&v)[WaveFft<LG>::P], cplx<T> *buf, const cplx<T> *tw, int lane)
-{
-    using F = WaveFft<LG>;
-    constexpr int LR = PassRadix<REM>::LR, R = 1 << LR, B = F::P / R, n = F::n;
-    constexpr int ls = LG - REM, s = 1 << ls;
-    // this pass's twiddles first, all of them: read between the region
-    // stores they would each wait for the stores before them
-    constexpr int NW = REM > LR ? R - 1 : 0;
-    cplx<T> wt[B][NW > 0 ? NW : 1];
-    if constexpr (NW > 0) {
-#pragma unroll
-        for (int i = 0; i < B; ++i) {
-            const int p = ((lane + 64 * i) & ((n >> LR) - 1)) >> ls;
-#pragma unroll
-            for (int k = 0; k < NW; ++k) wt[i][k] = tw[(tw_entries(LG) - tw_entries(REM)) + p * NW + k];
-        }
-    }
-#pragma unroll
-    for (int i = 0; i < B; ++i) {
-        const int b = lane + 64 * i;
-        const int seq = b >> (LG - LR), t = b & ((n >> LR) - 1);
-        const int q = t & (s - 1), p = t >> ls;
-        cplx<T> *a = &v[i * R];
-        if constexpr (R == 8) dft8(a);
-        else if constexpr (R == 4) dft4(a[0], a[1], a[2], a[3]);
-        else dft2(a);
-        const int base = (seq << LG) + q + s * R * p;
-#pragma unroll
-        for (int k = 0; k < R; ++k) {
-            cplx<T> o = a[k];
-            if constexpr (NW > 0) {
-                if (k > 0) o = cmul(o, wt[i][k - 1]);
-            }
-            buf[pidx(base + s * k)] = o;
-        }
-    }
-    wave_sync();
-    if constexpr (REM > LR) {
-        constexpr int REM2 = REM - LR, LR2 = PassRadix<REM2>::LR, R2 = 1 << LR2;
-#pragma unroll
-        for (int i = 0; i < F::P / R2; ++i) {
-#pragma unroll
-            for (int k = 0; k < R2; ++k) {
-                int seq, idx;
-                pass_input<LG, LR2>(lane, i, k, seq, idx);
-                v[i * R2 + k] = buf[pidx((seq << LG) + idx)];
-            }
-        }
-        wave_sync();
-        wave_fft<T, LG, REM2>(v, buf, tw, lane);
-    }
-}
-
-// Per-pass twiddle tables of a length-2^LG transform from the natural table
-// exp(-2 pi i t/n): pass at sub-length 2^rem, stride s = 2^(LG-rem), entry
-// (p, k) = exp(-2 pi i k p s / n).  Block-cooperative.
-template <typename T, int LG>
-__device__ __forceinline__ void fill_pass_twiddles(cplx<T> *dst, const cplx<T> *__restrict__ nat)
-{
-    constexpr int n = 1 << LG;
-    int off = 0;
-    for (int rem = LG; rem > 0;) {
-        const int lr = pass_lr(rem), r = 1 << lr;
-        if (rem > lr) {
-            const int m = 1 << (rem - lr), s = 1 << (LG - rem);
-            for (int e = threadIdx.x; e < m * (r - 1); e += blockDim.x) {
-                const int p = e / (r - 1), k = e - p * (r - 1) + 1;
-                dst[off + e] = nat[(k * p * s) & (n - 1)];
-            }
-            off += m * (r - 1);
-        }
-        rem -= lr;
-    }
-}
 
 // twiddle table exp(-2 pi i t/n), t < n, in the transform's precision
 template <typename T>
@@ -296,7 +78,7 @@ constexpr int row_waves()
 template <typename T, int LGX>
 __global__ void __launch_bounds__(512)
     k_sk_rows(StepArg sarg, const T *__restrict__ field, int ny, double u0, const cplx<T> *__restrict__ twx,
-              cplx<T> *__restrict__ half)
+              cplx<T> *__restrict__ half, int ltc, int nkb)
 {
     SHE_SAMPLE_GATE();
     using F = WaveFft<LGX>;
@@ -331,23 +113,21 @@ __global__ void __launch_bounds__(512)
     __syncthreads();
     wave_fft<T, LGX, LGX>(v, reg + wave * F::lds, tw, lane);
     __syncthreads();
-    // kx-major store: per kx a run of 2*npairs consecutive y (rows fastest)
+    // column-tiled store: the block's rows of one tile are one contiguous run
     constexpr int nh = n / 2 + 1;
-    const int nrow = 2 * npairs;  // a power of two (ny and W S are)
-    const int lrow = 31 - __builtin_clz(nrow);
+    const int nrow = 2 * npairs, tcw = 1 << ltc;
     constexpr int lS = 31 - __builtin_clz(S);
-    cplx<T> *h = half + static_cast<int64_t>(inst) * nh * ny + 2 * pair0;
-    for (int e = threadIdx.x; e < nrow * nh; e += blockDim.x) {
-        const int k = e >> lrow, rr = e & (nrow - 1);
+    for (int e = threadIdx.x; e < nkb * nrow * tcw; e += blockDim.x) {
+        const int t = e / (nrow * tcw), rest = e - t * (nrow * tcw);
+        const int rr = rest >> ltc, k = (t << ltc) + (rest & (tcw - 1));
+        if (k >= nh) continue;
         const int pair = rr >> 1;
         const cplx<T> *z0 = reg + (pair >> lS) * F::lds;
         const int sb = (pair & (S - 1)) << LGX;
         const cplx<T> z = z0[pidx(sb + k)];
         const cplx<T> zm = z0[pidx(sb + ((n - k) & (n - 1)))];
         // A = (z + conj zm)/2 (row 2q), B = (z - conj zm)/(2i) (row 2q+1)
-        const cplx<T> o = (rr & 1) ? cplx<T>{T(0.5) * (z.im + zm.im), T(-0.5) * (z.re - zm.re)}
-                                   : cplx<T>{T(0.5) * (z.re + zm.re), T(0.5) * (z.im - zm.im)};
-        h[static_cast<int64_t>(k) * ny + rr] = o;
+        half[half_index(inst, 2 * pair0 + rr, k, ny, ltc, nkb)] = (rr & 1) ? unpack_b(z, zm) : unpack_a(z, zm);
     }
 }
 
@@ -357,14 +137,32 @@ __global__ void __launch_bounds__(512)
 // it, so they need no room of their own.
 constexpr int col_region(int es, int lg)
 {
-    return es * wave_lds(lg) + (wave_seqs(lg) == 1 ? 0 : 8 * ((1 << lg) / 2 + 1));
+    return es * wave_lds(lg) + (wave_seqs(lg) == 1 ? 0 : 8 * (((1 << lg) / 2 + 1) * 5 / 4 + 1));
 }
 
-// Waves per block of the column transform: 4, or 2 where 4 regions and the
-// twiddles exceed the LDS budget (the largest FP64 columns).
-constexpr int col_waves(int es, int lg)
+// Index of |ky| = m in a column's prefix sums: one pad entry per four, so the
+// lanes' runs of four consecutive m fall in distinct banks.
+__device__ __forceinline__ int ppad(int m)
 {
-    return es * tw_entries(lg) + 4 * col_region(es, lg) <= kLdsBudget ? 4 : 2;
+    return m + (m >> 2);
+}
+
+// Shape of the tiled column transform: a tile of TC = CW CPW S columns by Ny
+// rows holds up to 32 KB of points, at most eight column groups (of S
+// columns); a block has CW <= 4 waves and each wave transforms CPW groups of
+// the tile in turn.  Wide tiles keep the row runs of the column-tiled half
+// spectrum at 64 bytes and more; small blocks keep the barriers cheap.
+template <typename T, int LGY>
+constexpr int colt_groups()
+{
+    constexpr int w = 32768 / (64 * WaveFft<LGY>::P * static_cast<int>(sizeof(cplx<T>)));
+    return w >= 8 ? 8 : (w >= 4 ? 4 : (w >= 2 ? 2 : 1));
+}
+
+template <typename T, int LGY>
+constexpr int colt_waves()
+{
+    return colt_groups<T, LGY>() >= 4 ? 4 : colt_groups<T, LGY>();
 }
 
 constexpr int kMaxBinIters = 12;  // shells per lane: nbins <= 64 * 12
@@ -389,118 +187,239 @@ __device__ __forceinline__ int shell_first(int kx4, int b, int hy)
     return (b == 0 || need <= 0) ? 0 : min(m, hy + 1);
 }
 
-// Loads the column group of one wave iteration (S columns from `g`) in the
-// first pass's order; columns beyond nh are zero.
-template <typename T, int LGY>
-__device__ __forceinline__ void load_cols(cplx<T> (&v)[WaveFft<LGY>::P], const cplx<T> *__restrict__ hc, int g,
-                                          int nh, int lane)
+// The shell table: first(b) for every column kx = 0..Nx/2 and shell
+// b = 0..nbins (the same for every instance and sample; built once).
+__global__ void __launch_bounds__(256) k_shell_table(int nh, int nbins, int hy, uint16_t *__restrict__ tab)
 {
-    using F = WaveFft<LGY>;
-    constexpr int LR = PassRadix<LGY>::LR, R = 1 << LR;
+    const int64_t e = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
+    if (e >= static_cast<int64_t>(nh) * (nbins + 1)) return;
+    const int kx = static_cast<int>(e / (nbins + 1)), b = static_cast<int>(e - static_cast<int64_t>(kx) * (nbins + 1));
+    tab[e] = static_cast<uint16_t>(shell_first(4 * kx * kx, b, hy));
+}
+
+// Power spectrum of one column folded onto |ky| and its FP64 prefix sums, from
+// a transform held in registers (one sequence per wave: lane l holds
+// X(l + 64 j), j < P, slot i R + k for j = i + k P/R with R the last pass's
+// radix).  e(m) = |X(m)|^2 + |X(n - m)|^2 for 0 < m < n/2, |X(m)|^2 at m = 0
+// and m = n/2 (powers in T, their sum in FP64); pre[ppad(m)] = e(0) + ... + e(m).
+// The mirror X(n - m) of m = l + 64 j is X((64 - l) + 64 (P - 1 - j)) for
+// l > 0 (another lane, read with a lane permute) and X(64 (P - j)) for l = 0
+// (this lane).  The e(m) go through pre so that lane l sums the Q = P/2
+// consecutive m = Q l .. Q l + Q - 1 (lane 63 also m = n/2) in order, and the
+// lane totals are scanned once over the wave.
+template <typename T, int LG>
+__device__ __forceinline__ void col_power_prefix(const cplx<T> (&v)[WaveFft<LG>::P], double *pre, int lane)
+{
+    using F = WaveFft<LG>;
+    static_assert(F::S == 1, "one sequence per wave");
+    constexpr int P = F::P, n = F::n, hy = n / 2, Q = P / 2;
+    constexpr int LR = LG - 3 * ((LG - 1) / 3), R = 1 << LR;  // radix 8 passes, then this one
+    T pw[P];
 #pragma unroll
-    for (int i = 0; i < F::P / R; ++i) {
+    for (int i = 0; i < P / R; ++i) {
 #pragma unroll
         for (int k = 0; k < R; ++k) {
-            int seq, y;
-            pass_input<LGY, LR>(lane, i, k, seq, y);
-            v[i * R + k] = g + seq < nh ? hc[(static_cast<int64_t>(g + seq) << LGY) + y] : cplx<T>{T(0), T(0)};
+            const cplx<T> x = v[i * R + k];
+            pw[i + k * (P / R)] = x.re * x.re + x.im * x.im;
+        }
+    }
+    const int src = ((64 - lane) & 63) << 2;
+#pragma unroll
+    for (int j = 0; j < Q; ++j) {
+        T mir;
+        if constexpr (sizeof(T) == 4) {
+            mir = __int_as_float(__builtin_amdgcn_ds_bpermute(src, __float_as_int(pw[P - 1 - j])));
+        } else {
+            const long long u = __double_as_longlong(pw[P - 1 - j]);
+            const int lo = __builtin_amdgcn_ds_bpermute(src, static_cast<int>(u & 0xffffffffLL));
+            const int hi = __builtin_amdgcn_ds_bpermute(src, static_cast<int>(u >> 32));
+            mir = __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<unsigned>(lo));
+        }
+        if (lane == 0) mir = j == 0 ? T(0) : pw[P - j];
+        pre[ppad(lane + 64 * j)] = static_cast<double>(pw[j]) + static_cast<double>(mir);
+    }
+    if (lane == 0) pre[ppad(hy)] = static_cast<double>(pw[Q]);
+    wave_sync();
+    double loc[Q + 1];
+    double run = 0.0;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        run += pre[ppad(Q * lane + i)];
+        loc[i] = run;
+    }
+    loc[Q] = lane == 63 ? run + pre[ppad(hy)] : 0.0;
+    // exclusive prefix of the lane totals: the inclusive scan moved one lane up
+    const long long u = __double_as_longlong(wave_inclusive_sum(run));
+    const int elo = __builtin_amdgcn_update_dpp(0, static_cast<int>(u & 0xffffffffLL), 0x138, 0xf, 0xf, false);
+    const int ehi = __builtin_amdgcn_update_dpp(0, static_cast<int>(u >> 32), 0x138, 0xf, 0xf, false);
+    const double excl = __longlong_as_double((static_cast<long long>(ehi) << 32) | static_cast<unsigned>(elo));
+    wave_sync();
+#pragma unroll
+    for (int i = 0; i < Q; ++i) pre[ppad(Q * lane + i)] = excl + loc[i];
+    if (lane == 63) pre[ppad(hy)] = excl + loc[Q];
+}
+
+// Adds column kx's power to the shell sums: lane b of group j takes shell
+// b = lane + 64 j, the range [first(b), first(b + 1)) of |ky| (from the shell
+// table, col = its row for kx), as pre[first(b + 1) - 1] - pre[first(b) - 1],
+// with weight 2 off the kx = 0 and Nx/2 columns (the mirrored half of the
+// spectrum; an exact scaling).  first(b) and its prefix value are lane
+// b - 1's, moved one lane up; lane 0 takes those of lane 63 of the previous
+// group, and 0 for the first group met (its shells lie below kx, first = 0).
+// Only shells kx .. round(sqrt(kx^2 + hy^2)) (bound by excess) meet the column.
+template <int NBJ>
+__device__ __forceinline__ void bin_column(double (&acc)[NBJ], const double *pre, const uint16_t *__restrict__ col,
+                                           int kx, int nx, int nbins, int nbj, int hy, int lane)
+{
+    const double w = (kx == 0 || 2 * kx == nx) ? 1.0 : 2.0;
+    const int jlo = kx >> 6;
+    const int jhi = static_cast<int>(__builtin_amdgcn_sqrtf(static_cast<float>(kx * kx + hy * hy)) + 1.5f) >> 6;
+    int m1s[NBJ];
+#pragma unroll
+    for (int j = 0; j < NBJ; ++j) {
+        const int b = lane + 64 * j;
+        m1s[j] = (j >= jlo && j <= jhi && j < nbj && b < nbins) ? static_cast<int>(col[b + 1]) : hy + 1;
+    }
+    int carry = 0, clo = 0, chi = 0;
+#pragma unroll
+    for (int j = 0; j < NBJ; ++j) {
+        if (j >= jlo && j <= jhi && j < nbj) {
+            const int b = lane + 64 * j;
+            const int m1 = m1s[j];
+            const int m0 = __builtin_amdgcn_update_dpp(carry, m1, 0x138, 0xf, 0xf, false);  // wave_shr:1
+            const double p1 = m1 > 0 ? pre[ppad(m1 - 1)] : 0.0;
+            const long long u = __double_as_longlong(p1);
+            const int ulo = static_cast<int>(u & 0xffffffffLL), uhi = static_cast<int>(u >> 32);
+            const int plo = __builtin_amdgcn_update_dpp(clo, ulo, 0x138, 0xf, 0xf, false);
+            const int phi = __builtin_amdgcn_update_dpp(chi, uhi, 0x138, 0xf, 0xf, false);
+            const double p0 = __longlong_as_double((static_cast<long long>(phi) << 32) | static_cast<unsigned>(plo));
+            carry = __builtin_amdgcn_readlane(m1, 63);
+            clo = __builtin_amdgcn_readlane(ulo, 63);
+            chi = __builtin_amdgcn_readlane(uhi, 63);
+            if (b < nbins && m1 > m0) acc[j] += w * (p1 - p0);
         }
     }
 }
 
-// grid: (groups, n_inst); block 64 CW; wave w handles, in iteration it, the
-// S columns from cb + S (it CW + w).  LDS: pass twiddles, then
-// per wave `rs` bytes: the transform region, the FP64 prefix sums of one
-// column (within the transform region when S = 1), and (after the loop) the
-// wave's shell sums.
+// grid: (groups, n_inst); block 64 CW.  Block b takes `iters` consecutive
+// tiles of TC columns from tile b iters.  The block copies a tile (one
+// contiguous block of the column-tiled half spectrum) through registers into
+// the LDS regions of its NG column groups (the transpose), and wave w
+// transforms groups w CPW .. w CPW + CPW - 1 in turn.  LDS: pass twiddles,
+// then per group `rs` bytes: its columns' transform region, the FP64 prefix
+// sums of one column (within the transform region when S = 1), and (after
+// the loop, the first CW) the waves' shell sums.
+// Compiled for four waves per SIMD (128 VGPRs) where the FP32 transform fits
+// without spilling, else two.
 template <typename T, int LGY, int NBJ>
-__global__ void __launch_bounds__(256)
-    k_sk_cols(StepArg sarg, const cplx<T> *__restrict__ half, int nx, int iters, int rs, int nbins,
-              const cplx<T> *__restrict__ twy, double *__restrict__ part)
+__global__ void __launch_bounds__(256, (sizeof(T) == 4 && LGY <= 9) ? 4 : 2)
+    k_sk_colt(StepArg sarg, const cplx<T> *__restrict__ half, int nx, int nkb, int iters, int rs, int nbins,
+              const cplx<T> *__restrict__ twy, const uint16_t *__restrict__ shells, double *__restrict__ part)
 {
     SHE_SAMPLE_GATE();
     using F = WaveFft<LGY>;
     constexpr int n = F::n, P = F::P, S = F::S, hy = n / 2;
-    constexpr int CW = col_waves(static_cast<int>(sizeof(cplx<T>)), LGY);
+    constexpr int LR = PassRadix<LGY>::LR, R = 1 << LR;
+    constexpr int CW = colt_waves<T, LGY>(), NG = colt_groups<T, LGY>(), CPW = NG / CW, TC = NG * S;
     constexpr int per = (hy + 1 + 63) >> 6;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     cplx<T> *tw = reinterpret_cast<cplx<T> *>(smem_raw);
     unsigned char *regions = smem_raw + sizeof(cplx<T>) * F::tw;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    cplx<T> *buf = reinterpret_cast<cplx<T> *>(regions + static_cast<size_t>(wave) * rs);
-    double *pre = S == 1 ? reinterpret_cast<double *>(buf) : reinterpret_cast<double *>(buf + F::lds);
     const int inst = blockIdx.y;
     const int nh = nx / 2 + 1;
-    const int cb = blockIdx.x * (CW * S * iters);
-    const cplx<T> *hc = half + static_cast<int64_t>(inst) * nh * n;
+    const cplx<T> *hi = half + static_cast<int64_t>(inst) * nkb * n * TC;
     fill_pass_twiddles<T, LGY>(tw, twy);
+    // a tile (contiguous: n rows of TC columns) has n TC = 64 CW CPW P
+    // points, CPW P per thread; point j of thread t is entry e = t + 64 CW j:
+    // row e / TC, column e % TC, in the region of column group e % TC / S
+    constexpr int lTC = 31 - __builtin_clz(TC), PT = CPW * P;
+    const int tc = threadIdx.x & (TC - 1);
+    cplx<T> pf[PT];
+    auto fetch = [&](int cb) {
+        const bool in = cb + tc < nh;
+        const cplx<T> *tile = hi + static_cast<unsigned>(cb * n);  // tile cb / TC
+#pragma unroll
+        for (int j = 0; j < PT; ++j)
+            pf[j] = in ? tile[threadIdx.x + 64 * CW * j] : cplx<T>{T(0), T(0)};
+    };
+    auto stash = [&]() {
+#pragma unroll
+        for (int j = 0; j < PT; ++j) {
+            const int e = threadIdx.x + 64 * CW * j, y = e >> lTC, c = e & (TC - 1);
+            cplx<T> *dst = reinterpret_cast<cplx<T> *>(regions + static_cast<size_t>(c / S) * rs);
+            dst[pidx(((c & (S - 1)) << LGY) + y)] = pf[j];
+        }
+    };
     const int nbj = (nbins + 63) >> 6;
     double acc[NBJ];
 #pragma unroll
     for (int j = 0; j < NBJ; ++j) acc[j] = 0.0;
-    cplx<T> nxt[P];
-    load_cols<T, LGY>(nxt, hc, cb + S * wave, nh, lane);
-    __syncthreads();
+    const int t0 = blockIdx.x * iters;
     for (int it = 0; it < iters; ++it) {
-        const int g = cb + S * (it * CW + wave);
-        if (g >= nh) break;  // wave-uniform; later iterations are further right
-        cplx<T> v[P];
+        const int cb = (t0 + it) * TC;
+        if (cb >= nh) break;  // block-uniform
+        fetch(cb);
+        stash();
+        __syncthreads();
+        for (int cg = 0; cg < CPW; ++cg) {
+            const int r = wave * CPW + cg;  // the column group's region
+            cplx<T> *buf = reinterpret_cast<cplx<T> *>(regions + static_cast<size_t>(r) * rs);
+            double *pre = S == 1 ? reinterpret_cast<double *>(buf) : reinterpret_cast<double *>(buf + F::lds);
+            const int g = cb + S * r;
+            if (g < nh) {  // wave-uniform
+                cplx<T> v[P];
 #pragma unroll
-        for (int j = 0; j < P; ++j) v[j] = nxt[j];
-        if (it + 1 < iters) load_cols<T, LGY>(nxt, hc, g + S * CW, nh, lane);
-        wave_fft<T, LGY, LGY>(v, buf, tw, lane);
-        for (int c = 0; c < S && g + c < nh; ++c) {
-            const int kx = g + c;
-            // mirrored half of the spectrum: weight 2 off the kx = 0 and Nx/2
-            // columns, applied to the shell sums (an exact scaling)
-            const double w = (kx == 0 || 2 * kx == nx) ? 1.0 : 2.0;
-            const cplx<T> *col = buf;
-            const int cbase = c << LGY;
-            double loc[per];
-            double run = 0.0;
+                for (int i = 0; i < P / R; ++i) {
 #pragma unroll
-            for (int j = 0; j < per; ++j) {
-                // power at |ky| = m: X(m), plus X(-m) for 0 < m < hy; m > hy is
-                // padding (both reads stay inside the column, masked after)
-                const int m = lane * per + j;
-                const cplx<T> a = col[pidx(cbase + min(m, hy))];
-                const cplx<T> b = col[pidx(cbase + ((n - m) & (n - 1)))];
-                const T ea = m <= hy ? a.re * a.re + a.im * a.im : T(0);
-                const T eb = (m != 0 && m < hy) ? b.re * b.re + b.im * b.im : T(0);
-                run += static_cast<double>(ea) + static_cast<double>(eb);
-                loc[j] = run;
-            }
-            const double excl = wave_inclusive_sum(run) - run;
-            if (S == 1) wave_sync();  // the prefix sums overwrite the column just read
+                    for (int k = 0; k < R; ++k) {
+                        int seq, y;
+                        pass_input<LGY, LR>(lane, i, k, seq, y);
+                        v[i * R + k] = buf[pidx((seq << LGY) + y)];
+                    }
+                }
+                wave_sync();
+                if constexpr (S == 1) {
+                    // the transform stays in registers: lane l holds X(l + 64 j)
+                    wave_fft<T, LGY, LGY, true>(v, buf, tw, lane);
+                    col_power_prefix<T, LGY>(v, pre, lane);
+                    wave_sync();
+                    bin_column<NBJ>(acc, pre, shells + g * (nbins + 1), g, nx, nbins, nbj, hy, lane);
+                } else {
+                    wave_fft<T, LGY, LGY>(v, buf, tw, lane);
+                    for (int c = 0; c < S && g + c < nh; ++c) {
+                        const int kx = g + c;
+                        const cplx<T> *col = buf;
+                        const int cbase = c << LGY;
+                        double loc[per];
+                        double run = 0.0;
 #pragma unroll
-            for (int j = 0; j < per; ++j) {
-                const int m = lane * per + j;
-                if (m <= hy) pre[m] = excl + loc[j];
-            }
-            wave_sync();
-            // shells met by this column: kx .. round(sqrt(kx^2 + hy^2)) (bound by
-            // excess).  Lane b takes the end of its shell, first(b + 1); the start,
-            // first(b), is the end of lane b - 1 (a whole-wave shift by one lane),
-            // and for lane 0 the end of lane 63 in the previous group (0 for the
-            // first group met: its shells lie below kx).
-            const int kx4 = 4 * kx * kx;
-            const int jlo = kx >> 6;
-            const int jhi = static_cast<int>(__builtin_amdgcn_sqrtf(static_cast<float>(kx * kx + hy * hy)) + 1.5f) >> 6;
-            int carry = 0;
+                        for (int j = 0; j < per; ++j) {
+                            // power at |ky| = m: X(m), plus X(-m) for 0 < m < hy; m > hy
+                            // is padding (both reads stay inside the column, masked after)
+                            const int m = lane * per + j;
+                            const cplx<T> a = col[pidx(cbase + min(m, hy))];
+                            const cplx<T> b = col[pidx(cbase + ((n - m) & (n - 1)))];
+                            const T ea = m <= hy ? a.re * a.re + a.im * a.im : T(0);
+                            const T eb = (m != 0 && m < hy) ? b.re * b.re + b.im * b.im : T(0);
+                            run += static_cast<double>(ea) + static_cast<double>(eb);
+                            loc[j] = run;
+                        }
+                        const double excl = wave_inclusive_sum(run) - run;
 #pragma unroll
-            for (int j = 0; j < NBJ; ++j) {
-                if (j >= jlo && j <= jhi && j < nbj) {
-                    const int b = lane + 64 * j;
-                    const int m1 = shell_first(kx4, b + 1, hy);
-                    const int m0 = __builtin_amdgcn_update_dpp(carry, m1, 0x138, 0xf, 0xf, false);  // wave_shr:1
-                    carry = __builtin_amdgcn_readlane(m1, 63);
-                    if (b < nbins && m1 > m0) acc[j] += w * (pre[m1 - 1] - (m0 > 0 ? pre[m0 - 1] : 0.0));
+                        for (int j = 0; j < per; ++j) {
+                            const int m = lane * per + j;
+                            if (m <= hy) pre[ppad(m)] = excl + loc[j];
+                        }
+                        wave_sync();
+                        bin_column<NBJ>(acc, pre, shells + kx * (nbins + 1), kx, nx, nbins, nbj, hy, lane);
+                        wave_sync();
+                    }
                 }
             }
-            wave_sync();
         }
+        __syncthreads();  // the regions take the next tile
     }
-    __syncthreads();
     double *mine = reinterpret_cast<double *>(regions + static_cast<size_t>(wave) * rs);
 #pragma unroll
     for (int j = 0; j < NBJ; ++j) {
@@ -553,30 +472,59 @@ int ilog2(int v)
     return 31 - __builtin_clz(v);
 }
 
-int elem_bytes(int prec)
+// LDS bytes of a column-transform block (nbins shell sums fit each wave's
+// region after the transforms)
+template <typename T, int LGY>
+size_t colt_lds(int nbins, size_t *rs_out)
 {
-    return prec == 0 ? static_cast<int>(sizeof(cplx<float>)) : static_cast<int>(sizeof(cplx<double>));
+    size_t rs = col_region(static_cast<int>(sizeof(cplx<T>)), LGY);
+    rs = std::max(rs, sizeof(double) * static_cast<size_t>(nbins));
+    // regions 64 bytes apart modulo the 256 bytes of the 64 LDS banks: the
+    // tile copy's eight 64-byte row runs of four regions fill the banks once
+    rs = ((rs + 191) & ~static_cast<size_t>(255)) + 64;
+    if (rs_out) *rs_out = rs;
+    return ((sizeof(cplx<T>) * WaveFft<LGY>::tw + 15) & ~static_cast<size_t>(15)) + colt_groups<T, LGY>() * rs;
 }
 
-// column iterations per wave: about 2048 blocks in flight over the batch
-int col_iters(int prec, int nx, int ny, int n_inst)
+int tile_cols(int prec, int lgy)
 {
-    const int nh = nx / 2 + 1;
-    const int per_iter = col_waves(elem_bytes(prec), ilog2(ny)) * wave_seqs(ilog2(ny));
-    const int64_t groups = static_cast<int64_t>((nh + per_iter - 1) / per_iter) * n_inst;
+#define SHE_TC(L)                                                                            \
+    case L:                                                                                  \
+        return prec == 0 ? colt_groups<float, L>() * WaveFft<L>::S : colt_groups<double, L>() * WaveFft<L>::S;
+    switch (lgy) {
+        SHE_TC(1) SHE_TC(2) SHE_TC(3) SHE_TC(4) SHE_TC(5) SHE_TC(6) SHE_TC(7) SHE_TC(8) SHE_TC(9) SHE_TC(10)
+    default: return 1;
+    }
+#undef SHE_TC
+}
+
+// tiles per column-transform block: about 2048 blocks in flight over the batch
+int colt_iters(int prec, int nx, int ny, int n_inst)
+{
+    const int tc = tile_cols(prec, ilog2(ny));
+    const int64_t tiles = static_cast<int64_t>((nx / 2 + 1 + tc - 1) / tc) * n_inst;
     int it = 1;
-    while (it < 8 && groups / (2 * it) >= 2048) it *= 2;
+    while (it < 8 && tiles / (2 * it) >= 2048) it *= 2;
     return it;
 }
 
 }  // namespace
 
+int half_tile_log2(int prec, int ny) { return ilog2(tile_cols(prec, ilog2(ny))); }
+
 int sk2d_groups(int prec, int nx, int ny, int n_inst)
 {
-    const int nh = nx / 2 + 1;
-    const int per_block =
-        col_waves(elem_bytes(prec), ilog2(ny)) * wave_seqs(ilog2(ny)) * col_iters(prec, nx, ny, n_inst);
-    return (nh + per_block - 1) / per_block;
+    const int tc = tile_cols(prec, ilog2(ny));
+    const int tiles = (nx / 2 + 1 + tc - 1) / tc, it = colt_iters(prec, nx, ny, n_inst);
+    return (tiles + it - 1) / it;
+}
+
+hipError_t launch_shell_table(hipStream_t s, int nx, int ny, int nbins, uint16_t *shells)
+{
+    const int64_t tot = static_cast<int64_t>(nx / 2 + 1) * (nbins + 1);
+    hipLaunchKernelGGL(k_shell_table, dim3(static_cast<unsigned>((tot + 255) / 256)), dim3(256), 0, s, nx / 2 + 1,
+                       nbins, ny / 2, shells);
+    return hipGetLastError();
 }
 
 hipError_t launch_twiddles(int prec, hipStream_t s, int n, void *tw)
@@ -593,7 +541,7 @@ namespace {
 
 template <typename T, int LGX>
 void rows_t(hipStream_t s, const StepArg &sa, int n_inst, int ny, double u0, const void *field, const void *twx,
-            void *half)
+            void *half, int ltc, int nkb)
 {
     using F = WaveFft<LGX>;
     constexpr int W = row_waves<T, LGX>();
@@ -602,38 +550,35 @@ void rows_t(hipStream_t s, const StepArg &sa, int n_inst, int ny, double u0, con
     const size_t smem = sizeof(cplx<T>) * (F::tw + static_cast<size_t>(W) * F::lds);
     static_assert(sizeof(cplx<T>) * (F::tw + W * F::lds) <= kLdsBudget, "row transform exceeds the LDS budget");
     hipLaunchKernelGGL((k_sk_rows<T, LGX>), grid, dim3(64 * W), smem, s, sa, static_cast<const T *>(field), ny, u0,
-                       static_cast<const cplx<T> *>(twx), static_cast<cplx<T> *>(half));
+                       static_cast<const cplx<T> *>(twx), static_cast<cplx<T> *>(half), ltc, nkb);
 }
 
 template <typename T, int LGY>
-bool cols_t(hipStream_t s, const StepArg &sa, int n_inst, int nx, int nbins, const void *half, const void *twy,
-            double *part, int groups, int iters)
+bool cols_t(hipStream_t s, const StepArg &sa, int n_inst, int nx, int nkb, int nbins, const void *half, const void *twy,
+            const uint16_t *shells, double *part, int groups, int iters)
 {
-    using F = WaveFft<LGY>;
-    constexpr int CW = col_waves(static_cast<int>(sizeof(cplx<T>)), LGY);
-    size_t rs = col_region(static_cast<int>(sizeof(cplx<T>)), LGY);
-    rs = std::max(rs, sizeof(double) * static_cast<size_t>(nbins));
-    rs = (rs + 15) & ~static_cast<size_t>(15);
-    const size_t smem = sizeof(cplx<T>) * F::tw + CW * rs;
+    size_t rs = 0;
+    const size_t smem = colt_lds<T, LGY>(nbins, &rs);
     if (smem > kLdsBudget) return false;
+    const dim3 grid(groups, n_inst), block(64 * colt_waves<T, LGY>());
     if (nbins <= 64 * (kMaxBinIters / 2))
-        hipLaunchKernelGGL((k_sk_cols<T, LGY, kMaxBinIters / 2>), dim3(groups, n_inst), dim3(64 * CW), smem, s, sa,
-                           static_cast<const cplx<T> *>(half), nx, iters, static_cast<int>(rs), nbins,
-                           static_cast<const cplx<T> *>(twy), part);
+        hipLaunchKernelGGL((k_sk_colt<T, LGY, kMaxBinIters / 2>), grid, block, smem, s, sa,
+                           static_cast<const cplx<T> *>(half), nx, nkb, iters, static_cast<int>(rs), nbins,
+                           static_cast<const cplx<T> *>(twy), shells, part);
     else
-        hipLaunchKernelGGL((k_sk_cols<T, LGY, kMaxBinIters>), dim3(groups, n_inst), dim3(64 * CW), smem, s, sa,
-                           static_cast<const cplx<T> *>(half), nx, iters, static_cast<int>(rs), nbins,
-                           static_cast<const cplx<T> *>(twy), part);
+        hipLaunchKernelGGL((k_sk_colt<T, LGY, kMaxBinIters>), grid, block, smem, s, sa,
+                           static_cast<const cplx<T> *>(half), nx, nkb, iters, static_cast<int>(rs), nbins,
+                           static_cast<const cplx<T> *>(twy), shells, part);
     return true;
 }
 
 template <typename T>
 bool rows_dispatch(int lgx, hipStream_t s, const StepArg &sa, int n_inst, int ny, double u0, const void *field,
-                   const void *twx, void *half)
+                   const void *twx, void *half, int ltc, int nkb)
 {
-#define SHE_ROWS(L)                                                 \
-    case L:                                                         \
-        rows_t<T, L>(s, sa, n_inst, ny, u0, field, twx, half);      \
+#define SHE_ROWS(L)                                                        \
+    case L:                                                                \
+        rows_t<T, L>(s, sa, n_inst, ny, u0, field, twx, half, ltc, nkb);  \
         return true;
     switch (lgx) {
         SHE_ROWS(3) SHE_ROWS(4) SHE_ROWS(5) SHE_ROWS(6) SHE_ROWS(7) SHE_ROWS(8) SHE_ROWS(9) SHE_ROWS(10)
@@ -643,12 +588,12 @@ bool rows_dispatch(int lgx, hipStream_t s, const StepArg &sa, int n_inst, int ny
 }
 
 template <typename T>
-bool cols_dispatch(int lgy, hipStream_t s, const StepArg &sa, int n_inst, int nx, int nbins, const void *half,
-                   const void *twy, double *part, int groups, int iters)
+bool cols_dispatch(int lgy, hipStream_t s, const StepArg &sa, int n_inst, int nx, int nkb, int nbins, const void *half,
+                   const void *twy, const uint16_t *shells, double *part, int groups, int iters)
 {
-#define SHE_COLS(L)                                                                      \
-    case L:                                                                              \
-        return cols_t<T, L>(s, sa, n_inst, nx, nbins, half, twy, part, groups, iters);
+#define SHE_COLS(L)                                                                              \
+    case L:                                                                                      \
+        return cols_t<T, L>(s, sa, n_inst, nx, nkb, nbins, half, twy, shells, part, groups, iters);
     switch (lgy) {
         SHE_COLS(1) SHE_COLS(2) SHE_COLS(3) SHE_COLS(4) SHE_COLS(5) SHE_COLS(6) SHE_COLS(7) SHE_COLS(8)
         SHE_COLS(9) SHE_COLS(10)
@@ -660,20 +605,20 @@ bool cols_dispatch(int lgy, hipStream_t s, const StepArg &sa, int n_inst, int nx
 }  // namespace
 
 hipError_t launch_sk2d(int prec, hipStream_t s, const StepArg &sa, int n_inst, int nx, int ny, double u0,
-                       const void *field, void *half, const void *twx, const void *twy, double *part, int nbins,
-                       double *sums, const InstAcc *acc, const BatchSk &bk)
+                       const void *field, void *half, const void *twx, const void *twy, const uint16_t *shells,
+                       double *part, int nbins, double *sums, const InstAcc *acc, const BatchSk &bk, bool rows_done)
 {
     if (nbins > 64 * kMaxBinIters) return hipErrorInvalidValue;
     const int lgx = ilog2(nx), lgy = ilog2(ny);
-    const int iters = col_iters(prec, nx, ny, n_inst);
-    const int groups = sk2d_groups(prec, nx, ny, n_inst);
+    const int ltc = half_tile_log2(prec, ny), nkb = half_tiles(nx, ltc);
+    const int groups = sk2d_groups(prec, nx, ny, n_inst), iters = colt_iters(prec, nx, ny, n_inst);
     bool ok;
     if (prec == 0) {
-        ok = rows_dispatch<float>(lgx, s, sa, n_inst, ny, u0, field, twx, half) &&
-             cols_dispatch<float>(lgy, s, sa, n_inst, nx, nbins, half, twy, part, groups, iters);
+        ok = (rows_done || rows_dispatch<float>(lgx, s, sa, n_inst, ny, u0, field, twx, half, ltc, nkb)) &&
+             cols_dispatch<float>(lgy, s, sa, n_inst, nx, nkb, nbins, half, twy, shells, part, groups, iters);
     } else {
-        ok = rows_dispatch<double>(lgx, s, sa, n_inst, ny, u0, field, twx, half) &&
-             cols_dispatch<double>(lgy, s, sa, n_inst, nx, nbins, half, twy, part, groups, iters);
+        ok = (rows_done || rows_dispatch<double>(lgx, s, sa, n_inst, ny, u0, field, twx, half, ltc, nkb)) &&
+             cols_dispatch<double>(lgy, s, sa, n_inst, nx, nkb, nbins, half, twy, shells, part, groups, iters);
     }
     if (!ok) return hipErrorInvalidValue;
     const int64_t tot = static_cast<int64_t>(n_inst) * nbins;

@@ -8,28 +8,30 @@ namespace she {
 // Typed launchers, instantiated in she_k2d_*.hip / she_k3d_*.hip.
 template <typename T, int CX>
 hipError_t step2d_e(int eq, int scheme, int n_blocks, hipStream_t s, const ParamsND &p, const void *src,
-                    void *dst, const StepArg &sa, double *part, InstAcc *acc);
+                    void *dst, const StepArg &sa, double *part, InstAcc *acc, const SkRows *skr);
 template <typename T, int CX>
 hipError_t step3d_e(int eq, int stage, int ty, int n_blocks, size_t smem, hipStream_t s, const ParamsND &p,
                     const void *src, const void *base, void *dst, const StepArg &sa, double *part, InstAcc *acc);
 
 template <typename T>
 static hipError_t step2d_c(int cx, int eq, int scheme, int n_blocks, hipStream_t s, const ParamsND &p,
-                           const void *src, void *dst, const StepArg &sa, double *part, InstAcc *acc)
+                           const void *src, void *dst, const StepArg &sa, double *part, InstAcc *acc,
+                           const SkRows *skr)
 {
     switch (cx) {
-    case 4: return step2d_e<T, 4>(eq, scheme, n_blocks, s, p, src, dst, sa, part, acc);
-    case 8: return step2d_e<T, 8>(eq, scheme, n_blocks, s, p, src, dst, sa, part, acc);
-    case 16: return step2d_e<T, 16>(eq, scheme, n_blocks, s, p, src, dst, sa, part, acc);
+    case 4: return step2d_e<T, 4>(eq, scheme, n_blocks, s, p, src, dst, sa, part, acc, skr);
+    case 8: return step2d_e<T, 8>(eq, scheme, n_blocks, s, p, src, dst, sa, part, acc, skr);
+    case 16: return step2d_e<T, 16>(eq, scheme, n_blocks, s, p, src, dst, sa, part, acc, skr);
     default: return hipErrorInvalidValue;
     }
 }
 
 hipError_t launch_step2d(int prec, int cx, int eq, int scheme, int n_blocks, hipStream_t s, const ParamsND &p,
-                         const void *src, void *dst, const StepArg &sa, double *part, InstAcc *acc)
+                         const void *src, void *dst, const StepArg &sa, double *part, InstAcc *acc,
+                         const SkRows *skr)
 {
-    if (prec == 0) return step2d_c<float>(cx, eq, scheme, n_blocks, s, p, src, dst, sa, part, acc);
-    return step2d_c<double>(cx, eq, scheme, n_blocks, s, p, src, dst, sa, part, acc);
+    if (prec == 0) return step2d_c<float>(cx, eq, scheme, n_blocks, s, p, src, dst, sa, part, acc, skr);
+    return step2d_c<double>(cx, eq, scheme, n_blocks, s, p, src, dst, sa, part, acc, skr);
 }
 
 hipError_t launch_step3d(int prec, int cx, int eq, int stage, int ty, int n_blocks, size_t smem, hipStream_t s,

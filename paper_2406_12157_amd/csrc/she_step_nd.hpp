@@ -40,8 +40,19 @@
 // Sample steps: every lane adds dU = U - u0 and dU^2 of its output cells in
 // FP64; the group / workgroup sum is written to a per-chunk partial; a small
 // kernel reduces the partials per instance in a fixed order.
+//
+// Structure factor rows (SK, sample launches of the two-step FE march with
+// one row per wave, nx = 512 or 1024): the wave keeps each even output row
+// and, once the odd row after it is out, transforms the pair along x as one
+// complex row (dU_even + i dU_odd) with the wave FFT of she_fft.hpp (the
+// lane's CX consecutive cells are first transposed through the wave's LDS
+// region into the transform's input order) and stores both half spectra,
+// kx = 0..nx/2, as two rows of the column-tiled half spectrum.  This is the row
+// stage of the S(k) transform of the field the launch writes, done while the
+// rows are still in registers instead of reading the field back.
 #include <type_traits>
 
+#include "she_fft.hpp"
 #include "she_internal.hpp"
 #include "she_rng.hpp"
 
@@ -184,14 +195,24 @@ __device__ __forceinline__ void accumulate(const T (&out)[CX], double u0, double
 
 // ------------------------------------------------------------------ 2D
 
-template <typename T, int CX, int EQ, int SCHEME>
+template <typename T, int CX, int EQ, int SCHEME, bool SK = false>
 __global__ void __launch_bounds__(256)
     k_step2d(ParamsND p, const T *__restrict__ src, T *__restrict__ dst, StepArg sarg, double *__restrict__ part,
-             InstAcc *__restrict__ acc)
+             InstAcc *__restrict__ acc, SkRows skr)
 {
     int64_t step;
     int sample;
     resolve_step(sarg, step, sample);
+    // SK: pass twiddles of the row transform in LDS, then one transform
+    // region per wave (= per row group)
+    constexpr int LGX = CX == 16 ? 10 : 9;
+    using FX = WaveFft<LGX>;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    cplx<T> *twl = reinterpret_cast<cplx<T> *>(smem_raw);
+    if constexpr (SK) {
+        fill_pass_twiddles<T, LGX>(twl, static_cast<const cplx<T> *>(skr.tw));
+        __syncthreads();
+    }
     const int LX = p.nx / CX;
     const int lx = threadIdx.x % LX;
     const int grp = threadIdx.x / LX;
@@ -259,6 +280,42 @@ __global__ void __launch_bounds__(256)
         auto emit = [&](const T (&out)[CX], int y) __attribute__((always_inline)) {
             if (sample) accumulate<T, CX>(out, u0d, sa, sb);
             store_row<T, CX>(D + static_cast<int64_t>(y) * p.nx, out);
+            if constexpr (SK) {
+                // the pair's complex row: the even row's dU goes to the real
+                // parts of the wave's region at once (the transpose), the odd
+                // row's to the imaginary parts
+                const T su0 = static_cast<T>(u0d);
+                constexpr int n = FX::n, LR = PassRadix<LGX>::LR, R = 1 << LR;
+                cplx<T> *wreg = twl + FX::tw + grp * FX::lds;
+                if ((y & 1) == 0) {
+#pragma unroll
+                    for (int j = 0; j < CX; ++j) wreg[pidx(CX * lx + j)].re = out[j] - su0;
+                } else {
+#pragma unroll
+                    for (int j = 0; j < CX; ++j) wreg[pidx(CX * lx + j)].im = out[j] - su0;
+                    wave_sync();
+                    cplx<T> v[FX::P];
+#pragma unroll
+                    for (int i = 0; i < FX::P / R; ++i) {
+#pragma unroll
+                        for (int k = 0; k < R; ++k) {
+                            int seq, x;
+                            pass_input<LGX, LR>(lx, i, k, seq, x);
+                            v[i * R + k] = wreg[pidx(x)];
+                        }
+                    }
+                    wave_sync();
+                    wave_fft<T, LGX, LGX>(v, wreg, twl, lx);
+                    cplx<T> *h = static_cast<cplx<T> *>(skr.half);
+                    for (int k = lx; k <= n / 2; k += 64) {
+                        const cplx<T> z = wreg[pidx(k)], zm = wreg[pidx((n - k) & (n - 1))];
+                        const int64_t e = half_index(inst, y - 1, k, p.ny, skr.ltc, skr.nkb);
+                        h[e] = unpack_a(z, zm);
+                        h[e + (1 << skr.ltc)] = unpack_b(z, zm);  // row y, same tile
+                    }
+                    wave_sync();  // the next pair's transpose overwrites the region
+                }
+            }
         };
         const int rows = y1 - y0;
         if constexpr (SCHEME == 0) {
@@ -679,26 +736,37 @@ __global__ void __launch_bounds__(256)
 
 template <typename T, int CX, int EQ>
 static hipError_t step2d_s(int scheme, int n_blocks, hipStream_t s, const ParamsND &p, const void *src, void *dst,
-                           const StepArg &sa, double *part, InstAcc *acc)
+                           const StepArg &sa, double *part, InstAcc *acc, const SkRows *skr)
 {
+    const SkRows none{nullptr, nullptr, 0, 0};
+    const T *in = static_cast<const T *>(src);
+    T *out = static_cast<T *>(dst);
     if (scheme == 0)
-        hipLaunchKernelGGL((k_step2d<T, CX, EQ, 0>), dim3(n_blocks), dim3(256), 0, s, p,
-                           static_cast<const T *>(src), static_cast<T *>(dst), sa, part, acc);
+        hipLaunchKernelGGL((k_step2d<T, CX, EQ, 0>), dim3(n_blocks), dim3(256), 0, s, p, in, out, sa, part, acc, none);
     else if (scheme == 1)
-        hipLaunchKernelGGL((k_step2d<T, CX, EQ, 1>), dim3(n_blocks), dim3(256), 0, s, p,
-                           static_cast<const T *>(src), static_cast<T *>(dst), sa, part, acc);
-    else
-        hipLaunchKernelGGL((k_step2d<T, CX, EQ, 2>), dim3(n_blocks), dim3(256), 0, s, p,
-                           static_cast<const T *>(src), static_cast<T *>(dst), sa, part, acc);
+        hipLaunchKernelGGL((k_step2d<T, CX, EQ, 1>), dim3(n_blocks), dim3(256), 0, s, p, in, out, sa, part, acc, none);
+    else if (!skr)
+        hipLaunchKernelGGL((k_step2d<T, CX, EQ, 2>), dim3(n_blocks), dim3(256), 0, s, p, in, out, sa, part, acc, none);
+    else {
+        if constexpr (CX == 8 || CX == 16) {
+            using FX = WaveFft<CX == 16 ? 10 : 9>;
+            const size_t smem = sizeof(cplx<T>) * (FX::tw + 4 * static_cast<size_t>(FX::lds));
+            if (p.nx != 64 * CX || smem > 64 * 1024) return hipErrorInvalidValue;
+            hipLaunchKernelGGL((k_step2d<T, CX, EQ, 2, true>), dim3(n_blocks), dim3(256), smem, s, p, in, out, sa,
+                               part, acc, *skr);
+        } else {
+            return hipErrorInvalidValue;
+        }
+    }
     return hipGetLastError();
 }
 
 template <typename T, int CX>
 hipError_t step2d_e(int eq, int scheme, int n_blocks, hipStream_t s, const ParamsND &p, const void *src,
-                           void *dst, const StepArg &sa, double *part, InstAcc *acc)
+                           void *dst, const StepArg &sa, double *part, InstAcc *acc, const SkRows *skr)
 {
-    if (eq == 0) return step2d_s<T, CX, 0>(scheme, n_blocks, s, p, src, dst, sa, part, acc);
-    return step2d_s<T, CX, 1>(scheme, n_blocks, s, p, src, dst, sa, part, acc);
+    if (eq == 0) return step2d_s<T, CX, 0>(scheme, n_blocks, s, p, src, dst, sa, part, acc, skr);
+    return step2d_s<T, CX, 1>(scheme, n_blocks, s, p, src, dst, sa, part, acc, skr);
 }
 
 template <typename T, int CX, int EQ>

@@ -22,12 +22,13 @@ def test_valu_record_gives_the_alu_roofline(tmp_path, monkeypatch):
     _write(tmp_path, "v.json", rec)
     monkeypatch.setattr(bench, "PROFILES", str(tmp_path))
     r = bench.roofline(0.05, 1000, 2, 10, "k", VARIANT, "v.json", None)
-    # two steps per launch: 0.1 ms; one sample launch in five: 62000 wave64
-    # instructions per SIMD, 64 lanes each, over 0.1 ms against 256 x 4 x 16
-    # lanes x 2.4 GHz
-    lane = 1024 * 62000.0 * 64
+    # two steps per launch: 0.1 ms, timed on launches outside sample steps:
+    # 60000 wave64 instructions per SIMD, 64 lanes each, over 0.1 ms against
+    # 256 x 4 x 16 lanes x 2.4 GHz; the sample launch's count beside it
+    lane = 1024 * 60000.0 * 64
     assert r["bound"] == "alu" and r["unit"] == "Tlane-instr/s"
     assert abs(r["achieved"] - lane / 1e-4 / 1e12) < 1e-9
+    assert r["sample_lane_instr_per_launch"] == 1024 * 70000.0 * 64
     assert abs(r["peak"] - 39.3216) < 1e-9
     assert abs(r["frac"] - r["achieved"] / r["peak"]) < 1e-12
     assert r["lane_instr_per_cell_update"] == lane / 2000

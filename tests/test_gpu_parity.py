@@ -989,3 +989,41 @@ def test_batch_means_checkpoint_and_reset(she):
         assert a.stats(0, se=True)["n_batches"] == 2
         a.close()
         b.close()
+
+
+@pytest.mark.parametrize("shape,precision,rpb", [((512, 16), 0, 0), ((512, 16), 1, 5), ((1024, 8), 0, 3),
+                                                 ((512, 64), 0, 32)])
+def test_sample_launch_row_transforms(she, shape, precision, rpb):
+    """On two-step FE launches that end on a sample, rows 512 or 1024 cells
+    wide are transformed along x by the step kernel itself, pair by pair, as
+    it writes them.  The structure factor equals, bit for bit, that of one
+    step per launch (which reads the field back with the row-transform
+    kernel), and the oracle's within 1e-3 (FP32) / 1e-9 (FP64); the fields are
+    identical.  Odd march lengths are rounded up to even, which regroups the
+    rows of the FP64 partial sums of the spatial moments: those agree to
+    rounding (1e-13)."""
+    insts = [inst2d(shape, W.EM, W.HEAT, realisation=q) for q in range(3)]
+    kw = dict(precision=precision, burn_in=5, sample_every=2, stats=she.STAT_SPATIAL | she.STAT_SK,
+              rows_per_block=rpb, batch_samples=4)
+    a = she.Handle([gpu_instance(she, i) for i in insts], tuning_flags=she.TUNE_SINGLE_STEP, **kw)
+    b = she.Handle([gpu_instance(she, i) for i in insts], **kw)
+    init = [b.read_field(q) for q in range(3)]
+    for k in (7, 30, 13):
+        a.run(k)
+        b.run(k)
+    tol = 1e-3 if precision == 0 else 1e-9
+    for q in range(3):
+        np.testing.assert_array_equal(a.read_field(q), b.read_field(q))
+        ga, gb = a.stats(q, sk=True, se=True), b.stats(q, sk=True, se=True)
+        assert ga["n_samples"] == gb["n_samples"] == 23
+        for key in ("sk", "sk_se"):
+            np.testing.assert_array_equal(ga[key], gb[key])
+        np.testing.assert_allclose(ga["var"], gb["var"], rtol=1e-13)
+        d = oracle_desc(insts[q], precision)
+        st = oracle.Stats(d, burn_in=5, every=2, per_cell=False, sk=True)
+        u = init[q].copy()
+        oracle.advance(d, u, 0, 50, st)
+        ok = gb["sk_modes"] > 0
+        assert max_rel(gb["sk"][ok], st.structure_factor()[ok]) < tol
+    a.close()
+    b.close()
