@@ -39,21 +39,20 @@ __device__ __forceinline__ cplx<T> cmul(cplx<T> a, cplx<T> w)
     return cplx<T>{fma(a.re, w.re, -(a.im * w.im)), fma(a.re, w.im, a.im * w.re)};
 }
 
-// Half spectra of two real sequences a, b transformed together as z = a + i b:
-// from Z_k and Z_(-k), A_k = (Z_k + conj Z_(-k)) / 2 and
-// B_k = (Z_k - conj Z_(-k)) / (2i).
+// Half spectra of two real sequences a, b transformed together as z = a + i b,
+// doubled: from Z_k and Z_(-k), 2 A_k = Z_k + conj Z_(-k) and
+// 2 B_k = (Z_k - conj Z_(-k)) / i.  The factor 2 is exact, and the power sums
+// take the 1/4 back once per column.
 template <typename T>
-__device__ __forceinline__ cplx<T> unpack_a(cplx<T> z, cplx<T> zm)
+__device__ __forceinline__ cplx<T> unpack2_a(cplx<T> z, cplx<T> zm)
 {
-#pragma clang fp contract(off)
-    return cplx<T>{T(0.5) * (z.re + zm.re), T(0.5) * (z.im - zm.im)};
+    return cplx<T>{z.re + zm.re, z.im - zm.im};
 }
 
 template <typename T>
-__device__ __forceinline__ cplx<T> unpack_b(cplx<T> z, cplx<T> zm)
+__device__ __forceinline__ cplx<T> unpack2_b(cplx<T> z, cplx<T> zm)
 {
-#pragma clang fp contract(off)
-    return cplx<T>{T(0.5) * (z.im + zm.im), T(-0.5) * (z.re - zm.re)};
+    return cplx<T>{z.im + zm.im, zm.re - z.re};
 }
 
 // Shape of the per-wave transform of length n = 2^lg: P points per lane,

@@ -7,24 +7,25 @@
 // restores that mode exactly from the spatial sums), in the state's precision.
 //
 // 1. Row transforms: two real rows are packed as one complex sequence
-//    (dU_a + i dU_b) and transformed along x by one wave; the two half spectra
-//    A_k = (Z_k + conj Z_-k)/2, B_k = (Z_k - conj Z_-k)/(2i), kx = 0..Nx/2,
-//    are stored column-tiled: tiles of the columns one column-transform block
-//    takes, each tile Ny rows of its columns, row-major and contiguous.  On the sample launches of
-//    the two-step 2D FE march the step kernel does this itself for the rows
-//    it has just written (she_step_nd.hpp); otherwise k_sk_rows reads the
-//    field back.
+//    (dU_a + i dU_b) and transformed along x by one wave; the two half spectra,
+//    doubled (2 A_k = Z_k + conj Z_-k, 2 B_k = (Z_k - conj Z_-k)/i,
+//    kx = 0..Nx/2; the shell sums take the exact 1/4 back), are stored
+//    column-tiled: tiles of the columns one column-transform block takes, each
+//    tile Ny rows of its columns, row-major and contiguous.  On the sample
+//    launches of the two-step 2D FE march the step kernel does this itself for
+//    the rows it has just written (she_step_nd.hpp); otherwise k_sk_rows reads
+//    the field back.
 // 2. k_sk_colt: a block streams a tile of columns of the half spectrum into
 //    its waves' LDS regions (the transpose), and each wave transforms its
-//    columns along y.  The power |X|^2 gets weight
-//    2 for 0 < kx < Nx/2 (the mirrored half of the spectrum) and is binned
-//    without atomics: per column the wave forms the FP64 prefix sum P(m) of
-//    the power over |ky| <= m (fixed-order scan), and lane b adds
+//    columns along y.  The power |X|^2 gets weight 2 for 0 < kx < Nx/2 (the
+//    mirrored half of the spectrum), times the 1/4 of the doubled rows, and
+//    is binned without atomics: per column the wave forms the FP64 prefix sum
+//    P(m) of the power over |ky| <= m (fixed-order scan), and lane b adds
 //    P(hi-1) - P(lo-1) over the range [lo(kx, b), lo(kx, b+1)) of |ky|, with
 //    lo(kx, b) the first |ky| in shell b: (2b-1)^2 <= 4(kx^2 + ky^2), exact in
-//    integers.  Only shells kx .. round(sqrt(kx^2 + (Ny/2)^2)) meet column kx.
-//    The waves' shell sums are added in a fixed order into one partial per
-//    block.
+//    integers (a table built once per handle).  Only shells
+//    kx .. round(sqrt(kx^2 + (Ny/2)^2)) meet column kx.  The waves' shell sums
+//    are added in a fixed order into one partial per block.
 // 3. k_bins_reduce: per instance and shell, the partials are added in a fixed
 //    order to the FP64 running sums.
 //
@@ -126,8 +127,8 @@ __global__ void __launch_bounds__(512)
         const int sb = (pair & (S - 1)) << LGX;
         const cplx<T> z = z0[pidx(sb + k)];
         const cplx<T> zm = z0[pidx(sb + ((n - k) & (n - 1)))];
-        // A = (z + conj zm)/2 (row 2q), B = (z - conj zm)/(2i) (row 2q+1)
-        half[half_index(inst, 2 * pair0 + rr, k, ny, ltc, nkb)] = (rr & 1) ? unpack_b(z, zm) : unpack_a(z, zm);
+        // 2A = z + conj zm (row 2q), 2B = (z - conj zm)/i (row 2q+1)
+        half[half_index(inst, 2 * pair0 + rr, k, ny, ltc, nkb)] = (rr & 1) ? unpack2_b(z, zm) : unpack2_a(z, zm);
     }
 }
 
@@ -262,8 +263,9 @@ __device__ __forceinline__ void col_power_prefix(const cplx<T> (&v)[WaveFft<LG>:
 // Adds column kx's power to the shell sums: lane b of group j takes shell
 // b = lane + 64 j, the range [first(b), first(b + 1)) of |ky| (from the shell
 // table, col = its row for kx), as pre[first(b + 1) - 1] - pre[first(b) - 1],
-// with weight 2 off the kx = 0 and Nx/2 columns (the mirrored half of the
-// spectrum; an exact scaling).  first(b) and its prefix value are lane
+// weighted 1/4 (the row stage stores doubled half spectra, so the powers are
+// 4 |X|^2), and twice that off the kx = 0 and Nx/2 columns (the mirrored half
+// of the spectrum); both scalings are exact.  first(b) and its prefix value are lane
 // b - 1's, moved one lane up; lane 0 takes those of lane 63 of the previous
 // group, and 0 for the first group met (its shells lie below kx, first = 0).
 // Only shells kx .. round(sqrt(kx^2 + hy^2)) (bound by excess) meet the column.
@@ -271,7 +273,7 @@ template <int NBJ>
 __device__ __forceinline__ void bin_column(double (&acc)[NBJ], const double *pre, const uint16_t *__restrict__ col,
                                            int kx, int nx, int nbins, int nbj, int hy, int lane)
 {
-    const double w = (kx == 0 || 2 * kx == nx) ? 1.0 : 2.0;
+    const double w = (kx == 0 || 2 * kx == nx) ? 0.25 : 0.5;
     const int jlo = kx >> 6;
     const int jhi = static_cast<int>(__builtin_amdgcn_sqrtf(static_cast<float>(kx * kx + hy * hy)) + 1.5f) >> 6;
     int m1s[NBJ];

@@ -306,12 +306,17 @@ __global__ void __launch_bounds__(256)
                     }
                     wave_sync();
                     wave_fft<T, LGX, LGX>(v, wreg, twl, lx);
-                    cplx<T> *h = static_cast<cplx<T> *>(skr.half);
+                    // 32-bit offsets from the instance's base: entry (y - 1, k)
+                    // of the column-tiled layout, and row y at +TC in the same tile
+                    cplx<T> *hb = static_cast<cplx<T> *>(skr.half) + half_index(inst, 0, 0, p.ny, skr.ltc, skr.nkb);
+                    const uint32_t ltc = static_cast<uint32_t>(skr.ltc), tcm = (1u << ltc) - 1u;
+                    const uint32_t yoff = static_cast<uint32_t>(y - 1) << ltc;
                     for (int k = lx; k <= n / 2; k += 64) {
                         const cplx<T> z = wreg[pidx(k)], zm = wreg[pidx((n - k) & (n - 1))];
-                        const int64_t e = half_index(inst, y - 1, k, p.ny, skr.ltc, skr.nkb);
-                        h[e] = unpack_a(z, zm);
-                        h[e + (1 << skr.ltc)] = unpack_b(z, zm);  // row y, same tile
+                        const uint32_t uk = static_cast<uint32_t>(k);
+                        const uint32_t e = (((uk >> ltc) * static_cast<uint32_t>(p.ny)) << ltc) + yoff + (uk & tcm);
+                        hb[e] = unpack2_a(z, zm);
+                        hb[e + tcm + 1u] = unpack2_b(z, zm);
                     }
                     wave_sync();  // the next pair's transpose overwrites the region
                 }
