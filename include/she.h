@@ -273,10 +273,21 @@ she_status she_arena_bytes(const she_config *cfg, size_t *bytes);
  * at once.  Synchronises cfg->stream.  SHE_EUNSUPPORTED if no shape runs. */
 she_status she_tune(const she_config *cfg, int32_t steps, she_config *tuned);
 
-/* Advance every instance by nsteps steps without sampling.  Async. */
+/* Advance every instance by nsteps time steps of its scheme (Sec. 3: the FE
+ * update and the PC predictor / corrector on the face fluxes, with one fresh
+ * standard normal per face per step from the counters (seed, face block,
+ * step, realisation); Sec. 4 for DK) without taking samples.  h: a handle
+ * from she_create; nsteps >= 0 (0: no work).  Enqueued on the handle's
+ * stream and returns without waiting.  SHE_EINVAL for a NULL handle or
+ * nsteps < 0; SHE_EDEVICE if a launch fails (she_last_error names the call).
+ * An instance whose state turns non-finite is frozen and reported by
+ * she_stats (SHE_ENONFINITE). */
 she_status she_step(she_handle *h, int64_t nsteps);
 
-/* Advance by nsteps steps, sampling by the burn-in / sample_every rule.  Async. */
+/* As she_step, sampling the statistics of stats_mask after each completed
+ * step t with t > burn_in and t a multiple of sample_every (Sec. 3: time
+ * averages after a relaxation period, samples taken every few steps so they
+ * are less correlated).  Same arguments, asynchrony and errors as she_step. */
 she_status she_run(she_handle *h, int64_t nsteps);
 
 /* Finalised statistics of one instance in FP64 (mean = ref + S1/M,
@@ -285,7 +296,9 @@ she_status she_run(she_handle *h, int64_t nsteps);
  * SHE_ENONFINITE (after filling out) if a sample met a non-finite value. */
 she_status she_stats(she_handle *h, int32_t instance, she_stats_out *out);
 
-/* Zero every statistics accumulator (the step count is kept). */
+/* Zero every statistics accumulator, batch means included (the step count
+ * is kept): a new relaxation period starts (Sec. 3).  Ordered on the stream;
+ * SHE_EINVAL for a NULL handle. */
 she_status she_reset_stats(she_handle *h);
 
 /* Copy the current field of one instance to / from host FP64 (n = cells,
@@ -297,8 +310,16 @@ she_status she_write_field(she_handle *h, int32_t instance, const double *host, 
 she_status she_get_step(const she_handle *h, int64_t *steps);
 
 /* Checkpoint: state + step count + every statistics accumulator, as one
- * host blob.  Resuming from it reproduces the uninterrupted run bit for bit
- * (the noise is a function of the step count, not of a generator state). */
+ * host blob.  Resuming from it reproduces the uninterrupted run bit for bit:
+ * the noise of Sec. 3 (one normal per face per step) is a function of the
+ * seed, face, step and realisation, not of a generator state.
+ * she_state_bytes: the blob size for this handle (SHE_EINVAL for NULL).
+ * she_get_state: copies the blob into caller-owned host memory of at least
+ * that size; synchronises the stream (SHE_EINVAL for NULL or a short buffer).
+ * she_set_state: loads a blob taken from a handle of the same layout (same
+ * dimension, precision, instance count and sizes, statistics and batch
+ * length); SHE_ESTATE if it is short or of another layout, and then the
+ * handle is unchanged.  Synchronises the stream. */
 she_status she_state_bytes(const she_handle *h, size_t *bytes);
 she_status she_get_state(she_handle *h, void *host, size_t bytes);
 she_status she_set_state(she_handle *h, const void *host, size_t bytes);
