@@ -164,8 +164,9 @@ typedef struct {
     const she_instance_desc *inst;/* n_instances entries, copied at create.
                                      1D instances may differ in every field;
                                      2D/3D instances must share the grid,
-                                     eq, scheme, noise, r, u0 and seed (eps,
-                                     init_sd and realisation may differ)     */
+                                     eq, scheme, noise and seed (r, u0, eps,
+                                     init_sd and realisation may differ;
+                                     otherwise SHE_EUNSUPPORTED)             */
     int64_t burn_in;              /* sample after completed step t when
                                      t > burn_in and t % sample_every == 0    */
     int32_t sample_every;         /* >= 1                                      */

@@ -700,10 +700,10 @@ static she_status plan_nd(she_handle *h, const she_config *cfg, Plan &plan)
     for (int i = 1; i < h->n_inst; ++i) {
         const she_instance_desc &d = h->inst[i];
         if (d.n[0] != d0.n[0] || d.n[1] != d0.n[1] || d.n[2] != d0.n[2] || d.eq != d0.eq || d.scheme != d0.scheme ||
-            d.noise != d0.noise || d.r != d0.r || d.u0 != d0.u0 || d.seed != d0.seed)
+            d.noise != d0.noise || d.seed != d0.seed)
             return fail(nullptr, SHE_EUNSUPPORTED,
-                        "2D/3D batches must share the grid, equation, scheme, noise mode, r, u0 and seed "
-                        "(eps, init_sd and the realisation may differ)");
+                        "2D/3D batches must share the grid, equation, scheme, noise mode and seed "
+                        "(r, u0, eps, init_sd and the realisation may differ)");
     }
     const int nx = d0.n[0];
     if (!is_pow2(nx) || nx < 8 || nx > 1024)
@@ -730,8 +730,6 @@ static she_status plan_nd(she_handle *h, const she_config *cfg, Plan &plan)
     p.noise = d0.noise;
     p.n_inst = h->n_inst;
     p.xcd_order = (cfg->tuning_flags & SHE_TUNE_XCD_ORDER) ? 1 : 0;
-    p.r = d0.r;
-    p.u0 = d0.u0;
     p.seed = d0.seed;
     h->ip_host.resize(h->n_inst);
     for (int i = 0; i < h->n_inst; ++i) {
@@ -745,6 +743,8 @@ static she_status plan_nd(she_handle *h, const she_config *cfg, Plan &plan)
         else
             q.ns = 0.0;
         q.init_sd = d.init_sd;
+        q.r = d.r;
+        q.u0 = d.u0;
         q.realisation = d.realisation;
         q.pad = 0;
     }
@@ -1170,9 +1170,9 @@ static hipError_t nd_enqueue(she_handle *h, hipStream_t s, const StepArg &sa, in
     e = launch_reduce_parts(h->n_inst, s, sa, h->d_part, two ? h->nparts2 : h->nparts,
                             1.0 / static_cast<double>(h->cells), h->batch_len, h->d_acc);
     if (e != hipSuccess || !(h->mask & SHE_STAT_SK)) return e;
-    const BatchSk bk{h->d_sksnap, h->d_skwm, h->d_skwm2, h->d_skmodes, static_cast<double>(h->cells), h->pnd.u0,
+    const BatchSk bk{h->d_sksnap, h->d_skwm, h->d_skwm2, h->d_skmodes, h->d_ip, static_cast<double>(h->cells),
                      h->d_sksnap ? h->batch_len : 0, 0};
-    return launch_sk2d(h->prec, s, sa, h->n_inst, h->pnd.nx, h->pnd.ny, h->pnd.u0, dst, h->d_half, h->d_twx, h->d_twy,
+    return launch_sk2d(h->prec, s, sa, h->n_inst, h->pnd.nx, h->pnd.ny, h->d_ip, dst, h->d_half, h->d_twx, h->d_twy,
                        h->d_shells, h->d_skpart, h->nbins, h->d_sksum, h->d_acc, bk, fused);
 }
 

@@ -94,6 +94,8 @@ struct Batch1D {
     int32_t pad;
 };
 
+struct InstND;
+
 // Batch-means arrays of the 2D structure factor (device; null when not
 // kept): the shell sums at the end of the last folded batch and the Welford
 // (mean, M2) of the batch shell averages, n_inst x nbins each.
@@ -102,8 +104,8 @@ struct BatchSk {
     double *wmean;
     double *wm2;
     const double *modes;
+    const InstND *ip;       // per-instance u0 (the k = 0 mode)
     double cells;
-    double u0;
     int32_t len;
     int32_t pad;
 };
@@ -175,12 +177,14 @@ struct InstND {
                             // sigma/sqrt(2) (DK), sigma A(u0) (deterministic face
                             // value), 0 without noise; sigma = sqrt(2 r eps)
     double init_sd;         // std. dev. of the initial perturbation
+    double r;               // mesh ratio of the instance
+    double u0;              // its reference value (start, statistics shift)
     uint32_t realisation;   // Philox counter word 3
     uint32_t pad;
 };
 
-// Parameters of a 2D/3D batch: one grid, scheme, r and u0; eps, init_sd
-// and the realisation per instance.
+// Parameters of a 2D/3D batch: one grid, equation, scheme, noise mode and
+// seed; r, u0, eps, init_sd and the realisation per instance (InstND).
 struct ParamsND {
     int32_t nx, ny, nz;     // nz = 1 in 2D
     int32_t dim;
@@ -188,7 +192,6 @@ struct ParamsND {
     int32_t n_inst;
     int32_t chunk;          // rows (2D, along y) or planes (3D, along z) per march
     int32_t xcd_order;      // 1: give each XCD a contiguous range of workgroups
-    double r, u0;
     uint64_t seed;
     const InstND *ip;       // device, n_inst
 };
@@ -325,7 +328,7 @@ inline int half_tiles(int nx, int ltc) { return (nx / 2 + 1 + (1 << ltc) - 1) >>
 // shell binning into per-block partials, fixed-order reduction into sums
 // (n_inst x nbins FP64).  half: n_inst * ny * (half_tiles << ltc) complex of
 // the state type.
-hipError_t launch_sk2d(int prec, hipStream_t s, const StepArg &st, int n_inst, int nx, int ny, double u0,
+hipError_t launch_sk2d(int prec, hipStream_t s, const StepArg &st, int n_inst, int nx, int ny, const InstND *ip,
                        const void *field, void *half, const void *twx, const void *twy, const uint16_t *shells,
                        double *part, int nbins, double *sums, const InstAcc *acc, const BatchSk &bk, bool rows_done);
 // shells[kx (nbins + 1) + b], kx = 0..nx/2, b = 0..nbins: the first |ky| of

@@ -78,7 +78,8 @@ constexpr int row_waves()
 // grid: (ceil(ny/2 / (W S)), n_inst); block 64 W; LDS: pass twiddles + W regions.
 template <typename T, int LGX>
 __global__ void __launch_bounds__(512)
-    k_sk_rows(StepArg sarg, const T *__restrict__ field, int ny, double u0, const cplx<T> *__restrict__ twx,
+    k_sk_rows(StepArg sarg, const T *__restrict__ field, int ny, const InstND *__restrict__ ip,
+              const cplx<T> *__restrict__ twx,
               cplx<T> *__restrict__ half, int ltc, int nkb)
 {
     SHE_SAMPLE_GATE();
@@ -93,7 +94,7 @@ __global__ void __launch_bounds__(512)
     const int pair0 = blockIdx.x * (W * S);
     const int npairs = min(W * S, ny / 2 - pair0);
     const T *f = field + static_cast<int64_t>(inst) * n * ny;
-    const T su0 = static_cast<T>(u0);
+    const T su0 = static_cast<T>(ip[inst].u0);
     cplx<T> v[P];
 #pragma unroll
     for (int i = 0; i < P / R; ++i) {
@@ -458,7 +459,8 @@ __global__ void __launch_bounds__(256)
     if (bk.len > 0 && q.n_samples % bk.len == 0) {
         const double L = static_cast<double>(bk.len), N = bk.cells;
         double v = tot - bk.snap[e];
-        if (b == 0) v += L * N * N * bk.u0 * bk.u0 + 2.0 * N * bk.u0 * (N * q.batch_sp_mean);
+        const double u0 = bk.ip[inst].u0;
+        if (b == 0) v += L * N * N * u0 * u0 + 2.0 * N * u0 * (N * q.batch_sp_mean);
         const double x = bk.modes[b] > 0 ? v / (L * bk.modes[b]) : 0.0;
         welford(x, static_cast<double>(q.n_batches), bk.wmean[e], bk.wm2[e]);
         bk.snap[e] = tot;
@@ -542,7 +544,7 @@ hipError_t launch_twiddles(int prec, hipStream_t s, int n, void *tw)
 namespace {
 
 template <typename T, int LGX>
-void rows_t(hipStream_t s, const StepArg &sa, int n_inst, int ny, double u0, const void *field, const void *twx,
+void rows_t(hipStream_t s, const StepArg &sa, int n_inst, int ny, const InstND *ip, const void *field, const void *twx,
             void *half, int ltc, int nkb)
 {
     using F = WaveFft<LGX>;
@@ -551,7 +553,7 @@ void rows_t(hipStream_t s, const StepArg &sa, int n_inst, int ny, double u0, con
     const dim3 grid((ny / 2 + pairs - 1) / pairs, n_inst);
     const size_t smem = sizeof(cplx<T>) * (F::tw + static_cast<size_t>(W) * F::lds);
     static_assert(sizeof(cplx<T>) * (F::tw + W * F::lds) <= kLdsBudget, "row transform exceeds the LDS budget");
-    hipLaunchKernelGGL((k_sk_rows<T, LGX>), grid, dim3(64 * W), smem, s, sa, static_cast<const T *>(field), ny, u0,
+    hipLaunchKernelGGL((k_sk_rows<T, LGX>), grid, dim3(64 * W), smem, s, sa, static_cast<const T *>(field), ny, ip,
                        static_cast<const cplx<T> *>(twx), static_cast<cplx<T> *>(half), ltc, nkb);
 }
 
@@ -575,12 +577,12 @@ bool cols_t(hipStream_t s, const StepArg &sa, int n_inst, int nx, int nkb, int n
 }
 
 template <typename T>
-bool rows_dispatch(int lgx, hipStream_t s, const StepArg &sa, int n_inst, int ny, double u0, const void *field,
+bool rows_dispatch(int lgx, hipStream_t s, const StepArg &sa, int n_inst, int ny, const InstND *ip, const void *field,
                    const void *twx, void *half, int ltc, int nkb)
 {
 #define SHE_ROWS(L)                                                        \
     case L:                                                                \
-        rows_t<T, L>(s, sa, n_inst, ny, u0, field, twx, half, ltc, nkb);  \
+        rows_t<T, L>(s, sa, n_inst, ny, ip, field, twx, half, ltc, nkb);  \
         return true;
     switch (lgx) {
         SHE_ROWS(3) SHE_ROWS(4) SHE_ROWS(5) SHE_ROWS(6) SHE_ROWS(7) SHE_ROWS(8) SHE_ROWS(9) SHE_ROWS(10)
@@ -606,7 +608,7 @@ bool cols_dispatch(int lgy, hipStream_t s, const StepArg &sa, int n_inst, int nx
 
 }  // namespace
 
-hipError_t launch_sk2d(int prec, hipStream_t s, const StepArg &sa, int n_inst, int nx, int ny, double u0,
+hipError_t launch_sk2d(int prec, hipStream_t s, const StepArg &sa, int n_inst, int nx, int ny, const InstND *ip,
                        const void *field, void *half, const void *twx, const void *twy, const uint16_t *shells,
                        double *part, int nbins, double *sums, const InstAcc *acc, const BatchSk &bk, bool rows_done)
 {
@@ -616,10 +618,10 @@ hipError_t launch_sk2d(int prec, hipStream_t s, const StepArg &sa, int n_inst, i
     const int groups = sk2d_groups(prec, nx, ny, n_inst), iters = colt_iters(prec, nx, ny, n_inst);
     bool ok;
     if (prec == 0) {
-        ok = (rows_done || rows_dispatch<float>(lgx, s, sa, n_inst, ny, u0, field, twx, half, ltc, nkb)) &&
+        ok = (rows_done || rows_dispatch<float>(lgx, s, sa, n_inst, ny, ip, field, twx, half, ltc, nkb)) &&
              cols_dispatch<float>(lgy, s, sa, n_inst, nx, nkb, nbins, half, twy, shells, part, groups, iters);
     } else {
-        ok = (rows_done || rows_dispatch<double>(lgx, s, sa, n_inst, ny, u0, field, twx, half, ltc, nkb)) &&
+        ok = (rows_done || rows_dispatch<double>(lgx, s, sa, n_inst, ny, ip, field, twx, half, ltc, nkb)) &&
              cols_dispatch<double>(lgy, s, sa, n_inst, nx, nkb, nbins, half, twy, shells, part, groups, iters);
     }
     if (!ok) return hipErrorInvalidValue;

@@ -99,8 +99,8 @@ __global__ void __launch_bounds__(256)
     const int inst = blockIdx.y;
     const int64_t c = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
     if (c >= cells) return;
-    double v = p.u0;
     const InstND ipar = p.ip[inst];
+    double v = ipar.u0;
     if (ipar.init_sd > 0.0) {
         const Normals4<double> nz = block_normals<double>(static_cast<uint32_t>(c >> 2), 0u, ctr_word2(0, 1u),
                                                           ipar.realisation, make_key(p.seed));
@@ -125,10 +125,11 @@ __global__ void __launch_bounds__(256)
         if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
         __syncthreads();
     }
+    const double u0 = p.ip[inst].u0;
     if (threadIdx.x == 0) {
         const InstAcc q = acc[inst];
         const double M = q.n_samples > 0 ? static_cast<double>(q.n_samples) : 1.0;
-        out[0] = p.u0 + q.sp_mean / M;
+        out[0] = u0 + q.sp_mean / M;
         out[1] = q.sp_var / M;
         out[2] = red[0];
     }
@@ -141,7 +142,7 @@ __global__ void __launch_bounds__(256)
         const double *ss = sk_sums + static_cast<int64_t>(inst) * nbins;
         for (int b = threadIdx.x; b < nbins; b += 256) {
             double v = ss[b];
-            if (b == 0) v += M * N * N * p.u0 * p.u0 + 2.0 * N * p.u0 * (N * q.sp_mean);
+            if (b == 0) v += M * N * N * u0 * u0 + 2.0 * N * u0 * (N * q.sp_mean);
             out[3 + b] = sk_modes[b] > 0 ? v / (M * sk_modes[b]) : 0.0;
         }
     }

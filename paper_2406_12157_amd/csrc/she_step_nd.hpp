@@ -95,9 +95,9 @@ __device__ __forceinline__ T face_flux(T lo, T hi, T zs, uint32_t &clamps)
 // scale ns of the instance over r (the fluxes are carried divided by r; r = 0
 // has no noise).
 template <typename T>
-__device__ __forceinline__ T flux_radius(const ParamsND &p, double ns)
+__device__ __forceinline__ T flux_radius(const InstND &ip)
 {
-    return radius_const<T>(p.r > 0.0 ? ns / p.r : 0.0);
+    return radius_const<T>(ip.r > 0.0 ? ip.ns / ip.r : 0.0);
 }
 
 __device__ __forceinline__ int wrap(int i, int n)
@@ -235,9 +235,9 @@ __global__ void __launch_bounds__(256)
         return;
     }
 
-    const T r = static_cast<T>(p.r);
     const InstND ipar = p.ip[inst];
-    const T rc = flux_radius<T>(p, ipar.ns);
+    const T r = static_cast<T>(ipar.r);
+    const T rc = flux_radius<T>(ipar);
     uint32_t clamps = 0;
     const int noise = p.noise;
     const uint32_t real = ipar.realisation;
@@ -251,7 +251,7 @@ __global__ void __launch_bounds__(256)
     auto drow = [&](int y, int e) { return static_cast<uint32_t>(wrap(y, ny) * 2 + e); };
 
     double sa = 0.0, sb = 0.0;
-    const double u0d = p.u0;
+    const double u0d = ipar.u0;
 
     // The march loops are unrolled over the period of their register window
     // (FE: three rows and two flux rows, period 6; PC: four rows and pairs,
@@ -584,9 +584,9 @@ __global__ void __launch_bounds__(256)
     T *fsh = tsh + 2 * ty * nx;                           // [2][ty][nx]
     const int cell0 = CX * lx;
 
-    const T r = static_cast<T>(p.r);
     const InstND ipar = p.ip[inst];
-    const T rc = flux_radius<T>(p, ipar.ns);
+    const T r = static_cast<T>(ipar.r);
+    const T rc = flux_radius<T>(ipar);
     uint32_t clamps = 0;
     const int noise = p.noise;
     const uint32_t real = ipar.realisation;
@@ -598,7 +598,7 @@ __global__ void __launch_bounds__(256)
     };
 
     double sa = 0.0, sb = 0.0;
-    const double u0d = p.u0;
+    const double u0d = ipar.u0;
 
     // As in 2D, the march is unrolled over the period of its register window
     // (three planes of the row and two z-flux rows: period 6) and the noise

@@ -77,7 +77,7 @@ def test_invalid_nd_configs():
         she.Handle.arena_bytes([gpu_instance(she, W.instance((64, 64), r=0.1, bc=W.DIRICHLET))])
     assert e.value.status == she.EINVAL
     a = W.instance((64, 64), r=0.1, realisation=0)
-    b = W.instance((64, 64), r=0.11, realisation=1)
+    b = W.instance((64, 32), r=0.1, realisation=1)            # another grid in the same batch
     with pytest.raises(she.SheError) as e:
         she.Handle.arena_bytes([gpu_instance(she, a), gpu_instance(she, b)])
     assert e.value.status == she.EUNSUPPORTED
@@ -211,11 +211,17 @@ def test_second_moment_stability_check_at_create():
     assert e.value.status == she.EINVAL
 
 
-def test_nd_batches_may_differ_in_eps_and_init_sd_only():
+def test_nd_batches_may_differ_in_r_u0_eps_and_init_sd():
     a = W.instance((64, 32), r=0.1, eps=1e-2, init_sd=0.1, realisation=0)
-    ok = [a, dict(a, eps=3e-2, realisation=1), dict(a, init_sd=0.0, realisation=2)]
+    ok = [a, dict(a, eps=3e-2, realisation=1), dict(a, init_sd=0.0, realisation=2), dict(a, r=0.2, realisation=3),
+          dict(a, u0=2.0, u_left=2.0, u_right=2.0, realisation=4)]
     she.Handle.arena_bytes([gpu_instance(she, i) for i in ok])
-    for bad in (dict(a, u0=2.0, u_left=2.0, u_right=2.0), dict(a, seed=4), dict(a, noise=1), dict(a, scheme=W.HEUN)):
+    # each instance is checked against its own stability limit
+    with pytest.raises(she.SheError) as e:
+        she.Handle.arena_bytes([gpu_instance(she, a), gpu_instance(she, dict(a, r=0.3))])
+    assert e.value.status == she.EUNSTABLE
+    for bad in (dict(a, seed=4), dict(a, noise=1), dict(a, scheme=W.HEUN), dict(a, eq=W.SPECIES, u0=100.0,
+                                                                                 u_left=100.0, u_right=100.0)):
         with pytest.raises(she.SheError) as e:
             she.Handle.arena_bytes([gpu_instance(she, a), gpu_instance(she, bad)])
         assert e.value.status == she.EUNSUPPORTED, bad

@@ -596,6 +596,47 @@ def test_nd_spatial_statistics_parity(she):
     h.close()
 
 
+@pytest.mark.parametrize("n,scheme,eq", [((64, 32), W.EM, W.HEAT), ((512, 16), W.EM, W.HEAT),
+                                         ((32, 16), W.HEUN, W.HEAT), ((16, 8, 6), W.HEUN, W.SPECIES)],
+                         ids=["2d-fe", "2d-fe-rows-in-step", "2d-pc", "3d-pc-dk"])
+def test_nd_heterogeneous_batch_parity(she, n, scheme, eq):
+    """One launch holds instances with different r, u0, eps and init_sd (the
+    grid, equation, scheme, noise mode and seed are shared): each instance's
+    state after 400 steps against the oracle run with its own parameters
+    (FP32 bar 1e-5), and in 2D its spatial statistics and radial S(k)
+    (1e-3), also on the sample launches that transform their rows in the
+    step kernel (512-cell rows)."""
+    two = len(n) == 2
+    if eq == W.HEAT:
+        params = [dict(r=0.1, u0=1.0, eps=1e-2, init_sd=0.1), dict(r=0.06, u0=2.5, eps=3e-2, init_sd=0.0),
+                  dict(r=0.2, u0=0.7, eps=5e-3, init_sd=0.05)]
+    else:
+        params = [dict(r=0.05, u0=200.0, eps=1.0, init_sd=14.0), dict(r=0.1, u0=900.0, eps=0.5, init_sd=20.0),
+                  dict(r=0.02, u0=50.0, eps=2.0, init_sd=5.0)]
+    insts = [W.instance(n, eq=eq, scheme=scheme, realisation=q, u_left=kw["u0"], u_right=kw["u0"], **kw)
+             for q, kw in enumerate(params)]
+    burn, every, steps = 20, 2, 400
+    mask = she.STAT_SPATIAL | (she.STAT_SK if two else 0)
+    h = she.Handle([gpu_instance(she, i) for i in insts], precision=0, burn_in=burn, sample_every=every, stats=mask)
+    init = [h.read_field(q) for q in range(3)]
+    h.run(steps)
+    for q in range(3):
+        d = oracle_desc(insts[q], 0)
+        st = oracle.Stats(d, burn_in=burn, every=every, per_cell=False, sk=two)
+        u = init[q].copy()
+        oracle.advance(d, u, 0, steps, st)
+        assert max_rel(h.read_field(q), u) <= 1e-5, q
+        g = h.stats(q, sk=two)
+        assert g["n_samples"] == st.n_samples == 190
+        sp = st.spatial()
+        assert abs(g["var"][0] / sp[2] - 1) < 1e-3, q
+        assert abs(g["mean"][0] - (params[q]["u0"] + sp[0])) < 1e-6 * params[q]["u0"], q
+        if two:
+            ok = g["sk_modes"] > 0
+            assert max_rel(g["sk"][ok], st.structure_factor()[ok]) < 1e-3, q
+    h.close()
+
+
 @pytest.mark.parametrize("shape,precision", [((32, 16), 0), ((8, 32), 0), ((64, 64), 0), ((512, 8), 0),
                                              ((16, 16), 1), ((1024, 8), 0), ((8, 1024), 0), ((16, 512), 1)])
 def test_2d_radial_structure_factor_parity(she, shape, precision):
