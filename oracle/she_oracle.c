@@ -53,7 +53,8 @@
  *   counter = (face >> 2, step mod 2^32, ((step >> 32) & 0xFFFF) | tag << 16,
  *              realisation)
  *   lane    = face & 3; lanes (0,1) and (2,3) form Box-Muller pairs,
- *   u       = ((word >> 9) + 1/2) * 2^-23   (exact in FP32 and FP64),
+ *   u_a     = ((word_a >> 9) + 1/2) * 2^-23 in (0, 1) (the radius needs u_a > 0),
+ *   u_b     = (word_b >> 9) * 2^-23 in [0, 1) (the angle; exact in FP32 and FP64),
  *   even lane: sqrt(-2 ln u_a) cos(2 pi u_b), odd lane: ... sin(2 pi u_b).
  * tag 0 = step noise, tag 1 = initial perturbation (one number per cell).
  *
@@ -182,12 +183,17 @@ static double unit_open(uint32_t w)
     return ((double)(w >> 9) + 0.5) * 0x1p-23;
 }
 
+static double unit_angle(uint32_t w)
+{
+    return (double)(w >> 9) * 0x1p-23;
+}
+
 /* Box-Muller on one Philox block: out[lane] for lanes 0..3. */
 static void block_normals(const uint32_t x[4], double out[4])
 {
     for (int p = 0; p < 4; p += 2) {
         double ua = unit_open(x[p]);
-        double ub = unit_open(x[p + 1]);
+        double ub = unit_angle(x[p + 1]);
         double rho = sqrt(-2.0 * log(ua));
         double ang = 2.0 * M_PI * ub;
         out[p] = rho * cos(ang);

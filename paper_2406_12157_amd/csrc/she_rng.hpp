@@ -6,12 +6,14 @@
 // advanced by the two Weyl increments between rounds.  The key is uniform over
 // a launch, so its schedule lives in scalar registers.
 //
-// Box-Muller: uniforms u = ((w >> 9) + 1/2) 2^-23 (exact in FP32 and FP64),
+// Box-Muller: the radius takes u_a = ((w_a >> 9) + 1/2) 2^-23 in (0, 1), the
+// angle u_b = (w_b >> 9) 2^-23 in [0, 1) (both exact in FP32 and FP64);
 // pairs (lane 0, lane 1) and (lane 2, lane 3); even lane
 // sqrt(-2 ln u_a) cos(2 pi u_b), odd lane sqrt(-2 ln u_a) sin(2 pi u_b).
 // The FP32 form uses the native v_log_f32 (log2), v_sqrt_f32 and
 // v_sin_f32 / v_cos_f32, whose argument is in revolutions, so 2 pi u_b
-// needs no multiply and no range reduction.
+// needs no multiply and no range reduction, and 1 + u_b (the bits of one
+// funnel shift, no subtraction) gives the same sine and cosine.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -83,10 +85,22 @@ __device__ __forceinline__ double unit_open_f64(uint32_t w)
     return (static_cast<double>(w >> 9) + 0.5) * 0x1p-23;
 }
 
+// The angle uniform: 1 + u_b in FP32 (a whole number of revolutions more),
+// u_b in FP64.
+__device__ __forceinline__ float unit_angle_f32(uint32_t w)
+{
+    return __uint_as_float(__builtin_amdgcn_alignbit(0x7Fu, w, 9));
+}
+
+__device__ __forceinline__ double unit_angle_f64(uint32_t w)
+{
+    return static_cast<double>(w >> 9) * 0x1p-23;
+}
+
 __device__ __forceinline__ void box_muller(uint32_t wa, uint32_t wb, float &zc, float &zs)
 {
     const float ua = unit_open_f32(wa);
-    const float ub = unit_open_f32(wb);
+    const float ub = unit_angle_f32(wb);
     // -2 ln(u) = -2 ln(2) log2(u)
     const float rho = __builtin_amdgcn_sqrtf(__builtin_amdgcn_logf(ua) * -1.38629436111989061883f);
     zc = rho * __builtin_amdgcn_cosf(ub);
@@ -96,7 +110,7 @@ __device__ __forceinline__ void box_muller(uint32_t wa, uint32_t wb, float &zc, 
 __device__ __forceinline__ void box_muller(uint32_t wa, uint32_t wb, double &zc, double &zs)
 {
     const double ua = unit_open_f64(wa);
-    const double ub = unit_open_f64(wb);
+    const double ub = unit_angle_f64(wb);
     const double rho = sqrt(-2.0 * log(ua));
     const double ang = (2.0 * 3.14159265358979323846) * ub;
     double s, c;
@@ -124,7 +138,7 @@ __device__ __forceinline__ Normals4<T> block_normals(uint32_t block, uint32_t st
 __device__ __forceinline__ void box_muller_scaled(uint32_t wa, uint32_t wb, float rc, float &zc, float &zs)
 {
     const float ua = unit_open_f32(wa);
-    const float ub = unit_open_f32(wb);
+    const float ub = unit_angle_f32(wb);
     const float rho = __builtin_amdgcn_sqrtf(__builtin_amdgcn_logf(ua) * rc);
     zc = rho * __builtin_amdgcn_cosf(ub);
     zs = rho * __builtin_amdgcn_sinf(ub);

@@ -592,7 +592,11 @@ def test_nd_spatial_statistics_parity(she):
         sp = st.spatial()
         assert abs(g["var"][0] / sp[2] - 1) < 1e-3
         assert abs(g["mean"][0] - (1.0 + sp[0])) < 1e-6
-        assert abs(g["sum_u"] / u.sum() - 1) < 1e-6
+        # sum_u reduces the GPU's own field in FP64; the FP32 field's sum
+        # drifts from the exactly conserved FP64 one by rounding (about 1e-6
+        # after 1500 steps here), within the FP32 state bar
+        assert abs(g["sum_u"] / h.read_field(q).sum() - 1) < 1e-12
+        assert abs(g["sum_u"] / u.sum() - 1) < 1e-5
     h.close()
 
 
