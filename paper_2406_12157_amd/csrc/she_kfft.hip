@@ -58,7 +58,7 @@ __global__ void __launch_bounds__(256) k_twiddles(int n, cplx<T> *__restrict__ t
 constexpr int kLdsBudget = 64 * 1024;  // bytes of LDS per block
 
 // Waves per block of the row transform: as many as fit the LDS budget, up to
-// 8 (8 row pairs give 128-byte runs per kx in the kx-major store).
+// 8 (a block's 16 rows of a tile are one contiguous run of the store).
 template <typename T, int LG>
 constexpr int row_waves()
 {
