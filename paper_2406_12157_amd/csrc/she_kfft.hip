@@ -133,10 +133,10 @@ __global__ void __launch_bounds__(512)
     }
 }
 
-// LDS bytes per wave of the column transform: its transform region and the
-// FP64 prefix sums of one column.  A wave that holds one column per
-// transform (S = 1) writes the prefix sums over that column once it has read
-// it, so they need no room of their own.
+// LDS bytes per column group of the column transform: its transform region
+// and the FP64 prefix sums of one column (ppad layout).  A group of one
+// column (S = 1) holds the prefix sums in its transform region once the
+// transform has left it, so they need no room of their own.
 constexpr int col_region(int es, int lg)
 {
     return es * wave_lds(lg) + (wave_seqs(lg) == 1 ? 0 : 8 * (((1 << lg) / 2 + 1) * 5 / 4 + 1));
