@@ -320,6 +320,36 @@ def roofline(kms_per_step, cells, per_launch, every, kernel, variant, valu_file,
     return out
 
 
+def copy_bandwidth(torch, nbytes, reps=10):
+    """Device-to-device copy rate (GB/s, bytes read + written) at a footprint
+    of nbytes each way: the streaming rate this part reaches there, the
+    second reference of the HBM roofline (the first is the 8 TB/s peak)."""
+    n = nbytes // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(2):
+        dst.copy_(src)
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    b.record()
+    torch.cuda.synchronize()
+    gbs = 2.0 * n * 4 * reps / (a.elapsed_time(b) * 1e-3) / 1e9
+    del src, dst
+    torch.cuda.empty_cache()
+    return gbs
+
+
+def add_copy_reference(roof, gbs):
+    """HBM fractions of a roofline against the measured copy rate."""
+    hbm = roof["hbm"]
+    hbm["copy_achieved"] = gbs
+    hbm["frac_of_copy"] = hbm["achieved"] / gbs
+    if "bus_achieved" in hbm:
+        hbm["bus_frac_of_copy"] = hbm["bus_achieved"] / gbs
+
+
 # ---------------------------------------------------------------- other workloads
 
 def other_error(she, W, name, cfg, stats):
@@ -401,12 +431,14 @@ def other_workload(args, torch, she, W):
         wall, kms, _ = timed_region(torch, h, args.steps, cfg["sample_every"])
         roof = roofline(kms, cells, 1, cfg["sample_every"], "k_step3d<float,4,dk,fe>", "she_k3d_f32.hip",
                         "valu_step3d_c5.json", "traffic_step3d_c5.json")
+        h.close()
+        add_copy_reference(roof, copy_bandwidth(torch, 4 * cells))
     else:
         t0 = time.perf_counter()
         h.run(args.steps)
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
-    h.close()
+        h.close()
     out = {"metric": METRIC, "value": cells * args.steps / wall, "unit": "cell-updates/s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": wall / args.steps * 1e3,
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
@@ -471,6 +503,7 @@ def main():
     roof = roofline(kms, cells, 2 if fe else 1, every,
                     "k_step2d<float,8,heat,%s>" % ("fe x2" if fe else "pc"), "she_k2d_f32x8.hip",
                     "valu_step2d_c3.json" if fe else None, "traffic_step2d_c3.json" if fe else None)
+    add_copy_reference(roof, copy_bandwidth(torch, 4 * cells))
     out = {"metric": METRIC, "value": value, "unit": "cell-updates/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
            "vs_baseline": None, "dtype": "f32", "data": "synthetic",

@@ -61,3 +61,14 @@ def test_closed_forms_of_the_error_leg():
         ok[0] = False
         np.testing.assert_allclose(got[ok], want[ok] / cnt[ok], rtol=1e-13)
         np.testing.assert_array_equal(c2, cnt)
+
+
+def test_copy_reference_fractions():
+    roof = {"hbm": {"achieved": 6000.0, "bus_achieved": 3000.0}}
+    bench.add_copy_reference(roof, 5000.0)
+    h = roof["hbm"]
+    assert h["copy_achieved"] == 5000.0
+    assert abs(h["frac_of_copy"] - 1.2) < 1e-15 and abs(h["bus_frac_of_copy"] - 0.6) < 1e-15
+    roof = {"hbm": {"achieved": 1000.0}}
+    bench.add_copy_reference(roof, 4000.0)
+    assert roof["hbm"]["frac_of_copy"] == 0.25 and "bus_frac_of_copy" not in roof["hbm"]
