@@ -56,7 +56,8 @@ __device__ __forceinline__ cplx<T> unpack2_b(cplx<T> z, cplx<T> zm)
 }
 
 // Shape of the per-wave transform of length n = 2^lg: P points per lane,
-// S sequences per wave (64 P = S n), padded LDS entries per wave region.
+// S sequences per wave (64 P = S n), padded LDS entries per wave region
+// (three pad entries per 32, see pidx).
 constexpr int wave_points(int lg)
 {
     return (1 << lg) >= 512 ? (1 << lg) / 64 : ((1 << lg) >= 8 ? 8 : (1 << lg));
@@ -69,7 +70,7 @@ constexpr int wave_seqs(int lg)
 
 constexpr int wave_lds(int lg)
 {
-    return (wave_seqs(lg) << lg) + (((wave_seqs(lg) << lg) - 1) >> 4) + 1;
+    return (wave_seqs(lg) << lg) + 3 * (((wave_seqs(lg) << lg) - 1) >> 5) + 1;
 }
 
 // log2 of the radix of the pass at sub-transform length 2^rem: 8, then 4 or 2
@@ -98,10 +99,17 @@ struct WaveFft {
     static constexpr int tw = tw_entries(LG) > 0 ? tw_entries(LG) : 1;  // per-pass twiddle entries
 };
 
-// one pad entry per 16 spreads the strided exchange accesses over the banks
+// Three pad entries after every 32.  A 64-bit access of a wave is served 32
+// lanes at a time by the 64 four-byte banks, so 32 lanes touching 32
+// distinct entries modulo 32 are conflict-free.  With this padding the
+// exchanges of the 512-point transform, entries l + 64 k and 8 l + k for lane
+// l, are; those of the middle pass, (l & 7) + 64 (l >> 3) + 8 k, conflict
+// two-way (a pad of one per 16 made all three two-way).  The pad of an entry
+// is a multiple of the lane's part plus one of k, so every access is a
+// per-lane base plus a constant offset.
 __device__ __forceinline__ int pidx(int i)
 {
-    return i + (i >> 4);
+    return i + 3 * (i >> 5);
 }
 
 // Order the LDS accesses of one wave (a wave's LDS operations complete in

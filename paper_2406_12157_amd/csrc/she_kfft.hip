@@ -334,22 +334,40 @@ __global__ void __launch_bounds__(256, (sizeof(T) == 4 && LGY <= 9) ? 4 : 2)
     const cplx<T> *hi = half + static_cast<int64_t>(inst) * nkb * n * TC;
     fill_pass_twiddles<T, LGY>(tw, twy);
     // a tile (contiguous: n rows of TC columns) has n TC = 64 CW CPW P
-    // points, CPW P per thread; point j of thread t is entry e = t + 64 CW j:
-    // row e / TC, column e % TC, in the region of column group e % TC / S
+    // points, CPW P per thread.  Entry e is row e / TC, column e % TC, and
+    // goes to the region of column group e % TC / S.  FP64: point j of thread
+    // t is entry t + 64 CW j.  FP32 points move two at a time, in 16-byte
+    // loads of two adjacent columns of a row: points 2 j and 2 j + 1 are
+    // entries 2 e and 2 e + 1, e = t + 64 CW j.
     constexpr int lTC = 31 - __builtin_clz(TC), PT = CPW * P;
     const int tc = threadIdx.x & (TC - 1);
     cplx<T> pf[PT];
+    constexpr bool V2 = sizeof(T) == 4 && TC >= 2;
     auto fetch = [&](int cb) {
-        const bool in = cb + tc < nh;
         const cplx<T> *tile = hi + static_cast<unsigned>(cb * n);  // tile cb / TC
+        if constexpr (V2) {
+            typedef float f4v __attribute__((ext_vector_type(4)));
+            const f4v *t4 = reinterpret_cast<const f4v *>(tile);
+            const int c0 = (2 * threadIdx.x) & (TC - 1);
+            const bool in0 = cb + c0 < nh, in1 = cb + c0 + 1 < nh;
 #pragma unroll
-        for (int j = 0; j < PT; ++j)
-            pf[j] = in ? tile[threadIdx.x + 64 * CW * j] : cplx<T>{T(0), T(0)};
+            for (int j = 0; j < PT / 2; ++j) {
+                const f4v q = t4[threadIdx.x + 64 * CW * j];
+                pf[2 * j] = in0 ? cplx<T>{q.x, q.y} : cplx<T>{T(0), T(0)};
+                pf[2 * j + 1] = in1 ? cplx<T>{q.z, q.w} : cplx<T>{T(0), T(0)};
+            }
+        } else {
+            const bool in = cb + tc < nh;
+#pragma unroll
+            for (int j = 0; j < PT; ++j)
+                pf[j] = in ? tile[threadIdx.x + 64 * CW * j] : cplx<T>{T(0), T(0)};
+        }
     };
     auto stash = [&]() {
 #pragma unroll
         for (int j = 0; j < PT; ++j) {
-            const int e = threadIdx.x + 64 * CW * j, y = e >> lTC, c = e & (TC - 1);
+            const int e = V2 ? 2 * (threadIdx.x + 64 * CW * (j >> 1)) + (j & 1) : threadIdx.x + 64 * CW * j;
+            const int y = e >> lTC, c = e & (TC - 1);
             cplx<T> *dst = reinterpret_cast<cplx<T> *>(regions + static_cast<size_t>(c / S) * rs);
             dst[pidx(((c & (S - 1)) << LGY) + y)] = pf[j];
         }
@@ -483,9 +501,11 @@ size_t colt_lds(int nbins, size_t *rs_out)
 {
     size_t rs = col_region(static_cast<int>(sizeof(cplx<T>)), LGY);
     rs = std::max(rs, sizeof(double) * static_cast<size_t>(nbins));
-    // regions 64 bytes apart modulo the 256 bytes of the 64 LDS banks: the
-    // tile copy's eight 64-byte row runs of four regions fill the banks once
-    rs = ((rs + 191) & ~static_cast<size_t>(255)) + 64;
+    // regions an odd multiple of 32 bytes apart: the eight regions then
+    // start 32 bytes apart modulo the 256 bytes of the 64 LDS banks (in some
+    // order), so the tile copy's half-wave stores (four rows of eight columns,
+    // or eight rows of four even or odd columns) meet each bank once
+    rs = ((rs + 31) & ~static_cast<size_t>(63)) + 32;
     if (rs_out) *rs_out = rs;
     return ((sizeof(cplx<T>) * WaveFft<LGY>::tw + 15) & ~static_cast<size_t>(15)) + colt_groups<T, LGY>() * rs;
 }
