@@ -56,10 +56,32 @@ __device__ __forceinline__ Words4 philox4x32_10(uint32_t c0, uint32_t c1, uint32
         const uint64_t p1 = static_cast<uint64_t>(0xCD9E8D57u) * c2;
         const uint32_t hi0 = static_cast<uint32_t>(p0 >> 32), lo0 = static_cast<uint32_t>(p0);
         const uint32_t hi1 = static_cast<uint32_t>(p1 >> 32), lo1 = static_cast<uint32_t>(p1);
-        // three-input xor in one v_bitop3_b32 (truth table 0x96)
-        c0 = __builtin_amdgcn_bitop3_b32(hi1, c1, k0, 0x96);
+        // Callers vary word 0 (the block number) per lane and keep the other
+        // words and the key uniform.  Up to round 2 some xors thus have two
+        // uniform inputs (round 0: word 0's product and word 2's inputs
+        // other than its product; round 1: the product of word 0, uniform
+        // after round 0, and the words beside the varying one; round 2: word
+        // 3, the low half of that uniform product).  Those pairs are formed
+        // first and the varying input is xored on by v_bitop3_b32 with a zero
+        // third input (table 0x96), which the compiler does not reassociate:
+        // the pair stays in scalar registers and one vector instruction
+        // remains, where a three-input vector xor would first need a scalar
+        // input moved to a vector register.  Elsewhere one three-input
+        // v_bitop3_b32 does the xor.
+        if (round == 0) {
+            c0 = hi1 ^ c1 ^ k0;
+            c2 = __builtin_amdgcn_bitop3_b32(hi0, c3 ^ k1, 0u, 0x96);
+        } else if (round == 1) {
+            c0 = __builtin_amdgcn_bitop3_b32(hi1, c1 ^ k0, 0u, 0x96);
+            c2 = __builtin_amdgcn_bitop3_b32(c3, hi0 ^ k1, 0u, 0x96);
+        } else if (round == 2) {
+            c0 = __builtin_amdgcn_bitop3_b32(hi1, c1, k0, 0x96);
+            c2 = __builtin_amdgcn_bitop3_b32(hi0, c3 ^ k1, 0u, 0x96);
+        } else {
+            c0 = __builtin_amdgcn_bitop3_b32(hi1, c1, k0, 0x96);
+            c2 = __builtin_amdgcn_bitop3_b32(hi0, c3, k1, 0x96);
+        }
         c1 = lo1;
-        c2 = __builtin_amdgcn_bitop3_b32(hi0, c3, k1, 0x96);
         c3 = lo0;
         k0 += 0x9E3779B9u;
         k1 += 0xBB67AE85u;

@@ -58,11 +58,26 @@
 
 namespace she {
 
+// max(x, 0) for a face density.  FP32 compares the bits as signed integers
+// (every negative float, -0 included, is a negative integer), one integer
+// max with no NaN canonicalisation; a NaN density stays NaN either way
+// through the difference term of the flux.
+__device__ __forceinline__ float clamp_nonneg(float x)
+{
+    return __int_as_float(max(__float_as_int(x), 0));
+}
+
+__device__ __forceinline__ double clamp_nonneg(double x)
+{
+    return fmax(x, 0.0);
+}
+
 // Flux through a face between cells with values lo (low side) and hi, for a
 // pre-scaled number zs (see above), in noise mode NZ (0 instantaneous,
-// 1 deterministic face value, 2 off).
+// 1 deterministic face value, 2 off); neg tells whether the Dean-Kawasaki
+// face density was negative and clamped to zero.
 template <typename T, int EQ, int NZ>
-__device__ __forceinline__ T face_flux(T lo, T hi, T zs, uint32_t &clamps)
+__device__ __forceinline__ T face_flux(T lo, T hi, T zs, bool &neg)
 {
     // The face flux divided by r: the difference hi - lo plus the noise term,
     // whose scale carries 1/r (the caller multiplies the divergence by r once
@@ -70,18 +85,16 @@ __device__ __forceinline__ T face_flux(T lo, T hi, T zs, uint32_t &clamps)
     // out so that every copy of this code rounds alike: a face computed in two
     // places gets one value.
     const T d = hi - lo;
+    neg = false;
     if constexpr (NZ == 0) {
         const T s = lo + hi;
         T a;
         if constexpr (EQ == 0) {
             a = s;
         } else {
-            if (s < T(0)) {
-                ++clamps;
-                a = T(0);
-            } else {
-                a = amp_sqrt(s);
-            }
+            // the root of max(s, 0): the compare only counts the clamp
+            neg = s < T(0);
+            a = amp_sqrt(clamp_nonneg(s));
         }
         return fma(a, zs, d);
     } else if constexpr (NZ == 1) {
@@ -89,6 +102,23 @@ __device__ __forceinline__ T face_flux(T lo, T hi, T zs, uint32_t &clamps)
     } else {
         return d;
     }
+}
+
+template <typename T, int EQ, int NZ>
+__device__ __forceinline__ T face_flux(T lo, T hi, T zs, uint32_t &clamps)
+{
+    bool neg;
+    const T f = face_flux<T, EQ, NZ>(lo, hi, zs, neg);
+    clamps += neg ? 1u : 0u;
+    return f;
+}
+
+// Number of lanes of the wave for which b holds (wave-uniform).  Called in
+// control flow that all lanes of the wave take, it lets a count of rare
+// events live in one scalar register: no per-lane select and add.
+__device__ __forceinline__ uint32_t wave_count(bool b)
+{
+    return static_cast<uint32_t>(__builtin_popcountll(__builtin_amdgcn_ballot_w64(b)));
 }
 
 // Box-Muller radius constant of the normals a face flux takes: the noise
@@ -146,19 +176,24 @@ __device__ __forceinline__ void row_normals(T (&z)[CX], uint32_t drow, uint32_t 
 
 // x-fluxes of one row held by a group of LX lanes: Flo[j] is the flux through
 // the low face of the lane's cell j, Fhi the flux through the high face of its
-// last cell (= the next lane's Flo[0]).
-template <typename T, int CX, int EQ, int NZ>
+// last cell (= the next lane's Flo[0]).  count(neg) is called once per face.
+template <typename T, int CX, int EQ, int NZ, typename Count>
 __device__ __forceinline__ void row_xflux(const T (&v)[CX], const T (&z)[CX], T (&Flo)[CX], T &Fhi, int lx, int LX,
-                                          uint32_t &clamps)
+                                          Count &&count)
 {
     const int lane = threadIdx.x & 63;
     const int gbase = lane - lx;
     const int left = gbase + (lx == 0 ? LX - 1 : lx - 1);
     const int right = gbase + (lx == LX - 1 ? 0 : lx + 1);
     const T vleft = __shfl(v[CX - 1], left, 64);
-    Flo[0] = face_flux<T, EQ, NZ>(vleft, v[0], z[0], clamps);
+    bool neg;
+    Flo[0] = face_flux<T, EQ, NZ>(vleft, v[0], z[0], neg);
+    count(neg);
 #pragma unroll
-    for (int j = 1; j < CX; ++j) Flo[j] = face_flux<T, EQ, NZ>(v[j - 1], v[j], z[j], clamps);
+    for (int j = 1; j < CX; ++j) {
+        Flo[j] = face_flux<T, EQ, NZ>(v[j - 1], v[j], z[j], neg);
+        count(neg);
+    }
     Fhi = __shfl(Flo[0], right, 64);
 }
 
@@ -274,7 +309,7 @@ __global__ void __launch_bounds__(256)
         auto xflux = [&](const T (&v)[CX], const T (&z)[CX], T (&fx)[CX], T &fxh,
                          bool own = true) __attribute__((always_inline)) {
             uint32_t c = 0;
-            row_xflux<T, CX, EQ, NZ>(v, z, fx, fxh, lx, LX, c);
+            row_xflux<T, CX, EQ, NZ>(v, z, fx, fxh, lx, LX, [&](bool neg) { c += neg ? 1u : 0u; });
             clamps += own ? c : 0u;
         };
         auto emit = [&](const T (&out)[CX], int y) __attribute__((always_inline)) {
@@ -540,7 +575,10 @@ __global__ void __launch_bounds__(256)
 // STAGE 0: FE step (or a PC predictor) dst = src + Delta(src);
 // STAGE 1: PC corrector dst = (base + src + Delta(src)) / 2, with src the
 // predictor and base the state it was taken from (same step, same numbers).
-template <typename T, int CX, int EQ, int STAGE>
+// RW: one row per wave (Nx = 64 CX).  The row, its plane offsets and its
+// counter words are then the same for the whole wave and live in scalar
+// registers; otherwise several rows share a wave.
+template <typename T, int CX, int EQ, int STAGE, bool RW>
 __global__ void __launch_bounds__(256)
     k_step3d(ParamsND p, int32_t ty, const T *__restrict__ src, const T *__restrict__ base, T *__restrict__ dst,
              StepArg sarg, double *__restrict__ part, InstAcc *__restrict__ acc)
@@ -549,9 +587,10 @@ __global__ void __launch_bounds__(256)
     int sample;
     resolve_step(sarg, step, sample);
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    const int LX = p.nx / CX;
-    const int lx = threadIdx.x % LX;
-    const int g = threadIdx.x / LX;                 // row within the tile
+    const int LX = RW ? 64 : p.nx / CX;
+    const int lx = RW ? static_cast<int>(threadIdx.x & 63) : static_cast<int>(threadIdx.x) % LX;
+    // row within the tile
+    const int g = RW ? __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x >> 6)) : static_cast<int>(threadIdx.x) / LX;
     const int nyt = p.ny / ty, nzc = (p.nz + p.chunk - 1) / p.chunk;
     const int tiles = nyt * nzc;
     const int lblock = p.xcd_order ? xcd_block(blockIdx.x, gridDim.x) : static_cast<int>(blockIdx.x);
@@ -587,6 +626,8 @@ __global__ void __launch_bounds__(256)
     const InstND ipar = p.ip[inst];
     const T r = static_cast<T>(ipar.r);
     const T rc = flux_radius<T>(ipar);
+    // density clamps of the wave: every count is taken in control flow that
+    // the whole wave follows, so the total is wave-uniform (lane 0 reports it)
     uint32_t clamps = 0;
     const int noise = p.noise;
     const uint32_t real = ipar.realisation;
@@ -608,13 +649,21 @@ __global__ void __launch_bounds__(256)
         auto normals = [&](T (&z)[CX], uint32_t dr) __attribute__((always_inline)) {
             row_normals<T, CX, NZ>(z, dr, nq, q0, slo, w2, real, key, rc);
         };
-        // clamps counted by the owner of each face (the low faces of the
-        // tile's rows and planes), as in 2D
+        // Each face's clamp is counted once: x- and low y-faces by the row
+        // they belong to, z-faces by the chunk below them (its planes' high
+        // z-faces, the last one included; so not the low z-faces of a chunk's
+        // first plane), and not the high y-faces a tile's top row recomputes
+        // (own = false, in a branch only that row takes).
         auto flux = [&](T lo, T hi, T z, bool own = true) __attribute__((always_inline)) {
-            uint32_t c = 0;
-            const T f = face_flux<T, EQ, NZ>(lo, hi, z, c);
-            clamps += own ? c : 0u;
+            bool neg;
+            const T f = face_flux<T, EQ, NZ>(lo, hi, z, neg);
+            if constexpr (EQ == 1 && NZ == 0) {
+                if (own) clamps += wave_count(neg);
+            }
             return f;
+        };
+        auto count = [&](bool neg) __attribute__((always_inline)) {
+            if constexpr (EQ == 1 && NZ == 0) clamps += wave_count(neg);
         };
         T ra[CX], rb[CX], rq[CX], fa[CX], fb[CX];
         {
@@ -624,7 +673,7 @@ __global__ void __launch_bounds__(256)
             load_row<T, CX>(S + rowp(y, z0 + 1), rb);
             normals(z, drow(y, z0, 2));
 #pragma unroll
-            for (int j = 0; j < CX; ++j) fa[j] = flux(tp[j], ra[j], z[j]);
+            for (int j = 0; j < CX; ++j) fa[j] = flux(tp[j], ra[j], z[j], false);
             T *dstp = tsh + ((z0 & 1) * ty + g) * nx + cell0;
 #pragma unroll
             for (int j = 0; j < CX; ++j) dstp[j] = ra[j];
@@ -639,11 +688,11 @@ __global__ void __launch_bounds__(256)
             T z[CX];
             normals(z, drow(y, zi + 1, 2));
 #pragma unroll
-            for (int j = 0; j < CX; ++j) fzhi[j] = flux(tc[j], tn[j], z[j], zi + 1 < z1);
+            for (int j = 0; j < CX; ++j) fzhi[j] = flux(tc[j], tn[j], z[j]);
 
             T fxlo[CX], fxhi;
             normals(z, drow(y, zi, 0));
-            row_xflux<T, CX, EQ, NZ>(tc, z, fxlo, fxhi, lx, LX, clamps);
+            row_xflux<T, CX, EQ, NZ>(tc, z, fxlo, fxhi, lx, LX, count);
 
             T ylo[CX], fylo[CX];
             normals(z, drow(y, zi, 1));
@@ -733,8 +782,9 @@ __global__ void __launch_bounds__(256)
             part[2 * static_cast<int64_t>(lblock) + 1] = tb;
         }
     }
-    if (clamps) atomicAdd(reinterpret_cast<unsigned long long *>(&acc[inst].clamp_count),
-                          static_cast<unsigned long long>(clamps));
+    if (clamps && (threadIdx.x & 63) == 0)
+        atomicAdd(reinterpret_cast<unsigned long long *>(&acc[inst].clamp_count),
+                  static_cast<unsigned long long>(clamps));
 }
 
 // ------------------------------------------------------------------ typed launchers
@@ -780,13 +830,20 @@ static hipError_t step3d_s(int stage, int ty, int n_blocks, size_t smem, hipStre
                            InstAcc *acc)
 {
     const dim3 block((p.nx / CX) * ty);
-    if (stage == 0)
-        hipLaunchKernelGGL((k_step3d<T, CX, EQ, 0>), dim3(n_blocks), block, smem, s, p, ty,
-                           static_cast<const T *>(src), static_cast<const T *>(base), static_cast<T *>(dst), sa,
+    const T *in = static_cast<const T *>(src), *bs = static_cast<const T *>(base);
+    T *out = static_cast<T *>(dst);
+    const bool rw = p.nx == 64 * CX;
+    if (stage == 0 && rw)
+        hipLaunchKernelGGL((k_step3d<T, CX, EQ, 0, true>), dim3(n_blocks), block, smem, s, p, ty, in, bs, out, sa,
+                           part, acc);
+    else if (stage == 0)
+        hipLaunchKernelGGL((k_step3d<T, CX, EQ, 0, false>), dim3(n_blocks), block, smem, s, p, ty, in, bs, out, sa,
+                           part, acc);
+    else if (rw)
+        hipLaunchKernelGGL((k_step3d<T, CX, EQ, 1, true>), dim3(n_blocks), block, smem, s, p, ty, in, bs, out, sa,
                            part, acc);
     else
-        hipLaunchKernelGGL((k_step3d<T, CX, EQ, 1>), dim3(n_blocks), block, smem, s, p, ty,
-                           static_cast<const T *>(src), static_cast<const T *>(base), static_cast<T *>(dst), sa,
+        hipLaunchKernelGGL((k_step3d<T, CX, EQ, 1, false>), dim3(n_blocks), block, smem, s, p, ty, in, bs, out, sa,
                            part, acc);
     return hipGetLastError();
 }

@@ -891,20 +891,24 @@ def test_nd_freeze_beside_healthy_instances(she, n, scheme):
 
 
 @pytest.mark.parametrize("n,scheme", [((32, 24), W.EM), ((32, 24), W.HEUN), ((16, 8, 6), W.EM),
-                                      ((16, 8, 6), W.HEUN)], ids=["2d-fe", "2d-pc", "3d-fe", "3d-pc"])
+                                      ((16, 8, 6), W.HEUN), ((256, 4, 3), W.EM), ((256, 4, 3), W.HEUN)],
+                         ids=["2d-fe", "2d-pc", "3d-fe", "3d-pc", "3d-fe-row-per-wave", "3d-pc-row-per-wave"])
 def test_nd_clamp_count_matches_oracle(she, n, scheme):
     """Dean-Kawasaki at a low density (u0 = 2 per cell, eps = 1/dV = 1) has
     negative face means: every face and stage that meets one is clamped and
     counted once, as the oracle counts them, whatever the march length,
-    tiling or number of steps per launch (FP64 state: the same signs)."""
+    tiling or number of steps per launch (FP64 state: the same signs).  At
+    Nx = 256 each wave holds one row and counts its clamps as a wave."""
     inst = W.instance(n, eq=W.SPECIES, scheme=scheme, r=0.05, eps=1.0, u0=2.0, init_sd=1.0, realisation=4)
     steps = 120
     u = None
     counts = []
     shapes = [dict(rows_per_block=1), dict(rows_per_block=5), dict(), dict(tuning_flags=she.TUNE_SINGLE_STEP)]
     if len(n) == 3:
+        # rows per workgroup: up to 256 threads of n[0]/cx lanes per row
+        wide = min(8, 256 // min(64, n[0] // 4))
         shapes = [dict(rows_per_block=1, rows_per_group=1), dict(rows_per_block=4, rows_per_group=2),
-                  dict(rows_per_block=3, rows_per_group=8), dict()]
+                  dict(rows_per_block=3, rows_per_group=wide), dict()]
     for kw in shapes:
         h = she.Handle([gpu_instance(she, inst)], precision=1, **kw)
         if u is None:
