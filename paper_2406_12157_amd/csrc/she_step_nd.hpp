@@ -230,7 +230,10 @@ __device__ __forceinline__ void accumulate(const T (&out)[CX], double u0, double
 
 // ------------------------------------------------------------------ 2D
 
-template <typename T, int CX, int EQ, int SCHEME, bool SK = false>
+// RW: one row per wave (Nx = 64 CX, i.e. every grid from Nx = 256 on).  The
+// wave's chunk, instance and rows are then wave-uniform: instance parameters,
+// row offsets and counter words live in scalar registers.
+template <typename T, int CX, int EQ, int SCHEME, bool SK, bool RW>
 __global__ void __launch_bounds__(256)
     k_step2d(ParamsND p, const T *__restrict__ src, T *__restrict__ dst, StepArg sarg, double *__restrict__ part,
              InstAcc *__restrict__ acc, SkRows skr)
@@ -248,10 +251,11 @@ __global__ void __launch_bounds__(256)
         fill_pass_twiddles<T, LGX>(twl, static_cast<const cplx<T> *>(skr.tw));
         __syncthreads();
     }
-    const int LX = p.nx / CX;
-    const int lx = threadIdx.x % LX;
-    const int grp = threadIdx.x / LX;
-    const int gpb = blockDim.x / LX;
+    const int LX = RW ? 64 : p.nx / CX;
+    const int lx = RW ? static_cast<int>(threadIdx.x & 63) : static_cast<int>(threadIdx.x) % LX;
+    const int grp = RW ? __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x >> 6))
+                       : static_cast<int>(threadIdx.x) / LX;
+    const int gpb = RW ? static_cast<int>(blockDim.x >> 6) : static_cast<int>(blockDim.x) / LX;
     const int nchunks = (p.ny + p.chunk - 1) / p.chunk;
     const int gchunk = (p.xcd_order ? xcd_block(blockIdx.x, gridDim.x) : static_cast<int>(blockIdx.x)) * gpb + grp;
     if (gchunk >= p.n_inst * nchunks) return;
@@ -796,19 +800,43 @@ static hipError_t step2d_s(int scheme, int n_blocks, hipStream_t s, const Params
     const SkRows none{nullptr, nullptr, 0, 0};
     const T *in = static_cast<const T *>(src);
     T *out = static_cast<T *>(dst);
+    // one row per wave from Nx = 64 CX on; the planner takes CX = 8 and 16
+    // only there, so those have no other form
+    const bool rw = p.nx == 64 * CX;
+    if (!rw) {
+        if constexpr (CX == 4) {
+            if (scheme == 0)
+                hipLaunchKernelGGL((k_step2d<T, CX, EQ, 0, false, false>), dim3(n_blocks), dim3(256), 0, s, p, in,
+                                   out, sa, part, acc, none);
+            else if (scheme == 1)
+                hipLaunchKernelGGL((k_step2d<T, CX, EQ, 1, false, false>), dim3(n_blocks), dim3(256), 0, s, p, in,
+                                   out, sa, part, acc, none);
+            else if (!skr)
+                hipLaunchKernelGGL((k_step2d<T, CX, EQ, 2, false, false>), dim3(n_blocks), dim3(256), 0, s, p, in,
+                                   out, sa, part, acc, none);
+            else
+                return hipErrorInvalidValue;
+            return hipGetLastError();
+        } else {
+            return hipErrorInvalidValue;
+        }
+    }
     if (scheme == 0)
-        hipLaunchKernelGGL((k_step2d<T, CX, EQ, 0>), dim3(n_blocks), dim3(256), 0, s, p, in, out, sa, part, acc, none);
+        hipLaunchKernelGGL((k_step2d<T, CX, EQ, 0, false, true>), dim3(n_blocks), dim3(256), 0, s, p, in, out, sa,
+                           part, acc, none);
     else if (scheme == 1)
-        hipLaunchKernelGGL((k_step2d<T, CX, EQ, 1>), dim3(n_blocks), dim3(256), 0, s, p, in, out, sa, part, acc, none);
+        hipLaunchKernelGGL((k_step2d<T, CX, EQ, 1, false, true>), dim3(n_blocks), dim3(256), 0, s, p, in, out, sa,
+                           part, acc, none);
     else if (!skr)
-        hipLaunchKernelGGL((k_step2d<T, CX, EQ, 2>), dim3(n_blocks), dim3(256), 0, s, p, in, out, sa, part, acc, none);
+        hipLaunchKernelGGL((k_step2d<T, CX, EQ, 2, false, true>), dim3(n_blocks), dim3(256), 0, s, p, in, out, sa,
+                           part, acc, none);
     else {
         if constexpr (CX == 8 || CX == 16) {
             using FX = WaveFft<CX == 16 ? 10 : 9>;
             const size_t smem = sizeof(cplx<T>) * (FX::tw + 4 * static_cast<size_t>(FX::lds));
-            if (p.nx != 64 * CX || smem > 64 * 1024) return hipErrorInvalidValue;
-            hipLaunchKernelGGL((k_step2d<T, CX, EQ, 2, true>), dim3(n_blocks), dim3(256), smem, s, p, in, out, sa,
-                               part, acc, *skr);
+            if (smem > 64 * 1024) return hipErrorInvalidValue;
+            hipLaunchKernelGGL((k_step2d<T, CX, EQ, 2, true, true>), dim3(n_blocks), dim3(256), smem, s, p, in, out,
+                               sa, part, acc, *skr);
         } else {
             return hipErrorInvalidValue;
         }
@@ -832,18 +860,26 @@ static hipError_t step3d_s(int stage, int ty, int n_blocks, size_t smem, hipStre
     const dim3 block((p.nx / CX) * ty);
     const T *in = static_cast<const T *>(src), *bs = static_cast<const T *>(base);
     T *out = static_cast<T *>(dst);
+    // as in 2D: CX = 8 and 16 only with one row per wave
     const bool rw = p.nx == 64 * CX;
-    if (stage == 0 && rw)
+    if (!rw) {
+        if constexpr (CX == 4) {
+            if (stage == 0)
+                hipLaunchKernelGGL((k_step3d<T, CX, EQ, 0, false>), dim3(n_blocks), block, smem, s, p, ty, in, bs,
+                                   out, sa, part, acc);
+            else
+                hipLaunchKernelGGL((k_step3d<T, CX, EQ, 1, false>), dim3(n_blocks), block, smem, s, p, ty, in, bs,
+                                   out, sa, part, acc);
+            return hipGetLastError();
+        } else {
+            return hipErrorInvalidValue;
+        }
+    }
+    if (stage == 0)
         hipLaunchKernelGGL((k_step3d<T, CX, EQ, 0, true>), dim3(n_blocks), block, smem, s, p, ty, in, bs, out, sa,
                            part, acc);
-    else if (stage == 0)
-        hipLaunchKernelGGL((k_step3d<T, CX, EQ, 0, false>), dim3(n_blocks), block, smem, s, p, ty, in, bs, out, sa,
-                           part, acc);
-    else if (rw)
-        hipLaunchKernelGGL((k_step3d<T, CX, EQ, 1, true>), dim3(n_blocks), block, smem, s, p, ty, in, bs, out, sa,
-                           part, acc);
     else
-        hipLaunchKernelGGL((k_step3d<T, CX, EQ, 1, false>), dim3(n_blocks), block, smem, s, p, ty, in, bs, out, sa,
+        hipLaunchKernelGGL((k_step3d<T, CX, EQ, 1, true>), dim3(n_blocks), block, smem, s, p, ty, in, bs, out, sa,
                            part, acc);
     return hipGetLastError();
 }
