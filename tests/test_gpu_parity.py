@@ -194,7 +194,8 @@ def test_1d_large_instance_parity(she, scheme):
 
 CASES_2D = [((64, 48), W.EM, W.HEAT), ((64, 48), W.HEUN, W.HEAT), ((32, 32), W.EM, W.SPECIES),
             ((128, 20), W.HEUN, W.SPECIES), ((512, 6), W.EM, W.HEAT), ((512, 5), W.HEUN, W.HEAT),
-            ((16, 16), W.HEUN, W.HEAT), ((1024, 3), W.EM, W.HEAT), ((8, 40), W.EM, W.HEAT)]
+            ((16, 16), W.HEUN, W.HEAT), ((1024, 3), W.EM, W.HEAT), ((8, 40), W.EM, W.HEAT),
+            ((256, 12), W.HEUN, W.SPECIES)]
 
 
 @pytest.mark.parametrize("precision,scheme", [(0, W.EM), (0, W.HEUN), (1, W.HEUN)])
@@ -891,8 +892,10 @@ def test_nd_freeze_beside_healthy_instances(she, n, scheme):
 
 
 @pytest.mark.parametrize("n,scheme", [((32, 24), W.EM), ((32, 24), W.HEUN), ((16, 8, 6), W.EM),
-                                      ((16, 8, 6), W.HEUN), ((256, 4, 3), W.EM), ((256, 4, 3), W.HEUN)],
-                         ids=["2d-fe", "2d-pc", "3d-fe", "3d-pc", "3d-fe-row-per-wave", "3d-pc-row-per-wave"])
+                                      ((16, 8, 6), W.HEUN), ((256, 8), W.EM), ((256, 4, 3), W.EM),
+                                      ((256, 4, 3), W.HEUN)],
+                         ids=["2d-fe", "2d-pc", "3d-fe", "3d-pc", "2d-fe-row-per-wave", "3d-fe-row-per-wave",
+                              "3d-pc-row-per-wave"])
 def test_nd_clamp_count_matches_oracle(she, n, scheme):
     """Dean-Kawasaki at a low density (u0 = 2 per cell, eps = 1/dV = 1) has
     negative face means: every face and stage that meets one is clamped and
