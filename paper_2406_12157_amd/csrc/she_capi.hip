@@ -1167,13 +1167,16 @@ static hipError_t nd_enqueue(she_handle *h, hipStream_t s, const StepArg &sa, in
                               src, dst, sa, h->d_part, h->d_acc);
     }
     if (e != hipSuccess || !may_sample) return e;
-    e = launch_reduce_parts(h->n_inst, s, sa, h->d_part, two ? h->nparts2 : h->nparts,
-                            1.0 / static_cast<double>(h->cells), h->batch_len, h->d_acc);
-    if (e != hipSuccess || !(h->mask & SHE_STAT_SK)) return e;
+    const SpatialParts sp{h->d_part, h->d_acc, 1.0 / static_cast<double>(h->cells), two ? h->nparts2 : h->nparts,
+                          h->batch_len};
+    // with S(k), the first column-transform block of each instance does the
+    // spatial reduction (one launch fewer per sample)
+    if (!(h->mask & SHE_STAT_SK))
+        return launch_reduce_parts(h->n_inst, s, sa, sp.part, sp.nparts, sp.inv_cells, sp.batch_len, sp.acc);
     const BatchSk bk{h->d_sksnap, h->d_skwm, h->d_skwm2, h->d_skmodes, h->d_ip, static_cast<double>(h->cells),
                      h->d_sksnap ? h->batch_len : 0, 0};
     return launch_sk2d(h->prec, s, sa, h->n_inst, h->pnd.nx, h->pnd.ny, h->d_ip, dst, h->d_half, h->d_twx, h->d_twy,
-                       h->d_shells, h->d_skpart, h->nbins, h->d_sksum, h->d_acc, bk, fused);
+                       h->d_shells, h->d_skpart, h->nbins, h->d_sksum, h->d_acc, bk, fused, sp);
 }
 
 // Whether completed step t samples.

@@ -80,6 +80,51 @@ __host__ __device__ inline void fold_spatial(InstAcc &q, int32_t len)
     q.n_batches += 1;
 }
 
+// Per-instance reduction of the FP64 spatial partials of a sample launch:
+// the partials of instance inst summed in a fixed order by one wave (lane
+// l adds pairs l, l + 64, ..., then a butterfly over the wave), then lane 0
+// updates the sums (or marks the instance non-finite) and folds a completed
+// batch.  Run by k_reduce_parts, and on 2D batches with S(k) by the first
+// column-transform block of each instance.
+struct SpatialParts {
+    const double *part;  // [n_inst][nparts][2]
+    InstAcc *acc;
+    double inv_cells;
+    int32_t nparts;
+    int32_t batch_len;
+};
+
+__device__ __forceinline__ void reduce_spatial_wave(const SpatialParts &sp, int inst, int lane)
+{
+    if (sp.acc[inst].nonfinite) return;
+    const double *pp = sp.part + 2 * static_cast<int64_t>(inst) * sp.nparts;
+    double a = 0.0, b = 0.0;
+    for (int i = lane; i < sp.nparts; i += 64) {
+        a += pp[2 * i];
+        b += pp[2 * i + 1];
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        a += __shfl_xor(a, off, 64);
+        b += __shfl_xor(b, off, 64);
+    }
+    if (lane == 0) {
+        if (!isfinite(a) || !isfinite(b)) {
+            sp.acc[inst].nonfinite = 1;
+            return;
+        }
+        a *= sp.inv_cells;
+        b *= sp.inv_cells;
+        InstAcc q = sp.acc[inst];
+        q.sp_mean += a;
+        q.sp_sq += b;
+        q.sp_var += b - a * a;
+        q.n_samples += 1;
+        // a sample that completes a batch folds it
+        if (sp.batch_len > 0 && q.n_samples % sp.batch_len == 0) fold_spatial(q, sp.batch_len);
+        sp.acc[inst] = q;
+    }
+}
+
 // Batch-means arrays of a 1D batch (device; null when not kept).  cell:
 // [6][total_cells] = snapshots of s1 and s2 at the end of the last folded
 // batch, Welford (mean, M2) of the batch means of dU, of the batch
@@ -330,7 +375,8 @@ inline int half_tiles(int nx, int ltc) { return (nx / 2 + 1 + (1 << ltc) - 1) >>
 // the state type.
 hipError_t launch_sk2d(int prec, hipStream_t s, const StepArg &st, int n_inst, int nx, int ny, const InstND *ip,
                        const void *field, void *half, const void *twx, const void *twy, const uint16_t *shells,
-                       double *part, int nbins, double *sums, const InstAcc *acc, const BatchSk &bk, bool rows_done);
+                       double *part, int nbins, double *sums, InstAcc *acc, const BatchSk &bk, bool rows_done,
+                       const SpatialParts &sp);
 // shells[kx (nbins + 1) + b], kx = 0..nx/2, b = 0..nbins: the first |ky| of
 // shell b in column kx (the range of |ky| in shell b is [first(b), first(b+1)))
 hipError_t launch_shell_table(hipStream_t s, int nx, int ny, int nbins, uint16_t *shells);

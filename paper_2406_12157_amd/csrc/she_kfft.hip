@@ -317,9 +317,14 @@ __device__ __forceinline__ void bin_column(double (&acc)[NBJ], const double *pre
 template <typename T, int LGY, int NBJ>
 __global__ void __launch_bounds__(256, (sizeof(T) == 4 && LGY <= 9) ? 4 : 2)
     k_sk_colt(StepArg sarg, const cplx<T> *__restrict__ half, int nx, int nkb, int iters, int rs, int nbins,
-              const cplx<T> *__restrict__ twy, const uint16_t *__restrict__ shells, double *__restrict__ part)
+              const cplx<T> *__restrict__ twy, const uint16_t *__restrict__ shells, double *__restrict__ part,
+              SpatialParts sp)
 {
     SHE_SAMPLE_GATE();
+    // the sample's spatial reduction of this instance, when it rides along
+    // (one wave of the instance's first block; the shell reduction that
+    // follows reads what it wrote)
+    if (sp.part && blockIdx.x == 0 && threadIdx.x < 64) reduce_spatial_wave(sp, blockIdx.y, threadIdx.x);
     using F = WaveFft<LGY>;
     constexpr int n = F::n, P = F::P, S = F::S, hy = n / 2;
     constexpr int LR = PassRadix<LGY>::LR, R = 1 << LR;
@@ -579,7 +584,7 @@ void rows_t(hipStream_t s, const StepArg &sa, int n_inst, int ny, const InstND *
 
 template <typename T, int LGY>
 bool cols_t(hipStream_t s, const StepArg &sa, int n_inst, int nx, int nkb, int nbins, const void *half, const void *twy,
-            const uint16_t *shells, double *part, int groups, int iters)
+            const uint16_t *shells, double *part, int groups, int iters, const SpatialParts &sp)
 {
     size_t rs = 0;
     const size_t smem = colt_lds<T, LGY>(nbins, &rs);
@@ -588,11 +593,11 @@ bool cols_t(hipStream_t s, const StepArg &sa, int n_inst, int nx, int nkb, int n
     if (nbins <= 64 * (kMaxBinIters / 2))
         hipLaunchKernelGGL((k_sk_colt<T, LGY, kMaxBinIters / 2>), grid, block, smem, s, sa,
                            static_cast<const cplx<T> *>(half), nx, nkb, iters, static_cast<int>(rs), nbins,
-                           static_cast<const cplx<T> *>(twy), shells, part);
+                           static_cast<const cplx<T> *>(twy), shells, part, sp);
     else
         hipLaunchKernelGGL((k_sk_colt<T, LGY, kMaxBinIters>), grid, block, smem, s, sa,
                            static_cast<const cplx<T> *>(half), nx, nkb, iters, static_cast<int>(rs), nbins,
-                           static_cast<const cplx<T> *>(twy), shells, part);
+                           static_cast<const cplx<T> *>(twy), shells, part, sp);
     return true;
 }
 
@@ -613,11 +618,12 @@ bool rows_dispatch(int lgx, hipStream_t s, const StepArg &sa, int n_inst, int ny
 
 template <typename T>
 bool cols_dispatch(int lgy, hipStream_t s, const StepArg &sa, int n_inst, int nx, int nkb, int nbins, const void *half,
-                   const void *twy, const uint16_t *shells, double *part, int groups, int iters)
+                   const void *twy, const uint16_t *shells, double *part, int groups, int iters,
+                   const SpatialParts &sp)
 {
 #define SHE_COLS(L)                                                                              \
     case L:                                                                                      \
-        return cols_t<T, L>(s, sa, n_inst, nx, nkb, nbins, half, twy, shells, part, groups, iters);
+        return cols_t<T, L>(s, sa, n_inst, nx, nkb, nbins, half, twy, shells, part, groups, iters, sp);
     switch (lgy) {
         SHE_COLS(1) SHE_COLS(2) SHE_COLS(3) SHE_COLS(4) SHE_COLS(5) SHE_COLS(6) SHE_COLS(7) SHE_COLS(8)
         SHE_COLS(9) SHE_COLS(10)
@@ -630,7 +636,8 @@ bool cols_dispatch(int lgy, hipStream_t s, const StepArg &sa, int n_inst, int nx
 
 hipError_t launch_sk2d(int prec, hipStream_t s, const StepArg &sa, int n_inst, int nx, int ny, const InstND *ip,
                        const void *field, void *half, const void *twx, const void *twy, const uint16_t *shells,
-                       double *part, int nbins, double *sums, const InstAcc *acc, const BatchSk &bk, bool rows_done)
+                       double *part, int nbins, double *sums, InstAcc *acc, const BatchSk &bk, bool rows_done,
+                       const SpatialParts &sp)
 {
     if (nbins > 64 * kMaxBinIters) return hipErrorInvalidValue;
     const int lgx = ilog2(nx), lgy = ilog2(ny);
@@ -639,10 +646,10 @@ hipError_t launch_sk2d(int prec, hipStream_t s, const StepArg &sa, int n_inst, i
     bool ok;
     if (prec == 0) {
         ok = (rows_done || rows_dispatch<float>(lgx, s, sa, n_inst, ny, ip, field, twx, half, ltc, nkb)) &&
-             cols_dispatch<float>(lgy, s, sa, n_inst, nx, nkb, nbins, half, twy, shells, part, groups, iters);
+             cols_dispatch<float>(lgy, s, sa, n_inst, nx, nkb, nbins, half, twy, shells, part, groups, iters, sp);
     } else {
         ok = (rows_done || rows_dispatch<double>(lgx, s, sa, n_inst, ny, ip, field, twx, half, ltc, nkb)) &&
-             cols_dispatch<double>(lgy, s, sa, n_inst, nx, nkb, nbins, half, twy, shells, part, groups, iters);
+             cols_dispatch<double>(lgy, s, sa, n_inst, nx, nkb, nbins, half, twy, shells, part, groups, iters, sp);
     }
     if (!ok) return hipErrorInvalidValue;
     const int64_t tot = static_cast<int64_t>(n_inst) * nbins;

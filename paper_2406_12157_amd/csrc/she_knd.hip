@@ -53,41 +53,13 @@ hipError_t launch_step3d(int prec, int cx, int eq, int stage, int ty, int n_bloc
 
 // Per-instance reduction of the sample partials, fixed order.
 __global__ void __launch_bounds__(64)
-    k_reduce_parts(StepArg sarg, const double *__restrict__ part, int32_t nparts, double inv_cells,
-                   int32_t batch_len, InstAcc *__restrict__ acc)
+    k_reduce_parts(StepArg sarg, SpatialParts sp)
 {
     int64_t step;
     int sample;
     resolve_step(sarg, step, sample);
     if (!sample) return;
-    const int inst = blockIdx.x;
-    if (acc[inst].nonfinite) return;
-    const double *pp = part + 2 * static_cast<int64_t>(inst) * nparts;
-    double a = 0.0, b = 0.0;
-    for (int i = threadIdx.x; i < nparts; i += 64) {
-        a += pp[2 * i];
-        b += pp[2 * i + 1];
-    }
-    for (int off = 32; off > 0; off >>= 1) {
-        a += __shfl_xor(a, off, 64);
-        b += __shfl_xor(b, off, 64);
-    }
-    if (threadIdx.x == 0) {
-        if (!isfinite(a) || !isfinite(b)) {
-            acc[inst].nonfinite = 1;
-            return;
-        }
-        a *= inv_cells;
-        b *= inv_cells;
-        InstAcc q = acc[inst];
-        q.sp_mean += a;
-        q.sp_sq += b;
-        q.sp_var += b - a * a;
-        q.n_samples += 1;
-        // a sample that completes a batch folds it
-        if (batch_len > 0 && q.n_samples % batch_len == 0) fold_spatial(q, batch_len);
-        acc[inst] = q;
-    }
+    reduce_spatial_wave(sp, blockIdx.x, threadIdx.x);
 }
 
 // ------------------------------------------------------------------ init / finalisation
@@ -153,7 +125,8 @@ __global__ void __launch_bounds__(256)
 hipError_t launch_reduce_parts(int n_inst, hipStream_t s, const StepArg &sa, const double *part, int32_t nparts,
                                double inv_cells, int32_t batch_len, InstAcc *acc)
 {
-    hipLaunchKernelGGL(k_reduce_parts, dim3(n_inst), dim3(64), 0, s, sa, part, nparts, inv_cells, batch_len, acc);
+    const SpatialParts sp{part, acc, inv_cells, nparts, batch_len};
+    hipLaunchKernelGGL(k_reduce_parts, dim3(n_inst), dim3(64), 0, s, sa, sp);
     return hipGetLastError();
 }
 
