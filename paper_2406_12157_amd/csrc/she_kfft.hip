@@ -472,8 +472,18 @@ __global__ void __launch_bounds__(256)
     const InstAcc q = acc[inst];
     if (q.nonfinite) return;
     const double *pp = part + static_cast<int64_t>(inst) * ngroups * nbins + b;
+    // in group order; four loads issued ahead of their adds
     double s = 0.0;
-    for (int g = 0; g < ngroups; ++g) s += pp[static_cast<int64_t>(g) * nbins];
+    int g = 0;
+    for (; g + 4 <= ngroups; g += 4) {
+        const double a0 = pp[static_cast<int64_t>(g) * nbins], a1 = pp[static_cast<int64_t>(g + 1) * nbins];
+        const double a2 = pp[static_cast<int64_t>(g + 2) * nbins], a3 = pp[static_cast<int64_t>(g + 3) * nbins];
+        s += a0;
+        s += a1;
+        s += a2;
+        s += a3;
+    }
+    for (; g < ngroups; ++g) s += pp[static_cast<int64_t>(g) * nbins];
     const double tot = sums[e] + s;
     sums[e] = tot;
     // The sample reduction ran first and folded the spatial sums of a batch
@@ -527,13 +537,16 @@ int tile_cols(int prec, int lgy)
 #undef SHE_TC
 }
 
-// tiles per column-transform block: about 2048 blocks in flight over the batch
+// Tiles per column-transform block: at least about 4096 blocks over the
+// batch (four resident per CU, so about four rounds).  Measured at
+// 512 x 512 x 256 (8448 tiles), us per sample: 1 tile per block 103.4, 2
+// 101.4, 3 102.0, 4 106.7, 5 107.6, 6 115.2, 8 118.8.
 int colt_iters(int prec, int nx, int ny, int n_inst)
 {
     const int tc = tile_cols(prec, ilog2(ny));
     const int64_t tiles = static_cast<int64_t>((nx / 2 + 1 + tc - 1) / tc) * n_inst;
     int it = 1;
-    while (it < 8 && tiles / (2 * it) >= 2048) it *= 2;
+    while (it < 8 && tiles / (2 * it) >= 4096) it *= 2;
     return it;
 }
 
