@@ -25,7 +25,10 @@
 //    lo(kx, b) the first |ky| in shell b: (2b-1)^2 <= 4(kx^2 + ky^2), exact in
 //    integers (a table built once per handle).  Only shells
 //    kx .. round(sqrt(kx^2 + (Ny/2)^2)) meet column kx.  The waves' shell sums
-//    are added in a fixed order into one partial per block.
+//    are added in a fixed order into one partial per block.  The first block
+//    of each instance also does the sample's spatial reduction (one wave, the
+//    same fixed-order sum as k_reduce_parts); k_bins_reduce, which follows,
+//    reads the sample counts it updates.
 // 3. k_bins_reduce: per instance and shell, the partials are added in a fixed
 //    order to the FP64 running sums.
 //
