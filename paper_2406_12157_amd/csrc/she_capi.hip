@@ -441,7 +441,7 @@ she_status validate(const she_config *cfg, she_handle *h)
 // workgroup) and are packed first-fit, largest first, into workgroups of
 // block / 64 waves and at most 64 KB of LDS.  Returns an error text, or null.
 static const char *pack_1d(const std::vector<Inst1D> &tab, int block, int32_t es, int mode,
-                           std::vector<Seg1D> &segs, int &n_blocks, size_t &smem)
+                           std::vector<Seg1D> &segs, int &n_blocks, size_t &smem, int cus)
 {
     const int W = block / 64;
     constexpr int kLdsCap = 64 * 1024;
@@ -477,6 +477,33 @@ static const char *pack_1d(const std::vector<Inst1D> &tab, int block, int32_t es
     }
     n_blocks = static_cast<int>(used_w.size());
     smem = static_cast<size_t>(*std::max_element(used_b.begin(), used_b.end()));
+    // Between one and two workgroups per CU: workgroup p and p + C (C CUs)
+    // are dispatched to the same CU, so the order pairs loads.  The heaviest
+    // workgroups (work ~ cells x stages per step) run alone, and the others
+    // go in pairs of a heavier with a lighter one.  Measured on the
+    // 1000-rod batch of log-uniform lengths (64..4096, FE and PC): 2.03-2.10
+    // against 2.16-2.17 us per step in packing order.
+    if (n_blocks > cus && n_blocks <= 2 * cus) {
+        std::vector<int64_t> wt(n_blocks, 0);
+        for (int b = 0; b < n_blocks; ++b)
+            for (int w = 0; w < W; ++w) {
+                const Seg1D &sg = segs[static_cast<size_t>(b) * W + w];
+                if (sg.inst >= 0 && sg.w0 == w) wt[b] += static_cast<int64_t>(tab[sg.inst].n) * (1 + tab[sg.inst].scheme);
+            }
+        std::vector<int> ord(n_blocks);
+        for (int b = 0; b < n_blocks; ++b) ord[b] = b;
+        std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) { return wt[a] > wt[b]; });
+        const int pairs = n_blocks - cus, singles = cus - pairs;
+        std::vector<int> pos(n_blocks);
+        for (int k = 0; k < singles; ++k) pos[pairs + k] = ord[k];        // alone on their CU
+        for (int k = 0; k < pairs; ++k) pos[k] = ord[singles + k];        // heavier of a pair
+        for (int k = 0; k < pairs; ++k) pos[cus + k] = ord[n_blocks - 1 - k];  // lighter partner
+        std::vector<Seg1D> moved(segs.size());
+        for (int p = 0; p < n_blocks; ++p)
+            for (int w = 0; w < W; ++w)
+                moved[static_cast<size_t>(p) * W + w] = segs[static_cast<size_t>(pos[p]) * W + w];
+        segs.swap(moved);
+    }
     return nullptr;
 }
 
@@ -645,7 +672,8 @@ static she_status plan_1d(she_handle *h, const she_config *cfg, Plan &plan)
             std::vector<Seg1D> sg;
             int nb = 0;
             size_t sm = 0;
-            if (!pack_1d(h->tab, 1024, static_cast<int32_t>(es), mode, sg, nb, sm) && nb <= device_cus())
+            const int cus = device_cus();
+            if (!pack_1d(h->tab, 1024, static_cast<int32_t>(es), mode, sg, nb, sm, cus) && nb <= cus)
                 block = 1024, maxg = 1;
         }
     } else {
@@ -661,7 +689,8 @@ static she_status plan_1d(she_handle *h, const she_config *cfg, Plan &plan)
     h->block1d = block;
     h->maxg = maxg;
     {
-        const char *why = pack_1d(h->tab, block, static_cast<int32_t>(es), mode, h->segs_host, h->blocks1d, h->smem1d);
+        const char *why =
+            pack_1d(h->tab, block, static_cast<int32_t>(es), mode, h->segs_host, h->blocks1d, h->smem1d, device_cus());
         if (why) return fail(nullptr, SHE_EUNSUPPORTED, why);
     }
 

@@ -117,6 +117,26 @@ def test_1d_ragged_batch_and_independence(she):
     np.testing.assert_array_equal(alone[0], got[2])
 
 
+def test_1d_many_workgroups_balanced_order(she):
+    # 400 rods of 64 threads each: more workgroups than CUs and at most two
+    # per CU, so the planner orders them to pair heavy with light ones on a
+    # CU.  The order changes time only: every rod matches the oracle, and
+    # rods run alone give the same bits.
+    rng = np.random.default_rng(11)
+    insts = []
+    for q in range(400):
+        n = int(rng.integers(60, 250))
+        bc = W.DIRICHLET if q % 2 == 0 else W.PERIODIC
+        scheme = W.HEUN if rng.random() < 0.5 else W.EM
+        insts.append(inst1d((n,), bc, scheme, W.HEAT, 0, realisation=q))
+    _, got, want = run_both(she, insts, 200, 0, block_threads=64)
+    for q in range(len(insts)):
+        assert max_rel(got[q], want[q]) <= 1e-5, q
+    for q in (0, 1, 57, 199, 398):
+        _, alone, _ = run_both(she, [insts[q]], 200, 0, block_threads=64)
+        np.testing.assert_array_equal(alone[0], got[q])
+
+
 def test_1d_launch_shape_invariance(she):
     # 64 threads: one instance per workgroup, up to two Philox blocks per
     # thread; 256, 512 and 1024 (the 64-VGPR kernel for plain FP32 batches):
