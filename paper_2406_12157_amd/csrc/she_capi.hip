@@ -781,15 +781,21 @@ static she_status plan_nd(she_handle *h, const she_config *cfg, Plan &plan)
     if (d0.dim == 2) {
         // Default march length.  FE: about 16384 row groups in flight, 1..8 rows
         // each (short marches keep more loads in flight; the halo row a chunk
-        // re-reads mostly hits the cache).  PC recomputes three rows per chunk,
-        // so it takes about 4096 groups of up to 32 rows.  Measured at
-        // 512 x 512 x 256: FE 0.1115 ms per step at 8 rows vs 0.1182 at 32; PC
-        // 0.1364 at 32 vs 0.1577 at 8.
+        // re-reads mostly hits the cache).  PC recomputes three rows per chunk
+        // and its kernel holds three waves per SIMD, so it takes as few groups
+        // as fill that once, 12 per CU, of up to 64 rows.  Measured at
+        // 512 x 512 x 256 (ms per step without statistics): 43 rows (3072
+        // groups, one round) 0.1222; 32 rows (4096) 0.1263; 64 rows 0.1238;
+        // 40 rows (3328, a short second round) 0.1422.
         int chunk = cfg->rows_per_block;
         const int64_t rows_all = static_cast<int64_t>(h->n_inst) * p.ny;
-        if (chunk <= 0)
-            chunk = d0.scheme == SHE_EM ? static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(8, rows_all / 16384)))
-                                        : static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(32, rows_all / 4096)));
+        if (chunk <= 0) {
+            const int64_t pc_groups = 12 * static_cast<int64_t>(device_cus());
+            chunk = d0.scheme == SHE_EM
+                        ? static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(8, rows_all / 16384)))
+                        : static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(64, (rows_all + pc_groups - 1) /
+                                                                                             pc_groups)));
+        }
         chunk = std::min(chunk, p.ny);
         p.chunk = chunk;
         const int nchunks = (p.ny + chunk - 1) / chunk;
