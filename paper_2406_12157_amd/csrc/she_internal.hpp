@@ -99,7 +99,22 @@ __device__ __forceinline__ void reduce_spatial_wave(const SpatialParts &sp, int 
     if (sp.acc[inst].nonfinite) return;
     const double *pp = sp.part + 2 * static_cast<int64_t>(inst) * sp.nparts;
     double a = 0.0, b = 0.0;
-    for (int i = lane; i < sp.nparts; i += 64) {
+    // pairs lane, lane + 64, ... in order; four pairs loaded ahead of their adds
+    int i = lane;
+    for (; i + 192 < sp.nparts; i += 256) {
+        double x[4], y[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            x[k] = pp[2 * (i + 64 * k)];
+            y[k] = pp[2 * (i + 64 * k) + 1];
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            a += x[k];
+            b += y[k];
+        }
+    }
+    for (; i < sp.nparts; i += 64) {
         a += pp[2 * i];
         b += pp[2 * i + 1];
     }
