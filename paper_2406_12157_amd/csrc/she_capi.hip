@@ -1353,7 +1353,16 @@ static she_status advance(she_handle *h, int64_t nsteps, bool sampling)
         return SHE_OK;
     }
     for (const int64_t end = h->steps + nsteps; h->steps < end;) {
-        she_status st = nd_direct(h, samp, end - h->steps >= 2);
+        // A pair of steps may not start with a sample step, so an odd distance
+        // to the next sample step inside the run is bridged by one single
+        // step first: the pairs that follow then end on the sample step, and
+        // the sample launch is a two-step one.
+        bool pair = end - h->steps >= 2;
+        if (pair && samp) {
+            const int64_t t = (std::max(h->steps, h->burn_in) / h->every + 1) * h->every;  // next sample step
+            if (t <= end && ((t - h->steps) & 1)) pair = false;
+        }
+        she_status st = nd_direct(h, samp, pair);
         if (st != SHE_OK) return st;
     }
     return SHE_OK;
