@@ -176,6 +176,46 @@ __device__ __forceinline__ void box_muller_scaled(uint32_t wa, uint32_t wb, doub
     zs = s * rc;
 }
 
+// The same pairs in the form a face whose amplitude is itself a square root
+// takes: the squared scaled radius r2 = -2 ln(u_a) s^2 and the unit factors
+// cos and sin of the angle, so that the face forms sqrt(x) rho = sqrt(x r2)
+// with one root (rc as for box_muller_scaled: -2 ln(2) s^2 in FP32, s in
+// FP64).
+__device__ __forceinline__ void box_muller_sq(uint32_t wa, uint32_t wb, float rc, float &r2, float &c, float &s)
+{
+    const float ua = unit_open_f32(wa);
+    const float ub = unit_angle_f32(wb);
+    r2 = __builtin_amdgcn_logf(ua) * rc;
+    c = __builtin_amdgcn_cosf(ub);
+    s = __builtin_amdgcn_sinf(ub);
+}
+
+__device__ __forceinline__ void box_muller_sq(uint32_t wa, uint32_t wb, double rc, double &r2, double &c,
+                                              double &s)
+{
+    const double ua = unit_open_f64(wa);
+    const double ub = unit_angle_f64(wb);
+    r2 = (-2.0 * log(ua)) * (rc * rc);
+    sincospi(2.0 * ub, &s, &c);
+}
+
+template <typename T>
+struct NormalsSq4 {
+    T t[4];   // cos, sin of pair 0; cos, sin of pair 1
+    T r2[2];  // squared scaled radius of each pair
+};
+
+template <typename T>
+__device__ __forceinline__ NormalsSq4<T> block_normals_sq(uint32_t block, uint32_t step_lo, uint32_t w2,
+                                                          uint32_t realisation, PhiloxKey key, T rc)
+{
+    const Words4 x = philox4x32_10(block, step_lo, w2, realisation, key);
+    NormalsSq4<T> n;
+    box_muller_sq(x.w[0], x.w[1], rc, n.r2[0], n.t[0], n.t[1]);
+    box_muller_sq(x.w[2], x.w[3], rc, n.r2[1], n.t[2], n.t[3]);
+    return n;
+}
+
 // Square root of a noise amplitude: FP32 takes the native v_sqrt_f32 (about
 // one ulp, one instruction; the library form adds a denormal-scaling and
 // rounding-correction sequence), FP64 the correctly rounded library sqrt.

@@ -72,12 +72,27 @@ __device__ __forceinline__ double clamp_nonneg(double x)
     return fmax(x, 0.0);
 }
 
-// Flux through a face between cells with values lo (low side) and hi, for a
-// pre-scaled number zs (see above), in noise mode NZ (0 instantaneous,
+// The numbers of one face.  Most forms carry the scaled normal zs.  The
+// Dean-Kawasaki face with instantaneous noise (SQ) carries instead the unit
+// factor t (cosine or sine of its Box-Muller angle) and the squared scaled
+// radius r2 of its pair: its amplitude sqrt(max(s, 0)) rho is then formed as
+// sqrt(max(s, 0) r2), one root per face and none for the radius.
+template <typename T, bool SQ>
+struct FaceNoise {
+    T zs;
+};
+
+template <typename T>
+struct FaceNoise<T, true> {
+    T t, r2;
+};
+
+// Flux through a face between cells with values lo (low side) and hi, for
+// its numbers z (see above), in noise mode NZ (0 instantaneous,
 // 1 deterministic face value, 2 off); neg tells whether the Dean-Kawasaki
 // face density was negative and clamped to zero.
-template <typename T, int EQ, int NZ>
-__device__ __forceinline__ T face_flux(T lo, T hi, T zs, bool &neg)
+template <typename T, int EQ, int NZ, bool SQ>
+__device__ __forceinline__ T face_flux(T lo, T hi, FaceNoise<T, SQ> z, bool &neg)
 {
     // The face flux divided by r: the difference hi - lo plus the noise term,
     // whose scale carries 1/r (the caller multiplies the divergence by r once
@@ -88,27 +103,28 @@ __device__ __forceinline__ T face_flux(T lo, T hi, T zs, bool &neg)
     neg = false;
     if constexpr (NZ == 0) {
         const T s = lo + hi;
-        T a;
         if constexpr (EQ == 0) {
-            a = s;
+            return fma(s, z.zs, d);
         } else {
             // the root of max(s, 0): the compare only counts the clamp
             neg = s < T(0);
-            a = amp_sqrt(clamp_nonneg(s));
+            if constexpr (SQ)
+                return fma(amp_sqrt(clamp_nonneg(s) * z.r2), z.t, d);
+            else
+                return fma(amp_sqrt(clamp_nonneg(s)), z.zs, d);
         }
-        return fma(a, zs, d);
     } else if constexpr (NZ == 1) {
-        return d + zs;
+        return d + z.zs;
     } else {
         return d;
     }
 }
 
-template <typename T, int EQ, int NZ>
-__device__ __forceinline__ T face_flux(T lo, T hi, T zs, uint32_t &clamps)
+template <typename T, int EQ, int NZ, bool SQ>
+__device__ __forceinline__ T face_flux(T lo, T hi, FaceNoise<T, SQ> z, uint32_t &clamps)
 {
     bool neg;
-    const T f = face_flux<T, EQ, NZ>(lo, hi, zs, neg);
+    const T f = face_flux<T, EQ, NZ>(lo, hi, z, neg);
     clamps += neg ? 1u : 0u;
     return f;
 }
@@ -156,30 +172,37 @@ __device__ __forceinline__ void copy_row(T (&d)[CX], const T (&s)[CX])
     for (int j = 0; j < CX; ++j) d[j] = s[j];
 }
 
-// Scaled numbers of one lane's CX faces of direction-row `drow` (= row*dim + e).
-template <typename T, int CX, int NZ>
-__device__ __forceinline__ void row_normals(T (&z)[CX], uint32_t drow, uint32_t nq, uint32_t q0,
+// Numbers of one lane's CX faces of direction-row `drow` (= row*dim + e).
+template <typename T, int CX, int NZ, bool SQ>
+__device__ __forceinline__ void row_normals(FaceNoise<T, SQ> (&z)[CX], uint32_t drow, uint32_t nq, uint32_t q0,
                                             uint32_t slo, uint32_t w2, uint32_t real, PhiloxKey key, T rc)
 {
     if constexpr (NZ == 2) {
+        static_assert(!SQ, "no numbers in noise mode 2");
 #pragma unroll
-        for (int j = 0; j < CX; ++j) z[j] = T(0);
+        for (int j = 0; j < CX; ++j) z[j].zs = T(0);
         return;
     }
 #pragma unroll
     for (int c = 0; c < CX / 4; ++c) {
-        const Normals4<T> nz = block_normals_scaled<T>(drow * nq + q0 + c, slo, w2, real, key, rc);
+        if constexpr (SQ) {
+            const NormalsSq4<T> nz = block_normals_sq<T>(drow * nq + q0 + c, slo, w2, real, key, rc);
 #pragma unroll
-        for (int l = 0; l < 4; ++l) z[4 * c + l] = nz.z[l];
+            for (int l = 0; l < 4; ++l) z[4 * c + l] = FaceNoise<T, true>{nz.t[l], nz.r2[l >> 1]};
+        } else {
+            const Normals4<T> nz = block_normals_scaled<T>(drow * nq + q0 + c, slo, w2, real, key, rc);
+#pragma unroll
+            for (int l = 0; l < 4; ++l) z[4 * c + l].zs = nz.z[l];
+        }
     }
 }
 
 // x-fluxes of one row held by a group of LX lanes: Flo[j] is the flux through
 // the low face of the lane's cell j, Fhi the flux through the high face of its
 // last cell (= the next lane's Flo[0]).  count(neg) is called once per face.
-template <typename T, int CX, int EQ, int NZ, typename Count>
-__device__ __forceinline__ void row_xflux(const T (&v)[CX], const T (&z)[CX], T (&Flo)[CX], T &Fhi, int lx, int LX,
-                                          Count &&count)
+template <typename T, int CX, int EQ, int NZ, bool SQ, typename Count>
+__device__ __forceinline__ void row_xflux(const T (&v)[CX], const FaceNoise<T, SQ> (&z)[CX], T (&Flo)[CX], T &Fhi,
+                                          int lx, int LX, Count &&count)
 {
     const int lane = threadIdx.x & 63;
     const int gbase = lane - lx;
@@ -298,22 +321,28 @@ __global__ void __launch_bounds__(256)
     // move through the window without register copies.
     auto march = [&](auto nzc) __attribute__((always_inline)) {
         constexpr int NZ = decltype(nzc)::value;
-        auto normals = [&](T (&z)[CX], uint32_t dr) __attribute__((always_inline)) {
-            row_normals<T, CX, NZ>(z, dr, nq, q0, slo, w2, real, key, rc);
+        // Dean-Kawasaki faces with instantaneous noise take their amplitude
+        // with one root (FaceNoise), except in the PC march, which holds two
+        // rows of numbers across its iterations and keeps them one register
+        // per face there
+        constexpr bool SQ = EQ == 1 && NZ == 0 && SCHEME != 1;
+        using Z = FaceNoise<T, SQ>;
+        auto normals = [&](Z (&z)[CX], uint32_t dr) __attribute__((always_inline)) {
+            row_normals<T, CX, NZ, SQ>(z, dr, nq, q0, slo, w2, real, key, rc);
         };
         // Density clamps are counted once per face and stage, by the chunk that
         // owns the face (the low faces of its rows); faces a chunk recomputes
         // for its halo (own = false) are not counted.
-        auto flux = [&](T lo, T hi, T z, bool own = true) __attribute__((always_inline)) {
+        auto flux = [&](T lo, T hi, Z z, bool own = true) __attribute__((always_inline)) {
             uint32_t c = 0;
             const T f = face_flux<T, EQ, NZ>(lo, hi, z, c);
             clamps += own ? c : 0u;
             return f;
         };
-        auto xflux = [&](const T (&v)[CX], const T (&z)[CX], T (&fx)[CX], T &fxh,
+        auto xflux = [&](const T (&v)[CX], const Z (&z)[CX], T (&fx)[CX], T &fxh,
                          bool own = true) __attribute__((always_inline)) {
             uint32_t c = 0;
-            row_xflux<T, CX, EQ, NZ>(v, z, fx, fxh, lx, LX, [&](bool neg) { c += neg ? 1u : 0u; });
+            row_xflux<T, CX, EQ, NZ, SQ>(v, z, fx, fxh, lx, LX, [&](bool neg) { c += neg ? 1u : 0u; });
             clamps += own ? c : 0u;
         };
         auto emit = [&](const T (&out)[CX], int y) __attribute__((always_inline)) {
@@ -383,7 +412,8 @@ __global__ void __launch_bounds__(256)
             if ((ch & 1) == 0) {
                 // upward march: the low-y flux of row y is carried from row y-1
                 {
-                    T tp[CX], z[CX];
+                    T tp[CX];
+                    Z z[CX];
                     load_row<T, CX>(rowp(y0 - 1), tp);
                     load_row<T, CX>(rowp(y0), ra);
                     load_row<T, CX>(rowp(y0 + 1), rb);
@@ -396,7 +426,8 @@ __global__ void __launch_bounds__(256)
                         int i) __attribute__((always_inline)) {
                     const int y = y0 + i;
                     if (y + 2 <= y1) load_row<T, CX>(rowp(y + 2), tq);
-                    T z[CX], fx[CX], fxh, out[CX];
+                    Z z[CX];
+                    T fx[CX], fxh, out[CX];
                     normals(z, drow(y + 1, 1));
 #pragma unroll
                     for (int j = 0; j < CX; ++j) fhi[j] = flux(tc[j], tn[j], z[j], y + 1 < y1);
@@ -412,7 +443,8 @@ __global__ void __launch_bounds__(256)
                 // read of its rows can hit the cache.  The high-y flux of row y is
                 // carried from row y+1; every face gets the same value either way.
                 {
-                    T tu[CX], z[CX];
+                    T tu[CX];
+                    Z z[CX];
                     load_row<T, CX>(rowp(y1), tu);
                     load_row<T, CX>(rowp(y1 - 1), ra);
                     load_row<T, CX>(rowp(y1 - 2), rb);
@@ -425,7 +457,8 @@ __global__ void __launch_bounds__(256)
                         int i) __attribute__((always_inline)) {
                     const int y = y1 - 1 - i;
                     if (y - 2 >= y0 - 1) load_row<T, CX>(rowp(y - 2), tq);
-                    T z[CX], fx[CX], fxh, out[CX];
+                    Z z[CX];
+                    T fx[CX], fxh, out[CX];
                     normals(z, drow(y, 1));
 #pragma unroll
                     for (int j = 0; j < CX; ++j) flo[j] = flux(tn[j], tc[j], z[j]);
@@ -446,13 +479,14 @@ __global__ void __launch_bounds__(256)
             // step-n low-y fluxes of rows k, k+1; fcm, fcc: the step-(n+1)
             // low-y fluxes of U1 rows k-1, k.  Each chunk recomputes the U1
             // rows on both sides of it.
-            auto normals1 = [&](T (&z)[CX], uint32_t dr) __attribute__((always_inline)) {
-                row_normals<T, CX, NZ>(z, dr, nq, q0, slo1, w21, real, key, rc);
+            auto normals1 = [&](Z (&z)[CX], uint32_t dr) __attribute__((always_inline)) {
+                row_normals<T, CX, NZ, SQ>(z, dr, nq, q0, slo1, w21, real, key, rc);
             };
             T ta[CX], tb[CX], tcc[CX], sa_[CX], sb_[CX], pa[CX], pb[CX], ma[CX], mb[CX];
             const int k0 = y0 - 1;
             {
-                T tp[CX], z[CX];
+                T tp[CX];
+                Z z[CX];
                 load_row<T, CX>(rowp(k0 - 1), tp);
                 load_row<T, CX>(rowp(k0), ta);
                 load_row<T, CX>(rowp(k0 + 1), tb);
@@ -465,7 +499,8 @@ __global__ void __launch_bounds__(256)
                            int i) __attribute__((always_inline)) {
                 const int k = k0 + i;
                 load_row<T, CX>(rowp(k + 2), tq);
-                T z[CX], fx[CX], fxh;
+                Z z[CX];
+                T fx[CX], fxh;
                 normals(z, drow(k + 1, 1));
 #pragma unroll
                 for (int j = 0; j < CX; ++j) fpn[j] = flux(tc[j], tn[j], z[j], k + 1 < y1);
@@ -508,8 +543,8 @@ __global__ void __launch_bounds__(256)
             // zyc, zyn the y numbers of rows k, k+1; zxm, zxc the x numbers of
             // rows k-1, k; fpc, fpn the predictor low-y fluxes of rows k, k+1;
             // fcm, fcc the corrector low-y fluxes of rows k-1, k.
-            T ta[CX], tb[CX], tcc[CX], td[CX], sa_[CX], sb_[CX], ya[CX], yb[CX], xa[CX], xb[CX], pa[CX], pb[CX],
-                ma[CX], mb[CX];
+            T ta[CX], tb[CX], tcc[CX], td[CX], sa_[CX], sb_[CX], pa[CX], pb[CX], ma[CX], mb[CX];
+            Z ya[CX], yb[CX], xa[CX], xb[CX];
             const int k0 = y0 - 1;
             load_row<T, CX>(rowp(k0 - 1), ta);
             load_row<T, CX>(rowp(k0), tb);
@@ -518,7 +553,7 @@ __global__ void __launch_bounds__(256)
 #pragma unroll
             for (int j = 0; j < CX; ++j) pa[j] = flux(ta[j], tb[j], ya[j], false);
             auto row = [&](const T (&tm)[CX], const T (&tc)[CX], const T (&tn)[CX], T (&tq)[CX], const T (&sc)[CX],
-                           T (&sn)[CX], const T (&zyc)[CX], T (&zyn)[CX], const T (&zxm)[CX], T (&zxc)[CX],
+                           T (&sn)[CX], const Z (&zyc)[CX], Z (&zyn)[CX], const Z (&zxm)[CX], Z (&zxc)[CX],
                            const T (&fpc)[CX], T (&fpn)[CX], const T (&fcm)[CX], T (&fcc)[CX],
                            int i) __attribute__((always_inline)) {
                 const int k = k0 + i;
@@ -650,15 +685,19 @@ __global__ void __launch_bounds__(256)
     // mode is fixed per copy.
     auto march = [&](auto nzc) __attribute__((always_inline)) {
         constexpr int NZ = decltype(nzc)::value;
-        auto normals = [&](T (&z)[CX], uint32_t dr) __attribute__((always_inline)) {
-            row_normals<T, CX, NZ>(z, dr, nq, q0, slo, w2, real, key, rc);
+        // Dean-Kawasaki faces with instantaneous noise take their amplitude
+        // with one root (FaceNoise)
+        constexpr bool SQ = EQ == 1 && NZ == 0;
+        using Z = FaceNoise<T, SQ>;
+        auto normals = [&](Z (&z)[CX], uint32_t dr) __attribute__((always_inline)) {
+            row_normals<T, CX, NZ, SQ>(z, dr, nq, q0, slo, w2, real, key, rc);
         };
         // Each face's clamp is counted once: x- and low y-faces by the row
         // they belong to, z-faces by the chunk below them (its planes' high
         // z-faces, the last one included; so not the low z-faces of a chunk's
         // first plane), and not the high y-faces a tile's top row recomputes
         // (own = false, in a branch only that row takes).
-        auto flux = [&](T lo, T hi, T z, bool own = true) __attribute__((always_inline)) {
+        auto flux = [&](T lo, T hi, Z z, bool own = true) __attribute__((always_inline)) {
             bool neg;
             const T f = face_flux<T, EQ, NZ>(lo, hi, z, neg);
             if constexpr (EQ == 1 && NZ == 0) {
@@ -671,7 +710,8 @@ __global__ void __launch_bounds__(256)
         };
         T ra[CX], rb[CX], rq[CX], fa[CX], fb[CX];
         {
-            T tp[CX], z[CX];
+            T tp[CX];
+            Z z[CX];
             load_row<T, CX>(S + rowp(y, z0 - 1), tp);
             load_row<T, CX>(S + rowp(y, z0), ra);
             load_row<T, CX>(S + rowp(y, z0 + 1), rb);
@@ -689,14 +729,14 @@ __global__ void __launch_bounds__(256)
                          int zi) __attribute__((always_inline)) {
             const int buf = zi & 1;
             load_row<T, CX>(S + rowp(y, zi + 2), tq);
-            T z[CX];
+            Z z[CX];
             normals(z, drow(y, zi + 1, 2));
 #pragma unroll
             for (int j = 0; j < CX; ++j) fzhi[j] = flux(tc[j], tn[j], z[j]);
 
             T fxlo[CX], fxhi;
             normals(z, drow(y, zi, 0));
-            row_xflux<T, CX, EQ, NZ>(tc, z, fxlo, fxhi, lx, LX, count);
+            row_xflux<T, CX, EQ, NZ, SQ>(tc, z, fxlo, fxhi, lx, LX, count);
 
             T ylo[CX], fylo[CX];
             normals(z, drow(y, zi, 1));
