@@ -1099,3 +1099,30 @@ def test_sample_launch_row_transforms(she, shape, precision, rpb):
         assert max_rel(gb["sk"][ok], st.structure_factor()[ok]) < tol
     a.close()
     b.close()
+
+
+def test_runs_from_odd_phases_pair_onto_sample_steps(she):
+    """A run that starts an odd number of steps before a sample step takes
+    one single step first, so that the two-step launches which follow end on
+    the sample step (its rows transformed in the step kernel).  Runs of every
+    length from every phase give the fields, the spatial moments and S(k) of
+    one step per launch: fields and S(k) bit for bit, the spatial moments to
+    rounding (the two-step march may group its rows into other partial sums;
+    512-cell rows, sampling every 10 steps from step 3 on)."""
+    insts = [inst2d((512, 16), W.EM, W.HEAT, realisation=q) for q in range(2)]
+    kw = dict(precision=0, burn_in=3, sample_every=10, stats=she.STAT_SPATIAL | she.STAT_SK)
+    a = she.Handle([gpu_instance(she, i) for i in insts], tuning_flags=she.TUNE_SINGLE_STEP, **kw)
+    b = she.Handle([gpu_instance(she, i) for i in insts], **kw)
+    for k in (5, 7, 1, 14, 3, 20, 9, 2, 11):
+        a.run(k)
+        b.run(k)
+    assert a.steps == b.steps == 72
+    for q in range(2):
+        np.testing.assert_array_equal(a.read_field(q), b.read_field(q))
+        ga, gb = a.stats(q, sk=True), b.stats(q, sk=True)
+        assert ga["n_samples"] == gb["n_samples"] == 7
+        np.testing.assert_array_equal(ga["sk"], gb["sk"])
+        for key in ("var", "mean"):
+            np.testing.assert_allclose(ga[key], gb[key], rtol=1e-13)
+    a.close()
+    b.close()
