@@ -322,10 +322,8 @@ __global__ void __launch_bounds__(256)
     auto march = [&](auto nzc) __attribute__((always_inline)) {
         constexpr int NZ = decltype(nzc)::value;
         // Dean-Kawasaki faces with instantaneous noise take their amplitude
-        // with one root (FaceNoise), except in the PC march, which holds two
-        // rows of numbers across its iterations and keeps them one register
-        // per face there
-        constexpr bool SQ = EQ == 1 && NZ == 0 && SCHEME != 1;
+        // with one root (FaceNoise)
+        constexpr bool SQ = EQ == 1 && NZ == 0;
         using Z = FaceNoise<T, SQ>;
         auto normals = [&](Z (&z)[CX], uint32_t dr) __attribute__((always_inline)) {
             row_normals<T, CX, NZ, SQ>(z, dr, nq, q0, slo, w2, real, key, rc);
