@@ -380,6 +380,16 @@ def add_copy_reference(roof, gbs):
 
 # ---------------------------------------------------------------- other workloads
 
+def checked_leg(fn, *args):
+    """Runs a leg that follows the timed region (error check, CPU baseline); a
+    leg that raises is reported in the line, with its message, instead of
+    ending the run before the line is printed."""
+    try:
+        return fn(*args)
+    except Exception as e:  # noqa: BLE001 - reported, not swallowed
+        return {"failed": "%s: %s" % (type(e).__name__, e)}
+
+
 def other_error_start(she, name, cfg, stats):
     """Creates the error leg's handles of c1, c2, c4 or c5, reads the initial
     fields it checks and enqueues their runs; other_error finishes the leg.
@@ -484,7 +494,7 @@ def other_workload(args, torch, she, W):
                       "sample_every": cfg["sample_every"], "stats_mask": int(stats), "parallelism": "single GPU"},
            "roofline": roof}
     if not args.no_error:
-        out["error"] = other_error(name, cfg, leg)
+        out["error"] = checked_leg(other_error, name, cfg, leg)
     print(json.dumps(out), flush=True)
 
 
@@ -568,9 +578,9 @@ def main():
                         "kernel_ms": pkms, "form": "1 realisation, one kernel launch per step, no graph"}
         out["batched_over_plain"] = value / out["plain"]["value"]
     if not args.no_error:
-        out["error"] = c3_error(err_cfg, leg)
+        out["error"] = checked_leg(c3_error, err_cfg, leg)
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(cfg, args.cpu_seconds)
+        out["cpu_baseline"] = checked_leg(cpu_baseline, cfg, args.cpu_seconds)
     if args.copy_calibration:
         src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)
