@@ -109,11 +109,12 @@ def timed_region(torch, h, steps, every):
     the step kernel inside them.  Each sampling period's back-to-back
     non-sample steps, an even number of them (2D FE takes two steps per
     launch), are one call bracketed by events on the library's stream (torch's
-    current stream).  The two steps that end on the sample step follow
-    unbracketed as one call (the sample launch is then a two-step one), after
-    a single step when the distance to the sample step is odd.  Steps past
-    the last sample step of the region go bracketed in pairs, and a last odd
-    one alone.  Returns (wall seconds, kernel ms per step, steps timed)."""
+    current stream).  The pair of steps that holds the sample step follows
+    unbracketed as one call: the pair that ends on it when the distance to it
+    is even, else the pair that starts with it (a two-step launch may sample
+    either of its steps).  Steps past the last sample step of the region go
+    bracketed in pairs, and a last odd one alone.  Returns (wall seconds,
+    kernel ms per step, steps timed)."""
     ev = []
 
     def bracketed(k):
@@ -139,16 +140,12 @@ def timed_region(torch, h, steps, every):
                 h.run(left - plain)
             done += left
             continue
-        plain = max(0, d - 2)
-        plain -= plain % 2
+        plain = d - 2 if d % 2 == 0 else d - 1
+        tail = min(2, left - plain)
         if plain > 0:
             bracketed(plain)
-        if d - plain == 3:
-            h.run(1)
-            h.run(2)
-        else:
-            h.run(d - plain)
-        done += d
+        h.run(tail)
+        done += plain + tail
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     n = sum(k for _, _, k in ev)

@@ -1220,13 +1220,23 @@ static bool samples_at(const she_handle *h, bool samp, int64_t t)
     return samp && t > h->burn_in && t % h->every == 0;
 }
 
-// One direct step, or two in one launch when `pair` allows it and the first
-// of them does not sample (its field never reaches memory).
+// Whether a two-step launch can sample its first step: the intermediate
+// field never reaches memory, so its statistics are taken in the kernel as
+// its rows are formed, which S(k) allows only with the row transforms there.
+static bool first_step_samples_ok(const she_handle *h)
+{
+    return !(h->mask & SHE_STAT_SK) || h->sk_fused;
+}
+
+// One direct step, or two in one launch when `pair` allows it and at most
+// one of them samples (the first only where first_step_samples_ok).  The
+// launch's sample flag: 1 its last step samples, 2 its first, 0 none.
 static she_status nd_direct(she_handle *h, bool samp, bool pair = false)
 {
-    const bool two = pair && h->two_step && !samples_at(h, samp, h->steps + 1);
+    const bool s1 = samples_at(h, samp, h->steps + 1), s2 = samples_at(h, samp, h->steps + 2);
+    const bool two = pair && h->two_step && !(s1 && (s2 || !first_step_samples_ok(h)));
     const int64_t t = h->steps + (two ? 2 : 1);
-    const int sample = samples_at(h, samp, t);
+    const int sample = two ? (s2 ? 1 : (s1 ? 2 : 0)) : (s1 ? 1 : 0);
     const StepArg sa{h->steps, nullptr, h->burn_in, h->every, sample};
     SHE_HIP(h, nd_enqueue(h, h->stream, sa, h->cur, sample != 0, two));
     h->cur ^= 1;
@@ -1353,12 +1363,12 @@ static she_status advance(she_handle *h, int64_t nsteps, bool sampling)
         return SHE_OK;
     }
     for (const int64_t end = h->steps + nsteps; h->steps < end;) {
-        // A pair of steps may not start with a sample step, so an odd distance
-        // to the next sample step inside the run is bridged by one single
-        // step first: the pairs that follow then end on the sample step, and
-        // the sample launch is a two-step one.
+        // Where a pair of steps may not start with a sample step, an odd
+        // distance to the next sample step inside the run is bridged by one
+        // single step first: the pairs that follow then end on the sample
+        // step, and the sample launch is a two-step one.
         bool pair = end - h->steps >= 2;
-        if (pair && samp) {
+        if (pair && samp && !first_step_samples_ok(h)) {
             const int64_t t = (std::max(h->steps, h->burn_in) / h->every + 1) * h->every;  // next sample step
             if (t <= end && ((t - h->steps) & 1)) pair = false;
         }

@@ -343,9 +343,10 @@ __global__ void __launch_bounds__(256)
             row_xflux<T, CX, EQ, NZ, SQ>(v, z, fx, fxh, lx, LX, [&](bool neg) { c += neg ? 1u : 0u; });
             clamps += own ? c : 0u;
         };
-        auto emit = [&](const T (&out)[CX], int y) __attribute__((always_inline)) {
+        // The sampling of a finished row of the sampled field: its spatial
+        // moments and, on sample launches with S(k), its transform along x.
+        auto take = [&](const T (&out)[CX], int y) __attribute__((always_inline)) {
             if (sample) accumulate<T, CX>(out, u0d, sa, sb);
-            store_row<T, CX>(D + static_cast<int64_t>(y) * p.nx, out);
             if constexpr (SK) {
                 // the pair's complex row: the even row's dU goes to the real
                 // parts of the wave's region at once (the transpose), the odd
@@ -387,6 +388,10 @@ __global__ void __launch_bounds__(256)
                     wave_sync();  // the next pair's transpose overwrites the region
                 }
             }
+        };
+        auto emit = [&](const T (&out)[CX], int y) __attribute__((always_inline)) {
+            store_row<T, CX>(D + static_cast<int64_t>(y) * p.nx, out);
+            take(out, y);
         };
         const int rows = y1 - y0;
         if constexpr (SCHEME == 0) {
@@ -476,7 +481,10 @@ __global__ void __launch_bounds__(256)
             // k+1, tq receiving row k+2; sc, sn: U1 rows k-1, k; fpc, fpn: the
             // step-n low-y fluxes of rows k, k+1; fcm, fcc: the step-(n+1)
             // low-y fluxes of U1 rows k-1, k.  Each chunk recomputes the U1
-            // rows on both sides of it.
+            // rows on both sides of it.  A launch whose first step samples
+            // (sample == 2) takes the chunk's own U1 rows as they are formed
+            // and only stores U2.
+            const bool first = sample == 2;
             auto normals1 = [&](Z (&z)[CX], uint32_t dr) __attribute__((always_inline)) {
                 row_normals<T, CX, NZ, SQ>(z, dr, nq, q0, slo1, w21, real, key, rc);
             };
@@ -506,6 +514,7 @@ __global__ void __launch_bounds__(256)
                 xflux(tc, z, fx, fxh, k >= y0 && k < y1);
 #pragma unroll
                 for (int j = 0; j < CX; ++j) sn[j] = fma(r, xdiv<T, CX>(fx, fxh, j) + (fpn[j] - fpc[j]), tc[j]);
+                if (first && k >= y0 && k < y1) take(sn, k);
                 if (i >= 1) {
                     normals1(z, drow(k, 1));
 #pragma unroll
@@ -517,7 +526,10 @@ __global__ void __launch_bounds__(256)
                     T out[CX];
 #pragma unroll
                     for (int j = 0; j < CX; ++j) out[j] = fma(r, xdiv<T, CX>(fx, fxh, j) + (fcc[j] - fcm[j]), sc[j]);
-                    emit(out, k - 1);
+                    if (first)
+                        store_row<T, CX>(D + static_cast<int64_t>(k - 1) * p.nx, out);
+                    else
+                        emit(out, k - 1);
                 }
             };
             const int iters = rows + 2;  // k = y0-1 .. y1
