@@ -113,43 +113,47 @@ def timed_region(torch, h, steps, every):
     unbracketed as one call: the pair that ends on it when the distance to it
     is even, else the pair that starts with it (a two-step launch may sample
     either of its steps).  Steps past the last sample step of the region go
-    bracketed in pairs, and a last odd one alone.  Returns (wall seconds,
-    kernel ms per step, steps timed)."""
-    ev = []
-
-    def bracketed(k):
-        a = torch.cuda.Event(enable_timing=True)
-        b = torch.cuda.Event(enable_timing=True)
-        a.record()
-        h.run(k)
-        b.record()
-        ev.append((a, b, k))
-
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    done = 0
+    bracketed in pairs, and a last odd one alone.  The calls are planned and
+    their events created and recorded once before the region starts, so the
+    region holds no first-use cost of the event machinery.  Returns (wall
+    seconds, kernel ms per step, steps timed)."""
+    plan = []                # (steps, bracketed)
+    t, done = h.steps, 0
     while done < steps:
-        d = (every - h.steps % every) % every or every    # steps until the next sample step completes
+        d = (every - t % every) % every or every    # steps until the next sample step completes
         left = steps - done
         if left < d:
             # no sample step in what is left
             plain = left - left % 2
-            if plain > 0:
-                bracketed(plain)
-            if left > plain:
-                h.run(left - plain)
-            done += left
-            continue
-        plain = d - 2 if d % 2 == 0 else d - 1
-        tail = min(2, left - plain)
-        if plain > 0:
-            bracketed(plain)
-        h.run(tail)
-        done += plain + tail
+            calls = [(plain, True), (left - plain, False)]
+        else:
+            plain = d - 2 if d % 2 == 0 else d - 1
+            calls = [(plain, True), (min(2, left - plain), False)]
+        for k, br in calls:
+            if k > 0:
+                plan.append((k, br))
+                t += k
+                done += k
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) if br else None
+          for _, br in plan]
+    for e in ev:
+        if e:
+            e[0].record()
+            e[1].record()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for (k, br), e in zip(plan, ev):
+        if br:
+            e[0].record()
+            h.run(k)
+            e[1].record()
+        else:
+            h.run(k)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    n = sum(k for _, _, k in ev)
-    kms = sum(a.elapsed_time(b) for a, b, _ in ev) / max(1, n)
+    timed = [(e, k) for (k, br), e in zip(plan, ev) if br]
+    n = sum(k for _, k in timed)
+    kms = sum(e[0].elapsed_time(e[1]) for e, _ in timed) / max(1, n)
     return wall, kms, n
 
 
