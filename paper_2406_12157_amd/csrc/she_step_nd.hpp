@@ -49,7 +49,10 @@
 // region into the transform's input order) and stores both half spectra,
 // kx = 0..nx/2, as two rows of the column-tiled half spectrum.  This is the row
 // stage of the S(k) transform of the field the launch writes, done while the
-// rows are still in registers instead of reading the field back.
+// rows are still in registers instead of reading the field back.  A two-step
+// launch whose first step samples (kernel variant SCHEME 3) takes the
+// statistics and transforms of its intermediate rows instead, as the march
+// forms them: that field never reaches memory.
 #include <type_traits>
 
 #include "she_fft.hpp"
@@ -472,7 +475,7 @@ __global__ void __launch_bounds__(256)
                     emit(out, y);
                 });
             }
-        } else if constexpr (SCHEME == 2) {
+        } else if constexpr (SCHEME == 2 || SCHEME == 3) {
             // Two FE steps in one pass (steps n and n+1 of the counter): the
             // intermediate field U1 lives only in registers.  Iteration k forms
             // row k of U1 = FE(U0) and row k-1 of U2 = FE(U1), with the same
@@ -481,10 +484,11 @@ __global__ void __launch_bounds__(256)
             // k+1, tq receiving row k+2; sc, sn: U1 rows k-1, k; fpc, fpn: the
             // step-n low-y fluxes of rows k, k+1; fcm, fcc: the step-(n+1)
             // low-y fluxes of U1 rows k-1, k.  Each chunk recomputes the U1
-            // rows on both sides of it.  A launch whose first step samples
-            // (sample == 2) takes the chunk's own U1 rows as they are formed
-            // and only stores U2.
-            const bool first = sample == 2;
+            // rows on both sides of it.  SCHEME 3, a launch whose first step
+            // samples, takes the chunk's own U1 rows as they are formed and
+            // only stores U2 (a variant of its own: one sampling site per
+            // kernel keeps the row transforms' registers out of the other).
+            constexpr bool first = SCHEME == 3;
             auto normals1 = [&](Z (&z)[CX], uint32_t dr) __attribute__((always_inline)) {
                 row_normals<T, CX, NZ, SQ>(z, dr, nq, q0, slo1, w21, real, key, rc);
             };
@@ -514,7 +518,9 @@ __global__ void __launch_bounds__(256)
                 xflux(tc, z, fx, fxh, k >= y0 && k < y1);
 #pragma unroll
                 for (int j = 0; j < CX; ++j) sn[j] = fma(r, xdiv<T, CX>(fx, fxh, j) + (fpn[j] - fpc[j]), tc[j]);
-                if (first && k >= y0 && k < y1) take(sn, k);
+                if constexpr (first) {
+                    if (k >= y0 && k < y1) take(sn, k);
+                }
                 if (i >= 1) {
                     normals1(z, drow(k, 1));
 #pragma unroll
@@ -526,7 +532,7 @@ __global__ void __launch_bounds__(256)
                     T out[CX];
 #pragma unroll
                     for (int j = 0; j < CX; ++j) out[j] = fma(r, xdiv<T, CX>(fx, fxh, j) + (fcc[j] - fcm[j]), sc[j]);
-                    if (first)
+                    if constexpr (first)
                         store_row<T, CX>(D + static_cast<int64_t>(k - 1) * p.nx, out);
                     else
                         emit(out, k - 1);
@@ -861,6 +867,9 @@ static hipError_t step2d_s(int scheme, int n_blocks, hipStream_t s, const Params
             else if (scheme == 1)
                 hipLaunchKernelGGL((k_step2d<T, CX, EQ, 1, false, false>), dim3(n_blocks), dim3(256), 0, s, p, in,
                                    out, sa, part, acc, none);
+            else if (!skr && sa.sample == 2)
+                hipLaunchKernelGGL((k_step2d<T, CX, EQ, 3, false, false>), dim3(n_blocks), dim3(256), 0, s, p, in,
+                                   out, sa, part, acc, none);
             else if (!skr)
                 hipLaunchKernelGGL((k_step2d<T, CX, EQ, 2, false, false>), dim3(n_blocks), dim3(256), 0, s, p, in,
                                    out, sa, part, acc, none);
@@ -877,6 +886,9 @@ static hipError_t step2d_s(int scheme, int n_blocks, hipStream_t s, const Params
     else if (scheme == 1)
         hipLaunchKernelGGL((k_step2d<T, CX, EQ, 1, false, true>), dim3(n_blocks), dim3(256), 0, s, p, in, out, sa,
                            part, acc, none);
+    else if (!skr && sa.sample == 2)
+        hipLaunchKernelGGL((k_step2d<T, CX, EQ, 3, false, true>), dim3(n_blocks), dim3(256), 0, s, p, in, out, sa,
+                           part, acc, none);
     else if (!skr)
         hipLaunchKernelGGL((k_step2d<T, CX, EQ, 2, false, true>), dim3(n_blocks), dim3(256), 0, s, p, in, out, sa,
                            part, acc, none);
@@ -885,8 +897,12 @@ static hipError_t step2d_s(int scheme, int n_blocks, hipStream_t s, const Params
             using FX = WaveFft<CX == 16 ? 10 : 9>;
             const size_t smem = sizeof(cplx<T>) * (FX::tw + 4 * static_cast<size_t>(FX::lds));
             if (smem > 64 * 1024) return hipErrorInvalidValue;
-            hipLaunchKernelGGL((k_step2d<T, CX, EQ, 2, true, true>), dim3(n_blocks), dim3(256), smem, s, p, in, out,
-                               sa, part, acc, *skr);
+            if (sa.sample == 2)
+                hipLaunchKernelGGL((k_step2d<T, CX, EQ, 3, true, true>), dim3(n_blocks), dim3(256), smem, s, p, in,
+                                   out, sa, part, acc, *skr);
+            else
+                hipLaunchKernelGGL((k_step2d<T, CX, EQ, 2, true, true>), dim3(n_blocks), dim3(256), smem, s, p, in,
+                                   out, sa, part, acc, *skr);
         } else {
             return hipErrorInvalidValue;
         }
