@@ -356,6 +356,16 @@ __global__ void __launch_bounds__(256, (sizeof(T) == 4 && LGY <= 9) ? 4 : 2)
         if constexpr (V2) {
             typedef float f4v __attribute__((ext_vector_type(4)));
             const f4v *t4 = reinterpret_cast<const f4v *>(tile);
+            if (cb + TC <= nh) {
+                // a full tile (all but an instance's last): no column to mask
+#pragma unroll
+                for (int j = 0; j < PT / 2; ++j) {
+                    const f4v q = t4[threadIdx.x + 64 * CW * j];
+                    pf[2 * j] = cplx<T>{q.x, q.y};
+                    pf[2 * j + 1] = cplx<T>{q.z, q.w};
+                }
+                return;
+            }
             const int c0 = (2 * threadIdx.x) & (TC - 1);
             const bool in0 = cb + c0 < nh, in1 = cb + c0 + 1 < nh;
 #pragma unroll
