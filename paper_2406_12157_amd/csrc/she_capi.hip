@@ -1223,9 +1223,10 @@ static bool samples_at(const she_handle *h, bool samp, int64_t t)
 // Whether a two-step launch can sample its first step: the intermediate
 // field never reaches memory, so its statistics are taken in the kernel as
 // its rows are formed, which S(k) allows only with the row transforms there.
+// That kernel variant is compiled for FP32 states only.
 static bool first_step_samples_ok(const she_handle *h)
 {
-    return !(h->mask & SHE_STAT_SK) || h->sk_fused;
+    return h->prec == SHE_F32 && (!(h->mask & SHE_STAT_SK) || h->sk_fused);
 }
 
 // One direct step, or two in one launch when `pair` allows it and at most

@@ -849,6 +849,11 @@ __global__ void __launch_bounds__(256)
 
 // ------------------------------------------------------------------ typed launchers
 
+// The two-step launch that samples its first step (SCHEME 3) is compiled for
+// FP32 only; the planner does not ask for it in FP64.
+template <typename T>
+constexpr bool kFirstStepVariant = std::is_same<T, float>::value;
+
 template <typename T, int CX, int EQ>
 static hipError_t step2d_s(int scheme, int n_blocks, hipStream_t s, const ParamsND &p, const void *src, void *dst,
                            const StepArg &sa, double *part, InstAcc *acc, const SkRows *skr)
@@ -867,9 +872,13 @@ static hipError_t step2d_s(int scheme, int n_blocks, hipStream_t s, const Params
             else if (scheme == 1)
                 hipLaunchKernelGGL((k_step2d<T, CX, EQ, 1, false, false>), dim3(n_blocks), dim3(256), 0, s, p, in,
                                    out, sa, part, acc, none);
-            else if (!skr && sa.sample == 2)
-                hipLaunchKernelGGL((k_step2d<T, CX, EQ, 3, false, false>), dim3(n_blocks), dim3(256), 0, s, p, in,
-                                   out, sa, part, acc, none);
+            else if (!skr && sa.sample == 2) {
+                if constexpr (kFirstStepVariant<T>)
+                    hipLaunchKernelGGL((k_step2d<T, CX, EQ, 3, false, false>), dim3(n_blocks), dim3(256), 0, s, p,
+                                       in, out, sa, part, acc, none);
+                else
+                    return hipErrorInvalidValue;
+            }
             else if (!skr)
                 hipLaunchKernelGGL((k_step2d<T, CX, EQ, 2, false, false>), dim3(n_blocks), dim3(256), 0, s, p, in,
                                    out, sa, part, acc, none);
@@ -886,9 +895,13 @@ static hipError_t step2d_s(int scheme, int n_blocks, hipStream_t s, const Params
     else if (scheme == 1)
         hipLaunchKernelGGL((k_step2d<T, CX, EQ, 1, false, true>), dim3(n_blocks), dim3(256), 0, s, p, in, out, sa,
                            part, acc, none);
-    else if (!skr && sa.sample == 2)
-        hipLaunchKernelGGL((k_step2d<T, CX, EQ, 3, false, true>), dim3(n_blocks), dim3(256), 0, s, p, in, out, sa,
-                           part, acc, none);
+    else if (!skr && sa.sample == 2) {
+        if constexpr (kFirstStepVariant<T>)
+            hipLaunchKernelGGL((k_step2d<T, CX, EQ, 3, false, true>), dim3(n_blocks), dim3(256), 0, s, p, in, out,
+                               sa, part, acc, none);
+        else
+            return hipErrorInvalidValue;
+    }
     else if (!skr)
         hipLaunchKernelGGL((k_step2d<T, CX, EQ, 2, false, true>), dim3(n_blocks), dim3(256), 0, s, p, in, out, sa,
                            part, acc, none);
@@ -897,10 +910,13 @@ static hipError_t step2d_s(int scheme, int n_blocks, hipStream_t s, const Params
             using FX = WaveFft<CX == 16 ? 10 : 9>;
             const size_t smem = sizeof(cplx<T>) * (FX::tw + 4 * static_cast<size_t>(FX::lds));
             if (smem > 64 * 1024) return hipErrorInvalidValue;
-            if (sa.sample == 2)
-                hipLaunchKernelGGL((k_step2d<T, CX, EQ, 3, true, true>), dim3(n_blocks), dim3(256), smem, s, p, in,
-                                   out, sa, part, acc, *skr);
-            else
+            if (sa.sample == 2) {
+                if constexpr (kFirstStepVariant<T>)
+                    hipLaunchKernelGGL((k_step2d<T, CX, EQ, 3, true, true>), dim3(n_blocks), dim3(256), smem, s, p,
+                                       in, out, sa, part, acc, *skr);
+                else
+                    return hipErrorInvalidValue;
+            } else
                 hipLaunchKernelGGL((k_step2d<T, CX, EQ, 2, true, true>), dim3(n_blocks), dim3(256), smem, s, p, in,
                                    out, sa, part, acc, *skr);
         } else {
