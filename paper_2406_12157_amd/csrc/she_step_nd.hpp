@@ -381,12 +381,29 @@ __global__ void __launch_bounds__(256)
                     cplx<T> *hb = static_cast<cplx<T> *>(skr.half) + half_index(inst, 0, 0, p.ny, skr.ltc, skr.nkb);
                     const uint32_t ltc = static_cast<uint32_t>(skr.ltc), tcm = (1u << ltc) - 1u;
                     const uint32_t yoff = static_cast<uint32_t>(y - 1) << ltc;
-                    for (int k = lx; k <= n / 2; k += 64) {
-                        const cplx<T> z = wreg[pidx(k)], zm = wreg[pidx((n - k) & (n - 1))];
-                        const uint32_t uk = static_cast<uint32_t>(k);
-                        const uint32_t e = (((uk >> ltc) * static_cast<uint32_t>(p.ny)) << ltc) + yoff + (uk & tcm);
-                        hb[e] = unpack2_a(z, zm);
-                        hb[e + tcm + 1u] = unpack2_b(z, zm);
+                    const uint32_t uny = static_cast<uint32_t>(p.ny);
+                    if (ltc <= 6) {
+                        // tiles of at most 64 columns: lane l's columns l + 64 i lie
+                        // 64/TC tiles apart, i.e. 64 ny entries, from its first one
+                        const uint32_t ul = static_cast<uint32_t>(lx);
+                        cplx<T> *hl = hb + ((((ul >> ltc) * uny) << ltc) + yoff + (ul & tcm));
+                        const size_t s64 = static_cast<size_t>(uny) << 6;
+#pragma unroll
+                        for (int i = 0; i <= n / 128; ++i) {
+                            if (i == n / 128 && lx != 0) break;  // kx = n/2: lane 0 only
+                            const int k = lx + 64 * i;
+                            const cplx<T> z = wreg[pidx(k)], zm = wreg[pidx((n - k) & (n - 1))];
+                            hl[i * s64] = unpack2_a(z, zm);
+                            hl[i * s64 + tcm + 1u] = unpack2_b(z, zm);
+                        }
+                    } else {
+                        for (int k = lx; k <= n / 2; k += 64) {
+                            const cplx<T> z = wreg[pidx(k)], zm = wreg[pidx((n - k) & (n - 1))];
+                            const uint32_t uk = static_cast<uint32_t>(k);
+                            const uint32_t e = (((uk >> ltc) * uny) << ltc) + yoff + (uk & tcm);
+                            hb[e] = unpack2_a(z, zm);
+                            hb[e + tcm + 1u] = unpack2_b(z, zm);
+                        }
                     }
                     wave_sync();  // the next pair's transpose overwrites the region
                 }
