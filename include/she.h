@@ -100,9 +100,13 @@ enum {
                                      its choice (not with an arena)          */
     SHE_TUNE_SINGLE_STEP = 4      /* 2D FE: one step per launch.  By default
                                      direct (not graph-replayed) steps go two
-                                     per launch wherever the first of the two
-                                     does not sample, the intermediate field
-                                     kept on chip; results are the same bits */
+                                     per launch, the intermediate field kept
+                                     on chip, wherever at most one of the two
+                                     samples (the first only for FP32 states,
+                                     and with SHE_STAT_SK only where the step
+                                     kernel transforms the rows: Nx 512 or
+                                     1024); fields and S(k) are the same bits,
+                                     spatial moments the same to rounding    */
 };
 
 /* she_config.flags */
